@@ -1,0 +1,186 @@
+"""Pins of the field-update oracle (Sec. IV.B, Sec. V, Sec. VI.A).
+
+  * the projected full-space trapezoidal update plus the Gauss-law solve equals the literal
+    tree/co-tree reduced system built from Z11..Z23 exactly as printed (Sec. IV.B.2);
+  * Z13 = 0 because Sigma = [*eps][grad] (Sec. IV.B.2);
+  * the result does not depend on which spanning trees are used;
+  * the source-free trapezoidal map has all eigenvalues on the unit circle (Sec. VI.A.1)
+    and rotates each mode by 2 atan(omega dt / 2) (closed form of the trapezoidal rule);
+  * the discrete energy is invariant without sources;
+  * D b is invariant bit for bit (Sec. IV.A, Sec. V item 5);
+  * Gauss's law holds after every step, and without the Gauss-law solve a loose Krylov
+    tolerance leaves an error in it (Sec. I and Sec. V: the null space is excited to the
+    level of the solver threshold).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import qh_inputs as qi
+from oracle import cotree as CT
+from oracle import field as Fo
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _exact_projected_step(cx, op, rs, dt, e, b, g, rho_new):
+    ie, inn = rs.ie, rs.inn
+    A = (op.Meps + dt * dt / 4 * op.S).toarray()[np.ix_(ie, ie)]
+    Bm = (op.Meps - dt * dt / 4 * op.S).toarray()
+    GtMe = (cx.G.T.astype(float) @ op.Meps).toarray()
+    rhs = (Bm @ e + dt * (op.CtMmu @ b) - g)[ie]
+    es = np.zeros(cx.Ne)
+    es[ie] = np.linalg.solve(A, rhs)
+    dl = np.linalg.solve(rs.K, rho_new - GtMe[inn] @ es)
+    en = es.copy()
+    en[ie] += rs.G @ dl
+    bn = b - dt / 2 * (cx.C.astype(float) @ (en + e))
+    return en, bn
+
+
+def _source_free_state(cx, rs, seed=0):
+    rng = np.random.default_rng(seed)
+    e = np.zeros(cx.Ne)
+    e[rs.ie] = rng.standard_normal(rs.ie.size)
+    a = np.zeros(cx.Ne)
+    a[rs.ie] = rng.standard_normal(rs.ie.size) * 1e-8
+    b = cx.C.astype(float) @ a                     # zero flux through the PEC walls
+    return e, b
+
+
+@pytest.mark.parametrize("dt", [1e-11, 2e-9])
+def test_literal_cotree_equals_projected(c1, dt):
+    _, cx, op = c1
+    rs = CT.ReducedSystem(cx, op, dt)
+    e, b = _source_free_state(cx, rs)
+    Ens, Es, Bs = rs.decompose(e[rs.ie], b[rs.jf])
+    rho = rs.G.T @ rs.Me @ e[rs.ie]
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        g = np.zeros(cx.Ne)
+        g[rs.ie] = rng.standard_normal(rs.ie.size) * 1e-12
+        rho_new = rho - rs.G.T @ g[rs.ie]          # continuity
+        e, b = _exact_projected_step(cx, op, rs, dt, e, b, g, rho_new)
+        Ens, Es, Bs = rs.step(Ens, Es, Bs, g[rs.ie], rho_new)
+        rho = rho_new
+        er, br = rs.compose(Ens, Es, Bs)
+        assert np.abs(er - e[rs.ie]).max() <= 1e-10 * np.abs(e).max()
+        assert np.abs(br - b[rs.jf]).max() <= 1e-10 * np.abs(b).max()
+
+
+def test_z13_vanishes_and_square_blocks(c1):
+    _, cx, op = c1
+    rs = CT.ReducedSystem(cx, op, 1e-10)
+    assert np.abs(rs.Z13).max() <= 1e-12 * np.abs(rs.Z12).max()
+    assert rs.Z11.shape == rs.Z21.shape == (289, 289)
+
+
+def test_tree_independence(c1):
+    _, cx, op = c1
+    dt = 1e-10
+    outs = []
+    for seed in (None, 5):
+        rs = CT.ReducedSystem(cx, op, dt, tree_seed=seed)
+        e, b = _source_free_state(cx, rs)
+        Ens, Es, Bs = rs.decompose(e[rs.ie], b[rs.jf])
+        rho = rs.G.T @ rs.Me @ e[rs.ie]
+        g = np.random.default_rng(2).standard_normal(rs.ie.size) * 1e-12
+        Ens, Es, Bs = rs.step(Ens, Es, Bs, g, rho - rs.G.T @ g)
+        outs.append(rs.compose(Ens, Es, Bs))
+    assert np.allclose(outs[0][0], outs[1][0], rtol=0, atol=1e-10 * np.abs(outs[0][0]).max())
+    assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-10 * np.abs(outs[0][1]).max())
+
+
+def test_trapezoidal_map_unit_circle_and_phase(c1):
+    _, cx, op = c1
+    dt = 2e-9                                       # ~10x the explicit limit of this mesh
+    ie = cx.int_edges
+    jf = np.flatnonzero(~cx.wall_face)
+    Me = op.Meps.toarray()[np.ix_(ie, ie)]
+    Mm = op.Mmu.toarray()[np.ix_(jf, jf)]
+    Cm = cx.C.toarray().astype(float)[np.ix_(jf, ie)]
+    nf, ne = jf.size, ie.size
+    M = np.block([[np.eye(nf), np.zeros((nf, ne))], [np.zeros((ne, nf)), Me]])
+    H = np.block([[np.zeros((nf, nf)), -Cm], [Cm.T @ Mm, np.zeros((ne, ne))]])
+    T = np.linalg.solve(M - 0.5 * dt * H, M + 0.5 * dt * H)
+    mu = np.linalg.eigvals(T)
+    assert np.abs(np.abs(mu) - 1).max() < 1e-10
+    # phases: 2 atan(omega dt/2) with omega^2 the eigenvalues of [*eps]^-1 S
+    S = Cm.T @ Mm @ Cm
+    w2 = np.linalg.eigvals(np.linalg.solve(Me, S)).real
+    w = np.sqrt(np.sort(w2[w2 > 1e-6 * w2.max()]))
+    ph = np.sort(np.abs(np.angle(mu)))
+    ph = ph[ph > 1e-8]
+    expect = np.sort(np.concatenate([2 * np.arctan(w * dt / 2)] * 2))
+    assert ph.size == expect.size
+    assert np.allclose(ph, expect, rtol=1e-10, atol=1e-12)
+
+
+def test_source_free_energy_and_divb(c1):
+    _, cx, op = c1
+    dt = 2e-9
+    fo = Fo.FieldOracle(cx, op, dt)
+    u_b = 2.0 ** -70
+    rng = np.random.default_rng(3)
+    e = np.zeros(cx.Ne)
+    e[cx.int_edges] = rng.standard_normal(cx.int_edges.size)
+    a = np.zeros(cx.Ne, np.int64)
+    a[cx.int_edges] = rng.integers(-2 ** 40, 2 ** 40, cx.int_edges.size)
+    b = cx.C @ a
+    Db0 = cx.D @ b
+    zero_n = np.zeros(cx.Nn, np.int64)
+    rho0 = (fo.GtMeps @ e)[fo.inn]
+    Qbg = np.zeros(cx.Nn, np.int64)
+
+    def energy(e, b):
+        br = b * u_b
+        return e @ (op.Meps @ e) + br @ (op.Mmu @ br)
+
+    W0 = energy(e, b)
+    # keep the initial charge: rho = G^T [*eps] e^0 expressed through a background
+    for _ in range(40):
+        e, b, info = fo.step_with_rho(e, b, u_b, np.zeros(cx.Ne, np.int64), 1.0, rho0, tol=1e-13,
+                                      tol_n=1e-13)
+        assert np.array_equal(cx.D @ b, Db0)
+    assert abs(energy(e, b) - W0) <= 1e-9 * W0
+
+
+def test_gauss_law_and_qh_benefit(c1):
+    """Loose edge solves (1e-6): with the Gauss-law solve the discrete Gauss residual stays
+    at the nodal tolerance; without it the error is orders of magnitude larger."""
+    m, cx, op = c1
+    dt = 2e-9
+    fo = Fo.FieldOracle(cx, op, dt)
+    u_b = 2.0 ** -56
+    rng = np.random.default_rng(4)
+    e0 = np.zeros(cx.Ne)
+    e0[cx.int_edges] = rng.standard_normal(cx.int_edges.size) * 1e2
+    b0 = cx.C @ np.rint(rng.standard_normal(cx.Ne) * 1e-6 / u_b).astype(np.int64)
+    u_q = 1e-12
+    res = {}
+    for gauss in (True, False):
+        e, b = e0.copy(), b0.copy()
+        Q = np.zeros(cx.Nn, np.int64)
+        Qbg = np.zeros(cx.Nn, np.int64)
+        errs = []
+        r2 = np.random.default_rng(5)
+        for _ in range(20):
+            g = np.zeros(cx.Ne, np.int64)
+            g[cx.int_edges] = r2.integers(-10 ** 6, 10 ** 6, cx.int_edges.size)
+            Q = Q + cx.G.T @ g                       # continuity fixes the charge
+            e, b, info = fo.step(e, b, u_b, g, u_q, Q, Qbg, tol=1e-6, tol_n=1e-12, gauss=gauss)
+            rho = u_q * (Qbg - Q).astype(float)[fo.inn]
+            errs.append(np.linalg.norm(fo.gauss_residual(e, rho)) / np.linalg.norm(rho))
+        res[gauss] = np.array(errs)
+    assert res[True][1:].max() < 1e-10
+    assert res[False][1:].max() > 1e3 * res[True][1:].max()
+
+
+def test_golden_beam_table_constants():
+    """The beam table (Sec. VI.B) prints v_p = 5e7 m/s and v_p/c = 0.16678."""
+    with open(os.path.join(HERE, "golden", "beam_table.json")) as f:
+        gold = json.load(f)
+    c = 1.0 / np.sqrt(qi.EPS0 * qi.MU0)
+    assert abs(gold["v_p"] / c - gold["v_p_over_c"]) < 5e-6
