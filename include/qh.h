@@ -1,0 +1,208 @@
+/* qh.h - C ABI of libqh: one charge-conserving FEM-PIC cycle on a tetrahedral mesh with
+ * the implicit quasi-Helmholtz field update, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: O'Connor, Crawford, Ramachandran, Luginsland, Shanker, "Quasi-Helmholtz
+ * Decomposition, Gauss' Laws and Charge Conservation for Finite Element Particle-in-Cell",
+ * arXiv 2103.06737. Section references below are to that paper.
+ *
+ * Conventions shared by every call
+ *  - Status: every int-returning call returns QH_OK (0) or a negative QH_E* code; the
+ *    message of the last failure is qh_last_error(ctx). Nothing throws across the ABI.
+ *  - Ownership: host arrays passed in are borrowed for the duration of the call and
+ *    copied; output arrays are caller-allocated with the sizes from qh_mesh_info. All
+ *    device state belongs to the context and is freed by qh_destroy.
+ *  - Ordering: all device work is queued on the context's HIP stream; a call returns
+ *    after its results are in the caller's host buffers. A context is not thread-safe.
+ *  - Mesh complex (Sec. II.C): each tet lists its 4 vertices; the library sorts them
+ *    ascending. Edges [a,b] (a<b) and faces [a,b,c] (a<b<c) are numbered in lexicographic
+ *    order of their vertex tuples. Edge a->b has G = -1 at a, +1 at b; face [a,b,c] has
+ *    boundary [b,c] - [a,c] + [a,b]. Local edge order inside a tet: 01 02 03 12 13 23;
+ *    local face k is opposite local vertex k.
+ *  - Walls: every boundary face is a perfect electric conductor (n x E = 0, Sec. II.A,
+ *    eq. bceq with Psi_D = 0) and a specularly reflecting particle wall. Wall edges keep
+ *    e = 0, wall nodes are grounded, wall-face fluxes never change.
+ *  - Fixed point: deposits are int64 in units of u_q (coulombs): a particle of charge
+ *    number z at barycentric coordinates lambda adds z * 2^20 * Lambda_n to node n, with
+ *    Lambda_n = lambda_n quantised to 2^-20; a straight piece adds
+ *    z * (L_a^0 L_b^1 - L_a^1 L_b^0) to edge a->b (2^40 times the line integral of W1 along
+ *    the piece, Sec. IV.B.1). Face fluxes b are int64 in units of u_b (webers).
+ */
+#ifndef QH_H
+#define QH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QH_OK 0
+#define QH_EINVAL (-1)    /* bad argument (null pointer, size, index out of range) */
+#define QH_ENOMEM (-2)    /* device or host allocation failed */
+#define QH_EHIP (-3)      /* a HIP runtime call failed */
+#define QH_ENOTCONV (-4)  /* a Krylov solve hit its iteration cap; stats are still filled */
+#define QH_EOVERFLOW (-5) /* fixed-point headroom exceeded */
+#define QH_ELOST (-6)     /* a particle hit the 64-piece walk cap; it is kept, flagged */
+#define QH_ESTATE (-7)    /* call out of order (e.g. a step before a mesh is uploaded) */
+
+#define QH_FIELDS_FROZEN 0 /* particles only: E, B stay as uploaded */
+#define QH_FIELDS_SOLVE 1  /* full cycle: implicit field update after each push */
+
+#define QH_PC_JACOBI 0  /* diagonal preconditioner, conjugate gradients */
+#define QH_PC_LEARNED 1 /* learned edge-local preconditioner, flexible CG, Jacobi fallback */
+
+#define QH_SYS_EDGE 0 /* ([*eps] + dt^2/4 S) on interior edges */
+#define QH_SYS_NODE 1 /* G^T [*eps] G on interior nodes (discrete Laplacian) */
+
+typedef struct qh_ctx qh_ctx;
+
+typedef struct {
+    int64_t n_nodes, n_edges, n_faces, n_tets;
+    int64_t n_int_nodes, n_int_edges; /* unknowns of the node and edge systems */
+    int64_t nnz_edge, nnz_node;       /* nonzeros of the two system matrices */
+} qh_mesh_info_t;
+
+typedef struct {
+    double eps0; /* permittivity (F/m) */
+    double mu0;  /* permeability (H/m) */
+    double dt;   /* time step (s) */
+    double u_q;  /* coulombs per integer deposit unit (e.g. e * weight * 2^-40) */
+    double u_b;  /* webers per integer face-flux unit */
+} qh_phys_t;
+
+typedef struct {
+    int32_t field_mode;  /* QH_FIELDS_FROZEN or QH_FIELDS_SOLVE */
+    int32_t sort_every;  /* counting-sort particles by tet every k steps (0 = never) */
+    int32_t precond;     /* QH_PC_JACOBI or QH_PC_LEARNED */
+    int32_t gauss;       /* 1: solve the discrete Gauss law each step (the method); 0: skip */
+    double tol_edge;     /* relative residual of the edge solve (e.g. 1e-8) */
+    double tol_node;     /* relative residual of the Gauss-law solve (e.g. 1e-8) */
+    int32_t max_it_edge, max_it_node;
+    int32_t check_every; /* iterations between host reads of the convergence flag */
+    int32_t verify;      /* 1: check continuity and D b on the device every step */
+} qh_step_params_t;
+
+typedef struct {
+    int32_t edge_iters, node_iters; /* Krylov iterations of this step */
+    double edge_res, node_res;      /* final relative residuals, recomputed in FP64 */
+    double gauss_res;               /* ||rho - G^T [*eps] e|| / (||rho|| + ||G^T [*eps] e||) */
+    int64_t crossings, wall_hits, lost;
+    int64_t continuity_bad;         /* nodes where G^T g != Q^{n+1} - Q^n (verify = 1) */
+    int64_t divb_bad;               /* tets where D b changed (verify = 1) */
+    int32_t fallbacks;              /* learned -> Jacobi restarts */
+    float ms_particles, ms_fields;  /* device time of the two halves (HIP events) */
+} qh_step_stats_t;
+
+typedef struct {
+    int32_t iters;
+    double res;  /* final ||b - A x|| / ||b||, recomputed with a fresh FP64 product */
+    int32_t fallback;
+    float ms;
+} qh_solve_stats_t;
+
+/* Context ------------------------------------------------------------------------------ */
+/* device: HIP device ordinal; stream: a hipStream_t (NULL = the null stream).
+ * device < 0 makes a host-only context: mesh build, assembly, qh_mesh_info,
+ * qh_mesh_topology and qh_matrix_* work; every call that needs the GPU returns QH_ESTATE. */
+int qh_create(qh_ctx **out, int device, void *stream);
+void qh_destroy(qh_ctx *ctx);
+const char *qh_last_error(const qh_ctx *ctx);
+
+/* Mesh (Sec. II.C): builds K = {N, E, F, T}, incidence, geometry, the Hodge matrices
+ * [*eps] (W1 mass), [*mu^-1] (W2 mass), S = C^T [*mu^-1] C and G^T [*eps] G on the host in
+ * FP64 and uploads them. xyz: 3*n_nodes doubles (x0 y0 z0 x1 ...); tet_nodes: 4*n_tets
+ * vertex ids. Errors: QH_EINVAL for ids out of range, degenerate tets, non-manifold faces. */
+int qh_mesh_upload(qh_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                   const int32_t *tet_nodes);
+int qh_mesh_info(const qh_ctx *ctx, qh_mesh_info_t *out);
+/* Topology as built (any pointer may be NULL): edges 2*Ne, faces 3*Nf, tet_nodes 4*Nt
+ * (sorted), tet_edges 6*Nt, tet_faces 4*Nt, tet_nbr 4*Nt (-1 = wall), wall_edge Ne,
+ * wall_node Nn (1 = on a wall). */
+int qh_mesh_topology(const qh_ctx *ctx, int32_t *edges, int32_t *faces, int32_t *tet_nodes,
+                     int32_t *tet_edges, int32_t *tet_faces, int32_t *tet_nbr,
+                     uint8_t *wall_edge, uint8_t *wall_node);
+
+/* Physical constants, time step and fixed-point units. Re-assembles the edge system
+ * A = [*eps] + dt^2/4 S when dt changes. */
+int qh_set_physics(qh_ctx *ctx, const qh_phys_t *phys);
+
+/* Fields (Sec. II.C: E = sum e_i W1_i, B = sum b_i W2_i). e: Ne doubles (volts; wall
+ * entries are forced to 0); b: Nf int64 in units of u_b. D b must be 0 in every tet
+ * (QH_EINVAL otherwise): B then is constant inside each tet. */
+int qh_fields_upload(qh_ctx *ctx, const double *e, const int64_t *b);
+int qh_fields_download(const qh_ctx *ctx, double *e, int64_t *b);
+/* Synthetic initial fields from caller-drawn standard normals (white_e, white_a: Ne each):
+ * e = l_e sigma_e w_e on interior edges; a = line integral of (0, bz x, 0) plus
+ * sigma_b l_e^2 / (2 sqrt 3) w'_e, rounded to units of u_b; b = C a. */
+int qh_fields_init_synthetic(qh_ctx *ctx, const double *white_e, const double *white_a,
+                             double sigma_e, double bz, double sigma_b);
+
+/* Particles (Sec. II.A, point charges moved by the Lorentz force). A species has one
+ * charge-to-mass ratio q_over_m (C/kg) and an integer charge number z (deposit sign and
+ * multiple of u_q). */
+int qh_species_add(qh_ctx *ctx, double q_over_m, int32_t charge_number, int32_t *species_id);
+/* x, v: 3n floats (x0 y0 z0 ...); tet: n tet ids holding each point. Replaces the
+ * species' particles and recomputes the node charge Q of all species. */
+int qh_particles_upload(qh_ctx *ctx, int32_t species, int64_t n, const float *x,
+                        const float *v, const int32_t *tet);
+/* In upload order. Any pointer may be NULL. */
+int qh_particles_download(const qh_ctx *ctx, int32_t species, float *x, float *v, int32_t *tet);
+/* Static background charge for Gauss's law: mode 0 none, mode 1 the negative of the
+ * present particle charge (neutral start); rho = u_q (Q_bg - Q) on interior nodes. */
+int qh_charge_background(qh_ctx *ctx, int32_t mode);
+
+/* n_steps PIC cycles (Sec. IV): field prep, per particle gather (E from W1, B from W2),
+ * Boris push, tet walk with wall reflection, integer deposit of the path integral of W1
+ * and of the W0 charge; then, if field_mode is QH_FIELDS_SOLVE, the implicit update of
+ * Sec. IV.B (trapezoidal edge solve, discrete Gauss law for the non-solenoidal part,
+ * integer Faraday update of b). stats: n_steps entries or NULL. Returns QH_ENOTCONV if a
+ * solve hit its cap (the step is still taken), QH_ELOST if a particle hit the walk cap. */
+int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
+                qh_step_stats_t *stats);
+/* Deposits of the last step: g (Ne) path-integrated current, Q (Nn) node charge,
+ * both int64 in units of u_q. Either may be NULL. */
+int qh_deposits_download(const qh_ctx *ctx, int64_t *g, int64_t *Q);
+/* Record every straight piece of the next qh_pic_step (first step only) into a device
+ * buffer of capacity cap (0 = off); read back with qh_segments_download. */
+int qh_capture_segments(qh_ctx *ctx, int64_t cap);
+/* n_out: pieces recorded (may exceed cap: then only cap were kept). Arrays of cap:
+ * pid (particle index in upload order), species, seq (piece index along the path),
+ * tet, lam0, lam1 (4 int32 each). */
+int qh_segments_download(const qh_ctx *ctx, int64_t *n_out, int32_t *pid, int32_t *species,
+                         int32_t *seq, int32_t *tet, int32_t *lam0, int32_t *lam1);
+
+/* Integer deposit from explicit lists (Sec. IV.B.1, the time-integrated current G^n and
+ * the charge rho^n = -[grad]^T G^n): piece s in tet seg_tet[s] from local coordinates
+ * lam0[4s..4s+3] to lam1[4s..] (each summing to 2^20) with charge number seg_z[s]; point
+ * p in tet pt_tet[p] with coordinates pt_lam[4p..] and charge number pt_z[p]. Writes g
+ * (Ne) and Q (Nn), int64 in units of u_q. Deterministic (integer sums). */
+int qh_deposit(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t *lam0,
+               const int32_t *lam1, const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet,
+               const int32_t *pt_lam, const int32_t *pt_z, int64_t *g_out, int64_t *q_out);
+
+/* Solve system (QH_SYS_EDGE or QH_SYS_NODE) A x = rhs on its interior unknowns
+ * (n_int_edges or n_int_nodes values), FP64 CG with FP64 dot products, to
+ * ||rhs - A x|| <= tol ||rhs||. x holds the initial guess on entry. */
+int qh_field_solve(qh_ctx *ctx, int32_t system, const double *rhs, double *x, double tol,
+                   int32_t max_it, int32_t precond, qh_solve_stats_t *stats);
+
+/* Assembled FP64 matrices as CSR (0-based, sorted columns), host copies. which:
+ * 0 A = [*eps] + dt^2/4 S, 1 [*eps], 2 S = C^T [*mu^-1] C (all interior edges x interior
+ * edges), 3 C^T [*mu^-1] (interior edges x all faces), 4 G^T [*eps] (interior nodes x
+ * interior edges), 5 K = G^T [*eps] G (interior nodes). ptr: nrow+1, col/val: nnz. */
+int qh_matrix_info(const qh_ctx *ctx, int32_t which, int64_t *nrow, int64_t *ncol, int64_t *nnz);
+int qh_matrix_download(const qh_ctx *ctx, int32_t which, int32_t *ptr, int32_t *col, double *val);
+
+/* Per-kernel device time, measured with HIP events recorded around each launch on the
+ * context stream while enabled (enabling resets the table). Index k of the table:
+ * 0 field prep, 1 particle step, 2 sort, 3 edge right-hand side, 4 CG product (fused
+ * direction update + SpMV + dot), 5 CG vector update, 6 CG init, 7 Gauss-law kernels,
+ * 8 Faraday update, 9 residual check. ms_total[k]: summed milliseconds; launches[k]: count. */
+int qh_timing_enable(qh_ctx *ctx, int32_t on);
+int qh_timing_read(const qh_ctx *ctx, int32_t n, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QH_H */

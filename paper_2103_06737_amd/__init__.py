@@ -1,0 +1,303 @@
+"""Python binding of libqh (argument marshalling only).
+
+Every step of the PIC cycle runs in the HIP kernels of libqh.so; this module converts
+numpy arrays to pointers and status codes to exceptions. The library must have been
+built in-tree (``python -m paper_2103_06737_amd.build``); importing fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqh.so")
+
+QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+FIELDS_FROZEN, FIELDS_SOLVE = 0, 1
+PC_JACOBI, PC_LEARNED = 0, 1
+SYS_EDGE, SYS_NODE = 0, 1
+KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
+           "gauss", "faraday", "true_res"]
+F_BITS = 20
+EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mesh_info",
+           "qh_mesh_topology", "qh_set_physics", "qh_fields_upload", "qh_fields_download",
+           "qh_fields_init_synthetic", "qh_species_add", "qh_particles_upload",
+           "qh_particles_download", "qh_charge_background", "qh_pic_step", "qh_deposits_download",
+           "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
+           "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read"]
+
+
+class QhError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libqh error {code}: {msg}")
+        self.code = code
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_edges", C.c_int64), ("n_faces", C.c_int64),
+                ("n_tets", C.c_int64), ("n_int_nodes", C.c_int64), ("n_int_edges", C.c_int64),
+                ("nnz_edge", C.c_int64), ("nnz_node", C.c_int64)]
+
+
+class Phys(C.Structure):
+    _fields_ = [("eps0", C.c_double), ("mu0", C.c_double), ("dt", C.c_double),
+                ("u_q", C.c_double), ("u_b", C.c_double)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("field_mode", C.c_int32), ("sort_every", C.c_int32), ("precond", C.c_int32),
+                ("gauss", C.c_int32), ("tol_edge", C.c_double), ("tol_node", C.c_double),
+                ("max_it_edge", C.c_int32), ("max_it_node", C.c_int32),
+                ("check_every", C.c_int32), ("verify", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("edge_iters", C.c_int32), ("node_iters", C.c_int32), ("edge_res", C.c_double),
+                ("node_res", C.c_double), ("gauss_res", C.c_double), ("crossings", C.c_int64),
+                ("wall_hits", C.c_int64), ("lost", C.c_int64), ("continuity_bad", C.c_int64),
+                ("divb_bad", C.c_int64), ("fallbacks", C.c_int32), ("ms_particles", C.c_float),
+                ("ms_fields", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("res", C.c_double), ("fallback", C.c_int32), ("ms", C.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqh.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2103_06737_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "qh_create": [C.POINTER(p), C.c_int, p],
+            "qh_destroy": [p],
+            "qh_mesh_upload": [p, i64, p, i64, p],
+            "qh_mesh_info": [p, C.POINTER(MeshInfo)],
+            "qh_mesh_topology": [p, p, p, p, p, p, p, p, p],
+            "qh_set_physics": [p, C.POINTER(Phys)],
+            "qh_fields_upload": [p, p, p],
+            "qh_fields_download": [p, p, p],
+            "qh_fields_init_synthetic": [p, p, p, d, d, d],
+            "qh_species_add": [p, d, i32, C.POINTER(i32)],
+            "qh_particles_upload": [p, i32, i64, p, p, p],
+            "qh_particles_download": [p, i32, p, p, p],
+            "qh_charge_background": [p, i32],
+            "qh_pic_step": [p, C.POINTER(StepParams), i32, p],
+            "qh_deposits_download": [p, p, p],
+            "qh_capture_segments": [p, i64],
+            "qh_segments_download": [p, C.POINTER(i64), p, p, p, p, p, p],
+            "qh_deposit": [p, i64, p, p, p, p, i64, p, p, p, p, p],
+            "qh_field_solve": [p, i32, p, p, d, i32, i32, C.POINTER(SolveStats)],
+            "qh_matrix_info": [p, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+            "qh_matrix_download": [p, i32, p, p, p],
+            "qh_timing_enable": [p, i32],
+            "qh_timing_read": [p, i32, p, p],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "qh_destroy" else C.c_int
+        L.qh_last_error.argtypes = [p]
+        L.qh_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Context:
+    """One libqh context (one mesh, its fields and particle species) on one device.
+
+    device < 0 gives a host-only context (mesh build and assembly only)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.L = lib()
+        h = C.c_void_p()
+        rc = self.L.qh_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+        if rc != QH_OK:
+            raise QhError(rc, "qh_create failed (no HIP device?)")
+        self.h = h
+        self.info = None
+
+    def close(self):
+        if self.h:
+            self.L.qh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != QH_OK and rc not in allow:
+            raise QhError(rc, self.L.qh_last_error(self.h).decode())
+        return rc
+
+    # mesh -----------------------------------------------------------------------------
+    def mesh_upload(self, xyz, tets):
+        xyz = _c(xyz, np.float64)
+        tets = _c(tets, np.int32)
+        self._check(self.L.qh_mesh_upload(self.h, xyz.shape[0], _ptr(xyz), tets.shape[0], _ptr(tets)))
+        mi = MeshInfo()
+        self._check(self.L.qh_mesh_info(self.h, C.byref(mi)))
+        self.info = mi
+        return mi
+
+    def mesh_info(self):
+        mi = MeshInfo()
+        self._check(self.L.qh_mesh_info(self.h, C.byref(mi)))
+        self.info = mi
+        return mi
+
+    def topology(self):
+        mi = self.info
+        out = dict(edges=np.zeros((mi.n_edges, 2), np.int32), faces=np.zeros((mi.n_faces, 3), np.int32),
+                   tet_nodes=np.zeros((mi.n_tets, 4), np.int32), tet_edges=np.zeros((mi.n_tets, 6), np.int32),
+                   tet_faces=np.zeros((mi.n_tets, 4), np.int32), tet_nbr=np.zeros((mi.n_tets, 4), np.int32),
+                   wall_edge=np.zeros(mi.n_edges, np.uint8), wall_node=np.zeros(mi.n_nodes, np.uint8))
+        self._check(self.L.qh_mesh_topology(self.h, *[_ptr(out[k]) for k in
+                                                      ("edges", "faces", "tet_nodes", "tet_edges", "tet_faces",
+                                                       "tet_nbr", "wall_edge", "wall_node")]))
+        return out
+
+    def set_physics(self, eps0, mu0, dt, u_q, u_b):
+        self.phys = Phys(eps0, mu0, dt, u_q, u_b)
+        self._check(self.L.qh_set_physics(self.h, C.byref(self.phys)))
+
+    def matrix(self, which):
+        import scipy.sparse as sp
+        nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.L.qh_matrix_info(self.h, which, C.byref(nr), C.byref(nc), C.byref(nz)))
+        ptr = np.zeros(nr.value + 1, np.int32)
+        col = np.zeros(nz.value, np.int32)
+        val = np.zeros(nz.value, np.float64)
+        self._check(self.L.qh_matrix_download(self.h, which, _ptr(ptr), _ptr(col), _ptr(val)))
+        return sp.csr_matrix((val, col, ptr), shape=(nr.value, nc.value))
+
+    # fields ---------------------------------------------------------------------------
+    def fields_upload(self, e, b):
+        e = _c(e, np.float64)
+        b = _c(b, np.int64)
+        self._check(self.L.qh_fields_upload(self.h, _ptr(e), _ptr(b)))
+
+    def fields_download(self):
+        e = np.zeros(self.info.n_edges)
+        b = np.zeros(self.info.n_faces, np.int64)
+        self._check(self.L.qh_fields_download(self.h, _ptr(e), _ptr(b)))
+        return e, b
+
+    def fields_init_synthetic(self, white_e, white_a, sigma_e, bz, sigma_b):
+        we = _c(white_e, np.float64)
+        wa = _c(white_a, np.float64)
+        self._check(self.L.qh_fields_init_synthetic(self.h, _ptr(we), _ptr(wa), sigma_e, bz, sigma_b))
+
+    # particles ------------------------------------------------------------------------
+    def species_add(self, q_over_m, charge_number):
+        sid = C.c_int32()
+        self._check(self.L.qh_species_add(self.h, float(q_over_m), int(charge_number), C.byref(sid)))
+        return sid.value
+
+    def particles_upload(self, sid, x, v, tet):
+        x = _c(x, np.float32)
+        v = _c(v, np.float32)
+        tet = _c(tet, np.int32)
+        self._check(self.L.qh_particles_upload(self.h, sid, tet.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+        self._np = getattr(self, "_np", {})
+        self._np[sid] = tet.shape[0]
+
+    def particles_download(self, sid):
+        n = self._np[sid]
+        x = np.zeros((n, 3), np.float32)
+        v = np.zeros((n, 3), np.float32)
+        t = np.zeros(n, np.int32)
+        self._check(self.L.qh_particles_download(self.h, sid, _ptr(x), _ptr(v), _ptr(t)))
+        return x, v, t
+
+    def charge_background(self, mode):
+        self._check(self.L.qh_charge_background(self.h, int(mode)))
+
+    # cycle ----------------------------------------------------------------------------
+    @staticmethod
+    def step_params(field_mode=FIELDS_FROZEN, sort_every=0, precond=PC_JACOBI, gauss=1,
+                    tol_edge=1e-8, tol_node=1e-8, max_it_edge=2000, max_it_node=5000,
+                    check_every=8, verify=0):
+        return StepParams(field_mode, sort_every, precond, gauss, tol_edge, tol_node, max_it_edge,
+                          max_it_node, check_every, verify)
+
+    def pic_step(self, params, n_steps=1, want_stats=True, allow=()):
+        stats = (StepStats * n_steps)() if want_stats else None
+        rc = self.L.qh_pic_step(self.h, C.byref(params), int(n_steps),
+                                C.cast(stats, C.c_void_p) if stats is not None else None)
+        self._check(rc, allow)
+        return [s.as_dict() for s in stats] if stats is not None else None
+
+    def deposits_download(self):
+        g = np.zeros(self.info.n_edges, np.int64)
+        Q = np.zeros(self.info.n_nodes, np.int64)
+        self._check(self.L.qh_deposits_download(self.h, _ptr(g), _ptr(Q)))
+        return g, Q
+
+    def capture_segments(self, cap):
+        self._check(self.L.qh_capture_segments(self.h, int(cap)))
+        self._cap = int(cap)
+
+    def segments_download(self):
+        cap = self._cap
+        n = C.c_int64()
+        out = dict(pid=np.zeros(cap, np.int32), species=np.zeros(cap, np.int32), seq=np.zeros(cap, np.int32),
+                   tet=np.zeros(cap, np.int32), lam0=np.zeros((cap, 4), np.int32), lam1=np.zeros((cap, 4), np.int32))
+        self._check(self.L.qh_segments_download(self.h, C.byref(n), *[_ptr(out[k]) for k in
+                                                                       ("pid", "species", "seq", "tet", "lam0", "lam1")]))
+        k = min(n.value, cap)
+        return n.value, {kk: vv[:k] for kk, vv in out.items()}
+
+    def deposit(self, seg_tet, lam0, lam1, seg_z, pt_tet, pt_lam, pt_z):
+        a = [_c(seg_tet, np.int32), _c(lam0, np.int32), _c(lam1, np.int32), _c(seg_z, np.int32),
+             _c(pt_tet, np.int32), _c(pt_lam, np.int32), _c(pt_z, np.int32)]
+        g = np.zeros(self.info.n_edges, np.int64)
+        Q = np.zeros(self.info.n_nodes, np.int64)
+        self._check(self.L.qh_deposit(self.h, a[0].shape[0], _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]),
+                                      a[4].shape[0], _ptr(a[4]), _ptr(a[5]), _ptr(a[6]), _ptr(g), _ptr(Q)))
+        return g, Q
+
+    def field_solve(self, system, rhs, x0=None, tol=1e-8, max_it=5000, precond=PC_JACOBI, allow=()):
+        rhs = _c(rhs, np.float64)
+        x = np.zeros_like(rhs) if x0 is None else _c(x0, np.float64).copy()
+        st = SolveStats()
+        rc = self.L.qh_field_solve(self.h, int(system), _ptr(rhs), _ptr(x), float(tol), int(max_it),
+                                   int(precond), C.byref(st))
+        self._check(rc, allow)
+        return x, dict(iters=st.iters, res=st.res, fallback=st.fallback, ms=st.ms)
+
+    # timing ---------------------------------------------------------------------------
+    def timing(self, on):
+        self._check(self.L.qh_timing_enable(self.h, int(bool(on))))
+
+    def timing_read(self):
+        n = len(KERNELS)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, np.int64)
+        self._check(self.L.qh_timing_read(self.h, n, _ptr(ms), _ptr(cnt)))
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNELS)}

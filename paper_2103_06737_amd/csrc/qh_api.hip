@@ -1,0 +1,717 @@
+// C ABI of libqh (declarations and contracts in include/qh.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "qh_internal.h"
+
+int qh_fail(qh_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+// ----------------------------------------------------------------------------- timing
+int qh_tbeg(qh_ctx *c) {
+    if (!c->timing) return -1;
+    int slot = (int)c->pending.size() * 2;
+    while ((int)c->ev_pool.size() < slot + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        c->ev_pool.push_back(e);
+    }
+    (void)hipEventRecord(c->ev_pool[slot], c->stream);
+    return slot;
+}
+
+void qh_tend(qh_ctx *c, int slot, int kernel) {
+    if (slot < 0) return;
+    (void)hipEventRecord(c->ev_pool[slot + 1], c->stream);
+    c->pending.push_back({slot, kernel});
+}
+
+void qh_tflush(qh_ctx *c) {
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->ev_pool[p.slot], c->ev_pool[p.slot + 1]);
+        c->t_ms[p.kernel] += ms;
+        c->t_cnt[p.kernel] += 1;
+    }
+    c->pending.clear();
+}
+
+namespace {
+
+template <class T>
+int upload(qh_ctx *c, T **dst, const T *src, size_t n) {
+    int rc = qh_alloc(c, dst, n);
+    if (rc) return rc;
+    QH_HIP(c, hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return QH_OK;
+}
+
+int upload_csr(qh_ctx *c, DevCsr &d, const HostCsr &h, bool two) {
+    d.n = (int32_t)h.nrow;
+    d.nnz = (int64_t)h.col.size();
+    int rc;
+    if ((rc = upload(c, &d.ptr, h.ptr.data(), h.ptr.size()))) return rc;
+    if ((rc = upload(c, &d.col, h.col.data(), h.col.size()))) return rc;
+    if ((rc = upload(c, two ? &d.val2 : &d.val, h.val.data(), h.val.size()))) return rc;
+    return QH_OK;
+}
+
+void free_all(qh_ctx *c) {
+    for (void *p : c->allocations) (void)hipFree(p);
+    c->allocations.clear();
+}
+
+int sync(qh_ctx *c) {
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    return QH_OK;
+}
+
+// Assemble on the host and upload the matrices once mesh and physics are both known.
+int ensure_assembled(qh_ctx *c) {
+    if (!c->have_mesh || !c->have_phys) return QH_OK;
+    int rc;
+    if (c->host_only) {
+        if (!c->assembled) qh_assemble(c->hm, c->phys.eps0, c->phys.mu0, c->hA, c->hCMb, c->hGtM, c->hK);
+        c->assembled = true;
+        return QH_OK;
+    }
+    if (!c->assembled) {
+        qh_assemble(c->hm, c->phys.eps0, c->phys.mu0, c->hA, c->hCMb, c->hGtM, c->hK);
+        // A: val2 = [*eps], A_S = S, val = [*eps] + tau S (device)
+        if ((rc = upload_csr(c, c->A, c->hA, true))) return rc;
+        if ((rc = upload(c, &c->A_S, c->hA.val2.data(), c->hA.val2.size()))) return rc;
+        if ((rc = qh_alloc(c, &c->A.val, c->A.nnz))) return rc;
+        if ((rc = upload_csr(c, c->CMb, c->hCMb, false))) return rc;
+        if ((rc = upload_csr(c, c->GtM, c->hGtM, false))) return rc;
+        if ((rc = upload_csr(c, c->K, c->hK, false))) return rc;
+        if ((rc = qh_cg_alloc(c, c->cge, c->A.n))) return rc;
+        if ((rc = qh_cg_alloc(c, c->cgn, c->K.n))) return rc;
+        if ((rc = qh_alloc(c, &c->e_old, std::max<int64_t>(1, c->A.n)))) return rc;
+        if ((rc = qh_alloc(c, &c->rho, std::max<int64_t>(1, c->K.n)))) return rc;
+        QH_HIP(c, launch_diag_inv(c, c->K, c->cgn.dinv));
+        c->assembled = true;
+        c->tau_assembled = -1.0;
+        // cge.x mirrors e on the interior edges
+        std::vector<double> e_h(c->hm.Ne, 0.0), x(c->A.n);
+        QH_HIP(c, hipMemcpyAsync(e_h.data(), c->e, sizeof(double) * c->hm.Ne, hipMemcpyDeviceToHost, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        for (int32_t i = 0; i < c->A.n; ++i) x[i] = e_h[c->hm.int_edges[i]];
+        QH_HIP(c, hipMemcpyAsync(c->cge.x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    double tau = 0.25 * c->phys.dt * c->phys.dt;
+    if (tau != c->tau_assembled) {
+        QH_HIP(c, launch_assemble_A(c, tau));
+        QH_HIP(c, launch_diag_inv(c, c->A, c->cge.dinv));
+        c->tau_assembled = tau;
+    }
+    return sync(c);
+}
+
+int check_divb_host(qh_ctx *c, const int64_t *b) {
+    const HostMesh &m = c->hm;
+    for (int64_t t = 0; t < m.Nt; ++t) {
+        const int32_t *f = &m.tf[4 * t];
+        int64_t s = b[f[0]] - b[f[1]] + b[f[2]] - b[f[3]];
+        if (s != 0) return qh_fail(c, QH_EINVAL, "D b != 0 in tet " + std::to_string(t));
+    }
+    return QH_OK;
+}
+
+int set_fields(qh_ctx *c, const double *e, const int64_t *b) {
+    const HostMesh &m = c->hm;
+    int rc = check_divb_host(c, b);
+    if (rc) return rc;
+    std::vector<double> eh(e, e + m.Ne);
+    for (int64_t i = 0; i < m.Ne; ++i)
+        if (m.wall_edge[i]) eh[i] = 0.0;
+    QH_HIP(c, hipMemcpyAsync(c->e, eh.data(), sizeof(double) * m.Ne, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemcpyAsync(c->b, b, sizeof(int64_t) * m.Nf, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->divb0, 0, sizeof(int64_t) * m.Nt, c->stream));
+    if (c->assembled) {
+        std::vector<double> x(m.int_edges.size());
+        for (size_t i = 0; i < x.size(); ++i) x[i] = eh[m.int_edges[i]];
+        QH_HIP(c, hipMemcpyAsync(c->cge.x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    c->have_fields = true;
+    c->fields_dirty = true;
+    return sync(c);
+}
+
+int recompute_charge(qh_ctx *c) {
+    QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * c->hm.Nn, c->stream));
+    for (auto &s : c->species) QH_HIP(c, launch_charge_deposit(c, s));
+    QH_HIP(c, hipMemcpyAsync(c->Q_old, c->Q, sizeof(int64_t) * c->hm.Nn, hipMemcpyDeviceToDevice, c->stream));
+    return sync(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int qh_create(qh_ctx **out, int device, void *stream) {
+    if (!out) return QH_EINVAL;
+    *out = nullptr;
+    if (device < 0) {
+        qh_ctx *c = new qh_ctx();
+        c->host_only = true;
+        *out = c;
+        return QH_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return QH_EHIP;
+    if (device < 0 || device >= n) return QH_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return QH_EHIP;
+    qh_ctx *c = new qh_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    unsigned long long *cnt = nullptr;
+    if (qh_alloc(c, &cnt, 8) != QH_OK) {
+        delete c;
+        return QH_ENOMEM;
+    }
+    c->counters = cnt;
+    if (qh_alloc(c, &c->scratch_d, 16) != QH_OK) {
+        free_all(c);
+        delete c;
+        return QH_ENOMEM;
+    }
+    *out = c;
+    return QH_OK;
+}
+
+void qh_destroy(qh_ctx *c) {
+    if (!c) return;
+    if (c->host_only) {
+        delete c;
+        return;
+    }
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    free_all(c);
+    delete c;
+}
+
+const char *qh_last_error(const qh_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tet_nodes) {
+    if (!c) return QH_EINVAL;
+    if (c->have_mesh) return qh_fail(c, QH_ESTATE, "mesh already uploaded (one mesh per context)");
+    std::string msg = qh_build_mesh(c->hm, n_nodes, xyz, n_tets, tet_nodes);
+    if (!msg.empty()) return qh_fail(c, QH_EINVAL, msg);
+    HostMesh &m = c->hm;
+    int rc;
+    if (c->host_only) {
+        c->have_mesh = true;
+        return ensure_assembled(c);
+    }
+    // FP32 geometry records: (grad l_i, centroid component)
+    std::vector<float4> geo(3 * m.Nt);
+    for (int64_t t = 0; t < m.Nt; ++t)
+        for (int i = 1; i <= 3; ++i) {
+            const double *g = &m.grad[12 * t + 3 * i];
+            geo[3 * t + i - 1] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)m.cen[3 * t + i - 1]);
+        }
+    std::vector<int32_t> te8(8 * m.Nt, -1);
+    for (int64_t t = 0; t < m.Nt; ++t)
+        for (int k = 0; k < 6; ++k) te8[8 * t + k] = m.te[6 * t + k];
+    if ((rc = upload(c, &c->geo, geo.data(), geo.size()))) return rc;
+    if ((rc = upload(c, &c->tnodes, (const int4 *)m.tn.data(), m.Nt))) return rc;
+    if ((rc = upload(c, &c->tedges, te8.data(), te8.size()))) return rc;
+    if ((rc = upload(c, &c->tnbr, (const int4 *)m.nbr.data(), m.Nt))) return rc;
+    if ((rc = upload(c, &c->tfaces, m.tf.data(), m.tf.size()))) return rc;
+    if ((rc = upload(c, &c->tsign, m.tsign.data(), m.tsign.size()))) return rc;
+    if ((rc = upload(c, &c->face_edges, m.face_edges.data(), m.face_edges.size()))) return rc;
+    if ((rc = upload(c, &c->int_edges, m.int_edges.data(), std::max<size_t>(1, m.int_edges.size())))) return rc;
+    if ((rc = upload(c, &c->int_nodes, m.int_nodes.data(), std::max<size_t>(1, m.int_nodes.size())))) return rc;
+    if ((rc = upload(c, &c->int_node_of, m.int_node_of.data(), m.int_node_of.size()))) return rc;
+    if ((rc = upload(c, &c->edge_nodes, m.edges.data(), m.edges.size()))) return rc;
+    if ((rc = upload(c, &c->n2e_ptr, m.n2e_ptr.data(), m.n2e_ptr.size()))) return rc;
+    if ((rc = upload(c, &c->n2e, m.n2e.data(), m.n2e.size()))) return rc;
+    if ((rc = qh_alloc(c, &c->frec, 3 * m.Nt))) return rc;
+    if ((rc = qh_alloc(c, &c->e, m.Ne)) || (rc = qh_alloc(c, &c->b, m.Nf)) || (rc = qh_alloc(c, &c->g, m.Ne)) ||
+        (rc = qh_alloc(c, &c->Q, m.Nn)) || (rc = qh_alloc(c, &c->Q_old, m.Nn)) || (rc = qh_alloc(c, &c->Q_bg, m.Nn)) ||
+        (rc = qh_alloc(c, &c->divb0, m.Nt)) || (rc = qh_alloc(c, &c->u_int, m.Ne)) ||
+        (rc = qh_alloc(c, &c->hist, m.Nt)) || (rc = qh_alloc(c, &c->cursor, m.Nt)) ||
+        (rc = qh_alloc(c, &c->scan_tmp, (m.Nt + 1023) / 1024 + 1)))
+        return rc;
+    QH_HIP(c, hipMemsetAsync(c->e, 0, sizeof(double) * m.Ne, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->b, 0, sizeof(int64_t) * m.Nf, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->g, 0, sizeof(int64_t) * m.Ne, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * m.Nn, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->Q_old, 0, sizeof(int64_t) * m.Nn, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->Q_bg, 0, sizeof(int64_t) * m.Nn, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->divb0, 0, sizeof(int64_t) * m.Nt, c->stream));
+    QH_HIP(c, hipMemsetAsync(c->u_int, 0, sizeof(int64_t) * m.Ne, c->stream));
+    c->have_mesh = true;
+    if ((rc = sync(c))) return rc;
+    return ensure_assembled(c);
+}
+
+int qh_mesh_info(const qh_ctx *c, qh_mesh_info_t *out) {
+    if (!c || !out) return QH_EINVAL;
+    if (!c->have_mesh) return QH_ESTATE;
+    const HostMesh &m = c->hm;
+    out->n_nodes = m.Nn;
+    out->n_edges = m.Ne;
+    out->n_faces = m.Nf;
+    out->n_tets = m.Nt;
+    out->n_int_nodes = (int64_t)m.int_nodes.size();
+    out->n_int_edges = (int64_t)m.int_edges.size();
+    out->nnz_edge = (int64_t)c->hA.col.size();
+    out->nnz_node = (int64_t)c->hK.col.size();
+    return QH_OK;
+}
+
+int qh_mesh_topology(const qh_ctx *c, int32_t *edges, int32_t *faces, int32_t *tet_nodes, int32_t *tet_edges,
+                     int32_t *tet_faces, int32_t *tet_nbr, uint8_t *wall_edge, uint8_t *wall_node) {
+    if (!c) return QH_EINVAL;
+    if (!c->have_mesh) return QH_ESTATE;
+    const HostMesh &m = c->hm;
+    if (edges) std::copy(m.edges.begin(), m.edges.end(), edges);
+    if (faces) std::copy(m.faces.begin(), m.faces.end(), faces);
+    if (tet_nodes) std::copy(m.tn.begin(), m.tn.end(), tet_nodes);
+    if (tet_edges) std::copy(m.te.begin(), m.te.end(), tet_edges);
+    if (tet_faces) std::copy(m.tf.begin(), m.tf.end(), tet_faces);
+    if (tet_nbr) std::copy(m.nbr.begin(), m.nbr.end(), tet_nbr);
+    if (wall_edge) std::copy(m.wall_edge.begin(), m.wall_edge.end(), wall_edge);
+    if (wall_node) std::copy(m.wall_node.begin(), m.wall_node.end(), wall_node);
+    return QH_OK;
+}
+
+int qh_set_physics(qh_ctx *c, const qh_phys_t *p) {
+    if (!c || !p) return QH_EINVAL;
+    if (!(p->eps0 > 0) || !(p->mu0 > 0) || !(p->dt > 0) || !(p->u_q > 0) || !(p->u_b > 0))
+        return qh_fail(c, QH_EINVAL, "physics: eps0, mu0, dt, u_q, u_b must be positive");
+    if (c->have_phys && (p->eps0 != c->phys.eps0 || p->mu0 != c->phys.mu0) && c->assembled)
+        return qh_fail(c, QH_ESTATE, "eps0/mu0 cannot change after assembly");
+    bool ub_changed = c->have_phys && p->u_b != c->phys.u_b;
+    if (ub_changed && c->have_fields) return qh_fail(c, QH_ESTATE, "u_b cannot change once fields are set");
+    c->phys = *p;
+    c->have_phys = true;
+    c->fields_dirty = true;
+    return ensure_assembled(c);
+}
+
+int qh_fields_upload(qh_ctx *c, const double *e, const int64_t *b) {
+    if (!c || !e || !b) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    return set_fields(c, e, b);
+}
+
+int qh_fields_download(const qh_ctx *cc, double *e, int64_t *b) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (e) QH_HIP(c, hipMemcpyAsync(e, c->e, sizeof(double) * c->hm.Ne, hipMemcpyDeviceToHost, c->stream));
+    if (b) QH_HIP(c, hipMemcpyAsync(b, c->b, sizeof(int64_t) * c->hm.Nf, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_fields_init_synthetic(qh_ctx *c, const double *we, const double *wa, double sigma_e, double bz,
+                             double sigma_b) {
+    if (!c || !we || !wa) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh || !c->have_phys) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    const HostMesh &m = c->hm;
+    std::vector<double> e(m.Ne, 0.0);
+    std::vector<int64_t> a(m.Ne), b(m.Nf);
+    const double k = sigma_b / (2.0 * std::sqrt(3.0));
+    for (int64_t i = 0; i < m.Ne; ++i) {
+        const double *pa = &m.xyz[3 * (int64_t)m.edges[2 * i]], *pb = &m.xyz[3 * (int64_t)m.edges[2 * i + 1]];
+        double d[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+        double ell = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!m.wall_edge[i]) e[i] = ell * sigma_e * we[i];
+        double av = bz * 0.5 * (pa[0] + pb[0]) * d[1] + k * ell * ell * wa[i];
+        a[i] = (int64_t)std::llrint(av / c->phys.u_b);
+    }
+    for (int64_t f = 0; f < m.Nf; ++f) {
+        const int32_t *fe = &m.face_edges[3 * f];
+        b[f] = a[fe[2]] - a[fe[1]] + a[fe[0]];
+    }
+    return set_fields(c, e.data(), b.data());
+}
+
+int qh_species_add(qh_ctx *c, double q_over_m, int32_t z, int32_t *sid) {
+    if (!c || !sid) return QH_EINVAL;
+    if (z == 0 || std::abs(z) > 64) return qh_fail(c, QH_EINVAL, "charge number must be in [-64, 64], nonzero");
+    Species s;
+    s.qm = q_over_m;
+    s.z = z;
+    c->species.push_back(s);
+    *sid = (int32_t)c->species.size() - 1;
+    return QH_OK;
+}
+
+int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet) {
+    if (!c || sid < 0 || sid >= (int32_t)c->species.size() || n < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (n > 0 && (!x || !v || !tet)) return QH_EINVAL;
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (n >= ((int64_t)1 << 31)) return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles per species");
+    for (int64_t i = 0; i < n; ++i)
+        if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    Species &s = c->species[sid];
+    int rc;
+    if (n > s.cap) {
+        float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
+        for (auto p : fs)
+            if ((rc = qh_alloc(c, p, n))) return rc;
+        int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
+        for (auto p : is)
+            if ((rc = qh_alloc(c, p, n))) return rc;
+        s.cap = n;
+    }
+    s.n = n;
+    if (n > 0) {
+        std::vector<float> comp(n);
+        float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+        for (int k = 0; k < 6; ++k) {
+            const float *src = k < 3 ? x : v;
+            int d = k % 3;
+            for (int64_t i = 0; i < n; ++i) comp[i] = src[3 * i + d];
+            QH_HIP(c, hipMemcpyAsync(dst[k], comp.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
+        std::vector<int32_t> ids(n);
+        std::iota(ids.begin(), ids.end(), 0);
+        QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        if ((rc = qh_sort_species(c, s))) return rc;
+    }
+    return recompute_charge(c);
+}
+
+int qh_particles_download(const qh_ctx *cc, int32_t sid, float *x, float *v, int32_t *tet) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c || sid < 0 || sid >= (int32_t)c->species.size()) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    const Species &s = c->species[sid];
+    int64_t n = s.n;
+    if (n == 0) return QH_OK;
+    std::vector<int32_t> ids(n), tt(n);
+    std::vector<float> comp(6 * n);
+    const float *src[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+    for (int k = 0; k < 6; ++k)
+        QH_HIP(c, hipMemcpyAsync(comp.data() + k * n, src[k], sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipMemcpyAsync(ids.data(), s.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipMemcpyAsync(tt.data(), s.tet, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = ids[i];
+        if (x)
+            for (int d = 0; d < 3; ++d) x[3 * j + d] = comp[d * n + i];
+        if (v)
+            for (int d = 0; d < 3; ++d) v[3 * j + d] = comp[(3 + d) * n + i];
+        if (tet) tet[j] = tt[i];
+    }
+    return QH_OK;
+}
+
+int qh_charge_background(qh_ctx *c, int32_t mode) {
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (mode == 0) QH_HIP(c, hipMemsetAsync(c->Q_bg, 0, sizeof(int64_t) * c->hm.Nn, c->stream));
+    else if (mode == 1) QH_HIP(c, hipMemcpyAsync(c->Q_bg, c->Q, sizeof(int64_t) * c->hm.Nn, hipMemcpyDeviceToDevice, c->stream));
+    else return qh_fail(c, QH_EINVAL, "background mode must be 0 or 1");
+    return sync(c);
+}
+
+int qh_capture_segments(qh_ctx *c, int64_t cap) {
+    if (!c || cap < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (cap > c->cap_segments) {
+        int rc;
+        if ((rc = qh_alloc(c, &c->seg_buf, 12 * cap))) return rc;
+        if (!c->seg_count && (rc = qh_alloc(c, &c->seg_count, 1))) return rc;
+        c->cap_segments = cap;
+    }
+    if (!c->seg_count) {
+        int rc;
+        if ((rc = qh_alloc(c, &c->seg_count, 1))) return rc;
+    }
+    QH_HIP(c, hipMemsetAsync(c->seg_count, 0, sizeof(unsigned long long), c->stream));
+    c->capture_next = cap > 0;
+    return sync(c);
+}
+
+int qh_segments_download(const qh_ctx *cc, int64_t *n_out, int32_t *pid, int32_t *sp, int32_t *seq, int32_t *tet,
+                         int32_t *lam0, int32_t *lam1) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c || !n_out) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->seg_count) {
+        *n_out = 0;
+        return QH_OK;
+    }
+    unsigned long long cnt = 0;
+    QH_HIP(c, hipMemcpyAsync(&cnt, c->seg_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    *n_out = (int64_t)cnt;
+    int64_t k = std::min<int64_t>((int64_t)cnt, c->cap_segments);
+    std::vector<int32_t> buf(12 * std::max<int64_t>(k, 1));
+    if (k > 0) QH_HIP(c, hipMemcpyAsync(buf.data(), c->seg_buf, sizeof(int32_t) * 12 * k, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < k; ++i) {
+        const int32_t *o = &buf[12 * i];
+        if (pid) pid[i] = o[0];
+        if (sp) sp[i] = o[1];
+        if (seq) seq[i] = o[2];
+        if (tet) tet[i] = o[3];
+        for (int q = 0; q < 4; ++q) {
+            if (lam0) lam0[4 * i + q] = o[4 + q];
+            if (lam1) lam1[4 * i + q] = o[8 + q];
+        }
+    }
+    return QH_OK;
+}
+
+int qh_deposits_download(const qh_ctx *cc, int64_t *g, int64_t *Q) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (g) QH_HIP(c, hipMemcpyAsync(g, c->g, sizeof(int64_t) * c->hm.Ne, hipMemcpyDeviceToHost, c->stream));
+    if (Q) QH_HIP(c, hipMemcpyAsync(Q, c->Q, sizeof(int64_t) * c->hm.Nn, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_deposit(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *lam0, const int32_t *lam1,
+               const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet, const int32_t *pt_lam, const int32_t *pt_z,
+               int64_t *g_out, int64_t *q_out) {
+    if (!c || n_seg < 0 || n_pt < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (n_seg > 0 && (!seg_tet || !lam0 || !lam1 || !seg_z)) return QH_EINVAL;
+    if (n_pt > 0 && (!pt_tet || !pt_lam || !pt_z)) return QH_EINVAL;
+    const HostMesh &m = c->hm;
+    for (int64_t s = 0; s < n_seg; ++s)
+        if (seg_tet[s] < 0 || seg_tet[s] >= m.Nt) return qh_fail(c, QH_EINVAL, "segment tet out of range");
+    for (int64_t p = 0; p < n_pt; ++p)
+        if (pt_tet[p] < 0 || pt_tet[p] >= m.Nt) return qh_fail(c, QH_EINVAL, "point tet out of range");
+    int32_t *d = nullptr;
+    int64_t *gd = nullptr, *qd = nullptr;
+    size_t ni = (size_t)(9 * n_seg + 6 * n_pt) + 1;
+    if (hipMalloc((void **)&d, ni * sizeof(int32_t)) != hipSuccess) return qh_fail(c, QH_ENOMEM, "deposit buffers");
+    if (hipMalloc((void **)&gd, (m.Ne + m.Nn) * sizeof(int64_t)) != hipSuccess) {
+        (void)hipFree(d);
+        return qh_fail(c, QH_ENOMEM, "deposit buffers");
+    }
+    qd = gd + m.Ne;
+    int32_t *st = d, *l0 = st + n_seg, *l1 = l0 + 4 * n_seg, *sz = l1 + 4 * n_seg;
+    int32_t *pt = sz + n_seg, *pl = pt + n_pt, *pz = pl + 4 * n_pt;
+    hipError_t e = hipSuccess;
+    auto cp = [&](int32_t *dst, const int32_t *src, int64_t k) {
+        if (k > 0 && e == hipSuccess) e = hipMemcpyAsync(dst, src, sizeof(int32_t) * k, hipMemcpyHostToDevice, c->stream);
+    };
+    cp(st, seg_tet, n_seg); cp(l0, lam0, 4 * n_seg); cp(l1, lam1, 4 * n_seg); cp(sz, seg_z, n_seg);
+    cp(pt, pt_tet, n_pt); cp(pl, pt_lam, 4 * n_pt); cp(pz, pt_z, n_pt);
+    if (e == hipSuccess) e = hipMemsetAsync(gd, 0, (m.Ne + m.Nn) * sizeof(int64_t), c->stream);
+    if (e == hipSuccess) e = launch_deposit_lists(c, n_seg, st, l0, l1, sz, n_pt, pt, pl, pz, gd, qd);
+    if (e == hipSuccess && g_out) e = hipMemcpyAsync(g_out, gd, sizeof(int64_t) * m.Ne, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && q_out) e = hipMemcpyAsync(q_out, qd, sizeof(int64_t) * m.Nn, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    (void)hipFree(gd);
+    if (e != hipSuccess) return qh_fail(c, QH_EHIP, std::string("deposit: ") + hipGetErrorString(e));
+    return QH_OK;
+}
+
+int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_stats_t *stats) {
+    if (!c || !P || n_steps < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh || !c->have_phys || !c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    if (!c->have_fields) return qh_fail(c, QH_ESTATE, "fields first");
+    if (P->field_mode != QH_FIELDS_FROZEN && P->field_mode != QH_FIELDS_SOLVE) return qh_fail(c, QH_EINVAL, "field_mode");
+    if (P->precond != QH_PC_JACOBI) return qh_fail(c, QH_EINVAL, "preconditioner not available");
+    const HostMesh &m = c->hm;
+    int status = QH_OK;
+    hipEvent_t ev[4];
+    bool use_ev = stats != nullptr;
+    if (use_ev)
+        for (auto &x : ev) QH_HIP(c, hipEventCreate(&x));
+    for (int32_t st = 0; st < n_steps; ++st) {
+        bool capture = c->capture_next;
+        c->capture_next = false;
+        if (use_ev) QH_HIP(c, hipEventRecord(ev[0], c->stream));
+        if (c->fields_dirty || P->field_mode == QH_FIELDS_SOLVE) {
+            int t0 = qh_tbeg(c);
+            launch_field_prep(c);
+            qh_tend(c, t0, QK_FIELD_PREP);
+            c->fields_dirty = false;
+        }
+        std::swap(c->Q, c->Q_old);
+        QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * m.Nn, c->stream));
+        QH_HIP(c, hipMemsetAsync(c->g, 0, sizeof(int64_t) * m.Ne, c->stream));
+        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * 8, c->stream));
+        for (size_t k = 0; k < c->species.size(); ++k) {
+            int t0 = qh_tbeg(c);
+            QH_HIP(c, launch_particle_step(c, c->species[k], (int)k, capture));
+            qh_tend(c, t0, QK_PARTICLE);
+        }
+        if (P->sort_every > 0 && (c->step_index + 1) % P->sort_every == 0)
+            for (auto &s : c->species) {
+                int t0 = qh_tbeg(c);
+                int rc = qh_sort_species(c, s);
+                if (rc) return rc;
+                qh_tend(c, t0, QK_SORT);
+            }
+        if (use_ev) QH_HIP(c, hipEventRecord(ev[1], c->stream));
+        SolveResult se, sn;
+        double gauss_out[3] = {0, 0, 0};
+        if (P->field_mode == QH_FIELDS_SOLVE) {
+            QH_HIP(c, hipMemcpyAsync(c->e_old, c->cge.x, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
+            int t0 = qh_tbeg(c);
+            QH_HIP(c, launch_edge_rhs(c));
+            qh_tend(c, t0, QK_EDGE_RHS);
+            int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr);
+            if (rc) return rc;
+            if (!se.converged) status = QH_ENOTCONV;
+            if (P->gauss) {
+                t0 = qh_tbeg(c);
+                QH_HIP(c, launch_gauss_rhs(c, c->scratch_d, P->tol_node));
+                QH_HIP(c, hipMemsetAsync(c->cgn.x, 0, sizeof(double) * c->K.n, c->stream));
+                qh_tend(c, t0, QK_GAUSS);
+                rc = qh_cg_solve(c, c->K, c->cgn, P->tol_node, P->max_it_node, P->check_every, sn, c->scratch_d);
+                if (rc) return rc;
+                if (!sn.converged) status = QH_ENOTCONV;
+                t0 = qh_tbeg(c);
+                QH_HIP(c, launch_gauss_apply(c));
+                qh_tend(c, t0, QK_GAUSS);
+            }
+            int t1 = qh_tbeg(c);
+            QH_HIP(c, launch_faraday(c));
+            qh_tend(c, t1, QK_FARADAY);
+            if (stats) {
+                // Gauss residual after the update (reuses the node right-hand-side buffer)
+                QH_HIP(c, launch_gauss_rhs(c, c->scratch_d + 4, P->tol_node));
+                QH_HIP(c, hipMemcpyAsync(gauss_out, c->scratch_d + 4, sizeof(gauss_out), hipMemcpyDeviceToHost, c->stream));
+            }
+        }
+        if (P->verify) QH_HIP(c, launch_verify(c, true));
+        if (use_ev) QH_HIP(c, hipEventRecord(ev[2], c->stream));
+        if (stats) {
+            unsigned long long cnt[8];
+            QH_HIP(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+            qh_step_stats_t &S = stats[st];
+            std::memset(&S, 0, sizeof(S));
+            S.edge_iters = se.iters;
+            S.node_iters = sn.iters;
+            S.edge_res = se.res;
+            S.node_res = sn.res;
+            S.gauss_res = gauss_out[1] > 0 ? std::sqrt(gauss_out[2]) / gauss_out[1] : 0.0;
+            S.crossings = (int64_t)cnt[0];
+            S.wall_hits = (int64_t)cnt[1];
+            S.lost = (int64_t)cnt[2];
+            S.continuity_bad = P->verify ? (int64_t)cnt[3] : -1;
+            S.divb_bad = P->verify ? (int64_t)cnt[4] : -1;
+            (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
+            if (S.lost && status == QH_OK) status = QH_ELOST;
+        }
+        qh_tflush(c);
+        c->step_index++;
+    }
+    if (use_ev)
+        for (auto &x : ev) (void)hipEventDestroy(x);
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    if (status == QH_ENOTCONV) c->err = "a Krylov solve hit its iteration cap";
+    if (status == QH_ELOST) c->err = "a particle hit the walk cap";
+    return status;
+}
+
+int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, double tol, int32_t max_it,
+                   int32_t precond, qh_solve_stats_t *stats) {
+    if (!c || !rhs || !x || max_it < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    if (precond != QH_PC_JACOBI) return qh_fail(c, QH_EINVAL, "preconditioner not available");
+    const DevCsr *M = system == QH_SYS_EDGE ? &c->A : system == QH_SYS_NODE ? &c->K : nullptr;
+    if (!M) return qh_fail(c, QH_EINVAL, "system must be QH_SYS_EDGE or QH_SYS_NODE");
+    int rc;
+    int32_t nmax = std::max(c->A.n, c->K.n);
+    if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
+    CgWork w = c->cgx;
+    w.n = M->n;
+    QH_HIP(c, hipMemcpyAsync(w.b, rhs, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemcpyAsync(w.x, x, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, launch_diag_inv(c, *M, w.dinv));
+    hipEvent_t e0, e1;
+    QH_HIP(c, hipEventCreate(&e0));
+    QH_HIP(c, hipEventCreate(&e1));
+    QH_HIP(c, hipEventRecord(e0, c->stream));
+    SolveResult r;
+    rc = qh_cg_solve(c, *M, w, tol, max_it, 8, r, nullptr);
+    QH_HIP(c, hipEventRecord(e1, c->stream));
+    if (rc) return rc;
+    QH_HIP(c, hipMemcpyAsync(x, w.x, sizeof(double) * w.n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    if (stats) {
+        stats->iters = r.iters;
+        stats->res = r.res;
+        stats->fallback = 0;
+        (void)hipEventElapsedTime(&stats->ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r.converged ? QH_OK : qh_fail(c, QH_ENOTCONV, "iteration cap reached");
+}
+
+int qh_matrix_info(const qh_ctx *c, int32_t which, int64_t *nrow, int64_t *ncol, int64_t *nnz) {
+    if (!c || !nrow || !ncol || !nnz) return QH_EINVAL;
+    if (!c->assembled) return QH_ESTATE;
+    const HostCsr *h = which <= 2 ? &c->hA : which == 3 ? &c->hCMb : which == 4 ? &c->hGtM : which == 5 ? &c->hK : nullptr;
+    if (!h) return QH_EINVAL;
+    *nrow = h->nrow;
+    *ncol = h->ncol;
+    *nnz = (int64_t)h->col.size();
+    return QH_OK;
+}
+
+int qh_matrix_download(const qh_ctx *c, int32_t which, int32_t *ptr, int32_t *col, double *val) {
+    if (!c) return QH_EINVAL;
+    if (!c->assembled) return QH_ESTATE;
+    const HostCsr *h = which <= 2 ? &c->hA : which == 3 ? &c->hCMb : which == 4 ? &c->hGtM : which == 5 ? &c->hK : nullptr;
+    if (!h || which < 0) return QH_EINVAL;
+    if (ptr) std::copy(h->ptr.begin(), h->ptr.end(), ptr);
+    if (col) std::copy(h->col.begin(), h->col.end(), col);
+    if (val) {
+        double tau = 0.25 * c->phys.dt * c->phys.dt;
+        for (size_t j = 0; j < h->col.size(); ++j)
+            val[j] = which == 0 ? h->val[j] + tau * h->val2[j] : which == 2 ? h->val2[j] : h->val[j];
+    }
+    return QH_OK;
+}
+
+// Per-kernel timing with HIP events on the context stream (for roofline figures).
+int qh_timing_enable(qh_ctx *c, int32_t on) {
+    if (!c) return QH_EINVAL;
+    qh_tflush(c);
+    c->timing = on != 0;
+    for (int k = 0; k < 16; ++k) {
+        c->t_ms[k] = 0;
+        c->t_cnt[k] = 0;
+    }
+    return QH_OK;
+}
+
+int qh_timing_read(const qh_ctx *c, int32_t n, double *ms_total, int64_t *launches) {
+    if (!c || n < 0 || n > 16) return QH_EINVAL;
+    for (int k = 0; k < n; ++k) {
+        if (ms_total) ms_total[k] = c->t_ms[k];
+        if (launches) launches[k] = c->t_cnt[k];
+    }
+    return QH_OK;
+}
+
+}  // extern "C"

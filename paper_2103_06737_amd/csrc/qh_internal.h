@@ -1,0 +1,216 @@
+// Internal declarations shared by the libqh translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qh.h"
+
+constexpr int QH_FBITS = 20;                  // fixed-point bits of barycentric coordinates
+constexpr int QH_SCALE = 1 << QH_FBITS;
+constexpr int QH_MAX_PIECES = 64;             // straight pieces per particle per step
+
+// ---------------------------------------------------------------------------------------
+// Host-side mesh complex and FP64 assembly (qh_mesh.hip)
+struct HostCsr {
+    int64_t nrow = 0, ncol = 0;
+    std::vector<int32_t> ptr, col;
+    std::vector<double> val, val2;  // val2: second value array on the same pattern
+};
+
+struct HostMesh {
+    int64_t Nn = 0, Ne = 0, Nf = 0, Nt = 0;
+    std::vector<double> xyz;                    // 3*Nn
+    std::vector<int32_t> tn;                    // 4*Nt, ascending
+    std::vector<int32_t> te;                    // 6*Nt
+    std::vector<int32_t> tf;                    // 4*Nt
+    std::vector<int32_t> nbr;                   // 4*Nt
+    std::vector<int8_t> tsign;                  // Nt, orientation of the sorted tet
+    std::vector<int32_t> edges;                 // 2*Ne
+    std::vector<int32_t> faces;                 // 3*Nf
+    std::vector<int32_t> face_edges;            // 3*Nf: [ab, ac, bc]
+    std::vector<uint8_t> wall_edge, wall_node, wall_face;
+    std::vector<int32_t> int_edge_of, int_node_of;  // global -> interior index or -1
+    std::vector<int32_t> int_edges, int_nodes;      // interior index -> global
+    std::vector<double> grad;                   // 12*Nt: grad lambda_0..3
+    std::vector<double> vol;                    // Nt
+    std::vector<double> cen;                    // 3*Nt
+    // incidence lists
+    std::vector<int32_t> e2t_ptr, e2t;          // edge -> (tet*8 + local edge)
+    std::vector<int32_t> n2t_ptr, n2t;          // node -> (tet*4 + local vertex)
+    std::vector<int32_t> n2e_ptr, n2e;          // node -> signed edge (+(e+1) head, -(e+1) tail)
+};
+
+// Build topology + geometry. Returns empty string or an error message.
+std::string qh_build_mesh(HostMesh &m, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                          const int32_t *tet_nodes);
+// Assemble: A pattern with val=[*eps], val2=S (interior edges); CMb = C^T [*mu^-1]
+// (interior edges x all faces); GtM = G^T [*eps] (interior nodes x interior edges);
+// K = G^T [*eps] G (interior nodes).
+void qh_assemble(const HostMesh &m, double eps0, double mu0, HostCsr &A, HostCsr &CMb,
+                 HostCsr &GtM, HostCsr &K);
+
+// ---------------------------------------------------------------------------------------
+// Device containers
+struct DevCsr {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *ptr = nullptr, *col = nullptr;
+    double *val = nullptr;
+    double *val2 = nullptr;
+};
+
+struct Species {
+    double qm = 0.0;
+    int32_t z = 0;
+    int64_t n = 0, cap = 0;
+    float *x = nullptr, *y = nullptr, *zz = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
+    int32_t *tet = nullptr, *id = nullptr;
+    // sort scratch (same layout)
+    float *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
+    int32_t *stet = nullptr, *sid = nullptr;
+};
+
+// Krylov workspace for one system.
+struct CgWork {
+    int32_t n = 0;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
+    double *dinv = nullptr, *b = nullptr;
+    double *partial = nullptr;  // reduction partials
+    double *scal = nullptr;     // device scalars (see qh_solver.hip)
+    unsigned int *counter = nullptr;
+    int32_t *flags = nullptr;   // [0] done, [1] iterations
+};
+
+struct qh_ctx {
+    int device = 0;
+    bool host_only = false;  // device < 0: host mesh and assembly only (no GPU calls)
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool have_mesh = false, have_phys = false, have_fields = false;
+
+    HostMesh hm;
+    HostCsr hA, hCMb, hGtM, hK;
+    qh_phys_t phys{};
+
+    // device mesh records
+    float4 *geo = nullptr;       // 3*Nt: (g1, cx) (g2, cy) (g3, cz), FP32
+    int4 *tnodes = nullptr;      // Nt
+    int32_t *tedges = nullptr;   // 8*Nt (6 used)
+    int4 *tnbr = nullptr;        // Nt
+    int32_t *tfaces = nullptr;   // 4*Nt
+    int8_t *tsign = nullptr;     // Nt
+    float4 *frec = nullptr;      // 3*Nt: (alpha, beta_x) (beta_y, beta_z, B_x, B_y) (B_z, -, -, -)
+    int32_t *face_edges = nullptr;  // 3*Nf
+    int32_t *int_edges = nullptr;   // interior -> global edge
+    int32_t *int_nodes = nullptr;   // interior -> global node
+    int32_t *int_node_of = nullptr; // global node -> interior or -1
+    int32_t *edge_nodes = nullptr;  // 2*Ne
+    int32_t *n2e_ptr = nullptr, *n2e = nullptr;
+
+    DevCsr A, CMb, GtM, K;  // A: val = [*eps] + tau S, val2 = [*eps]
+    double *A_S = nullptr;  // S values on the pattern of A
+    double tau_assembled = -1.0;
+    bool assembled = false;
+
+    // fields and deposits
+    double *e = nullptr;                    // Ne (wall entries 0)
+    double *e_old = nullptr;                // interior edges: e^n during a field update
+    int64_t *b = nullptr;                   // Nf
+    int64_t *g = nullptr;                   // Ne
+    int64_t *Q = nullptr, *Q_old = nullptr, *Q_bg = nullptr;  // Nn
+    int64_t *divb0 = nullptr;               // Nt
+    int64_t *u_int = nullptr;               // Ne (Faraday increments)
+    double *rhs_e = nullptr, *rho = nullptr;  // interior edges, interior nodes
+
+    CgWork cge, cgn;            // cge.x holds e on the interior edges between steps
+    CgWork cgx;                 // standalone solves (qh_field_solve)
+    double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
+    unsigned long long *counters = nullptr;  // [0] crossings [1] wall hits [2] lost [3] bad
+    int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
+
+    std::vector<Species> species;
+
+    // segment capture
+    int64_t cap_segments = 0;
+    bool capture_next = false;
+    unsigned long long *seg_count = nullptr;
+    int32_t *seg_buf = nullptr;  // cap * 12 ints: pid species seq tet lam0[4] lam1[4]
+
+    int64_t step_index = 0;
+    bool fields_dirty = true;
+    std::vector<void *> allocations;
+
+    // optional per-kernel timing with HIP events on the context stream
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { int slot; int kernel; };
+    std::vector<Pending> pending;
+    double t_ms[16] = {0};
+    int64_t t_cnt[16] = {0};
+};
+
+// kernel ids of the timing table
+enum {
+    QK_FIELD_PREP = 0, QK_PARTICLE, QK_SORT, QK_EDGE_RHS, QK_CG_SPMV, QK_CG_UPDATE, QK_CG_INIT,
+    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NKERNELS
+};
+int qh_tbeg(qh_ctx *c);
+void qh_tend(qh_ctx *c, int slot, int kernel);
+void qh_tflush(qh_ctx *c);
+
+// error helpers
+int qh_fail(qh_ctx *c, int code, const std::string &msg);
+#define QH_HIP(c, call)                                                                   \
+    do {                                                                                  \
+        hipError_t _e = (call);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return qh_fail((c), QH_EHIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <class T>
+int qh_alloc(qh_ctx *c, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) return qh_fail(c, QH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->allocations.push_back((void *)*p);
+    return QH_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernel launchers
+// qh_particles.hip
+void launch_field_prep(qh_ctx *c);
+hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture);
+hipError_t launch_charge_deposit(qh_ctx *c, Species &s);
+int qh_sort_species(qh_ctx *c, Species &s);
+hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet,
+                                const int32_t *l0, const int32_t *l1, const int32_t *sz,
+                                int64_t n_pt, const int32_t *pt_tet, const int32_t *pl,
+                                const int32_t *pz, int64_t *g, int64_t *Q);
+hipError_t launch_verify(qh_ctx *c, bool check_divb);
+hipError_t launch_divb(qh_ctx *c, int64_t *out);
+
+// qh_solver.hip
+struct SolveResult {
+    int iters = 0;
+    double res = 0.0;
+    bool converged = false;
+};
+int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
+// Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.
+int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
+                SolveResult &out, const double *abs_thr2_dev);
+hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);
+hipError_t launch_assemble_A(qh_ctx *c, double tau);
+hipError_t launch_edge_rhs(qh_ctx *c);
+hipError_t launch_gauss_rhs(qh_ctx *c, double *thr2_dev, double tol_n);
+hipError_t launch_gauss_apply(qh_ctx *c);
+hipError_t launch_faraday(qh_ctx *c);
+hipError_t launch_true_residual(qh_ctx *c, const DevCsr &M, const double *x, const double *b,
+                                double *out2 /* [0] ||b-Ax||^2 [1] ||b||^2 */);
+hipError_t launch_gauss_check(qh_ctx *c, double *out3);

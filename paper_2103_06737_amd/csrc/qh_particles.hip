@@ -1,0 +1,545 @@
+// Particle half of the PIC cycle on gfx950: per-tet field records, the fused
+// gather -> Boris -> tet walk -> integer deposit kernel, and the counting sort by tet.
+//
+// Gather (Sec. II.C): E = sum e_i W1_i is affine inside a tet, E(r) = alpha + beta x (r - c)
+// with alpha = E(c) = sum e_ab (grad l_b - grad l_a)/4 and beta = sum e_ab grad l_a x grad l_b;
+// B = sum b_f W2_f is constant inside a tet whenever D b = 0 there (the integer Faraday update
+// keeps D b = 0 exactly), B = sum b_f W2_f(c) with W2_abc(c) = (grad l_b - grad l_a) x
+// (grad l_c - grad l_a) / 2. Both are computed once per tet per step (field_prep) and read by
+// every particle of the tet.
+//
+// Deposit (Sec. IV.B.1): the time-integrated current of a particle is the path integral of W1
+// along its path. For a straight piece inside a tet, int W1_ab . dl = l_a(r0) l_b(r1) -
+// l_a(r1) l_b(r0); with coordinates quantised to 2^-20 (summing to exactly 2^20, carried across
+// faces by vertex id) the piece adds z (L_a^0 L_b^1 - L_a^1 L_b^0) to edge a->b and the end
+// point adds z 2^20 L_n to node n. G^T g then telescopes to Q^{n+1} - Q^n in int64: discrete
+// continuity holds bit for bit and the sums are independent of order.
+#include "qh_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWin = 128;  // LDS tet window per block (particles are sorted by tet)
+
+__device__ __forceinline__ void lam4(const float4 A, const float4 B, const float4 C, float x,
+                                     float y, float z, float l[4]) {
+    float dx = x - A.w, dy = y - B.w, dz = z - C.w;
+    l[1] = __fmaf_rn(A.x, dx, __fmaf_rn(A.y, dy, __fmaf_rn(A.z, dz, 0.25f)));
+    l[2] = __fmaf_rn(B.x, dx, __fmaf_rn(B.y, dy, __fmaf_rn(B.z, dz, 0.25f)));
+    l[3] = __fmaf_rn(C.x, dx, __fmaf_rn(C.y, dy, __fmaf_rn(C.z, dz, 0.25f)));
+    l[0] = __fsub_rn(__fsub_rn(__fsub_rn(1.0f, l[1]), l[2]), l[3]);
+}
+
+// Fixed point: round half to even, clamp to [0, 2^F], the largest coordinate (first on
+// ties) absorbs the remainder so the four sum to 2^F. forced >= 0 pins that one to 0.
+__device__ __forceinline__ void quantize(const float l[4], int forced, int L[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float q = rintf(l[i] * (float)QH_SCALE);
+        q = fminf(fmaxf(q, 0.0f), (float)QH_SCALE);
+        L[i] = (i == forced) ? 0 : (int)q;
+    }
+    int im = 0;
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+        if (L[i] > L[im]) im = i;
+    int rest = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (i != im) rest += L[i];
+    L[im] = QH_SCALE - rest;
+}
+
+__device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
+__device__ __forceinline__ void atomic_add_lds(long long *p, long long v) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
+struct StepArgs {
+    const float4 *geo;
+    const float4 *frec;
+    const int4 *tnodes;
+    const int32_t *tedges;
+    const int4 *tnbr;
+    float *x, *y, *z, *vx, *vy, *vz;
+    int32_t *tet;
+    const int32_t *pid;
+    int64_t n;
+    int32_t nt;
+    float hqm;   // q/m * dt / 2
+    float dt;
+    int32_t zq;  // charge number
+    int64_t *g, *Q;
+    unsigned long long *counters;
+    // capture
+    int32_t species;
+    int64_t cap;
+    unsigned long long *seg_count;
+    int32_t *seg_buf;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Field records: (alpha.xyz, beta.x) (beta.y, beta.z, B.x, B.y) (B.z, 0, 0, 0)
+__global__ void __launch_bounds__(256) k_field_prep(const float4 *__restrict__ geo,
+                                                    const int32_t *__restrict__ tedges,
+                                                    const int32_t *__restrict__ tfaces,
+                                                    const double *__restrict__ e,
+                                                    const int64_t *__restrict__ b, double u_b,
+                                                    int32_t nt, float4 *__restrict__ frec) {
+    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    float4 A = geo[3 * t], B = geo[3 * t + 1], C = geo[3 * t + 2];
+    double g[4][3];
+    g[1][0] = A.x; g[1][1] = A.y; g[1][2] = A.z;
+    g[2][0] = B.x; g[2][1] = B.y; g[2][2] = B.z;
+    g[3][0] = C.x; g[3][1] = C.y; g[3][2] = C.z;
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    const int LF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    double al[3] = {0, 0, 0}, be[3] = {0, 0, 0}, Bf[3] = {0, 0, 0};
+    for (int k = 0; k < 6; ++k) {
+        double c = e[tedges[8 * t + k]];
+        const double *ga = g[LE[k][0]], *gb = g[LE[k][1]];
+        double cx = ga[1] * gb[2] - ga[2] * gb[1];
+        double cy = ga[2] * gb[0] - ga[0] * gb[2];
+        double cz = ga[0] * gb[1] - ga[1] * gb[0];
+        al[0] += 0.25 * c * (gb[0] - ga[0]);
+        al[1] += 0.25 * c * (gb[1] - ga[1]);
+        al[2] += 0.25 * c * (gb[2] - ga[2]);
+        be[0] += c * cx; be[1] += c * cy; be[2] += c * cz;
+    }
+    for (int k = 0; k < 4; ++k) {
+        double c = (double)b[tfaces[4 * t + k]] * u_b;
+        const double *ga = g[LF[k][0]], *gb = g[LF[k][1]], *gc = g[LF[k][2]];
+        double u[3] = {gb[0] - ga[0], gb[1] - ga[1], gb[2] - ga[2]};
+        double w[3] = {gc[0] - ga[0], gc[1] - ga[1], gc[2] - ga[2]};
+        Bf[0] += 0.5 * c * (u[1] * w[2] - u[2] * w[1]);
+        Bf[1] += 0.5 * c * (u[2] * w[0] - u[0] * w[2]);
+        Bf[2] += 0.5 * c * (u[0] * w[1] - u[1] * w[0]);
+    }
+    frec[3 * t] = make_float4((float)al[0], (float)al[1], (float)al[2], (float)be[0]);
+    frec[3 * t + 1] = make_float4((float)be[1], (float)be[2], (float)Bf[0], (float)Bf[1]);
+    frec[3 * t + 2] = make_float4((float)Bf[2], 0.f, 0.f, 0.f);
+}
+
+void launch_field_prep(qh_ctx *c) {
+    int32_t nt = (int32_t)c->hm.Nt;
+    hipLaunchKernelGGL(k_field_prep, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->geo,
+                       c->tedges, c->tfaces, c->e, c->b, c->phys.u_b, nt, c->frec);
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused particle step. One thread per particle; a block accumulates deposits of tets in
+// [tbase, tbase + kWin) in LDS (int64, order-free) and flushes them once; other tets go
+// straight to global int64 atomics.
+template <bool CAPTURE>
+__global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
+    __shared__ long long acc[kWin * 10];
+    __shared__ int s_tbase;
+    __shared__ unsigned int s_cnt[3];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int j = threadIdx.x; j < kWin * 10; j += kBlock) acc[j] = 0;
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        int64_t i0 = (int64_t)blockIdx.x * kBlock;
+        s_tbase = a.tet[i0];
+    }
+    __syncthreads();
+    const int tbase = s_tbase;
+    unsigned int n_cross = 0, n_wall = 0, n_lost = 0;
+
+    if (i < a.n) {
+        float px = a.x[i], py = a.y[i], pz = a.z[i];
+        float vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+        int t = a.tet[i];
+        const int32_t zq = a.zq;
+        int32_t pid = 0;
+        if (CAPTURE) pid = a.pid[i];
+        int seq = 0;
+
+        auto deposit = [&](int tt, const int L0[4], const int L1[4]) {
+            const int LE0[6] = {0, 0, 0, 1, 1, 2};
+            const int LE1[6] = {1, 2, 3, 2, 3, 3};
+            int slot = tt - tbase;
+            bool local = (unsigned)slot < (unsigned)kWin;
+            const int32_t *te = a.tedges + 8 * (int64_t)tt;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                long long v = (long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]];
+                v *= zq;
+                if (v == 0) continue;
+                if (local) atomic_add_lds(&acc[slot * 10 + k], v);
+                else atomic_add_i64(a.g + te[k], v);
+            }
+            if (CAPTURE) {
+                unsigned long long s = atomicAdd(a.seg_count, 1ull);
+                if ((int64_t)s < a.cap) {
+                    int32_t *o = a.seg_buf + 12 * s;
+                    o[0] = pid; o[1] = a.species; o[2] = seq; o[3] = tt;
+                    for (int q = 0; q < 4; ++q) { o[4 + q] = L0[q]; o[8 + q] = L1[q]; }
+                }
+            }
+            ++seq;
+        };
+
+        // gather at x^n
+        float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
+        float4 F0 = a.frec[3 * t], F1 = a.frec[3 * t + 1], F2 = a.frec[3 * t + 2];
+        float dx = px - A.w, dy = py - B.w, dz = pz - C.w;
+        // E = alpha + beta x (r - c)
+        float Ex = F0.x + (F1.x * dz - F1.y * dy);
+        float Ey = F0.y + (F1.y * dx - F0.w * dz);
+        float Ez = F0.z + (F0.w * dy - F1.x * dx);
+        float Bx = F1.z, By = F1.w, Bz = F2.x;
+        // Boris
+        const float h = a.hqm;
+        float mx = vx + h * Ex, my = vy + h * Ey, mz = vz + h * Ez;
+        float tx = h * Bx, ty = h * By, tz = h * Bz;
+        float s2 = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+        float sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
+        float qx = mx + (my * tz - mz * ty);
+        float qy = my + (mz * tx - mx * tz);
+        float qz = mz + (mx * ty - my * tx);
+        vx = mx + (qy * sz - qz * sy) + h * Ex;
+        vy = my + (qz * sx - qx * sz) + h * Ey;
+        vz = mz + (qx * sy - qy * sx) + h * Ez;
+        float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
+
+        // tet walk along x^n -> x^n + dt v^{n+1/2}
+        float l[4];
+        int Lp[4], Lc[4];
+        lam4(A, B, C, px, py, pz, l);
+        quantize(l, -1, Lp);
+        int entry = -1, pieces = 0;
+        for (;;) {
+            float gl[4];
+            gl[1] = A.x * rx + A.y * ry + A.z * rz;
+            gl[2] = B.x * rx + B.y * ry + B.z * rz;
+            gl[3] = C.x * rx + C.y * ry + C.z * rz;
+            gl[0] = -(gl[1] + gl[2] + gl[3]);
+            lam4(A, B, C, px, py, pz, l);
+            int k = -1;
+            float smin = 2.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q == entry) continue;
+                float le = l[q] + gl[q];
+                if (!(le < 0.0f)) continue;
+                float s = l[q] <= 0.0f ? 0.0f : l[q] / (l[q] - le);
+                if (s < smin) { smin = s; k = q; }
+            }
+            if (k < 0) { px += rx; py += ry; pz += rz; break; }
+            if (pieces >= QH_MAX_PIECES - 1) { ++n_lost; break; }
+            float cx = __fmaf_rn(smin, rx, px), cy = __fmaf_rn(smin, ry, py), cz = __fmaf_rn(smin, rz, pz);
+            lam4(A, B, C, cx, cy, cz, l);
+            quantize(l, k, Lc);
+            deposit(t, Lp, Lc);
+            ++pieces;
+            float rem = 1.0f - smin;
+            rx *= rem; ry *= rem; rz *= rem;
+            px = cx; py = cy; pz = cz;
+            int4 nb4 = a.tnbr[t];
+            int nb = k == 0 ? nb4.x : k == 1 ? nb4.y : k == 2 ? nb4.z : nb4.w;
+            if (nb >= 0) {
+                int4 on = a.tnodes[t], nn = a.tnodes[nb];
+                int ov[4] = {on.x, on.y, on.z, on.w}, nv[4] = {nn.x, nn.y, nn.z, nn.w};
+                int fresh = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int val = 0, found = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (ov[q] == nv[j]) { val = Lc[q]; found = 1; }
+                    Lp[j] = val;
+                    if (!found) fresh = j;
+                }
+                entry = fresh;
+                t = nb;
+                A = a.geo[3 * t]; B = a.geo[3 * t + 1]; C = a.geo[3 * t + 2];
+                ++n_cross;
+            } else {
+                // specular reflection at an axis-aligned wall: the wall normal is grad l_k
+                float nx, ny, nz;
+                if (k == 0) { nx = -(A.x + B.x + C.x); ny = -(A.y + B.y + C.y); nz = -(A.z + B.z + C.z); }
+                else if (k == 1) { nx = A.x; ny = A.y; nz = A.z; }
+                else if (k == 2) { nx = B.x; ny = B.y; nz = B.z; }
+                else { nx = C.x; ny = C.y; nz = C.z; }
+                float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
+                if (ax >= ay && ax >= az) { rx = -rx; vx = -vx; }
+                else if (ay >= az) { ry = -ry; vy = -vy; }
+                else { rz = -rz; vz = -vz; }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Lp[q] = Lc[q];
+                entry = k;
+                ++n_wall;
+            }
+        }
+        int Le[4];
+        lam4(A, B, C, px, py, pz, l);
+        quantize(l, -1, Le);
+        deposit(t, Lp, Le);
+        {
+            int slot = t - tbase;
+            int4 tn = a.tnodes[t];
+            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+            bool local = (unsigned)slot < (unsigned)kWin;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                long long v = (long long)zq * QH_SCALE * Le[q];
+                if (v == 0) continue;
+                if (local) atomic_add_lds(&acc[slot * 10 + 6 + q], v);
+                else atomic_add_i64(a.Q + nv[q], v);
+            }
+        }
+        a.x[i] = px; a.y[i] = py; a.z[i] = pz;
+        a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+        a.tet[i] = t;
+    }
+    if (n_cross) atomicAdd(&s_cnt[0], n_cross);
+    if (n_wall) atomicAdd(&s_cnt[1], n_wall);
+    if (n_lost) atomicAdd(&s_cnt[2], n_lost);
+    __syncthreads();
+    // flush the window
+    for (int j = threadIdx.x; j < kWin * 10; j += kBlock) {
+        long long v = acc[j];
+        if (v == 0) continue;
+        int slot = j / 10, c = j % 10;
+        int tt = tbase + slot;
+        if (c < 6) atomic_add_i64(a.g + a.tedges[8 * (int64_t)tt + c], v);
+        else {
+            int4 tn = a.tnodes[tt];
+            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+            atomic_add_i64(a.Q + nv[c - 6], v);
+        }
+    }
+    if (threadIdx.x < 3 && s_cnt[threadIdx.x]) atomicAdd(&a.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
+    if (s.n == 0) return hipSuccess;
+    StepArgs a;
+    a.geo = c->geo; a.frec = c->frec; a.tnodes = c->tnodes; a.tedges = c->tedges; a.tnbr = c->tnbr;
+    a.x = s.x; a.y = s.y; a.z = s.zz; a.vx = s.vx; a.vy = s.vy; a.vz = s.vz;
+    a.tet = s.tet; a.pid = s.id; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
+    a.hqm = (float)(0.5 * s.qm * c->phys.dt);
+    a.dt = (float)c->phys.dt;
+    a.zq = s.z;
+    a.g = c->g; a.Q = c->Q; a.counters = c->counters;
+    a.species = sidx; a.cap = c->cap_segments; a.seg_count = c->seg_count; a.seg_buf = c->seg_buf;
+    dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
+    if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// W0 charge of the present positions (after an upload).
+__global__ void __launch_bounds__(256) k_charge(const float4 *__restrict__ geo, const int4 *__restrict__ tnodes,
+                                                const float *__restrict__ x, const float *__restrict__ y,
+                                                const float *__restrict__ z, const int32_t *__restrict__ tet,
+                                                int64_t n, int32_t zq, int64_t *__restrict__ Q) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int t = tet[i];
+    float l[4];
+    int L[4];
+    lam4(geo[3 * t], geo[3 * t + 1], geo[3 * t + 2], x[i], y[i], z[i], l);
+    quantize(l, -1, L);
+    int4 tn = tnodes[t];
+    int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+    for (int q = 0; q < 4; ++q) atomic_add_i64(Q + nv[q], (long long)zq * QH_SCALE * L[q]);
+}
+
+hipError_t launch_charge_deposit(qh_ctx *c, Species &s) {
+    if (s.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_charge, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, c->stream, c->geo,
+                       c->tnodes, s.x, s.y, s.zz, s.tet, s.n, s.z, c->Q);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Integer deposit from explicit lists.
+__global__ void k_deposit_segments(const int32_t *__restrict__ tedges, int64_t n,
+                                   const int32_t *__restrict__ st, const int32_t *__restrict__ l0,
+                                   const int32_t *__restrict__ l1, const int32_t *__restrict__ sz,
+                                   int64_t *__restrict__ g) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int LE0[6] = {0, 0, 0, 1, 1, 2};
+    const int LE1[6] = {1, 2, 3, 2, 3, 3};
+    int t = st[s];
+    for (int k = 0; k < 6; ++k) {
+        long long v = (long long)l0[4 * s + LE0[k]] * l1[4 * s + LE1[k]] -
+                      (long long)l1[4 * s + LE0[k]] * l0[4 * s + LE1[k]];
+        v *= sz[s];
+        if (v) atomic_add_i64(g + tedges[8 * (int64_t)t + k], v);
+    }
+}
+
+__global__ void k_deposit_points(const int4 *__restrict__ tnodes, int64_t n, const int32_t *__restrict__ pt,
+                                 const int32_t *__restrict__ pl, const int32_t *__restrict__ pz,
+                                 int64_t *__restrict__ Q) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int4 tn = tnodes[pt[p]];
+    int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+    for (int q = 0; q < 4; ++q) atomic_add_i64(Q + nv[q], (long long)pz[p] * QH_SCALE * pl[4 * p + q]);
+}
+
+hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *l0,
+                                const int32_t *l1, const int32_t *sz, int64_t n_pt, const int32_t *pt_tet,
+                                const int32_t *pl, const int32_t *pz, int64_t *g, int64_t *Q) {
+    if (n_seg > 0)
+        hipLaunchKernelGGL(k_deposit_segments, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, c->stream,
+                           c->tedges, n_seg, seg_tet, l0, l1, sz, g);
+    if (n_pt > 0)
+        hipLaunchKernelGGL(k_deposit_points, dim3((unsigned)((n_pt + 255) / 256)), dim3(256), 0, c->stream,
+                           c->tnodes, n_pt, pt_tet, pl, pz, Q);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Invariants: continuity (G^T g == Q - Q_old at every node) and D b == D b0 in every tet.
+__global__ void k_continuity(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lst,
+                             const int64_t *__restrict__ g, const int64_t *__restrict__ Q,
+                             const int64_t *__restrict__ Qo, int64_t nn, unsigned long long *bad) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    int64_t s = 0;
+    for (int j = ptr[n]; j < ptr[n + 1]; ++j) {
+        int32_t v = lst[j];
+        s += v > 0 ? g[v - 1] : -g[-v - 1];
+    }
+    if (s != Q[n] - Qo[n]) atomicAdd(bad, 1ull);
+}
+
+__global__ void k_divb(const int32_t *__restrict__ tfaces, const int8_t *__restrict__ tsign,
+                       const int64_t *__restrict__ b, int32_t nt, int64_t *__restrict__ out,
+                       const int64_t *__restrict__ ref, unsigned long long *bad) {
+    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int64_t s = (int64_t)tsign[t] * (b[tfaces[4 * t]] - b[tfaces[4 * t + 1]] + b[tfaces[4 * t + 2]] - b[tfaces[4 * t + 3]]);
+    if (out) out[t] = s;
+    if (ref && s != ref[t]) atomicAdd(bad, 1ull);
+}
+
+hipError_t launch_verify(qh_ctx *c, bool check_divb) {
+    int64_t nn = c->hm.Nn;
+    hipLaunchKernelGGL(k_continuity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, c->n2e_ptr,
+                       c->n2e, c->g, c->Q, c->Q_old, nn, c->counters + 3);
+    if (check_divb) {
+        int32_t nt = (int32_t)c->hm.Nt;
+        hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
+                           (int64_t *)nullptr, c->divb0, c->counters + 4);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_divb(qh_ctx *c, int64_t *out) {
+    int32_t nt = (int32_t)c->hm.Nt;
+    hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
+                       out, (const int64_t *)nullptr, (unsigned long long *)nullptr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Counting sort of one species by tet: histogram, exclusive scan, scatter.
+__global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t *__restrict__ hist) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&hist[tet[i]], 1);
+}
+
+// scan over chunks of 1024: per-chunk sums
+__global__ void __launch_bounds__(1024) k_scan_sums(const int32_t *__restrict__ in, int32_t n,
+                                                    int32_t *__restrict__ sums) {
+    __shared__ int32_t sh[1024];
+    int32_t i = blockIdx.x * 1024 + threadIdx.x;
+    sh[threadIdx.x] = i < n ? in[i] : 0;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of the chunk sums in one block (serial over groups of 1024)
+__global__ void __launch_bounds__(1024) k_scan_top(int32_t *__restrict__ sums, int32_t m) {
+    __shared__ int32_t sh[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < m; base += 1024) {
+        int32_t i = base + threadIdx.x;
+        int32_t v = i < m ? sums[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < m) sums[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_final(const int32_t *__restrict__ in, int32_t n,
+                                                     const int32_t *__restrict__ sums,
+                                                     int32_t *__restrict__ out) {
+    __shared__ int32_t sh[1024];
+    int32_t i = blockIdx.x * 1024 + threadIdx.x;
+    int32_t v = i < n ? in[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = sums[blockIdx.x] + sh[threadIdx.x] - v;
+}
+
+__global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+                          const float *__restrict__ z, const float *__restrict__ vx,
+                          const float *__restrict__ vy, const float *__restrict__ vz,
+                          const int32_t *__restrict__ tet, const int32_t *__restrict__ id,
+                          int32_t *__restrict__ cursor, float *__restrict__ ox, float *__restrict__ oy,
+                          float *__restrict__ oz, float *__restrict__ ovx, float *__restrict__ ovy,
+                          float *__restrict__ ovz, int32_t *__restrict__ otet, int32_t *__restrict__ oid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int t = tet[i];
+    int32_t j = atomicAdd(&cursor[t], 1);
+    ox[j] = x[i]; oy[j] = y[i]; oz[j] = z[i];
+    ovx[j] = vx[i]; ovy[j] = vy[i]; ovz[j] = vz[i];
+    otet[j] = t; oid[j] = id[i];
+}
+
+int qh_sort_species(qh_ctx *c, Species &s) {
+    if (s.n == 0) return QH_OK;
+    int32_t nt = (int32_t)c->hm.Nt;
+    QH_HIP(c, hipMemsetAsync(c->hist, 0, sizeof(int32_t) * nt, c->stream));
+    unsigned pb = (unsigned)((s.n + 255) / 256);
+    hipLaunchKernelGGL(k_hist, dim3(pb), dim3(256), 0, c->stream, s.tet, s.n, c->hist);
+    int32_t chunks = (nt + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_sums, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nt, c->scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->scan_tmp, chunks);
+    hipLaunchKernelGGL(k_scan_final, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nt, c->scan_tmp, c->cursor);
+    hipLaunchKernelGGL(k_scatter, dim3(pb), dim3(256), 0, c->stream, s.n, s.x, s.y, s.zz, s.vx, s.vy, s.vz, s.tet,
+                       s.id, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
+    QH_HIP(c, hipGetLastError());
+    std::swap(s.x, s.sx); std::swap(s.y, s.sy); std::swap(s.zz, s.sz);
+    std::swap(s.vx, s.svx); std::swap(s.vy, s.svy); std::swap(s.vz, s.svz);
+    std::swap(s.tet, s.stet); std::swap(s.id, s.sid);
+    return QH_OK;
+}

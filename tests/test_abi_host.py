@@ -1,0 +1,86 @@
+"""C-ABI library on the CPU: it loads, exports every symbol include/qh.h declares, and its
+host-side mesh complex and FP64 assembly (Sec. II.C) match the oracle's, built independently.
+No GPU compute is called here (a host-only context does not touch the device)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qh_inputs as qi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qh.h")).read()
+    return sorted(set(re.findall(r"\b(qh_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2103_06737_amd as qh
+    L = qh.lib()
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(qh.EXPORTS)
+
+
+def test_host_context_rejects_device_calls():
+    import paper_2103_06737_amd as qh
+    m = qi.BoxMesh(2)
+    ctx = qh.Context(-1)
+    ctx.mesh_upload(m.xyz, m.tets)
+    with pytest.raises(qh.QhError) as ei:
+        ctx.fields_upload(np.zeros(ctx.info.n_edges), np.zeros(ctx.info.n_faces, np.int64))
+    assert ei.value.code == qh.QH_ESTATE
+
+
+def test_host_rejects_bad_meshes():
+    import paper_2103_06737_amd as qh
+    m = qi.BoxMesh(2)
+    bad = m.tets.copy()
+    bad[3, 2] = m.n_nodes + 5
+    with pytest.raises(qh.QhError):
+        qh.Context(-1).mesh_upload(m.xyz, bad)
+    flat = m.xyz.copy()
+    flat[:, 2] = 0.0
+    with pytest.raises(qh.QhError):
+        qh.Context(-1).mesh_upload(flat, m.tets)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "graded"])
+def test_host_topology_and_matrices_match_oracle(cfg):
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    from oracle.whitney import Operators
+    m = qi.make_mesh(qi.CONFIGS["c1"]) if cfg == "c1" else qi.BoxMesh(5, z_ratio=1.3)
+    ctx = qh.Context(-1)
+    ctx.mesh_upload(m.xyz, m.tets)
+    dt = 3e-10
+    ctx.set_physics(qi.EPS0, qi.MU0, dt, 1.0, 2.0 ** -56)
+    cx = Complex(m.xyz, m.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    top = ctx.topology()
+    assert np.array_equal(top["edges"], cx.edges)
+    assert np.array_equal(top["faces"], cx.faces)
+    assert np.array_equal(top["tet_nodes"], cx.tets)
+    assert np.array_equal(top["tet_edges"], cx.tet_edges)
+    assert np.array_equal(top["tet_faces"], cx.tet_faces)
+    assert np.array_equal(top["tet_nbr"], cx.tet_nbr)
+    assert np.array_equal(top["wall_edge"].astype(bool), cx.wall_edge)
+    assert np.array_equal(top["wall_node"].astype(bool), cx.wall_node)
+    ie, inn = cx.int_edges, cx.int_nodes
+    G = cx.G.astype(float)
+    ref = {0: (op.Meps + dt * dt / 4 * op.S)[ie][:, ie], 1: op.Meps[ie][:, ie], 2: op.S[ie][:, ie],
+           3: op.CtMmu[ie], 4: (G.T @ op.Meps)[inn][:, ie], 5: op.K[inn][:, inn]}
+    for w, R in ref.items():
+        M = ctx.matrix(w)
+        R = R.tocsr()
+        R.eliminate_zeros()
+        assert M.shape == R.shape
+        # same pattern up to entries that cancel to rounding level
+        assert abs(M - R).max() <= 1e-13 * abs(R).max(), w
+    info = ctx.mesh_info()
+    assert info.nnz_edge == ctx.matrix(0).nnz and info.nnz_node == ctx.matrix(5).nnz
