@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: one full PIC cycle per step of the 64^3 uniform-plasma workload on one MI355X.
+
+Workload: unit cube, 64^3 boxes x 6 Kuhn tets (1,572,864 tets, 1,872,064 edges), 16,000,000
+electrons (uniform, Maxwellian v_th = 1e6 m/s, n = 1e16 m^-3, neutralising background),
+uniform B_z = 0.1 T, dt = 1.2e-10 s (~10x the explicit limit), counting sort by tet every 20
+steps, full cycle: gather + Boris + tet walk + int64 deposit, then the implicit field update
+(edge CG to 1e-8, Gauss-law CG to 1e-8, integer Faraday). Synthetic seeded inputs.
+
+Prints one JSON line. value = particle-steps/s of the whole cycle (N_p * K / wall time of K
+steps, inputs resident on the GPU). Extra keys give the particle phase and the field solve
+separately, per-kernel device times (HIP events), the roofline of the dominant kernel and
+the FP64 oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import qh_inputs as qi  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {"c3": "64^3 Kuhn cube, 16M-electron uniform plasma, full implicit cycle",
+             "c2": "32^3 Kuhn cube, 1M-electron beam in frozen random fields"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(wl: str, n_particles: int | None):
+    import paper_2103_06737_amd as qh
+    cfg = dict(qi.CONFIGS[wl])
+    mesh = qi.make_mesh(cfg)
+    n_e = cfg["n_e"] if n_particles is None else n_particles
+    weight = cfg["weight"] * cfg["n_e"] / n_e
+    t0 = time.perf_counter()
+    ctx = qh.Context(0)
+    ctx.mesh_upload(mesh.xyz, mesh.tets)
+    u_b = 2.0 ** -56
+    ctx.set_physics(qi.EPS0, qi.MU0, cfg["dt"], qi.QE * weight * 2.0 ** -40, u_b)
+    mi = ctx.mesh_info()
+    ctx.fields_init_synthetic(qi.white(mi.n_edges, 0, 3), qi.white(mi.n_edges, 0, 5), cfg["sigma_e"], cfg["bz"],
+                              cfg["sigma_b"])
+    log(f"[bench] mesh + assembly {time.perf_counter() - t0:.1f}s  tets={mi.n_tets} edges={mi.n_edges} "
+        f"nnz_edge={mi.nnz_edge}")
+    t0 = time.perf_counter()
+    parts = qi.make_particles(mesh, cfg, n_e=n_e)
+    sids = []
+    for name, (x, v, tet) in parts.items():
+        qm, z = (-qi.QE / qi.ME, -1) if name == "e" else (qi.QE / qi.MI, 1)
+        sid = ctx.species_add(qm, z)
+        ctx.particles_upload(sid, x, v, tet)
+        sids.append(sid)
+    if cfg["mode"] == "solve":
+        ctx.charge_background(1)
+    log(f"[bench] particles {time.perf_counter() - t0:.1f}s  n={sum(p[2].size for p in parts.values())}")
+    return ctx, cfg, mesh, parts, mi
+
+
+def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
+    """Bytes one launch must move at least (each datum read or written once)."""
+    if kernel in ("cg_spmv",):
+        n, nnz = mi.n_int_edges, mi.nnz_edge
+        return 12 * nnz + 4 * (n + 1) + 32 * n          # A (val+col), rowptr, z, p_old in; p_new, q out
+    if kernel in ("node_spmv",):
+        n, nnz = mi.n_int_nodes, mi.nnz_node
+        return 12 * nnz + 4 * (n + 1) + 32 * n
+    if kernel in ("cg_update", "node_update"):
+        n = mi.n_int_edges if kernel == "cg_update" else mi.n_int_nodes
+        return 64 * n                                    # x, r rw; p, q, dinv in; z out
+    if kernel == "particle_step":
+        # particle state in+out (28 B each way), per tet: geometry 48 + field 48 + vertex ids 16
+        # + edge ids 24, per crossing: neighbour ids 16 + the next tet's records 136,
+        # accumulators read-modify-write once (16 B per edge and node)
+        return 56 * n_particles + 136 * mi.n_tets + 152 * crossings + 16 * (mi.n_edges + mi.n_nodes)
+    if kernel == "field_prep":
+        return (48 + 24 + 16 + 48) * mi.n_tets + 8 * mi.n_edges + 8 * mi.n_faces
+    return None
+
+
+def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: float = 25.0):
+    """The FP64 oracle as it stands, on the host cores: one particle push over a sample of the
+    particles plus one oracle field update on the full mesh; whole-step rate extrapolated to
+    the full particle count."""
+    from oracle.complex_ import Complex
+    from oracle.field import FieldOracle
+    from oracle.particles import ParticleOracle
+    from oracle.whitney import Operators
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    cores = min(cores, 16)
+    cx = Complex(mesh.xyz, mesh.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    po = ParticleOracle(cx, op.Minv)
+    from oracle.field import init_fields
+    u_b = 2.0 ** -56
+    e, b = init_fields(cx, qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), cfg["sigma_e"], cfg["bz"], cfg["sigma_b"], u_b)
+    x, v, tet = parts["e"]
+    n_s = min(sample_particles, tet.size)
+    t0 = time.perf_counter()
+    out = po.push(e, b * u_b, x[:n_s], v[:n_s], tet[:n_s], -qi.QE / qi.ME, cfg["dt"], -1, nthreads=cores)
+    t_push = time.perf_counter() - t0
+    n_total = sum(p[2].size for p in parts.values())
+    t_field = 0.0
+    if cfg["mode"] == "solve":
+        fo = FieldOracle(cx, op, cfg["dt"])
+        weight = cfg["weight"]
+        u_q = qi.QE * weight * 2.0 ** -40
+        Q = np.zeros(cx.Nn, np.int64)
+        t0 = time.perf_counter()
+        fo.step(e, b, u_b, out["g"], u_q, out["Q"], out["Q"], tol=1e-8, tol_n=1e-8)
+        t_field = time.perf_counter() - t0
+    t_step = t_push * n_total / n_s + t_field
+    return {"value": n_total / t_step, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one step of {n_s} of {n_total} particles (FP64 C oracle, {cores} threads, "
+                      f"{t_push:.2f}s) + one FP64 field update on the full mesh (numpy/scipy, "
+                      f"{t_field:.2f}s); rate = N_p / (push time scaled to N_p + field time)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--particles", type=int, default=None, help="override the particle count")
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import paper_2103_06737_amd as qh
+    ctx, cfg, mesh, parts, mi = setup(args.workload, args.particles)
+    n_p = sum(p[2].size for p in parts.values())
+    solve = cfg["mode"] == "solve"
+    params = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE if solve else qh.FIELDS_FROZEN,
+                                    sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
+                                    max_it_edge=2000, max_it_node=5000, check_every=16)
+    st = ctx.pic_step(params, args.warmup, want_stats=True)
+    log(f"[bench] warmup done: last step {st[-1]}")
+    t0 = time.perf_counter()
+    ctx.pic_step(params, args.steps, want_stats=False)   # returns after its stream is synchronised
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    value = n_p * args.steps / wall
+    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} particle-steps/s")
+
+    # profiling pass: per-step stats and per-kernel HIP-event times
+    ctx.timing(True)
+    pst = ctx.pic_step(params, args.profile_steps, want_stats=True)
+    kt = ctx.timing_read()
+    ctx.timing(False)
+    crossings = float(np.mean([s["crossings"] for s in pst]))
+    kernels = {}
+    for k, (ms, cnt) in kt.items():
+        if cnt:
+            kernels[k] = {"ms_total": round(ms, 4), "launches": cnt, "us_per_launch": round(1e3 * ms / cnt, 3)}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    def roof(k):
+        by = algorithmic_bytes(k, mi, n_p, crossings)
+        if by is None:
+            return None
+        avg_s = kernels[k]["ms_total"] / kernels[k]["launches"] * 1e-3
+        ach = by / avg_s / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k,
+                "algorithmic_bytes_per_launch": int(by), "us_per_launch": kernels[k]["us_per_launch"]}
+    ms_part = float(np.mean([s["ms_particles"] for s in pst]))
+    ms_field = float(np.mean([s["ms_fields"] for s in pst]))
+    out = {
+        "metric": "particle-steps/s (gather+push+deposit), % HBM roofline; field-solve ms/step learned vs Jacobi",
+        "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 push / int64 deposit / f64 solve", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "particles": n_p,
+                   "tets": mi.n_tets, "edges": mi.n_edges, "nnz_edge": mi.nnz_edge, "dt": cfg["dt"],
+                   "sort_every": cfg.get("sort_every", 0), "tol": 1e-8},
+        "roofline": roof(dom),
+        "particle_phase": {"ms_per_step": round(ms_part, 4),
+                           "particle_steps_per_s": round(n_p / (ms_part * 1e-3), 1),
+                           "roofline": roof("particle_step")},
+        "field_solve_ms_per_step": {"jacobi": round(ms_field, 4), "learned": None},
+        "solver": {"edge_iters": [s["edge_iters"] for s in pst], "node_iters": [s["node_iters"] for s in pst],
+                   "edge_res": max(s["edge_res"] for s in pst), "gauss_res": max(s["gauss_res"] for s in pst)},
+        "kernels": kernels,
+        "crossings_per_step": crossings,
+        "foreign_deposits_per_step": float(np.mean([s["foreign"] for s in pst])),
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.workload, cfg, mesh, parts, args.cpu_sample)
+        except Exception as ex:  # the baseline must not hide the GPU result
+            out["cpu_baseline"] = {"error": repr(ex)}
+        log(f"[bench] cpu baseline {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

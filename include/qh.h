@@ -77,7 +77,7 @@ typedef struct {
     int32_t precond;     /* QH_PC_JACOBI or QH_PC_LEARNED */
     int32_t gauss;       /* 1: solve the discrete Gauss law each step (the method); 0: skip */
     double tol_edge;     /* relative residual of the edge solve (e.g. 1e-8) */
-    double tol_node;     /* relative residual of the Gauss-law solve (e.g. 1e-8) */
+    double tol_node;     /* Gauss-law residual target, relative to ||rho|| + || |G^T[*eps]| |e| || */
     int32_t max_it_edge, max_it_node;
     int32_t check_every; /* iterations between host reads of the convergence flag */
     int32_t verify;      /* 1: check continuity and D b on the device every step */
@@ -86,12 +86,13 @@ typedef struct {
 typedef struct {
     int32_t edge_iters, node_iters; /* Krylov iterations of this step */
     double edge_res, node_res;      /* final relative residuals, recomputed in FP64 */
-    double gauss_res;               /* ||rho - G^T [*eps] e|| / (||rho|| + ||G^T [*eps] e||) */
+    double gauss_res;               /* ||rho - G^T[*eps] e|| / (||rho|| + || |G^T[*eps]| |e| ||) */
     int64_t crossings, wall_hits, lost;
     int64_t continuity_bad;         /* nodes where G^T g != Q^{n+1} - Q^n (verify = 1) */
     int64_t divb_bad;               /* tets where D b changed (verify = 1) */
     int32_t fallbacks;              /* learned -> Jacobi restarts */
     float ms_particles, ms_fields;  /* device time of the two halves (HIP events) */
+    int64_t foreign;                /* deposits into tets outside a block's range (atomics) */
 } qh_step_stats_t;
 
 typedef struct {
@@ -196,9 +197,10 @@ int qh_matrix_download(const qh_ctx *ctx, int32_t which, int32_t *ptr, int32_t *
 
 /* Per-kernel device time, measured with HIP events recorded around each launch on the
  * context stream while enabled (enabling resets the table). Index k of the table:
- * 0 field prep, 1 particle step, 2 sort, 3 edge right-hand side, 4 CG product (fused
- * direction update + SpMV + dot), 5 CG vector update, 6 CG init, 7 Gauss-law kernels,
- * 8 Faraday update, 9 residual check. ms_total[k]: summed milliseconds; launches[k]: count. */
+ * 0 field prep, 1 particle step, 2 sort, 3 edge right-hand side, 4 edge-system CG product
+ * (fused direction update + SpMV + dot), 5 edge-system CG vector update, 6 CG init,
+ * 7 Gauss-law set-up and correction, 8 Faraday update, 9 residual check, 10 node-system CG
+ * product, 11 node-system CG vector update. ms_total[k]: summed ms; launches[k]: count. */
 int qh_timing_enable(qh_ctx *ctx, int32_t on);
 int qh_timing_read(const qh_ctx *ctx, int32_t n, double *ms_total, int64_t *launches);
 

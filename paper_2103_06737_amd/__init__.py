@@ -21,7 +21,7 @@ FIELDS_FROZEN, FIELDS_SOLVE = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
-           "gauss", "faraday", "true_res"]
+           "gauss", "faraday", "true_res", "node_spmv", "node_update"]
 F_BITS = 20
 EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mesh_info",
            "qh_mesh_topology", "qh_set_physics", "qh_fields_upload", "qh_fields_download",
@@ -60,7 +60,7 @@ class StepStats(C.Structure):
                 ("node_res", C.c_double), ("gauss_res", C.c_double), ("crossings", C.c_int64),
                 ("wall_hits", C.c_int64), ("lost", C.c_int64), ("continuity_bad", C.c_int64),
                 ("divb_bad", C.c_int64), ("fallbacks", C.c_int32), ("ms_particles", C.c_float),
-                ("ms_fields", C.c_float)]
+                ("ms_fields", C.c_float), ("foreign", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

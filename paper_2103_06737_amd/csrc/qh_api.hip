@@ -171,7 +171,7 @@ int qh_create(qh_ctx **out, int device, void *stream) {
     c->device = device;
     c->stream = (hipStream_t)stream;
     unsigned long long *cnt = nullptr;
-    if (qh_alloc(c, &cnt, 8) != QH_OK) {
+    if (qh_alloc(c, &cnt, 4 * QH_COUNTER_SLOTS + 8) != QH_OK) {
         delete c;
         return QH_ENOMEM;
     }
@@ -234,6 +234,11 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = upload(c, &c->edge_nodes, m.edges.data(), m.edges.size()))) return rc;
     if ((rc = upload(c, &c->n2e_ptr, m.n2e_ptr.data(), m.n2e_ptr.size()))) return rc;
     if ((rc = upload(c, &c->n2e, m.n2e.data(), m.n2e.size()))) return rc;
+    if ((rc = upload(c, &c->e2t_ptr, m.e2t_ptr.data(), m.e2t_ptr.size()))) return rc;
+    if ((rc = upload(c, &c->e2t, m.e2t.data(), m.e2t.size()))) return rc;
+    if ((rc = upload(c, &c->n2t_ptr, m.n2t_ptr.data(), m.n2t_ptr.size()))) return rc;
+    if ((rc = upload(c, &c->n2t, m.n2t.data(), m.n2t.size()))) return rc;
+    if ((rc = qh_alloc(c, &c->acc_tet, 10 * m.Nt))) return rc;
     if ((rc = qh_alloc(c, &c->frec, 3 * m.Nt))) return rc;
     if ((rc = qh_alloc(c, &c->e, m.Ne)) || (rc = qh_alloc(c, &c->b, m.Nf)) || (rc = qh_alloc(c, &c->g, m.Ne)) ||
         (rc = qh_alloc(c, &c->Q, m.Nn)) || (rc = qh_alloc(c, &c->Q_old, m.Nn)) || (rc = qh_alloc(c, &c->Q_bg, m.Nn)) ||
@@ -368,6 +373,7 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
         for (auto p : is)
             if ((rc = qh_alloc(c, p, n))) return rc;
+        if ((rc = qh_alloc(c, &s.own, qh_species_blocks(n) + 1))) return rc;
         s.cap = n;
     }
     s.n = n;
@@ -500,7 +506,7 @@ int qh_deposit(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *
         if (pt_tet[p] < 0 || pt_tet[p] >= m.Nt) return qh_fail(c, QH_EINVAL, "point tet out of range");
     int32_t *d = nullptr;
     int64_t *gd = nullptr, *qd = nullptr;
-    size_t ni = (size_t)(9 * n_seg + 6 * n_pt) + 1;
+    size_t ni = (size_t)(10 * n_seg + 6 * n_pt) + 1;  // st, l0, l1, sz | pt, pl, pz
     if (hipMalloc((void **)&d, ni * sizeof(int32_t)) != hipSuccess) return qh_fail(c, QH_ENOMEM, "deposit buffers");
     if (hipMalloc((void **)&gd, (m.Ne + m.Nn) * sizeof(int64_t)) != hipSuccess) {
         (void)hipFree(d);
@@ -552,7 +558,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         std::swap(c->Q, c->Q_old);
         QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * m.Nn, c->stream));
         QH_HIP(c, hipMemsetAsync(c->g, 0, sizeof(int64_t) * m.Ne, c->stream));
-        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * 8, c->stream));
+        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * (4 * QH_COUNTER_SLOTS + 8), c->stream));
         for (size_t k = 0; k < c->species.size(); ++k) {
             int t0 = qh_tbeg(c);
             QH_HIP(c, launch_particle_step(c, c->species[k], (int)k, capture));
@@ -581,7 +587,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
                 QH_HIP(c, launch_gauss_rhs(c, c->scratch_d, P->tol_node));
                 QH_HIP(c, hipMemsetAsync(c->cgn.x, 0, sizeof(double) * c->K.n, c->stream));
                 qh_tend(c, t0, QK_GAUSS);
-                rc = qh_cg_solve(c, c->K, c->cgn, P->tol_node, P->max_it_node, P->check_every, sn, c->scratch_d);
+                rc = qh_cg_solve(c, c->K, c->cgn, P->tol_node, P->max_it_node, P->check_every, sn, c->scratch_d, true);
                 if (rc) return rc;
                 if (!sn.converged) status = QH_ENOTCONV;
                 t0 = qh_tbeg(c);
@@ -600,9 +606,17 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         if (P->verify) QH_HIP(c, launch_verify(c, true));
         if (use_ev) QH_HIP(c, hipEventRecord(ev[2], c->stream));
         if (stats) {
-            unsigned long long cnt[8];
-            QH_HIP(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+            std::vector<unsigned long long> raw(4 * QH_COUNTER_SLOTS + 8);
+            QH_HIP(c, hipMemcpyAsync(raw.data(), c->counters, sizeof(unsigned long long) * raw.size(),
+                                     hipMemcpyDeviceToHost, c->stream));
             QH_HIP(c, hipStreamSynchronize(c->stream));
+            unsigned long long cnt[6] = {0, 0, 0, 0, 0, 0};
+            for (int k = 0; k < QH_COUNTER_SLOTS; ++k) {
+                for (int j = 0; j < 3; ++j) cnt[j] += raw[4 * k + j];
+                cnt[5] += raw[4 * k + 3];
+            }
+            cnt[3] = raw[4 * QH_COUNTER_SLOTS];
+            cnt[4] = raw[4 * QH_COUNTER_SLOTS + 1];
             qh_step_stats_t &S = stats[st];
             std::memset(&S, 0, sizeof(S));
             S.edge_iters = se.iters;
@@ -615,6 +629,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.lost = (int64_t)cnt[2];
             S.continuity_bad = P->verify ? (int64_t)cnt[3] : -1;
             S.divb_bad = P->verify ? (int64_t)cnt[4] : -1;
+            S.foreign = (int64_t)cnt[5];
             (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
             (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
             if (S.lost && status == QH_OK) status = QH_ELOST;

@@ -12,6 +12,7 @@
 constexpr int QH_FBITS = 20;                  // fixed-point bits of barycentric coordinates
 constexpr int QH_SCALE = 1 << QH_FBITS;
 constexpr int QH_MAX_PIECES = 64;             // straight pieces per particle per step
+constexpr int QH_COUNTER_SLOTS = 256;         // spread of the per-block event counters
 
 // ---------------------------------------------------------------------------------------
 // Host-side mesh complex and FP64 assembly (qh_mesh.hip)
@@ -72,6 +73,7 @@ struct Species {
     // sort scratch (same layout)
     float *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
     int32_t *stet = nullptr, *sid = nullptr;
+    int32_t *own = nullptr;  // owned tet range per particle block (see qh_particles.hip)
 };
 
 // Krylov workspace for one system.
@@ -110,6 +112,9 @@ struct qh_ctx {
     int32_t *int_node_of = nullptr; // global node -> interior or -1
     int32_t *edge_nodes = nullptr;  // 2*Ne
     int32_t *n2e_ptr = nullptr, *n2e = nullptr;
+    int32_t *e2t_ptr = nullptr, *e2t = nullptr;  // edge -> tet*8 + local edge
+    int32_t *n2t_ptr = nullptr, *n2t = nullptr;  // node -> tet*8 + local vertex
+    int64_t *acc_tet = nullptr;                  // 10*Nt per-tet owned deposit sums
 
     DevCsr A, CMb, GtM, K;  // A: val = [*eps] + tau S, val2 = [*eps]
     double *A_S = nullptr;  // S values on the pattern of A
@@ -129,7 +134,8 @@ struct qh_ctx {
     CgWork cge, cgn;            // cge.x holds e on the interior edges between steps
     CgWork cgx;                 // standalone solves (qh_field_solve)
     double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
-    unsigned long long *counters = nullptr;  // [0] crossings [1] wall hits [2] lost [3] bad
+    unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS slots (crossings, wall hits,
+                                             // lost), then continuity and D b violations
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
 
     std::vector<Species> species;
@@ -156,7 +162,7 @@ struct qh_ctx {
 // kernel ids of the timing table
 enum {
     QK_FIELD_PREP = 0, QK_PARTICLE, QK_SORT, QK_EDGE_RHS, QK_CG_SPMV, QK_CG_UPDATE, QK_CG_INIT,
-    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NKERNELS
+    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NODE_SPMV, QK_NODE_UPDATE, QK_NKERNELS
 };
 int qh_tbeg(qh_ctx *c);
 void qh_tend(qh_ctx *c, int slot, int kernel);
@@ -188,6 +194,7 @@ void launch_field_prep(qh_ctx *c);
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture);
 hipError_t launch_charge_deposit(qh_ctx *c, Species &s);
 int qh_sort_species(qh_ctx *c, Species &s);
+int64_t qh_species_blocks(int64_t n);
 hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet,
                                 const int32_t *l0, const int32_t *l1, const int32_t *sz,
                                 int64_t n_pt, const int32_t *pt_tet, const int32_t *pl,
@@ -204,7 +211,7 @@ struct SolveResult {
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
 // Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
-                SolveResult &out, const double *abs_thr2_dev);
+                SolveResult &out, const double *abs_thr2_dev, bool node_system = false);
 hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);
 hipError_t launch_assemble_A(qh_ctx *c, double tau);
 hipError_t launch_edge_rhs(qh_ctx *c);

@@ -19,7 +19,9 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWin = 128;  // LDS tet window per block (particles are sorted by tet)
+constexpr int kPpt = 2;                  // consecutive particles per thread
+constexpr int kChunk = kBlock * kPpt;    // particles per block
+constexpr int kWin = 128;                // owned tets whose sums a block keeps in LDS
 
 __device__ __forceinline__ void lam4(const float4 A, const float4 B, const float4 C, float x,
                                      float y, float z, float l[4]) {
@@ -67,12 +69,14 @@ struct StepArgs {
     float *x, *y, *z, *vx, *vy, *vz;
     int32_t *tet;
     const int32_t *pid;
+    const int32_t *own;     // own[b] .. own[b+1]: tets owned by block b (from the last sort)
     int64_t n;
     int32_t nt;
-    float hqm;   // q/m * dt / 2
+    float hqm;              // q/m * dt / 2
     float dt;
-    int32_t zq;  // charge number
-    int64_t *g, *Q;
+    int32_t zq;             // charge number
+    int64_t *g, *Q;         // deposits into tets a block does not own (atomics)
+    int64_t *acc_tet;       // per-tet sums of owned deposits: 6 edges, 4 nodes (plain stores)
     unsigned long long *counters;
     // capture
     int32_t species;
@@ -134,72 +138,106 @@ void launch_field_prep(qh_ctx *c) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused particle step. One thread per particle; a block accumulates deposits of tets in
-// [tbase, tbase + kWin) in LDS (int64, order-free) and flushes them once; other tets go
-// straight to global int64 atomics.
+// Fused particle step. A block takes kChunk consecutive particles (sorted by tet at the last
+// sort), kPpt consecutive ones per thread. The block owns the tets [own[b], own[b+1]) its
+// particles held at that sort: their deposits are summed in LDS (after a per-thread register
+// sum over consecutive particles of one tet) and written once per tet as plain stores into
+// acc_tet; a gather kernel then adds acc_tet into edges and nodes. Deposits into other tets
+// (particles that moved since the sort, pieces past a block's range) use int64 atomics.
+// Integer sums do not depend on order, so the result is the same bits either way.
 template <bool CAPTURE>
 __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     __shared__ long long acc[kWin * 10];
-    __shared__ int s_tbase;
-    __shared__ unsigned int s_cnt[3];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (int j = threadIdx.x; j < kWin * 10; j += kBlock) acc[j] = 0;
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        int64_t i0 = (int64_t)blockIdx.x * kBlock;
-        s_tbase = a.tet[i0];
-    }
+    __shared__ unsigned short queue[kChunk];  // block-local index of each particle that leaves its tet
+    __shared__ float sx_[kChunk], sy_[kChunk], sz_[kChunk], svx_[kChunk], svy_[kChunk], svz_[kChunk];
+    __shared__ int st_[kChunk];           // particle state staged for one coalesced write-back
+    __shared__ unsigned int s_cnt[5];     // crossings, wall hits, lost, queue length, foreign puts
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const int T0 = a.own[blockIdx.x], T1 = a.own[blockIdx.x + 1];
+    const int W = min(T1 - T0, kWin);
+    for (int j = threadIdx.x; j < W * 10; j += kBlock) acc[j] = 0;
+    if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int tbase = s_tbase;
-    unsigned int n_cross = 0, n_wall = 0, n_lost = 0;
+    const int32_t zq = a.zq;
+    unsigned int n_foreign = 0;
+    const int LE0[6] = {0, 0, 0, 1, 1, 2};
+    const int LE1[6] = {1, 2, 3, 2, 3, 3};
 
-    if (i < a.n) {
-        float px = a.x[i], py = a.y[i], pz = a.z[i];
-        float vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
-        int t = a.tet[i];
-        const int32_t zq = a.zq;
-        int32_t pid = 0;
-        if (CAPTURE) pid = a.pid[i];
-        int seq = 0;
-
-        auto deposit = [&](int tt, const int L0[4], const int L1[4]) {
-            const int LE0[6] = {0, 0, 0, 1, 1, 2};
-            const int LE1[6] = {1, 2, 3, 2, 3, 3};
-            int slot = tt - tbase;
-            bool local = (unsigned)slot < (unsigned)kWin;
-            const int32_t *te = a.tedges + 8 * (int64_t)tt;
+    // add the 10 values of one tet (6 edges, 4 nodes) to the owned LDS sums or atomically
+    auto put = [&](int tt, const long long *v) {
+        int slot = tt - T0;
+        if ((unsigned)slot < (unsigned)W) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                long long v = (long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]];
-                v *= zq;
-                if (v == 0) continue;
-                if (local) atomic_add_lds(&acc[slot * 10 + k], v);
-                else atomic_add_i64(a.g + te[k], v);
-            }
-            if (CAPTURE) {
-                unsigned long long s = atomicAdd(a.seg_count, 1ull);
-                if ((int64_t)s < a.cap) {
-                    int32_t *o = a.seg_buf + 12 * s;
-                    o[0] = pid; o[1] = a.species; o[2] = seq; o[3] = tt;
-                    for (int q = 0; q < 4; ++q) { o[4 + q] = L0[q]; o[8 + q] = L1[q]; }
-                }
-            }
-            ++seq;
-        };
+            for (int k = 0; k < 10; ++k)
+                if (v[k]) atomic_add_lds(&acc[slot * 10 + k], v[k]);
+        } else {
+            ++n_foreign;
+            const int32_t *te = a.tedges + 8 * (int64_t)tt;
+            int4 tn = a.tnodes[tt];
+            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (v[k]) atomic_add_i64(a.g + te[k], v[k]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (v[6 + k]) atomic_add_i64(a.Q + nv[k], v[6 + k]);
+        }
+    };
+    auto record = [&](int32_t pid, int seq, int tt, const int L0[4], const int L1[4]) {
+        unsigned long long s = atomicAdd(a.seg_count, 1ull);
+        if ((int64_t)s < a.cap) {
+            int32_t *o = a.seg_buf + 12 * s;
+            o[0] = pid; o[1] = a.species; o[2] = seq; o[3] = tt;
+            for (int r = 0; r < 4; ++r) { o[4 + r] = L0[r]; o[8 + r] = L1[r]; }
+        }
+    };
 
-        // gather at x^n
-        float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
-        float4 F0 = a.frec[3 * t], F1 = a.frec[3 * t + 1], F2 = a.frec[3 * t + 2];
+    // ---- phase A: gather, push; particles that stay in their tet are finished here
+    int cur = -1;
+    long long rs[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) rs[k] = 0;
+    const int64_t i0 = base + (int64_t)threadIdx.x * kPpt;
+    const bool full = base + kChunk <= a.n;
+    float2 X, Y, Z, VX, VY, VZ;
+    int2 TT;
+    if (full) {
+        const int64_t v = i0 / 2;
+        X = ((const float2 *)a.x)[v]; Y = ((const float2 *)a.y)[v]; Z = ((const float2 *)a.z)[v];
+        VX = ((const float2 *)a.vx)[v]; VY = ((const float2 *)a.vy)[v]; VZ = ((const float2 *)a.vz)[v];
+        TT = ((const int2 *)a.tet)[v];
+    }
+#pragma unroll
+    for (int q = 0; q < kPpt; ++q) {
+        const int64_t i = i0 + q;
+        const int li = threadIdx.x * kPpt + q;
+        if (!full && i >= a.n) break;
+        float px, py, pz, vx, vy, vz;
+        int t;
+        if (full) {
+            px = q == 0 ? X.x : X.y;
+            py = q == 0 ? Y.x : Y.y;
+            pz = q == 0 ? Z.x : Z.y;
+            vx = q == 0 ? VX.x : VX.y;
+            vy = q == 0 ? VY.x : VY.y;
+            vz = q == 0 ? VZ.x : VZ.y;
+            t = q == 0 ? TT.x : TT.y;
+        } else {
+            px = a.x[i]; py = a.y[i]; pz = a.z[i];
+            vx = a.vx[i]; vy = a.vy[i]; vz = a.vz[i];
+            t = a.tet[i];
+        }
+        // gather at x^n: E = alpha + beta x (r - c), B constant
+        const float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
+        const float4 F0 = a.frec[3 * t], F1 = a.frec[3 * t + 1], F2 = a.frec[3 * t + 2];
         float dx = px - A.w, dy = py - B.w, dz = pz - C.w;
-        // E = alpha + beta x (r - c)
         float Ex = F0.x + (F1.x * dz - F1.y * dy);
         float Ey = F0.y + (F1.y * dx - F0.w * dz);
         float Ez = F0.z + (F0.w * dy - F1.x * dx);
-        float Bx = F1.z, By = F1.w, Bz = F2.x;
         // Boris
         const float h = a.hqm;
         float mx = vx + h * Ex, my = vy + h * Ey, mz = vz + h * Ez;
-        float tx = h * Bx, ty = h * By, tz = h * Bz;
+        float tx = h * F1.z, ty = h * F1.w, tz = h * F2.x;
         float s2 = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
         float sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
         float qx = mx + (my * tz - mz * ty);
@@ -208,9 +246,61 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         vx = mx + (qy * sz - qz * sy) + h * Ex;
         vy = my + (qz * sx - qx * sz) + h * Ey;
         vz = mz + (qx * sy - qy * sx) + h * Ez;
-        float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
+        const float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
+        // does the straight path leave the tet? (same test as the walk's first step)
+        float l[4], gl[4];
+        lam4(A, B, C, px, py, pz, l);
+        gl[1] = A.x * rx + A.y * ry + A.z * rz;
+        gl[2] = B.x * rx + B.y * ry + B.z * rz;
+        gl[3] = C.x * rx + C.y * ry + C.z * rz;
+        gl[0] = -(gl[1] + gl[2] + gl[3]);
+        bool leaves = (l[0] + gl[0] < 0.0f) | (l[1] + gl[1] < 0.0f) | (l[2] + gl[2] < 0.0f) |
+                      (l[3] + gl[3] < 0.0f);
+        svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
+        st_[li] = t;
+        if (leaves) {
+            // walked in phase B from the staged start point and new velocity
+            unsigned int k = atomicAdd(&s_cnt[3], 1u);
+            queue[k] = (unsigned short)li;
+            sx_[li] = px; sy_[li] = py; sz_[li] = pz;
+            continue;
+        }
+        px += rx; py += ry; pz += rz;
+        sx_[li] = px; sy_[li] = py; sz_[li] = pz;
+        int L0[4], L1[4];
+        quantize(l, -1, L0);
+        lam4(A, B, C, px, py, pz, l);
+        quantize(l, -1, L1);
+        if (t != cur) {
+            if (cur >= 0) put(cur, rs);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) rs[k] = 0;
+            cur = t;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            rs[k] += zq * ((long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rs[6 + r] += (long long)zq * QH_SCALE * L1[r];
+        if (CAPTURE) record(a.pid[i], 0, t, L0, L1);
+    }
+    if (cur >= 0) put(cur, rs);
+    __syncthreads();
 
-        // tet walk along x^n -> x^n + dt v^{n+1/2}
+    // ---- phase B: walk the particles that leave their tet, one per lane
+    const int nq = (int)s_cnt[3];
+    unsigned int n_cross = 0, n_wall = 0, n_lost = 0;
+    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+        const int li = queue[qi];
+        const int64_t i = base + li;
+        float vx = svx_[li], vy = svy_[li], vz = svz_[li];
+        float px = sx_[li], py = sy_[li], pz = sz_[li];
+        int t = st_[li];
+        int32_t pid = 0;
+        if (CAPTURE) pid = a.pid[i];
+        int seq = 0;
+        float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
+        float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
         float l[4];
         int Lp[4], Lc[4];
         lam4(A, B, C, px, py, pz, l);
@@ -226,19 +316,29 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             int k = -1;
             float smin = 2.0f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q == entry) continue;
-                float le = l[q] + gl[q];
+            for (int r = 0; r < 4; ++r) {
+                if (r == entry) continue;
+                float le = l[r] + gl[r];
                 if (!(le < 0.0f)) continue;
-                float s = l[q] <= 0.0f ? 0.0f : l[q] / (l[q] - le);
-                if (s < smin) { smin = s; k = q; }
+                float s = l[r] <= 0.0f ? 0.0f : l[r] / (l[r] - le);
+                if (s < smin) { smin = s; k = r; }
             }
             if (k < 0) { px += rx; py += ry; pz += rz; break; }
             if (pieces >= QH_MAX_PIECES - 1) { ++n_lost; break; }
             float cx = __fmaf_rn(smin, rx, px), cy = __fmaf_rn(smin, ry, py), cz = __fmaf_rn(smin, rz, pz);
             lam4(A, B, C, cx, cy, cz, l);
             quantize(l, k, Lc);
-            deposit(t, Lp, Lc);
+            {
+                long long v[10];
+#pragma unroll
+                for (int j = 0; j < 6; ++j)
+                    v[j] = zq * ((long long)Lp[LE0[j]] * Lc[LE1[j]] - (long long)Lc[LE0[j]] * Lp[LE1[j]]);
+#pragma unroll
+                for (int j = 6; j < 10; ++j) v[j] = 0;
+                put(t, v);
+                if (CAPTURE) record(pid, seq, t, Lp, Lc);
+                ++seq;
+            }
             ++pieces;
             float rem = 1.0f - smin;
             rx *= rem; ry *= rem; rz *= rem;
@@ -253,8 +353,8 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
                 for (int j = 0; j < 4; ++j) {
                     int val = 0, found = 0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (ov[q] == nv[j]) { val = Lc[q]; found = 1; }
+                    for (int r = 0; r < 4; ++r)
+                        if (ov[r] == nv[j]) { val = Lc[r]; found = 1; }
                     Lp[j] = val;
                     if (!found) fresh = j;
                 }
@@ -274,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
                 else if (ay >= az) { ry = -ry; vy = -vy; }
                 else { rz = -rz; vz = -vz; }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) Lp[q] = Lc[q];
+                for (int r = 0; r < 4; ++r) Lp[r] = Lc[r];
                 entry = k;
                 ++n_wall;
             }
@@ -282,42 +382,93 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         int Le[4];
         lam4(A, B, C, px, py, pz, l);
         quantize(l, -1, Le);
-        deposit(t, Lp, Le);
         {
-            int slot = t - tbase;
-            int4 tn = a.tnodes[t];
-            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
-            bool local = (unsigned)slot < (unsigned)kWin;
+            long long v[10];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                long long v = (long long)zq * QH_SCALE * Le[q];
-                if (v == 0) continue;
-                if (local) atomic_add_lds(&acc[slot * 10 + 6 + q], v);
-                else atomic_add_i64(a.Q + nv[q], v);
-            }
+            for (int j = 0; j < 6; ++j)
+                v[j] = zq * ((long long)Lp[LE0[j]] * Le[LE1[j]] - (long long)Le[LE0[j]] * Lp[LE1[j]]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[6 + r] = (long long)zq * QH_SCALE * Le[r];
+            put(t, v);
+            if (CAPTURE) record(pid, seq, t, Lp, Le);
         }
-        a.x[i] = px; a.y[i] = py; a.z[i] = pz;
-        a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
-        a.tet[i] = t;
+        sx_[li] = px; sy_[li] = py; sz_[li] = pz;
+        svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
+        st_[li] = t;
     }
     if (n_cross) atomicAdd(&s_cnt[0], n_cross);
     if (n_wall) atomicAdd(&s_cnt[1], n_wall);
     if (n_lost) atomicAdd(&s_cnt[2], n_lost);
+    if (n_foreign) atomicAdd(&s_cnt[4], n_foreign);
     __syncthreads();
-    // flush the window
-    for (int j = threadIdx.x; j < kWin * 10; j += kBlock) {
-        long long v = acc[j];
-        if (v == 0) continue;
-        int slot = j / 10, c = j % 10;
-        int tt = tbase + slot;
-        if (c < 6) atomic_add_i64(a.g + a.tedges[8 * (int64_t)tt + c], v);
-        else {
-            int4 tn = a.tnodes[tt];
-            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
-            atomic_add_i64(a.Q + nv[c - 6], v);
+    // coalesced write-back of the staged particle state
+    if (full) {
+        const int64_t v = i0 / 2;
+        const int l0 = threadIdx.x * kPpt;
+        ((float2 *)a.x)[v] = make_float2(sx_[l0], sx_[l0 + 1]);
+        ((float2 *)a.y)[v] = make_float2(sy_[l0], sy_[l0 + 1]);
+        ((float2 *)a.z)[v] = make_float2(sz_[l0], sz_[l0 + 1]);
+        ((float2 *)a.vx)[v] = make_float2(svx_[l0], svx_[l0 + 1]);
+        ((float2 *)a.vy)[v] = make_float2(svy_[l0], svy_[l0 + 1]);
+        ((float2 *)a.vz)[v] = make_float2(svz_[l0], svz_[l0 + 1]);
+        ((int2 *)a.tet)[v] = make_int2(st_[l0], st_[l0 + 1]);
+    } else {
+        for (int li = threadIdx.x; li < kChunk && base + li < a.n; li += kBlock) {
+            const int64_t i = base + li;
+            a.x[i] = sx_[li]; a.y[i] = sy_[li]; a.z[i] = sz_[li];
+            a.vx[i] = svx_[li]; a.vy[i] = svy_[li]; a.vz[i] = svz_[li];
+            a.tet[i] = st_[li];
         }
     }
-    if (threadIdx.x < 3 && s_cnt[threadIdx.x]) atomicAdd(&a.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    // owned tets: LDS sums for the first W, zeros beyond (their deposits went to atomics)
+    int64_t *dst = a.acc_tet + 10 * (int64_t)T0;
+    const int m = (T1 - T0) * 10;
+    for (int j = threadIdx.x; j < m; j += kBlock) dst[j] = j < W * 10 ? acc[j] : 0;
+    if (threadIdx.x < 4) {
+        unsigned int v = s_cnt[threadIdx.x < 3 ? threadIdx.x : 4];
+        if (v) atomicAdd(&a.counters[(blockIdx.x & (QH_COUNTER_SLOTS - 1)) * 4 + threadIdx.x], (unsigned long long)v);
+    }
+}
+
+// Owned per-tet sums into edges and nodes: deterministic gathers over the incidence lists,
+// 8 lanes per edge or node. Blocks are dealt to the 8 XCDs round-robin by the hardware; the
+// block index is remapped so each XCD takes one contiguous range (its L2 then holds the
+// neighbouring tets' sums the range needs, instead of every L2 fetching all of them).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
+    const unsigned per = (nblocks + 7) / 8;
+    const unsigned x = b & 7, k = b >> 3;
+    const unsigned lb = x * per + k;
+    return lb < nblocks ? lb : 0xffffffffu;
+}
+
+template <int OFF>
+__global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ lst,
+                                                const int64_t *__restrict__ acc_tet, int64_t *__restrict__ out,
+                                                unsigned nblocks_grid) {
+    // grid is padded to a multiple of 8 blocks so the remap is a bijection onto [0, grid)
+    const unsigned lb = xcd_block(blockIdx.x, nblocks_grid);
+    const int sub = threadIdx.x & 7;
+    const int64_t item = (int64_t)lb * 32 + (threadIdx.x >> 3);
+    int64_t s = 0;
+    if (lb != 0xffffffffu && item < nitems) {
+        for (int32_t j = ptr[item] + sub; j < ptr[item + 1]; j += 8) {
+            int32_t v = lst[j];
+            s += acc_tet[10 * (int64_t)(v >> 3) + OFF + (v & 7)];
+        }
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+    if (sub == 0 && lb != 0xffffffffu && item < nitems) out[item] += s;
+}
+
+// owned tet ranges after a sort: own[b] = tet of the block's first particle, own[0] = 0,
+// own[nblocks] = nt
+__global__ void k_own(const int32_t *__restrict__ tet, int64_t n, int32_t nblocks, int32_t nt,
+                      int32_t *__restrict__ own) {
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nblocks) return;
+    own[b] = b == 0 ? 0 : b == nblocks ? nt : tet[(int64_t)b * kChunk];
 }
 
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
@@ -325,17 +476,23 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     StepArgs a;
     a.geo = c->geo; a.frec = c->frec; a.tnodes = c->tnodes; a.tedges = c->tedges; a.tnbr = c->tnbr;
     a.x = s.x; a.y = s.y; a.z = s.zz; a.vx = s.vx; a.vy = s.vy; a.vz = s.vz;
-    a.tet = s.tet; a.pid = s.id; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
+    a.tet = s.tet; a.pid = s.id; a.own = s.own; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
     a.hqm = (float)(0.5 * s.qm * c->phys.dt);
     a.dt = (float)c->phys.dt;
     a.zq = s.z;
-    a.g = c->g; a.Q = c->Q; a.counters = c->counters;
+    a.g = c->g; a.Q = c->Q; a.acc_tet = c->acc_tet; a.counters = c->counters;
     a.species = sidx; a.cap = c->cap_segments; a.seg_count = c->seg_count; a.seg_buf = c->seg_buf;
-    dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
+    dim3 grid((unsigned)((s.n + kChunk - 1) / kChunk));
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
+    const HostMesh &m = c->hm;
+    unsigned ge = (unsigned)(((m.Ne + 31) / 32 + 7) / 8 * 8), gn = (unsigned)(((m.Nn + 31) / 32 + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_gather<0>, dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet, c->g, ge);
+    hipLaunchKernelGGL(k_gather<6>, dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet, c->Q, gn);
     return hipGetLastError();
 }
+
+int64_t qh_species_blocks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
 // ------------------------------------------------------------------------------------------
 // W0 charge of the present positions (after an upload).
@@ -431,11 +588,11 @@ __global__ void k_divb(const int32_t *__restrict__ tfaces, const int8_t *__restr
 hipError_t launch_verify(qh_ctx *c, bool check_divb) {
     int64_t nn = c->hm.Nn;
     hipLaunchKernelGGL(k_continuity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, c->n2e_ptr,
-                       c->n2e, c->g, c->Q, c->Q_old, nn, c->counters + 3);
+                       c->n2e, c->g, c->Q, c->Q_old, nn, c->counters + 4 * QH_COUNTER_SLOTS);
     if (check_divb) {
         int32_t nt = (int32_t)c->hm.Nt;
         hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
-                           (int64_t *)nullptr, c->divb0, c->counters + 4);
+                           (int64_t *)nullptr, c->divb0, c->counters + 4 * QH_COUNTER_SLOTS + 1);
     }
     return hipGetLastError();
 }
@@ -541,5 +698,8 @@ int qh_sort_species(qh_ctx *c, Species &s) {
     std::swap(s.x, s.sx); std::swap(s.y, s.sy); std::swap(s.zz, s.sz);
     std::swap(s.vx, s.svx); std::swap(s.vy, s.svy); std::swap(s.vz, s.svz);
     std::swap(s.tet, s.stet); std::swap(s.id, s.sid);
+    int32_t nb = (int32_t)qh_species_blocks(s.n);
+    hipLaunchKernelGGL(k_own, dim3((nb + 1 + 255) / 256), dim3(256), 0, c->stream, s.tet, s.n, nb, nt, s.own);
+    QH_HIP(c, hipGetLastError());
     return QH_OK;
 }

@@ -15,7 +15,7 @@ constexpr int kLpr = 8;          // lanes per CSR row
 constexpr int kMaxBlocks = 2048; // fixed grid of the reducing kernels (fixed summation order)
 
 // device scalar slots of a CgWork
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_THR2, S_BB, S_RZ0, S_NSLOT };
+enum { S_RZ = 0, S_RZ1, S_RR, S_THR2, S_BB, S_NSLOT };  // S_RZ + parity: r.z (double-buffered)
 
 __device__ __forceinline__ double wave_sum_lpr(double v) {
 #pragma unroll
@@ -23,9 +23,61 @@ __device__ __forceinline__ double wave_sum_lpr(double v) {
     return v;
 }
 
-// Block-wide sum of NV doubles (thread 0 holds the result).
+inline unsigned grid_rows(int64_t nrows) {
+    int64_t b = (nrows * kLpr + kThreads - 1) / kThreads;
+    b = b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks;
+    return (unsigned)((b + 7) / 8 * 8);
+}
+inline unsigned grid_elems(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (unsigned)(b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks);
+}
+
+// Rows of a CSR kernel: each block takes one contiguous range, and the block index is
+// remapped so that each of the 8 XCDs (which receive blocks round-robin) covers one
+// contiguous span of rows: neighbouring rows share the vector entries they gather, and
+// those then stay in one XCD's L2. Grids are multiples of 8 blocks.
+struct Rows {
+    int64_t begin, end;
+};
+__device__ __forceinline__ Rows block_rows(int64_t n) {
+    const unsigned nb = gridDim.x, per_x = nb / 8;
+    const unsigned lb = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
+    const int64_t per = (n + nb - 1) / nb;
+    Rows r;
+    r.begin = (int64_t)lb * per;
+    r.end = r.begin + per < n ? r.begin + per : n;
+    return r;
+}
+
+// ---------------------------------------------------------------------------------------
+// CG kernels. Cross-block sums never use in-kernel synchronisation: a kernel writes one
+// partial per block and every block of the NEXT kernel sums all partials itself in the same
+// fixed order (a few KB from L2), so the result is identical in every block, deterministic,
+// and needs no device-scope fence (which would write back the whole L2 on this part).
+// Scalars: scal[S_RZ + parity] holds r.z of the current iterate (double-buffered by the
+// iteration parity so no block reads a slot another block of the same kernel writes).
+
+// Every block: sum of part[0..m) in a fixed order, returned to all threads.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int m, double *sh) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < m; j += kThreads) s += part[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
+    return t;
+}
+
+// Block-wide sum of NV values, written as this block's partials part[k * kMaxBlocks + block].
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kThreads / 64]) {
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ part) {
+    __shared__ double sh[NV][kThreads / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -35,63 +87,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kThreads
         if (lane == 0) sh[k][wid] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < kThreads / 64; ++w) s += sh[k][w];
-            v[k] = s;
-        }
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += sh[threadIdx.x][w];
+        part[threadIdx.x * kMaxBlocks + blockIdx.x] = t;
     }
 }
 
-// Write NV block partials; the last block to finish sums all partials in a fixed order and
-// returns true in every thread of that block (totals in tot[] of thread 0).
-template <int NV>
-__device__ bool last_block_reduce(double (&v)[NV], double *partial, unsigned int *counter,
-                                  double (&tot)[NV]) {
-    __shared__ double sh[NV][kThreads / 64];
-    __shared__ bool am_last;
-    block_sum<NV>(v, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) partial[k * kMaxBlocks + blockIdx.x] = v[k];
-        __threadfence();
-        unsigned int prev = atomicAdd(counter, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
-    double s[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        s[k] = 0.0;
-        for (int j = threadIdx.x; j < (int)gridDim.x; j += kThreads) s[k] += partial[k * kMaxBlocks + j];
-    }
-    __syncthreads();
-    block_sum<NV>(s, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) tot[k] = s[k];
-        *counter = 0u;
-    }
-    return true;
-}
-
-inline unsigned grid_rows(int64_t nrows) {
-    int64_t b = (nrows * kLpr + kThreads - 1) / kThreads;
-    return (unsigned)(b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks);
-}
-inline unsigned grid_elems(int64_t n) {
-    int64_t b = (n + kThreads - 1) / kThreads;
-    return (unsigned)(b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks);
-}
-
-// ---------------------------------------------------------------------------------------
-// CG kernels
-// init: r = b - A x, z = D^-1 r, p_old = 0, beta = 0; rz, rr, bb; thr2 = tol^2 bb unless an
-// absolute threshold is supplied.
+// init: r = b - A x, z = D^-1 r, p_old = 0; partials of r.z, r.r, b.b
 __global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
@@ -99,14 +102,11 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *
                                                       const double *__restrict__ b,
                                                       const double *__restrict__ dinv,
                                                       double *__restrict__ r, double *__restrict__ z,
-                                                      double *__restrict__ p_old, double *partial,
-                                                      unsigned int *counter, double *scal,
-                                                      int32_t *flags, double tol2,
-                                                      const double *abs_thr2) {
+                                                      double *__restrict__ p_old, double *__restrict__ part) {
     const int sub = threadIdx.x % kLpr;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kThreads / kLpr);
+    const Rows rr_ = block_rows(n);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t row = (int64_t)blockIdx.x * (kThreads / kLpr) + threadIdx.x / kLpr; row < n; row += rows_per_grid) {
+    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
         double s = 0.0;
         for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * x[col[j]];
         s = wave_sum_lpr(s);
@@ -121,65 +121,85 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *
             acc[2] += b[row] * b[row];
         }
     }
-    double tot[3];
-    if (last_block_reduce<3>(acc, partial, counter, tot) && threadIdx.x == 0) {
-        scal[S_RZ] = tot[0];
-        scal[S_RR] = tot[1];
-        scal[S_BB] = tot[2];
-        scal[S_RZ0] = tot[0];
-        scal[S_BETA] = 0.0;
-        double thr2 = abs_thr2 ? *abs_thr2 : tol2 * tot[2];
+    write_partials<3>(acc, part);
+}
+
+// one block: totals of the init partials; threshold; convergence flag
+__global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict__ part, int m, double *scal,
+                                                       int32_t *flags, double tol2, const double *abs_thr2) {
+    __shared__ double sh[kThreads / 64];
+    double rz = sum_partials(part, m, sh);
+    double rr = sum_partials(part + kMaxBlocks, m, sh);
+    double bb = sum_partials(part + 2 * kMaxBlocks, m, sh);
+    if (threadIdx.x == 0) {
+        double thr2 = abs_thr2 ? *abs_thr2 : tol2 * bb;
+        scal[S_RZ] = rz;
+        scal[S_RR] = rr;
+        scal[S_BB] = bb;
         scal[S_THR2] = thr2;
-        flags[0] = (tot[1] <= thr2) ? 1 : 0;
+        flags[0] = (rr <= thr2) ? 1 : 0;
         flags[1] = 0;
     }
 }
 
-// p_new = z + beta p_old (own rows); q = A p_new, gathered on the fly; pq.
+// Iteration k (parity par = k & 1). For k > 0 first finish the previous update: r.z and
+// r.r from its partials, convergence test, beta. Then, with w = A z (the only gathered
+// vector), p = z + beta p and q = A p = w + beta q in place (own rows only), and the
+// partials of p.q. Gathering one vector instead of z and p halves the scattered loads.
 __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ z,
-                                                      const double *__restrict__ p_old,
-                                                      double *__restrict__ p_new, double *__restrict__ q,
-                                                      double *partial, unsigned int *counter,
-                                                      double *scal, const int32_t *flags) {
+                                                      double *__restrict__ p, double *__restrict__ q,
+                                                      const double *__restrict__ upart, double *__restrict__ part,
+                                                      int m, double *scal, int32_t *flags, int32_t k, int32_t par) {
     if (flags[0]) return;
-    const double beta = scal[S_BETA];
-    const int sub = threadIdx.x % kLpr;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kThreads / kLpr);
-    double acc[1] = {0.0};
-    for (int64_t row = (int64_t)blockIdx.x * (kThreads / kLpr) + threadIdx.x / kLpr; row < n; row += rows_per_grid) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) {
-            int32_t cj = col[j];
-            s += val[j] * (z[cj] + beta * p_old[cj]);
+    __shared__ double sh[kThreads / 64];
+    double beta = 0.0;
+    if (k > 0) {
+        double rz_new = sum_partials(upart, m, sh);
+        double rr = sum_partials(upart + kMaxBlocks, m, sh);
+        bool done = rr <= scal[S_THR2] || !(rr == rr);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[S_RZ + (par ^ 1)] = rz_new;
+            scal[S_RR] = rr;
+            flags[1] = k;
+            if (done) flags[0] = 1;
         }
+        if (done) return;
+        beta = rz_new / scal[S_RZ + par];
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_RZ + 1] = scal[S_RZ];
+    }
+    const int sub = threadIdx.x % kLpr;
+    const Rows rr_ = block_rows(n);
+    double acc[1] = {0.0};
+    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
+        double s = 0.0;
+        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * z[col[j]];
         s = wave_sum_lpr(s);
         if (sub == 0) {
-            double pn = z[row] + beta * p_old[row];
-            p_new[row] = pn;
-            q[row] = s;
-            acc[0] += pn * s;
+            double pn = k > 0 ? z[row] + beta * p[row] : z[row];
+            double qn = k > 0 ? s + beta * q[row] : s;
+            p[row] = pn;
+            q[row] = qn;
+            acc[0] += pn * qn;
         }
     }
-    double tot[1];
-    if (last_block_reduce<1>(acc, partial, counter, tot) && threadIdx.x == 0) {
-        scal[S_PQ] = tot[0];
-        scal[S_ALPHA] = scal[S_RZ] / tot[0];
-    }
+    write_partials<1>(acc, part);
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r; rz, rr -> beta, convergence flag.
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials of r.z, r.r
 __global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__restrict__ x,
                                                         double *__restrict__ r, double *__restrict__ z,
                                                         const double *__restrict__ p,
                                                         const double *__restrict__ q,
                                                         const double *__restrict__ dinv,
-                                                        double *partial, unsigned int *counter,
-                                                        double *scal, int32_t *flags) {
+                                                        const double *__restrict__ qpart, double *__restrict__ part,
+                                                        int m, const double *scal, const int32_t *flags, int32_t par) {
     if (flags[0]) return;
-    const double alpha = scal[S_ALPHA];
+    __shared__ double sh[kThreads / 64];
+    const double alpha = scal[S_RZ + (par ^ 1)] / sum_partials(qpart, m, sh);
     double acc[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         x[i] += alpha * p[i];
@@ -190,13 +210,19 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__res
         acc[0] += ri * zi;
         acc[1] += ri * ri;
     }
-    double tot[2];
-    if (last_block_reduce<2>(acc, partial, counter, tot) && threadIdx.x == 0) {
-        scal[S_BETA] = tot[0] / scal[S_RZ];
-        scal[S_RZ] = tot[0];
-        scal[S_RR] = tot[1];
-        flags[1] += 1;
-        if (tot[1] <= scal[S_THR2] || !(tot[1] == tot[1])) flags[0] = 1;
+    write_partials<2>(acc, part);
+}
+
+// one block, after a batch: finish the last update's convergence test
+__global__ void __launch_bounds__(kThreads) k_cg_check(const double *__restrict__ upart, int m, double *scal,
+                                                       int32_t *flags, int32_t k) {
+    if (flags[0]) return;
+    __shared__ double sh[kThreads / 64];
+    double rr = sum_partials(upart + kMaxBlocks, m, sh);
+    if (threadIdx.x == 0) {
+        scal[S_RR] = rr;
+        flags[1] = k;
+        if (rr <= scal[S_THR2] || !(rr == rr)) flags[0] = 1;
     }
 }
 
@@ -230,8 +256,9 @@ __global__ void __launch_bounds__(kThreads) k_edge_rhs(int32_t n, const int32_t 
                                                        const int32_t *__restrict__ int_edges, double dtub,
                                                        double u_q, double *__restrict__ rhs) {
     const int sub = threadIdx.x % kLpr;
-    const int64_t row = (int64_t)blockIdx.x * (kThreads / kLpr) + threadIdx.x / kLpr;
-    if (row >= n) return;
+    const Rows rr_ = block_rows(n);
+    const int64_t row = rr_.begin + threadIdx.x / kLpr;
+    if (row >= rr_.end) return;
     double s = 0.0, t = 0.0;
     for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += (2.0 * mval[j] - aval[j]) * e[col[j]];
     for (int32_t j = cptr[row] + sub; j < cptr[row + 1]; j += kLpr) t += cval[j] * (double)b[ccol[j]];
@@ -241,7 +268,9 @@ __global__ void __launch_bounds__(kThreads) k_edge_rhs(int32_t n, const int32_t 
 }
 
 // Gauss residual rg = rho - G^T [*eps] e on interior nodes, rho = u_q (Q_bg - Q);
-// threshold thr2 = (tol_n (||rho|| + ||G^T [*eps] e||))^2.
+// threshold thr2 = (tol_n (||rho|| + || |G^T [*eps]| |e| ||))^2: the residual is measured
+// against the size of the terms that cancel in G^T [*eps] e (normwise backward error), so
+// the tolerance stays above the FP64 rounding floor when the charge is small against E.
 __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t *__restrict__ ptr,
                                                         const int32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -250,15 +279,19 @@ __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t
                                                         const int64_t *__restrict__ Q,
                                                         const int32_t *__restrict__ int_nodes, double u_q,
                                                         double *__restrict__ rg, double *__restrict__ rho_out,
-                                                        double *partial, unsigned int *counter,
-                                                        double *out, double tol_n) {
+                                                        double *__restrict__ part) {
     const int sub = threadIdx.x % kLpr;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kThreads / kLpr);
+    const Rows rr_ = block_rows(n);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t row = (int64_t)blockIdx.x * (kThreads / kLpr) + threadIdx.x / kLpr; row < n; row += rows_per_grid) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * e[col[j]];
+    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
+        double s = 0.0, sa = 0.0;
+        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) {
+            double t = val[j] * e[col[j]];
+            s += t;
+            sa += fabs(t);
+        }
         s = wave_sum_lpr(s);
+        sa = wave_sum_lpr(sa);
         if (sub == 0) {
             int32_t gn = int_nodes[row];
             double rho = u_q * (double)(Qbg[gn] - Q[gn]);
@@ -266,16 +299,25 @@ __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t
             rg[row] = r;
             if (rho_out) rho_out[row] = rho;
             acc[0] += rho * rho;
-            acc[1] += s * s;
+            acc[1] += sa * sa;
             acc[2] += r * r;
         }
     }
-    double tot[3];
-    if (last_block_reduce<3>(acc, partial, counter, tot) && threadIdx.x == 0) {
-        double scale = sqrt(tot[0]) + sqrt(tot[1]);
-        out[0] = tol_n * tol_n * scale * scale;  // threshold on ||r||^2
+    write_partials<3>(acc, part);
+}
+
+// one block: out[0] = (tol_n scale)^2, out[1] = scale, out[2] = ||r||^2
+__global__ void __launch_bounds__(kThreads) k_gauss_finish(const double *__restrict__ part, int m, double *out,
+                                                           double tol_n) {
+    __shared__ double sh[kThreads / 64];
+    double a = sum_partials(part, m, sh);
+    double b = sum_partials(part + kMaxBlocks, m, sh);
+    double c = sum_partials(part + 2 * kMaxBlocks, m, sh);
+    if (threadIdx.x == 0) {
+        double scale = sqrt(a) + sqrt(b);
+        out[0] = tol_n * tol_n * scale * scale;
         out[1] = scale;
-        out[2] = tot[2];
+        out[2] = c;
     }
 }
 
@@ -310,17 +352,16 @@ __global__ void k_faraday_b(int64_t nf, const int32_t *__restrict__ fe, const in
     b[f] -= u[fe[3 * f + 2]] - u[fe[3 * f + 1]] + u[fe[3 * f]];
 }
 
-// ||b - A x||^2 and ||b||^2
+// ||b - A x||^2 and ||b||^2 (partials)
 __global__ void __launch_bounds__(kThreads) k_true_res(int32_t n, const int32_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val,
                                                        const double *__restrict__ x,
-                                                       const double *__restrict__ b, double *partial,
-                                                       unsigned int *counter, double *out) {
+                                                       const double *__restrict__ b, double *__restrict__ part) {
     const int sub = threadIdx.x % kLpr;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kThreads / kLpr);
+    const Rows rr_ = block_rows(n);
     double acc[2] = {0.0, 0.0};
-    for (int64_t row = (int64_t)blockIdx.x * (kThreads / kLpr) + threadIdx.x / kLpr; row < n; row += rows_per_grid) {
+    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
         double s = 0.0;
         for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * x[col[j]];
         s = wave_sum_lpr(s);
@@ -330,10 +371,16 @@ __global__ void __launch_bounds__(kThreads) k_true_res(int32_t n, const int32_t 
             acc[1] += b[row] * b[row];
         }
     }
-    double tot[2];
-    if (last_block_reduce<2>(acc, partial, counter, tot) && threadIdx.x == 0) {
-        out[0] = tot[0];
-        out[1] = tot[1];
+    write_partials<2>(acc, part);
+}
+
+__global__ void __launch_bounds__(kThreads) k_sum2(const double *__restrict__ part, int m, double *out) {
+    __shared__ double sh[kThreads / 64];
+    double a = sum_partials(part, m, sh);
+    double b = sum_partials(part + kMaxBlocks, m, sh);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
     }
 }
 
@@ -345,7 +392,7 @@ int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n) {
     if ((rc = qh_alloc(c, &w.x, n)) || (rc = qh_alloc(c, &w.r, n)) || (rc = qh_alloc(c, &w.z, n)) ||
         (rc = qh_alloc(c, &w.q, n)) || (rc = qh_alloc(c, &w.p0, n)) || (rc = qh_alloc(c, &w.p1, n)) ||
         (rc = qh_alloc(c, &w.dinv, n)) || (rc = qh_alloc(c, &w.b, n)) ||
-        (rc = qh_alloc(c, &w.partial, 4 * kMaxBlocks)) || (rc = qh_alloc(c, &w.scal, 16)) ||
+        (rc = qh_alloc(c, &w.partial, 8 * kMaxBlocks)) || (rc = qh_alloc(c, &w.scal, 16)) ||
         (rc = qh_alloc(c, &w.counter, 4)) || (rc = qh_alloc(c, &w.flags, 4)))
         return rc;
     QH_HIP(c, hipMemsetAsync(w.counter, 0, 4 * sizeof(unsigned int), c->stream));
@@ -360,43 +407,57 @@ hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv) {
 }
 
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
-                SolveResult &out, const double *abs_thr2_dev) {
+                SolveResult &out, const double *abs_thr2_dev, bool node_system) {
+    const int k_spmv = node_system ? QK_NODE_SPMV : QK_CG_SPMV;
+    const int k_upd = node_system ? QK_NODE_UPDATE : QK_CG_UPDATE;
     out = SolveResult();
     if (w.n == 0) {
         out.converged = true;
         return QH_OK;
     }
+    // partial arrays: [0, 4K) init / update, [4K, 8K) products
+    double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks;
     const unsigned gr = grid_rows(w.n), ge = grid_elems(w.n);
+    int t0 = qh_tbeg(c);
     hipLaunchKernelGGL(k_cg_init, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, w.dinv,
-                       w.r, w.z, w.p0, w.partial, w.counter, w.scal, w.flags, tol * tol, abs_thr2_dev);
+                       w.r, w.z, w.p0, upart);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr, w.scal, w.flags, tol * tol,
+                       abs_thr2_dev);
+    qh_tend(c, t0, QK_CG_INIT);
     QH_HIP(c, hipGetLastError());
     if (check_every <= 0) check_every = 8;
     int32_t hflags[2] = {0, 0};
     int it = 0;
-    double *pa = w.p0, *pb = w.p1;
-    while (it < max_it) {
+    // the update partials come from the update kernel's grid (ge blocks), the init's from gr
+    int m_up = (int)gr;
+    QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    while (it < max_it && !hflags[0]) {
         int batch = std::min(check_every, max_it - it);
-        for (int k = 0; k < batch; ++k) {
-            int t0 = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_spmv, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.z, pa, pb,
-                               w.q, w.partial, w.counter, w.scal, w.flags);
-            qh_tend(c, t0, QK_CG_SPMV);
-            int t1 = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, pb, w.q, w.dinv,
-                               w.partial, w.counter, w.scal, w.flags);
-            qh_tend(c, t1, QK_CG_UPDATE);
-            std::swap(pa, pb);
+        for (int k = it; k < it + batch; ++k) {
+            int par = k & 1;
+            int ta = qh_tbeg(c);
+            hipLaunchKernelGGL(k_cg_spmv, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.z, w.p0,
+                               w.q, upart, qpart, m_up, w.scal, w.flags, k, par);
+            qh_tend(c, ta, k_spmv);
+            int tb = qh_tbeg(c);
+            hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0, w.q,
+                               w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
+            qh_tend(c, tb, k_upd);
+            m_up = (int)ge;
         }
         it += batch;
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags, it);
         QH_HIP(c, hipGetLastError());
         QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
-        if (hflags[0]) break;
     }
     out.iters = hflags[1];
     // true residual, recomputed
-    hipLaunchKernelGGL(k_true_res, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b,
-                       w.partial, w.counter, w.scal + 8);
+    int tr = qh_tbeg(c);
+    hipLaunchKernelGGL(k_true_res, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, upart);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr, w.scal + 8);
+    qh_tend(c, tr, QK_TRUE_RES);
     double res2[2];
     QH_HIP(c, hipMemcpyAsync(res2, w.scal + 8, sizeof(res2), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
@@ -414,7 +475,8 @@ hipError_t launch_assemble_A(qh_ctx *c, double tau) {
 
 hipError_t launch_edge_rhs(qh_ctx *c) {
     int32_t n = c->A.n;
-    unsigned gr = (unsigned)(((int64_t)n * kLpr + kThreads - 1) / kThreads);
+    // one row per lane group: a grid of ceil(n / 32) blocks, padded to a multiple of 8
+    unsigned gr = (unsigned)((((int64_t)n * kLpr + kThreads - 1) / kThreads + 7) / 8 * 8);
     hipLaunchKernelGGL(k_edge_rhs, dim3(gr), dim3(kThreads), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val, c->A.val2,
                        c->cge.x, c->CMb.ptr, c->CMb.col, c->CMb.val, c->b, c->g, c->int_edges,
                        c->phys.dt * c->phys.u_b, c->phys.u_q, c->cge.b);
@@ -423,9 +485,11 @@ hipError_t launch_edge_rhs(qh_ctx *c) {
 
 hipError_t launch_gauss_rhs(qh_ctx *c, double *out3, double tol_n) {
     int32_t n = c->GtM.n;
-    hipLaunchKernelGGL(k_gauss_rhs, dim3(grid_rows(n)), dim3(kThreads), 0, c->stream, n, c->GtM.ptr, c->GtM.col,
+    unsigned gr = grid_rows(n);
+    hipLaunchKernelGGL(k_gauss_rhs, dim3(gr), dim3(kThreads), 0, c->stream, n, c->GtM.ptr, c->GtM.col,
                        c->GtM.val, c->cge.x, c->Q_bg, c->Q, c->int_nodes, c->phys.u_q, c->cgn.b, c->rho,
-                       c->cgn.partial, c->cgn.counter, out3, tol_n);
+                       c->cgn.partial);
+    hipLaunchKernelGGL(k_gauss_finish, dim3(1), dim3(kThreads), 0, c->stream, c->cgn.partial, (int)gr, out3, tol_n);
     return hipGetLastError();
 }
 
@@ -447,7 +511,9 @@ hipError_t launch_faraday(qh_ctx *c) {
 }
 
 hipError_t launch_true_residual(qh_ctx *c, const DevCsr &M, const double *x, const double *b, double *out2) {
-    hipLaunchKernelGGL(k_true_res, dim3(grid_rows(M.n)), dim3(kThreads), 0, c->stream, M.n, M.ptr, M.col, M.val, x, b,
-                       c->cge.partial, c->cge.counter, out2);
+    unsigned gr = grid_rows(M.n);
+    hipLaunchKernelGGL(k_true_res, dim3(gr), dim3(kThreads), 0, c->stream, M.n, M.ptr, M.col, M.val, x, b,
+                       c->cge.partial);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, c->cge.partial, (int)gr, out2);
     return hipGetLastError();
 }

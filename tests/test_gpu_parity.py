@@ -87,7 +87,8 @@ def test_one_step_integer_path_bit_exact(c1):
     # Q0 equals the oracle's W0 charge of the same FP32 start points (FP32 lambda in a tie
     # band can differ by one unit; all others equal)
     Qo = node_charge(po, cx, r["x0"], r["t0"], -1)
-    assert np.abs(r["Q0"] - Qo).max() <= 4 * S
+    per_node = np.bincount(cx.tets[r["t0"]].ravel(), minlength=cx.Nn)
+    assert (np.abs(r["Q0"] - Qo) <= 4 * S * per_node).all()
     # the GPU's own pieces, re-deposited by the oracle, reproduce its g and Q bit for bit
     seg = r["seg"]
     assert r["nseg"] == seg["tet"].size
