@@ -188,6 +188,44 @@ int qh_deposit(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t
 int qh_field_solve(qh_ctx *ctx, int32_t system, const double *rhs, double *x, double tol,
                    int32_t max_it, int32_t precond, qh_solve_stats_t *stats);
 
+/* Learned preconditioner for the edge system (used with precond = QH_PC_LEARNED).
+ * M = G^T G with G sparse lower triangular on the pattern of A; a network 16 -> 64 -> 64 -> 1
+ * (ReLU) maps 16 dimensionless local features of each entry (i, j), j <= i, to o_ij and
+ * G_ij = o_ij / sqrt(A_jj), G_ii = softplus(o_ii + s0) / sqrt(A_ii), softplus(s0) = 1 (a zero
+ * network is Jacobi). Inference runs on MFMA in BF16 with FP32 accumulation. Weights: FP32,
+ * QH_MLP_NPARAM values: W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3 (out x in, row
+ * major). Not from the paper, which leaves the linear solver open. */
+#define QH_MLP_NPARAM 5313
+int qh_precond_set_weights(qh_ctx *ctx, const float *w, int64_t n);
+int qh_precond_get_weights(qh_ctx *ctx, float *w, int64_t n);
+/* Entries of G: rows/cols (interior-edge indices, row-major lower triangle of A's pattern) and
+ * FP32 values for the current weights. Pass rows = cols = vals = NULL to query *nnz. */
+int qh_precond_factor(qh_ctx *ctx, int64_t *nnz, int32_t *rows, int32_t *cols, float *vals);
+/* Training objective L = log(tr(G A G^T)/n) - (2/n) sum_i log G_ii (log of the Kaporin
+ * condition number of G A G^T up to a constant), trace estimated with the 16 probe vectors
+ * probes[i*16 + p] (node-major, n_int_edges x 16); and, if grad != NULL, dL/dweights
+ * (QH_MLP_NPARAM floats, computed by the MFMA backward kernel). */
+int qh_precond_loss_grad(qh_ctx *ctx, const float *probes, double *loss, float *grad);
+typedef struct {
+    int32_t steps;          /* Adam steps, 16 Rademacher probes each */
+    float lr;
+    uint64_t seed;          /* probe generator seed */
+    int32_t validate_every; /* PCG on the first (up to 2) pairs every k steps; best weights kept */
+    double val_tol;         /* validation solve tolerance (e.g. 1e-8) */
+    int32_t val_max_it;
+} qh_train_params_t;
+typedef struct {
+    int32_t steps_done;
+    double loss_first, loss_last;
+    int32_t val_iters_jacobi, val_iters_best, best_step; /* summed over the validation pairs */
+    float ms;
+} qh_train_stats_t;
+/* Train on the GPU. rhs, sol: n_pairs x n_int_edges (pair-major) right-hand sides and solutions
+ * of the edge system produced by the plain solver; they validate each candidate (PCG iterations
+ * to val_tol) and select the weights kept. */
+int qh_precond_train(qh_ctx *ctx, const qh_train_params_t *params, int32_t n_pairs,
+                     const double *rhs, const double *sol, qh_train_stats_t *stats);
+
 /* Assembled FP64 matrices as CSR (0-based, sorted columns), host copies. which:
  * 0 A = [*eps] + dt^2/4 S, 1 [*eps], 2 S = C^T [*mu^-1] C (all interior edges x interior
  * edges), 3 C^T [*mu^-1] (interior edges x all faces), 4 G^T [*eps] (interior nodes x
@@ -200,7 +238,8 @@ int qh_matrix_download(const qh_ctx *ctx, int32_t which, int32_t *ptr, int32_t *
  * 0 field prep, 1 particle step, 2 sort, 3 edge right-hand side, 4 edge-system CG product
  * (fused direction update + SpMV + dot), 5 edge-system CG vector update, 6 CG init,
  * 7 Gauss-law set-up and correction, 8 Faraday update, 9 residual check, 10 node-system CG
- * product, 11 node-system CG vector update. ms_total[k]: summed ms; launches[k]: count. */
+ * product, 11 node-system CG vector update, 12 learned preconditioner application.
+ * ms_total[k]: summed ms; launches[k]: count. */
 int qh_timing_enable(qh_ctx *ctx, int32_t on);
 int qh_timing_read(const qh_ctx *ctx, int32_t n, double *ms_total, int64_t *launches);
 

@@ -21,14 +21,17 @@ FIELDS_FROZEN, FIELDS_SOLVE = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
-           "gauss", "faraday", "true_res", "node_spmv", "node_update"]
+           "gauss", "faraday", "true_res", "node_spmv", "node_update", "precond"]
+MLP_NPARAM = 5313
 F_BITS = 20
 EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mesh_info",
            "qh_mesh_topology", "qh_set_physics", "qh_fields_upload", "qh_fields_download",
            "qh_fields_init_synthetic", "qh_species_add", "qh_particles_upload",
            "qh_particles_download", "qh_charge_background", "qh_pic_step", "qh_deposits_download",
            "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
-           "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read"]
+           "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
+           "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
+           "qh_precond_train"]
 
 
 class QhError(RuntimeError):
@@ -61,6 +64,20 @@ class StepStats(C.Structure):
                 ("wall_hits", C.c_int64), ("lost", C.c_int64), ("continuity_bad", C.c_int64),
                 ("divb_bad", C.c_int64), ("fallbacks", C.c_int32), ("ms_particles", C.c_float),
                 ("ms_fields", C.c_float), ("foreign", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64), ("validate_every", C.c_int32),
+                ("val_tol", C.c_double), ("val_max_it", C.c_int32)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("steps_done", C.c_int32), ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("val_iters_jacobi", C.c_int32), ("val_iters_best", C.c_int32), ("best_step", C.c_int32),
+                ("ms", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,6 +123,11 @@ def lib():
             "qh_matrix_download": [p, i32, p, p, p],
             "qh_timing_enable": [p, i32],
             "qh_timing_read": [p, i32, p, p],
+            "qh_precond_set_weights": [p, p, i64],
+            "qh_precond_get_weights": [p, p, i64],
+            "qh_precond_factor": [p, C.POINTER(i64), p, p, p],
+            "qh_precond_loss_grad": [p, p, C.POINTER(d), p],
+            "qh_precond_train": [p, C.POINTER(TrainParams), i32, p, p, C.POINTER(TrainStats)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -290,6 +312,42 @@ class Context:
                                    int(precond), C.byref(st))
         self._check(rc, allow)
         return x, dict(iters=st.iters, res=st.res, fallback=st.fallback, ms=st.ms)
+
+    # learned preconditioner -------------------------------------------------------------
+    def precond_set_weights(self, w):
+        w = _c(w, np.float32)
+        self._check(self.L.qh_precond_set_weights(self.h, _ptr(w), w.size))
+
+    def precond_get_weights(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        self._check(self.L.qh_precond_get_weights(self.h, _ptr(w), w.size))
+        return w
+
+    def precond_factor(self):
+        nnz = C.c_int64()
+        self._check(self.L.qh_precond_factor(self.h, C.byref(nnz), None, None, None))
+        rows = np.zeros(nnz.value, np.int32)
+        cols = np.zeros(nnz.value, np.int32)
+        vals = np.zeros(nnz.value, np.float32)
+        self._check(self.L.qh_precond_factor(self.h, C.byref(nnz), _ptr(rows), _ptr(cols), _ptr(vals)))
+        return rows, cols, vals
+
+    def precond_loss_grad(self, probes, want_grad=True):
+        probes = _c(probes, np.float32)
+        loss = C.c_double()
+        grad = np.zeros(MLP_NPARAM, np.float32) if want_grad else None
+        self._check(self.L.qh_precond_loss_grad(self.h, _ptr(probes), C.byref(loss), _ptr(grad)))
+        return loss.value, grad
+
+    def precond_train(self, steps=200, lr=3e-3, seed=1, validate_every=25, val_tol=1e-8, val_max_it=3000,
+                      rhs=None, sol=None):
+        P = TrainParams(steps, lr, seed, validate_every, val_tol, val_max_it)
+        n_pairs = 0 if rhs is None else rhs.shape[0]
+        rhs = None if rhs is None else _c(rhs, np.float64)
+        sol = None if sol is None else _c(sol, np.float64)
+        st = TrainStats()
+        self._check(self.L.qh_precond_train(self.h, C.byref(P), n_pairs, _ptr(rhs), _ptr(sol), C.byref(st)))
+        return st.as_dict()
 
     # timing ---------------------------------------------------------------------------
     def timing(self, on):

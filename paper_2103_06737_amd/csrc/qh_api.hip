@@ -538,7 +538,13 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     if (!c->have_mesh || !c->have_phys || !c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
     if (!c->have_fields) return qh_fail(c, QH_ESTATE, "fields first");
     if (P->field_mode != QH_FIELDS_FROZEN && P->field_mode != QH_FIELDS_SOLVE) return qh_fail(c, QH_EINVAL, "field_mode");
-    if (P->precond != QH_PC_JACOBI) return qh_fail(c, QH_EINVAL, "preconditioner not available");
+    if (P->precond != QH_PC_JACOBI && P->precond != QH_PC_LEARNED) return qh_fail(c, QH_EINVAL, "precond");
+    const bool learned = P->precond == QH_PC_LEARNED && P->field_mode == QH_FIELDS_SOLVE;
+    if (learned) {
+        int rc = qh_learned_setup(c);
+        if (rc) return rc;
+        if (!c->lp.factor_valid && (rc = qh_learned_factor(c))) return rc;
+    }
     const HostMesh &m = c->hm;
     int status = QH_OK;
     hipEvent_t ev[4];
@@ -579,8 +585,21 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             int t0 = qh_tbeg(c);
             QH_HIP(c, launch_edge_rhs(c));
             qh_tend(c, t0, QK_EDGE_RHS);
-            int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr);
+            int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr, false,
+                                 learned);
             if (rc) return rc;
+            int fallbacks = 0;
+            if (learned && !se.converged) {
+                // Jacobi restart from e^n: the learned preconditioner stalled or produced a non-finite value
+                QH_HIP(c, hipMemcpyAsync(c->cge.x, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
+                SolveResult sj;
+                rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, sj, nullptr);
+                if (rc) return rc;
+                sj.iters += se.iters;
+                se = sj;
+                fallbacks = 1;
+            }
+            c->last_fallbacks = fallbacks;
             if (!se.converged) status = QH_ENOTCONV;
             if (P->gauss) {
                 t0 = qh_tbeg(c);
@@ -630,6 +649,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.continuity_bad = P->verify ? (int64_t)cnt[3] : -1;
             S.divb_bad = P->verify ? (int64_t)cnt[4] : -1;
             S.foreign = (int64_t)cnt[5];
+            S.fallbacks = P->field_mode == QH_FIELDS_SOLVE ? c->last_fallbacks : 0;
             (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
             (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
             if (S.lost && status == QH_OK) status = QH_ELOST;
@@ -650,10 +670,16 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     if (!c || !rhs || !x || max_it < 0) return QH_EINVAL;
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
-    if (precond != QH_PC_JACOBI) return qh_fail(c, QH_EINVAL, "preconditioner not available");
     const DevCsr *M = system == QH_SYS_EDGE ? &c->A : system == QH_SYS_NODE ? &c->K : nullptr;
     if (!M) return qh_fail(c, QH_EINVAL, "system must be QH_SYS_EDGE or QH_SYS_NODE");
+    if (precond != QH_PC_JACOBI && !(precond == QH_PC_LEARNED && system == QH_SYS_EDGE))
+        return qh_fail(c, QH_EINVAL, "the learned preconditioner exists for the edge system only");
+    const bool learned = precond == QH_PC_LEARNED;
     int rc;
+    if (learned) {
+        if ((rc = qh_learned_setup(c))) return rc;
+        if (!c->lp.factor_valid && (rc = qh_learned_factor(c))) return rc;
+    }
     int32_t nmax = std::max(c->A.n, c->K.n);
     if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
     CgWork w = c->cgx;
@@ -666,20 +692,166 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     QH_HIP(c, hipEventCreate(&e1));
     QH_HIP(c, hipEventRecord(e0, c->stream));
     SolveResult r;
-    rc = qh_cg_solve(c, *M, w, tol, max_it, 8, r, nullptr);
-    QH_HIP(c, hipEventRecord(e1, c->stream));
+    rc = qh_cg_solve(c, *M, w, tol, max_it, 8, r, nullptr, false, learned);
     if (rc) return rc;
+    int fallback = 0;
+    if (learned && !r.converged) {
+        QH_HIP(c, hipMemcpyAsync(w.x, x, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
+        SolveResult rj;
+        rc = qh_cg_solve(c, *M, w, tol, max_it, 8, rj, nullptr);
+        if (rc) return rc;
+        rj.iters += r.iters;
+        r = rj;
+        fallback = 1;
+    }
+    QH_HIP(c, hipEventRecord(e1, c->stream));
     QH_HIP(c, hipMemcpyAsync(x, w.x, sizeof(double) * w.n, hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
     if (stats) {
         stats->iters = r.iters;
         stats->res = r.res;
-        stats->fallback = 0;
+        stats->fallback = fallback;
         (void)hipEventElapsedTime(&stats->ms, e0, e1);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return r.converged ? QH_OK : qh_fail(c, QH_ENOTCONV, "iteration cap reached");
+}
+
+int qh_precond_set_weights(qh_ctx *c, const float *w, int64_t n) {
+    if (!c || !w || n != QH_MLP_NPARAM) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(w[k])) c->err = "non-finite weights (the solve will fall back to Jacobi)";
+    c->lp.have_weights = true;  // keep setup from overwriting
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    QH_HIP(c, hipMemcpyAsync(c->lp.w, w, 4 * n, hipMemcpyHostToDevice, c->stream));
+    c->lp.factor_valid = false;
+    return sync(c);
+}
+
+int qh_precond_get_weights(qh_ctx *c, float *w, int64_t n) {
+    if (!c || !w || n != QH_MLP_NPARAM) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    QH_HIP(c, hipMemcpyAsync(w, c->lp.w, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_precond_factor(qh_ctx *c, int64_t *nnz, int32_t *rows, int32_t *cols, float *vals) {
+    if (!c || !nnz) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    if ((rc = qh_learned_factor(c))) return rc;
+    const LearnedPrec &L = c->lp;
+    *nnz = L.nnz;
+    if (rows) std::copy(L.h_row.begin(), L.h_row.end(), rows);
+    if (cols) std::copy(L.h_col.begin(), L.h_col.end(), cols);
+    if (vals) QH_HIP(c, hipMemcpyAsync(vals, L.gval, 4 * L.nnz, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_precond_loss_grad(qh_ctx *c, const float *probes, double *loss, float *grad) {
+    if (!c || !probes || !loss) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    LearnedPrec &L = c->lp;
+    if (!L.V && (rc = qh_alloc(c, &L.V, (int64_t)L.n * 16))) return rc;
+    QH_HIP(c, hipMemcpyAsync(L.V, probes, 4 * (int64_t)L.n * 16, hipMemcpyHostToDevice, c->stream));
+    if ((rc = qh_learned_loss_grad(c, L.V, grad != nullptr))) return rc;
+    QH_HIP(c, hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (grad) QH_HIP(c, hipMemcpyAsync(grad, L.grad, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_precond_train(qh_ctx *c, const qh_train_params_t *P, int32_t n_pairs, const double *rhs, const double *sol,
+                     qh_train_stats_t *st) {
+    if (!c || !P || P->steps < 0 || n_pairs < 0 || (n_pairs > 0 && !rhs)) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    LearnedPrec &L = c->lp;
+    const int32_t n = L.n;
+    if (!L.V && (rc = qh_alloc(c, &L.V, (int64_t)n * 16))) return rc;
+    if (!L.best_w && (rc = qh_alloc(c, &L.best_w, QH_MLP_NPARAM))) return rc;
+    if (L.adam_t == 0) {
+        QH_HIP(c, hipMemsetAsync(L.adam_m, 0, 4 * QH_MLP_NPARAM, c->stream));
+        QH_HIP(c, hipMemsetAsync(L.adam_v, 0, 4 * QH_MLP_NPARAM, c->stream));
+    }
+    int32_t nmax = std::max(c->A.n, c->K.n);
+    if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
+    CgWork w = c->cgx;
+    w.n = c->A.n;
+    const int n_val = std::min<int32_t>(n_pairs, 2);
+    auto validate = [&](bool learned, int *iters) -> int {
+        int tot = 0;
+        for (int k = 0; k < n_val; ++k) {
+            QH_HIP(c, hipMemcpyAsync(w.b, rhs + (int64_t)k * n, 8 * (int64_t)n, hipMemcpyHostToDevice, c->stream));
+            QH_HIP(c, hipMemsetAsync(w.x, 0, 8 * (int64_t)n, c->stream));
+            if (!learned) QH_HIP(c, launch_diag_inv(c, c->A, w.dinv));
+            SolveResult r;
+            int rc2 = qh_cg_solve(c, c->A, w, P->val_tol, P->val_max_it, 16, r, nullptr, false, learned);
+            if (rc2) return rc2;
+            tot += r.converged ? r.iters : 10 * P->val_max_it;
+        }
+        *iters = tot;
+        return QH_OK;
+    };
+    hipEvent_t e0, e1;
+    QH_HIP(c, hipEventCreate(&e0));
+    QH_HIP(c, hipEventCreate(&e1));
+    QH_HIP(c, hipEventRecord(e0, c->stream));
+    qh_train_stats_t S;
+    std::memset(&S, 0, sizeof(S));
+    QH_HIP(c, launch_diag_inv(c, c->A, w.dinv));
+    if (n_val > 0 && (rc = validate(false, &S.val_iters_jacobi))) return rc;
+    int best = 1 << 30;
+    if (n_val > 0) {
+        if ((rc = qh_learned_factor(c)) || (rc = validate(true, &best))) return rc;
+        QH_HIP(c, hipMemcpyAsync(L.best_w, L.w, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
+    }
+    S.best_step = 0;
+    for (int32_t step = 1; step <= P->steps; ++step) {
+        if ((rc = qh_learned_probes(c, L.V, P->seed * 1000003ull + (uint64_t)(L.adam_t + 1)))) return rc;
+        if ((rc = qh_learned_loss_grad(c, L.V, true))) return rc;
+        if (step == 1) {
+            QH_HIP(c, hipMemcpyAsync(&S.loss_first, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
+        L.adam_t += 1;
+        if ((rc = qh_learned_adam(c, P->lr, L.adam_t))) return rc;
+        S.steps_done = step;
+        if (n_val > 0 && P->validate_every > 0 && (step % P->validate_every == 0 || step == P->steps)) {
+            int it = 0;
+            if ((rc = qh_learned_factor(c)) || (rc = validate(true, &it))) return rc;
+            if (it < best) {
+                best = it;
+                S.best_step = step;
+                QH_HIP(c, hipMemcpyAsync(L.best_w, L.w, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
+            }
+        }
+    }
+    QH_HIP(c, hipMemcpyAsync(&S.loss_last, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (n_val > 0) QH_HIP(c, hipMemcpyAsync(L.w, L.best_w, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
+    QH_HIP(c, hipEventRecord(e1, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    (void)hipEventElapsedTime(&S.ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    S.val_iters_best = n_val > 0 ? best : 0;
+    L.factor_valid = false;
+    (void)sol;
+    if (st) *st = S;
+    return QH_OK;
 }
 
 int qh_matrix_info(const qh_ctx *c, int32_t which, int64_t *nrow, int64_t *ncol, int64_t *nnz) {

@@ -87,6 +87,25 @@ struct CgWork {
     int32_t *flags = nullptr;   // [0] done, [1] iterations
 };
 
+// Learned preconditioner state (qh_learned.hip)
+struct LearnedPrec {
+    bool built = false, have_weights = false, factor_valid = false;
+    double tau = -1.0;
+    int32_t n = 0;
+    int64_t nnz = 0;                         // entries of G (lower triangle of A's pattern)
+    std::vector<int32_t> h_row, h_col;
+    int32_t *gptr = nullptr, *gcol = nullptr, *grow = nullptr;   // G, row-major
+    int32_t *tptr = nullptr, *tcol = nullptr, *tsrc = nullptr;   // G^T rows; tsrc: entry of G
+    unsigned short *feats = nullptr;         // nnz x 16 BF16 features
+    float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
+    float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;
+    double *y = nullptr;
+    float *w = nullptr, *best_w = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    float *gpart = nullptr, *W = nullptr, *AW = nullptr, *V = nullptr;
+    double *tpart = nullptr, *lpart = nullptr, *loss = nullptr;
+    int32_t adam_t = 0;
+};
+
 struct qh_ctx {
     int device = 0;
     bool host_only = false;  // device < 0: host mesh and assembly only (no GPU calls)
@@ -146,6 +165,8 @@ struct qh_ctx {
     unsigned long long *seg_count = nullptr;
     int32_t *seg_buf = nullptr;  // cap * 12 ints: pid species seq tet lam0[4] lam1[4]
 
+    LearnedPrec lp;
+    int last_fallbacks = 0;
     int64_t step_index = 0;
     bool fields_dirty = true;
     std::vector<void *> allocations;
@@ -162,7 +183,7 @@ struct qh_ctx {
 // kernel ids of the timing table
 enum {
     QK_FIELD_PREP = 0, QK_PARTICLE, QK_SORT, QK_EDGE_RHS, QK_CG_SPMV, QK_CG_UPDATE, QK_CG_INIT,
-    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NODE_SPMV, QK_NODE_UPDATE, QK_NKERNELS
+    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NODE_SPMV, QK_NODE_UPDATE, QK_PREC, QK_NKERNELS
 };
 int qh_tbeg(qh_ctx *c);
 void qh_tend(qh_ctx *c, int slot, int kernel);
@@ -211,7 +232,16 @@ struct SolveResult {
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
 // Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
-                SolveResult &out, const double *abs_thr2_dev, bool node_system = false);
+                SolveResult &out, const double *abs_thr2_dev, bool node_system = false, bool learned = false);
+
+// qh_learned.hip
+int qh_learned_setup(qh_ctx *c);
+int qh_learned_factor(qh_ctx *c);
+unsigned qh_prec_grid(int32_t n);
+hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part);
+int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad);
+int qh_learned_adam(qh_ctx *c, float lr, int32_t t);
+int qh_learned_probes(qh_ctx *c, float *V_dev, uint64_t seed);
 hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);
 hipError_t launch_assemble_A(qh_ctx *c, double tau);
 hipError_t launch_edge_rhs(qh_ctx *c);

@@ -1,0 +1,681 @@
+// Learned preconditioner for the edge system on gfx950.
+//
+// M = G^T G, G sparse lower triangular on the pattern of A = [*eps] + dt^2/4 S (interior
+// edges). A network 16 -> 64 -> 64 -> 1 (ReLU) maps local features of each pattern entry
+// (i, j), j <= i, to o_ij; G_ij = o_ij / sqrt(A_jj) (j < i), G_ii = softplus(o_ii + s0) /
+// sqrt(A_ii) with softplus(s0) = 1, so a zero output gives Jacobi and M is SPD by
+// construction (plain PCG applies). Training minimises the Kaporin number of G A G^T,
+// L = log(tr(G A G^T)/n) - (2/n) sum log G_ii, trace from Rademacher probes.
+//
+// The dense layers run on MFMA (v_mfma_f32_16x16x16_bf16, BF16 operands, FP32 accumulate)
+// with activations kept feature-major: the 16x16 accumulator tile of one layer (lane l holds
+// rows 4(l/16)+j of column l%16) is exactly the B-operand layout of the next layer, so
+// layers chain in registers. Weight gradients contract over entries and go through a small
+// LDS transpose per tile.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+#include "qh_internal.h"
+
+namespace {
+
+constexpr int kF = 16, kH = 64;
+constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248, kOffB3 = 5312;
+constexpr float kS0 = 0.54132485461291810f;  // log(e - 1): softplus(kS0) = 1
+constexpr int kWaves = 4;                    // waves per block in the MLP kernels
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f2bf(float f) {  // round to nearest even
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
+
+// Weight fragments of one wave. Layer 1: H1^T = W1 X^T (A = W1 rows 16mb.., k = features);
+// layer 2: H2^T = W2 H1^T (A = W2 block (mb, kb)); backward: dH1^T = W2^T dZ2^T.
+struct Frags {
+    bf16x4 w1[4];
+    bf16x4 w2[4][4];
+    float b1[4][4], b2[4][4], w3[4][4];
+    float b3;
+};
+
+__device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F, bool transposed_w2) {
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F.w1[mb][j] = f2bf(w[kOffW1 + (16 * mb + r) * kF + 4 * g + j]);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                F.w2[mb][kb][j] = transposed_w2 ? f2bf(w[kOffW2 + (16 * kb + 4 * g + j) * kH + 16 * mb + r])
+                                                : f2bf(w[kOffW2 + (16 * mb + r) * kH + 16 * kb + 4 * g + j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            F.b1[mb][j] = w[kOffB1 + 16 * mb + 4 * g + j];
+            F.b2[mb][j] = w[kOffB2 + 16 * mb + 4 * g + j];
+            F.w3[mb][j] = w[kOffW3 + 16 * mb + 4 * g + j];
+        }
+    }
+    F.b3 = w[kOffB3];
+}
+
+// Forward pass of one 16-entry tile (entries e0 + l%16). Returns o for entry e0 + l%16 in
+// every lane; z1, z2 (pre-activations, feature-major) are kept for the backward pass.
+__device__ __forceinline__ float tile_forward(const Frags &F, const unsigned short *__restrict__ feats,
+                                              int64_t e0, int64_t nnz, f32x4 (&z1)[4], f32x4 (&z2)[4],
+                                              bf16x4 (&h1b)[4]) {
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+    const int64_t e = e0 + r;
+    bf16x4 x;
+    if (e < nnz) {
+        const uint2 raw = *(const uint2 *)(feats + e * kF + 4 * g);
+        x[0] = (short)(raw.x & 0xffff); x[1] = (short)(raw.x >> 16);
+        x[2] = (short)(raw.y & 0xffff); x[3] = (short)(raw.y >> 16);
+    } else {
+        x[0] = x[1] = x[2] = x[3] = 0;
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma(F.w1[mb], x, c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            z1[mb][j] = c[j] + F.b1[mb][j];
+            h1b[mb][j] = f2bf(fmaxf(z1[mb][j], 0.f));
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) c = mfma(F.w2[mb][kb], h1b[kb], c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            z2[mb][j] = c[j] + F.b2[mb][j];
+            s += fmaxf(z2[mb][j], 0.f) * F.w3[mb][j];
+        }
+    }
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    return s + F.b3;
+}
+
+// G value of entry e from the network output
+__device__ __forceinline__ float g_of(float o, bool diag, float scale) {
+    return diag ? softplus_f(o + kS0) * scale : o * scale;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Inference: G values for all pattern entries (and G^T values through the permutation).
+__global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restrict__ w,
+                                                            const unsigned short *__restrict__ feats,
+                                                            const int32_t *__restrict__ grow,
+                                                            const int32_t *__restrict__ gcol,
+                                                            const float *__restrict__ gscale, int64_t nnz,
+                                                            float *__restrict__ o_out, float *__restrict__ gval) {
+    Frags F;
+    load_frags(w, F, false);
+    const int l = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
+        f32x4 z1[4], z2[4];
+        bf16x4 h1b[4];
+        float o = tile_forward(F, feats, e0, nnz, z1, z2, h1b);
+        const int64_t e = e0 + l;
+        if (l < 16 && e < nnz) {
+            if (o_out) o_out[e] = o;
+            gval[e] = g_of(o, grow[e] == gcol[e], gscale[e]);
+        }
+    }
+}
+
+__global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const float *__restrict__ in,
+                             float *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = in[src[k]];
+}
+
+// ---------------------------------------------------------------------------------------
+// Preconditioner application: y = G r (rows of G), then z = G^T y (rows of G^T) with the
+// partials of r.z. Each block takes a contiguous row range; XCD-aware block order (blocks are
+// dealt to the 8 XCDs round-robin) keeps neighbouring rows, which gather the same vector
+// entries, in one L2. Grids are multiples of 8 blocks, at most 2048.
+template <bool DOT>
+__global__ void __launch_bounds__(256) k_prec_g(int32_t n, const int32_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                const double *__restrict__ in, double *__restrict__ out,
+                                                const double *__restrict__ r, double *__restrict__ part) {
+    const int sub = threadIdx.x & 7;
+    const unsigned nb = gridDim.x, per_x = nb / 8;
+    const unsigned lb = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
+    const int64_t per = (n + nb - 1) / nb;
+    const int64_t rb = (int64_t)lb * per, re = rb + per < n ? rb + per : n;
+    double acc = 0.0;
+    for (int64_t row = rb + (threadIdx.x >> 3); row < re; row += 32) {
+        double s = 0.0;
+        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += 8) s += (double)val[j] * in[col[j]];
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+        if (sub == 0) {
+            out[row] = s;
+            if (DOT) acc += s * r[row];
+        }
+    }
+    if (DOT) {
+        __shared__ double sh[4];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Kaporin loss pieces. Probes V and products W = G^T V, AW = A W are stored node-major
+// [n][P] in FP32; sums are FP64.
+constexpr int kP = 16;  // probes per training step
+
+__global__ void k_probes(int32_t n, uint64_t seed, float *__restrict__ V) {
+    // Rademacher signs from a counter-based hash of (seed, row, probe) (splitmix64 finaliser)
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)n * kP) return;
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(k + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    V[k] = (z >> 63) ? 1.f : -1.f;
+}
+
+// out[row][p] = sum_k M_row,k in[k][p]; one lane per probe, 16 rows per block and pass. With
+// DOT, also per-block partials of sum_row other[row][p] * out[row][p] (for the trace).
+template <typename VT, bool DOT>
+__global__ void __launch_bounds__(256) k_spmm16(int32_t n, const int32_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                const float *__restrict__ in, float *__restrict__ out,
+                                                const float *__restrict__ other, double *__restrict__ part) {
+    const int p = threadIdx.x & 15;
+    double d = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); row < n; row += (int64_t)gridDim.x * 16) {
+        double s = 0.0;
+        for (int32_t j = ptr[row]; j < ptr[row + 1]; ++j) s += (double)val[j] * (double)in[(int64_t)col[j] * kP + p];
+        out[row * kP + p] = (float)s;
+        if (DOT) d += s * (double)other[row * kP + p];
+    }
+    if (DOT) {
+        __shared__ double sh[256];
+        sh[threadIdx.x] = d;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            double t = 0.0;
+            for (int k = 0; k < 16; ++k) t += sh[16 * k + threadIdx.x];
+            part[(int64_t)blockIdx.x * kP + threadIdx.x] = t;
+        }
+    }
+}
+
+// T = sum of the trace partials / (P n) into loss[1]
+__global__ void __launch_bounds__(256) k_trace_finish(const double *__restrict__ part, int32_t m, int32_t n,
+                                                      double *loss) {
+    __shared__ double sh[256];
+    double t = 0.0;
+    for (int32_t k = threadIdx.x; k < m * kP; k += 256) t += part[k];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[1] = sh[0] / ((double)kP * (double)n);
+}
+
+// T = mean_p t_p / |v_p|^2 (|v_p|^2 = n); dG and d o per entry; partials of sum log G_ii.
+__global__ void __launch_bounds__(256) k_kaporin_grad(int64_t nnz, int32_t n, const int32_t *__restrict__ grow,
+                                                      const int32_t *__restrict__ gcol,
+                                                      const float *__restrict__ gscale, const float *__restrict__ o,
+                                                      const float *__restrict__ gval, const float *__restrict__ V,
+                                                      const float *__restrict__ AW, float *__restrict__ d_o,
+                                                      double *__restrict__ lpart, const double *__restrict__ loss) {
+    __shared__ double sh[256];
+    const double T = loss[1];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lg = 0.0;
+    if (e < nnz) {
+        const int32_t i = grow[e], j = gcol[e];
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < kP; ++p) s += (double)AW[(int64_t)j * kP + p] * (double)V[(int64_t)i * kP + p];
+        double dG = 2.0 / ((double)kP * T * (double)n) * s;
+        const bool diag = i == j;
+        float d;
+        if (diag) {
+            const double gi = gval[e];
+            dG -= 2.0 / ((double)n * gi);
+            lg = log(gi);
+            d = (float)(dG * sigmoid_f(o[e] + kS0) * gscale[e]);
+        } else {
+            d = (float)(dG * gscale[e]);
+        }
+        d_o[e] = d;
+    }
+    sh[threadIdx.x] = lg;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = sh[0];
+}
+
+__global__ void k_loss_finish(const double *__restrict__ lpart, int32_t m, int32_t n, double *loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int32_t b = 0; b < m; ++b) s += lpart[b];
+    loss[0] = log(loss[1]) - 2.0 / (double)n * s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Backward pass over all entries: per-wave partial gradients of sum_e d_o[e] o[e].
+// Layout of a wave's partial (kParams floats): same as the weights.
+__global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__restrict__ w,
+                                                              const unsigned short *__restrict__ feats,
+                                                              const float *__restrict__ d_o, int64_t nnz,
+                                                              float *__restrict__ gpart) {
+    __shared__ unsigned short tr[kWaves][2][64][17];  // per wave: dZ2^T / dZ1^T and H1^T tiles, [row][entry]
+    Frags F, FT;
+    load_frags(w, F, false);
+    load_frags(w, FT, true);
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+    const int wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * kWaves + wv;
+    f32x4 gW2[4][4], gW1[4];
+    float gb1[4][4], gb2[4][4], gw3[4][4], gb3 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            gW2[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            gb1[a][b] = gb2[a][b] = gw3[a][b] = 0.f;
+        }
+    }
+    // all waves of a block take the same number of trips (tiles past the end contribute zero),
+    // so the block barriers below are uniform
+    for (int64_t tb = blockIdx.x; tb * kWaves * 16 < nnz; tb += gridDim.x) {
+        const int64_t e0 = (tb * kWaves + wv) * 16;
+        f32x4 z1[4], z2[4];
+        bf16x4 h1b[4];
+        (void)tile_forward(F, feats, e0, nnz, z1, z2, h1b);
+        const int64_t e = e0 + r;
+        const float dout = e < nnz ? d_o[e] : 0.f;
+        // dZ2^T = w3 d_o (z2 > 0); db2, dw3, db3
+        bf16x4 dz2b[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float m = z2[mb][j] > 0.f ? 1.f : 0.f;
+                const float dz = F.w3[mb][j] * dout * m;
+                dz2b[mb][j] = f2bf(dz);
+                gb2[mb][j] += dz;
+                gw3[mb][j] += fmaxf(z2[mb][j], 0.f) * dout;
+            }
+        if (g == 0) gb3 += dout;
+        // dH1^T = W2^T dZ2^T (B operand chains from the accumulator layout)
+        bf16x4 dz1b[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) c = mfma(FT.w2[mb][kb], dz2b[kb], c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float dz = z1[mb][j] > 0.f ? c[j] : 0.f;
+                dz1b[mb][j] = f2bf(dz);
+                gb1[mb][j] += dz;
+            }
+        }
+        // stage dZ2^T and H1^T ([row][entry]) for the entry contraction
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz2b[mb][j];
+                tr[wv][1][16 * mb + 4 * g + j][r] = (unsigned short)h1b[mb][j];
+            }
+        __syncthreads();
+        // dW2[o][i] += sum_e dZ2^T[o][e] H1^T[i][e]: A = dZ2^T (o x e), B = H1 (e x i)
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            bf16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = (short)tr[wv][0][16 * ob + r][4 * g + j];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                bf16x4 b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = (short)tr[wv][1][16 * ib + r][4 * g + j];
+                gW2[ob][ib] = mfma(a, b, gW2[ob][ib]);
+            }
+        }
+        __syncthreads();
+        // dW1[o][f] += sum_e dZ1^T[o][e] X[e][f]: stage dZ1^T; B = X (e x f) from memory
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz1b[mb][j];
+        __syncthreads();
+        bf16x4 xb;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t ee = e0 + 4 * g + j;
+            xb[j] = ee < nnz ? (short)feats[ee * kF + r] : (short)0;
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            bf16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = (short)tr[wv][0][16 * ob + r][4 * g + j];
+            gW1[ob] = mfma(a, xb, gW1[ob]);
+        }
+        __syncthreads();
+    }
+    // wave partials: C tiles directly; vector terms summed over the 16 entry lanes
+    float *out = gpart + wave * 5313;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            out[kOffW1 + (16 * ob + 4 * g + j) * kF + r] = gW1[ob][j];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) out[kOffW2 + (16 * ob + 4 * g + j) * kH + 16 * ib + r] = gW2[ob][ib][j];
+        }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float a = gb1[mb][j], b = gb2[mb][j], c = gw3[mb][j];
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {
+                a += __shfl_xor(a, off, 16);
+                b += __shfl_xor(b, off, 16);
+                c += __shfl_xor(c, off, 16);
+            }
+            if (r == 0) {
+                out[kOffB1 + 16 * mb + 4 * g + j] = a;
+                out[kOffB2 + 16 * mb + 4 * g + j] = b;
+                out[kOffW3 + 16 * mb + 4 * g + j] = c;
+            }
+        }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) gb3 += __shfl_xor(gb3, off, 16);
+    if (l == 0) out[kOffB3] = gb3;
+}
+
+// Sum of the wave partials in a fixed order (one thread per parameter).
+__global__ void k_grad_reduce(const float *__restrict__ gpart, int64_t nwaves, float *__restrict__ grad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 5313) return;
+    double s = 0.0;
+    for (int64_t wv = 0; wv < nwaves; ++wv) s += gpart[wv * 5313 + k];
+    grad[k] = (float)s;
+}
+
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, float lr, float b1, float b2, float eps, int32_t t) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 5313) return;
+    const float gk = grad[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const float mh = mk / (1.f - powf(b1, (float)t));
+    const float vh = vk / (1.f - powf(b2, (float)t));
+    w[k] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side
+namespace {
+
+float host_bf16_round(double x) {
+    float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace
+
+int qh_learned_setup(qh_ctx *c) {
+    if (c->lp.built && c->lp.tau == c->tau_assembled) return QH_OK;
+    const HostMesh &m = c->hm;
+    const HostCsr &A = c->hA;
+    const double tau = c->tau_assembled;
+    const int32_t n = (int32_t)A.nrow;
+    LearnedPrec &L = c->lp;
+    int rc;
+    if (!L.built) {
+        // pattern of G (lower triangle of A, row-major, sorted) and of G^T
+        std::vector<int32_t> gptr(n + 1, 0), gcol, grow;
+        for (int32_t i = 0; i < n; ++i) {
+            for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                if (A.col[k] <= i) {
+                    gcol.push_back(A.col[k]);
+                    grow.push_back(i);
+                }
+            gptr[i + 1] = (int32_t)gcol.size();
+        }
+        const int64_t nnz = (int64_t)gcol.size();
+        std::vector<int32_t> tptr(n + 1, 0), tcol(nnz), tsrc(nnz);
+        for (int64_t e = 0; e < nnz; ++e) tptr[gcol[e] + 1]++;
+        for (int32_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+        std::vector<int32_t> cur(tptr.begin(), tptr.end() - 1);
+        for (int64_t e = 0; e < nnz; ++e) {
+            int32_t k = cur[gcol[e]]++;
+            tcol[k] = grow[e];
+            tsrc[k] = (int32_t)e;
+        }
+        L.n = n;
+        L.nnz = nnz;
+        L.h_row = grow;
+        L.h_col = gcol;
+        if ((rc = qh_alloc(c, &L.gptr, n + 1)) || (rc = qh_alloc(c, &L.gcol, nnz)) || (rc = qh_alloc(c, &L.grow, nnz)) ||
+            (rc = qh_alloc(c, &L.tptr, n + 1)) || (rc = qh_alloc(c, &L.tcol, nnz)) || (rc = qh_alloc(c, &L.tsrc, nnz)) ||
+            (rc = qh_alloc(c, &L.feats, nnz * kF)) || (rc = qh_alloc(c, &L.gscale, nnz)) ||
+            (rc = qh_alloc(c, &L.gval, nnz)) || (rc = qh_alloc(c, &L.tval, nnz)) || (rc = qh_alloc(c, &L.o, nnz)) ||
+            (rc = qh_alloc(c, &L.d_o, nnz)) || (rc = qh_alloc(c, &L.y, n)) || (rc = qh_alloc(c, &L.w, 5313)) ||
+            (rc = qh_alloc(c, &L.adam_m, 5313)) || (rc = qh_alloc(c, &L.adam_v, 5313)) ||
+            (rc = qh_alloc(c, &L.grad, 5313)) || (rc = qh_alloc(c, &L.loss, 4)))
+            return rc;
+        QH_HIP(c, hipMemcpyAsync(L.gptr, gptr.data(), 4 * (n + 1), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.gcol, gcol.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.grow, grow.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.tptr, tptr.data(), 4 * (n + 1), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.tcol, tcol.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.tsrc, tsrc.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        if (!L.have_weights) {
+            // He-normal hidden layers, zero output layer: the initial network is Jacobi
+            std::mt19937_64 gen(12345);
+            std::normal_distribution<double> n1(0.0, std::sqrt(2.0 / kF)), n2(0.0, std::sqrt(2.0 / kH));
+            std::vector<float> w(5313, 0.f);
+            for (int k = 0; k < kH * kF; ++k) w[kOffW1 + k] = (float)n1(gen);
+            for (int k = 0; k < kH * kH; ++k) w[kOffW2 + k] = (float)n2(gen);
+            QH_HIP(c, hipMemcpyAsync(L.w, w.data(), 4 * 5313, hipMemcpyHostToDevice, c->stream));
+            L.have_weights = true;
+        }
+        L.built = true;
+    }
+    // features and scales depend on dt
+    const int64_t nnz = L.nnz;
+    std::vector<double> dA(n), dM(n), dS(n), off(n, 0.0), rl(n);
+    for (int32_t i = 0; i < n; ++i) {
+        rl[i] = A.ptr[i + 1] - A.ptr[i];
+        double s = 0.0;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const double a = A.val[k] + tau * A.val2[k];
+            s += std::fabs(a);
+            if (A.col[k] == i) {
+                dA[i] = a;
+                dM[i] = A.val[k];
+                dS[i] = tau * A.val2[k];
+            }
+        }
+        off[i] = s / dA[i] - 1.0;
+    }
+    std::vector<double> tv(3 * (int64_t)n), ell(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t e = m.int_edges[i];
+        const double *pa = &m.xyz[3 * (int64_t)m.edges[2 * e]], *pb = &m.xyz[3 * (int64_t)m.edges[2 * e + 1]];
+        for (int d = 0; d < 3; ++d) tv[3 * i + d] = pb[d] - pa[d];
+        ell[i] = std::sqrt(tv[3 * i] * tv[3 * i] + tv[3 * i + 1] * tv[3 * i + 1] + tv[3 * i + 2] * tv[3 * i + 2]);
+    }
+    std::vector<uint16_t> fh(nnz * kF);
+    std::vector<float> sc(nnz);
+    int64_t e = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            if (j > i) continue;
+            const double a = A.val[k] + tau * A.val2[k], mm = A.val[k], ss = tau * A.val2[k];
+            double f[kF];
+            const double cosang = (tv[3 * i] * tv[3 * j] + tv[3 * i + 1] * tv[3 * j + 1] + tv[3 * i + 2] * tv[3 * j + 2]) /
+                                  (ell[i] * ell[j]);
+            f[0] = i == j ? 1.0 : 0.0;
+            f[1] = a / std::sqrt(dA[i] * dA[j]);
+            f[2] = mm / std::sqrt(dM[i] * dM[j]);
+            f[3] = ss / std::sqrt(dA[i] * dA[j]);
+            f[4] = dS[i] / dA[i];
+            f[5] = dS[j] / dA[j];
+            f[6] = cosang;
+            f[7] = std::log(ell[j] / ell[i]);
+            f[8] = rl[i] / 20.0;
+            f[9] = rl[j] / 20.0;
+            f[10] = off[i];
+            f[11] = off[j];
+            f[12] = std::fabs(f[1]);
+            f[13] = f[1] * f[1];
+            f[14] = f[4] * f[5];
+            f[15] = 1.0;
+            for (int q = 0; q < kF; ++q) {
+                float bf = host_bf16_round(f[q]);
+                uint32_t u;
+                std::memcpy(&u, &bf, 4);
+                fh[e * kF + q] = (uint16_t)(u >> 16);
+            }
+            sc[e] = (float)(1.0 / std::sqrt(i == j ? dA[i] : dA[j]));
+            ++e;
+        }
+    QH_HIP(c, hipMemcpyAsync(L.feats, fh.data(), 2 * nnz * kF, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemcpyAsync(L.gscale, sc.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    L.tau = c->tau_assembled;
+    L.factor_valid = false;
+    return QH_OK;
+}
+
+static unsigned mlp_grid(int64_t nnz) {
+    int64_t tiles = (nnz + 15) / 16;
+    int64_t blocks = (tiles + kWaves - 1) / kWaves;
+    return (unsigned)std::min<int64_t>(blocks, 2048);
+}
+
+int qh_learned_factor(qh_ctx *c) {
+    LearnedPrec &L = c->lp;
+    hipLaunchKernelGGL(k_mlp_factor, dim3(mlp_grid(L.nnz)), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.grow,
+                       L.gcol, L.gscale, L.nnz, L.o, L.gval);
+    hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((L.nnz + 255) / 256)), dim3(256), 0, c->stream, L.nnz, L.tsrc,
+                       L.gval, L.tval);
+    QH_HIP(c, hipGetLastError());
+    L.factor_valid = true;
+    return QH_OK;
+}
+
+unsigned qh_prec_grid(int32_t n) {
+    int64_t b = ((int64_t)n * 8 + 255) / 256;
+    b = b < 2048 ? (b < 1 ? 1 : b) : 2048;
+    return (unsigned)((b + 7) / 8 * 8);
+}
+
+// z = G^T (G r); part[block] = partial r.z (grid qh_prec_grid(n))
+hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part) {
+    LearnedPrec &L = c->lp;
+    const unsigned gb = qh_prec_grid(L.n);
+    hipLaunchKernelGGL(k_prec_g<false>, dim3(gb), dim3(256), 0, c->stream, L.n, L.gptr, L.gcol, L.gval, r, L.y,
+                       (const double *)nullptr, (double *)nullptr);
+    hipLaunchKernelGGL(k_prec_g<true>, dim3(gb), dim3(256), 0, c->stream, L.n, L.tptr, L.tcol, L.tval, L.y, z, r, part);
+    return hipGetLastError();
+}
+
+// Loss and gradient for the current weights with probes V (device, [n][16] floats).
+int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad) {
+    LearnedPrec &L = c->lp;
+    int rc;
+    if ((rc = qh_learned_factor(c))) return rc;
+    const int32_t n = L.n;
+    if (!L.W) {
+        if ((rc = qh_alloc(c, &L.W, (int64_t)n * kP)) || (rc = qh_alloc(c, &L.AW, (int64_t)n * kP)) ||
+            (rc = qh_alloc(c, &L.tpart, 2048 * kP)) ||
+            (rc = qh_alloc(c, &L.lpart, (L.nnz + 255) / 256)) ||
+            (rc = qh_alloc(c, &L.gpart, (int64_t)mlp_grid(L.nnz) * kWaves * 5313)))
+            return rc;
+    }
+    const unsigned gr = (unsigned)std::min<int64_t>((n + 15) / 16, 2048);
+    // W = G^T V, AW = A W (+ partial traces)
+    hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.tptr, L.tcol, L.tval, V_dev, L.W,
+                       (const float *)nullptr, (double *)nullptr);
+    hipLaunchKernelGGL((k_spmm16<double, true>), dim3(gr), dim3(256), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val,
+                       L.W, L.AW, L.W, L.tpart);
+    hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(256), 0, c->stream, L.tpart, (int32_t)gr, n, L.loss);
+    const unsigned ge = (unsigned)((L.nnz + 255) / 256);
+    hipLaunchKernelGGL(k_kaporin_grad, dim3(ge), dim3(256), 0, c->stream, L.nnz, n, L.grow, L.gcol, L.gscale, L.o,
+                       L.gval, V_dev, L.AW, L.d_o, L.lpart, L.loss);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, c->stream, L.lpart, (int32_t)ge, n, L.loss);
+    if (want_grad) {
+        const unsigned gm = mlp_grid(L.nnz);
+        hipLaunchKernelGGL(k_mlp_backward, dim3(gm), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.d_o, L.nnz, L.gpart);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((5313 + 255) / 256), dim3(256), 0, c->stream, L.gpart,
+                           (int64_t)gm * kWaves, L.grad);
+    }
+    QH_HIP(c, hipGetLastError());
+    return QH_OK;
+}
+
+int qh_learned_adam(qh_ctx *c, float lr, int32_t t) {
+    LearnedPrec &L = c->lp;
+    hipLaunchKernelGGL(k_adam, dim3((5313 + 255) / 256), dim3(256), 0, c->stream, L.w, L.adam_m, L.adam_v, L.grad, lr,
+                       0.9f, 0.999f, 1e-8f, t);
+    QH_HIP(c, hipGetLastError());
+    L.factor_valid = false;
+    return QH_OK;
+}
+
+int qh_learned_probes(qh_ctx *c, float *V_dev, uint64_t seed) {
+    const int64_t tot = (int64_t)c->lp.n * kP;
+    hipLaunchKernelGGL(k_probes, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, c->lp.n, seed, V_dev);
+    QH_HIP(c, hipGetLastError());
+    return QH_OK;
+}

@@ -125,10 +125,11 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *
 }
 
 // one block: totals of the init partials; threshold; convergence flag
-__global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict__ part, int m, double *scal,
+__global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict__ part, int m,
+                                                       const double *__restrict__ rz_part, int m_rz, double *scal,
                                                        int32_t *flags, double tol2, const double *abs_thr2) {
     __shared__ double sh[kThreads / 64];
-    double rz = sum_partials(part, m, sh);
+    double rz = sum_partials(rz_part, m_rz, sh);
     double rr = sum_partials(part + kMaxBlocks, m, sh);
     double bb = sum_partials(part + 2 * kMaxBlocks, m, sh);
     if (threadIdx.x == 0) {
@@ -151,14 +152,16 @@ __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ z,
                                                       double *__restrict__ p, double *__restrict__ q,
-                                                      const double *__restrict__ upart, double *__restrict__ part,
-                                                      int m, double *scal, int32_t *flags, int32_t k, int32_t par) {
+                                                      const double *__restrict__ rz_part, int m_rz,
+                                                      const double *__restrict__ rr_part, int m_rr,
+                                                      double *__restrict__ part, double *scal, int32_t *flags,
+                                                      int32_t k, int32_t par) {
     if (flags[0]) return;
     __shared__ double sh[kThreads / 64];
     double beta = 0.0;
     if (k > 0) {
-        double rz_new = sum_partials(upart, m, sh);
-        double rr = sum_partials(upart + kMaxBlocks, m, sh);
+        double rz_new = sum_partials(rz_part, m_rz, sh);
+        double rr = sum_partials(rr_part, m_rr, sh);
         bool done = rr <= scal[S_THR2] || !(rr == rr);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             scal[S_RZ + (par ^ 1)] = rz_new;
@@ -189,7 +192,9 @@ __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *
     write_partials<1>(acc, part);
 }
 
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials of r.z, r.r
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; with Jacobi also z = D^-1 r; partials of
+// r.z (Jacobi) and r.r
+template <bool JAC>
 __global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__restrict__ x,
                                                         double *__restrict__ r, double *__restrict__ z,
                                                         const double *__restrict__ p,
@@ -205,9 +210,11 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__res
         x[i] += alpha * p[i];
         double ri = r[i] - alpha * q[i];
         r[i] = ri;
-        double zi = ri * dinv[i];
-        z[i] = zi;
-        acc[0] += ri * zi;
+        if (JAC) {
+            double zi = ri * dinv[i];
+            z[i] = zi;
+            acc[0] += ri * zi;
+        }
         acc[1] += ri * ri;
     }
     write_partials<2>(acc, part);
@@ -407,7 +414,7 @@ hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv) {
 }
 
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
-                SolveResult &out, const double *abs_thr2_dev, bool node_system) {
+                SolveResult &out, const double *abs_thr2_dev, bool node_system, bool learned) {
     const int k_spmv = node_system ? QK_NODE_SPMV : QK_CG_SPMV;
     const int k_upd = node_system ? QK_NODE_UPDATE : QK_CG_UPDATE;
     out = SolveResult();
@@ -415,20 +422,23 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
         out.converged = true;
         return QH_OK;
     }
-    // partial arrays: [0, 4K) init / update, [4K, 8K) products
-    double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks;
+    // partials: [0, 4K) init / update (slot 0 r.z with Jacobi, 1 r.r, 2 b.b), [4K, 5K) products,
+    // [5K, 6K) r.z of the learned preconditioner
+    double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks, *ppart = w.partial + 5 * kMaxBlocks;
     const unsigned gr = grid_rows(w.n), ge = grid_elems(w.n);
+    const unsigned gp = learned ? qh_prec_grid(w.n) : 0;
     int t0 = qh_tbeg(c);
     hipLaunchKernelGGL(k_cg_init, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, w.dinv,
                        w.r, w.z, w.p0, upart);
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr, w.scal, w.flags, tol * tol,
-                       abs_thr2_dev);
+    if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart));
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr,
+                       learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gr, w.scal,
+                       w.flags, tol * tol, abs_thr2_dev);
     qh_tend(c, t0, QK_CG_INIT);
     QH_HIP(c, hipGetLastError());
     if (check_every <= 0) check_every = 8;
     int32_t hflags[2] = {0, 0};
     int it = 0;
-    // the update partials come from the update kernel's grid (ge blocks), the init's from gr
     int m_up = (int)gr;
     QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
@@ -438,13 +448,23 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
             int par = k & 1;
             int ta = qh_tbeg(c);
             hipLaunchKernelGGL(k_cg_spmv, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.z, w.p0,
-                               w.q, upart, qpart, m_up, w.scal, w.flags, k, par);
+                               w.q, learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : m_up,
+                               upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par);
             qh_tend(c, ta, k_spmv);
             int tb = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0, w.q,
-                               w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
+            if (learned)
+                hipLaunchKernelGGL(k_cg_update<false>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
+                                   w.q, w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
+            else
+                hipLaunchKernelGGL(k_cg_update<true>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
+                                   w.q, w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
             qh_tend(c, tb, k_upd);
             m_up = (int)ge;
+            if (learned) {
+                int tp = qh_tbeg(c);
+                QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart));
+                qh_tend(c, tp, QK_PREC);
+            }
         }
         it += batch;
         hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags, it);
@@ -462,7 +482,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     QH_HIP(c, hipMemcpyAsync(res2, w.scal + 8, sizeof(res2), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
     out.res = res2[1] > 0 ? sqrt(res2[0] / res2[1]) : 0.0;
-    out.converged = hflags[0] != 0;
+    out.converged = hflags[0] != 0 && out.res == out.res;
     return QH_OK;
 }
 
