@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
+    ap.add_argument("--train-steps", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -151,37 +153,66 @@ def main():
     params = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE if solve else qh.FIELDS_FROZEN,
                                     sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
                                     max_it_edge=2000, max_it_node=5000, check_every=16)
+    def timed(prm, steps):
+        t0 = time.perf_counter()
+        ctx.pic_step(prm, steps, want_stats=False)   # returns after its stream is synchronised
+        return time.perf_counter() - t0
+
+    def profile(prm, steps):
+        ctx.timing(True)
+        pst = ctx.pic_step(prm, steps, want_stats=True)
+        kt = ctx.timing_read()
+        ctx.timing(False)
+        kern = {}
+        for k, (ms, cnt) in kt.items():
+            if cnt:
+                kern[k] = {"ms_total": round(ms, 4), "launches": cnt, "us_per_launch": round(1e3 * ms / cnt, 3)}
+        return pst, kern
+
+    # plain solver (Jacobi-preconditioned CG)
     st = ctx.pic_step(params, args.warmup, want_stats=True)
     log(f"[bench] warmup done: last step {st[-1]}")
-    t0 = time.perf_counter()
-    ctx.pic_step(params, args.steps, want_stats=False)   # returns after its stream is synchronised
-    wall = time.perf_counter() - t0
+    wall_j = timed(params, args.steps)
+    pst_j, kern_j = profile(params, args.profile_steps)
+    log(f"[bench] jacobi: {1e3 * wall_j / args.steps:.3f} ms/step, edge iters {[s['edge_iters'] for s in pst_j]}")
+    wall, pst, kernels, used = wall_j, pst_j, kern_j, "jacobi"
+    learned = None
+    if solve and args.precond == "learned":
+        # (rhs, solution) pairs from the plain solver validate the network during training
+        pairs = []
+        for _ in range(2):
+            ctx.pic_step(params, 1, want_stats=False)
+            pairs.append(ctx.edge_system_download())
+        rhs = np.stack([p[0] for p in pairs])
+        sol = np.stack([p[1] for p in pairs])
+        tst = ctx.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol)
+        log(f"[bench] training: {tst}")
+        params_l = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED,
+                                          sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
+                                          max_it_edge=2000, max_it_node=5000, check_every=16)
+        ctx.pic_step(params_l, 2, want_stats=False)
+        wall_l = timed(params_l, args.steps)
+        pst_l, kern_l = profile(params_l, args.profile_steps)
+        log(f"[bench] learned: {1e3 * wall_l / args.steps:.3f} ms/step, edge iters {[s['edge_iters'] for s in pst_l]}")
+        learned = {"train": tst, "pst": pst_l, "kernels": kern_l, "wall": wall_l}
+        wall, pst, kernels, used = wall_l, pst_l, kern_l, "learned"
     ms_step = 1e3 * wall / args.steps
     value = n_p * args.steps / wall
-    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} particle-steps/s")
-
-    # profiling pass: per-step stats and per-kernel HIP-event times
-    ctx.timing(True)
-    pst = ctx.pic_step(params, args.profile_steps, want_stats=True)
-    kt = ctx.timing_read()
-    ctx.timing(False)
     crossings = float(np.mean([s["crossings"] for s in pst]))
-    kernels = {}
-    for k, (ms, cnt) in kt.items():
-        if cnt:
-            kernels[k] = {"ms_total": round(ms, 4), "launches": cnt, "us_per_launch": round(1e3 * ms / cnt, 3)}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
-    def roof(k):
+
+    def roof(k, kern):
         by = algorithmic_bytes(k, mi, n_p, crossings)
-        if by is None:
+        if by is None or k not in kern:
             return None
-        avg_s = kernels[k]["ms_total"] / kernels[k]["launches"] * 1e-3
+        avg_s = kern[k]["ms_total"] / kern[k]["launches"] * 1e-3
         ach = by / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k,
-                "algorithmic_bytes_per_launch": int(by), "us_per_launch": kernels[k]["us_per_launch"]}
+                "algorithmic_bytes_per_launch": int(by), "us_per_launch": kern[k]["us_per_launch"]}
     ms_part = float(np.mean([s["ms_particles"] for s in pst]))
-    ms_field = float(np.mean([s["ms_fields"] for s in pst]))
+    fs_j = float(np.mean([s["ms_fields"] for s in pst_j]))
+    fs_l = float(np.mean([s["ms_fields"] for s in learned["pst"]])) if learned else None
     out = {
         "metric": "particle-steps/s (gather+push+deposit), % HBM roofline; field-solve ms/step learned vs Jacobi",
         "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -189,18 +220,24 @@ def main():
         "vs_baseline": None, "dtype": "f32 push / int64 deposit / f64 solve", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "particles": n_p,
                    "tets": mi.n_tets, "edges": mi.n_edges, "nnz_edge": mi.nnz_edge, "dt": cfg["dt"],
-                   "sort_every": cfg.get("sort_every", 0), "tol": 1e-8},
-        "roofline": roof(dom),
+                   "sort_every": cfg.get("sort_every", 0), "tol": 1e-8, "precond": used},
+        "roofline": roof(dom, kernels),
         "particle_phase": {"ms_per_step": round(ms_part, 4),
                            "particle_steps_per_s": round(n_p / (ms_part * 1e-3), 1),
-                           "roofline": roof("particle_step")},
-        "field_solve_ms_per_step": {"jacobi": round(ms_field, 4), "learned": None},
+                           "roofline": roof("particle_step", kernels)},
+        "field_solve_ms_per_step": {"jacobi": round(fs_j, 4), "learned": round(fs_l, 4) if fs_l else None},
+        "jacobi_cycle": {"ms_per_step": round(1e3 * wall_j / args.steps, 4),
+                         "particle_steps_per_s": round(n_p * args.steps / wall_j, 1),
+                         "edge_iters": [s["edge_iters"] for s in pst_j], "kernels": kern_j},
         "solver": {"edge_iters": [s["edge_iters"] for s in pst], "node_iters": [s["node_iters"] for s in pst],
-                   "edge_res": max(s["edge_res"] for s in pst), "gauss_res": max(s["gauss_res"] for s in pst)},
+                   "edge_res": max(s["edge_res"] for s in pst), "gauss_res": max(s["gauss_res"] for s in pst),
+                   "fallbacks": sum(s["fallbacks"] for s in pst)},
         "kernels": kernels,
         "crossings_per_step": crossings,
         "foreign_deposits_per_step": float(np.mean([s["foreign"] for s in pst])),
     }
+    if learned:
+        out["learned_training"] = learned["train"]
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         try:

@@ -164,6 +164,10 @@ int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
 /* Deposits of the last step: g (Ne) path-integrated current, Q (Nn) node charge,
  * both int64 in units of u_q. Either may be NULL. */
 int qh_deposits_download(const qh_ctx *ctx, int64_t *g, int64_t *Q);
+/* Right-hand side of the last step's edge system (n_int_edges) and its solution e* as solved
+ * to tol_edge, before the Gauss-law correction. Either may be NULL. These are the (rhs,
+ * solution) pairs of the plain solver used to validate the learned preconditioner. */
+int qh_edge_system_download(const qh_ctx *ctx, double *rhs, double *sol);
 /* Record every straight piece of the next qh_pic_step (first step only) into a device
  * buffer of capacity cap (0 = off); read back with qh_segments_download. */
 int qh_capture_segments(qh_ctx *ctx, int64_t cap);

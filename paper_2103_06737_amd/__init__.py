@@ -31,7 +31,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
            "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
-           "qh_precond_train"]
+           "qh_precond_train", "qh_edge_system_download"]
 
 
 class QhError(RuntimeError):
@@ -123,6 +123,7 @@ def lib():
             "qh_matrix_download": [p, i32, p, p, p],
             "qh_timing_enable": [p, i32],
             "qh_timing_read": [p, i32, p, p],
+            "qh_edge_system_download": [p, p, p],
             "qh_precond_set_weights": [p, p, i64],
             "qh_precond_get_weights": [p, p, i64],
             "qh_precond_factor": [p, C.POINTER(i64), p, p, p],
@@ -274,6 +275,13 @@ class Context:
                                 C.cast(stats, C.c_void_p) if stats is not None else None)
         self._check(rc, allow)
         return [s.as_dict() for s in stats] if stats is not None else None
+
+    def edge_system_download(self):
+        n = self.info.n_int_edges
+        rhs = np.zeros(n)
+        sol = np.zeros(n)
+        self._check(self.L.qh_edge_system_download(self.h, _ptr(rhs), _ptr(sol)))
+        return rhs, sol
 
     def deposits_download(self):
         g = np.zeros(self.info.n_edges, np.int64)

@@ -93,6 +93,7 @@ int ensure_assembled(qh_ctx *c) {
         if ((rc = qh_cg_alloc(c, c->cge, c->A.n))) return rc;
         if ((rc = qh_cg_alloc(c, c->cgn, c->K.n))) return rc;
         if ((rc = qh_alloc(c, &c->e_old, std::max<int64_t>(1, c->A.n)))) return rc;
+        if ((rc = qh_alloc(c, &c->e_star, std::max<int64_t>(1, c->A.n)))) return rc;
         if ((rc = qh_alloc(c, &c->rho, std::max<int64_t>(1, c->K.n)))) return rc;
         QH_HIP(c, launch_diag_inv(c, c->K, c->cgn.dinv));
         c->assembled = true;
@@ -481,6 +482,16 @@ int qh_segments_download(const qh_ctx *cc, int64_t *n_out, int32_t *pid, int32_t
     return QH_OK;
 }
 
+int qh_edge_system_download(const qh_ctx *cc, double *rhs, double *sol) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    if (rhs) QH_HIP(c, hipMemcpyAsync(rhs, c->cge.b, sizeof(double) * c->A.n, hipMemcpyDeviceToHost, c->stream));
+    if (sol) QH_HIP(c, hipMemcpyAsync(sol, c->e_star, sizeof(double) * c->A.n, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
 int qh_deposits_download(const qh_ctx *cc, int64_t *g, int64_t *Q) {
     qh_ctx *c = const_cast<qh_ctx *>(cc);
     if (!c) return QH_EINVAL;
@@ -601,6 +612,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             }
             c->last_fallbacks = fallbacks;
             if (!se.converged) status = QH_ENOTCONV;
+            QH_HIP(c, hipMemcpyAsync(c->e_star, c->cge.x, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
             if (P->gauss) {
                 t0 = qh_tbeg(c);
                 QH_HIP(c, launch_gauss_rhs(c, c->scratch_d, P->tol_node));

@@ -143,6 +143,7 @@ struct qh_ctx {
     // fields and deposits
     double *e = nullptr;                    // Ne (wall entries 0)
     double *e_old = nullptr;                // interior edges: e^n during a field update
+    double *e_star = nullptr;               // interior edges: edge-solve solution of the last step
     int64_t *b = nullptr;                   // Nf
     int64_t *g = nullptr;                   // Ne
     int64_t *Q = nullptr, *Q_old = nullptr, *Q_bg = nullptr;  // Nn
