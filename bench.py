@@ -82,9 +82,48 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
         # + edge ids 24, per crossing: neighbour ids 16 + the next tet's records 136,
         # accumulators read-modify-write once (16 B per edge and node)
         return 56 * n_particles + 136 * mi.n_tets + 152 * crossings + 16 * (mi.n_edges + mi.n_nodes)
+    if kernel == "precond":
+        # z = G^T (G r): two CSR passes over the lower factor (FP32 value + int32 column per
+        # entry) and its transpose; per row: r in, y out, y in, z out, r in (dot), row pointers
+        n, nnz = mi.n_int_edges, mi.nnz_edge
+        nnz_l = (nnz + n) // 2
+        return 16 * nnz_l + 40 * n + 8 * (n + 1)
     if kernel == "field_prep":
         return (48 + 24 + 16 + 48) * mi.n_tets + 8 * mi.n_edges + 8 * mi.n_faces
     return None
+
+
+# HIP kernels behind each timed entry (one entry may launch several kernels)
+HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
+               "precond": ["k_prec_g<false>", "k_prec_g<true>"],
+               "particle_step": ["k_particle_step<false>", "k_gather<0>", "k_gather<6>"],
+               "edge_rhs": ["k_edge_rhs"], "field_prep": ["k_field_prep"]}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_64cube_16M.md")
+
+
+def measured_traffic(entry: str, workload: str):
+    """HBM bytes per launch from the profiler's byte counters (scaled by the copy calibration),
+    as recorded in the traffic summary; None when the summary is absent, covers another
+    workload, or any kernel's source file has changed since the counters were taken."""
+    import hashlib
+    if workload != "c3" or entry not in HIP_KERNELS or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rows = {}
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0].startswith("`k_"):
+            src = cells[5].split()
+            rows[cells[0].strip("`")] = (float(cells[4]) * 1e6, src)
+    total = 0.0
+    for k in HIP_KERNELS[entry]:
+        if k not in rows or len(rows[k][1]) != 2:
+            return None
+        path, digest = rows[k][1]
+        with open(os.path.join(ROOT, path), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest()[:16] != digest:
+                return None
+        total += rows[k][0]
+    return int(total)
 
 
 def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: float = 25.0):
@@ -129,6 +168,24 @@ def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: 
                       f"{t_field:.2f}s); rate = N_p / (push time scaled to N_p + field time)"}
 
 
+def copy_calibration(mib: int, reps: int = 5):
+    """A plain elementwise copy of known size (reads and writes mib MiB once per launch): the
+    profiler's FETCH_SIZE / WRITE_SIZE for this kernel, divided by the known bytes, gives the
+    factor that turns those counters into HBM bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)   # one read and one write of every element
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": reps,
+                                           "GB_per_s": round(8 * n / dt / 1e9, 1)}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,11 +198,17 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
     ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (read + write) a few times, to "
+                         "scale the HBM byte counters of the profiler; prints its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import paper_2103_06737_amd as qh
     ctx, cfg, mesh, parts, mi = setup(args.workload, args.particles)
     n_p = sum(p[2].size for p in parts.values())
@@ -208,7 +271,8 @@ def main():
         avg_s = kern[k]["ms_total"] / kern[k]["launches"] * 1e-3
         ach = by / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k, args.workload), "kernel": k,
+                "hip_kernels": HIP_KERNELS.get(k, []),
                 "algorithmic_bytes_per_launch": int(by), "us_per_launch": kern[k]["us_per_launch"]}
     ms_part = float(np.mean([s["ms_particles"] for s in pst]))
     fs_j = float(np.mean([s["ms_fields"] for s in pst_j]))

@@ -719,6 +719,7 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     QH_HIP(c, hipEventRecord(e1, c->stream));
     QH_HIP(c, hipMemcpyAsync(x, w.x, sizeof(double) * w.n, hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
+    qh_tflush(c);
     if (stats) {
         stats->iters = r.iters;
         stats->res = r.res;

@@ -162,17 +162,17 @@ __global__ void __launch_bounds__(256) k_prec_g(int32_t n, const int32_t *__rest
                                                 const int32_t *__restrict__ col, const float *__restrict__ val,
                                                 const double *__restrict__ in, double *__restrict__ out,
                                                 const double *__restrict__ r, double *__restrict__ part) {
-    const int sub = threadIdx.x & 7;
+    const int sub = threadIdx.x & 3;  // 4 lanes per row (rows of G hold ~9 entries)
     const unsigned nb = gridDim.x, per_x = nb / 8;
     const unsigned lb = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
     const int64_t per = (n + nb - 1) / nb;
     const int64_t rb = (int64_t)lb * per, re = rb + per < n ? rb + per : n;
     double acc = 0.0;
-    for (int64_t row = rb + (threadIdx.x >> 3); row < re; row += 32) {
+    for (int64_t row = rb + (threadIdx.x >> 2); row < re; row += 64) {
         double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += 8) s += (double)val[j] * in[col[j]];
+        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += 4) s += (double)val[j] * in[col[j]];
 #pragma unroll
-        for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+        for (int off = 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 4);
         if (sub == 0) {
             out[row] = s;
             if (DOT) acc += s * r[row];
@@ -615,7 +615,7 @@ int qh_learned_factor(qh_ctx *c) {
 }
 
 unsigned qh_prec_grid(int32_t n) {
-    int64_t b = ((int64_t)n * 8 + 255) / 256;
+    int64_t b = ((int64_t)n * 4 + 255) / 256;
     b = b < 2048 ? (b < 1 ? 1 : b) : 2048;
     return (unsigned)((b + 7) / 8 * 8);
 }
