@@ -5,6 +5,7 @@
 #include <numeric>
 
 #include "qh_internal.h"
+#include "qh_spmv.h"
 
 int qh_fail(qh_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg;
@@ -59,6 +60,10 @@ int upload_csr(qh_ctx *c, DevCsr &d, const HostCsr &h, bool two) {
     if ((rc = upload(c, &d.ptr, h.ptr.data(), h.ptr.size()))) return rc;
     if ((rc = upload(c, &d.col, h.col.data(), h.col.size()))) return rc;
     if ((rc = upload(c, two ? &d.val2 : &d.val, h.val.data(), h.val.size()))) return rc;
+    std::vector<int2> tiles;
+    if (!qh_make_tiles(h.ptr.data(), d.n, tiles)) return qh_fail(c, QH_EINVAL, "matrix row longer than a product tile");
+    d.ntiles = (int32_t)tiles.size() - 1;
+    if ((rc = upload(c, &d.tiles, tiles.data(), tiles.size()))) return rc;
     return QH_OK;
 }
 

@@ -62,6 +62,8 @@ struct DevCsr {
     int32_t *ptr = nullptr, *col = nullptr;
     double *val = nullptr;
     double *val2 = nullptr;
+    int2 *tiles = nullptr;  // row tiles of the tiled product (qh_spmv.h)
+    int32_t ntiles = 0;
 };
 
 struct Species {
@@ -96,6 +98,8 @@ struct LearnedPrec {
     std::vector<int32_t> h_row, h_col;
     int32_t *gptr = nullptr, *gcol = nullptr, *grow = nullptr;   // G, row-major
     int32_t *tptr = nullptr, *tcol = nullptr, *tsrc = nullptr;   // G^T rows; tsrc: entry of G
+    int2 *gtiles = nullptr, *ttiles = nullptr;                   // row tiles of G and G^T
+    int32_t ngtiles = 0, nttiles = 0;
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;
@@ -238,8 +242,8 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
 // qh_learned.hip
 int qh_learned_setup(qh_ctx *c);
 int qh_learned_factor(qh_ctx *c);
-unsigned qh_prec_grid(int32_t n);
-hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part);
+unsigned qh_prec_grid(qh_ctx *c);
+hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done);
 int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad);
 int qh_learned_adam(qh_ctx *c, float lr, int32_t t);
 int qh_learned_probes(qh_ctx *c, float *V_dev, uint64_t seed);

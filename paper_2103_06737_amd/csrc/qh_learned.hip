@@ -18,6 +18,7 @@
 #include <random>
 
 #include "qh_internal.h"
+#include "qh_spmv.h"
 
 namespace {
 
@@ -154,32 +155,24 @@ __global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const f
 
 // ---------------------------------------------------------------------------------------
 // Preconditioner application: y = G r (rows of G), then z = G^T y (rows of G^T) with the
-// partials of r.z. Each block takes a contiguous row range; XCD-aware block order (blocks are
-// dealt to the 8 XCDs round-robin) keeps neighbouring rows, which gather the same vector
-// entries, in one L2. Grids are multiples of 8 blocks, at most 2048.
+// partials of r.z, both as tiled products (each block a contiguous, XCD-grouped range of row
+// tiles). Grids are multiples of 8 blocks, at most 2048.
 template <bool DOT>
-__global__ void __launch_bounds__(256) k_prec_g(int32_t n, const int32_t *__restrict__ ptr,
-                                                const int32_t *__restrict__ col, const float *__restrict__ val,
-                                                const double *__restrict__ in, double *__restrict__ out,
-                                                const double *__restrict__ r, double *__restrict__ part) {
-    const int sub = threadIdx.x & 3;  // 4 lanes per row (rows of G hold ~9 entries)
-    const unsigned nb = gridDim.x, per_x = nb / 8;
-    const unsigned lb = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
-    const int64_t per = (n + nb - 1) / nb;
-    const int64_t rb = (int64_t)lb * per, re = rb + per < n ? rb + per : n;
+__global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                         const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                         const double *__restrict__ in, double *__restrict__ out,
+                                                         const double *__restrict__ r, double *__restrict__ part,
+                                                         const int32_t *__restrict__ done) {
+    if (done && done[0]) return;  // the solve has converged: nothing left to precondition
+    __shared__ double prod[kTileCap];
     double acc = 0.0;
-    for (int64_t row = rb + (threadIdx.x >> 2); row < re; row += 64) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += 4) s += (double)val[j] * in[col[j]];
-#pragma unroll
-        for (int off = 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 4);
-        if (sub == 0) {
-            out[row] = s;
-            if (DOT) acc += s * r[row];
-        }
-    }
+    tile_spmv(tiles, ntiles, ptr, col, val, in, prod, [&](int32_t row, double s) {
+        out[row] = s;
+        if (DOT) acc += s * r[row];
+    });
     if (DOT) {
-        __shared__ double sh[4];
+        __shared__ double sh[kTileThreads / 64];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -516,6 +509,14 @@ int qh_learned_setup(qh_ctx *c) {
         QH_HIP(c, hipMemcpyAsync(L.tptr, tptr.data(), 4 * (n + 1), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.tcol, tcol.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.tsrc, tsrc.data(), 4 * nnz, hipMemcpyHostToDevice, c->stream));
+        std::vector<int2> gt, tt;
+        if (!qh_make_tiles(gptr.data(), n, gt) || !qh_make_tiles(tptr.data(), n, tt))
+            return qh_fail(c, QH_EINVAL, "factor row longer than a product tile");
+        L.ngtiles = (int32_t)gt.size() - 1;
+        L.nttiles = (int32_t)tt.size() - 1;
+        if ((rc = qh_alloc(c, &L.gtiles, gt.size())) || (rc = qh_alloc(c, &L.ttiles, tt.size()))) return rc;
+        QH_HIP(c, hipMemcpyAsync(L.gtiles, gt.data(), sizeof(int2) * gt.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.ttiles, tt.data(), sizeof(int2) * tt.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
         if (!L.have_weights) {
             // He-normal hidden layers, zero output layer: the initial network is Jacobi
@@ -614,19 +615,16 @@ int qh_learned_factor(qh_ctx *c) {
     return QH_OK;
 }
 
-unsigned qh_prec_grid(int32_t n) {
-    int64_t b = ((int64_t)n * 4 + 255) / 256;
-    b = b < 2048 ? (b < 1 ? 1 : b) : 2048;
-    return (unsigned)((b + 7) / 8 * 8);
-}
+unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 
-// z = G^T (G r); part[block] = partial r.z (grid qh_prec_grid(n))
-hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part) {
+// z = G^T (G r); part[block] = partial r.z (qh_prec_grid blocks). With done != null both
+// passes return at once when done[0] is set (a converged solve).
+hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
-    const unsigned gb = qh_prec_grid(L.n);
-    hipLaunchKernelGGL(k_prec_g<false>, dim3(gb), dim3(256), 0, c->stream, L.n, L.gptr, L.gcol, L.gval, r, L.y,
-                       (const double *)nullptr, (double *)nullptr);
-    hipLaunchKernelGGL(k_prec_g<true>, dim3(gb), dim3(256), 0, c->stream, L.n, L.tptr, L.tcol, L.tval, L.y, z, r, part);
+    hipLaunchKernelGGL(k_prec_g<false>, dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
+                       L.ngtiles, L.gptr, L.gcol, L.gval, r, L.y, (const double *)nullptr, (double *)nullptr, done);
+    hipLaunchKernelGGL(k_prec_g<true>, dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
+                       L.nttiles, L.tptr, L.tcol, L.tval, L.y, z, r, part, done);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // Gauss law (eq. discreteGauss): G^T [*eps] G delta = rho^{n+1} - G^T [*eps] e*, e = e* + G delta
 // Faraday: b^{n+1} = b^n - C round((dt/2)(e^{n+1} + e^n)/u_b)  (D C = 0 keeps D b fixed).
 #include "qh_internal.h"
+#include "qh_spmv.h"
 
 namespace {
 
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict_
 // r.r from its partials, convergence test, beta. Then, with w = A z (the only gathered
 // vector), p = z + beta p and q = A p = w + beta q in place (own rows only), and the
 // partials of p.q. Gathering one vector instead of z and p halves the scattered loads.
-__global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *__restrict__ ptr,
+__global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int2 *__restrict__ tiles, int32_t ntiles,
+                                                      const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ z,
@@ -158,6 +160,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *
                                                       int32_t k, int32_t par) {
     if (flags[0]) return;
     __shared__ double sh[kThreads / 64];
+    __shared__ double prod[kTileCap];
     double beta = 0.0;
     if (k > 0) {
         double rz_new = sum_partials(rz_part, m_rz, sh);
@@ -169,26 +172,19 @@ __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int32_t *
             flags[1] = k;
             if (done) flags[0] = 1;
         }
-        if (done) return;
+        if (done) return;  // the same decision in every block (same sums, same order)
         beta = rz_new / scal[S_RZ + par];
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[S_RZ + 1] = scal[S_RZ];
     }
-    const int sub = threadIdx.x % kLpr;
-    const Rows rr_ = block_rows(n);
     double acc[1] = {0.0};
-    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * z[col[j]];
-        s = wave_sum_lpr(s);
-        if (sub == 0) {
-            double pn = k > 0 ? z[row] + beta * p[row] : z[row];
-            double qn = k > 0 ? s + beta * q[row] : s;
-            p[row] = pn;
-            q[row] = qn;
-            acc[0] += pn * qn;
-        }
-    }
+    tile_spmv(tiles, ntiles, ptr, col, val, z, prod, [&](int32_t row, double s) {
+        const double pn = k > 0 ? z[row] + beta * p[row] : z[row];
+        const double qn = k > 0 ? s + beta * q[row] : s;
+        p[row] = pn;
+        q[row] = qn;
+        acc[0] += pn * qn;
+    });
     write_partials<1>(acc, part);
 }
 
@@ -425,12 +421,12 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     // partials: [0, 4K) init / update (slot 0 r.z with Jacobi, 1 r.r, 2 b.b), [4K, 5K) products,
     // [5K, 6K) r.z of the learned preconditioner
     double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks, *ppart = w.partial + 5 * kMaxBlocks;
-    const unsigned gr = grid_rows(w.n), ge = grid_elems(w.n);
-    const unsigned gp = learned ? qh_prec_grid(w.n) : 0;
+    const unsigned gr = grid_rows(w.n), ge = grid_elems(w.n), gt = tile_grid(M.ntiles);
+    const unsigned gp = learned ? qh_prec_grid(c) : 0;
     int t0 = qh_tbeg(c);
     hipLaunchKernelGGL(k_cg_init, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, w.dinv,
                        w.r, w.z, w.p0, upart);
-    if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart));
+    if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, nullptr));
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr,
                        learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gr, w.scal,
                        w.flags, tol * tol, abs_thr2_dev);
@@ -447,22 +443,22 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
         for (int k = it; k < it + batch; ++k) {
             int par = k & 1;
             int ta = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_spmv, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.z, w.p0,
-                               w.q, learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : m_up,
-                               upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par);
+            hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr, M.col,
+                               M.val, w.z, w.p0, w.q, learned ? (const double *)ppart : (const double *)upart,
+                               learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par);
             qh_tend(c, ta, k_spmv);
             int tb = qh_tbeg(c);
             if (learned)
                 hipLaunchKernelGGL(k_cg_update<false>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
-                                   w.q, w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
+                                   w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
             else
                 hipLaunchKernelGGL(k_cg_update<true>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
-                                   w.q, w.dinv, qpart, upart, (int)gr, w.scal, w.flags, par);
+                                   w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
             qh_tend(c, tb, k_upd);
             m_up = (int)ge;
             if (learned) {
                 int tp = qh_tbeg(c);
-                QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart));
+                QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, w.flags));
                 qh_tend(c, tp, QK_PREC);
             }
         }
@@ -484,6 +480,20 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     out.res = res2[1] > 0 ? sqrt(res2[0] / res2[1]) : 0.0;
     out.converged = hflags[0] != 0 && out.res == out.res;
     return QH_OK;
+}
+
+bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles) {
+    tiles.clear();
+    int32_t r = 0;
+    tiles.push_back(make_int2(0, ptr[0]));
+    while (r < n) {
+        int32_t e = r;
+        while (e < n && e - r < kTileRows && ptr[e + 1] - ptr[r] <= kTileCap) ++e;
+        if (e == r) return false;
+        tiles.push_back(make_int2(e, ptr[e]));
+        r = e;
+    }
+    return true;
 }
 
 hipError_t launch_assemble_A(qh_ctx *c, double tau) {

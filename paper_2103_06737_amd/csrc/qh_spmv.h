@@ -1,0 +1,89 @@
+// Tiled CSR products y_i = sum_j a_ij x_j for the FP64 solver (shared by qh_solver.hip and
+// qh_learned.hip).
+//
+// A tile is a run of at most kTileRows consecutive rows holding at most kTileCap entries.
+// One 256-thread block walks a contiguous range of tiles. Per tile, every thread first forms
+// kTileCap / 256 products a_ij * x_j over the tile's entries in storage order (the value and
+// column loads are coalesced and independent of the row structure, so many are in flight at
+// once), keeping them in LDS; then thread t adds up the products of row (first row + t) and
+// hands the sum to an epilogue. Against one row per lane group this removes the chain of
+// dependent loads (row pointer -> entries -> gathered vector) per row.
+#pragma once
+
+#include "qh_internal.h"
+
+constexpr int kTileThreads = 256;
+constexpr int kTileRows = kTileThreads;  // one row per thread in the summing pass
+constexpr int kTileCap = 4096;           // products per tile (32 KB of LDS)
+constexpr int kTileUnroll = 8;           // product loads issued together per thread
+
+// Tile starts {first row, first entry}; tiles[ntiles] = {n, nnz}. Rows longer than kTileCap
+// entries are not supported (returns false).
+bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles);
+
+// Contiguous tile range of this block; the block index is remapped so that each of the 8
+// XCDs (which receive blocks round-robin) covers one contiguous span of tiles. The grid must
+// be a multiple of 8 blocks.
+__device__ __forceinline__ void tile_range(int32_t ntiles, int32_t &tb, int32_t &te) {
+    const unsigned nb = gridDim.x, per_x = nb / 8;
+    const unsigned lb = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
+    const int32_t per = (int32_t)((ntiles + nb - 1) / nb);
+    tb = (int32_t)lb * per;
+    te = tb + per < ntiles ? tb + per : ntiles;
+    if (tb > ntiles) tb = ntiles;
+}
+
+// For every row of this block's tiles: epi(row, sum_j a_row,j x_j). All threads of the block
+// must call it (it synchronises the block).
+template <typename VT, typename Epi>
+__device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
+                                          const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                          const VT *__restrict__ val, const double *__restrict__ x,
+                                          double *prod /* LDS, kTileCap */, Epi &&epi) {
+    int32_t tb, te;
+    tile_range(ntiles, tb, te);
+    const int tid = threadIdx.x;
+    for (int32_t ti = tb; ti < te; ++ti) {
+        const int2 t0 = tiles[ti], t1 = tiles[ti + 1];
+        const int32_t row = t0.x + tid;
+        int32_t js = 0, je = 0;
+        if (row < t1.x) {
+            js = ptr[row] - t0.y;
+            je = ptr[row + 1] - t0.y;
+        }
+        const int32_t cnt = t1.y - t0.y;  // >= 1 whenever the tile has rows with entries
+        for (int32_t b = 0; b < cnt; b += kTileUnroll * kTileThreads) {
+            VT v[kTileUnroll];
+            int32_t c[kTileUnroll];
+#pragma unroll
+            for (int u = 0; u < kTileUnroll; ++u) {
+                int32_t j = b + u * kTileThreads + tid;
+                j = j < cnt ? j : cnt - 1;  // clamped: every load stays inside the tile
+                v[u] = val[t0.y + j];
+                c[u] = col[t0.y + j];
+            }
+            double xv[kTileUnroll];
+#pragma unroll
+            for (int u = 0; u < kTileUnroll; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < kTileUnroll; ++u) {
+                const int32_t j = b + u * kTileThreads + tid;
+                if (j < cnt) prod[j] = (double)v[u] * xv[u];
+            }
+        }
+        __syncthreads();
+        if (row < t1.x) {
+            double s = 0.0;
+            for (int32_t j = js; j < je; ++j) s += prod[j];
+            epi(row, s);
+        }
+        __syncthreads();
+    }
+}
+
+// Grid of a tiled product: one block per tile up to 2048 blocks, a multiple of 8.
+inline unsigned tile_grid(int32_t ntiles) {
+    int64_t b = ntiles < 2048 ? ntiles : 2048;
+    if (b < 8) b = 8;
+    return (unsigned)((b + 7) / 8 * 8);
+}
