@@ -50,7 +50,7 @@ extern "C" {
 #define QH_FIELDS_SOLVE 1  /* full cycle: implicit field update after each push */
 
 #define QH_PC_JACOBI 0  /* diagonal preconditioner, conjugate gradients */
-#define QH_PC_LEARNED 1 /* learned edge-local preconditioner, flexible CG, Jacobi fallback */
+#define QH_PC_LEARNED 1 /* learned edge-local preconditioner M = G^T G, conjugate gradients, Jacobi fallback */
 
 #define QH_SYS_EDGE 0 /* ([*eps] + dt^2/4 S) on interior edges */
 #define QH_SYS_NODE 1 /* G^T [*eps] G on interior nodes (discrete Laplacian) */
@@ -79,7 +79,9 @@ typedef struct {
     double tol_edge;     /* relative residual of the edge solve (e.g. 1e-8) */
     double tol_node;     /* Gauss-law residual target, relative to ||rho|| + || |G^T[*eps]| |e| || */
     int32_t max_it_edge, max_it_node;
-    int32_t check_every; /* iterations between host reads of the convergence flag */
+    int32_t check_every; /* iterations between host reads of the convergence flag; the first read
+                            of a solve comes after as many iterations as the previous solve of
+                            the same system and preconditioner took */
     int32_t verify;      /* 1: check continuity and D b on the device every step */
 } qh_step_params_t;
 
@@ -92,7 +94,7 @@ typedef struct {
     int64_t divb_bad;               /* tets where D b changed (verify = 1) */
     int32_t fallbacks;              /* learned -> Jacobi restarts */
     float ms_particles, ms_fields;  /* device time of the two halves (HIP events) */
-    int64_t foreign;                /* deposits into tets outside a block's range (atomics) */
+    int64_t foreign;                /* deposits into tets outside a block's range (mailbox records) */
 } qh_step_stats_t;
 
 typedef struct {

@@ -92,6 +92,7 @@ int ensure_assembled(qh_ctx *c) {
         if ((rc = upload_csr(c, c->A, c->hA, true))) return rc;
         if ((rc = upload(c, &c->A_S, c->hA.val2.data(), c->hA.val2.size()))) return rc;
         if ((rc = qh_alloc(c, &c->A.val, c->A.nnz))) return rc;
+        if ((rc = qh_alloc(c, &c->A_rhs, c->A.nnz))) return rc;
         if ((rc = upload_csr(c, c->CMb, c->hCMb, false))) return rc;
         if ((rc = upload_csr(c, c->GtM, c->hGtM, false))) return rc;
         if ((rc = upload_csr(c, c->K, c->hK, false))) return rc;
@@ -245,6 +246,10 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = upload(c, &c->n2t_ptr, m.n2t_ptr.data(), m.n2t_ptr.size()))) return rc;
     if ((rc = upload(c, &c->n2t, m.n2t.data(), m.n2t.size()))) return rc;
     if ((rc = qh_alloc(c, &c->acc_tet, 10 * m.Nt))) return rc;
+    {
+        const int64_t nmail = (m.Nt + kMailTets - 1) / kMailTets;
+        if ((rc = qh_alloc(c, &c->mail_cnt, nmail)) || (rc = qh_alloc(c, &c->mail, nmail * kMailCap * 9))) return rc;
+    }
     if ((rc = qh_alloc(c, &c->frec, 3 * m.Nt))) return rc;
     if ((rc = qh_alloc(c, &c->e, m.Ne)) || (rc = qh_alloc(c, &c->b, m.Nf)) || (rc = qh_alloc(c, &c->g, m.Ne)) ||
         (rc = qh_alloc(c, &c->Q, m.Nn)) || (rc = qh_alloc(c, &c->Q_old, m.Nn)) || (rc = qh_alloc(c, &c->Q_bg, m.Nn)) ||

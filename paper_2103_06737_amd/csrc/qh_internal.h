@@ -13,6 +13,9 @@ constexpr int QH_FBITS = 20;                  // fixed-point bits of barycentric
 constexpr int QH_SCALE = 1 << QH_FBITS;
 constexpr int QH_MAX_PIECES = 64;             // straight pieces per particle per step
 constexpr int QH_COUNTER_SLOTS = 256;         // spread of the per-block event counters
+constexpr int QH_CHUNK = 512;                 // particles per block of the particle kernels
+constexpr int kMailTets = 128;                // tets per deposit mailbox
+constexpr int kMailCap = 1024;                // records per mailbox
 
 // ---------------------------------------------------------------------------------------
 // Host-side mesh complex and FP64 assembly (qh_mesh.hip)
@@ -75,7 +78,7 @@ struct Species {
     // sort scratch (same layout)
     float *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
     int32_t *stet = nullptr, *sid = nullptr;
-    int32_t *own = nullptr;  // owned tet range per particle block (see qh_particles.hip)
+    int32_t *own = nullptr;    // owned tet range per particle block (see qh_particles.hip)
 };
 
 // Krylov workspace for one system.
@@ -87,6 +90,7 @@ struct CgWork {
     double *scal = nullptr;     // device scalars (see qh_solver.hip)
     unsigned int *counter = nullptr;
     int32_t *flags = nullptr;   // [0] done, [1] iterations
+    int32_t last_iters[2] = {0, 0};  // iterations of the last converged solve (Jacobi, learned)
 };
 
 // Learned preconditioner state (qh_learned.hip)
@@ -137,10 +141,13 @@ struct qh_ctx {
     int32_t *n2e_ptr = nullptr, *n2e = nullptr;
     int32_t *e2t_ptr = nullptr, *e2t = nullptr;  // edge -> tet*8 + local edge
     int32_t *n2t_ptr = nullptr, *n2t = nullptr;  // node -> tet*8 + local vertex
-    int64_t *acc_tet = nullptr;                  // 10*Nt per-tet owned deposit sums
+    int64_t *acc_tet = nullptr;                  // 10*Nt per-tet deposit sums, plane-major [10][Nt]
+    unsigned int *mail_cnt = nullptr;            // per mailbox (run of kMailTets tets): records posted
+    int32_t *mail = nullptr;                     // mailboxes: ceil(Nt / kMailTets) x kMailCap x 9 int32
 
     DevCsr A, CMb, GtM, K;  // A: val = [*eps] + tau S, val2 = [*eps]
     double *A_S = nullptr;  // S values on the pattern of A
+    double *A_rhs = nullptr;  // [*eps] - tau S on the pattern of A (right-hand side)
     double tau_assembled = -1.0;
     bool assembled = false;
 

@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict_
     if (done && done[0]) return;  // the solve has converged: nothing left to precondition
     __shared__ double prod[kTileCap];
     double acc = 0.0;
-    tile_spmv(tiles, ntiles, ptr, col, val, in, prod, [&](int32_t row, double s) {
+    tile_spmv(tiles, ntiles, ptr, col, val, in, prod, [&](int32_t row) { return DOT ? r[row] : 0.0; },
+              [&](int32_t row, double s, double rr) {
         out[row] = s;
-        if (DOT) acc += s * r[row];
+        if (DOT) acc += s * rr;
     });
     if (DOT) {
         __shared__ double sh[kTileThreads / 64];

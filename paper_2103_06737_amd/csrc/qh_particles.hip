@@ -21,7 +21,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kPpt = 2;                  // consecutive particles per thread
 constexpr int kChunk = kBlock * kPpt;    // particles per block
+static_assert(kChunk == QH_CHUNK, "particle chunk size");
 constexpr int kWin = 128;                // owned tets whose sums a block keeps in LDS
+constexpr int kRec = 9;                  // int32 words of a mailbox record: tet | end << 31, L0[4], L1[4]
 
 __device__ __forceinline__ void lam4(const float4 A, const float4 B, const float4 C, float x,
                                      float y, float z, float l[4]) {
@@ -70,13 +72,15 @@ struct StepArgs {
     int32_t *tet;
     const int32_t *pid;
     const int32_t *own;     // own[b] .. own[b+1]: tets owned by block b (from the last sort)
+    unsigned int *mail_cnt; // records posted to each mailbox (tets [kMailTets m, kMailTets (m+1))) this launch
+    int32_t *mail;          // kMailCap records of kRec words per mailbox
     int64_t n;
     int32_t nt;
     float hqm;              // q/m * dt / 2
     float dt;
     int32_t zq;             // charge number
-    int64_t *g, *Q;         // deposits into tets a block does not own (atomics)
-    int64_t *acc_tet;       // per-tet sums of owned deposits: 6 edges, 4 nodes (plain stores)
+    int64_t *g, *Q;         // deposits that find no mailbox slot (atomics)
+    int64_t *acc_tet;       // per-tet sums, plane-major: acc_tet[k * nt + t], k = 6 edges, 4 nodes
     unsigned long long *counters;
     // capture
     int32_t species;
@@ -138,61 +142,205 @@ void launch_field_prep(qh_ctx *c) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Deposit routing.
+//
+// A block owns the tets [own[b], own[b+1]) that its chunk of particles held at the last sort;
+// the first kWin of them (its window) are summed in LDS per unit charge (edges sum
+// L_a^0 L_b^1 - L_a^1 L_b^0, nodes sum the L_n of end points; the charge number and 2^20 scale
+// them when they leave LDS). A piece in a tet outside the window (a particle that moved since
+// the sort, a walk piece past the range) is posted as one compact record into the mailbox of
+// that tet's run of kMailTets tets; slots are reserved with one 32-bit atomic per wave and
+// mailbox instead of ten 64-bit atomics per piece. k_mail_apply adds each mailbox into acc_tet, and the gather
+// kernels add acc_tet into edges and nodes. Only records that find no mailbox slot use int64
+// atomics on edges and nodes. Integer sums do not depend on order, so the result is the same
+// bits on every path.
+
+// Unit-charge values of one straight piece P0 -> P1 (6 edges; 4 nodes when P1 is the end).
+__device__ __forceinline__ void piece_values(const int P0[4], const int P1[4], bool end, long long v[10]) {
+    const int LE0[6] = {0, 0, 0, 1, 1, 2};
+    const int LE1[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        v[j] = (long long)P0[LE0[j]] * P1[LE1[j]] - (long long)P1[LE0[j]] * P0[LE1[j]];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[6 + r] = end ? P1[r] : 0;
+}
+
+template <int WIN>
+__device__ __forceinline__ void put_lds(long long *acc, int slot, const long long *v) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) atomic_add_lds(&acc[k * WIN + slot], v[k]);
+}
+
+// A piece in a tet outside the window: one record into the tet's mailbox, or, when the
+// mailbox is full, int64 atomics on edges and nodes.
+__device__ __forceinline__ void post_piece(const StepArgs &a, int tt, const int P0[4], const int P1[4], bool end) {
+    const int o = tt / kMailTets;
+    // slots are reserved with one atomic per distinct mailbox among the active lanes
+    unsigned int slot = 0xffffffffu;
+    const int lane = __lane_id();
+    unsigned long long pending = __ballot(1);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lo = __shfl(o, leader);
+        const unsigned long long same = __ballot(o == lo);
+        unsigned int first = 0;
+        if (lane == leader) first = atomicAdd(&a.mail_cnt[lo], (unsigned int)__popcll(same));
+        first = (unsigned int)__shfl((int)first, leader);
+        if (o == lo) slot = first + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    if (slot < (unsigned)kMailCap) {
+        int32_t *r = a.mail + ((int64_t)o * kMailCap + slot) * kRec;
+        r[0] = tt | (end ? (int32_t)0x80000000u : 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { r[1 + j] = P0[j]; r[5 + j] = P1[j]; }
+        return;
+    }
+    long long v[10];
+    piece_values(P0, P1, end, v);
+    const int32_t *te = a.tedges + 8 * (int64_t)tt;
+    const int4 tn = a.tnodes[tt];
+    const int nv[4] = {tn.x, tn.y, tn.z, tn.w};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (v[k]) atomic_add_i64(a.g + te[k], a.zq * v[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (v[6 + k]) atomic_add_i64(a.Q + nv[k], (long long)a.zq * QH_SCALE * v[6 + k]);
+}
+
+__device__ __forceinline__ void record_piece(const StepArgs &a, int32_t pid, int seq, int tt, const int L0[4],
+                                             const int L1[4]) {
+    unsigned long long s = atomicAdd(a.seg_count, 1ull);
+    if ((int64_t)s < a.cap) {
+        int32_t *o = a.seg_buf + 12 * s;
+        o[0] = pid; o[1] = a.species; o[2] = seq; o[3] = tt;
+        for (int r = 0; r < 4; ++r) { o[4 + r] = L0[r]; o[8 + r] = L1[r]; }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Walk of one particle from (px, py, pz) in tet t along dt v^{n+1/2}, face by face (exit
+// face = smallest crossing parameter, the entry face excluded; at most QH_MAX_PIECES
+// pieces), reflecting specularly at axis-aligned walls. deposit(tet, L_start, L_end, end)
+// takes each straight piece; on return the state holds the end point, its tet and the
+// (possibly reflected) velocity.
+template <bool CAPTURE, typename Dep>
+__device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py, float &pz, float &vx, float &vy,
+                                         float &vz, int &t, int32_t pid, Dep &&deposit, unsigned int &n_cross,
+                                         unsigned int &n_wall, unsigned int &n_lost) {
+    int seq = 0;
+    float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
+    int4 nb4 = a.tnbr[t], on = a.tnodes[t];  // loaded with the geometry: one round trip per tet
+    float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
+    float l[4];
+    int Lp[4], Lc[4];
+    lam4(A, B, C, px, py, pz, l);
+    quantize(l, -1, Lp);
+    int entry = -1, pieces = 0;
+    for (;;) {
+        float gl[4];
+        gl[1] = A.x * rx + A.y * ry + A.z * rz;
+        gl[2] = B.x * rx + B.y * ry + B.z * rz;
+        gl[3] = C.x * rx + C.y * ry + C.z * rz;
+        gl[0] = -(gl[1] + gl[2] + gl[3]);
+        lam4(A, B, C, px, py, pz, l);
+        int k = -1;
+        float smin = 2.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r == entry) continue;
+            float le = l[r] + gl[r];
+            if (!(le < 0.0f)) continue;
+            float s = l[r] <= 0.0f ? 0.0f : l[r] / (l[r] - le);
+            if (s < smin) { smin = s; k = r; }
+        }
+        if (k < 0) { px += rx; py += ry; pz += rz; break; }
+        if (pieces >= QH_MAX_PIECES - 1) { ++n_lost; break; }
+        float cx = __fmaf_rn(smin, rx, px), cy = __fmaf_rn(smin, ry, py), cz = __fmaf_rn(smin, rz, pz);
+        lam4(A, B, C, cx, cy, cz, l);
+        quantize(l, k, Lc);
+        deposit(t, Lp, Lc, false);
+        if (CAPTURE) record_piece(a, pid, seq, t, Lp, Lc);
+        ++seq;
+        ++pieces;
+        float rem = 1.0f - smin;
+        rx *= rem; ry *= rem; rz *= rem;
+        px = cx; py = cy; pz = cz;
+        int nb = k == 0 ? nb4.x : k == 1 ? nb4.y : k == 2 ? nb4.z : nb4.w;
+        if (nb >= 0) {
+            const int4 nn = a.tnodes[nb];
+            A = a.geo[3 * nb]; B = a.geo[3 * nb + 1]; C = a.geo[3 * nb + 2];
+            const int4 nbn = a.tnbr[nb];
+            int ov[4] = {on.x, on.y, on.z, on.w}, nv[4] = {nn.x, nn.y, nn.z, nn.w};
+            int fresh = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int val = 0, found = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (ov[r] == nv[j]) { val = Lc[r]; found = 1; }
+                Lp[j] = val;
+                if (!found) fresh = j;
+            }
+            entry = fresh;
+            t = nb;
+            nb4 = nbn;
+            on = nn;
+            ++n_cross;
+        } else {
+            // specular reflection at an axis-aligned wall: the wall normal is grad l_k
+            float nx, ny, nz;
+            if (k == 0) { nx = -(A.x + B.x + C.x); ny = -(A.y + B.y + C.y); nz = -(A.z + B.z + C.z); }
+            else if (k == 1) { nx = A.x; ny = A.y; nz = A.z; }
+            else if (k == 2) { nx = B.x; ny = B.y; nz = B.z; }
+            else { nx = C.x; ny = C.y; nz = C.z; }
+            const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
+            const bool fx = ax >= ay && ax >= az, fy = !fx && ay >= az, fz = !fx && !fy;
+            // selects, not branches: keeps the components in registers
+            rx = fx ? -rx : rx; vx = fx ? -vx : vx;
+            ry = fy ? -ry : ry; vy = fy ? -vy : vy;
+            rz = fz ? -rz : rz; vz = fz ? -vz : vz;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Lp[r] = Lc[r];
+            entry = k;
+            ++n_wall;
+        }
+    }
+    int Le[4];
+    lam4(A, B, C, px, py, pz, l);
+    quantize(l, -1, Le);
+    deposit(t, Lp, Le, true);
+    if (CAPTURE) record_piece(a, pid, seq, t, Lp, Le);
+}
+
+// ------------------------------------------------------------------------------------------
 // Fused particle step. A block takes kChunk consecutive particles (sorted by tet at the last
-// sort), kPpt consecutive ones per thread. The block owns the tets [own[b], own[b+1]) its
-// particles held at that sort: their deposits are summed in LDS (after a per-thread register
-// sum over consecutive particles of one tet) and written once per tet as plain stores into
-// acc_tet; a gather kernel then adds acc_tet into edges and nodes. Deposits into other tets
-// (particles that moved since the sort, pieces past a block's range) use int64 atomics.
-// Integer sums do not depend on order, so the result is the same bits either way.
+// sort), kPpt consecutive ones per thread.
+// Phase A: gather, Boris, and for a particle whose straight path stays in its tet, the new
+// position and its deposit (a per-thread register sum over consecutive particles of one tet,
+// then LDS). Particles whose path leaves the tet are queued in LDS.
+// Phase B: the queued particles are walked one per lane.
+// The state is staged in LDS and written back once, coalesced; the window sums are written as
+// plain stores into acc_tet (zeros for owned tets past the window, whose pieces are posted).
 template <bool CAPTURE>
 __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
-    __shared__ long long acc[kWin * 10];
+    __shared__ long long acc[10 * kWin];  // plane-major: acc[k * kWin + slot]
     __shared__ unsigned short queue[kChunk];  // block-local index of each particle that leaves its tet
     __shared__ float sx_[kChunk], sy_[kChunk], sz_[kChunk], svx_[kChunk], svy_[kChunk], svz_[kChunk];
     __shared__ int st_[kChunk];           // particle state staged for one coalesced write-back
-    __shared__ unsigned int s_cnt[5];     // crossings, wall hits, lost, queue length, foreign puts
+    __shared__ unsigned int s_cnt[5];     // queue length, crossings, wall hits, lost, posted pieces
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     const int T0 = a.own[blockIdx.x], T1 = a.own[blockIdx.x + 1];
     const int W = min(T1 - T0, kWin);
-    for (int j = threadIdx.x; j < W * 10; j += kBlock) acc[j] = 0;
+    for (int j = threadIdx.x; j < 10 * kWin; j += kBlock) acc[j] = 0;
     if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int32_t zq = a.zq;
     unsigned int n_foreign = 0;
     const int LE0[6] = {0, 0, 0, 1, 1, 2};
     const int LE1[6] = {1, 2, 3, 2, 3, 3};
 
-    // add the 10 values of one tet (6 edges, 4 nodes) to the owned LDS sums or atomically
-    auto put = [&](int tt, const long long *v) {
-        int slot = tt - T0;
-        if ((unsigned)slot < (unsigned)W) {
-#pragma unroll
-            for (int k = 0; k < 10; ++k)
-                if (v[k]) atomic_add_lds(&acc[slot * 10 + k], v[k]);
-        } else {
-            ++n_foreign;
-            const int32_t *te = a.tedges + 8 * (int64_t)tt;
-            int4 tn = a.tnodes[tt];
-            int nv[4] = {tn.x, tn.y, tn.z, tn.w};
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                if (v[k]) atomic_add_i64(a.g + te[k], v[k]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (v[6 + k]) atomic_add_i64(a.Q + nv[k], v[6 + k]);
-        }
-    };
-    auto record = [&](int32_t pid, int seq, int tt, const int L0[4], const int L1[4]) {
-        unsigned long long s = atomicAdd(a.seg_count, 1ull);
-        if ((int64_t)s < a.cap) {
-            int32_t *o = a.seg_buf + 12 * s;
-            o[0] = pid; o[1] = a.species; o[2] = seq; o[3] = tt;
-            for (int r = 0; r < 4; ++r) { o[4 + r] = L0[r]; o[8 + r] = L1[r]; }
-        }
-    };
-
-    // ---- phase A: gather, push; particles that stay in their tet are finished here
     int cur = -1;
     long long rs[10];
 #pragma unroll
@@ -259,8 +407,8 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
         st_[li] = t;
         if (leaves) {
-            // walked in phase B from the staged start point and new velocity
-            unsigned int k = atomicAdd(&s_cnt[3], 1u);
+            // walked in phase B from the start point with the new velocity
+            unsigned int k = atomicAdd(&s_cnt[0], 1u);
             queue[k] = (unsigned short)li;
             sx_[li] = px; sy_[li] = py; sz_[li] = pz;
             continue;
@@ -271,134 +419,55 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         quantize(l, -1, L0);
         lam4(A, B, C, px, py, pz, l);
         quantize(l, -1, L1);
+        if (CAPTURE) record_piece(a, a.pid[i], 0, t, L0, L1);
+        if ((unsigned)(t - T0) >= (unsigned)W) {
+            ++n_foreign;
+            post_piece(a, t, L0, L1, true);  // a particle that has moved out of the block's window
+            continue;
+        }
         if (t != cur) {
-            if (cur >= 0) put(cur, rs);
+            if (cur >= 0) put_lds<kWin>(acc, cur - T0, rs);
 #pragma unroll
             for (int k = 0; k < 10; ++k) rs[k] = 0;
             cur = t;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            rs[k] += zq * ((long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]]);
+            rs[k] += (long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) rs[6 + r] += (long long)zq * QH_SCALE * L1[r];
-        if (CAPTURE) record(a.pid[i], 0, t, L0, L1);
+        for (int r = 0; r < 4; ++r) rs[6 + r] += L1[r];
     }
-    if (cur >= 0) put(cur, rs);
+    if (cur >= 0) put_lds<kWin>(acc, cur - T0, rs);
     __syncthreads();
 
     // ---- phase B: walk the particles that leave their tet, one per lane
-    const int nq = (int)s_cnt[3];
+    const int nq = (int)s_cnt[0];
     unsigned int n_cross = 0, n_wall = 0, n_lost = 0;
+    auto deposit = [&](int tt, const int P0[4], const int P1[4], bool end) {
+        const int slot = tt - T0;
+        if ((unsigned)slot < (unsigned)W) {
+            long long v[10];
+            piece_values(P0, P1, end, v);
+            put_lds<kWin>(acc, slot, v);
+        } else {
+            ++n_foreign;
+            post_piece(a, tt, P0, P1, end);
+        }
+    };
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
         const int li = queue[qi];
-        const int64_t i = base + li;
-        float vx = svx_[li], vy = svy_[li], vz = svz_[li];
         float px = sx_[li], py = sy_[li], pz = sz_[li];
+        float vx = svx_[li], vy = svy_[li], vz = svz_[li];
         int t = st_[li];
-        int32_t pid = 0;
-        if (CAPTURE) pid = a.pid[i];
-        int seq = 0;
-        float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
-        float rx = a.dt * vx, ry = a.dt * vy, rz = a.dt * vz;
-        float l[4];
-        int Lp[4], Lc[4];
-        lam4(A, B, C, px, py, pz, l);
-        quantize(l, -1, Lp);
-        int entry = -1, pieces = 0;
-        for (;;) {
-            float gl[4];
-            gl[1] = A.x * rx + A.y * ry + A.z * rz;
-            gl[2] = B.x * rx + B.y * ry + B.z * rz;
-            gl[3] = C.x * rx + C.y * ry + C.z * rz;
-            gl[0] = -(gl[1] + gl[2] + gl[3]);
-            lam4(A, B, C, px, py, pz, l);
-            int k = -1;
-            float smin = 2.0f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (r == entry) continue;
-                float le = l[r] + gl[r];
-                if (!(le < 0.0f)) continue;
-                float s = l[r] <= 0.0f ? 0.0f : l[r] / (l[r] - le);
-                if (s < smin) { smin = s; k = r; }
-            }
-            if (k < 0) { px += rx; py += ry; pz += rz; break; }
-            if (pieces >= QH_MAX_PIECES - 1) { ++n_lost; break; }
-            float cx = __fmaf_rn(smin, rx, px), cy = __fmaf_rn(smin, ry, py), cz = __fmaf_rn(smin, rz, pz);
-            lam4(A, B, C, cx, cy, cz, l);
-            quantize(l, k, Lc);
-            {
-                long long v[10];
-#pragma unroll
-                for (int j = 0; j < 6; ++j)
-                    v[j] = zq * ((long long)Lp[LE0[j]] * Lc[LE1[j]] - (long long)Lc[LE0[j]] * Lp[LE1[j]]);
-#pragma unroll
-                for (int j = 6; j < 10; ++j) v[j] = 0;
-                put(t, v);
-                if (CAPTURE) record(pid, seq, t, Lp, Lc);
-                ++seq;
-            }
-            ++pieces;
-            float rem = 1.0f - smin;
-            rx *= rem; ry *= rem; rz *= rem;
-            px = cx; py = cy; pz = cz;
-            int4 nb4 = a.tnbr[t];
-            int nb = k == 0 ? nb4.x : k == 1 ? nb4.y : k == 2 ? nb4.z : nb4.w;
-            if (nb >= 0) {
-                int4 on = a.tnodes[t], nn = a.tnodes[nb];
-                int ov[4] = {on.x, on.y, on.z, on.w}, nv[4] = {nn.x, nn.y, nn.z, nn.w};
-                int fresh = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int val = 0, found = 0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (ov[r] == nv[j]) { val = Lc[r]; found = 1; }
-                    Lp[j] = val;
-                    if (!found) fresh = j;
-                }
-                entry = fresh;
-                t = nb;
-                A = a.geo[3 * t]; B = a.geo[3 * t + 1]; C = a.geo[3 * t + 2];
-                ++n_cross;
-            } else {
-                // specular reflection at an axis-aligned wall: the wall normal is grad l_k
-                float nx, ny, nz;
-                if (k == 0) { nx = -(A.x + B.x + C.x); ny = -(A.y + B.y + C.y); nz = -(A.z + B.z + C.z); }
-                else if (k == 1) { nx = A.x; ny = A.y; nz = A.z; }
-                else if (k == 2) { nx = B.x; ny = B.y; nz = B.z; }
-                else { nx = C.x; ny = C.y; nz = C.z; }
-                float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
-                if (ax >= ay && ax >= az) { rx = -rx; vx = -vx; }
-                else if (ay >= az) { ry = -ry; vy = -vy; }
-                else { rz = -rz; vz = -vz; }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Lp[r] = Lc[r];
-                entry = k;
-                ++n_wall;
-            }
-        }
-        int Le[4];
-        lam4(A, B, C, px, py, pz, l);
-        quantize(l, -1, Le);
-        {
-            long long v[10];
-#pragma unroll
-            for (int j = 0; j < 6; ++j)
-                v[j] = zq * ((long long)Lp[LE0[j]] * Le[LE1[j]] - (long long)Le[LE0[j]] * Lp[LE1[j]]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[6 + r] = (long long)zq * QH_SCALE * Le[r];
-            put(t, v);
-            if (CAPTURE) record(pid, seq, t, Lp, Le);
-        }
+        const int32_t pid = CAPTURE ? a.pid[base + li] : 0;
+        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit, n_cross, n_wall, n_lost);
         sx_[li] = px; sy_[li] = py; sz_[li] = pz;
         svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
         st_[li] = t;
     }
-    if (n_cross) atomicAdd(&s_cnt[0], n_cross);
-    if (n_wall) atomicAdd(&s_cnt[1], n_wall);
-    if (n_lost) atomicAdd(&s_cnt[2], n_lost);
+    if (n_cross) atomicAdd(&s_cnt[1], n_cross);
+    if (n_wall) atomicAdd(&s_cnt[2], n_wall);
+    if (n_lost) atomicAdd(&s_cnt[3], n_lost);
     if (n_foreign) atomicAdd(&s_cnt[4], n_foreign);
     __syncthreads();
     // coalesced write-back of the staged particle state
@@ -420,12 +489,17 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             a.tet[i] = st_[li];
         }
     }
-    // owned tets: LDS sums for the first W, zeros beyond (their deposits went to atomics)
-    int64_t *dst = a.acc_tet + 10 * (int64_t)T0;
-    const int m = (T1 - T0) * 10;
-    for (int j = threadIdx.x; j < m; j += kBlock) dst[j] = j < W * 10 ? acc[j] : 0;
+    // owned tets: window sums, zeros beyond (their deposits are posted)
+    const int m = T1 - T0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        int64_t *dst = a.acc_tet + (int64_t)k * a.nt + T0;
+        const long long scale = k < 6 ? (long long)a.zq : (long long)a.zq * QH_SCALE;
+        for (int j = threadIdx.x; j < m; j += kBlock) dst[j] = j < W ? scale * acc[k * kWin + j] : 0;
+    }
+    // event counters: crossings, wall hits, lost, posted pieces
     if (threadIdx.x < 4) {
-        unsigned int v = s_cnt[threadIdx.x < 3 ? threadIdx.x : 4];
+        const unsigned int v = s_cnt[1 + threadIdx.x];
         if (v) atomicAdd(&a.counters[(blockIdx.x & (QH_COUNTER_SLOTS - 1)) * 4 + threadIdx.x], (unsigned long long)v);
     }
 }
@@ -444,7 +518,8 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
 template <int OFF>
 __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ lst,
-                                                const int64_t *__restrict__ acc_tet, int64_t *__restrict__ out,
+                                                const int64_t *__restrict__ acc_tet, int64_t nt,
+                                                int64_t *__restrict__ out,
                                                 unsigned nblocks_grid) {
     // grid is padded to a multiple of 8 blocks so the remap is a bijection onto [0, grid)
     const unsigned lb = xcd_block(blockIdx.x, nblocks_grid);
@@ -454,12 +529,66 @@ __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *_
     if (lb != 0xffffffffu && item < nitems) {
         for (int32_t j = ptr[item] + sub; j < ptr[item + 1]; j += 8) {
             int32_t v = lst[j];
-            s += acc_tet[10 * (int64_t)(v >> 3) + OFF + (v & 7)];
+            s += acc_tet[(int64_t)(OFF + (v & 7)) * nt + (v >> 3)];
         }
     }
 #pragma unroll
     for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
     if (sub == 0 && lb != 0xffffffffu && item < nitems) out[item] += s;
+}
+
+// Mailbox m (tets [kMailTets m, kMailTets (m+1))) into acc_tet: each record's 10 values (as
+// in the particle kernel) summed in LDS by tet, then added to the (already written) per-tet
+// sums. One block per mailbox, so every tet has a single writer.
+__global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restrict__ mail_cnt,
+                                                    const int32_t *__restrict__ mail, int32_t zq, int64_t nt,
+                                                    int64_t *__restrict__ acc_tet) {
+    const int o = blockIdx.x;
+    const unsigned int cnt = min(mail_cnt[o], (unsigned)kMailCap);
+    if (cnt == 0) return;
+    __shared__ long long acc[10 * kMailTets];
+    const int T0 = o * kMailTets;
+    const int W = (int)min((int64_t)kMailTets, nt - T0);
+    for (int j = threadIdx.x; j < 10 * kMailTets; j += 256) acc[j] = 0;
+    __syncthreads();
+    const int LE0[6] = {0, 0, 0, 1, 1, 2};
+    const int LE1[6] = {1, 2, 3, 2, 3, 3};
+    for (unsigned int r = threadIdx.x; r < cnt; r += 256) {
+        const int32_t *rec = mail + ((int64_t)o * kMailCap + r) * kRec;
+        const int head = rec[0];
+        const int tt = head & 0x7fffffff;
+        const bool end = head < 0;
+        int P0[4], P1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { P0[j] = rec[1 + j]; P1[j] = rec[5 + j]; }
+        long long v[10];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            v[j] = zq * ((long long)P0[LE0[j]] * P1[LE1[j]] - (long long)P1[LE0[j]] * P0[LE1[j]]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[6 + j] = end ? (long long)zq * QH_SCALE * P1[j] : 0;
+        const int slot = tt - T0;  // in [0, W): records are posted to the mailbox of their tet
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (v[k]) atomic_add_lds(&acc[k * kMailTets + slot], v[k]);
+    }
+    __syncthreads();
+    // all loads of a thread issued before its stores
+    constexpr int kPer = 10 * kMailTets / 256;
+    long long vv[kPer], old[kPer];
+    int64_t at[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int j = threadIdx.x + 256 * u;
+        const int k = j / kMailTets, sl = j - k * kMailTets;
+        vv[u] = sl < W ? acc[j] : 0;
+        at[u] = (int64_t)k * nt + T0 + sl;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) old[u] = vv[u] ? acc_tet[at[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        if (vv[u]) acc_tet[at[u]] = old[u] + vv[u];
 }
 
 // owned tet ranges after a sort: own[b] = tet of the block's first particle, own[0] = 0,
@@ -477,18 +606,25 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     a.geo = c->geo; a.frec = c->frec; a.tnodes = c->tnodes; a.tedges = c->tedges; a.tnbr = c->tnbr;
     a.x = s.x; a.y = s.y; a.z = s.zz; a.vx = s.vx; a.vy = s.vy; a.vz = s.vz;
     a.tet = s.tet; a.pid = s.id; a.own = s.own; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
+    a.mail_cnt = c->mail_cnt; a.mail = c->mail;
     a.hqm = (float)(0.5 * s.qm * c->phys.dt);
     a.dt = (float)c->phys.dt;
     a.zq = s.z;
     a.g = c->g; a.Q = c->Q; a.acc_tet = c->acc_tet; a.counters = c->counters;
     a.species = sidx; a.cap = c->cap_segments; a.seg_count = c->seg_count; a.seg_buf = c->seg_buf;
     dim3 grid((unsigned)((s.n + kChunk - 1) / kChunk));
+    const unsigned nmail = (unsigned)((c->hm.Nt + kMailTets - 1) / kMailTets);
+    hipError_t e = hipMemsetAsync(c->mail_cnt, 0, sizeof(unsigned int) * nmail, c->stream);
+    if (e != hipSuccess) return e;
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
     const HostMesh &m = c->hm;
+    hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(256), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
     unsigned ge = (unsigned)(((m.Ne + 31) / 32 + 7) / 8 * 8), gn = (unsigned)(((m.Nn + 31) / 32 + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_gather<0>, dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet, c->g, ge);
-    hipLaunchKernelGGL(k_gather<6>, dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet, c->Q, gn);
+    hipLaunchKernelGGL(k_gather<0>, dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet, m.Nt, c->g,
+                       ge);
+    hipLaunchKernelGGL(k_gather<6>, dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet, m.Nt, c->Q,
+                       gn);
     return hipGetLastError();
 }
 

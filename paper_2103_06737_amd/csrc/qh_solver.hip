@@ -96,7 +96,8 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *__restri
 }
 
 // init: r = b - A x, z = D^-1 r, p_old = 0; partials of r.z, r.r, b.b
-__global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *__restrict__ ptr,
+__global__ void __launch_bounds__(kThreads) k_cg_init(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                      const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ x,
@@ -104,24 +105,20 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(int32_t n, const int32_t *
                                                       const double *__restrict__ dinv,
                                                       double *__restrict__ r, double *__restrict__ z,
                                                       double *__restrict__ p_old, double *__restrict__ part) {
-    const int sub = threadIdx.x % kLpr;
-    const Rows rr_ = block_rows(n);
+    __shared__ double prod[kTileCap];
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * x[col[j]];
-        s = wave_sum_lpr(s);
-        if (sub == 0) {
-            double rr = b[row] - s;
-            double zz = rr * dinv[row];
-            r[row] = rr;
-            z[row] = zz;
-            p_old[row] = 0.0;
-            acc[0] += rr * zz;
-            acc[1] += rr * rr;
-            acc[2] += b[row] * b[row];
-        }
-    }
+    tile_spmv(tiles, ntiles, ptr, col, val, x, prod, [&](int32_t row) { return make_double2(b[row], dinv[row]); },
+              [&](int32_t row, double s, double2 bd) {
+        const double bb = bd.x;
+        const double rr = bb - s;
+        const double zz = rr * bd.y;
+        r[row] = rr;
+        z[row] = zz;
+        p_old[row] = 0.0;
+        acc[0] += rr * zz;
+        acc[1] += rr * rr;
+        acc[2] += bb * bb;
+    });
     write_partials<3>(acc, part);
 }
 
@@ -148,7 +145,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict_
 // r.r from its partials, convergence test, beta. Then, with w = A z (the only gathered
 // vector), p = z + beta p and q = A p = w + beta q in place (own rows only), and the
 // partials of p.q. Gathering one vector instead of z and p halves the scattered loads.
-__global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int2 *__restrict__ tiles, int32_t ntiles,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) k_cg_spmv(int32_t n, const int2 *__restrict__ tiles, int32_t ntiles,
                                                       const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
@@ -178,7 +175,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_spmv(int32_t n, const int2 *__r
         scal[S_RZ + 1] = scal[S_RZ];
     }
     double acc[1] = {0.0};
-    tile_spmv(tiles, ntiles, ptr, col, val, z, prod, [&](int32_t row, double s) {
+    tile_spmv(tiles, ntiles, ptr, col, val, z, prod, [&](int32_t) { return 0; },
+              [&](int32_t row, double s, int) {
         const double pn = k > 0 ? z[row] + beta * p[row] : z[row];
         const double qn = k > 0 ? s + beta * q[row] : s;
         p[row] = pn;
@@ -239,35 +237,41 @@ __global__ void k_diag_inv(int32_t n, const int32_t *__restrict__ ptr, const int
     dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
 }
 
+// A = [*eps] + tau S and the right-hand-side matrix [*eps] - tau S on one pattern
 __global__ void k_axpy_vals(int64_t n, const double *__restrict__ a, const double *__restrict__ s, double tau,
-                            double *__restrict__ out) {
+                            double *__restrict__ out, double *__restrict__ out_m) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = a[i] + tau * s[i];
+    if (i < n) {
+        out[i] = a[i] + tau * s[i];
+        out_m[i] = a[i] - tau * s[i];
+    }
 }
 
-// rhs_i = sum_j (2 Meps_ij - A_ij) e_j + dt u_b sum_f CMb_if b_f - u_q g[int_edge_i]
-__global__ void __launch_bounds__(kThreads) k_edge_rhs(int32_t n, const int32_t *__restrict__ ptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const double *__restrict__ aval,
-                                                       const double *__restrict__ mval,
-                                                       const double *__restrict__ e,
-                                                       const int32_t *__restrict__ cptr,
-                                                       const int32_t *__restrict__ ccol,
-                                                       const double *__restrict__ cval,
-                                                       const int64_t *__restrict__ b,
-                                                       const int64_t *__restrict__ g,
-                                                       const int32_t *__restrict__ int_edges, double dtub,
-                                                       double u_q, double *__restrict__ rhs) {
-    const int sub = threadIdx.x % kLpr;
-    const Rows rr_ = block_rows(n);
-    const int64_t row = rr_.begin + threadIdx.x / kLpr;
-    if (row >= rr_.end) return;
-    double s = 0.0, t = 0.0;
-    for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += (2.0 * mval[j] - aval[j]) * e[col[j]];
-    for (int32_t j = cptr[row] + sub; j < cptr[row + 1]; j += kLpr) t += cval[j] * (double)b[ccol[j]];
-    s = wave_sum_lpr(s);
-    t = wave_sum_lpr(t);
-    if (sub == 0) rhs[row] = s + dtub * t - u_q * (double)g[int_edges[row]];
+// Edge right-hand side in two tiled passes over the interior edges:
+//   rhs_i = sum_j ([*eps] - tau S)_ij e_j - u_q g[int_edge_i]          (k_edge_rhs_e)
+//   rhs_i += dt u_b sum_f (C^T [*mu^-1])_if b_f                          (k_edge_rhs_b)
+__global__ void __launch_bounds__(kThreads) k_edge_rhs_e(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                         const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ mval,
+                                                         const double *__restrict__ e,
+                                                         const int64_t *__restrict__ g,
+                                                         const int32_t *__restrict__ int_edges, double u_q,
+                                                         double *__restrict__ rhs) {
+    __shared__ double prod[kTileCap];
+    tile_spmv(tiles, ntiles, ptr, col, mval, e, prod, [&](int32_t row) { return g[int_edges[row]]; },
+              [&](int32_t row, double s, int64_t gi) { rhs[row] = s - u_q * (double)gi; });
+}
+
+__global__ void __launch_bounds__(kThreads) k_edge_rhs_b(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                         const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ cval,
+                                                         const int64_t *__restrict__ b, double dtub,
+                                                         double *__restrict__ rhs) {
+    __shared__ double prod[kTileCap];
+    tile_spmv(tiles, ntiles, ptr, col, cval, b, prod, [&](int32_t row) { return rhs[row]; },
+              [&](int32_t row, double t, double r0) { rhs[row] = r0 + dtub * t; });
 }
 
 // Gauss residual rg = rho - G^T [*eps] e on interior nodes, rho = u_q (Q_bg - Q);
@@ -356,24 +360,20 @@ __global__ void k_faraday_b(int64_t nf, const int32_t *__restrict__ fe, const in
 }
 
 // ||b - A x||^2 and ||b||^2 (partials)
-__global__ void __launch_bounds__(kThreads) k_true_res(int32_t n, const int32_t *__restrict__ ptr,
+__global__ void __launch_bounds__(kThreads) k_true_res(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                       const int32_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val,
                                                        const double *__restrict__ x,
                                                        const double *__restrict__ b, double *__restrict__ part) {
-    const int sub = threadIdx.x % kLpr;
-    const Rows rr_ = block_rows(n);
+    __shared__ double prod[kTileCap];
     double acc[2] = {0.0, 0.0};
-    for (int64_t row = rr_.begin + threadIdx.x / kLpr; row < rr_.end; row += kThreads / kLpr) {
-        double s = 0.0;
-        for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += kLpr) s += val[j] * x[col[j]];
-        s = wave_sum_lpr(s);
-        if (sub == 0) {
-            double r = b[row] - s;
-            acc[0] += r * r;
-            acc[1] += b[row] * b[row];
-        }
-    }
+    tile_spmv(tiles, ntiles, ptr, col, val, x, prod, [&](int32_t row) { return b[row]; },
+              [&](int32_t row, double s, double bb) {
+        const double r = bb - s;
+        acc[0] += r * r;
+        acc[1] += bb * bb;
+    });
     write_partials<2>(acc, part);
 }
 
@@ -421,25 +421,28 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     // partials: [0, 4K) init / update (slot 0 r.z with Jacobi, 1 r.r, 2 b.b), [4K, 5K) products,
     // [5K, 6K) r.z of the learned preconditioner
     double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks, *ppart = w.partial + 5 * kMaxBlocks;
-    const unsigned gr = grid_rows(w.n), ge = grid_elems(w.n), gt = tile_grid(M.ntiles);
+    const unsigned ge = grid_elems(w.n), gt = tile_grid(M.ntiles);
     const unsigned gp = learned ? qh_prec_grid(c) : 0;
     int t0 = qh_tbeg(c);
-    hipLaunchKernelGGL(k_cg_init, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, w.dinv,
-                       w.r, w.z, w.p0, upart);
+    hipLaunchKernelGGL(k_cg_init, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, w.x,
+                       w.b, w.dinv, w.r, w.z, w.p0, upart);
     if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, nullptr));
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr,
-                       learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gr, w.scal,
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt,
+                       learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gt, w.scal,
                        w.flags, tol * tol, abs_thr2_dev);
     qh_tend(c, t0, QK_CG_INIT);
     QH_HIP(c, hipGetLastError());
     if (check_every <= 0) check_every = 8;
     int32_t hflags[2] = {0, 0};
     int it = 0;
-    int m_up = (int)gr;
+    int m_up = (int)gt;
     QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
+    // iterations after convergence return at once on the device; sizing the first batch from
+    // the previous solve avoids most of them and most host reads of the flag
+    int first = w.last_iters[learned ? 1 : 0];
     while (it < max_it && !hflags[0]) {
-        int batch = std::min(check_every, max_it - it);
+        int batch = std::min(it == 0 && first > 0 ? first : check_every, max_it - it);
         for (int k = it; k < it + batch; ++k) {
             int par = k & 1;
             int ta = qh_tbeg(c);
@@ -471,14 +474,16 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     out.iters = hflags[1];
     // true residual, recomputed
     int tr = qh_tbeg(c);
-    hipLaunchKernelGGL(k_true_res, dim3(gr), dim3(kThreads), 0, c->stream, w.n, M.ptr, M.col, M.val, w.x, w.b, upart);
-    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gr, w.scal + 8);
+    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, w.x,
+                       w.b, upart);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + 8);
     qh_tend(c, tr, QK_TRUE_RES);
     double res2[2];
     QH_HIP(c, hipMemcpyAsync(res2, w.scal + 8, sizeof(res2), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
     out.res = res2[1] > 0 ? sqrt(res2[0] / res2[1]) : 0.0;
     out.converged = hflags[0] != 0 && out.res == out.res;
+    if (out.converged) w.last_iters[learned ? 1 : 0] = out.iters;
     return QH_OK;
 }
 
@@ -499,17 +504,16 @@ bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles) {
 hipError_t launch_assemble_A(qh_ctx *c, double tau) {
     int64_t nnz = c->A.nnz;
     hipLaunchKernelGGL(k_axpy_vals, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, c->stream, nnz, c->A.val2,
-                       c->A_S, tau, c->A.val);
+                       c->A_S, tau, c->A.val, c->A_rhs);
     return hipGetLastError();
 }
 
 hipError_t launch_edge_rhs(qh_ctx *c) {
-    int32_t n = c->A.n;
-    // one row per lane group: a grid of ceil(n / 32) blocks, padded to a multiple of 8
-    unsigned gr = (unsigned)((((int64_t)n * kLpr + kThreads - 1) / kThreads + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_edge_rhs, dim3(gr), dim3(kThreads), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val, c->A.val2,
-                       c->cge.x, c->CMb.ptr, c->CMb.col, c->CMb.val, c->b, c->g, c->int_edges,
-                       c->phys.dt * c->phys.u_b, c->phys.u_q, c->cge.b);
+    hipLaunchKernelGGL(k_edge_rhs_e, dim3(tile_grid(c->A.ntiles)), dim3(kThreads), 0, c->stream, c->A.tiles,
+                       c->A.ntiles, c->A.ptr, c->A.col, c->A_rhs, c->cge.x, c->g, c->int_edges, c->phys.u_q,
+                       c->cge.b);
+    hipLaunchKernelGGL(k_edge_rhs_b, dim3(tile_grid(c->CMb.ntiles)), dim3(kThreads), 0, c->stream, c->CMb.tiles,
+                       c->CMb.ntiles, c->CMb.ptr, c->CMb.col, c->CMb.val, c->b, c->phys.dt * c->phys.u_b, c->cge.b);
     return hipGetLastError();
 }
 
@@ -541,9 +545,9 @@ hipError_t launch_faraday(qh_ctx *c) {
 }
 
 hipError_t launch_true_residual(qh_ctx *c, const DevCsr &M, const double *x, const double *b, double *out2) {
-    unsigned gr = grid_rows(M.n);
-    hipLaunchKernelGGL(k_true_res, dim3(gr), dim3(kThreads), 0, c->stream, M.n, M.ptr, M.col, M.val, x, b,
+    const unsigned gt = tile_grid(M.ntiles);
+    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, x, b,
                        c->cge.partial);
-    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, c->cge.partial, (int)gr, out2);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, c->cge.partial, (int)gt, out2);
     return hipGetLastError();
 }

@@ -14,7 +14,7 @@
 
 constexpr int kTileThreads = 256;
 constexpr int kTileRows = kTileThreads;  // one row per thread in the summing pass
-constexpr int kTileCap = 4096;           // products per tile (32 KB of LDS)
+constexpr int kTileCap = 2048;           // products per tile (16 KB of LDS)
 constexpr int kTileUnroll = 8;           // product loads issued together per thread
 
 // Tile starts {first row, first entry}; tiles[ntiles] = {n, nnz}. Rows longer than kTileCap
@@ -33,23 +33,31 @@ __device__ __forceinline__ void tile_range(int32_t ntiles, int32_t &tb, int32_t 
     if (tb > ntiles) tb = ntiles;
 }
 
-// For every row of this block's tiles: epi(row, sum_j a_row,j x_j). All threads of the block
+// For every row of this block's tiles: epi(row, sum_j a_row,j x_j, pre(row)) (x converted to
+// FP64). pre(row) loads what the epilogue needs from the row's own entries; it is issued with
+// the tile's entry loads, and the next tile's header is fetched one tile ahead, so a tile costs
+// two dependent memory round trips (entries, then gathered vector). All threads of the block
 // must call it (it synchronises the block).
-template <typename VT, typename Epi>
+template <typename VT, typename XT, typename Pre, typename Epi>
 __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
                                           const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                          const VT *__restrict__ val, const double *__restrict__ x,
-                                          double *prod /* LDS, kTileCap */, Epi &&epi) {
+                                          const VT *__restrict__ val, const XT *__restrict__ x,
+                                          double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
+    using PF = decltype(pre(0));
     int32_t tb, te;
     tile_range(ntiles, tb, te);
+    if (tb >= te) return;  // the same for every thread of the block
     const int tid = threadIdx.x;
+    int2 t0 = tiles[tb], t1 = tiles[tb + 1];
     for (int32_t ti = tb; ti < te; ++ti) {
-        const int2 t0 = tiles[ti], t1 = tiles[ti + 1];
+        const int2 t2 = tiles[ti + 2 <= ntiles ? ti + 2 : ntiles];
         const int32_t row = t0.x + tid;
         int32_t js = 0, je = 0;
+        PF pf{};
         if (row < t1.x) {
             js = ptr[row] - t0.y;
             je = ptr[row + 1] - t0.y;
+            pf = pre(row);
         }
         const int32_t cnt = t1.y - t0.y;  // >= 1 whenever the tile has rows with entries
         for (int32_t b = 0; b < cnt; b += kTileUnroll * kTileThreads) {
@@ -64,7 +72,7 @@ __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_
             }
             double xv[kTileUnroll];
 #pragma unroll
-            for (int u = 0; u < kTileUnroll; ++u) xv[u] = x[c[u]];
+            for (int u = 0; u < kTileUnroll; ++u) xv[u] = (double)x[c[u]];
 #pragma unroll
             for (int u = 0; u < kTileUnroll; ++u) {
                 const int32_t j = b + u * kTileThreads + tid;
@@ -75,9 +83,11 @@ __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_
         if (row < t1.x) {
             double s = 0.0;
             for (int32_t j = js; j < je; ++j) s += prod[j];
-            epi(row, s);
+            epi(row, s, pf);
         }
         __syncthreads();
+        t0 = t1;
+        t1 = t2;
     }
 }
 
