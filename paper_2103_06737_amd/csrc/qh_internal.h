@@ -107,6 +107,7 @@ struct LearnedPrec {
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;
+    uint16_t *gval_h = nullptr, *tval_h = nullptr;  // BF16 copies of G and G^T for the application
     double *y = nullptr;
     float *w = nullptr, *best_w = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
     float *gpart = nullptr, *W = nullptr, *AW = nullptr, *V = nullptr;

@@ -147,20 +147,27 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
     }
 }
 
+// G^T values out[k] = in[src[k]], and BF16 copies of G and G^T for the application
 __global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const float *__restrict__ in,
-                             float *__restrict__ out) {
+                             float *__restrict__ out, uint16_t *__restrict__ in_h, uint16_t *__restrict__ out_h) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) out[k] = in[src[k]];
+    if (k < n) {
+        const float v = in[src[k]];
+        out[k] = v;
+        out_h[k] = (uint16_t)f2bf(v);
+        in_h[k] = (uint16_t)f2bf(in[k]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
 // Preconditioner application: y = G r (rows of G), then z = G^T y (rows of G^T) with the
-// partials of r.z, both as tiled products (each block a contiguous, XCD-grouped range of row
+// partials of r.z, from BF16 copies of G and G^T (the network's own precision; the products
+// and sums are FP64, so M = G^T G stays one fixed SPD operator), both as tiled products (each block a contiguous, XCD-grouped range of row
 // tiles). Grids are multiples of 8 blocks, at most 2048.
 template <bool DOT>
 __global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict__ tiles, int32_t ntiles,
                                                          const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                         const int32_t *__restrict__ col, const uint16_t *__restrict__ val,
                                                          const double *__restrict__ in, double *__restrict__ out,
                                                          const double *__restrict__ r, double *__restrict__ part,
                                                          const int32_t *__restrict__ done) {
@@ -499,7 +506,8 @@ int qh_learned_setup(qh_ctx *c) {
         if ((rc = qh_alloc(c, &L.gptr, n + 1)) || (rc = qh_alloc(c, &L.gcol, nnz)) || (rc = qh_alloc(c, &L.grow, nnz)) ||
             (rc = qh_alloc(c, &L.tptr, n + 1)) || (rc = qh_alloc(c, &L.tcol, nnz)) || (rc = qh_alloc(c, &L.tsrc, nnz)) ||
             (rc = qh_alloc(c, &L.feats, nnz * kF)) || (rc = qh_alloc(c, &L.gscale, nnz)) ||
-            (rc = qh_alloc(c, &L.gval, nnz)) || (rc = qh_alloc(c, &L.tval, nnz)) || (rc = qh_alloc(c, &L.o, nnz)) ||
+            (rc = qh_alloc(c, &L.gval, nnz)) || (rc = qh_alloc(c, &L.tval, nnz)) ||
+            (rc = qh_alloc(c, &L.gval_h, nnz)) || (rc = qh_alloc(c, &L.tval_h, nnz)) || (rc = qh_alloc(c, &L.o, nnz)) ||
             (rc = qh_alloc(c, &L.d_o, nnz)) || (rc = qh_alloc(c, &L.y, n)) || (rc = qh_alloc(c, &L.w, 5313)) ||
             (rc = qh_alloc(c, &L.adam_m, 5313)) || (rc = qh_alloc(c, &L.adam_v, 5313)) ||
             (rc = qh_alloc(c, &L.grad, 5313)) || (rc = qh_alloc(c, &L.loss, 4)))
@@ -610,7 +618,7 @@ int qh_learned_factor(qh_ctx *c) {
     hipLaunchKernelGGL(k_mlp_factor, dim3(mlp_grid(L.nnz)), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.grow,
                        L.gcol, L.gscale, L.nnz, L.o, L.gval);
     hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((L.nnz + 255) / 256)), dim3(256), 0, c->stream, L.nnz, L.tsrc,
-                       L.gval, L.tval);
+                       L.gval, L.tval, L.gval_h, L.tval_h);
     QH_HIP(c, hipGetLastError());
     L.factor_valid = true;
     return QH_OK;
@@ -623,9 +631,9 @@ unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
     hipLaunchKernelGGL(k_prec_g<false>, dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, L.gcol, L.gval, r, L.y, (const double *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, L.gcol, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(k_prec_g<true>, dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, L.tcol, L.tval, L.y, z, r, part, done);
+                       L.nttiles, L.tptr, L.tcol, L.tval_h, L.y, z, r, part, done);
     return hipGetLastError();
 }
 

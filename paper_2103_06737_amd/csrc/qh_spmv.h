@@ -21,6 +21,11 @@ constexpr int kTileUnroll = 8;           // product loads issued together per th
 // entries are not supported (returns false).
 bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles);
 
+// Entry values: FP64, FP32, or BF16 (stored as its 16 bits), all widened to FP64.
+__device__ __forceinline__ double tile_val(double v) { return v; }
+__device__ __forceinline__ double tile_val(float v) { return (double)v; }
+__device__ __forceinline__ double tile_val(uint16_t h) { return (double)__uint_as_float((unsigned)h << 16); }
+
 // Contiguous tile range of this block; the block index is remapped so that each of the 8
 // XCDs (which receive blocks round-robin) covers one contiguous span of tiles. The grid must
 // be a multiple of 8 blocks.
@@ -76,7 +81,7 @@ __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_
 #pragma unroll
             for (int u = 0; u < kTileUnroll; ++u) {
                 const int32_t j = b + u * kTileThreads + tid;
-                if (j < cnt) prod[j] = (double)v[u] * xv[u];
+                if (j < cnt) prod[j] = tile_val(v[u]) * xv[u];
             }
         }
         __syncthreads();
