@@ -1,0 +1,149 @@
+"""The HIP path at full workload size, in the launch configuration the benchmark times (needs an
+MI355X). The oracle checks what it can afford at this size: every integer deposit (re-deposited
+from the GPU's own pieces, bit for bit), continuity and D b on the host, sampled particles pushed
+one by one, and the field update step by step: the edge right-hand side, the solution's residual
+with its own FP64 matrix, the Gauss-law residual and the integer Faraday update.
+
+Workloads (sizes as quoted): 64^3 Kuhn cube with 16M electrons, full implicit cycle with the
+learned preconditioner; 32^3 Kuhn cube with a 1M-electron beam in frozen random fields for 200
+steps.
+"""
+import numpy as np
+import pytest
+
+import qh_inputs as qi
+
+from .gpu_setup import S, gpu_context, oracle_fields, oracle_setup
+
+pytestmark = pytest.mark.gpu
+
+U_B = 2.0 ** -56
+
+
+@pytest.fixture(scope="module")
+def c3():
+    cfg = qi.CONFIGS["c3"]
+    mesh = qi.make_mesh(cfg)
+    parts = qi.make_particles(mesh, cfg)
+    cx, op, po = oracle_setup(mesh)
+    return cfg, mesh, parts, cx, op, po
+
+
+def test_c3_full_cycle(c3):
+    import paper_2103_06737_amd as qh
+    from oracle.field import FieldOracle
+    cfg, mesh, parts, cx, op, po = c3
+    dt, weight = cfg["dt"], cfg["weight"]
+    u_q = qi.QE * weight * 2.0 ** -40
+    ctx = gpu_context(mesh, dt, weight=weight)
+    ctx.fields_init_synthetic(qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), cfg["sigma_e"], cfg["bz"],
+                              cfg["sigma_b"])
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = parts["e"]
+    n = tet.size
+    assert n == 16_000_000
+    ctx.particles_upload(sid, x, v, tet)
+    ctx.charge_background(1)
+    ctx.precond_train(steps=60, lr=3e-3, seed=1, validate_every=0)
+    e0, b0 = ctx.fields_download()
+    _, Q0 = ctx.deposits_download()
+    ctx.capture_segments(int(1.5 * n))
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1)
+    st = ctx.pic_step(params)[0]
+    assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+    assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8
+    assert st["crossings"] > 100_000
+    g, Q1 = ctx.deposits_download()
+    e1, b1 = ctx.fields_download()
+    xg, vg, tg = ctx.particles_download(sid)
+
+    # continuity on the host, bit for bit
+    assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+    # the GPU's own pieces, re-deposited by the oracle, give its g and Q bit for bit
+    nseg, seg = ctx.segments_download()
+    assert nseg == seg["tet"].size and nseg >= n
+    g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], -np.ones(nseg), np.zeros(0),
+                              np.zeros((0, 4)), np.zeros(0))
+    assert np.array_equal(g_re, g)
+    order = np.lexsort((seg["seq"], seg["pid"]))
+    pid = seg["pid"][order]
+    last = np.r_[pid[1:] != pid[:-1], True]
+    assert last.sum() == n
+    _, Q_re = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                              seg["tet"][order][last], seg["lam1"][order][last], -np.ones(n))
+    assert np.array_equal(Q_re, Q1)
+    assert (seg["lam0"].sum(1) == S).all() and (seg["lam1"].sum(1) == S).all()
+
+    # sampled particles pushed one by one by the oracle through the same start fields
+    idx = np.random.default_rng(7).choice(n, 4096, replace=False)
+    orc = po.push(e0, b0 * U_B, x[idx], v[idx], tet[idx], -qi.QE / qi.ME, dt, -1)
+    same = tg[idx] == orc["tet"]
+    assert same.mean() > 0.999
+    assert np.abs(xg[idx] - orc["x"]).max(axis=1)[same].max() < 1e-5
+    assert (np.abs(vg[idx] - orc["v"]).max(axis=1)[same] / np.abs(orc["v"]).max()).max() < 1e-5
+
+    # the field update of this step, piece by piece against the oracle's FP64 operators:
+    # right-hand side of the edge system (same sums, another order), the solution's residual,
+    # the discrete Gauss law after the correction, and the integer Faraday update bit for bit
+    fo = FieldOracle(cx, op, dt)
+    rhs, sol = ctx.edge_system_download()
+    b_real, g_real = b0.astype(np.float64) * U_B, g.astype(np.float64) * u_q
+    rhs_o = fo.rhs(e0, b_real, g_real)
+    # the terms cancel strongly (a uniform B has no discrete curl): bound the difference row by
+    # row by the rounding of sums of |terms| (64 ulps of the absolute sum)
+    terms = (abs(fo.Bm) @ np.abs(e0) + dt * (abs(op.CtMmu) @ np.abs(b_real)) + np.abs(g_real))[cx.int_edges]
+    assert (np.abs(rhs - rhs_o) <= 64 * np.finfo(float).eps * terms).all()
+    assert np.linalg.norm(fo.A @ sol - rhs_o) <= 1.001e-8 * np.linalg.norm(rhs_o)
+    rho = u_q * (Q0 - Q1).astype(np.float64)[cx.int_nodes]   # Q_bg = Q0
+    assert fo.gauss_error(e1, rho) <= 1.01e-8
+    u = np.rint((0.5 * dt / U_B) * (e1 + e0)).astype(np.int64)
+    assert np.array_equal(b1, b0 - cx.C @ u)
+    assert np.array_equal(cx.D @ b1, cx.D @ b0)
+
+
+def test_c2_beam_200_steps():
+    """1M-electron beam in frozen random fields, 200 steps: continuity and D b every step on the
+    device, FP32 positions within 1e-5 of the box size of the FP64 oracle's after 200 steps.
+
+    Tie-consistent replay: E jumps across faces, so a particle that the two arithmetics place on
+    different sides of a face would see different fields from then on. After each step the
+    oracle adopts the GPU's tet when the gap is explained by the FP32/FP64 position difference
+    d of that particle: its own point lies inside the GPU's tet up to |grad lambda| d (twice,
+    plus 1e-6 for the FP32 point itself). Likewise at the walls (the planes of the unit cube): a
+    particle that ends the step within 1e-5 of a wall may be reflected by one arithmetic and
+    not (yet) by the other; the oracle then takes the GPU's sign of that velocity component."""
+    cfg = qi.CONFIGS["c2"]
+    mesh = qi.make_mesh(cfg)
+    cx, op, po = oracle_setup(mesh)
+    e, b = oracle_fields(cx, cfg, U_B)
+    x, v, tet = qi.make_particles(mesh, cfg)["e"]
+    assert tet.size == 1_000_000
+    ctx = gpu_context(mesh, cfg["dt"])
+    ctx.fields_upload(e, b)
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    ctx.particles_upload(sid, x, v, tet)
+    xo, vo, to = x.astype(np.float64), v.astype(np.float64), tet.astype(np.int64)
+    params = ctx.step_params(sort_every=20, verify=1)
+    crossings = 0
+    for _ in range(200):
+        st = ctx.pic_step(params)[0]
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+        crossings += st["crossings"]
+        out = po.push(e, b * U_B, xo, vo, to, -qi.QE / qi.ME, cfg["dt"], -1)
+        xo, vo, to = out["x"], out["v"], out["tet"]
+        xg, vg, tg = ctx.particles_download(sid)
+        near_wall = np.minimum(xo, 1.0 - xo) <= 1e-5
+        flip = near_wall & (np.sign(vg) != np.sign(vo)) & (np.abs(np.abs(vg) - np.abs(vo)) <= 1e-3 * np.abs(vo))
+        vo[flip] = -vo[flip]
+        diff = np.flatnonzero(tg != to)
+        if diff.size:
+            M = op.Minv[tg[diff]]
+            lam = M[:, :, 0] + np.einsum("ijk,ik->ij", M[:, :, 1:], xo[diff])
+            grad = np.linalg.norm(M[:, :, 1:], axis=2).max(axis=1)
+            band = 2.0 * grad * np.abs(xg[diff] - xo[diff]).max(axis=1) + 1e-6
+            tie = lam.min(axis=1) >= -band
+            to[diff[tie]] = tg[diff[tie]]
+    assert crossings > 1_000_000
+    xg, vg, tg = ctx.particles_download(sid)
+    assert np.array_equal(tg, to)
+    assert np.abs(xg - xo).max() <= 1e-5
