@@ -29,7 +29,8 @@ import qh_inputs as qi  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {"c3": "64^3 Kuhn cube, 16M-electron uniform plasma, full implicit cycle",
-             "c2": "32^3 Kuhn cube, 1M-electron beam in frozen random fields"}
+             "c2": "32^3 Kuhn cube, 1M-electron beam in frozen random fields",
+             "c5": "96^3 Kuhn cube graded toward z=0 (ratio 1.05), 32M electrons + 32M ions, full implicit cycle"}
 
 
 def log(*a):

@@ -6,7 +6,7 @@ with its own FP64 matrix, the Gauss-law residual and the integer Faraday update.
 
 Workloads (sizes as quoted): 64^3 Kuhn cube with 16M electrons, full implicit cycle with the
 learned preconditioner; 32^3 Kuhn cube with a 1M-electron beam in frozen random fields for 200
-steps.
+steps; the 96^3 graded mesh with two species (particle count reduced to 2M + 2M).
 """
 import numpy as np
 import pytest
@@ -147,3 +147,41 @@ def test_c2_beam_200_steps():
     xg, vg, tg = ctx.particles_download(sid)
     assert np.array_equal(tg, to)
     assert np.abs(xg - xo).max() <= 1e-5
+
+
+def test_c5_graded_two_species():
+    """96^3 mesh graded toward z = 0 (5.3M tets), electrons and ions (2M each here, the full
+    workload's mesh and species mix), full cycle with Jacobi and then the learned
+    preconditioner: continuity (on the device every step, and on the host), D b, residuals,
+    and fewer edge iterations with the trained network."""
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    cfg = qi.CONFIGS["c5"]
+    mesh = qi.make_mesh(cfg)
+    n_e = 2_000_000
+    parts = qi.make_particles(mesh, cfg, n_e=n_e)
+    weight = cfg["weight"] * cfg["n_e"] / n_e
+    ctx = gpu_context(mesh, cfg["dt"], weight=weight)
+    mi = ctx.mesh_info()
+    assert mi.n_tets == 6 * 96 ** 3
+    ctx.fields_init_synthetic(qi.white(mi.n_edges, 0, 3), qi.white(mi.n_edges, 0, 5), cfg["sigma_e"], cfg["bz"],
+                              cfg["sigma_b"])
+    for name, (x, v, tet) in parts.items():
+        qm, z = (-qi.QE / qi.ME, -1) if name == "e" else (qi.QE / qi.MI, 1)
+        ctx.particles_upload(ctx.species_add(qm, z), x, v, tet)
+    ctx.charge_background(1)
+    cx = Complex(mesh.xyz, mesh.tets)
+    iters = {}
+    for pc in (qh.PC_JACOBI, qh.PC_LEARNED):
+        if pc == qh.PC_LEARNED:
+            ctx.precond_train(steps=60, lr=3e-3, seed=1, validate_every=0)
+        params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=pc, sort_every=20, verify=1)
+        for _ in range(2):
+            _, Q0 = ctx.deposits_download()
+            st = ctx.pic_step(params)[0]
+            g, Q1 = ctx.deposits_download()
+            assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+            assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8
+            assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+        iters[pc] = st["edge_iters"]
+    assert iters[qh.PC_LEARNED] < 0.75 * iters[qh.PC_JACOBI]
