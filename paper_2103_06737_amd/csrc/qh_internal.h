@@ -111,7 +111,7 @@ struct LearnedPrec {
     double *y = nullptr;
     float *w = nullptr, *best_w = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
     float *gpart = nullptr, *W = nullptr, *AW = nullptr, *V = nullptr;
-    double *tpart = nullptr, *lpart = nullptr, *loss = nullptr;
+    double *tpart = nullptr, *lpart = nullptr, *loss = nullptr, *gpart2 = nullptr;
     int32_t adam_t = 0;
 };
 

@@ -39,6 +39,13 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// Orders this wave's LDS accesses (a staging area private to one wave needs no block barrier:
+// the wave's LDS instructions execute in program order once the compiler keeps that order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
 __device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
 
@@ -285,11 +292,19 @@ __global__ void __launch_bounds__(256) k_kaporin_grad(int64_t nnz, int32_t n, co
     if (threadIdx.x == 0) lpart[blockIdx.x] = sh[0];
 }
 
-__global__ void k_loss_finish(const double *__restrict__ lpart, int32_t m, int32_t n, double *loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one block of 256: strided per-thread sums, then a tree (fixed order)
+__global__ void __launch_bounds__(256) k_loss_finish(const double *__restrict__ lpart, int32_t m, int32_t n,
+                                                     double *loss) {
+    __shared__ double sh[256];
     double s = 0.0;
-    for (int32_t b = 0; b < m; ++b) s += lpart[b];
-    loss[0] = log(loss[1]) - 2.0 / (double)n * s;
+    for (int32_t b = threadIdx.x; b < m; b += 256) s += lpart[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = log(loss[1]) - 2.0 / (double)n * sh[0];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -317,10 +332,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
             gb1[a][b] = gb2[a][b] = gw3[a][b] = 0.f;
         }
     }
-    // all waves of a block take the same number of trips (tiles past the end contribute zero),
-    // so the block barriers below are uniform
-    for (int64_t tb = blockIdx.x; tb * kWaves * 16 < nnz; tb += gridDim.x) {
-        const int64_t e0 = (tb * kWaves + wv) * 16;
+    // the LDS staging area tr[wv] belongs to this wave alone: wave-level ordering suffices
+    const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
         f32x4 z1[4], z2[4];
         bf16x4 h1b[4];
         (void)tile_forward(F, feats, e0, nnz, z1, z2, h1b);
@@ -361,7 +375,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
                 tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz2b[mb][j];
                 tr[wv][1][16 * mb + 4 * g + j][r] = (unsigned short)h1b[mb][j];
             }
-        __syncthreads();
+        wave_lds_sync();
         // dW2[o][i] += sum_e dZ2^T[o][e] H1^T[i][e]: A = dZ2^T (o x e), B = H1 (e x i)
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
@@ -376,13 +390,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
                 gW2[ob][ib] = mfma(a, b, gW2[ob][ib]);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         // dW1[o][f] += sum_e dZ1^T[o][e] X[e][f]: stage dZ1^T; B = X (e x f) from memory
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
             for (int j = 0; j < 4; ++j) tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz1b[mb][j];
-        __syncthreads();
+        wave_lds_sync();
         bf16x4 xb;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -396,7 +410,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
             for (int j = 0; j < 4; ++j) a[j] = (short)tr[wv][0][16 * ob + r][4 * g + j];
             gW1[ob] = mfma(a, xb, gW1[ob]);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
     // wave partials: C tiles directly; vector terms summed over the 16 entry lanes
     float *out = gpart + wave * 5313;
@@ -432,11 +446,23 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
 }
 
 // Sum of the wave partials in a fixed order (one thread per parameter).
-__global__ void k_grad_reduce(const float *__restrict__ gpart, int64_t nwaves, float *__restrict__ grad) {
+// Sum of the per-wave partial gradients in two fixed-order passes: chunk c of the waves
+// (blockIdx.y) into part2[c][k], then the kGradChunks chunks per parameter.
+constexpr int kGradChunks = 64;
+__global__ void k_grad_reduce(const float *__restrict__ gpart, int64_t nwaves, double *__restrict__ part2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 5313) return;
+    const int64_t per = (nwaves + kGradChunks - 1) / kGradChunks;
+    const int64_t w0 = (int64_t)blockIdx.y * per, w1 = w0 + per < nwaves ? w0 + per : nwaves;
+    double s = 0.0;
+    for (int64_t wv = w0; wv < w1; ++wv) s += gpart[wv * 5313 + k];
+    part2[(int64_t)blockIdx.y * 5313 + k] = s;
+}
+__global__ void k_grad_finish(const double *__restrict__ part2, float *__restrict__ grad) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 5313) return;
     double s = 0.0;
-    for (int64_t wv = 0; wv < nwaves; ++wv) s += gpart[wv * 5313 + k];
+    for (int c = 0; c < kGradChunks; ++c) s += part2[(int64_t)c * 5313 + k];
     grad[k] = (float)s;
 }
 
@@ -647,7 +673,8 @@ int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad) {
         if ((rc = qh_alloc(c, &L.W, (int64_t)n * kP)) || (rc = qh_alloc(c, &L.AW, (int64_t)n * kP)) ||
             (rc = qh_alloc(c, &L.tpart, 2048 * kP)) ||
             (rc = qh_alloc(c, &L.lpart, (L.nnz + 255) / 256)) ||
-            (rc = qh_alloc(c, &L.gpart, (int64_t)mlp_grid(L.nnz) * kWaves * 5313)))
+            (rc = qh_alloc(c, &L.gpart, (int64_t)mlp_grid(L.nnz) * kWaves * 5313)) ||
+            (rc = qh_alloc(c, &L.gpart2, (int64_t)kGradChunks * 5313)))
             return rc;
     }
     const unsigned gr = (unsigned)std::min<int64_t>((n + 15) / 16, 2048);
@@ -660,12 +687,13 @@ int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad) {
     const unsigned ge = (unsigned)((L.nnz + 255) / 256);
     hipLaunchKernelGGL(k_kaporin_grad, dim3(ge), dim3(256), 0, c->stream, L.nnz, n, L.grow, L.gcol, L.gscale, L.o,
                        L.gval, V_dev, L.AW, L.d_o, L.lpart, L.loss);
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, c->stream, L.lpart, (int32_t)ge, n, L.loss);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, c->stream, L.lpart, (int32_t)ge, n, L.loss);
     if (want_grad) {
         const unsigned gm = mlp_grid(L.nnz);
         hipLaunchKernelGGL(k_mlp_backward, dim3(gm), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.d_o, L.nnz, L.gpart);
-        hipLaunchKernelGGL(k_grad_reduce, dim3((5313 + 255) / 256), dim3(256), 0, c->stream, L.gpart,
-                           (int64_t)gm * kWaves, L.grad);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((5313 + 255) / 256, kGradChunks), dim3(256), 0, c->stream, L.gpart,
+                           (int64_t)gm * kWaves, L.gpart2);
+        hipLaunchKernelGGL(k_grad_finish, dim3((5313 + 255) / 256), dim3(256), 0, c->stream, L.gpart2, L.grad);
     }
     QH_HIP(c, hipGetLastError());
     return QH_OK;
