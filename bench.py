@@ -67,7 +67,7 @@ def setup(wl: str, n_particles: int | None):
     return ctx, cfg, mesh, parts, mi
 
 
-def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
+def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False):
     """Bytes one launch must move at least (each datum read or written once)."""
     if kernel in ("cg_spmv",):
         n, nnz = mi.n_int_edges, mi.nnz_edge
@@ -77,6 +77,8 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
         return 12 * nnz + 4 * (n + 1) + 32 * n
     if kernel in ("cg_update", "node_update"):
         n = mi.n_int_edges if kernel == "cg_update" else mi.n_int_nodes
+        if learned and kernel == "cg_update":
+            return 48 * n                                # x, r rw; p, q in (z comes from the factor)
         return 64 * n                                    # x, r rw; p, q, dinv in; z out
     if kernel == "particle_step":
         # particle state in+out (28 B each way), per tet: geometry 48 + field 48 + vertex ids 16
@@ -84,11 +86,11 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
         # accumulators read-modify-write once (16 B per edge and node)
         return 56 * n_particles + 136 * mi.n_tets + 152 * crossings + 16 * (mi.n_edges + mi.n_nodes)
     if kernel == "precond":
-        # z = G^T (G r): two CSR passes over the lower factor (FP32 value + int32 column per
+        # z = G^T (G r): two CSR passes over the lower factor (BF16 value + int32 column per
         # entry) and its transpose; per row: r in, y out, y in, z out, r in (dot), row pointers
         n, nnz = mi.n_int_edges, mi.nnz_edge
         nnz_l = (nnz + n) // 2
-        return 16 * nnz_l + 40 * n + 8 * (n + 1)
+        return 12 * nnz_l + 40 * n + 8 * (n + 1)
     if kernel == "field_prep":
         return (48 + 24 + 16 + 48) * mi.n_tets + 8 * mi.n_edges + 8 * mi.n_faces
     return None
@@ -97,7 +99,7 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float):
 # HIP kernels behind each timed entry (one entry may launch several kernels)
 HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
                "precond": ["k_prec_g<false>", "k_prec_g<true>"],
-               "particle_step": ["k_particle_step<false>", "k_gather<0>", "k_gather<6>"],
+               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0>", "k_gather<6>"],
                "edge_rhs": ["k_edge_rhs"], "field_prep": ["k_field_prep"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_64cube_16M.md")
 
@@ -267,7 +269,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
 
     def roof(k, kern):
-        by = algorithmic_bytes(k, mi, n_p, crossings)
+        by = algorithmic_bytes(k, mi, n_p, crossings, learned=used == "learned")
         if by is None or k not in kern:
             return None
         avg_s = kern[k]["ms_total"] / kern[k]["launches"] * 1e-3
