@@ -165,7 +165,14 @@ def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: 
         fo.step(e, b, u_b, out["g"], u_q, out["Q"], out["Q"], tol=1e-8, tol_n=1e-8)
         t_field = time.perf_counter() - t0
     t_step = t_push * n_total / n_s + t_field
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n_total / t_step, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "push_s": round(t_push, 3), "field_s": round(t_field, 3),
             "sample": f"one step of {n_s} of {n_total} particles (FP64 C oracle, {cores} threads, "
                       f"{t_push:.2f}s) + one FP64 field update on the full mesh (numpy/scipy, "
                       f"{t_field:.2f}s); rate = N_p / (push time scaled to N_p + field time)"}
