@@ -742,9 +742,32 @@ hipError_t launch_divb(qh_ctx *c, int64_t *out) {
 
 // ------------------------------------------------------------------------------------------
 // Counting sort of one species by tet: histogram, exclusive scan, scatter.
+// Particles are nearly sorted by tet between sorts, so a wave sees a few runs of equal tets:
+// the first lane of each run (its head) adds the run's length, one atomic per run.
+__device__ __forceinline__ void wave_runs(int t, bool valid, int &head, int &len, int &rank) {
+    const int lane = __lane_id();
+    const int prev = __shfl_up(t, 1, 64);
+    const bool is_head = valid && (lane == 0 || prev != t);
+    const unsigned long long heads = __ballot(is_head);
+    const unsigned long long valid_m = __ballot(valid);
+    // my run's head: the highest head at or below this lane
+    const unsigned long long below = heads & ((2ull << lane) - 1ull);  // lanes 0..lane
+    head = 63 - __clzll((long long)below);
+    // run end: the next head above this lane, else the end of the valid lanes
+    const unsigned long long above = heads & ~((2ull << lane) - 1ull);
+    const int vend = 64 - __clzll((long long)valid_m);
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : vend;
+    len = next - head;
+    rank = lane - head;
+}
+
 __global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t *__restrict__ hist) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&hist[tet[i]], 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int t = valid ? tet[i] : -1;
+    int head, len, rank;
+    wave_runs(t, valid, head, len, rank);
+    if (valid && rank == 0) atomicAdd(&hist[t], len);
 }
 
 // scan over chunks of 1024: per-chunk sums
@@ -809,10 +832,16 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
                           int32_t *__restrict__ cursor, float *__restrict__ ox, float *__restrict__ oy,
                           float *__restrict__ oz, float *__restrict__ ovx, float *__restrict__ ovy,
                           float *__restrict__ ovz, int32_t *__restrict__ otet, int32_t *__restrict__ oid) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int t = tet[i];
-    int32_t j = atomicAdd(&cursor[t], 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int t = valid ? tet[i] : -1;
+    int head, len, rank;
+    wave_runs(t, valid, head, len, rank);
+    int32_t first = 0;
+    if (valid && rank == 0) first = atomicAdd(&cursor[t], len);
+    first = __shfl(first, head, 64);
+    if (!valid) return;
+    const int32_t j = first + rank;
     ox[j] = x[i]; oy[j] = y[i]; oz[j] = z[i];
     ovx[j] = vx[i]; ovy[j] = vy[i]; ovz[j] = vz[i];
     otet[j] = t; oid[j] = id[i];
