@@ -385,6 +385,7 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         for (auto p : is)
             if ((rc = qh_alloc(c, p, n))) return rc;
         if ((rc = qh_alloc(c, &s.own, qh_species_blocks(n) + 1))) return rc;
+        if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(n) * QH_CHUNK))) return rc;
         s.cap = n;
     }
     s.n = n;

@@ -79,6 +79,7 @@ struct Species {
     float *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
     int32_t *stet = nullptr, *sid = nullptr;
     int32_t *own = nullptr;    // owned tet range per particle block (see qh_particles.hip)
+    uint16_t *ovf = nullptr;   // per particle block: overflow list of the walk queue
 };
 
 // Krylov workspace for one system.

@@ -81,6 +81,7 @@ struct StepArgs {
     int32_t zq;             // charge number
     int64_t *g, *Q;         // deposits that find no mailbox slot (atomics)
     int64_t *acc_tet;       // per-tet sums, plane-major: acc_tet[k * nt + t], k = 6 edges, 4 nodes
+    uint16_t *ovf;          // per block: chunk indices of queued particles past the LDS queue
     unsigned long long *counters;
     // capture
     int32_t species;
@@ -318,33 +319,39 @@ __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py
 // ------------------------------------------------------------------------------------------
 // Fused particle step. A block takes kChunk consecutive particles (sorted by tet at the last
 // sort), kPpt consecutive ones per thread.
-// Phase A: gather, Boris, and for a particle whose straight path stays in its tet, the new
-// position and its deposit (a per-thread register sum over consecutive particles of one tet,
-// then LDS). Particles whose path leaves the tet are queued in LDS.
-// Phase B: the queued particles are walked one per lane.
-// The state is staged in LDS and written back once, coalesced; the window sums are written as
-// plain stores into acc_tet (zeros for owned tets past the window, whose pieces are posted).
+// Phase A (all waves): gather, Boris; a particle whose straight path stays in its tet gets its
+// new position and the deposit of the piece (LDS window or post) and is written back from
+// registers; a particle whose path leaves the tet is queued in LDS with its start state (past
+// kQueue queued particles: its new velocity to memory and its index to an overflow list).
+// Phase B (wave 0 only; the other waves exit): the queued particles are walked one per lane and
+// written back; then the window sums go to acc_tet as plain stores (zeros for owned tets past the
+// window) and the event counters to memory. Waves 1-3 do not wait for the walks.
+constexpr int kQueue = 128;
 template <bool CAPTURE>
 __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     __shared__ long long acc[10 * kWin];  // plane-major: acc[k * kWin + slot]
-    __shared__ unsigned short queue[kChunk];  // block-local index of each particle that leaves its tet
-    __shared__ float sx_[kChunk], sy_[kChunk], sz_[kChunk], svx_[kChunk], svy_[kChunk], svz_[kChunk];
-    __shared__ int st_[kChunk];           // particle state staged for one coalesced write-back
-    __shared__ unsigned int s_cnt[5];     // queue length, crossings, wall hits, lost, posted pieces
+    __shared__ float4 qrec[2 * kQueue];   // queued particle: (x, y, z, vx) (vy, vz, tet, chunk index) as bits
+    __shared__ unsigned int s_cnt[5];     // queued particles, -, -, -, posted pieces of phase A
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     const int T0 = a.own[blockIdx.x], T1 = a.own[blockIdx.x + 1];
     const int W = min(T1 - T0, kWin);
     for (int j = threadIdx.x; j < 10 * kWin; j += kBlock) acc[j] = 0;
     if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    unsigned int n_foreign = 0;
-    const int LE0[6] = {0, 0, 0, 1, 1, 2};
-    const int LE1[6] = {1, 2, 3, 2, 3, 3};
+    unsigned int n_cross = 0, n_wall = 0, n_lost = 0, n_foreign = 0;
+    auto deposit = [&](int tt, const int P0[4], const int P1[4], bool end) {
+        const int slot = tt - T0;
+        if ((unsigned)slot < (unsigned)W) {
+            long long v[10];
+            piece_values(P0, P1, end, v);
+            put_lds<kWin>(acc, slot, v);
+        } else {
+            ++n_foreign;
+            post_piece(a, tt, P0, P1, end);
+        }
+    };
 
-    int cur = -1;
-    long long rs[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) rs[k] = 0;
+    // ---- phase A
     const int64_t i0 = base + (int64_t)threadIdx.x * kPpt;
     const bool full = base + kChunk <= a.n;
     float2 X, Y, Z, VX, VY, VZ;
@@ -355,10 +362,11 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         VX = ((const float2 *)a.vx)[v]; VY = ((const float2 *)a.vy)[v]; VZ = ((const float2 *)a.vz)[v];
         TT = ((const int2 *)a.tet)[v];
     }
+    bool queued[kPpt];
 #pragma unroll
     for (int q = 0; q < kPpt; ++q) {
+        queued[q] = false;
         const int64_t i = i0 + q;
-        const int li = threadIdx.x * kPpt + q;
         if (!full && i >= a.n) break;
         float px, py, pz, vx, vy, vz;
         int t;
@@ -402,105 +410,108 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         gl[2] = B.x * rx + B.y * ry + B.z * rz;
         gl[3] = C.x * rx + C.y * ry + C.z * rz;
         gl[0] = -(gl[1] + gl[2] + gl[3]);
-        bool leaves = (l[0] + gl[0] < 0.0f) | (l[1] + gl[1] < 0.0f) | (l[2] + gl[2] < 0.0f) |
-                      (l[3] + gl[3] < 0.0f);
-        svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
-        st_[li] = t;
-        if (leaves) {
-            // walked in phase B from the start point with the new velocity
-            unsigned int k = atomicAdd(&s_cnt[0], 1u);
-            queue[k] = (unsigned short)li;
-            sx_[li] = px; sy_[li] = py; sz_[li] = pz;
-            continue;
-        }
-        px += rx; py += ry; pz += rz;
-        sx_[li] = px; sy_[li] = py; sz_[li] = pz;
-        int L0[4], L1[4];
-        quantize(l, -1, L0);
-        lam4(A, B, C, px, py, pz, l);
-        quantize(l, -1, L1);
-        if (CAPTURE) record_piece(a, a.pid[i], 0, t, L0, L1);
-        if ((unsigned)(t - T0) >= (unsigned)W) {
-            ++n_foreign;
-            post_piece(a, t, L0, L1, true);  // a particle that has moved out of the block's window
-            continue;
-        }
-        if (t != cur) {
-            if (cur >= 0) put_lds<kWin>(acc, cur - T0, rs);
-#pragma unroll
-            for (int k = 0; k < 10; ++k) rs[k] = 0;
-            cur = t;
-        }
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            rs[k] += (long long)L0[LE0[k]] * L1[LE1[k]] - (long long)L1[LE0[k]] * L0[LE1[k]];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rs[6 + r] += L1[r];
-    }
-    if (cur >= 0) put_lds<kWin>(acc, cur - T0, rs);
-    __syncthreads();
-
-    // ---- phase B: walk the particles that leave their tet, one per lane
-    const int nq = (int)s_cnt[0];
-    unsigned int n_cross = 0, n_wall = 0, n_lost = 0;
-    auto deposit = [&](int tt, const int P0[4], const int P1[4], bool end) {
-        const int slot = tt - T0;
-        if ((unsigned)slot < (unsigned)W) {
-            long long v[10];
-            piece_values(P0, P1, end, v);
-            put_lds<kWin>(acc, slot, v);
+        const bool leaves = (l[0] + gl[0] < 0.0f) | (l[1] + gl[1] < 0.0f) | (l[2] + gl[2] < 0.0f) |
+                            (l[3] + gl[3] < 0.0f);
+        if (!leaves) {
+            int L0[4], L1[4];
+            quantize(l, -1, L0);
+            px += rx; py += ry; pz += rz;
+            lam4(A, B, C, px, py, pz, l);
+            quantize(l, -1, L1);
+            deposit(t, L0, L1, true);
+            if (CAPTURE) record_piece(a, a.pid[i], 0, t, L0, L1);
         } else {
-            ++n_foreign;
-            post_piece(a, tt, P0, P1, end);
+            const unsigned int k = atomicAdd(&s_cnt[0], 1u);
+            queued[q] = true;
+            if (k < (unsigned)kQueue) {
+                qrec[2 * k] = make_float4(px, py, pz, vx);
+                qrec[2 * k + 1] = make_float4(vy, vz, __int_as_float(t), __int_as_float(threadIdx.x * kPpt + q));
+            } else {
+                // past the LDS queue: the new velocity goes to memory (position and tet there are
+                // still the start state) and the chunk index to this block's overflow list
+                a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+                a.ovf[base + (k - kQueue)] = (uint16_t)(threadIdx.x * kPpt + q);
+            }
         }
-    };
-    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-        const int li = queue[qi];
-        float px = sx_[li], py = sy_[li], pz = sz_[li];
-        float vx = svx_[li], vy = svy_[li], vz = svz_[li];
-        int t = st_[li];
-        const int32_t pid = CAPTURE ? a.pid[base + li] : 0;
-        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit, n_cross, n_wall, n_lost);
-        sx_[li] = px; sy_[li] = py; sz_[li] = pz;
-        svx_[li] = vx; svy_[li] = vy; svz_[li] = vz;
-        st_[li] = t;
+        if (full) {
+            if (q == 0) {
+                X.x = px; Y.x = py; Z.x = pz; VX.x = vx; VY.x = vy; VZ.x = vz; TT.x = t;
+            } else {
+                X.y = px; Y.y = py; Z.y = pz; VX.y = vx; VY.y = vy; VZ.y = vz; TT.y = t;
+            }
+        } else if (!queued[q]) {
+            a.x[i] = px; a.y[i] = py; a.z[i] = pz;
+            a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+            a.tet[i] = t;
+        }
     }
-    if (n_cross) atomicAdd(&s_cnt[1], n_cross);
-    if (n_wall) atomicAdd(&s_cnt[2], n_wall);
-    if (n_lost) atomicAdd(&s_cnt[3], n_lost);
-    if (n_foreign) atomicAdd(&s_cnt[4], n_foreign);
-    __syncthreads();
-    // coalesced write-back of the staged particle state
+    // write-back of the finished particles; a queued one is written by its walker
     if (full) {
         const int64_t v = i0 / 2;
-        const int l0 = threadIdx.x * kPpt;
-        ((float2 *)a.x)[v] = make_float2(sx_[l0], sx_[l0 + 1]);
-        ((float2 *)a.y)[v] = make_float2(sy_[l0], sy_[l0 + 1]);
-        ((float2 *)a.z)[v] = make_float2(sz_[l0], sz_[l0 + 1]);
-        ((float2 *)a.vx)[v] = make_float2(svx_[l0], svx_[l0 + 1]);
-        ((float2 *)a.vy)[v] = make_float2(svy_[l0], svy_[l0 + 1]);
-        ((float2 *)a.vz)[v] = make_float2(svz_[l0], svz_[l0 + 1]);
-        ((int2 *)a.tet)[v] = make_int2(st_[l0], st_[l0 + 1]);
-    } else {
-        for (int li = threadIdx.x; li < kChunk && base + li < a.n; li += kBlock) {
-            const int64_t i = base + li;
-            a.x[i] = sx_[li]; a.y[i] = sy_[li]; a.z[i] = sz_[li];
-            a.vx[i] = svx_[li]; a.vy[i] = svy_[li]; a.vz[i] = svz_[li];
-            a.tet[i] = st_[li];
+        if (!queued[0] && !queued[1]) {
+            ((float2 *)a.x)[v] = X; ((float2 *)a.y)[v] = Y; ((float2 *)a.z)[v] = Z;
+            ((float2 *)a.vx)[v] = VX; ((float2 *)a.vy)[v] = VY; ((float2 *)a.vz)[v] = VZ;
+            ((int2 *)a.tet)[v] = TT;
+        } else if (!queued[0]) {
+            a.x[i0] = X.x; a.y[i0] = Y.x; a.z[i0] = Z.x; a.vx[i0] = VX.x; a.vy[i0] = VY.x; a.vz[i0] = VZ.x;
+            a.tet[i0] = TT.x;
+        } else if (!queued[1]) {
+            a.x[i0 + 1] = X.y; a.y[i0 + 1] = Y.y; a.z[i0 + 1] = Z.y; a.vx[i0 + 1] = VX.y; a.vy[i0 + 1] = VY.y;
+            a.vz[i0 + 1] = VZ.y; a.tet[i0 + 1] = TT.y;
         }
     }
-    // owned tets: window sums, zeros beyond (their deposits are posted)
+    // posted pieces of phase A
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n_foreign += __shfl_xor(n_foreign, off, 64);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0 && n_foreign) atomicAdd(&s_cnt[4], n_foreign);
+    __syncthreads();
+    if (threadIdx.x >= 64) return;  // phase B and the write-out are wave 0's
+
+    // ---- phase B: the queued particles, one per lane of wave 0
+    n_foreign = 0;
+    const int nall = (int)s_cnt[0], nq = min(nall, kQueue);
+    for (int qi = lane; qi < nall; qi += 64) {
+        int64_t i;
+        float px, py, pz, vx, vy, vz;
+        int t;
+        if (qi < nq) {
+            const float4 q0 = qrec[2 * qi], q1 = qrec[2 * qi + 1];
+            i = base + __float_as_int(q1.w);
+            px = q0.x; py = q0.y; pz = q0.z; vx = q0.w; vy = q1.x; vz = q1.y;
+            t = __float_as_int(q1.z);
+        } else {
+            i = base + a.ovf[base + (qi - kQueue)];
+            px = a.x[i]; py = a.y[i]; pz = a.z[i];
+            vx = a.vx[i]; vy = a.vy[i]; vz = a.vz[i];
+            t = a.tet[i];
+        }
+        const int32_t pid = CAPTURE ? a.pid[i] : 0;
+        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit, n_cross, n_wall, n_lost);
+        a.x[i] = px; a.y[i] = py; a.z[i] = pz;
+        a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+        a.tet[i] = t;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        n_cross += __shfl_xor(n_cross, off, 64);
+        n_wall += __shfl_xor(n_wall, off, 64);
+        n_lost += __shfl_xor(n_lost, off, 64);
+        n_foreign += __shfl_xor(n_foreign, off, 64);
+    }
+    // owned tets: window sums, zeros beyond (their deposits are posted); this wave's own LDS
+    // additions are ordered before these reads
     const int m = T1 - T0;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         int64_t *dst = a.acc_tet + (int64_t)k * a.nt + T0;
         const long long scale = k < 6 ? (long long)a.zq : (long long)a.zq * QH_SCALE;
-        for (int j = threadIdx.x; j < m; j += kBlock) dst[j] = j < W ? scale * acc[k * kWin + j] : 0;
+        for (int j = lane; j < m; j += 64) dst[j] = j < W ? scale * acc[k * kWin + j] : 0;
     }
     // event counters: crossings, wall hits, lost, posted pieces
-    if (threadIdx.x < 4) {
-        const unsigned int v = s_cnt[1 + threadIdx.x];
-        if (v) atomicAdd(&a.counters[(blockIdx.x & (QH_COUNTER_SLOTS - 1)) * 4 + threadIdx.x], (unsigned long long)v);
+    if (lane < 4) {
+        const unsigned int v = lane == 0 ? n_cross : lane == 1 ? n_wall : lane == 2 ? n_lost : n_foreign + s_cnt[4];
+        if (v) atomicAdd(&a.counters[(blockIdx.x & (QH_COUNTER_SLOTS - 1)) * 4 + lane], (unsigned long long)v);
     }
 }
 
@@ -606,7 +617,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     a.geo = c->geo; a.frec = c->frec; a.tnodes = c->tnodes; a.tedges = c->tedges; a.tnbr = c->tnbr;
     a.x = s.x; a.y = s.y; a.z = s.zz; a.vx = s.vx; a.vy = s.vy; a.vz = s.vz;
     a.tet = s.tet; a.pid = s.id; a.own = s.own; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
-    a.mail_cnt = c->mail_cnt; a.mail = c->mail;
+    a.mail_cnt = c->mail_cnt; a.mail = c->mail; a.ovf = s.ovf;
     a.hqm = (float)(0.5 * s.qm * c->phys.dt);
     a.dt = (float)c->phys.dt;
     a.zq = s.z;
