@@ -526,25 +526,26 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
     return lb < nblocks ? lb : 0xffffffffu;
 }
 
-template <int OFF>
+template <int OFF, int LPI>
 __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ lst,
                                                 const int64_t *__restrict__ acc_tet, int64_t nt,
                                                 int64_t *__restrict__ out,
                                                 unsigned nblocks_grid) {
-    // grid is padded to a multiple of 8 blocks so the remap is a bijection onto [0, grid)
+    // LPI lanes per item; the grid is padded to a multiple of 8 blocks so the remap is a
+    // bijection onto [0, grid)
     const unsigned lb = xcd_block(blockIdx.x, nblocks_grid);
-    const int sub = threadIdx.x & 7;
-    const int64_t item = (int64_t)lb * 32 + (threadIdx.x >> 3);
+    const int sub = threadIdx.x & (LPI - 1);
+    const int64_t item = (int64_t)lb * (256 / LPI) + (threadIdx.x / LPI);
     int64_t s = 0;
     if (lb != 0xffffffffu && item < nitems) {
-        for (int32_t j = ptr[item] + sub; j < ptr[item + 1]; j += 8) {
+        for (int32_t j = ptr[item] + sub; j < ptr[item + 1]; j += LPI) {
             int32_t v = lst[j];
             s += acc_tet[(int64_t)(OFF + (v & 7)) * nt + (v >> 3)];
         }
     }
 #pragma unroll
-    for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+    for (int off = LPI / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPI);
     if (sub == 0 && lb != 0xffffffffu && item < nitems) out[item] += s;
 }
 
@@ -631,11 +632,13 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
     const HostMesh &m = c->hm;
     hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(256), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
-    unsigned ge = (unsigned)(((m.Ne + 31) / 32 + 7) / 8 * 8), gn = (unsigned)(((m.Nn + 31) / 32 + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_gather<0>, dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet, m.Nt, c->g,
-                       ge);
-    hipLaunchKernelGGL(k_gather<6>, dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet, m.Nt, c->Q,
-                       gn);
+    constexpr int kLpiE = 2, kLpiN = 8;  // lanes per edge / per node (edges border 4-6 tets, nodes ~24)
+    const unsigned ge = (unsigned)(((m.Ne + 256 / kLpiE - 1) / (256 / kLpiE) + 7) / 8 * 8);
+    const unsigned gn = (unsigned)(((m.Nn + 256 / kLpiN - 1) / (256 / kLpiN) + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_gather<0, kLpiE>), dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet,
+                       m.Nt, c->g, ge);
+    hipLaunchKernelGGL((k_gather<6, kLpiN>), dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet,
+                       m.Nt, c->Q, gn);
     return hipGetLastError();
 }
 

@@ -38,16 +38,15 @@ __device__ __forceinline__ void tile_range(int32_t ntiles, int32_t &tb, int32_t 
     if (tb > ntiles) tb = ntiles;
 }
 
-// For every row of this block's tiles: epi(row, sum_j a_row,j x_j, pre(row)) (x converted to
-// FP64). pre(row) loads what the epilogue needs from the row's own entries; it is issued with
+// For every row of this block's tiles: epi(row, sum_j a_row,j xg(j), pre(row)). pre(row) loads what the epilogue needs from the row's own entries; it is issued with
 // the tile's entry loads, and the next tile's header is fetched one tile ahead, so a tile costs
 // two dependent memory round trips (entries, then gathered vector). All threads of the block
 // must call it (it synchronises the block).
-template <typename VT, typename XT, typename Pre, typename Epi>
-__device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
-                                          const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                          const VT *__restrict__ val, const XT *__restrict__ x,
-                                          double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
+template <typename VT, typename XG, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int32_t ntiles,
+                                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                            const VT *__restrict__ val, XG &&xg,
+                                            double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
     using PF = decltype(pre(0));
     int32_t tb, te;
     tile_range(ntiles, tb, te);
@@ -77,7 +76,7 @@ __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_
             }
             double xv[kTileUnroll];
 #pragma unroll
-            for (int u = 0; u < kTileUnroll; ++u) xv[u] = (double)x[c[u]];
+            for (int u = 0; u < kTileUnroll; ++u) xv[u] = xg(c[u]);
 #pragma unroll
             for (int u = 0; u < kTileUnroll; ++u) {
                 const int32_t j = b + u * kTileThreads + tid;
@@ -94,6 +93,15 @@ __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_
         t0 = t1;
         t1 = t2;
     }
+}
+
+// The same with the gathered vector read from memory (converted to FP64).
+template <typename VT, typename XT, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
+                                          const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                          const VT *__restrict__ val, const XT *__restrict__ x,
+                                          double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
+    tile_spmv_g(tiles, ntiles, ptr, col, val, [&](int32_t j) { return (double)x[j]; }, prod, pre, epi);
 }
 
 // Grid of a tiled product: one block per tile up to 2048 blocks, a multiple of 8.
