@@ -35,7 +35,19 @@ __device__ __forceinline__ short f2bf(float f) {  // round to nearest even
     u += 0x7fffu + ((u >> 16) & 1u);
     return (short)(u >> 16);
 }
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+// two floats to two BF16 (round to nearest even) in one instruction on gfx950 (low half = lo)
+__device__ __forceinline__ unsigned pk_bf16(float lo, float hi) {
+    const f32x2 f = {lo, hi};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f, b16x2));
+}
+__device__ __forceinline__ bf16x4 bf16x4_of(float a, float b, float c, float d) {
+    const u32x2 u = {pk_bf16(a, b), pk_bf16(c, d)};
+    return __builtin_bit_cast(bf16x4, u);
+}
+__device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -58,7 +70,7 @@ struct Frags {
     float b3;
 };
 
-__device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F, bool transposed_w2) {
+__device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F) {
     const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
@@ -68,8 +80,7 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                F.w2[mb][kb][j] = transposed_w2 ? f2bf(w[kOffW2 + (16 * kb + 4 * g + j) * kH + 16 * mb + r])
-                                                : f2bf(w[kOffW2 + (16 * mb + r) * kH + 16 * kb + 4 * g + j]);
+                F.w2[mb][kb][j] = f2bf(w[kOffW2 + (16 * mb + r) * kH + 16 * kb + 4 * g + j]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             F.b1[mb][j] = w[kOffB1 + 16 * mb + 4 * g + j];
@@ -80,42 +91,39 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F
     F.b3 = w[kOffB3];
 }
 
-// Forward pass of one 16-entry tile (entries e0 + l%16). Returns o for entry e0 + l%16 in
-// every lane; z1, z2 (pre-activations, feature-major) are kept for the backward pass.
-__device__ __forceinline__ float tile_forward(const Frags &F, const unsigned short *__restrict__ feats,
-                                              int64_t e0, int64_t nnz, f32x4 (&z1)[4], f32x4 (&z2)[4],
-                                              bf16x4 (&h1b)[4]) {
+// Features of entry e0 + l%16 for this lane's quarter (4 BF16), zero past the end.
+__device__ __forceinline__ bf16x4 load_x(const unsigned short *__restrict__ feats, int64_t e0, int64_t nnz) {
     const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
     const int64_t e = e0 + r;
-    bf16x4 x;
+    u32x2 u = {0u, 0u};
     if (e < nnz) {
         const uint2 raw = *(const uint2 *)(feats + e * kF + 4 * g);
-        x[0] = (short)(raw.x & 0xffff); x[1] = (short)(raw.x >> 16);
-        x[2] = (short)(raw.y & 0xffff); x[3] = (short)(raw.y >> 16);
-    } else {
-        x[0] = x[1] = x[2] = x[3] = 0;
+        u[0] = raw.x;
+        u[1] = raw.y;
     }
+    return __builtin_bit_cast(bf16x4, u);
+}
+
+// Forward pass of one 16-entry tile (entries e0 + l%16, features x). Returns o for entry
+// e0 + l%16 in every lane; z1, z2 (pre-activations, feature-major) are kept for the backward
+// pass. Biases initialise the accumulators.
+__device__ __forceinline__ float tile_forward(const Frags &F, bf16x4 x, f32x4 (&z1)[4], f32x4 (&z2)[4],
+                                              bf16x4 (&h1b)[4]) {
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-        c = mfma(F.w1[mb], x, c);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            z1[mb][j] = c[j] + F.b1[mb][j];
-            h1b[mb][j] = f2bf(fmaxf(z1[mb][j], 0.f));
-        }
+        f32x4 c = {F.b1[mb][0], F.b1[mb][1], F.b1[mb][2], F.b1[mb][3]};
+        z1[mb] = mfma(F.w1[mb], x, c);
+        h1b[mb] = bf16x4_of(relu(z1[mb][0]), relu(z1[mb][1]), relu(z1[mb][2]), relu(z1[mb][3]));
     }
     float s = 0.f;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        f32x4 c = {F.b2[mb][0], F.b2[mb][1], F.b2[mb][2], F.b2[mb][3]};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) c = mfma(F.w2[mb][kb], h1b[kb], c);
+        z2[mb] = c;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            z2[mb][j] = c[j] + F.b2[mb][j];
-            s += fmaxf(z2[mb][j], 0.f) * F.w3[mb][j];
-        }
+        for (int j = 0; j < 4; ++j) s += relu(c[j]) * F.w3[mb][j];
     }
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
@@ -138,14 +146,17 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
                                                             const float *__restrict__ gscale, int64_t nnz,
                                                             float *__restrict__ o_out, float *__restrict__ gval) {
     Frags F;
-    load_frags(w, F, false);
+    load_frags(w, F);
     const int l = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    bf16x4 xn = load_x(feats, wave * 16, nnz);  // the next tile's features are always in flight
     for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
+        const bf16x4 x = xn;
+        xn = load_x(feats, e0 + nwaves * 16, nnz);
         f32x4 z1[4], z2[4];
         bf16x4 h1b[4];
-        float o = tile_forward(F, feats, e0, nnz, z1, z2, h1b);
+        float o = tile_forward(F, x, z1, z2, h1b);
         const int64_t e = e0 + l;
         if (l < 16 && e < nnz) {
             if (o_out) o_out[e] = o;
@@ -315,9 +326,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
                                                               const float *__restrict__ d_o, int64_t nnz,
                                                               float *__restrict__ gpart) {
     __shared__ unsigned short tr[kWaves][2][64][17];  // per wave: dZ2^T / dZ1^T and H1^T tiles, [row][entry]
-    Frags F, FT;
-    load_frags(w, F, false);
-    load_frags(w, FT, true);
+    Frags F;
+    load_frags(w, F);
+    bf16x4 w2t[4][4];  // W2^T fragments for dH1^T = W2^T dZ2^T
+    {
+        const int ll = threadIdx.x & 63, rr = ll & 15, gg = ll >> 4;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                w2t[mb][kb] = bf16x4_of(w[kOffW2 + (16 * kb + 4 * gg + 0) * kH + 16 * mb + rr],
+                                        w[kOffW2 + (16 * kb + 4 * gg + 1) * kH + 16 * mb + rr],
+                                        w[kOffW2 + (16 * kb + 4 * gg + 2) * kH + 16 * mb + rr],
+                                        w[kOffW2 + (16 * kb + 4 * gg + 3) * kH + 16 * mb + rr]);
+    }
     const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
     const int wv = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * kWaves + wv;
@@ -334,24 +356,28 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
     }
     // the LDS staging area tr[wv] belongs to this wave alone: wave-level ordering suffices
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    bf16x4 xn = load_x(feats, wave * 16, nnz);
     for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
+        const bf16x4 x = xn;
+        xn = load_x(feats, e0 + nwaves * 16, nnz);
         f32x4 z1[4], z2[4];
         bf16x4 h1b[4];
-        (void)tile_forward(F, feats, e0, nnz, z1, z2, h1b);
+        (void)tile_forward(F, x, z1, z2, h1b);
         const int64_t e = e0 + r;
         const float dout = e < nnz ? d_o[e] : 0.f;
         // dZ2^T = w3 d_o (z2 > 0); db2, dw3, db3
         bf16x4 dz2b[4];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+        for (int mb = 0; mb < 4; ++mb) {
+            float dz[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float m = z2[mb][j] > 0.f ? 1.f : 0.f;
-                const float dz = F.w3[mb][j] * dout * m;
-                dz2b[mb][j] = f2bf(dz);
-                gb2[mb][j] += dz;
-                gw3[mb][j] += fmaxf(z2[mb][j], 0.f) * dout;
+                dz[j] = z2[mb][j] > 0.f ? F.w3[mb][j] * dout : 0.f;
+                gb2[mb][j] += dz[j];
+                gw3[mb][j] += relu(z2[mb][j]) * dout;
             }
+            dz2b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
+        }
         if (g == 0) gb3 += dout;
         // dH1^T = W2^T dZ2^T (B operand chains from the accumulator layout)
         bf16x4 dz1b[4];
@@ -359,13 +385,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
         for (int mb = 0; mb < 4; ++mb) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) c = mfma(FT.w2[mb][kb], dz2b[kb], c);
+            for (int kb = 0; kb < 4; ++kb) c = mfma(w2t[mb][kb], dz2b[kb], c);
+            float dz[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float dz = z1[mb][j] > 0.f ? c[j] : 0.f;
-                dz1b[mb][j] = f2bf(dz);
-                gb1[mb][j] += dz;
+                dz[j] = z1[mb][j] > 0.f ? c[j] : 0.f;
+                gb1[mb][j] += dz[j];
             }
+            dz1b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
         }
         // stage dZ2^T and H1^T ([row][entry]) for the entry contraction
 #pragma unroll
