@@ -225,16 +225,43 @@ __global__ void k_probes(int32_t n, uint64_t seed, float *__restrict__ V) {
 
 // out[row][p] = sum_k M_row,k in[k][p]; one lane per probe, 16 rows per block and pass. With
 // DOT, also per-block partials of sum_row other[row][p] * out[row][p] (for the trace).
+// The row's entries go through LDS eight at a time (one coalesced load per group of 16 lanes,
+// then broadcast reads), so the eight gathers of in[] are independent loads in flight together;
+// the products are summed in entry order, as a plain row loop would.
 template <typename VT, bool DOT>
 __global__ void __launch_bounds__(256) k_spmm16(int32_t n, const int32_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ col, const VT *__restrict__ val,
                                                 const float *__restrict__ in, float *__restrict__ out,
                                                 const float *__restrict__ other, double *__restrict__ part) {
-    const int p = threadIdx.x & 15;
+    struct Ent {
+        int32_t c;
+        VT v;
+    };
+    __shared__ Ent ent[16][8];  // per group of 16 lanes (one row): the current eight entries
+    const int p = threadIdx.x & 15, grp = threadIdx.x >> 4;
     double d = 0.0;
-    for (int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); row < n; row += (int64_t)gridDim.x * 16) {
+    for (int64_t row = (int64_t)blockIdx.x * 16 + grp; row < n; row += (int64_t)gridDim.x * 16) {
+        const int32_t beg = ptr[row], end = ptr[row + 1];
         double s = 0.0;
-        for (int32_t j = ptr[row]; j < ptr[row + 1]; ++j) s += (double)val[j] * (double)in[(int64_t)col[j] * kP + p];
+        for (int32_t j0 = beg; j0 < end; j0 += 8) {
+            if (p < 8) {
+                // past the row's end: a zero weight on column of the row's first entry
+                const bool ok = j0 + p < end;
+                ent[grp][p] = Ent{col[ok ? j0 + p : beg], ok ? val[j0 + p] : (VT)0};
+            }
+            wave_lds_sync();
+            float x[8];
+            VT v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const Ent q = ent[grp][k];
+                v[k] = q.v;
+                x[k] = in[(int64_t)q.c * kP + p];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += (double)v[k] * (double)x[k];
+            wave_lds_sync();
+        }
         out[row * kP + p] = (float)s;
         if (DOT) d += s * (double)other[row * kP + p];
     }
@@ -278,9 +305,23 @@ __global__ void __launch_bounds__(256) k_kaporin_grad(int64_t nnz, int32_t n, co
     double lg = 0.0;
     if (e < nnz) {
         const int32_t i = grow[e], j = gcol[e];
+        // rows of 16 floats, 64-byte aligned: four 16-byte loads each
+        const float4 *aw4 = reinterpret_cast<const float4 *>(AW + (int64_t)j * kP);
+        const float4 *v4 = reinterpret_cast<const float4 *>(V + (int64_t)i * kP);
+        float4 a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = aw4[q];
+            b[q] = v4[q];
+        }
         double s = 0.0;
 #pragma unroll
-        for (int p = 0; p < kP; ++p) s += (double)AW[(int64_t)j * kP + p] * (double)V[(int64_t)i * kP + p];
+        for (int q = 0; q < 4; ++q) {
+            s += (double)a[q].x * (double)b[q].x;
+            s += (double)a[q].y * (double)b[q].y;
+            s += (double)a[q].z * (double)b[q].z;
+            s += (double)a[q].w * (double)b[q].w;
+        }
         double dG = 2.0 / ((double)kP * T * (double)n) * s;
         const bool diag = i == j;
         float d;
