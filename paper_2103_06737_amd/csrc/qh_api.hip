@@ -248,7 +248,7 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = qh_alloc(c, &c->acc_tet, 10 * m.Nt))) return rc;
     {
         const int64_t nmail = (m.Nt + kMailTets - 1) / kMailTets;
-        if ((rc = qh_alloc(c, &c->mail_cnt, nmail)) || (rc = qh_alloc(c, &c->mail, nmail * kMailCap * 9))) return rc;
+        if ((rc = qh_alloc(c, &c->mail_cnt, nmail)) || (rc = qh_alloc(c, &c->mail, nmail * kMailCap * kMailWords))) return rc;
     }
     if ((rc = qh_alloc(c, &c->frec, 3 * m.Nt))) return rc;
     if ((rc = qh_alloc(c, &c->e, m.Ne)) || (rc = qh_alloc(c, &c->b, m.Nf)) || (rc = qh_alloc(c, &c->g, m.Ne)) ||

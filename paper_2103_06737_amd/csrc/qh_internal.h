@@ -16,6 +16,7 @@ constexpr int QH_COUNTER_SLOTS = 256;         // spread of the per-block event c
 constexpr int QH_CHUNK = 512;                 // particles per block of the particle kernels
 constexpr int kMailTets = 128;                // tets per deposit mailbox
 constexpr int kMailCap = 1024;                // records per mailbox
+constexpr int kMailWords = 5;                 // int32 words per record: both points packed (4), tet | end << 31 (1)
 
 // ---------------------------------------------------------------------------------------
 // Host-side mesh complex and FP64 assembly (qh_mesh.hip)
@@ -145,7 +146,7 @@ struct qh_ctx {
     int32_t *n2t_ptr = nullptr, *n2t = nullptr;  // node -> tet*8 + local vertex
     int64_t *acc_tet = nullptr;                  // 10*Nt per-tet deposit sums, plane-major [10][Nt]
     unsigned int *mail_cnt = nullptr;            // per mailbox (run of kMailTets tets): records posted
-    int32_t *mail = nullptr;                     // mailboxes: ceil(Nt / kMailTets) x kMailCap x 9 int32
+    int32_t *mail = nullptr;                     // mailboxes: ceil(Nt / kMailTets) x kMailCap x kMailWords int32
 
     DevCsr A, CMb, GtM, K;  // A: val = [*eps] + tau S, val2 = [*eps]
     double *A_S = nullptr;  // S values on the pattern of A

@@ -23,7 +23,6 @@ constexpr int kPpt = 2;                  // consecutive particles per thread
 constexpr int kChunk = kBlock * kPpt;    // particles per block
 static_assert(kChunk == QH_CHUNK, "particle chunk size");
 constexpr int kWin = 128;                // owned tets whose sums a block keeps in LDS
-constexpr int kRec = 9;                  // int32 words of a mailbox record: tet | end << 31, L0[4], L1[4]
 
 __device__ __forceinline__ void lam4(const float4 A, const float4 B, const float4 C, float x,
                                      float y, float z, float l[4]) {
@@ -73,7 +72,7 @@ struct StepArgs {
     const int32_t *pid;
     const int32_t *own;     // own[b] .. own[b+1]: tets owned by block b (from the last sort)
     unsigned int *mail_cnt; // records posted to each mailbox (tets [kMailTets m, kMailTets (m+1))) this launch
-    int32_t *mail;          // kMailCap records of kRec words per mailbox
+    int32_t *mail;          // per mailbox: kMailCap packed point pairs (uint4), then kMailCap heads (tet | end << 31)
     int64_t n;
     int32_t nt;
     float hqm;              // q/m * dt / 2
@@ -156,6 +155,25 @@ void launch_field_prep(qh_ctx *c) {
 // atomics on edges and nodes. Integer sums do not depend on order, so the result is the same
 // bits on every path.
 
+// A mailbox record holds a piece's two points in 16 bytes: the four quantised coordinates of a
+// point sum to exactly 2^20, so three of them (21 bits each, values 0 .. 2^20) fix the fourth.
+static_assert(QH_FBITS <= 20, "a quantised coordinate must fit 21 bits");
+__device__ __forceinline__ uint4 pack_points(const int P0[4], const int P1[4]) {
+    const unsigned long long a = (unsigned long long)P0[1] | (unsigned long long)P0[2] << 21 |
+                                 (unsigned long long)P0[3] << 42;
+    const unsigned long long b = (unsigned long long)P1[1] | (unsigned long long)P1[2] << 21 |
+                                 (unsigned long long)P1[3] << 42;
+    return make_uint4((unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32));
+}
+
+__device__ __forceinline__ void unpack_point(unsigned lo, unsigned hi, int P[4]) {
+    const unsigned long long w = (unsigned long long)hi << 32 | lo;
+    P[1] = (int)(w & 0x1fffff);
+    P[2] = (int)((w >> 21) & 0x1fffff);
+    P[3] = (int)((w >> 42) & 0x1fffff);
+    P[0] = QH_SCALE - P[1] - P[2] - P[3];
+}
+
 // Unit-charge values of one straight piece P0 -> P1 (6 edges; 4 nodes when P1 is the end).
 __device__ __forceinline__ void piece_values(const int P0[4], const int P1[4], bool end, long long v[10]) {
     const int LE0[6] = {0, 0, 0, 1, 1, 2};
@@ -192,10 +210,9 @@ __device__ __forceinline__ void post_piece(const StepArgs &a, int tt, const int 
         pending &= ~same;
     }
     if (slot < (unsigned)kMailCap) {
-        int32_t *r = a.mail + ((int64_t)o * kMailCap + slot) * kRec;
-        r[0] = tt | (end ? (int32_t)0x80000000u : 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { r[1 + j] = P0[j]; r[5 + j] = P1[j]; }
+        int32_t *box = a.mail + (int64_t)o * kMailCap * kMailWords;
+        reinterpret_cast<uint4 *>(box)[slot] = pack_points(P0, P1);
+        box[4 * kMailCap + slot] = tt | (end ? (int32_t)0x80000000u : 0);
         return;
     }
     long long v[10];
@@ -565,14 +582,15 @@ __global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restri
     __syncthreads();
     const int LE0[6] = {0, 0, 0, 1, 1, 2};
     const int LE1[6] = {1, 2, 3, 2, 3, 3};
+    const int32_t *box = mail + (int64_t)o * kMailCap * kMailWords;
     for (unsigned int r = threadIdx.x; r < cnt; r += 256) {
-        const int32_t *rec = mail + ((int64_t)o * kMailCap + r) * kRec;
-        const int head = rec[0];
+        const uint4 pk = reinterpret_cast<const uint4 *>(box)[r];
+        const int head = box[4 * kMailCap + r];
         const int tt = head & 0x7fffffff;
         const bool end = head < 0;
         int P0[4], P1[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { P0[j] = rec[1 + j]; P1[j] = rec[5 + j]; }
+        unpack_point(pk.x, pk.y, P0);
+        unpack_point(pk.z, pk.w, P1);
         long long v[10];
 #pragma unroll
         for (int j = 0; j < 6; ++j)
