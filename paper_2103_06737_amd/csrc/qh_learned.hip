@@ -7,11 +7,13 @@
 // construction (plain PCG applies). Training minimises the Kaporin number of G A G^T,
 // L = log(tr(G A G^T)/n) - (2/n) sum log G_ii, trace from Rademacher probes.
 //
-// The dense layers run on MFMA (v_mfma_f32_16x16x16_bf16, BF16 operands, FP32 accumulate)
-// with activations kept feature-major: the 16x16 accumulator tile of one layer (lane l holds
-// rows 4(l/16)+j of column l%16) is exactly the B-operand layout of the next layer, so
-// layers chain in registers. Weight gradients contract over entries and go through a small
-// LDS transpose per tile.
+// The dense layers run on MFMA with BF16 operands and FP32 accumulation, activations kept
+// feature-major (entries along the 16 accumulator columns). The accumulator tile of one layer
+// (lane l holds rows 4(l/16)+j of column l%16) feeds the next layer's B operand without a
+// shuffle: the 16-feature input layer uses v_mfma_f32_16x16x16_bf16; the 64-wide contractions
+// use v_mfma_f32_16x16x32_bf16 (lane l holds k = 8(l/16)+j), whose B operand is two
+// accumulator tiles side by side, with the weight columns permuted to match. Weight gradients
+// contract over entries (32 per step) through a small per-wave LDS transpose.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -28,6 +30,8 @@ constexpr float kS0 = 0.54132485461291810f;  // log(e - 1): softplus(kS0) = 1
 constexpr int kWaves = 4;                    // waves per block in the MLP kernels
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short f2bf(float f) {  // round to nearest even
@@ -47,10 +51,25 @@ __device__ __forceinline__ bf16x4 bf16x4_of(float a, float b, float c, float d) 
     const u32x2 u = {pk_bf16(a, b), pk_bf16(c, d)};
     return __builtin_bit_cast(bf16x4, u);
 }
+__device__ __forceinline__ bf16x4 bf16x4_relu(f32x4 z) {
+    return bf16x4_of(fmaxf(z[0], 0.f), fmaxf(z[1], 0.f), fmaxf(z[2], 0.f), fmaxf(z[3], 0.f));
+}
 __device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+// K = 16: A lane l holds A[l%16][4(l/16)+j], B lane l holds B[4(l/16)+j][l%16]
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// K = 32: A lane l holds A[l%16][8(l/16)+j], B lane l holds B[8(l/16)+j][l%16]
+__device__ __forceinline__ f32x4 mfma32(bf16x8s a, bf16x8s b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
+// B operand of a 32-wide contraction from accumulator tiles t0 (rows 0..15) and t1 (16..31):
+// position k = 8(l/16)+j of the lane's group then stands for row hid32(l/16, j) of the pair
+__device__ __forceinline__ bf16x8s cat8(bf16x4 t0, bf16x4 t1) {
+    return __builtin_shufflevector(t0, t1, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+__device__ __forceinline__ int hid32(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4); }
 // Orders this wave's LDS accesses (a staging area private to one wave needs no block barrier:
 // the wave's LDS instructions execute in program order once the compiler keeps that order).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -61,13 +80,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
 __device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
 
-// Weight fragments of one wave. Layer 1: H1^T = W1 X^T (A = W1 rows 16mb.., k = features);
-// layer 2: H2^T = W2 H1^T (A = W2 block (mb, kb)); backward: dH1^T = W2^T dZ2^T.
+// Weight fragments of one wave. Layer 1: Z1^T = W1 X^T (A = rows 16mb.. of W1, k = features);
+// layer 2: Z2^T = W2 H1^T (A = rows 16mb.. of W2, k block q = hidden units 32q + hid32).
 struct Frags {
     bf16x4 w1[4];
-    bf16x4 w2[4][4];
-    float b1[4][4], b2[4][4], w3[4][4];
-    float b3;
+    bf16x8s w2[4][2];
 };
 
 __device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F) {
@@ -77,18 +94,23 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ w, Frags &F
 #pragma unroll
         for (int j = 0; j < 4; ++j) F.w1[mb][j] = f2bf(w[kOffW1 + (16 * mb + r) * kF + 4 * g + j]);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                F.w2[mb][kb][j] = f2bf(w[kOffW2 + (16 * mb + r) * kH + 16 * kb + 4 * g + j]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            F.b1[mb][j] = w[kOffB1 + 16 * mb + 4 * g + j];
-            F.b2[mb][j] = w[kOffB2 + 16 * mb + 4 * g + j];
-            F.w3[mb][j] = w[kOffW3 + 16 * mb + 4 * g + j];
-        }
+            for (int j = 0; j < 8; ++j) F.w2[mb][q][j] = f2bf(w[kOffW2 + (16 * mb + r) * kH + 32 * q + hid32(g, j)]);
     }
-    F.b3 = w[kOffB3];
+}
+
+// b1, b2, w3 (64 each) and b3 of the block in LDS; every thread of the block must call it.
+constexpr int kVecB1 = 0, kVecB2 = 64, kVecW3 = 128, kVecB3 = 192;
+__device__ __forceinline__ void load_vecs(const float *__restrict__ w, float *vec) {
+    for (int k = threadIdx.x; k < 193; k += blockDim.x)
+        vec[k] = k < 64 ? w[kOffB1 + k] : k < 128 ? w[kOffB2 + k - 64] : k < 192 ? w[kOffW3 + k - 128] : w[kOffB3];
+    __syncthreads();
+}
+// the lane's four values of rows 16mb + 4(l/16) + j of a vector in LDS
+__device__ __forceinline__ f32x4 vec4(const float *vec, int off, int mb) {
+    const int g = (threadIdx.x & 63) >> 4;
+    return *(const f32x4 *)(vec + off + 16 * mb + 4 * g);
 }
 
 // Features of entry e0 + l%16 for this lane's quarter (4 BF16), zero past the end.
@@ -105,29 +127,29 @@ __device__ __forceinline__ bf16x4 load_x(const unsigned short *__restrict__ feat
 }
 
 // Forward pass of one 16-entry tile (entries e0 + l%16, features x). Returns o for entry
-// e0 + l%16 in every lane; z1, z2 (pre-activations, feature-major) are kept for the backward
-// pass. Biases initialise the accumulators.
-__device__ __forceinline__ float tile_forward(const Frags &F, bf16x4 x, f32x4 (&z1)[4], f32x4 (&z2)[4],
-                                              bf16x4 (&h1b)[4]) {
+// e0 + l%16 in every lane; z1, z2 (pre-activations, feature-major) and H1 in BF16 are kept
+// for the backward pass. Biases initialise the accumulators.
+__device__ __forceinline__ float tile_forward(const Frags &F, const float *vec, bf16x4 x, f32x4 (&z1)[4],
+                                              f32x4 (&z2)[4], bf16x4 (&h1b)[4]) {
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        f32x4 c = {F.b1[mb][0], F.b1[mb][1], F.b1[mb][2], F.b1[mb][3]};
-        z1[mb] = mfma(F.w1[mb], x, c);
-        h1b[mb] = bf16x4_of(relu(z1[mb][0]), relu(z1[mb][1]), relu(z1[mb][2]), relu(z1[mb][3]));
+        z1[mb] = mfma16(F.w1[mb], x, vec4(vec, kVecB1, mb));
+        h1b[mb] = bf16x4_relu(z1[mb]);
     }
     float s = 0.f;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        f32x4 c = {F.b2[mb][0], F.b2[mb][1], F.b2[mb][2], F.b2[mb][3]};
+        f32x4 c = vec4(vec, kVecB2, mb);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) c = mfma(F.w2[mb][kb], h1b[kb], c);
+        for (int q = 0; q < 2; ++q) c = mfma32(F.w2[mb][q], cat8(h1b[2 * q], h1b[2 * q + 1]), c);
         z2[mb] = c;
+        const f32x4 w3 = vec4(vec, kVecW3, mb);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) s += relu(c[j]) * F.w3[mb][j];
+        for (int j = 0; j < 4; ++j) s += relu(c[j]) * w3[j];
     }
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
-    return s + F.b3;
+    return s + vec[kVecB3];
 }
 
 // G value of entry e from the network output
@@ -145,6 +167,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
                                                             const int32_t *__restrict__ gcol,
                                                             const float *__restrict__ gscale, int64_t nnz,
                                                             float *__restrict__ o_out, float *__restrict__ gval) {
+    __shared__ __align__(16) float vec[196];
+    load_vecs(w, vec);
     Frags F;
     load_frags(w, F);
     const int l = threadIdx.x & 63;
@@ -156,7 +180,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
         xn = load_x(feats, e0 + nwaves * 16, nnz);
         f32x4 z1[4], z2[4];
         bf16x4 h1b[4];
-        float o = tile_forward(F, x, z1, z2, h1b);
+        float o = tile_forward(F, vec, x, z1, z2, h1b);
         const int64_t e = e0 + l;
         if (l < 16 && e < nnz) {
             if (o_out) o_out[e] = o;
@@ -362,27 +386,32 @@ __global__ void __launch_bounds__(256) k_loss_finish(const double *__restrict__ 
 // ---------------------------------------------------------------------------------------
 // Backward pass over all entries: per-wave partial gradients of sum_e d_o[e] o[e].
 // Layout of a wave's partial (kParams floats): same as the weights.
+// A wave takes 32 entries per step (two 16-entry tiles): forward, dZ2^T = w3 d_o (z2 > 0),
+// dH1^T = W2^T dZ2^T, dZ1^T = dH1^T (z1 > 0); then dZ2^T, H1^T, dZ1^T and X^T of both tiles go
+// to the wave's LDS area as [row][entry] and the weight gradients contract over the 32 entries:
+// dW2 += dZ2^T H1, dW1 += dZ1^T X. Bias and w3 gradients are per-lane sums.
+constexpr int kTrStride = 40;               // BF16 per staged row: 32 entries + 8 (16-byte aligned rows, spread banks)
+constexpr int kTrRows = 3 * kH + kF;        // dZ2^T, H1^T, dZ1^T, X^T
+constexpr int kTrDZ2 = 0, kTrH1 = kH, kTrDZ1 = 2 * kH, kTrX = 3 * kH;
 __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__restrict__ w,
                                                               const unsigned short *__restrict__ feats,
                                                               const float *__restrict__ d_o, int64_t nnz,
                                                               float *__restrict__ gpart) {
-    __shared__ unsigned short tr[kWaves][2][64][17];  // per wave: dZ2^T / dZ1^T and H1^T tiles, [row][entry]
+    __shared__ __align__(16) unsigned short tr[kWaves][kTrRows][kTrStride];
+    __shared__ __align__(16) float vec[196];
+    load_vecs(w, vec);
     Frags F;
     load_frags(w, F);
-    bf16x4 w2t[4][4];  // W2^T fragments for dH1^T = W2^T dZ2^T
-    {
-        const int ll = threadIdx.x & 63, rr = ll & 15, gg = ll >> 4;
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                w2t[mb][kb] = bf16x4_of(w[kOffW2 + (16 * kb + 4 * gg + 0) * kH + 16 * mb + rr],
-                                        w[kOffW2 + (16 * kb + 4 * gg + 1) * kH + 16 * mb + rr],
-                                        w[kOffW2 + (16 * kb + 4 * gg + 2) * kH + 16 * mb + rr],
-                                        w[kOffW2 + (16 * kb + 4 * gg + 3) * kH + 16 * mb + rr]);
-    }
     const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+    bf16x8s w2t[4][2];  // W2^T fragments for dH1^T = W2^T dZ2^T (k block q = outputs 32q + hid32)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w2t[mb][q][j] = f2bf(w[kOffW2 + (32 * q + hid32(g, j)) * kH + 16 * mb + r]);
     const int wv = threadIdx.x >> 6;
+    unsigned short(*T)[kTrStride] = tr[wv];
     const int64_t wave = (int64_t)blockIdx.x * kWaves + wv;
     f32x4 gW2[4][4], gW1[4];
     float gb1[4][4], gb2[4][4], gw3[4][4], gb3 = 0.f;
@@ -395,88 +424,77 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
             gb1[a][b] = gb2[a][b] = gw3[a][b] = 0.f;
         }
     }
-    // the LDS staging area tr[wv] belongs to this wave alone: wave-level ordering suffices
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-    bf16x4 xn = load_x(feats, wave * 16, nnz);
-    for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
-        const bf16x4 x = xn;
-        xn = load_x(feats, e0 + nwaves * 16, nnz);
-        f32x4 z1[4], z2[4];
-        bf16x4 h1b[4];
-        (void)tile_forward(F, x, z1, z2, h1b);
-        const int64_t e = e0 + r;
-        const float dout = e < nnz ? d_o[e] : 0.f;
-        // dZ2^T = w3 d_o (z2 > 0); db2, dw3, db3
-        bf16x4 dz2b[4];
+    bf16x4 xn[2] = {load_x(feats, wave * 32, nnz), load_x(feats, wave * 32 + 16, nnz)};
+    for (int64_t e0 = wave * 32; e0 < nnz; e0 += nwaves * 32) {
+        const bf16x4 xt[2] = {xn[0], xn[1]};
+        xn[0] = load_x(feats, e0 + nwaves * 32, nnz);
+        xn[1] = load_x(feats, e0 + nwaves * 32 + 16, nnz);
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            float dz[4];
+        for (int s = 0; s < 2; ++s) {
+            f32x4 z1[4], z2[4];
+            bf16x4 h1b[4];
+            (void)tile_forward(F, vec, xt[s], z1, z2, h1b);
+            const int64_t e = e0 + 16 * s + r;
+            const float dout = e < nnz ? d_o[e] : 0.f;
+            bf16x4 dz2b[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                dz[j] = z2[mb][j] > 0.f ? F.w3[mb][j] * dout : 0.f;
-                gb2[mb][j] += dz[j];
-                gw3[mb][j] += relu(z2[mb][j]) * dout;
+            for (int mb = 0; mb < 4; ++mb) {
+                const f32x4 w3 = vec4(vec, kVecW3, mb);
+                float dz[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    dz[j] = z2[mb][j] > 0.f ? w3[j] * dout : 0.f;
+                    gb2[mb][j] += dz[j];
+                    gw3[mb][j] += relu(z2[mb][j]) * dout;
+                }
+                dz2b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
             }
-            dz2b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
+            if (g == 0) gb3 += dout;
+            bf16x4 dz1b[4];
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < 2; ++q) c = mfma32(w2t[mb][q], cat8(dz2b[2 * q], dz2b[2 * q + 1]), c);
+                float dz[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    dz[j] = z1[mb][j] > 0.f ? c[j] : 0.f;
+                    gb1[mb][j] += dz[j];
+                }
+                dz1b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
+            }
+            // stage this tile's columns (entry 16s + l%16)
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mb + 4 * g + j;
+                    T[kTrDZ2 + row][16 * s + r] = (unsigned short)dz2b[mb][j];
+                    T[kTrH1 + row][16 * s + r] = (unsigned short)h1b[mb][j];
+                    T[kTrDZ1 + row][16 * s + r] = (unsigned short)dz1b[mb][j];
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) T[kTrX + 4 * g + j][16 * s + r] = (unsigned short)xt[s][j];
         }
-        if (g == 0) gb3 += dout;
-        // dH1^T = W2^T dZ2^T (B operand chains from the accumulator layout)
-        bf16x4 dz1b[4];
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) c = mfma(w2t[mb][kb], dz2b[kb], c);
-            float dz[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                dz[j] = z1[mb][j] > 0.f ? c[j] : 0.f;
-                gb1[mb][j] += dz[j];
-            }
-            dz1b[mb] = bf16x4_of(dz[0], dz[1], dz[2], dz[3]);
-        }
-        // stage dZ2^T and H1^T ([row][entry]) for the entry contraction
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz2b[mb][j];
-                tr[wv][1][16 * mb + 4 * g + j][r] = (unsigned short)h1b[mb][j];
-            }
         wave_lds_sync();
-        // dW2[o][i] += sum_e dZ2^T[o][e] H1^T[i][e]: A = dZ2^T (o x e), B = H1 (e x i)
+        // dW2[o][i] += sum_e dZ2^T[o][e] H1^T[i][e]: A = dZ2^T (o x e), B = H1 (e x i), k = 8(l/16)+j
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
-            bf16x4 a;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) a[j] = (short)tr[wv][0][16 * ob + r][4 * g + j];
+            const bf16x8s a = *(const bf16x8s *)&T[kTrDZ2 + 16 * ob + r][8 * g];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) {
-                bf16x4 b;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = (short)tr[wv][1][16 * ib + r][4 * g + j];
-                gW2[ob][ib] = mfma(a, b, gW2[ob][ib]);
+                const bf16x8s b = *(const bf16x8s *)&T[kTrH1 + 16 * ib + r][8 * g];
+                gW2[ob][ib] = mfma32(a, b, gW2[ob][ib]);
             }
         }
-        wave_lds_sync();
-        // dW1[o][f] += sum_e dZ1^T[o][e] X[e][f]: stage dZ1^T; B = X (e x f) from memory
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) tr[wv][0][16 * mb + 4 * g + j][r] = (unsigned short)dz1b[mb][j];
-        wave_lds_sync();
-        bf16x4 xb;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t ee = e0 + 4 * g + j;
-            xb[j] = ee < nnz ? (short)feats[ee * kF + r] : (short)0;
-        }
+        // dW1[o][f] += sum_e dZ1^T[o][e] X[e][f]
+        const bf16x8s xb = *(const bf16x8s *)&T[kTrX + r][8 * g];
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
-            bf16x4 a;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) a[j] = (short)tr[wv][0][16 * ob + r][4 * g + j];
-            gW1[ob] = mfma(a, xb, gW1[ob]);
+            const bf16x8s a = *(const bf16x8s *)&T[kTrDZ1 + 16 * ob + r][8 * g];
+            gW1[ob] = mfma32(a, xb, gW1[ob]);
         }
         wave_lds_sync();
     }
