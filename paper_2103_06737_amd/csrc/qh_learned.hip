@@ -174,17 +174,37 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
     const int l = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-    bf16x4 xn = load_x(feats, wave * 16, nnz);  // the next tile's features are always in flight
-    for (int64_t e0 = wave * 16; e0 < nnz; e0 += nwaves * 16) {
-        const bf16x4 x = xn;
-        xn = load_x(feats, e0 + nwaves * 16, nnz);
+    // two 16-entry tiles per step (two independent MFMA chains); the next step's features and
+    // output scales are always in flight
+    auto load_out = [&](int64_t e0, float &gs, bool &dg) {
+        const int64_t e = e0 + l;
+        gs = 0.f;
+        dg = false;
+        if (l < 32 && e < nnz) {
+            gs = gscale[e];
+            dg = grow[e] == gcol[e];
+        }
+    };
+    bf16x4 xn[2] = {load_x(feats, wave * 32, nnz), load_x(feats, wave * 32 + 16, nnz)};
+    float gsn;
+    bool dgn;
+    load_out(wave * 32, gsn, dgn);
+    for (int64_t e0 = wave * 32; e0 < nnz; e0 += nwaves * 32) {
+        const bf16x4 x0 = xn[0], x1 = xn[1];
+        const float gs = gsn;
+        const bool dg = dgn;
+        xn[0] = load_x(feats, e0 + nwaves * 32, nnz);
+        xn[1] = load_x(feats, e0 + nwaves * 32 + 16, nnz);
+        load_out(e0 + nwaves * 32, gsn, dgn);
         f32x4 z1[4], z2[4];
         bf16x4 h1b[4];
-        float o = tile_forward(F, vec, x, z1, z2, h1b);
+        const float o0 = tile_forward(F, vec, x0, z1, z2, h1b);
+        const float o1 = tile_forward(F, vec, x1, z1, z2, h1b);
         const int64_t e = e0 + l;
-        if (l < 16 && e < nnz) {
+        if (l < 32 && e < nnz) {
+            const float o = l < 16 ? o0 : o1;
             if (o_out) o_out[e] = o;
-            gval[e] = g_of(o, grow[e] == gcol[e], gscale[e]);
+            gval[e] = g_of(o, dg, gs);
         }
     }
 }
@@ -301,19 +321,30 @@ __global__ void __launch_bounds__(256) k_spmm16(int32_t n, const int32_t *__rest
     }
 }
 
-// T = sum of the trace partials / (P n) into loss[1]
-__global__ void __launch_bounds__(256) k_trace_finish(const double *__restrict__ part, int32_t m, int32_t n,
-                                                      double *loss) {
-    __shared__ double sh[256];
-    double t = 0.0;
-    for (int32_t k = threadIdx.x; k < m * kP; k += 256) t += part[k];
-    sh[threadIdx.x] = t;
+// Sum of m partials by one 256-thread block: eight independent strided loads in flight per
+// thread, then a fixed-order tree (deterministic).
+__device__ __forceinline__ double block_sum(const double *__restrict__ part, int32_t m, double *sh) {
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int32_t b = threadIdx.x;
+    for (; b + 7 * 256 < m; b += 8 * 256)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[b + u * 256];
+    for (; b < m; b += 256) s[0] += part[b];
+    sh[threadIdx.x] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     for (int s2 = 128; s2 > 0; s2 >>= 1) {
         if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[1] = sh[0] / ((double)kP * (double)n);
+    return sh[0];
+}
+
+// T = sum of the trace partials / (P n) into loss[1]
+__global__ void __launch_bounds__(256) k_trace_finish(const double *__restrict__ part, int32_t m, int32_t n,
+                                                      double *loss) {
+    __shared__ double sh[256];
+    const double t = block_sum(part, m * kP, sh);
+    if (threadIdx.x == 0) loss[1] = t / ((double)kP * (double)n);
 }
 
 // T = mean_p t_p / |v_p|^2 (|v_p|^2 = n); dG and d o per entry; partials of sum log G_ii.
@@ -372,15 +403,8 @@ __global__ void __launch_bounds__(256) k_kaporin_grad(int64_t nnz, int32_t n, co
 __global__ void __launch_bounds__(256) k_loss_finish(const double *__restrict__ lpart, int32_t m, int32_t n,
                                                      double *loss) {
     __shared__ double sh[256];
-    double s = 0.0;
-    for (int32_t b = threadIdx.x; b < m; b += 256) s += lpart[b];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
-        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[0] = log(loss[1]) - 2.0 / (double)n * sh[0];
+    const double lg = block_sum(lpart, m, sh);
+    if (threadIdx.x == 0) loss[0] = log(loss[1]) - 2.0 / (double)n * lg;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -425,18 +449,23 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_backward(const float *__res
         }
     }
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    // the next step's features and output gradients are always in flight
+    auto load_d = [&](int64_t e) { return e < nnz ? d_o[e] : 0.f; };
     bf16x4 xn[2] = {load_x(feats, wave * 32, nnz), load_x(feats, wave * 32 + 16, nnz)};
+    float dn[2] = {load_d(wave * 32 + r), load_d(wave * 32 + 16 + r)};
     for (int64_t e0 = wave * 32; e0 < nnz; e0 += nwaves * 32) {
         const bf16x4 xt[2] = {xn[0], xn[1]};
+        const float dt[2] = {dn[0], dn[1]};
         xn[0] = load_x(feats, e0 + nwaves * 32, nnz);
         xn[1] = load_x(feats, e0 + nwaves * 32 + 16, nnz);
+        dn[0] = load_d(e0 + nwaves * 32 + r);
+        dn[1] = load_d(e0 + nwaves * 32 + 16 + r);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             f32x4 z1[4], z2[4];
             bf16x4 h1b[4];
             (void)tile_forward(F, vec, xt[s], z1, z2, h1b);
-            const int64_t e = e0 + 16 * s + r;
-            const float dout = e < nnz ? d_o[e] : 0.f;
+            const float dout = dt[s];
             bf16x4 dz2b[4];
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb) {
