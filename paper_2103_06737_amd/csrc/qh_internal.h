@@ -60,6 +60,15 @@ void qh_assemble(const HostMesh &m, double eps0, double mu0, HostCsr &A, HostCsr
 
 // ---------------------------------------------------------------------------------------
 // Device containers
+// Column indices of a tiled matrix as the tiled products read them: a tile whose columns all
+// lie in [b, b + 65535] keeps them as 16-bit offsets from b (tbase[tile] = b); any other tile
+// reads the 32-bit columns (tbase[tile] = -1). tbase == nullptr: 32-bit columns throughout.
+struct TileCols {
+    const int32_t *col;
+    const uint16_t *col16;
+    const int32_t *tbase;
+};
+
 struct DevCsr {
     int32_t n = 0;
     int64_t nnz = 0;
@@ -68,6 +77,9 @@ struct DevCsr {
     double *val2 = nullptr;
     int2 *tiles = nullptr;  // row tiles of the tiled product (qh_spmv.h)
     int32_t ntiles = 0;
+    uint16_t *col16 = nullptr;  // per-tile 16-bit column offsets (TileCols)
+    int32_t *tbase = nullptr;
+    TileCols cols() const { return TileCols{col, col16, tbase}; }
 };
 
 struct Species {
@@ -106,6 +118,8 @@ struct LearnedPrec {
     int32_t *tptr = nullptr, *tcol = nullptr, *tsrc = nullptr;   // G^T rows; tsrc: entry of G
     int2 *gtiles = nullptr, *ttiles = nullptr;                   // row tiles of G and G^T
     int32_t ngtiles = 0, nttiles = 0;
+    uint16_t *gcol16 = nullptr, *tcol16 = nullptr;               // their compact columns (TileCols)
+    int32_t *gtbase = nullptr, *ttbase = nullptr;
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;

@@ -229,14 +229,14 @@ __global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const f
 template <bool DOT>
 __global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict__ tiles, int32_t ntiles,
                                                          const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ col, const uint16_t *__restrict__ val,
+                                                         const TileCols cols, const uint16_t *__restrict__ val,
                                                          const double *__restrict__ in, double *__restrict__ out,
                                                          const double *__restrict__ r, double *__restrict__ part,
                                                          const int32_t *__restrict__ done) {
     if (done && done[0]) return;  // the solve has converged: nothing left to precondition
     __shared__ double prod[kTileCap];
     double acc = 0.0;
-    tile_spmv(tiles, ntiles, ptr, col, val, in, prod, [&](int32_t row) { return DOT ? r[row] : 0.0; },
+    tile_spmv(tiles, ntiles, ptr, cols, val, in, prod, [&](int32_t row) { return DOT ? r[row] : 0.0; },
               [&](int32_t row, double s, double rr) {
         out[row] = s;
         if (DOT) acc += s * rr;
@@ -667,6 +667,17 @@ int qh_learned_setup(qh_ctx *c) {
         if ((rc = qh_alloc(c, &L.gtiles, gt.size())) || (rc = qh_alloc(c, &L.ttiles, tt.size()))) return rc;
         QH_HIP(c, hipMemcpyAsync(L.gtiles, gt.data(), sizeof(int2) * gt.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.ttiles, tt.data(), sizeof(int2) * tt.size(), hipMemcpyHostToDevice, c->stream));
+        std::vector<int32_t> gb, tb;
+        std::vector<uint16_t> g16, t16;
+        qh_compact_cols(gcol.data(), gt, gb, g16);
+        qh_compact_cols(tcol.data(), tt, tb, t16);
+        if ((rc = qh_alloc(c, &L.gtbase, gb.size())) || (rc = qh_alloc(c, &L.ttbase, tb.size())) ||
+            (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())))
+            return rc;
+        QH_HIP(c, hipMemcpyAsync(L.gtbase, gb.data(), 4 * gb.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.ttbase, tb.data(), 4 * tb.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.gcol16, g16.data(), 2 * g16.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.tcol16, t16.data(), 2 * t16.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
         if (!L.have_weights) {
             // He-normal hidden layers, zero output layer: the initial network is Jacobi
@@ -772,9 +783,9 @@ unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
     hipLaunchKernelGGL(k_prec_g<false>, dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, L.gcol, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(k_prec_g<true>, dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, L.tcol, L.tval_h, L.y, z, r, part, done);
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase}, L.tval_h, L.y, z, r, part, done);
     return hipGetLastError();
 }
 

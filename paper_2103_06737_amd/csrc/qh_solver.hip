@@ -6,6 +6,8 @@
 //   ([*eps] + tau S) e* = ([*eps] - tau S) e^n + dt C^T [*mu^-1] b^n - u_q g,   tau = dt^2/4
 // Gauss law (eq. discreteGauss): G^T [*eps] G delta = rho^{n+1} - G^T [*eps] e*, e = e* + G delta
 // Faraday: b^{n+1} = b^n - C round((dt/2)(e^{n+1} + e^n)/u_b)  (D C = 0 keeps D b fixed).
+#include <algorithm>
+
 #include "qh_internal.h"
 #include "qh_spmv.h"
 
@@ -98,7 +100,7 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *__restri
 // init: r = b - A x, z = D^-1 r, p_old = 0; partials of r.z, r.r, b.b
 __global__ void __launch_bounds__(kThreads) k_cg_init(const int2 *__restrict__ tiles, int32_t ntiles,
                                                       const int32_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ col,
+                                                      const TileCols cols,
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ x,
                                                       const double *__restrict__ b,
@@ -107,7 +109,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(const int2 *__restrict__ t
                                                       double *__restrict__ p_old, double *__restrict__ part) {
     __shared__ double prod[kTileCap];
     double acc[3] = {0.0, 0.0, 0.0};
-    tile_spmv(tiles, ntiles, ptr, col, val, x, prod, [&](int32_t row) { return make_double2(b[row], dinv[row]); },
+    tile_spmv(tiles, ntiles, ptr, cols, val, x, prod, [&](int32_t row) { return make_double2(b[row], dinv[row]); },
               [&](int32_t row, double s, double2 bd) {
         const double bb = bd.x;
         const double rr = bb - s;
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict_
 // partials of p.q. Gathering one vector instead of z and p halves the scattered loads.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) k_cg_spmv(int32_t n, const int2 *__restrict__ tiles, int32_t ntiles,
                                                       const int32_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ col,
+                                                      const TileCols cols,
                                                       const double *__restrict__ val,
                                                       const double *__restrict__ z,
                                                       double *__restrict__ p, double *__restrict__ q,
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8
         scal[S_RZ + 1] = scal[S_RZ];
     }
     double acc[1] = {0.0};
-    tile_spmv(tiles, ntiles, ptr, col, val, z, prod, [&](int32_t) { return 0; },
+    tile_spmv(tiles, ntiles, ptr, cols, val, z, prod, [&](int32_t) { return 0; },
               [&](int32_t row, double s, int) {
         const double pn = k > 0 ? z[row] + beta * p[row] : z[row];
         const double qn = k > 0 ? s + beta * q[row] : s;
@@ -252,25 +254,25 @@ __global__ void k_axpy_vals(int64_t n, const double *__restrict__ a, const doubl
 //   rhs_i += dt u_b sum_f (C^T [*mu^-1])_if b_f                          (k_edge_rhs_b)
 __global__ void __launch_bounds__(kThreads) k_edge_rhs_e(const int2 *__restrict__ tiles, int32_t ntiles,
                                                          const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ col,
+                                                         const TileCols cols,
                                                          const double *__restrict__ mval,
                                                          const double *__restrict__ e,
                                                          const int64_t *__restrict__ g,
                                                          const int32_t *__restrict__ int_edges, double u_q,
                                                          double *__restrict__ rhs) {
     __shared__ double prod[kTileCap];
-    tile_spmv(tiles, ntiles, ptr, col, mval, e, prod, [&](int32_t row) { return g[int_edges[row]]; },
+    tile_spmv(tiles, ntiles, ptr, cols, mval, e, prod, [&](int32_t row) { return g[int_edges[row]]; },
               [&](int32_t row, double s, int64_t gi) { rhs[row] = s - u_q * (double)gi; });
 }
 
 __global__ void __launch_bounds__(kThreads) k_edge_rhs_b(const int2 *__restrict__ tiles, int32_t ntiles,
                                                          const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ col,
+                                                         const TileCols cols,
                                                          const double *__restrict__ cval,
                                                          const int64_t *__restrict__ b, double dtub,
                                                          double *__restrict__ rhs) {
     __shared__ double prod[kTileCap];
-    tile_spmv(tiles, ntiles, ptr, col, cval, b, prod, [&](int32_t row) { return rhs[row]; },
+    tile_spmv(tiles, ntiles, ptr, cols, cval, b, prod, [&](int32_t row) { return rhs[row]; },
               [&](int32_t row, double t, double r0) { rhs[row] = r0 + dtub * t; });
 }
 
@@ -362,13 +364,13 @@ __global__ void k_faraday_b(int64_t nf, const int32_t *__restrict__ fe, const in
 // ||b - A x||^2 and ||b||^2 (partials)
 __global__ void __launch_bounds__(kThreads) k_true_res(const int2 *__restrict__ tiles, int32_t ntiles,
                                                        const int32_t *__restrict__ ptr,
-                                                       const int32_t *__restrict__ col,
+                                                       const TileCols cols,
                                                        const double *__restrict__ val,
                                                        const double *__restrict__ x,
                                                        const double *__restrict__ b, double *__restrict__ part) {
     __shared__ double prod[kTileCap];
     double acc[2] = {0.0, 0.0};
-    tile_spmv(tiles, ntiles, ptr, col, val, x, prod, [&](int32_t row) { return b[row]; },
+    tile_spmv(tiles, ntiles, ptr, cols, val, x, prod, [&](int32_t row) { return b[row]; },
               [&](int32_t row, double s, double bb) {
         const double r = bb - s;
         acc[0] += r * r;
@@ -424,7 +426,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     const unsigned ge = grid_elems(w.n), gt = tile_grid(M.ntiles);
     const unsigned gp = learned ? qh_prec_grid(c) : 0;
     int t0 = qh_tbeg(c);
-    hipLaunchKernelGGL(k_cg_init, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, w.x,
+    hipLaunchKernelGGL(k_cg_init, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val, w.x,
                        w.b, w.dinv, w.r, w.z, w.p0, upart);
     if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, nullptr));
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt,
@@ -446,7 +448,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
         for (int k = it; k < it + batch; ++k) {
             int par = k & 1;
             int ta = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr, M.col,
+            hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr, M.cols(),
                                M.val, w.z, w.p0, w.q, learned ? (const double *)ppart : (const double *)upart,
                                learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par);
             qh_tend(c, ta, k_spmv);
@@ -474,7 +476,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     out.iters = hflags[1];
     // true residual, recomputed
     int tr = qh_tbeg(c);
-    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, w.x,
+    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val, w.x,
                        w.b, upart);
     hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + 8);
     qh_tend(c, tr, QK_TRUE_RES);
@@ -501,6 +503,25 @@ bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles) {
     return true;
 }
 
+void qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
+                     std::vector<uint16_t> &col16) {
+    const size_t nt = tiles.size() - 1;
+    tbase.assign(nt, -1);
+    col16.assign((size_t)tiles[nt].y, 0);
+    for (size_t k = 0; k < nt; ++k) {
+        const int32_t e0 = tiles[k].y, e1 = tiles[k + 1].y;
+        if (e1 <= e0) continue;
+        int32_t lo = col[e0], hi = col[e0];
+        for (int32_t e = e0; e < e1; ++e) {
+            lo = std::min(lo, col[e]);
+            hi = std::max(hi, col[e]);
+        }
+        if ((int64_t)hi - lo > 65535) continue;
+        tbase[k] = lo;
+        for (int32_t e = e0; e < e1; ++e) col16[e] = (uint16_t)(col[e] - lo);
+    }
+}
+
 hipError_t launch_assemble_A(qh_ctx *c, double tau) {
     int64_t nnz = c->A.nnz;
     hipLaunchKernelGGL(k_axpy_vals, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, c->stream, nnz, c->A.val2,
@@ -510,10 +531,10 @@ hipError_t launch_assemble_A(qh_ctx *c, double tau) {
 
 hipError_t launch_edge_rhs(qh_ctx *c) {
     hipLaunchKernelGGL(k_edge_rhs_e, dim3(tile_grid(c->A.ntiles)), dim3(kThreads), 0, c->stream, c->A.tiles,
-                       c->A.ntiles, c->A.ptr, c->A.col, c->A_rhs, c->cge.x, c->g, c->int_edges, c->phys.u_q,
+                       c->A.ntiles, c->A.ptr, c->A.cols(), c->A_rhs, c->cge.x, c->g, c->int_edges, c->phys.u_q,
                        c->cge.b);
     hipLaunchKernelGGL(k_edge_rhs_b, dim3(tile_grid(c->CMb.ntiles)), dim3(kThreads), 0, c->stream, c->CMb.tiles,
-                       c->CMb.ntiles, c->CMb.ptr, c->CMb.col, c->CMb.val, c->b, c->phys.dt * c->phys.u_b, c->cge.b);
+                       c->CMb.ntiles, c->CMb.ptr, c->CMb.cols(), c->CMb.val, c->b, c->phys.dt * c->phys.u_b, c->cge.b);
     return hipGetLastError();
 }
 
@@ -546,7 +567,7 @@ hipError_t launch_faraday(qh_ctx *c) {
 
 hipError_t launch_true_residual(qh_ctx *c, const DevCsr &M, const double *x, const double *b, double *out2) {
     const unsigned gt = tile_grid(M.ntiles);
-    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.col, M.val, x, b,
+    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val, x, b,
                        c->cge.partial);
     hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, c->cge.partial, (int)gt, out2);
     return hipGetLastError();

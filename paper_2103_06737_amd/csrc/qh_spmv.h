@@ -7,7 +7,8 @@
 // column loads are coalesced and independent of the row structure, so many are in flight at
 // once), keeping them in LDS; then thread t adds up the products of row (first row + t) and
 // hands the sum to an epilogue. Against one row per lane group this removes the chain of
-// dependent loads (row pointer -> entries -> gathered vector) per row.
+// dependent loads (row pointer -> entries -> gathered vector) per row. Column indices are read
+// as 16-bit offsets from a per-tile base wherever the tile's columns allow it (TileCols).
 #pragma once
 
 #include "qh_internal.h"
@@ -20,6 +21,11 @@ constexpr int kTileUnroll = 8;           // product loads issued together per th
 // Tile starts {first row, first entry}; tiles[ntiles] = {n, nnz}. Rows longer than kTileCap
 // entries are not supported (returns false).
 bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles);
+
+// Compact columns of every tile (TileCols): tbase[k] = smallest column of tile k when its
+// columns span at most 65536 values (col16 then holds column - tbase[k]), else -1.
+void qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
+                     std::vector<uint16_t> &col16);
 
 // Entry values: FP64, FP32, or BF16 (stored as its 16 bits), all widened to FP64.
 __device__ __forceinline__ double tile_val(double v) { return v; }
@@ -44,7 +50,7 @@ __device__ __forceinline__ void tile_range(int32_t ntiles, int32_t &tb, int32_t 
 // must call it (it synchronises the block).
 template <typename VT, typename XG, typename Pre, typename Epi>
 __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int32_t ntiles,
-                                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                            const int32_t *__restrict__ ptr, const TileCols cols,
                                             const VT *__restrict__ val, XG &&xg,
                                             double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
     using PF = decltype(pre(0));
@@ -53,8 +59,10 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
     if (tb >= te) return;  // the same for every thread of the block
     const int tid = threadIdx.x;
     int2 t0 = tiles[tb], t1 = tiles[tb + 1];
+    int32_t base0 = cols.tbase ? cols.tbase[tb] : -1;
     for (int32_t ti = tb; ti < te; ++ti) {
         const int2 t2 = tiles[ti + 2 <= ntiles ? ti + 2 : ntiles];
+        const int32_t base1 = cols.tbase && ti + 1 < ntiles ? cols.tbase[ti + 1] : -1;
         const int32_t row = t0.x + tid;
         int32_t js = 0, je = 0;
         PF pf{};
@@ -67,12 +75,22 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
         for (int32_t b = 0; b < cnt; b += kTileUnroll * kTileThreads) {
             VT v[kTileUnroll];
             int32_t c[kTileUnroll];
+            if (base0 >= 0) {  // the same for the whole block
 #pragma unroll
-            for (int u = 0; u < kTileUnroll; ++u) {
-                int32_t j = b + u * kTileThreads + tid;
-                j = j < cnt ? j : cnt - 1;  // clamped: every load stays inside the tile
-                v[u] = val[t0.y + j];
-                c[u] = col[t0.y + j];
+                for (int u = 0; u < kTileUnroll; ++u) {
+                    int32_t j = b + u * kTileThreads + tid;
+                    j = j < cnt ? j : cnt - 1;  // clamped: every load stays inside the tile
+                    v[u] = val[t0.y + j];
+                    c[u] = base0 + (int32_t)cols.col16[t0.y + j];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kTileUnroll; ++u) {
+                    int32_t j = b + u * kTileThreads + tid;
+                    j = j < cnt ? j : cnt - 1;
+                    v[u] = val[t0.y + j];
+                    c[u] = cols.col[t0.y + j];
+                }
             }
             double xv[kTileUnroll];
 #pragma unroll
@@ -92,16 +110,17 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
         __syncthreads();
         t0 = t1;
         t1 = t2;
+        base0 = base1;
     }
 }
 
 // The same with the gathered vector read from memory (converted to FP64).
 template <typename VT, typename XT, typename Pre, typename Epi>
 __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
-                                          const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                          const int32_t *__restrict__ ptr, const TileCols cols,
                                           const VT *__restrict__ val, const XT *__restrict__ x,
                                           double *prod /* LDS, kTileCap */, Pre &&pre, Epi &&epi) {
-    tile_spmv_g(tiles, ntiles, ptr, col, val, [&](int32_t j) { return (double)x[j]; }, prod, pre, epi);
+    tile_spmv_g(tiles, ntiles, ptr, cols, val, [&](int32_t j) { return (double)x[j]; }, prod, pre, epi);
 }
 
 // Grid of a tiled product: one block per tile up to 2048 blocks, a multiple of 8.
