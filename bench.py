@@ -70,8 +70,10 @@ def setup(wl: str, n_particles: int | None):
 def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False):
     """Bytes one launch must move at least (each datum read or written once)."""
     if kernel in ("cg_spmv",):
-        n, nnz = mi.n_int_edges, mi.nnz_edge
-        return 12 * nnz + 4 * (n + 1) + 32 * n          # A (val+col), rowptr, z, p_old in; p_new, q out
+        # A: FP64 value + column (2 bytes in tiles read with 16-bit offsets, else 4); rowptr;
+        # z, p_old in; p_new, q out
+        n, nnz, c16 = mi.n_int_edges, mi.nnz_edge, mi.nnz_edge_c16
+        return 8 * nnz + 2 * c16 + 4 * (nnz - c16) + 4 * (n + 1) + 32 * n
     if kernel in ("node_spmv",):
         n, nnz = mi.n_int_nodes, mi.nnz_node
         return 12 * nnz + 4 * (n + 1) + 32 * n
@@ -86,11 +88,11 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
         # accumulators read-modify-write once (16 B per edge and node)
         return 56 * n_particles + 136 * mi.n_tets + 152 * crossings + 16 * (mi.n_edges + mi.n_nodes)
     if kernel == "precond":
-        # z = G^T (G r): two CSR passes over the lower factor (BF16 value + int32 column per
-        # entry) and its transpose; per row: r in, y out, y in, z out, r in (dot), row pointers
-        n, nnz = mi.n_int_edges, mi.nnz_edge
-        nnz_l = (nnz + n) // 2
-        return 12 * nnz_l + 40 * n + 8 * (n + 1)
+        # z = G^T (G r): two CSR passes over the lower factor and its transpose (BF16 value,
+        # column of 2 or 4 bytes as in cg_spmv); per row: r in, y out, y in, z out, r in (dot),
+        # row pointers
+        n, nnz_l, c16 = mi.n_int_edges, mi.nnz_factor, mi.nnz_factor_c16
+        return 4 * nnz_l + 2 * c16 + 4 * (2 * nnz_l - c16) + 40 * n + 8 * (n + 1)
     if kernel == "field_prep":
         return (48 + 24 + 16 + 48) * mi.n_tets + 8 * mi.n_edges + 8 * mi.n_faces
     return None
@@ -99,15 +101,18 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
 # HIP kernels behind each timed entry (one entry may launch several kernels)
 HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
                "precond": ["k_prec_g<false>", "k_prec_g<true>"],
-               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0>", "k_gather<6>"],
-               "edge_rhs": ["k_edge_rhs"], "field_prep": ["k_field_prep"]}
+               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
+               "edge_rhs": ["k_edge_rhs_e", "k_edge_rhs_b"], "field_prep": ["k_field_prep"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_64cube_16M.md")
+# headers every kernel file includes: part of the source a traffic figure was taken from
+SHARED_SOURCES = ["paper_2103_06737_amd/csrc/qh_spmv.h", "paper_2103_06737_amd/csrc/qh_internal.h"]
 
 
 def measured_traffic(entry: str, workload: str):
     """HBM bytes per launch from the profiler's byte counters (scaled by the copy calibration),
     as recorded in the traffic summary; None when the summary is absent, covers another
-    workload, or any kernel's source file has changed since the counters were taken."""
+    workload, or any kernel's source (its file and the shared headers) has changed since the
+    counters were taken."""
     import hashlib
     if workload != "c3" or entry not in HIP_KERNELS or not os.path.exists(TRAFFIC_FILE):
         return None
@@ -122,9 +127,12 @@ def measured_traffic(entry: str, workload: str):
         if k not in rows or len(rows[k][1]) != 2:
             return None
         path, digest = rows[k][1]
-        with open(os.path.join(ROOT, path), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest()[:16] != digest:
-                return None
+        data = b""
+        for p in [path] + SHARED_SOURCES:
+            with open(os.path.join(ROOT, p), "rb") as fh:
+                data += fh.read()
+        if hashlib.sha256(data).hexdigest()[:16] != digest:
+            return None
         total += rows[k][0]
     return int(total)
 
@@ -273,6 +281,7 @@ def main():
     ms_step = 1e3 * wall / args.steps
     value = n_p * args.steps / wall
     crossings = float(np.mean([s["crossings"] for s in pst]))
+    mi = ctx.mesh_info()  # now with the learned factor's sizes
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
 
     def roof(k, kern):

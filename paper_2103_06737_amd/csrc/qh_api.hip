@@ -66,7 +66,7 @@ int upload_csr(qh_ctx *c, DevCsr &d, const HostCsr &h, bool two) {
     if ((rc = upload(c, &d.tiles, tiles.data(), tiles.size()))) return rc;
     std::vector<int32_t> tbase;
     std::vector<uint16_t> col16;
-    qh_compact_cols(h.col.data(), tiles, tbase, col16);
+    d.nnz_c16 = qh_compact_cols(h.col.data(), tiles, tbase, col16);
     if ((rc = upload(c, &d.tbase, tbase.data(), tbase.size()))) return rc;
     if ((rc = upload(c, &d.col16, col16.data(), col16.size()))) return rc;
     return QH_OK;
@@ -287,6 +287,9 @@ int qh_mesh_info(const qh_ctx *c, qh_mesh_info_t *out) {
     out->n_int_edges = (int64_t)m.int_edges.size();
     out->nnz_edge = (int64_t)c->hA.col.size();
     out->nnz_node = (int64_t)c->hK.col.size();
+    out->nnz_edge_c16 = c->A.nnz_c16;
+    out->nnz_factor = c->lp.built ? c->lp.nnz : 0;
+    out->nnz_factor_c16 = c->lp.built ? c->lp.nnz_c16 : 0;
     return QH_OK;
 }
 

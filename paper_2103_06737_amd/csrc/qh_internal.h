@@ -79,6 +79,7 @@ struct DevCsr {
     int32_t ntiles = 0;
     uint16_t *col16 = nullptr;  // per-tile 16-bit column offsets (TileCols)
     int32_t *tbase = nullptr;
+    int64_t nnz_c16 = 0;        // entries in tiles with 16-bit columns
     TileCols cols() const { return TileCols{col, col16, tbase}; }
 };
 
@@ -120,6 +121,7 @@ struct LearnedPrec {
     int32_t ngtiles = 0, nttiles = 0;
     uint16_t *gcol16 = nullptr, *tcol16 = nullptr;               // their compact columns (TileCols)
     int32_t *gtbase = nullptr, *ttbase = nullptr;
+    int64_t nnz_c16 = 0;                                         // entries of G and G^T in such tiles
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;

@@ -669,8 +669,7 @@ int qh_learned_setup(qh_ctx *c) {
         QH_HIP(c, hipMemcpyAsync(L.ttiles, tt.data(), sizeof(int2) * tt.size(), hipMemcpyHostToDevice, c->stream));
         std::vector<int32_t> gb, tb;
         std::vector<uint16_t> g16, t16;
-        qh_compact_cols(gcol.data(), gt, gb, g16);
-        qh_compact_cols(tcol.data(), tt, tb, t16);
+        L.nnz_c16 = qh_compact_cols(gcol.data(), gt, gb, g16) + qh_compact_cols(tcol.data(), tt, tb, t16);
         if ((rc = qh_alloc(c, &L.gtbase, gb.size())) || (rc = qh_alloc(c, &L.ttbase, tb.size())) ||
             (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())))
             return rc;

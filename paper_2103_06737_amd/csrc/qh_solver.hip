@@ -503,8 +503,9 @@ bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles) {
     return true;
 }
 
-void qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
-                     std::vector<uint16_t> &col16) {
+int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
+                        std::vector<uint16_t> &col16) {
+    int64_t n16 = 0;
     const size_t nt = tiles.size() - 1;
     tbase.assign(nt, -1);
     col16.assign((size_t)tiles[nt].y, 0);
@@ -519,7 +520,9 @@ void qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::ve
         if ((int64_t)hi - lo > 65535) continue;
         tbase[k] = lo;
         for (int32_t e = e0; e < e1; ++e) col16[e] = (uint16_t)(col[e] - lo);
+        n16 += e1 - e0;
     }
+    return n16;
 }
 
 hipError_t launch_assemble_A(qh_ctx *c, double tau) {

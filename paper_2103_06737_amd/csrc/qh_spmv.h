@@ -23,8 +23,9 @@ constexpr int kTileUnroll = 8;           // product loads issued together per th
 bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles);
 
 // Compact columns of every tile (TileCols): tbase[k] = smallest column of tile k when its
-// columns span at most 65536 values (col16 then holds column - tbase[k]), else -1.
-void qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
+// columns span at most 65536 values (col16 then holds column - tbase[k]), else -1. Returns the
+// number of entries in such tiles.
+int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
                      std::vector<uint16_t> &col16);
 
 // Entry values: FP64, FP32, or BF16 (stored as its 16 bits), all widened to FP64.
