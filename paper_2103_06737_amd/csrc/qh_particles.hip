@@ -14,6 +14,8 @@
 // faces by vertex id) the piece adds z (L_a^0 L_b^1 - L_a^1 L_b^0) to edge a->b and the end
 // point adds z 2^20 L_n to node n. G^T g then telescopes to Q^{n+1} - Q^n in int64: discrete
 // continuity holds bit for bit and the sums are independent of order.
+#include <type_traits>
+
 #include "qh_internal.h"
 
 namespace {
@@ -149,9 +151,9 @@ void launch_field_prep(qh_ctx *c) {
 // L_a^0 L_b^1 - L_a^1 L_b^0, nodes sum the L_n of end points; the charge number and 2^20 scale
 // them when they leave LDS). A piece in a tet outside the window (a particle that moved since
 // the sort, a walk piece past the range) is posted as one compact record into the mailbox of
-// that tet's run of kMailTets tets; slots are reserved with one 32-bit atomic per wave and
-// mailbox instead of ten 64-bit atomics per piece. k_mail_apply adds each mailbox into acc_tet, and the gather
-// kernels add acc_tet into edges and nodes. Only records that find no mailbox slot use int64
+// that tet's run of kMailTets tets; a slot costs one 32-bit atomic (per wave and mailbox on the
+// fast path, per piece in the walk) instead of ten 64-bit atomics per piece. k_mail_apply adds
+// each mailbox into acc_tet, and the gather kernels add acc_tet into edges and nodes. Only records that find no mailbox slot use int64
 // atomics on edges and nodes. Integer sums do not depend on order, so the result is the same
 // bits on every path.
 
@@ -192,22 +194,29 @@ __device__ __forceinline__ void put_lds(long long *acc, int slot, const long lon
 }
 
 // A piece in a tet outside the window: one record into the tet's mailbox, or, when the
-// mailbox is full, int64 atomics on edges and nodes.
+// mailbox is full, int64 atomics on edges and nodes. GROUP: slots are reserved with one atomic
+// per distinct mailbox among the active lanes (the lanes' tets cluster in a few mailboxes, as in
+// the fast path); otherwise one atomic per lane (walk pieces scatter over the neighbours in all
+// directions, and a serial loop over their mailboxes costs more than it saves).
+template <bool GROUP>
 __device__ __forceinline__ void post_piece(const StepArgs &a, int tt, const int P0[4], const int P1[4], bool end) {
     const int o = tt / kMailTets;
-    // slots are reserved with one atomic per distinct mailbox among the active lanes
     unsigned int slot = 0xffffffffu;
-    const int lane = __lane_id();
-    unsigned long long pending = __ballot(1);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int lo = __shfl(o, leader);
-        const unsigned long long same = __ballot(o == lo);
-        unsigned int first = 0;
-        if (lane == leader) first = atomicAdd(&a.mail_cnt[lo], (unsigned int)__popcll(same));
-        first = (unsigned int)__shfl((int)first, leader);
-        if (o == lo) slot = first + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
-        pending &= ~same;
+    if (GROUP) {
+        const int lane = __lane_id();
+        unsigned long long pending = __ballot(1);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int lo = __shfl(o, leader);
+            const unsigned long long same = __ballot(o == lo);
+            unsigned int first = 0;
+            if (lane == leader) first = atomicAdd(&a.mail_cnt[lo], (unsigned int)__popcll(same));
+            first = (unsigned int)__shfl((int)first, leader);
+            if (o == lo) slot = first + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+            pending &= ~same;
+        }
+    } else {
+        slot = atomicAdd(&a.mail_cnt[o], 1u);
     }
     if (slot < (unsigned)kMailCap) {
         int32_t *box = a.mail + (int64_t)o * kMailCap * kMailWords;
@@ -356,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     unsigned int n_cross = 0, n_wall = 0, n_lost = 0, n_foreign = 0;
-    auto deposit = [&](int tt, const int P0[4], const int P1[4], bool end) {
+    auto deposit_to = [&](auto group, int tt, const int P0[4], const int P1[4], bool end) {
         const int slot = tt - T0;
         if ((unsigned)slot < (unsigned)W) {
             long long v[10];
@@ -364,8 +373,15 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             put_lds<kWin>(acc, slot, v);
         } else {
             ++n_foreign;
-            post_piece(a, tt, P0, P1, end);
+            post_piece<decltype(group)::value>(a, tt, P0, P1, end);
         }
+    };
+    // fast path: grouped mailbox reservations; walk: one per lane
+    auto deposit = [&](int tt, const int P0[4], const int P1[4], bool end) {
+        deposit_to(std::true_type{}, tt, P0, P1, end);
+    };
+    auto deposit_walk = [&](int tt, const int P0[4], const int P1[4], bool end) {
+        deposit_to(std::false_type{}, tt, P0, P1, end);
     };
 
     // ---- phase A
@@ -504,7 +520,7 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             t = a.tet[i];
         }
         const int32_t pid = CAPTURE ? a.pid[i] : 0;
-        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit, n_cross, n_wall, n_lost);
+        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit_walk, n_cross, n_wall, n_lost);
         a.x[i] = px; a.y[i] = py; a.z[i] = pz;
         a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
         a.tet[i] = t;
