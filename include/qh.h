@@ -62,8 +62,9 @@ typedef struct {
     int64_t n_int_nodes, n_int_edges; /* unknowns of the node and edge systems */
     int64_t nnz_edge, nnz_node;       /* nonzeros of the two system matrices */
     int64_t nnz_edge_c16;             /* nonzeros of the edge matrix whose column index the products
-                                         read as a 16-bit offset from their tile's base (the rest:
-                                         32-bit); 0 until the matrices are assembled on the device */
+                                         read as 16 bits (one of four windows of 2^14 columns per
+                                         row tile, and the offset in it; the rest: 32-bit); 0 until
+                                         the matrices are assembled on the device */
     int64_t nnz_factor, nnz_factor_c16; /* entries of the learned factor G (lower triangle of the
                                          edge pattern) and of G and G^T together read with 16-bit
                                          columns; 0 until the learned preconditioner is built */

@@ -64,7 +64,7 @@ int upload_csr(qh_ctx *c, DevCsr &d, const HostCsr &h, bool two) {
     if (!qh_make_tiles(h.ptr.data(), d.n, tiles)) return qh_fail(c, QH_EINVAL, "matrix row longer than a product tile");
     d.ntiles = (int32_t)tiles.size() - 1;
     if ((rc = upload(c, &d.tiles, tiles.data(), tiles.size()))) return rc;
-    std::vector<int32_t> tbase;
+    std::vector<int4> tbase;
     std::vector<uint16_t> col16;
     d.nnz_c16 = qh_compact_cols(h.col.data(), tiles, tbase, col16);
     if ((rc = upload(c, &d.tbase, tbase.data(), tbase.size()))) return rc;

@@ -60,13 +60,16 @@ void qh_assemble(const HostMesh &m, double eps0, double mu0, HostCsr &A, HostCsr
 
 // ---------------------------------------------------------------------------------------
 // Device containers
-// Column indices of a tiled matrix as the tiled products read them: a tile whose columns all
-// lie in [b, b + 65535] keeps them as 16-bit offsets from b (tbase[tile] = b); any other tile
-// reads the 32-bit columns (tbase[tile] = -1). tbase == nullptr: 32-bit columns throughout.
+// Column indices of a tiled matrix as the tiled products read them. A tile whose columns lie in
+// at most four windows [w_k, w_k + 2^14) keeps each as 16 bits: the window number in the top two
+// bits, the offset from its start in the low fourteen (tbase[tile] = {w_0, w_1, w_2, w_3}); a
+// row couples a few index clusters (on a box mesh: the layers below, at and above it), each
+// narrow. Any other tile reads the 32-bit columns (tbase[tile].x = -1). tbase == nullptr: 32-bit
+// columns throughout.
 struct TileCols {
     const int32_t *col;
     const uint16_t *col16;
-    const int32_t *tbase;
+    const int4 *tbase;
 };
 
 struct DevCsr {
@@ -77,8 +80,8 @@ struct DevCsr {
     double *val2 = nullptr;
     int2 *tiles = nullptr;  // row tiles of the tiled product (qh_spmv.h)
     int32_t ntiles = 0;
-    uint16_t *col16 = nullptr;  // per-tile 16-bit column offsets (TileCols)
-    int32_t *tbase = nullptr;
+    uint16_t *col16 = nullptr;  // per-tile 16-bit columns (TileCols)
+    int4 *tbase = nullptr;
     int64_t nnz_c16 = 0;        // entries in tiles with 16-bit columns
     TileCols cols() const { return TileCols{col, col16, tbase}; }
 };
@@ -120,7 +123,7 @@ struct LearnedPrec {
     int2 *gtiles = nullptr, *ttiles = nullptr;                   // row tiles of G and G^T
     int32_t ngtiles = 0, nttiles = 0;
     uint16_t *gcol16 = nullptr, *tcol16 = nullptr;               // their compact columns (TileCols)
-    int32_t *gtbase = nullptr, *ttbase = nullptr;
+    int4 *gtbase = nullptr, *ttbase = nullptr;
     int64_t nnz_c16 = 0;                                         // entries of G and G^T in such tiles
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)

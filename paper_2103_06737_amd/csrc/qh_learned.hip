@@ -667,14 +667,14 @@ int qh_learned_setup(qh_ctx *c) {
         if ((rc = qh_alloc(c, &L.gtiles, gt.size())) || (rc = qh_alloc(c, &L.ttiles, tt.size()))) return rc;
         QH_HIP(c, hipMemcpyAsync(L.gtiles, gt.data(), sizeof(int2) * gt.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.ttiles, tt.data(), sizeof(int2) * tt.size(), hipMemcpyHostToDevice, c->stream));
-        std::vector<int32_t> gb, tb;
+        std::vector<int4> gb, tb;
         std::vector<uint16_t> g16, t16;
         L.nnz_c16 = qh_compact_cols(gcol.data(), gt, gb, g16) + qh_compact_cols(tcol.data(), tt, tb, t16);
         if ((rc = qh_alloc(c, &L.gtbase, gb.size())) || (rc = qh_alloc(c, &L.ttbase, tb.size())) ||
             (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())))
             return rc;
-        QH_HIP(c, hipMemcpyAsync(L.gtbase, gb.data(), 4 * gb.size(), hipMemcpyHostToDevice, c->stream));
-        QH_HIP(c, hipMemcpyAsync(L.ttbase, tb.data(), 4 * tb.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.gtbase, gb.data(), sizeof(int4) * gb.size(), hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(L.ttbase, tb.data(), sizeof(int4) * tb.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.gcol16, g16.data(), 2 * g16.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.tcol16, t16.data(), 2 * t16.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));

@@ -503,23 +503,38 @@ bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles) {
     return true;
 }
 
-int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
+int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int4> &tbase,
                         std::vector<uint16_t> &col16) {
-    int64_t n16 = 0;
+    constexpr int32_t kSpan = 1 << 14;
     const size_t nt = tiles.size() - 1;
-    tbase.assign(nt, -1);
+    tbase.assign(nt, make_int4(-1, 0, 0, 0));
     col16.assign((size_t)tiles[nt].y, 0);
+    int64_t n16 = 0;
+    std::vector<int32_t> cs;
     for (size_t k = 0; k < nt; ++k) {
         const int32_t e0 = tiles[k].y, e1 = tiles[k + 1].y;
         if (e1 <= e0) continue;
-        int32_t lo = col[e0], hi = col[e0];
-        for (int32_t e = e0; e < e1; ++e) {
-            lo = std::min(lo, col[e]);
-            hi = std::max(hi, col[e]);
+        cs.assign(col + e0, col + e1);
+        std::sort(cs.begin(), cs.end());
+        int32_t w[4];
+        int nw = 0;
+        bool fits = true;
+        for (int32_t v : cs) {
+            if (nw > 0 && v < w[nw - 1] + kSpan) continue;
+            if (nw == 4) {
+                fits = false;
+                break;
+            }
+            w[nw++] = v;
         }
-        if ((int64_t)hi - lo > 65535) continue;
-        tbase[k] = lo;
-        for (int32_t e = e0; e < e1; ++e) col16[e] = (uint16_t)(col[e] - lo);
+        if (!fits) continue;
+        for (int i = nw; i < 4; ++i) w[i] = w[nw - 1];
+        tbase[k] = make_int4(w[0], w[1], w[2], w[3]);
+        for (int32_t e = e0; e < e1; ++e) {
+            int i = nw - 1;
+            while (col[e] < w[i]) --i;  // the last window starting at or below the column
+            col16[e] = (uint16_t)((uint32_t)i << 14 | (uint32_t)(col[e] - w[i]));
+        }
         n16 += e1 - e0;
     }
     return n16;

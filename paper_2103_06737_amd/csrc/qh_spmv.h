@@ -8,7 +8,7 @@
 // once), keeping them in LDS; then thread t adds up the products of row (first row + t) and
 // hands the sum to an epilogue. Against one row per lane group this removes the chain of
 // dependent loads (row pointer -> entries -> gathered vector) per row. Column indices are read
-// as 16-bit offsets from a per-tile base wherever the tile's columns allow it (TileCols).
+// as 16 bits (a window of the tile and an offset in it) wherever the tile allows it (TileCols).
 #pragma once
 
 #include "qh_internal.h"
@@ -22,11 +22,11 @@ constexpr int kTileUnroll = 8;           // product loads issued together per th
 // entries are not supported (returns false).
 bool qh_make_tiles(const int32_t *ptr, int32_t n, std::vector<int2> &tiles);
 
-// Compact columns of every tile (TileCols): tbase[k] = smallest column of tile k when its
-// columns span at most 65536 values (col16 then holds column - tbase[k]), else -1. Returns the
-// number of entries in such tiles.
-int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int32_t> &tbase,
-                     std::vector<uint16_t> &col16);
+// Compact columns of every tile (TileCols): the windows of tile k are laid greedily from its
+// smallest column up (each starts at the smallest column not yet covered); a tile that needs more
+// than four keeps 32-bit columns (tbase[k].x = -1). Returns the number of entries in compact tiles.
+int64_t qh_compact_cols(const int32_t *col, const std::vector<int2> &tiles, std::vector<int4> &tbase,
+                        std::vector<uint16_t> &col16);
 
 // Entry values: FP64, FP32, or BF16 (stored as its 16 bits), all widened to FP64.
 __device__ __forceinline__ double tile_val(double v) { return v; }
@@ -45,6 +45,15 @@ __device__ __forceinline__ void tile_range(int32_t ntiles, int32_t &tb, int32_t 
     if (tb > ntiles) tb = ntiles;
 }
 
+// Tile headers and window bases are the same for the whole block: kept in scalar registers.
+__device__ __forceinline__ int2 uniform2(int2 v) {
+    return make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y));
+}
+__device__ __forceinline__ int4 uniform4(int4 v) {
+    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
 // For every row of this block's tiles: epi(row, sum_j a_row,j xg(j), pre(row)). pre(row) loads what the epilogue needs from the row's own entries; it is issued with
 // the tile's entry loads, and the next tile's header is fetched one tile ahead, so a tile costs
 // two dependent memory round trips (entries, then gathered vector). All threads of the block
@@ -59,11 +68,11 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
     tile_range(ntiles, tb, te);
     if (tb >= te) return;  // the same for every thread of the block
     const int tid = threadIdx.x;
-    int2 t0 = tiles[tb], t1 = tiles[tb + 1];
-    int32_t base0 = cols.tbase ? cols.tbase[tb] : -1;
+    int2 t0 = uniform2(tiles[tb]), t1 = uniform2(tiles[tb + 1]);
+    int4 base0 = uniform4(cols.tbase ? cols.tbase[tb] : make_int4(-1, 0, 0, 0));
     for (int32_t ti = tb; ti < te; ++ti) {
-        const int2 t2 = tiles[ti + 2 <= ntiles ? ti + 2 : ntiles];
-        const int32_t base1 = cols.tbase && ti + 1 < ntiles ? cols.tbase[ti + 1] : -1;
+        const int2 t2 = uniform2(tiles[ti + 2 <= ntiles ? ti + 2 : ntiles]);
+        const int4 base1 = uniform4(cols.tbase && ti + 1 < ntiles ? cols.tbase[ti + 1] : make_int4(-1, 0, 0, 0));
         const int32_t row = t0.x + tid;
         int32_t js = 0, je = 0;
         PF pf{};
@@ -76,13 +85,15 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
         for (int32_t b = 0; b < cnt; b += kTileUnroll * kTileThreads) {
             VT v[kTileUnroll];
             int32_t c[kTileUnroll];
-            if (base0 >= 0) {  // the same for the whole block
+            if (base0.x >= 0) {  // the same for the whole block
 #pragma unroll
                 for (int u = 0; u < kTileUnroll; ++u) {
                     int32_t j = b + u * kTileThreads + tid;
                     j = j < cnt ? j : cnt - 1;  // clamped: every load stays inside the tile
                     v[u] = val[t0.y + j];
-                    c[u] = base0 + (int32_t)cols.col16[t0.y + j];
+                    const uint32_t h = cols.col16[t0.y + j];
+                    const uint32_t w = h >> 14;
+                    c[u] = (w == 0 ? base0.x : w == 1 ? base0.y : w == 2 ? base0.z : base0.w) + (int32_t)(h & 0x3fffu);
                 }
             } else {
 #pragma unroll
