@@ -28,9 +28,9 @@ sys.path.insert(0, ROOT)
 import qh_inputs as qi  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = {"c3": "64^3 Kuhn cube, 16M-electron uniform plasma, full implicit cycle",
-             "c2": "32^3 Kuhn cube, 1M-electron beam in frozen random fields",
-             "c5": "96^3 Kuhn cube graded toward z=0 (ratio 1.05), 32M electrons + 32M ions, full implicit cycle"}
+WORKLOADS = {"plasma64": "64^3 Kuhn cube, 16M-electron uniform plasma, full implicit cycle",
+             "beam32": "32^3 Kuhn cube, 1M-electron beam in frozen random fields",
+             "graded96": "96^3 Kuhn cube graded toward z=0 (ratio 1.05), 32M electrons + 32M ions, full implicit cycle"}
 
 
 def log(*a):
@@ -103,7 +103,7 @@ HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
                "precond": ["k_prec_g<false>", "k_prec_g<true>"],
                "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
                "edge_rhs": ["k_edge_rhs_e", "k_edge_rhs_b"], "field_prep": ["k_field_prep"]}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_64cube_16M.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plasma_64cube_16M.md")
 # headers every kernel file includes: part of the source a traffic figure was taken from
 SHARED_SOURCES = ["paper_2103_06737_amd/csrc/qh_spmv.h", "paper_2103_06737_amd/csrc/qh_internal.h"]
 
@@ -114,7 +114,7 @@ def measured_traffic(entry: str, workload: str):
     workload, or any kernel's source (its file and the shared headers) has changed since the
     counters were taken."""
     import hashlib
-    if workload != "c3" or entry not in HIP_KERNELS or not os.path.exists(TRAFFIC_FILE):
+    if workload != "plasma64" or entry not in HIP_KERNELS or not os.path.exists(TRAFFIC_FILE):
         return None
     rows = {}
     for line in open(TRAFFIC_FILE):
@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="plasma64", choices=sorted(WORKLOADS))
     ap.add_argument("--particles", type=int, default=None, help="override the particle count")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -166,16 +166,16 @@ def white(count: int, seed: int = 0, stream: int = 3) -> np.ndarray:
 
 CONFIGS = {
     # jittered 4^3 Kuhn cube, 1,000 electrons, full cycle, 100 steps
-    "c1": dict(n=4, jitter=0.1, z_ratio=1.0, n_e=1000, n_i=0, v_th_e=1e6, v_th_i=0.0,
+    "jitter4": dict(n=4, jitter=0.1, z_ratio=1.0, n_e=1000, n_i=0, v_th_e=1e6, v_th_i=0.0,
                weight=1.0, dt=1e-11, steps=100, sigma_e=1e3, bz=0.1, sigma_b=0.0,
                mode="solve", load="uniform"),
     # 32^3, 1M-electron beam in frozen random fields, 200 steps
-    "c2": dict(n=32, jitter=0.0, z_ratio=1.0, n_e=1_000_000, n_i=0, v_th_e=1e5, v_th_i=0.0,
+    "beam32": dict(n=32, jitter=0.0, z_ratio=1.0, n_e=1_000_000, n_i=0, v_th_e=1e5, v_th_i=0.0,
                weight=1.0, dt=1e-11, steps=200, sigma_e=1e4, bz=0.1, sigma_b=1e-3,
                mode="frozen", load="beam", beam_sigma=0.1, drift_z=1e7),
     # 64^3, 16M-electron uniform plasma (n = 1e16 m^-3), full cycle at 10x the explicit
     # limit (dt_CFL(64^3) ~ 1.20e-11 s from the oracle's eigen-analysis, oracle/cfl.py)
-    "c3": dict(n=64, jitter=0.0, z_ratio=1.0, n_e=16_000_000, n_i=0, v_th_e=1e6, v_th_i=0.0,
+    "plasma64": dict(n=64, jitter=0.0, z_ratio=1.0, n_e=16_000_000, n_i=0, v_th_e=1e6, v_th_i=0.0,
                weight=1e16 / 16_000_000, dt=1.2e-10, steps=100, sigma_e=0.0, bz=0.1,
                sigma_b=0.0, mode="solve", load="uniform", sort_every=20),
     # 96^3 graded toward z=0 (ratio 1.05), 32M electrons + 32M ions, quiet start
@@ -183,7 +183,7 @@ CONFIGS = {
     # explicit limit. dt_CFL: the oracle's eigen-analysis of a 16^3 mesh graded to the same
     # thinnest-cell aspect (22:1, ratio 1.35) gives n * dt_CFL = 5.32e-10 s, so ~5.5e-12 s at
     # n = 96 (the thin layers cost only a factor 1.45 against the uniform lattice).
-    "c5": dict(n=96, jitter=0.0, z_ratio=1.05, n_e=32_000_000, n_i=32_000_000, v_th_e=1e6,
+    "graded96": dict(n=96, jitter=0.0, z_ratio=1.05, n_e=32_000_000, n_i=32_000_000, v_th_e=1e6,
                v_th_i=2e4, weight=1e16 / 32_000_000, dt_cfl_mult=10.0, dt=5.5e-11, steps=200,
                sigma_e=0.0, bz=0.1, sigma_b=0.0, mode="solve", load="uniform", sort_every=20),
 }

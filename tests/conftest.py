@@ -14,12 +14,12 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1():
+def jitter4():
     """Jittered 4^3 Kuhn cube (384 tets), its complex and operators."""
     import qh_inputs as qi
     from oracle.complex_ import Complex
     from oracle.whitney import Operators
-    m = qi.make_mesh(qi.CONFIGS["c1"])
+    m = qi.make_mesh(qi.CONFIGS["jitter4"])
     cx = Complex(m.xyz, m.tets)
     op = Operators(cx, qi.EPS0, qi.MU0)
     return m, cx, op

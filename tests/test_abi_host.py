@@ -50,12 +50,12 @@ def test_host_rejects_bad_meshes():
         qh.Context(-1).mesh_upload(flat, m.tets)
 
 
-@pytest.mark.parametrize("cfg", ["c1", "graded"])
+@pytest.mark.parametrize("cfg", ["jitter4", "graded"])
 def test_host_topology_and_matrices_match_oracle(cfg):
     import paper_2103_06737_amd as qh
     from oracle.complex_ import Complex
     from oracle.whitney import Operators
-    m = qi.make_mesh(qi.CONFIGS["c1"]) if cfg == "c1" else qi.BoxMesh(5, z_ratio=1.3)
+    m = qi.make_mesh(qi.CONFIGS["jitter4"]) if cfg == "jitter4" else qi.BoxMesh(5, z_ratio=1.3)
     ctx = qh.Context(-1)
     ctx.mesh_upload(m.xyz, m.tets)
     dt = 3e-10

@@ -21,18 +21,18 @@ U_B = 2.0 ** -56
 
 
 @pytest.fixture(scope="module")
-def c3():
-    cfg = qi.CONFIGS["c3"]
+def plasma64():
+    cfg = qi.CONFIGS["plasma64"]
     mesh = qi.make_mesh(cfg)
     parts = qi.make_particles(mesh, cfg)
     cx, op, po = oracle_setup(mesh)
     return cfg, mesh, parts, cx, op, po
 
 
-def test_c3_full_cycle(c3):
+def test_plasma64_full_cycle(plasma64):
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
-    cfg, mesh, parts, cx, op, po = c3
+    cfg, mesh, parts, cx, op, po = plasma64
     dt, weight = cfg["dt"], cfg["weight"]
     u_q = qi.QE * weight * 2.0 ** -40
     ctx = gpu_context(mesh, dt, weight=weight)
@@ -104,7 +104,7 @@ def test_c3_full_cycle(c3):
     assert np.array_equal(cx.D @ b1, cx.D @ b0)
 
 
-def test_c2_beam_200_steps():
+def test_beam32_200_steps():
     """1M-electron beam in frozen random fields, 200 steps: continuity and D b every step on the
     device, FP32 positions within 1e-5 of the box size of the FP64 oracle's after 200 steps.
 
@@ -115,7 +115,7 @@ def test_c2_beam_200_steps():
     plus 1e-6 for the FP32 point itself). Likewise at the walls (the planes of the unit cube): a
     particle that ends the step within 1e-5 of a wall may be reflected by one arithmetic and
     not (yet) by the other; the oracle then takes the GPU's sign of that velocity component."""
-    cfg = qi.CONFIGS["c2"]
+    cfg = qi.CONFIGS["beam32"]
     mesh = qi.make_mesh(cfg)
     cx, op, po = oracle_setup(mesh)
     e, b = oracle_fields(cx, cfg, U_B)
@@ -152,14 +152,14 @@ def test_c2_beam_200_steps():
     assert np.abs(xg - xo).max() <= 1e-5
 
 
-def test_c5_graded_two_species():
+def test_graded96_two_species():
     """96^3 mesh graded toward z = 0 (5.3M tets), electrons and ions (2M each here, the full
     workload's mesh and species mix), full cycle with Jacobi and then the learned
     preconditioner: continuity (on the device every step, and on the host), D b, residuals,
     and fewer edge iterations with the trained network."""
     import paper_2103_06737_amd as qh
     from oracle.complex_ import Complex
-    cfg = qi.CONFIGS["c5"]
+    cfg = qi.CONFIGS["graded96"]
     mesh = qi.make_mesh(cfg)
     n_e = 2_000_000
     parts = qi.make_particles(mesh, cfg, n_e=n_e)

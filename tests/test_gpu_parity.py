@@ -19,8 +19,8 @@ U_B = 2.0 ** -56
 
 
 @pytest.fixture(scope="module")
-def c1():
-    cfg = qi.CONFIGS["c1"]
+def jitter4():
+    cfg = qi.CONFIGS["jitter4"]
     mesh = qi.make_mesh(cfg)
     cx, op, po = oracle_setup(mesh)
     e, b = oracle_fields(cx, cfg, U_B)
@@ -28,8 +28,8 @@ def c1():
     return cfg, mesh, cx, op, po, e, b, parts
 
 
-def test_deposit_lists_bit_exact(c1):
-    cfg, mesh, cx, op, po, e, b, parts = c1
+def test_deposit_lists_bit_exact(jitter4):
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     ctx = gpu_context(mesh, cfg["dt"])
     for seed in range(3):
         st, l0, l1, sz, pt, pl, pz = chained_segments(cx, 3000, seed)
@@ -43,8 +43,8 @@ def test_deposit_lists_bit_exact(c1):
     assert not g0.any() and not Q0.any()
 
 
-def test_synthetic_fields_match_oracle(c1):
-    cfg, mesh, cx, op, po, e, b, parts = c1
+def test_synthetic_fields_match_oracle(jitter4):
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     ctx = gpu_context(mesh, cfg["dt"])
     ctx.fields_init_synthetic(qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), 1e3, 0.1, 1e-3)
     eg, bg = ctx.fields_download()
@@ -55,9 +55,9 @@ def test_synthetic_fields_match_oracle(c1):
     assert not (cx.D @ bg).any()
 
 
-def _stress_step(c1, n=1000):
+def _stress_step(jitter4, n=1000):
     """One step with displacements of order a cell: many crossings and wall hits."""
-    cfg, mesh, cx, op, po, e, b, parts = c1
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     dt = 2e-9
     ctx = gpu_context(mesh, dt)
     ctx.fields_upload(e, b)
@@ -76,9 +76,9 @@ def _stress_step(c1, n=1000):
                 nseg=nseg, seg=seg, orc=orc)
 
 
-def test_one_step_integer_path_bit_exact(c1):
-    cfg, mesh, cx, op, po, e, b, parts = c1
-    r = _stress_step(c1)
+def test_one_step_integer_path_bit_exact(jitter4):
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    r = _stress_step(jitter4)
     st = r["st"]
     assert st["crossings"] > 200 and st["wall_hits"] > 10 and st["lost"] == 0
     assert st["continuity_bad"] == 0
@@ -106,9 +106,9 @@ def test_one_step_integer_path_bit_exact(c1):
     assert np.unique(pid).size == r["x0"].shape[0]
 
 
-def test_one_step_fp32_vs_fp64(c1):
-    cfg, mesh, cx, op, po, e, b, parts = c1
-    r = _stress_step(c1)
+def test_one_step_fp32_vs_fp64(jitter4):
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    r = _stress_step(jitter4)
     orc = r["orc"]
     same = r["tg"] == orc["tet"]
     assert same.mean() > 0.99
@@ -130,10 +130,10 @@ def test_one_step_fp32_vs_fp64(c1):
     assert np.abs(seg["lam0"][i0] - np.clip(lam0, 0, 1) * S).max() <= 64
 
 
-def test_positions_100_steps_tie_consistent(c1):
+def test_positions_100_steps_tie_consistent(jitter4):
     """FP32 positions within 1e-5 of the box size after 100 steps; the oracle adopts the GPU's
     tet whenever its own point lies within 1e-5 of it (tie band), and counts those events."""
-    cfg, mesh, cx, op, po, e, b, parts = c1
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     ctx = gpu_context(mesh, cfg["dt"])
     ctx.fields_upload(e, b)
     sid = ctx.species_add(-qi.QE / qi.ME, -1)
@@ -159,10 +159,10 @@ def test_positions_100_steps_tie_consistent(c1):
     assert np.array_equal(tg, to)
 
 
-def test_full_cycle_field_update_matches_oracle(c1):
+def test_full_cycle_field_update_matches_oracle(jitter4):
     """Each GPU field update equals the oracle's applied to the same state and deposits."""
     from oracle.field import FieldOracle
-    cfg, mesh, cx, op, po, e, b, parts = c1
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     dt = 2e-10
     ctx = gpu_context(mesh, dt)
     ctx.fields_upload(e, b)
@@ -187,10 +187,10 @@ def test_full_cycle_field_update_matches_oracle(c1):
         assert not (cx.D @ b_g).any()
 
 
-def test_field_solve_residual(c1):
+def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
-    cfg, mesh, cx, op, po, e, b, parts = c1
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     dt = 1e-9
     ctx = gpu_context(mesh, dt)
     ie, inn = cx.int_edges, cx.int_nodes
@@ -240,8 +240,8 @@ def test_scattered_numbering_reads_wide_column_tiles():
     assert np.linalg.norm(A @ xl - rhs) <= 1.0001e-8 * np.linalg.norm(rhs)
 
 
-def test_sort_keeps_particles_and_invariants(c1):
-    cfg, mesh, cx, op, po, e, b, parts = c1
+def test_sort_keeps_particles_and_invariants(jitter4):
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
     ctx = gpu_context(mesh, 2e-9)
     ctx.fields_upload(e, b)
     sid = ctx.species_add(-qi.QE / qi.ME, -1)

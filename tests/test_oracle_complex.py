@@ -27,8 +27,8 @@ def test_kuhn_counts_closed_form(n):
     assert cx.wall_node.sum() == (n + 1) ** 3 - max(n - 1, 0) ** 3
 
 
-def test_complex_identities(c1):
-    _, cx, _ = c1
+def test_complex_identities(jitter4):
+    _, cx, _ = jitter4
     assert abs(cx.C @ cx.G).max() == 0          # curl grad = 0
     assert abs(cx.D @ cx.C).max() == 0          # div curl = 0
     assert cx.Nn - cx.Ne + cx.Nf - cx.Nt == 1   # Euler characteristic of a ball
@@ -36,17 +36,17 @@ def test_complex_identities(c1):
     assert set(np.unique(cx.face_count)) == {1, 2}
 
 
-def test_cotree_counts_equal(c1):
+def test_cotree_counts_equal(jitter4):
     """#E_s = #B_s for a simply connected PEC box (Sec. V item 7)."""
-    _, cx, _ = c1
+    _, cx, _ = jitter4
     n_cotree_edges = cx.int_edges.size - cx.int_nodes.size
     n_cotree_faces = int((~cx.wall_face).sum()) - (cx.Nt - 1)
     assert n_cotree_edges == n_cotree_faces == 289
 
 
-def test_operators_are_incidence(c1):
+def test_operators_are_incidence(jitter4):
     """[grad] = eps [*eps]^-1 M_g = G, [curl] = mu^-1 [*mu^-1]^-1 M_c = C, [div] = D."""
-    _, cx, op = c1
+    _, cx, op = jitter4
     Mg = W.mixed_g(cx, op.Minv, op.vol).toarray()
     grad = qi.EPS0 * np.linalg.solve(op.Meps.toarray(), Mg)
     assert np.allclose(grad, cx.G.toarray(), atol=1e-12)
@@ -58,26 +58,26 @@ def test_operators_are_incidence(c1):
     assert np.allclose(div, cx.D.toarray(), atol=1e-12)
 
 
-def test_laplacian_and_curlcurl_two_formulas(c1):
+def test_laplacian_and_curlcurl_two_formulas(jitter4):
     """G^T [*eps] G equals the P1 stiffness matrix; C^T [*mu^-1] C the Nedelec curl-curl."""
-    _, _, op = c1
+    _, _, op = jitter4
     K1, K2 = op.K.toarray(), op.stiffness_p1().toarray()
     assert np.abs(K1 - K2).max() <= 1e-13 * np.abs(K2).max()
     S1, S2 = op.S.toarray(), op.curlcurl_nedelec().toarray()
     assert np.abs(S1 - S2).max() <= 1e-13 * np.abs(S2).max()
 
 
-def test_hodge_matrices_spd(c1):
-    _, _, op = c1
+def test_hodge_matrices_spd(jitter4):
+    _, _, op = jitter4
     for M in (op.Meps, op.Mmu):
         A = M.toarray()
         assert np.allclose(A, A.T, rtol=0, atol=1e-14 * np.abs(A).max())
         assert np.linalg.eigvalsh(A).min() > 0
 
 
-def test_whitney_reproduces_constants(c1):
+def test_whitney_reproduces_constants(jitter4):
     """Edge DOFs of a uniform E and face fluxes of a uniform B are reproduced exactly."""
-    _, cx, op = c1
+    _, cx, op = jitter4
     rng = np.random.default_rng(7)
     E0 = np.array([1.5, -0.25, 0.75])
     B0 = np.array([-0.3, 0.1, 0.2])
@@ -92,9 +92,9 @@ def test_whitney_reproduces_constants(c1):
     assert np.allclose(W.field_B(cx, op.Minv, b, tet, r), B0, atol=1e-12)
 
 
-def test_tangential_and_normal_continuity(c1):
+def test_tangential_and_normal_continuity(jitter4):
     """W1 fields have continuous tangential E, W2 fields continuous normal B across faces."""
-    _, cx, op = c1
+    _, cx, op = jitter4
     rng = np.random.default_rng(3)
     e = rng.standard_normal(cx.Ne)
     b = rng.standard_normal(cx.Nf)

@@ -51,8 +51,8 @@ def _source_free_state(cx, rs, seed=0):
 
 
 @pytest.mark.parametrize("dt", [1e-11, 2e-9])
-def test_literal_cotree_equals_projected(c1, dt):
-    _, cx, op = c1
+def test_literal_cotree_equals_projected(jitter4, dt):
+    _, cx, op = jitter4
     rs = CT.ReducedSystem(cx, op, dt)
     e, b = _source_free_state(cx, rs)
     Ens, Es, Bs = rs.decompose(e[rs.ie], b[rs.jf])
@@ -70,15 +70,15 @@ def test_literal_cotree_equals_projected(c1, dt):
         assert np.abs(br - b[rs.jf]).max() <= 1e-10 * np.abs(b).max()
 
 
-def test_z13_vanishes_and_square_blocks(c1):
-    _, cx, op = c1
+def test_z13_vanishes_and_square_blocks(jitter4):
+    _, cx, op = jitter4
     rs = CT.ReducedSystem(cx, op, 1e-10)
     assert np.abs(rs.Z13).max() <= 1e-12 * np.abs(rs.Z12).max()
     assert rs.Z11.shape == rs.Z21.shape == (289, 289)
 
 
-def test_tree_independence(c1):
-    _, cx, op = c1
+def test_tree_independence(jitter4):
+    _, cx, op = jitter4
     dt = 1e-10
     outs = []
     for seed in (None, 5):
@@ -93,8 +93,8 @@ def test_tree_independence(c1):
     assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-10 * np.abs(outs[0][1]).max())
 
 
-def test_trapezoidal_map_unit_circle_and_phase(c1):
-    _, cx, op = c1
+def test_trapezoidal_map_unit_circle_and_phase(jitter4):
+    _, cx, op = jitter4
     dt = 2e-9                                       # ~10x the explicit limit of this mesh
     ie = cx.int_edges
     jf = np.flatnonzero(~cx.wall_face)
@@ -118,8 +118,8 @@ def test_trapezoidal_map_unit_circle_and_phase(c1):
     assert np.allclose(ph, expect, rtol=1e-10, atol=1e-12)
 
 
-def test_source_free_energy_and_divb(c1):
-    _, cx, op = c1
+def test_source_free_energy_and_divb(jitter4):
+    _, cx, op = jitter4
     dt = 2e-9
     fo = Fo.FieldOracle(cx, op, dt)
     u_b = 2.0 ** -70
@@ -147,10 +147,10 @@ def test_source_free_energy_and_divb(c1):
     assert abs(energy(e, b) - W0) <= 1e-9 * W0
 
 
-def test_gauss_law_and_qh_benefit(c1):
+def test_gauss_law_and_qh_benefit(jitter4):
     """Loose edge solves (1e-6): with the Gauss-law solve the discrete Gauss residual stays
     at the nodal tolerance; without it the error is orders of magnitude larger."""
-    m, cx, op = c1
+    m, cx, op = jitter4
     dt = 2e-9
     fo = Fo.FieldOracle(cx, op, dt)
     u_b = 2.0 ** -56

@@ -110,11 +110,11 @@ def test_deposit_equals_brute_force_line_integral(box8):
         assert out["Q"].sum() == S * S
 
 
-def test_continuity_bitwise_with_crossings_and_walls(c1):
+def test_continuity_bitwise_with_crossings_and_walls(jitter4):
     """G^T g = Q^{n+1} - Q^n exactly, over steps with many crossings and wall hits."""
-    m, cx, op = c1
+    m, cx, op = jitter4
     po = P.ParticleOracle(cx, op.Minv)
-    parts = qi.make_particles(m, qi.CONFIGS["c1"])
+    parts = qi.make_particles(m, qi.CONFIGS["jitter4"])
     x, v, tet = (a.astype(np.float64) for a in parts["e"])
     tet = tet.astype(np.int64)
     rng = np.random.default_rng(0)
@@ -138,10 +138,10 @@ def test_continuity_bitwise_with_crossings_and_walls(c1):
     assert tot_cross > 1000 and tot_wall > 50
 
 
-def test_walk_final_tet_matches_brute_force(c1):
-    m, cx, op = c1
+def test_walk_final_tet_matches_brute_force(jitter4):
+    m, cx, op = jitter4
     po = P.ParticleOracle(cx, op.Minv)
-    parts = qi.make_particles(m, qi.CONFIGS["c1"])
+    parts = qi.make_particles(m, qi.CONFIGS["jitter4"])
     x, v, tet = (a.astype(np.float64) for a in parts["e"])
     out = po.push(np.zeros(cx.Ne), np.zeros(cx.Nf), x[:300], v[:300] * 1e5, tet[:300], 0.0,
                   1e-11, -1)
@@ -229,20 +229,20 @@ def test_boris_exb_drift(box8):
     assert abs(drift[1] - expect[1]) < 2e-3 * abs(expect[1])
 
 
-def test_quantize_sums_and_bounds(c1):
-    m, cx, op = c1
+def test_quantize_sums_and_bounds(jitter4):
+    m, cx, op = jitter4
     po = P.ParticleOracle(cx, op.Minv)
-    x, _, tet = qi.make_particles(m, qi.CONFIGS["c1"])["e"]
+    x, _, tet = qi.make_particles(m, qi.CONFIGS["jitter4"])["e"]
     L = po.quantize_points(x.astype(np.float64), tet)
     assert (L.sum(1) == S).all() and (L >= 0).all() and (L <= S).all()
     lam = op.Minv[tet, :, 0] + np.einsum("pij,pj->pi", op.Minv[tet, :, 1:], x.astype(np.float64))
     assert np.abs(L / S - lam).max() <= 2.0 ** -P.F_BITS * 2
 
 
-def test_integer_deposit_list_telescopes(c1):
+def test_integer_deposit_list_telescopes(jitter4):
     """Pieces chained through shared faces (Lambda carried by vertex id): G^T g equals the
     end-point charge minus the start-point charge, for random integer coordinates."""
-    _, cx, op = c1
+    _, cx, op = jitter4
     po = P.ParticleOracle(cx, op.Minv)
     rng = np.random.default_rng(11)
     segs_t, l0s, l1s, zs = [], [], [], []
