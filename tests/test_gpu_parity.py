@@ -206,6 +206,62 @@ def test_field_solve_residual(jitter4):
         assert np.linalg.norm(x - ref) <= 1e-5 * np.linalg.norm(ref)
 
 
+def test_degenerate_particle_sets(jitter4):
+    """An empty species, a lone particle, and 513 particles (one full block and one particle)
+    holding 120 degenerate starts: on a vertex, a face centroid or an edge midpoint of their tet,
+    every fourth one at rest, the rest moving a cell or so. Nothing is lost; the integer deposits
+    are the GPU's own pieces re-deposited by the oracle, bit for bit; continuity holds on the
+    host; positions and tets agree with the oracle's FP64 push (ties aside)."""
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    dt = 2e-9
+    ctx = gpu_context(mesh, dt)
+    ctx.fields_upload(e, b)
+    x, v, tet = parts["e"]
+    rng = np.random.default_rng(11)
+    T, k = cx.tets, 40
+    tt = rng.integers(cx.Nt, size=k)
+    special = np.concatenate([cx.xyz[T[tt, 0]], cx.xyz[T[tt][:, [0, 1, 2]]].mean(axis=1),
+                              cx.xyz[T[tt][:, [0, 3]]].mean(axis=1)]).astype(np.float32)
+    sets = {"empty": (np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros(0, np.int32)),
+            "one": (x[:1], (v[:1] * 40).astype(np.float32), tet[:1])}
+    xs = np.concatenate([special, x[1:1 + 513 - 3 * k]])
+    vs = (v[1:514] * 40).astype(np.float32)
+    vs[:3 * k:4] = 0.0
+    ts = np.concatenate([np.tile(tt, 3), tet[1:1 + 513 - 3 * k]]).astype(np.int32)
+    sets["many"] = (xs, vs, ts)
+    sids = {}
+    for name, (xx, vv, tq) in sets.items():
+        sids[name] = ctx.species_add(-qi.QE / qi.ME, -1)
+        ctx.particles_upload(sids[name], xx, vv, tq)
+    _, Q0 = ctx.deposits_download()
+    ctx.capture_segments(64 * 600)
+    st = ctx.pic_step(ctx.step_params(verify=1))[0]
+    assert st["lost"] == 0 and st["continuity_bad"] == 0
+    g, Q1 = ctx.deposits_download()
+    assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+    nseg, seg = ctx.segments_download()
+    assert nseg == seg["tet"].size and np.unique(seg["species"]).size == 2
+    g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], -np.ones(nseg), np.zeros(0),
+                              np.zeros((0, 4)), np.zeros(0))
+    assert np.array_equal(g_re, g)
+    order = np.lexsort((seg["seq"], seg["pid"], seg["species"]))
+    key = seg["species"][order].astype(np.int64) << 32 | seg["pid"][order]
+    last = np.r_[key[1:] != key[:-1], True]
+    assert last.sum() == 514
+    _, Q_re = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                              seg["tet"][order][last], seg["lam1"][order][last], -np.ones(last.sum()))
+    assert np.array_equal(Q_re, Q1)
+    for name, (xx, vv, tq) in sets.items():
+        xg, vg, tg = ctx.particles_download(sids[name])
+        assert xg.shape[0] == tq.size
+        if tq.size == 0:
+            continue
+        orc = po.push(e, b * U_B, xx, vv, tq, -qi.QE / qi.ME, dt, -1)
+        same = tg == orc["tet"]
+        assert same.mean() > 0.95
+        assert np.abs(xg - orc["x"]).max(axis=1)[same].max() < 1e-5
+
+
 def test_scattered_numbering_reads_wide_column_tiles():
     """Nodes numbered at random on a 24^3 box: the columns of a product tile then scatter over
     the whole range of ~97 K interior edges, more than four 2^14-column windows hold, so the
