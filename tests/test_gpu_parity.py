@@ -262,6 +262,39 @@ def test_degenerate_particle_sets(jitter4):
         assert np.abs(xg - orc["x"]).max(axis=1)[same].max() < 1e-5
 
 
+def test_gauss_correction_holds_the_law(jitter4):
+    """Sec. I, Sec. V: with a loose edge solve (relative residual 1e-4) the error of the discrete
+    Gauss law is orders of magnitude above the node solve's tolerance when the correction is
+    skipped, and stays within that tolerance (1e-8) when it runs. The error the library reports equals the oracle's
+    evaluation of the law on the library's own e and Q. The start satisfies the law exactly
+    (E = 0, neutralising background)."""
+    import paper_2103_06737_amd as qh
+    from oracle.field import FieldOracle
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    dt = cfg["dt"]
+    u_q = qi.QE * 2.0 ** -40
+    fo = FieldOracle(cx, op, dt)
+    res = {}
+    for gauss in (1, 0):
+        ctx = gpu_context(mesh, dt)
+        ctx.fields_upload(np.zeros_like(e), b)
+        sid = ctx.species_add(-qi.QE / qi.ME, -1)
+        x, v, tet = parts["e"]
+        ctx.particles_upload(sid, x, v, tet)
+        ctx.charge_background(1)
+        _, Q_bg = ctx.deposits_download()
+        prm = ctx.step_params(field_mode=qh.FIELDS_SOLVE, gauss=gauss, tol_edge=1e-4, tol_node=1e-8, verify=1)
+        st = ctx.pic_step(prm, 30)
+        assert all(s["continuity_bad"] == 0 and s["divb_bad"] == 0 for s in st)
+        res[gauss] = np.array([s["gauss_res"] for s in st])
+        e1, _ = ctx.fields_download()
+        _, Q1 = ctx.deposits_download()
+        rho = u_q * (Q_bg - Q1).astype(np.float64)[cx.int_nodes]
+        assert abs(fo.gauss_error(e1, rho) - res[gauss][-1]) <= 1e-4 * res[gauss][-1] + 1e-14
+    assert res[1].max() <= 1.01e-8
+    assert res[0][2:].min() > 1e3 * res[1].max()
+
+
 def test_scattered_numbering_reads_wide_column_tiles():
     """Nodes numbered at random on a 24^3 box: the columns of a product tile then scatter over
     the whole range of ~97 K interior edges, more than four 2^14-column windows hold, so the
