@@ -83,6 +83,19 @@ class FieldOracle:
     def gauss_error(self, e, rho):
         return np.linalg.norm(self.gauss_residual(e, rho)) / self.gauss_scale(e, rho)
 
+    def gauss_project(self, es, rho, tol_n, info):
+        """e = e* + G delta with G^T [*eps] G delta = rho - G^T [*eps] e* (eq. discreteGauss),
+        solved until the Gauss residual is below tol_n times its scale."""
+        rg = self.gauss_residual(es, rho)
+        scale = self.gauss_scale(es, rho)
+        if scale > 0 and np.linalg.norm(rg) > tol_n * scale:
+            tol_rel = tol_n * scale / np.linalg.norm(rg)
+            dl, itn, _ = pcg(self.K, rg, tol=tol_rel)
+        else:
+            dl, itn = np.zeros(self.inn.size), 0
+        info.update(node_it=itn)
+        return es + self.Gint @ dl
+
     def step(self, e, b_int, u_b, g_int, u_q, Q_new, Q_bg, tol=1e-12, tol_n=1e-12, gauss=True):
         """One field update with rho^{n+1} = u_q (Q_bg - Q^{n+1}) on the interior nodes."""
         rho = u_q * (Q_bg - Q_new).astype(np.float64)[self.inn]
@@ -97,22 +110,41 @@ class FieldOracle:
         es = np.zeros_like(e)
         es[self.ie] = xs
         info = dict(edge_it=it, edge_res=res)
-        if gauss:
-            rg = self.gauss_residual(es, rho)
-            scale = self.gauss_scale(es, rho)
-            if scale > 0 and np.linalg.norm(rg) > tol_n * scale:
-                tol_rel = tol_n * scale / np.linalg.norm(rg)
-                dl, itn, _ = pcg(self.K, rg, tol=tol_rel)
-            else:
-                dl, itn = np.zeros(self.inn.size), 0
-            e_new = es + self.Gint @ dl
-            info.update(node_it=itn)
-        else:
-            e_new = es
+        e_new = self.gauss_project(es, rho, tol_n, info) if gauss else es
         info["gauss_res"] = self.gauss_error(e_new, rho)
         u = np.rint(0.5 * self.dt * (e_new + e) / u_b).astype(np.int64)
         b_new = b_int - self.cx.C @ u
         return e_new, b_new, info
+
+
+class WaveOracle(FieldOracle):
+    """Edge update of the wave equation (eq. wave_cont): [*eps] e'' + S e = -J', S = C^T [*mu^-1] C,
+    with Newmark beta = 1/4, gamma = 1/2 (the constants of the trapezoidal rule, reading R1):
+        ([*eps] + tau S) e^{n+1} = [*eps](2 e^n - e^{n-1}) - tau S (2 e^n + e^{n-1})
+                                   - (g^{n+1/2} - g^{n-1/2}),
+    the forcing dt^2 J' taken as the difference of the currents integrated over the two steps
+    around t^n (the path integrals of Sec. IV.B.1). G^T S = 0 then gives G^T [*eps] of the second
+    difference of e equal to the second difference of the charge: the discrete Gauss law is
+    kept up to what each solve leaves in the irrotational part, and that error grows linearly
+    in time (the t grad Phi null space, Sec. V) unless the Gauss-law correction removes it.
+    Face fluxes follow Faraday's law in integers as in FieldOracle."""
+
+    def wave_rhs(self, e, e_prev, dg_real):
+        r = self.op.Meps @ (2.0 * e - e_prev) - self.tau * (self.op.S @ (2.0 * e + e_prev)) - dg_real
+        return r[self.ie]
+
+    def wave_step(self, e, e_prev, b_int, u_b, g_int, g_prev_int, u_q, rho, tol=1e-12, tol_n=1e-12, gauss=True):
+        """One wave-equation update given e^n, e^{n-1}, the step currents g^{n+1/2}, g^{n-1/2}
+        and rho^{n+1} on the interior nodes. Returns (e^{n+1}, b^{n+1}, info)."""
+        rhs = self.wave_rhs(e, e_prev, (g_int - g_prev_int).astype(np.float64) * u_q)
+        xs, it, res = pcg(self.A, rhs, x0=e[self.ie].copy(), tol=tol)
+        es = np.zeros_like(e)
+        es[self.ie] = xs
+        info = dict(edge_it=it, edge_res=res)
+        e_new = self.gauss_project(es, rho, tol_n, info) if gauss else es
+        info["gauss_res"] = self.gauss_error(e_new, rho)
+        u = np.rint(0.5 * self.dt * (e_new + e) / u_b).astype(np.int64)
+        return e_new, b_int - self.cx.C @ u, info
 
 
 def init_fields(cx: Complex, white_e, white_a, sigma_e, bz, sigma_b, u_b):

@@ -184,3 +184,61 @@ def test_golden_beam_table_constants():
         gold = json.load(f)
     c = 1.0 / np.sqrt(qi.EPS0 * qi.MU0)
     assert abs(gold["v_p"] / c - gold["v_p_over_c"]) < 5e-6
+
+
+def _wave_vs_trapezoidal(jitter4, tol, gauss, steps=20):
+    """The trapezoidal (E-B) update from a Gauss-consistent start, and the wave-equation update
+    started from its first two fields, driven by the same step currents."""
+    m, cx, op = jitter4
+    dt, u_b, u_q = 2e-9, 2.0 ** -56, 1e-12
+    fo, wo = Fo.FieldOracle(cx, op, dt), Fo.WaveOracle(cx, op, dt)
+    rng = np.random.default_rng(4)
+    e0 = np.zeros(cx.Ne)
+    e0[cx.int_edges] = rng.standard_normal(cx.int_edges.size) * 1e2
+    e0 = fo.gauss_project(e0, np.zeros(cx.int_nodes.size), 1e-14, {})   # G^T [*eps] e0 = 0 = rho0
+    b0 = cx.C @ np.rint(rng.standard_normal(cx.Ne) * 1e-6 / u_b).astype(np.int64)
+    r2 = np.random.default_rng(5)
+    gs = []
+    for _ in range(steps):
+        g = np.zeros(cx.Ne, np.int64)
+        g[cx.int_edges] = r2.integers(-10 ** 6, 10 ** 6, cx.int_edges.size)
+        gs.append(g)
+    Qbg = np.zeros(cx.Nn, np.int64)
+    e, b, Q = e0.copy(), b0.copy(), np.zeros(cx.Nn, np.int64)
+    E_t, err_t = [e.copy()], []
+    for k in range(steps):
+        Q = Q + cx.G.T @ gs[k]
+        e, b, info = fo.step(e, b, u_b, gs[k], u_q, Q, Qbg, tol=tol, tol_n=1e-12, gauss=gauss)
+        E_t.append(e.copy())
+        err_t.append(info["gauss_res"])
+    Q = cx.G.T @ gs[0]
+    ep, e, b = E_t[0].copy(), E_t[1].copy(), b0.copy()
+    err_w, rel = [err_t[0]], []
+    for k in range(1, steps):
+        Q = Q + cx.G.T @ gs[k]
+        rho = u_q * (Qbg - Q).astype(float)[wo.inn]
+        en, b, info = wo.wave_step(e, ep, b, u_b, gs[k], gs[k - 1], u_q, rho, tol=tol, tol_n=1e-12, gauss=gauss)
+        ep, e = e, en
+        err_w.append(info["gauss_res"])
+        rel.append(np.linalg.norm(e - E_t[k + 1]) / np.linalg.norm(E_t[k + 1]))
+    return np.array(err_t), np.array(err_w), max(rel)
+
+
+def test_wave_update_equals_trapezoidal(jitter4):
+    """Newmark beta = 1/4 on the wave equation (eq. wave_cont) is the trapezoidal E-B update with
+    b eliminated: from the same two first fields and currents the two sequences agree to the
+    solver tolerance (tight solves: 1e-12)."""
+    _, _, rel = _wave_vs_trapezoidal(jitter4, tol=1e-12, gauss=False)
+    assert rel < 1e-9
+
+
+def test_wave_gauss_error_grows_without_correction(jitter4):
+    """Sec. V and the Gauss-law figure of Sec. VI: with loose solves (1e-6) and no correction the
+    Gauss-law error of the E-B update levels off, that of the wave update grows step after
+    step (the t grad Phi null space); with the correction both hold the law to the node
+    solve's tolerance."""
+    err_t, err_w, _ = _wave_vs_trapezoidal(jitter4, tol=1e-6, gauss=False)
+    assert err_w[-1] > 5 * err_w[4] and err_w[-1] > 5 * err_t[-1]
+    assert err_t[-1] < 2 * err_t[9]
+    err_t, err_w, _ = _wave_vs_trapezoidal(jitter4, tol=1e-6, gauss=True)
+    assert err_t.max() < 1e-10 and err_w.max() < 1e-10
