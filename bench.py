@@ -138,25 +138,27 @@ def measured_traffic(entry: str, workload: str):
 
 
 def gauss_study(workload: str, particles, steps: int, tols):
-    """Gauss-law error per step of the full cycle with and without the Gauss-law correction,
-    at loose edge-solve tolerances (Sec. I, Sec. V: without the correction the solver's error in
-    the irrotational part of e is never removed and accumulates; with it the discrete law holds
-    to the node solve's tolerance every step). Each run starts from the same seeded state."""
+    """Gauss-law error per step of the full cycle with and without the Gauss-law correction, at
+    loose edge-solve tolerances, for the trapezoidal (E-B) update and the wave-equation update
+    (Sec. I, Sec. V, the Gauss-law figure of Sec. VI: without the correction the solver's error in
+    the irrotational part of e is never removed; it levels off for the E-B update and grows in
+    time for the wave equation; with it the discrete law holds to the node solve's tolerance
+    every step). Each run starts from the same seeded state."""
     import paper_2103_06737_amd as qh
     runs = []
-    for tol in tols:
-        for gauss in (1, 0):
-            ctx, cfg, mesh, parts, mi = setup(workload, particles)
-            prm = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, sort_every=cfg.get("sort_every", 0),
-                                         gauss=gauss, tol_edge=tol, tol_node=1e-8, max_it_edge=2000,
-                                         max_it_node=5000, check_every=16)
-            st = ctx.pic_step(prm, steps)
-            runs.append({"tol_edge": tol, "gauss_correction": bool(gauss),
-                         "gauss_res": [s["gauss_res"] for s in st],
-                         "edge_iters": [s["edge_iters"] for s in st], "node_iters": [s["node_iters"] for s in st]})
-            log(f"[study] tol_edge {tol:g} correction {bool(gauss)}: gauss_res step 1 {st[0]['gauss_res']:.3e}, "
-                f"step {steps} {st[-1]['gauss_res']:.3e}")
-            ctx.close()
+    for tol, mode, gauss in [(t, m, g) for t in tols for m in (qh.FIELDS_SOLVE, qh.FIELDS_WAVE) for g in (1, 0)]:
+        ctx, cfg, mesh, parts, mi = setup(workload, particles)
+        prm = qh.Context.step_params(field_mode=mode, sort_every=cfg.get("sort_every", 0), gauss=gauss,
+                                     tol_edge=tol, tol_node=1e-8, max_it_edge=2000, max_it_node=5000,
+                                     check_every=16)
+        st = ctx.pic_step(prm, steps)
+        runs.append({"update": "wave" if mode == qh.FIELDS_WAVE else "trapezoidal",
+                     "tol_edge": tol, "gauss_correction": bool(gauss),
+                     "gauss_res": [s["gauss_res"] for s in st],
+                     "edge_iters": [s["edge_iters"] for s in st], "node_iters": [s["node_iters"] for s in st]})
+        log(f"[study] {runs[-1]['update']} tol_edge {tol:g} correction {bool(gauss)}: "
+            f"gauss_res step 1 {st[0]['gauss_res']:.3e}, step {steps} {st[-1]['gauss_res']:.3e}")
+        ctx.close()
     print(json.dumps({"study": "gauss_law_error_per_step", "workload": f"{workload}: {WORKLOADS[workload]}",
                       "steps": steps, "tol_node": 1e-8, "runs": runs}))
 
@@ -245,8 +247,9 @@ def main():
                     help="only run a plain device copy of MIB MiB (read + write) a few times, to "
                          "scale the HBM byte counters of the profiler; prints its own JSON line")
     ap.add_argument("--gauss-study", type=int, default=0, metavar="STEPS",
-                    help="Gauss-law error per step with and without the correction at loose edge "
-                         "tolerances (1e-4, 1e-6); prints its own JSON line")
+                    help="Gauss-law error per step of the trapezoidal and wave-equation updates with "
+                         "and without the correction at loose edge tolerances (1e-4, 1e-6); prints its "
+                         "own JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",

@@ -48,6 +48,13 @@ extern "C" {
 
 #define QH_FIELDS_FROZEN 0 /* particles only: E, B stay as uploaded */
 #define QH_FIELDS_SOLVE 1  /* full cycle: implicit field update after each push */
+/* full cycle with the edge update of the wave equation (eq. wave_cont, [*eps] e'' + S e = -J'),
+ * Newmark beta = 1/4, gamma = 1/2: ([*eps] + tau S) e^{n+1} = [*eps](2e^n - e^{n-1})
+ * - tau S (2e^n + e^{n-1}) - u_q (g^{n+1/2} - g^{n-1/2}); the same matrix, preconditioners,
+ * Gauss-law correction and integer Faraday update as QH_FIELDS_SOLVE. It needs e^{n-1} and the
+ * previous step's current: a step in this mode after any other step (or after fields,
+ * particles or physics are set) takes the QH_FIELDS_SOLVE update and records them. */
+#define QH_FIELDS_WAVE 2
 
 #define QH_PC_JACOBI 0  /* diagonal preconditioner, conjugate gradients */
 #define QH_PC_LEARNED 1 /* learned edge-local preconditioner M = G^T G, conjugate gradients, Jacobi fallback */
@@ -79,7 +86,7 @@ typedef struct {
 } qh_phys_t;
 
 typedef struct {
-    int32_t field_mode;  /* QH_FIELDS_FROZEN or QH_FIELDS_SOLVE */
+    int32_t field_mode;  /* QH_FIELDS_FROZEN, QH_FIELDS_SOLVE or QH_FIELDS_WAVE */
     int32_t sort_every;  /* counting-sort particles by tet every k steps (0 = never) */
     int32_t precond;     /* QH_PC_JACOBI or QH_PC_LEARNED */
     int32_t gauss;       /* 1: solve the discrete Gauss law each step (the method); 0: skip */
@@ -166,7 +173,8 @@ int qh_charge_background(qh_ctx *ctx, int32_t mode);
  * Boris push, tet walk with wall reflection, integer deposit of the path integral of W1
  * and of the W0 charge; then, if field_mode is QH_FIELDS_SOLVE, the implicit update of
  * Sec. IV.B (trapezoidal edge solve, discrete Gauss law for the non-solenoidal part,
- * integer Faraday update of b). stats: n_steps entries or NULL. Returns QH_ENOTCONV if a
+ * integer Faraday update of b); QH_FIELDS_WAVE replaces the edge solve's right-hand side by
+ * that of the wave equation (see its definition). stats: n_steps entries or NULL. Returns QH_ENOTCONV if a
  * solve hit its cap (the step is still taken), QH_ELOST if a particle hit the walk cap. */
 int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
                 qh_step_stats_t *stats);

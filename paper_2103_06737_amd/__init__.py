@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libqh.so")
 
 QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
-FIELDS_FROZEN, FIELDS_SOLVE = 0, 1
+FIELDS_FROZEN, FIELDS_SOLVE, FIELDS_WAVE = 0, 1, 2
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",

@@ -104,6 +104,8 @@ int ensure_assembled(qh_ctx *c) {
         if ((rc = qh_cg_alloc(c, c->cge, c->A.n))) return rc;
         if ((rc = qh_cg_alloc(c, c->cgn, c->K.n))) return rc;
         if ((rc = qh_alloc(c, &c->e_old, std::max<int64_t>(1, c->A.n)))) return rc;
+        if ((rc = qh_alloc(c, &c->e_prev, std::max<int64_t>(1, c->A.n)))) return rc;
+        if ((rc = qh_alloc(c, &c->g_prev, c->hm.Ne))) return rc;
         if ((rc = qh_alloc(c, &c->e_star, std::max<int64_t>(1, c->A.n)))) return rc;
         if ((rc = qh_alloc(c, &c->rho, std::max<int64_t>(1, c->K.n)))) return rc;
         QH_HIP(c, launch_diag_inv(c, c->K, c->cgn.dinv));
@@ -152,6 +154,7 @@ int set_fields(qh_ctx *c, const double *e, const int64_t *b) {
     }
     c->have_fields = true;
     c->fields_dirty = true;
+    c->wave_hist = false;
     return sync(c);
 }
 
@@ -320,6 +323,7 @@ int qh_set_physics(qh_ctx *c, const qh_phys_t *p) {
     c->phys = *p;
     c->have_phys = true;
     c->fields_dirty = true;
+    c->wave_hist = false;
     return ensure_assembled(c);
 }
 
@@ -413,6 +417,7 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
         if ((rc = qh_sort_species(c, s))) return rc;
     }
+    c->wave_hist = false;
     return recompute_charge(c);
 }
 
@@ -567,9 +572,11 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     if (!c->have_mesh || !c->have_phys || !c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
     if (!c->have_fields) return qh_fail(c, QH_ESTATE, "fields first");
-    if (P->field_mode != QH_FIELDS_FROZEN && P->field_mode != QH_FIELDS_SOLVE) return qh_fail(c, QH_EINVAL, "field_mode");
+    if (P->field_mode != QH_FIELDS_FROZEN && P->field_mode != QH_FIELDS_SOLVE && P->field_mode != QH_FIELDS_WAVE)
+        return qh_fail(c, QH_EINVAL, "field_mode");
+    const bool solve = P->field_mode != QH_FIELDS_FROZEN;
     if (P->precond != QH_PC_JACOBI && P->precond != QH_PC_LEARNED) return qh_fail(c, QH_EINVAL, "precond");
-    const bool learned = P->precond == QH_PC_LEARNED && P->field_mode == QH_FIELDS_SOLVE;
+    const bool learned = P->precond == QH_PC_LEARNED && solve;
     if (learned) {
         int rc = qh_learned_setup(c);
         if (rc) return rc;
@@ -585,7 +592,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         bool capture = c->capture_next;
         c->capture_next = false;
         if (use_ev) QH_HIP(c, hipEventRecord(ev[0], c->stream));
-        if (c->fields_dirty || P->field_mode == QH_FIELDS_SOLVE) {
+        if (c->fields_dirty || solve) {
             int t0 = qh_tbeg(c);
             launch_field_prep(c);
             qh_tend(c, t0, QK_FIELD_PREP);
@@ -610,10 +617,13 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         if (use_ev) QH_HIP(c, hipEventRecord(ev[1], c->stream));
         SolveResult se, sn;
         double gauss_out[3] = {0, 0, 0};
-        if (P->field_mode == QH_FIELDS_SOLVE) {
+        if (solve) {
             QH_HIP(c, hipMemcpyAsync(c->e_old, c->cge.x, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
+            // the wave-equation right-hand side needs e^{n-1} and the previous current: without
+            // them (first step in this mode) the step takes the trapezoidal update
+            const bool wave = P->field_mode == QH_FIELDS_WAVE && c->wave_hist;
             int t0 = qh_tbeg(c);
-            QH_HIP(c, launch_edge_rhs(c));
+            QH_HIP(c, wave ? launch_wave_rhs(c) : launch_edge_rhs(c));
             qh_tend(c, t0, QK_EDGE_RHS);
             int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr, false,
                                  learned);
@@ -647,12 +657,19 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             int t1 = qh_tbeg(c);
             QH_HIP(c, launch_faraday(c));
             qh_tend(c, t1, QK_FARADAY);
+            if (P->field_mode == QH_FIELDS_WAVE) {
+                QH_HIP(c, hipMemcpyAsync(c->e_prev, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice,
+                                         c->stream));
+                QH_HIP(c, hipMemcpyAsync(c->g_prev, c->g, sizeof(int64_t) * m.Ne, hipMemcpyDeviceToDevice, c->stream));
+            }
+            c->wave_hist = P->field_mode == QH_FIELDS_WAVE;
             if (stats) {
                 // Gauss residual after the update (reuses the node right-hand-side buffer)
                 QH_HIP(c, launch_gauss_rhs(c, c->scratch_d + 4, P->tol_node));
                 QH_HIP(c, hipMemcpyAsync(gauss_out, c->scratch_d + 4, sizeof(gauss_out), hipMemcpyDeviceToHost, c->stream));
             }
         }
+        if (!solve) c->wave_hist = false;  // the fields did not follow this step's current
         if (P->verify) QH_HIP(c, launch_verify(c, true));
         if (use_ev) QH_HIP(c, hipEventRecord(ev[2], c->stream));
         if (stats) {
@@ -680,7 +697,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.continuity_bad = P->verify ? (int64_t)cnt[3] : -1;
             S.divb_bad = P->verify ? (int64_t)cnt[4] : -1;
             S.foreign = (int64_t)cnt[5];
-            S.fallbacks = P->field_mode == QH_FIELDS_SOLVE ? c->last_fallbacks : 0;
+            S.fallbacks = solve ? c->last_fallbacks : 0;
             (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
             (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
             if (S.lost && status == QH_OK) status = QH_ELOST;

@@ -176,6 +176,9 @@ struct qh_ctx {
     // fields and deposits
     double *e = nullptr;                    // Ne (wall entries 0)
     double *e_old = nullptr;                // interior edges: e^n during a field update
+    double *e_prev = nullptr;               // interior edges: e^{n-1} for the wave-equation update
+    int64_t *g_prev = nullptr;              // Ne: the previous step's current (wave-equation update)
+    bool wave_hist = false;                 // e_prev, g_prev hold the previous step's values
     double *e_star = nullptr;               // interior edges: edge-solve solution of the last step
     int64_t *b = nullptr;                   // Nf
     int64_t *g = nullptr;                   // Ne
@@ -279,6 +282,7 @@ int qh_learned_probes(qh_ctx *c, float *V_dev, uint64_t seed);
 hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);
 hipError_t launch_assemble_A(qh_ctx *c, double tau);
 hipError_t launch_edge_rhs(qh_ctx *c);
+hipError_t launch_wave_rhs(qh_ctx *c);
 hipError_t launch_gauss_rhs(qh_ctx *c, double *thr2_dev, double tol_n);
 hipError_t launch_gauss_apply(qh_ctx *c);
 hipError_t launch_faraday(qh_ctx *c);

@@ -389,6 +389,32 @@ __global__ void __launch_bounds__(kThreads) k_sum2(const double *__restrict__ pa
     }
 }
 
+// Right-hand side of the wave-equation update (eq. wave_cont, Newmark beta = 1/4, gamma = 1/2)
+// on the interior edges:
+//   rhs = 2 ([*eps] - tau S) e^n - ([*eps] + tau S) e^{n-1} - u_q (g^{n+1/2} - g^{n-1/2}),
+// the two products over the pattern of A in one kernel (the same thread owns the same row in
+// both passes, so the second adds to what the first wrote).
+__global__ void __launch_bounds__(kThreads) k_wave_rhs(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                       const int32_t *__restrict__ ptr, const TileCols cols,
+                                                       const double *__restrict__ arhs,
+                                                       const double *__restrict__ aval,
+                                                       const double *__restrict__ e,
+                                                       const double *__restrict__ e_prev,
+                                                       const int64_t *__restrict__ g,
+                                                       const int64_t *__restrict__ g_prev,
+                                                       const int32_t *__restrict__ int_edges, double u_q,
+                                                       double *__restrict__ rhs) {
+    __shared__ double prod[kTileCap];
+    tile_spmv(tiles, ntiles, ptr, cols, arhs, e, prod,
+              [&](int32_t row) {
+                  const int32_t ge = int_edges[row];
+                  return (double)(g[ge] - g_prev[ge]);
+              },
+              [&](int32_t row, double s, double dg) { rhs[row] = 2.0 * s - u_q * dg; });
+    tile_spmv(tiles, ntiles, ptr, cols, aval, e_prev, prod, [&](int32_t) { return 0; },
+              [&](int32_t row, double s, int) { rhs[row] -= s; });
+}
+
 }  // namespace
 
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n) {
@@ -553,6 +579,13 @@ hipError_t launch_edge_rhs(qh_ctx *c) {
                        c->cge.b);
     hipLaunchKernelGGL(k_edge_rhs_b, dim3(tile_grid(c->CMb.ntiles)), dim3(kThreads), 0, c->stream, c->CMb.tiles,
                        c->CMb.ntiles, c->CMb.ptr, c->CMb.cols(), c->CMb.val, c->b, c->phys.dt * c->phys.u_b, c->cge.b);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_rhs(qh_ctx *c) {
+    hipLaunchKernelGGL(k_wave_rhs, dim3(tile_grid(c->A.ntiles)), dim3(kThreads), 0, c->stream, c->A.tiles,
+                       c->A.ntiles, c->A.ptr, c->A.cols(), c->A_rhs, c->A.val, c->cge.x, c->e_prev, c->g, c->g_prev,
+                       c->int_edges, c->phys.u_q, c->cge.b);
     return hipGetLastError();
 }
 

@@ -187,6 +187,61 @@ def test_full_cycle_field_update_matches_oracle(jitter4):
         assert not (cx.D @ b_g).any()
 
 
+def test_wave_field_update_matches_oracle(jitter4):
+    """Field updates of the wave-equation mode (eq. wave_cont): the first step (no history) is the
+    trapezoidal update, every later one equals the oracle's wave update applied to the same
+    e^n, e^{n-1}, b^n and step currents."""
+    import paper_2103_06737_amd as qh
+    from oracle.field import FieldOracle, WaveOracle
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    dt = 2e-10
+    ctx = gpu_context(mesh, dt)
+    ctx.fields_upload(e, b)
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = parts["e"]
+    ctx.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
+    fo, wo = FieldOracle(cx, op, dt), WaveOracle(cx, op, dt)
+    u_q = qi.QE * 2.0 ** -40
+    params = ctx.step_params(field_mode=qh.FIELDS_WAVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    Qbg = np.zeros(cx.Nn, np.int64)
+    e_prev = g_prev = None
+    for k in range(8):
+        e_n, b_n = ctx.fields_download()
+        st = ctx.pic_step(params)[0]
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
+        assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+        e_g, b_g = ctx.fields_download()
+        g, Q = ctx.deposits_download()
+        if k == 0:
+            e_o, b_o, _ = fo.step(e_n, b_n, U_B, g, u_q, Q, Qbg, tol=1e-13, tol_n=1e-13)
+        else:
+            rho = u_q * (Qbg - Q).astype(np.float64)[cx.int_nodes]
+            e_o, b_o, _ = wo.wave_step(e_n, e_prev, b_n, U_B, g, g_prev, u_q, rho, tol=1e-13, tol_n=1e-13)
+        assert np.linalg.norm(e_g - e_o) <= 1e-8 * np.linalg.norm(e_o)
+        assert np.abs(b_g - b_o).max() <= 2 + 1e-9 * np.abs(b_o).max()
+        assert not (cx.D @ b_g).any()
+        e_prev, g_prev = e_n, g
+
+
+def test_wave_mode_equals_trapezoidal_source_free(jitter4):
+    """Without particles the wave-equation mode and the trapezoidal mode give the same fields
+    (Newmark beta = 1/4 on the wave equation is the trapezoidal rule with b eliminated), step
+    after step, to the solver tolerance."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    dt = 2e-10
+    out = {}
+    for mode in (qh.FIELDS_SOLVE, qh.FIELDS_WAVE):
+        ctx = gpu_context(mesh, dt)
+        ctx.fields_upload(e, b)
+        ctx.pic_step(ctx.step_params(field_mode=mode, tol_edge=1e-12, tol_node=1e-12), 12)
+        out[mode] = ctx.fields_download()
+    e_t, b_t = out[qh.FIELDS_SOLVE]
+    e_w, b_w = out[qh.FIELDS_WAVE]
+    assert np.linalg.norm(e_w - e_t) <= 1e-8 * np.linalg.norm(e_t)
+    assert np.abs(b_w - b_t).max() <= 2 + 1e-8 * np.abs(b_t).max()
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
@@ -293,6 +348,29 @@ def test_gauss_correction_holds_the_law(jitter4):
         assert abs(fo.gauss_error(e1, rho) - res[gauss][-1]) <= 1e-4 * res[gauss][-1] + 1e-14
     assert res[1].max() <= 1.01e-8
     assert res[0][2:].min() > 1e3 * res[1].max()
+
+
+def test_wave_gauss_error_grows_without_correction(jitter4):
+    """The Gauss-law figure of Sec. VI on the device: with a loose edge solve (1e-4) and no
+    correction, the Gauss-law error of the trapezoidal update levels off while that of the
+    wave-equation update keeps growing (the t grad Phi null space); with the correction the
+    wave-equation update holds the law to the node solve's tolerance."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    x, v, tet = parts["e"]
+    res = {}
+    for mode, gauss in ((qh.FIELDS_SOLVE, 0), (qh.FIELDS_WAVE, 0), (qh.FIELDS_WAVE, 1)):
+        ctx = gpu_context(mesh, cfg["dt"])
+        ctx.fields_upload(np.zeros_like(e), b)
+        sid = ctx.species_add(-qi.QE / qi.ME, -1)
+        ctx.particles_upload(sid, x, v, tet)
+        ctx.charge_background(1)
+        st = ctx.pic_step(ctx.step_params(field_mode=mode, gauss=gauss, tol_edge=1e-4, tol_node=1e-8), 40)
+        res[mode, gauss] = np.array([s["gauss_res"] for s in st])
+    t, w = res[qh.FIELDS_SOLVE, 0], res[qh.FIELDS_WAVE, 0]
+    assert t[-1] < 1.2 * t[2]
+    assert w[-1] > 3 * w[2] and w[-1] > 3 * t[-1]
+    assert res[qh.FIELDS_WAVE, 1].max() <= 1.01e-8
 
 
 def test_scattered_numbering_reads_wide_column_tiles():
