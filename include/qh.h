@@ -126,6 +126,16 @@ int qh_create(qh_ctx **out, int device, void *stream);
 void qh_destroy(qh_ctx *ctx);
 const char *qh_last_error(const qh_ctx *ctx);
 
+#define QH_BC_PEC 0     /* walls are perfect conductors: wall edges carry no E, wall nodes are grounded */
+#define QH_BC_NEUMANN 1 /* natural boundary: every edge and node is an unknown; the Gauss-law solve
+                           is singular (constants) and its potential is fixed only up to the
+                           zero-mean constraint of eq. zero_mean_constraint, which e does not see */
+
+/* Field boundary condition of the context (Sec. II.C, eq. zero_mean_constraint): QH_BC_PEC
+ * (default) or QH_BC_NEUMANN. Call before qh_mesh_upload (QH_ESTATE afterwards). Particles
+ * reflect specularly at the walls in both cases. */
+int qh_set_boundary(qh_ctx *ctx, int32_t mode);
+
 /* Mesh (Sec. II.C): builds K = {N, E, F, T}, incidence, geometry, the Hodge matrices
  * [*eps] (W1 mass), [*mu^-1] (W2 mass), S = C^T [*mu^-1] C and G^T [*eps] G on the host in
  * FP64 and uploads them. xyz: 3*n_nodes doubles (x0 y0 z0 x1 ...); tet_nodes: 4*n_tets

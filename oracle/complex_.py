@@ -17,7 +17,10 @@ LOCAL_FACES = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]  # face k is opposite
 
 
 class Complex:
-    def __init__(self, xyz: np.ndarray, tets: np.ndarray):
+    def __init__(self, xyz: np.ndarray, tets: np.ndarray, neumann: bool = False):
+        # neumann: natural boundary, every edge and node an unknown (PEC otherwise: wall edges
+        # carry no E and wall nodes are grounded)
+        self.neumann = neumann
         self.xyz = np.asarray(xyz, dtype=np.float64)
         T = np.sort(np.asarray(tets, dtype=np.int64), axis=1)
         self.tets = T
@@ -119,11 +122,11 @@ class Complex:
     # interior index sets (PEC walls: wall edges carry e = 0, wall nodes are grounded)
     @property
     def int_edges(self) -> np.ndarray:
-        return np.flatnonzero(~self.wall_edge)
+        return np.arange(self.Ne) if self.neumann else np.flatnonzero(~self.wall_edge)
 
     @property
     def int_nodes(self) -> np.ndarray:
-        return np.flatnonzero(~self.wall_node)
+        return np.arange(self.Nn) if self.neumann else np.flatnonzero(~self.wall_node)
 
     def edge_lengths(self) -> np.ndarray:
         d = self.xyz[self.edges[:, 1]] - self.xyz[self.edges[:, 0]]

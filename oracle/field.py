@@ -63,6 +63,19 @@ class FieldOracle:
         self.A = A[ie][:, ie].tocsr()
         self.Bm = (op.Meps - self.tau * op.S).tocsr()
         self.K = op.K[inn][:, inn].tocsr()
+        if cx.neumann:
+            # natural boundary: K has the constants as null space; the potential is fixed by the
+            # zero-mean constraint of eq. zero_mean_constraint, delta = C_z y with the last
+            # node's value -sum_i alpha_i y_i / alpha_n, alpha_i = integral of W0_i
+            P = cx.xyz[cx.tets]
+            vol = np.abs(np.einsum("ti,ti->t", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))) / 6.0
+            alpha = np.bincount(cx.tets.ravel(), weights=np.repeat(vol / 4.0, 4), minlength=cx.Nn)
+            n = cx.Nn
+            top = sp.identity(n - 1, format="csr")
+            last = sp.csr_matrix(-alpha[:-1] / alpha[-1])
+            self.Cz = sp.vstack([top, last]).tocsr()
+            self.Kz = (self.Cz.T @ self.K @ self.Cz).tocsr()
+            self.alpha = alpha
         self.Gf = cx.G.astype(np.float64).tocsr()
         self.GtMeps = (self.Gf.T @ op.Meps).tocsr()
         self.Gint = self.Gf[:, inn].tocsr()
@@ -90,7 +103,12 @@ class FieldOracle:
         scale = self.gauss_scale(es, rho)
         if scale > 0 and np.linalg.norm(rg) > tol_n * scale:
             tol_rel = tol_n * scale / np.linalg.norm(rg)
-            dl, itn, _ = pcg(self.K, rg, tol=tol_rel)
+            if self.cx.neumann:
+                rz = self.Cz.T @ rg
+                y, itn, _ = pcg(self.Kz, rz, tol=tol_rel * np.linalg.norm(rg) / max(np.linalg.norm(rz), 1e-300))
+                dl = self.Cz @ y
+            else:
+                dl, itn, _ = pcg(self.K, rg, tol=tol_rel)
         else:
             dl, itn = np.zeros(self.inn.size), 0
         info.update(node_it=itn)
@@ -157,7 +175,8 @@ def init_fields(cx: Complex, white_e, white_a, sigma_e, bz, sigma_b, u_b):
     """
     ell = cx.edge_lengths()
     e = ell * sigma_e * white_e
-    e[cx.wall_edge] = 0.0
+    if not cx.neumann:
+        e[cx.wall_edge] = 0.0
     xa, xb = cx.xyz[cx.edges[:, 0]], cx.xyz[cx.edges[:, 1]]
     a = bz * 0.5 * (xa[:, 0] + xb[:, 0]) * (xb[:, 1] - xa[:, 1])
     a = a + sigma_b * ell ** 2 / (2.0 * np.sqrt(3.0)) * white_a

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqh.so")
 QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 FIELDS_FROZEN, FIELDS_SOLVE, FIELDS_WAVE = 0, 1, 2
+BC_PEC, BC_NEUMANN = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
@@ -31,7 +32,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
            "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
-           "qh_precond_train", "qh_edge_system_download"]
+           "qh_precond_train", "qh_edge_system_download", "qh_set_boundary"]
 
 
 class QhError(RuntimeError):
@@ -104,6 +105,7 @@ def lib():
             "qh_create": [C.POINTER(p), C.c_int, p],
             "qh_destroy": [p],
             "qh_mesh_upload": [p, i64, p, i64, p],
+            "qh_set_boundary": [p, i32],
             "qh_mesh_info": [p, C.POINTER(MeshInfo)],
             "qh_mesh_topology": [p, p, p, p, p, p, p, p, p],
             "qh_set_physics": [p, C.POINTER(Phys)],
@@ -180,6 +182,10 @@ class Context:
         return rc
 
     # mesh -----------------------------------------------------------------------------
+    def set_boundary(self, mode):
+        """BC_PEC (default) or BC_NEUMANN; before mesh_upload."""
+        self._check(self.L.qh_set_boundary(self.h, int(mode)))
+
     def mesh_upload(self, xyz, tets):
         xyz = _c(xyz, np.float64)
         tets = _c(tets, np.int32)

@@ -143,7 +143,7 @@ int set_fields(qh_ctx *c, const double *e, const int64_t *b) {
     if (rc) return rc;
     std::vector<double> eh(e, e + m.Ne);
     for (int64_t i = 0; i < m.Ne; ++i)
-        if (m.wall_edge[i]) eh[i] = 0.0;
+        if (m.wall_edge[i] && !m.neumann) eh[i] = 0.0;
     QH_HIP(c, hipMemcpyAsync(c->e, eh.data(), sizeof(double) * m.Ne, hipMemcpyHostToDevice, c->stream));
     QH_HIP(c, hipMemcpyAsync(c->b, b, sizeof(int64_t) * m.Nf, hipMemcpyHostToDevice, c->stream));
     QH_HIP(c, hipMemsetAsync(c->divb0, 0, sizeof(int64_t) * m.Nt, c->stream));
@@ -215,9 +215,18 @@ void qh_destroy(qh_ctx *c) {
 
 const char *qh_last_error(const qh_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int qh_set_boundary(qh_ctx *c, int32_t mode) {
+    if (!c) return QH_EINVAL;
+    if (mode != QH_BC_PEC && mode != QH_BC_NEUMANN) return qh_fail(c, QH_EINVAL, "boundary mode");
+    if (c->have_mesh) return qh_fail(c, QH_ESTATE, "the boundary condition is set before the mesh");
+    c->bc = mode;
+    return QH_OK;
+}
+
 int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tet_nodes) {
     if (!c) return QH_EINVAL;
     if (c->have_mesh) return qh_fail(c, QH_ESTATE, "mesh already uploaded (one mesh per context)");
+    c->hm.neumann = c->bc == QH_BC_NEUMANN;
     std::string msg = qh_build_mesh(c->hm, n_nodes, xyz, n_tets, tet_nodes);
     if (!msg.empty()) return qh_fail(c, QH_EINVAL, msg);
     HostMesh &m = c->hm;
@@ -357,7 +366,7 @@ int qh_fields_init_synthetic(qh_ctx *c, const double *we, const double *wa, doub
         const double *pa = &m.xyz[3 * (int64_t)m.edges[2 * i]], *pb = &m.xyz[3 * (int64_t)m.edges[2 * i + 1]];
         double d[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
         double ell = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        if (!m.wall_edge[i]) e[i] = ell * sigma_e * we[i];
+        if (m.neumann || !m.wall_edge[i]) e[i] = ell * sigma_e * we[i];
         double av = bz * 0.5 * (pa[0] + pb[0]) * d[1] + k * ell * ell * wa[i];
         a[i] = (int64_t)std::llrint(av / c->phys.u_b);
     }

@@ -28,6 +28,7 @@ struct HostCsr {
 
 struct HostMesh {
     int64_t Nn = 0, Ne = 0, Nf = 0, Nt = 0;
+    bool neumann = false;                       // every edge and node is an unknown (no PEC walls)
     std::vector<double> xyz;                    // 3*Nn
     std::vector<int32_t> tn;                    // 4*Nt, ascending
     std::vector<int32_t> te;                    // 6*Nt
@@ -138,6 +139,7 @@ struct LearnedPrec {
 
 struct qh_ctx {
     int device = 0;
+    int32_t bc = QH_BC_PEC;  // field boundary condition (qh_set_boundary, before the mesh)
     bool host_only = false;  // device < 0: host mesh and assembly only (no GPU calls)
     hipStream_t stream = nullptr;
     std::string err;

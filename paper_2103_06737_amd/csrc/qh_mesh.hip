@@ -30,7 +30,9 @@ std::string qh_build_mesh(HostMesh &m, int64_t Nn, const double *xyz, int64_t Nt
                           const int32_t *tet_nodes) {
     if (Nn <= 0 || Nt <= 0 || !xyz || !tet_nodes) return "empty mesh or null pointer";
     if (Nn >= (int64_t)1 << 31 || 6 * Nt >= (int64_t)1 << 31) return "mesh too large for int32 ids";
+    const bool neumann = m.neumann;  // the boundary condition is chosen before the mesh
     m = HostMesh();
+    m.neumann = neumann;
     m.Nn = Nn;
     m.Nt = Nt;
     m.xyz.assign(xyz, xyz + 3 * Nn);
@@ -128,13 +130,14 @@ std::string qh_build_mesh(HostMesh &m, int64_t Nn, const double *xyz, int64_t Nt
         }
     m.int_edge_of.assign(m.Ne, -1);
     m.int_node_of.assign(Nn, -1);
+    // unknowns: everything but the walls (PEC), or everything (natural boundary)
     for (int64_t e = 0; e < m.Ne; ++e)
-        if (!m.wall_edge[e]) {
+        if (m.neumann || !m.wall_edge[e]) {
             m.int_edge_of[e] = (int32_t)m.int_edges.size();
             m.int_edges.push_back((int32_t)e);
         }
     for (int64_t n = 0; n < Nn; ++n)
-        if (!m.wall_node[n]) {
+        if (m.neumann || !m.wall_node[n]) {
             m.int_node_of[n] = (int32_t)m.int_nodes.size();
             m.int_nodes.push_back((int32_t)n);
         }

@@ -242,6 +242,47 @@ def test_wave_mode_equals_trapezoidal_source_free(jitter4):
     assert np.abs(b_w - b_t).max() <= 2 + 1e-8 * np.abs(b_t).max()
 
 
+def test_neumann_field_update_matches_oracle(jitter4):
+    """Natural boundary (eq. zero_mean_constraint): every edge and node is an unknown and the
+    Gauss-law system is singular (constants). The device solves it by CG on the consistent right-
+    hand side (a neutral plasma); the oracle on the zero-mean subspace of the paper. e does not
+    see the constant, so the field updates agree step by step."""
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    from oracle.field import FieldOracle
+    from oracle.particles import ParticleOracle
+    from oracle.whitney import Operators
+    cfg, mesh, _, _, _, _, _, parts = jitter4
+    cx = Complex(mesh.xyz, mesh.tets, neumann=True)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    e, b = oracle_fields(cx, cfg, U_B)
+    assert np.abs(e[cx.wall_edge]).max() > 0
+    dt = 2e-10
+    ctx = qh.Context(0)
+    ctx.set_boundary(qh.BC_NEUMANN)
+    ctx.mesh_upload(mesh.xyz, mesh.tets)
+    u_q = qi.QE * 2.0 ** -40
+    ctx.set_physics(qi.EPS0, qi.MU0, dt, u_q, U_B)
+    ctx.fields_upload(e, b)
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = parts["e"]
+    ctx.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
+    ctx.charge_background(1)
+    _, Q_bg = ctx.deposits_download()
+    fo = FieldOracle(cx, op, dt)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    for k in range(6):
+        e_n, b_n = ctx.fields_download()
+        st = ctx.pic_step(params)[0]
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
+        assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+        e_g, b_g = ctx.fields_download()
+        g, Q = ctx.deposits_download()
+        e_o, b_o, _ = fo.step(e_n, b_n, U_B, g, u_q, Q, Q_bg, tol=1e-13, tol_n=1e-13)
+        assert np.linalg.norm(e_g - e_o) <= 1e-8 * np.linalg.norm(e_o)
+        assert np.abs(b_g - b_o).max() <= 2 + 1e-9 * np.abs(b_o).max()
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh

@@ -242,3 +242,31 @@ def test_wave_gauss_error_grows_without_correction(jitter4):
     assert err_t[-1] < 2 * err_t[9]
     err_t, err_w, _ = _wave_vs_trapezoidal(jitter4, tol=1e-6, gauss=True)
     assert err_t.max() < 1e-10 and err_w.max() < 1e-10
+
+
+def test_neumann_gauss_projection_zero_mean():
+    """Natural boundary (eq. zero_mean_constraint): the Gauss-law system G^T[*eps]G on all nodes
+    has the constants as null space; the projection solves it on the zero-mean subspace
+    (alpha^T delta = 0, alpha_i the integral of W0_i) and reaches the law to its tolerance. e does
+    not depend on the constant (G 1 = 0): the least-squares solution of the singular system gives
+    the same field."""
+    import scipy.sparse.linalg as sla
+    from oracle.complex_ import Complex
+    from oracle.whitney import Operators
+    m = qi.make_mesh(qi.CONFIGS["jitter4"])
+    cx = Complex(m.xyz, m.tets, neumann=True)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    fo = Fo.FieldOracle(cx, op, 2e-9)
+    assert cx.int_edges.size == cx.Ne and cx.int_nodes.size == cx.Nn
+    assert np.allclose(fo.K @ np.ones(cx.Nn), 0.0, atol=1e-12 * abs(fo.K).max())
+    assert np.isclose(fo.alpha.sum(), 1.0)           # the unit cube's volume
+    rng = np.random.default_rng(6)
+    es = rng.standard_normal(cx.Ne) * 1e2
+    q = rng.standard_normal(cx.Nn)
+    rho = (q - q.mean()) * 1e-10                       # neutral: a consistent right-hand side
+    info = {}
+    e = fo.gauss_project(es, rho, 1e-13, info)
+    assert fo.gauss_error(e, rho) < 1e-12
+    dl = np.linalg.lstsq(fo.K.toarray(), fo.gauss_residual(es, rho), rcond=None)[0]
+    e_ls = es + fo.Gint @ dl
+    assert np.linalg.norm(e - e_ls) <= 1e-10 * np.linalg.norm(e)
