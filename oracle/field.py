@@ -114,15 +114,18 @@ class FieldOracle:
         info.update(node_it=itn)
         return es + self.Gint @ dl
 
-    def step(self, e, b_int, u_b, g_int, u_q, Q_new, Q_bg, tol=1e-12, tol_n=1e-12, gauss=True):
+    def step(self, e, b_int, u_b, g_int, u_q, Q_new, Q_bg, tol=1e-12, tol_n=1e-12, gauss=True, h_sum=None):
         """One field update with rho^{n+1} = u_q (Q_bg - Q^{n+1}) on the interior nodes."""
         rho = u_q * (Q_bg - Q_new).astype(np.float64)[self.inn]
-        return self.step_with_rho(e, b_int, u_b, g_int, u_q, rho, tol, tol_n, gauss)
+        return self.step_with_rho(e, b_int, u_b, g_int, u_q, rho, tol, tol_n, gauss, h_sum)
 
-    def step_with_rho(self, e, b_int, u_b, g_int, u_q, rho, tol=1e-12, tol_n=1e-12, gauss=True):
-        """One field update given rho^{n+1} on the interior nodes. Returns (e, b, info)."""
+    def step_with_rho(self, e, b_int, u_b, g_int, u_q, rho, tol=1e-12, tol_n=1e-12, gauss=True, h_sum=None):
+        """One field update given rho^{n+1} on the interior nodes; h_sum: the boundary source
+        dt/2 (h^n + h^{n+1}) on every edge, or None. Returns (e, b, info)."""
         b_real = b_int.astype(np.float64) * u_b
         rhs = self.rhs(e, b_real, g_int.astype(np.float64) * u_q)
+        if h_sum is not None:
+            rhs = rhs + h_sum[self.ie]
         x0 = e[self.ie].copy()
         xs, it, res = pcg(self.A, rhs, x0=x0, tol=tol)
         es = np.zeros_like(e)
@@ -151,10 +154,14 @@ class WaveOracle(FieldOracle):
         r = self.op.Meps @ (2.0 * e - e_prev) - self.tau * (self.op.S @ (2.0 * e + e_prev)) - dg_real
         return r[self.ie]
 
-    def wave_step(self, e, e_prev, b_int, u_b, g_int, g_prev_int, u_q, rho, tol=1e-12, tol_n=1e-12, gauss=True):
+    def wave_step(self, e, e_prev, b_int, u_b, g_int, g_prev_int, u_q, rho, tol=1e-12, tol_n=1e-12, gauss=True,
+                  h_diff=None):
         """One wave-equation update given e^n, e^{n-1}, the step currents g^{n+1/2}, g^{n-1/2}
-        and rho^{n+1} on the interior nodes. Returns (e^{n+1}, b^{n+1}, info)."""
+        and rho^{n+1} on the interior nodes; h_diff: the boundary source dt/2 (h^{n+1} - h^{n-1})
+        on every edge, or None. Returns (e^{n+1}, b^{n+1}, info)."""
         rhs = self.wave_rhs(e, e_prev, (g_int - g_prev_int).astype(np.float64) * u_q)
+        if h_diff is not None:
+            rhs = rhs + h_diff[self.ie]
         xs, it, res = pcg(self.A, rhs, x0=e[self.ie].copy(), tol=tol)
         es = np.zeros_like(e)
         es[self.ie] = xs
@@ -163,6 +170,79 @@ class WaveOracle(FieldOracle):
         info["gauss_res"] = self.gauss_error(e_new, rho)
         u = np.rint(0.5 * self.dt * (e_new + e) / u_b).astype(np.int64)
         return e_new, b_int - self.cx.C @ u, info
+
+
+# Dunavant's degree-4 rule on a triangle: barycentric points and weights (summing to 1)
+_DUNAVANT4 = [((0.108103018168070, 0.445948490915965, 0.445948490915965), 0.223381589678011),
+              ((0.445948490915965, 0.108103018168070, 0.445948490915965), 0.223381589678011),
+              ((0.445948490915965, 0.445948490915965, 0.108103018168070), 0.223381589678011),
+              ((0.816847572980459, 0.091576213509771, 0.091576213509771), 0.109951743655322),
+              ((0.091576213509771, 0.816847572980459, 0.091576213509771), 0.109951743655322),
+              ((0.091576213509771, 0.091576213509771, 0.816847572980459), 0.109951743655322)]
+
+
+class PlaneWave:
+    """Plane wave entering through a natural boundary (the Neumann test of Sec. VI.A.2): E along
+    -z, travelling along +x, with the time signature of a derivative of a modulated Gaussian (our
+    own; the paper's formula is in a reference that is not available),
+        s(u) = exp(-u^2 / (2 sig^2)) cos(2 pi f0 u), u = tau - t0, sig = 1 / (2 pi bw),
+        E_inc = -z E0 s'(t - x/c),   H_inc = y (E0 / eta) s'(t - x/c).
+    Integrating W1_i . curl H by parts in Ampere's law leaves the boundary term
+    h_i(t) = integral over the boundary of W1_i . (n x H_inc) dS (n outward), taken here with
+    Dunavant's degree-4 rule on every boundary face; the trapezoidal update adds
+    dt/2 (h^n + h^{n+1}) to its right-hand side, the wave update dt/2 (h^{n+1} - h^{n-1})."""
+
+    def __init__(self, cx: Complex, op: Operators, E0, f0, bw, t0):
+        from .whitney import w1_at
+        from .complex_ import LOCAL_EDGES, LOCAL_FACES
+        self.cx, self.E0, self.f0, self.t0 = cx, E0, f0, t0
+        self.sig = 1.0 / (2.0 * np.pi * bw)
+        eps, mu = op.eps, op.mu
+        self.c = 1.0 / np.sqrt(eps * mu)
+        self.eta = np.sqrt(mu / eps)
+        # per boundary face and rule point: x of the point and, for the face's three edges, the
+        # weight times W1_i . (n x y-hat)
+        edges, coef, xq = [], [], []
+        for f in np.flatnonzero(cx.wall_face):
+            t, k = np.argwhere(cx.tet_faces == f)[0]
+            verts = LOCAL_FACES[k]
+            P = cx.xyz[cx.tets[t, list(verts)]]
+            area = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+            gk = op.Minv[t, k, 1:]
+            nvec = -gk / np.linalg.norm(gk)               # outward: lambda_k grows inward
+            nxy = np.cross(nvec, np.array([0.0, 1.0, 0.0]))
+            on_face = [j for j, (a, b) in enumerate(LOCAL_EDGES) if a in verts and b in verts]
+            for bary, w in _DUNAVANT4:
+                r = bary[0] * P[0] + bary[1] * P[1] + bary[2] * P[2]
+                for j in on_face:
+                    W = w1_at(op.Minv[t][None], r[None], LOCAL_EDGES[j])[0]
+                    edges.append(cx.tet_edges[t, j])
+                    coef.append(w * area * (W @ nxy))
+                    xq.append(r[0])
+        self.edges, self.coef, self.xq = np.array(edges), np.array(coef), np.array(xq)
+
+    def ds(self, tau):
+        """s'(tau)."""
+        u = tau - self.t0
+        om = 2.0 * np.pi * self.f0
+        env = np.exp(-u * u / (2.0 * self.sig ** 2))
+        return env * (-(u / self.sig ** 2) * np.cos(om * u) - om * np.sin(om * u))
+
+    def h(self, t):
+        """Boundary term h(t) on every edge (zero off the boundary)."""
+        out = np.zeros(self.cx.Ne)
+        np.add.at(out, self.edges, self.coef * (self.E0 / self.eta) * self.ds(t - self.xq / self.c))
+        return out
+
+    def e_line(self, t, npts=5):
+        """Line integrals of E_inc along every edge at time t (Gauss-Legendre)."""
+        xg, wg = np.polynomial.legendre.leggauss(npts)
+        a, b = self.cx.xyz[self.cx.edges[:, 0]], self.cx.xyz[self.cx.edges[:, 1]]
+        out = np.zeros(self.cx.Ne)
+        for s_, w in zip(0.5 * (xg + 1.0), 0.5 * wg):
+            x = a[:, 0] + s_ * (b[:, 0] - a[:, 0])
+            out += w * (-self.E0 * self.ds(t - x / self.c)) * (b[:, 2] - a[:, 2])
+        return out
 
 
 def init_fields(cx: Complex, white_e, white_a, sigma_e, bz, sigma_b, u_b):
