@@ -136,6 +136,18 @@ const char *qh_last_error(const qh_ctx *ctx);
  * reflect specularly at the walls in both cases. */
 int qh_set_boundary(qh_ctx *ctx, int32_t mode);
 
+/* Plane wave entering through the natural boundary (the Neumann test of Sec. VI.A.2): E along
+ * -z, travelling along +x, E_inc = -z E0 s'(t - x/c), H_inc = y (E0/eta) s'(t - x/c), with
+ * s(u) = exp(-(u - t0)^2 / (2 sig^2)) cos(2 pi f0 (u - t0)), sig = 1/(2 pi bandwidth) (the
+ * derivative of a modulated Gaussian). Each field update adds the boundary term of Ampere's law,
+ * h_i(t) = integral over the boundary of W1_i . (n x H_inc) dS (Dunavant's degree-4 rule per
+ * face), averaged over the step as the update's rule requires, and the Gauss-law target gains
+ * the normal flux this brings in (G^T of the same term, accumulated). t = steps taken by the
+ * context x dt. Needs QH_BC_NEUMANN, a mesh and physics; E0 = 0 switches it off. The accumulated
+ * flux survives a later call (the field still holds it) and is cleared by qh_fields_upload. A
+ * call replaces the previous wave's tables (device memory of the size of the boundary). */
+int qh_set_plane_wave(qh_ctx *ctx, double E0, double f0, double bandwidth, double t0);
+
 /* Mesh (Sec. II.C): builds K = {N, E, F, T}, incidence, geometry, the Hodge matrices
  * [*eps] (W1 mass), [*mu^-1] (W2 mass), S = C^T [*mu^-1] C and G^T [*eps] G on the host in
  * FP64 and uploads them. xyz: 3*n_nodes doubles (x0 y0 z0 x1 ...); tet_nodes: 4*n_tets

@@ -32,7 +32,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
            "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
-           "qh_precond_train", "qh_edge_system_download", "qh_set_boundary"]
+           "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave"]
 
 
 class QhError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
             "qh_destroy": [p],
             "qh_mesh_upload": [p, i64, p, i64, p],
             "qh_set_boundary": [p, i32],
+            "qh_set_plane_wave": [p, d, d, d, d],
             "qh_mesh_info": [p, C.POINTER(MeshInfo)],
             "qh_mesh_topology": [p, p, p, p, p, p, p, p, p],
             "qh_set_physics": [p, C.POINTER(Phys)],
@@ -185,6 +186,10 @@ class Context:
     def set_boundary(self, mode):
         """BC_PEC (default) or BC_NEUMANN; before mesh_upload."""
         self._check(self.L.qh_set_boundary(self.h, int(mode)))
+
+    def set_plane_wave(self, E0, f0, bandwidth, t0):
+        """Plane wave through the natural boundary (E along -z, travelling along +x)."""
+        self._check(self.L.qh_set_plane_wave(self.h, float(E0), float(f0), float(bandwidth), float(t0)))
 
     def mesh_upload(self, xyz, tets):
         xyz = _c(xyz, np.float64)

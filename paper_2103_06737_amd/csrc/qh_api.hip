@@ -155,6 +155,7 @@ int set_fields(qh_ctx *c, const double *e, const int64_t *b) {
     c->have_fields = true;
     c->fields_dirty = true;
     c->wave_hist = false;
+    if (c->dbnd) QH_HIP(c, hipMemsetAsync(c->dbnd, 0, sizeof(double) * m.Nn, c->stream));
     return sync(c);
 }
 
@@ -221,6 +222,120 @@ int qh_set_boundary(qh_ctx *c, int32_t mode) {
     if (c->have_mesh) return qh_fail(c, QH_ESTATE, "the boundary condition is set before the mesh");
     c->bc = mode;
     return QH_OK;
+}
+
+int qh_set_plane_wave(qh_ctx *c, double E0, double f0, double bandwidth, double t0) {
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh || !c->have_phys) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    if (c->bc != QH_BC_NEUMANN)
+        return qh_fail(c, QH_ESTATE, "a plane wave enters through a natural boundary (QH_BC_NEUMANN)");
+    if (E0 == 0.0) {
+        c->pw_on = false;
+        return QH_OK;
+    }
+    if (!std::isfinite(E0) || !std::isfinite(t0) || !(f0 > 0) || !(bandwidth > 0))
+        return qh_fail(c, QH_EINVAL, "plane wave: E0, t0 finite, f0 and bandwidth positive");
+    const HostMesh &m = c->hm;
+    // Dunavant's degree-4 rule on a triangle (barycentric points, weights summing to 1)
+    static const double kP[6][3] = {{0.108103018168070, 0.445948490915965, 0.445948490915965},
+                                    {0.445948490915965, 0.108103018168070, 0.445948490915965},
+                                    {0.445948490915965, 0.445948490915965, 0.108103018168070},
+                                    {0.816847572980459, 0.091576213509771, 0.091576213509771},
+                                    {0.091576213509771, 0.816847572980459, 0.091576213509771},
+                                    {0.091576213509771, 0.091576213509771, 0.816847572980459}};
+    static const double kW[6] = {0.223381589678011, 0.223381589678011, 0.223381589678011,
+                                 0.109951743655322, 0.109951743655322, 0.109951743655322};
+    static const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    struct Pt {
+        int32_t e;
+        double coef, x;
+    };
+    std::vector<Pt> pts;
+    for (int64_t t = 0; t < m.Nt; ++t)
+        for (int k = 0; k < 4; ++k) {
+            if (!m.wall_face[m.tf[4 * t + k]]) continue;
+            int v[3], nv = 0;
+            for (int i = 0; i < 4; ++i)
+                if (i != k) v[nv++] = i;
+            const double *g = &m.grad[12 * t];
+            const double gn = std::sqrt(g[3 * k] * g[3 * k] + g[3 * k + 1] * g[3 * k + 1] + g[3 * k + 2] * g[3 * k + 2]);
+            const double n[3] = {-g[3 * k] / gn, -g[3 * k + 1] / gn, -g[3 * k + 2] / gn};  // outward
+            const double nxy[3] = {-n[2], 0.0, n[0]};                                           // n x y-hat
+            const double *P[3];
+            for (int j = 0; j < 3; ++j) P[j] = &m.xyz[3 * (int64_t)m.tn[4 * t + v[j]]];
+            const double u[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+            const double w[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+            const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+            const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            for (int q = 0; q < 6; ++q) {
+                double lam[4] = {0.0, 0.0, 0.0, 0.0};
+                double x = 0.0;
+                for (int j = 0; j < 3; ++j) {
+                    lam[v[j]] = kP[q][j];
+                    x += kP[q][j] * P[j][0];
+                }
+                for (int j = 0; j < 6; ++j) {
+                    const int a = LE[j][0], b = LE[j][1];
+                    if (a == k || b == k) continue;  // the edge is not on this face
+                    double dotv = 0.0;                // W1_ab = lam_a grad lam_b - lam_b grad lam_a
+                    for (int d = 0; d < 3; ++d) dotv += (lam[a] * g[3 * b + d] - lam[b] * g[3 * a + d]) * nxy[d];
+                    pts.push_back({m.int_edge_of[m.te[6 * t + j]], kW[q] * area * dotv, x});
+                }
+            }
+        }
+    std::stable_sort(pts.begin(), pts.end(), [](const Pt &p, const Pt &q) { return p.e < q.e; });
+    std::vector<int32_t> ptr(1, 0), edge;
+    std::vector<double> coef(pts.size()), xq(pts.size());
+    for (size_t k = 0; k < pts.size(); ++k) {
+        if (k == 0 || pts[k].e != pts[k - 1].e) {
+            if (k) ptr.push_back((int32_t)k);
+            edge.push_back(pts[k].e);
+        }
+        coef[k] = pts[k].coef;
+        xq[k] = pts[k].x;
+    }
+    ptr.push_back((int32_t)pts.size());
+    const int32_t nb = (int32_t)edge.size();
+    // boundary nodes: per node, its boundary edges with the sign of G (head +1, tail -1)
+    std::vector<std::vector<int32_t>> lists(m.Nn);
+    for (int32_t i = 0; i < nb; ++i) {
+        const int32_t ge = m.int_edges[edge[i]];
+        lists[m.edges[2 * ge + 1]].push_back(i << 1);
+        lists[m.edges[2 * ge]].push_back(i << 1 | 1);
+    }
+    std::vector<int32_t> nptr(1, 0), nlist, node;
+    for (int64_t v = 0; v < m.Nn; ++v)
+        if (!lists[v].empty()) {
+            node.push_back((int32_t)v);
+            nlist.insert(nlist.end(), lists[v].begin(), lists[v].end());
+            nptr.push_back((int32_t)nlist.size());
+        }
+    QH_HIP(c, hipStreamSynchronize(c->stream));  // a second call replaces the first one's tables
+    qh_release(c, c->pw_ptr), qh_release(c, c->pw_edge), qh_release(c, c->pw_coef), qh_release(c, c->pw_x);
+    qh_release(c, c->pw_nptr), qh_release(c, c->pw_nlist), qh_release(c, c->pw_node);
+    qh_release(c, c->pw_hsum);
+    c->pw_on = false;
+    int rc;
+    if ((rc = upload(c, &c->pw_ptr, ptr.data(), ptr.size())) || (rc = upload(c, &c->pw_edge, edge.data(), edge.size())) ||
+        (rc = upload(c, &c->pw_coef, coef.data(), coef.size())) || (rc = upload(c, &c->pw_x, xq.data(), xq.size())) ||
+        (rc = upload(c, &c->pw_nptr, nptr.data(), nptr.size())) ||
+        (rc = upload(c, &c->pw_nlist, nlist.data(), nlist.size())) || (rc = upload(c, &c->pw_node, node.data(), node.size())) ||
+        (rc = qh_alloc(c, &c->pw_hsum, std::max<int32_t>(1, nb))))
+        return rc;
+    if (!c->dbnd) {  // the flux already brought in stays in the Gauss-law target
+        if ((rc = qh_alloc(c, &c->dbnd, m.Nn))) return rc;
+        QH_HIP(c, hipMemsetAsync(c->dbnd, 0, sizeof(double) * m.Nn, c->stream));
+    }
+    c->pw_nb = nb;
+    c->pw_nn = (int32_t)node.size();
+    c->pw_amp = E0 / std::sqrt(c->phys.mu0 / c->phys.eps0);
+    c->pw_c = 1.0 / std::sqrt(c->phys.eps0 * c->phys.mu0);
+    c->pw_f0 = f0;
+    c->pw_sig = 1.0 / (2.0 * M_PI * bandwidth);
+    c->pw_t0 = t0;
+    c->pw_on = true;
+    return sync(c);
 }
 
 int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tet_nodes) {
@@ -633,6 +748,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             const bool wave = P->field_mode == QH_FIELDS_WAVE && c->wave_hist;
             int t0 = qh_tbeg(c);
             QH_HIP(c, wave ? launch_wave_rhs(c) : launch_edge_rhs(c));
+            if (c->pw_on) QH_HIP(c, launch_plane_wave(c, wave));
             qh_tend(c, t0, QK_EDGE_RHS);
             int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr, false,
                                  learned);

@@ -181,6 +181,16 @@ struct qh_ctx {
     double *e_prev = nullptr;               // interior edges: e^{n-1} for the wave-equation update
     int64_t *g_prev = nullptr;              // Ne: the previous step's current (wave-equation update)
     bool wave_hist = false;                 // e_prev, g_prev hold the previous step's values
+    // plane wave through the natural boundary (qh_set_plane_wave)
+    bool pw_on = false;
+    double pw_amp = 0.0, pw_f0 = 0.0, pw_sig = 0.0, pw_t0 = 0.0, pw_c = 0.0;  // amp = E0 / eta
+    int32_t pw_nb = 0, pw_nn = 0;           // boundary edges, boundary nodes
+    int32_t *pw_ptr = nullptr, *pw_edge = nullptr;   // per boundary edge: its rule points, its unknown index
+    double *pw_coef = nullptr, *pw_x = nullptr;      // per point: weight x W1 . (n x y-hat), x
+    double *pw_hsum = nullptr;              // per boundary edge: dt/2 (h^n + h^{n+1}) of this step
+    int32_t *pw_nptr = nullptr, *pw_nlist = nullptr; // per boundary node: boundary edge index << 1 | (1: tail)
+    int32_t *pw_node = nullptr;             // boundary node ids
+    double *dbnd = nullptr;                 // Nn: boundary flux accumulated into the Gauss-law target
     double *e_star = nullptr;               // interior edges: edge-solve solution of the last step
     int64_t *b = nullptr;                   // Nf
     int64_t *g = nullptr;                   // Ne
@@ -247,6 +257,19 @@ int qh_alloc(qh_ctx *c, T **p, size_t count) {
     return QH_OK;
 }
 
+// Frees a buffer from qh_alloc before qh_destroy (the caller has synchronised its stream).
+template <class T>
+void qh_release(qh_ctx *c, T *&p) {
+    if (!p) return;
+    for (auto it = c->allocations.begin(); it != c->allocations.end(); ++it)
+        if (*it == (void *)p) {
+            c->allocations.erase(it);
+            (void)hipFree((void *)p);
+            break;
+        }
+    p = nullptr;
+}
+
 // ---------------------------------------------------------------------------------------
 // Kernel launchers
 // qh_particles.hip
@@ -285,6 +308,7 @@ hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);
 hipError_t launch_assemble_A(qh_ctx *c, double tau);
 hipError_t launch_edge_rhs(qh_ctx *c);
 hipError_t launch_wave_rhs(qh_ctx *c);
+hipError_t launch_plane_wave(qh_ctx *c, bool wave);
 hipError_t launch_gauss_rhs(qh_ctx *c, double *thr2_dev, double tol_n);
 hipError_t launch_gauss_apply(qh_ctx *c);
 hipError_t launch_faraday(qh_ctx *c);

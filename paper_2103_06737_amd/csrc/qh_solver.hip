@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t
                                                         const int64_t *__restrict__ Qbg,
                                                         const int64_t *__restrict__ Q,
                                                         const int32_t *__restrict__ int_nodes, double u_q,
+                                                        const double *__restrict__ dbnd,
                                                         double *__restrict__ rg, double *__restrict__ rho_out,
                                                         double *__restrict__ part) {
     const int sub = threadIdx.x % kLpr;
@@ -303,7 +304,8 @@ __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t
         sa = wave_sum_lpr(sa);
         if (sub == 0) {
             int32_t gn = int_nodes[row];
-            double rho = u_q * (double)(Qbg[gn] - Q[gn]);
+            // charge, plus the normal flux a plane wave brought in through a natural boundary
+            double rho = u_q * (double)(Qbg[gn] - Q[gn]) + (dbnd ? dbnd[gn] : 0.0);
             double r = rho - s;
             rg[row] = r;
             if (rho_out) rho_out[row] = rho;
@@ -413,6 +415,51 @@ __global__ void __launch_bounds__(kThreads) k_wave_rhs(const int2 *__restrict__ 
               [&](int32_t row, double s, double dg) { rhs[row] = 2.0 * s - u_q * dg; });
     tile_spmv(tiles, ntiles, ptr, cols, aval, e_prev, prod, [&](int32_t) { return 0; },
               [&](int32_t row, double s, int) { rhs[row] -= s; });
+}
+
+// Plane wave through the natural boundary. s'(tau) of the modulated Gaussian s(u) =
+// exp(-(u - t0)^2 / (2 sig^2)) cos(2 pi f0 (u - t0)).
+__device__ __forceinline__ double pw_ds(double tau, double f0, double sig, double t0) {
+    const double u = tau - t0, om = 2.0 * M_PI * f0;
+    const double env = exp(-u * u / (2.0 * sig * sig));
+    return env * (-(u / (sig * sig)) * cos(om * u) - om * sin(om * u));
+}
+
+// Boundary term h_i(t) = sum over the edge's rule points of coef * (E0/eta) s'(t - x/c), at the
+// step's times; adds the update's share to the right-hand side (trapezoidal: dt/2 (h^n +
+// h^{n+1}); wave equation: dt/2 (h^{n+1} - h^{n-1})) and keeps dt/2 (h^n + h^{n+1}) for the
+// Gauss-law target.
+__global__ void k_plane_wave(int32_t nb, const int32_t *__restrict__ ptr, const int32_t *__restrict__ edge,
+                             const double *__restrict__ coef, const double *__restrict__ xq, double amp, double f0,
+                             double sig, double t0, double c0, double t_prev, double t_n, double t_next, double half_dt,
+                             int wave, double *__restrict__ rhs, double *__restrict__ hsum) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    double hp = 0.0, hn = 0.0, hx = 0.0;
+    for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const double ret = xq[k] / c0;
+        hn += coef[k] * pw_ds(t_n - ret, f0, sig, t0);
+        hx += coef[k] * pw_ds(t_next - ret, f0, sig, t0);
+        if (wave) hp += coef[k] * pw_ds(t_prev - ret, f0, sig, t0);
+    }
+    const double hs = half_dt * amp * (hn + hx);
+    hsum[i] = hs;
+    rhs[edge[i]] += wave ? half_dt * amp * (hx - hp) : hs;
+}
+
+// dbnd += G^T hsum on the boundary nodes (edge a -> b: +1 at b, -1 at a), one thread per node in
+// a fixed order.
+__global__ void k_boundary_flux(int32_t nn, const int32_t *__restrict__ nptr, const int32_t *__restrict__ nlist,
+                                const int32_t *__restrict__ node, const double *__restrict__ hsum,
+                                double *__restrict__ dbnd) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    double s = 0.0;
+    for (int32_t k = nptr[i]; k < nptr[i + 1]; ++k) {
+        const int32_t v = nlist[k];
+        s += (v & 1) ? -hsum[v >> 1] : hsum[v >> 1];
+    }
+    dbnd[node[i]] += s;
 }
 
 }  // namespace
@@ -589,12 +636,22 @@ hipError_t launch_wave_rhs(qh_ctx *c) {
     return hipGetLastError();
 }
 
+hipError_t launch_plane_wave(qh_ctx *c, bool wave) {
+    const double dt = c->phys.dt, tn = (double)c->step_index * dt;
+    hipLaunchKernelGGL(k_plane_wave, dim3((c->pw_nb + 255) / 256), dim3(256), 0, c->stream, c->pw_nb, c->pw_ptr,
+                       c->pw_edge, c->pw_coef, c->pw_x, c->pw_amp, c->pw_f0, c->pw_sig, c->pw_t0, c->pw_c, tn - dt, tn,
+                       tn + dt, 0.5 * dt, wave ? 1 : 0, c->cge.b, c->pw_hsum);
+    hipLaunchKernelGGL(k_boundary_flux, dim3((c->pw_nn + 255) / 256), dim3(256), 0, c->stream, c->pw_nn, c->pw_nptr,
+                       c->pw_nlist, c->pw_node, c->pw_hsum, c->dbnd);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauss_rhs(qh_ctx *c, double *out3, double tol_n) {
     int32_t n = c->GtM.n;
     unsigned gr = grid_rows(n);
     hipLaunchKernelGGL(k_gauss_rhs, dim3(gr), dim3(kThreads), 0, c->stream, n, c->GtM.ptr, c->GtM.col,
-                       c->GtM.val, c->cge.x, c->Q_bg, c->Q, c->int_nodes, c->phys.u_q, c->cgn.b, c->rho,
-                       c->cgn.partial);
+                       c->GtM.val, c->cge.x, c->Q_bg, c->Q, c->int_nodes, c->phys.u_q,
+                       (const double *)c->dbnd, c->cgn.b, c->rho, c->cgn.partial);
     hipLaunchKernelGGL(k_gauss_finish, dim3(1), dim3(kThreads), 0, c->stream, c->cgn.partial, (int)gr, out3, tol_n);
     return hipGetLastError();
 }
