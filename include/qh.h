@@ -281,7 +281,8 @@ int qh_matrix_download(const qh_ctx *ctx, int32_t which, int32_t *ptr, int32_t *
  * 0 field prep, 1 particle step, 2 sort, 3 edge right-hand side, 4 edge-system CG product
  * (fused direction update + SpMV + dot), 5 edge-system CG vector update, 6 CG init,
  * 7 Gauss-law set-up and correction, 8 Faraday update, 9 residual check, 10 node-system CG
- * product, 11 node-system CG vector update, 12 learned preconditioner application.
+ * product, 11 node-system CG vector update, 12 learned preconditioner application, 13 plane-wave
+ * boundary source (edge term and boundary flux).
  * ms_total[k]: summed ms; launches[k]: count. */
 int qh_timing_enable(qh_ctx *ctx, int32_t on);
 int qh_timing_read(const qh_ctx *ctx, int32_t n, double *ms_total, int64_t *launches);

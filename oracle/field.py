@@ -74,11 +74,18 @@ class FieldOracle:
             top = sp.identity(n - 1, format="csr")
             last = sp.csr_matrix(-alpha[:-1] / alpha[-1])
             self.Cz = sp.vstack([top, last]).tocsr()
-            self.Kz = (self.Cz.T @ self.K @ self.Cz).tocsr()
             self.alpha = alpha
+            self._Kz = None
         self.Gf = cx.G.astype(np.float64).tocsr()
         self.GtMeps = (self.Gf.T @ op.Meps).tocsr()
         self.Gint = self.Gf[:, inn].tocsr()
+
+    @property
+    def Kz(self):
+        """C_z^T K C_z (formed at first use: its last row and column are dense)."""
+        if self._Kz is None:
+            self._Kz = (self.Cz.T @ self.K @ self.Cz).tocsr()
+        return self._Kz
 
     def rhs(self, e, b_real, g_real):
         r = self.Bm @ e + self.dt * (self.op.CtMmu @ b_real) - g_real
@@ -192,7 +199,9 @@ class PlaneWave:
     Dunavant's degree-4 rule on every boundary face; the trapezoidal update adds
     dt/2 (h^n + h^{n+1}) to its right-hand side, the wave update dt/2 (h^{n+1} - h^{n-1})."""
 
-    def __init__(self, cx: Complex, op: Operators, E0, f0, bw, t0):
+    def __init__(self, cx: Complex, op: Operators, E0, f0, bw, t0, faces=None):
+        """faces: the wall faces to integrate over (all by default); h is then complete on the
+        edges all of whose wall faces are listed."""
         from .whitney import w1_at
         from .complex_ import LOCAL_EDGES, LOCAL_FACES
         self.cx, self.E0, self.f0, self.t0 = cx, E0, f0, t0
@@ -203,8 +212,10 @@ class PlaneWave:
         # per boundary face and rule point: x of the point and, for the face's three edges, the
         # weight times W1_i . (n x y-hat)
         edges, coef, xq = [], [], []
-        for f in np.flatnonzero(cx.wall_face):
-            t, k = np.argwhere(cx.tet_faces == f)[0]
+        slot = np.flatnonzero(cx.wall_face[cx.tet_faces.ravel()])   # a wall face has one tet
+        if faces is not None:
+            slot = slot[np.isin(cx.tet_faces.ravel()[slot], faces)]
+        for t, k in zip(*np.divmod(slot, 4)):
             verts = LOCAL_FACES[k]
             P = cx.xyz[cx.tets[t, list(verts)]]
             area = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))

@@ -22,7 +22,7 @@ BC_PEC, BC_NEUMANN = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
-           "gauss", "faraday", "true_res", "node_spmv", "node_update", "precond"]
+           "gauss", "faraday", "true_res", "node_spmv", "node_update", "precond", "boundary"]
 MLP_NPARAM = 5313
 F_BITS = 20
 EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mesh_info",

@@ -748,8 +748,12 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             const bool wave = P->field_mode == QH_FIELDS_WAVE && c->wave_hist;
             int t0 = qh_tbeg(c);
             QH_HIP(c, wave ? launch_wave_rhs(c) : launch_edge_rhs(c));
-            if (c->pw_on) QH_HIP(c, launch_plane_wave(c, wave));
             qh_tend(c, t0, QK_EDGE_RHS);
+            if (c->pw_on) {
+                t0 = qh_tbeg(c);
+                QH_HIP(c, launch_plane_wave(c, wave));
+                qh_tend(c, t0, QK_BOUNDARY);
+            }
             int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr, false,
                                  learned);
             if (rc) return rc;

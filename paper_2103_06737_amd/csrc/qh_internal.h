@@ -232,7 +232,7 @@ struct qh_ctx {
 // kernel ids of the timing table
 enum {
     QK_FIELD_PREP = 0, QK_PARTICLE, QK_SORT, QK_EDGE_RHS, QK_CG_SPMV, QK_CG_UPDATE, QK_CG_INIT,
-    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NODE_SPMV, QK_NODE_UPDATE, QK_PREC, QK_NKERNELS
+    QK_GAUSS, QK_FARADAY, QK_TRUE_RES, QK_NODE_SPMV, QK_NODE_UPDATE, QK_PREC, QK_BOUNDARY, QK_NKERNELS
 };
 int qh_tbeg(qh_ctx *c);
 void qh_tend(qh_ctx *c, int slot, int kernel);

@@ -178,7 +178,6 @@ CONFIGS = {
     "plasma64": dict(n=64, jitter=0.0, z_ratio=1.0, n_e=16_000_000, n_i=0, v_th_e=1e6, v_th_i=0.0,
                weight=1e16 / 16_000_000, dt=1.2e-10, steps=100, sigma_e=0.0, bz=0.1,
                sigma_b=0.0, mode="solve", load="uniform", sort_every=20),
-    # 96^3 graded toward z=0 (ratio 1.05), 32M electrons + 32M ions, quiet start
     # 96^3 graded toward z = 0 (ratio 1.05), 32M electrons + 32M ions, full cycle at 10x the
     # explicit limit. dt_CFL: the oracle's eigen-analysis of a 16^3 mesh graded to the same
     # thinnest-cell aspect (22:1, ratio 1.35) gives n * dt_CFL = 5.32e-10 s, so ~5.5e-12 s at

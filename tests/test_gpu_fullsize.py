@@ -104,6 +104,81 @@ def test_plasma64_full_cycle(plasma64):
     assert np.array_equal(cx.D @ b1, cx.D @ b0)
 
 
+def test_plasma64_plane_wave_natural_boundary(plasma64):
+    """Natural walls and a plane-wave pulse (300 MHz, 150 MHz bandwidth, its peak passing x = 0 at
+    t = 0) on the 64^3 / 16M workload, unmagnetised (natural walls carry no surface current to
+    hold a static B), with the learned preconditioner, as the benchmark's plane-wave run
+    launches it. One step, piece by piece: the edge right-hand side is the
+    oracle's source-free one plus a boundary term that vanishes off the wall edges and equals the
+    oracle's on 256 sampled wall edges (integrated over their wall faces only); the solution's
+    residual; the Gauss law with the charge and the normal flux G^T of that term; the integer
+    Faraday update bit for bit."""
+    import copy
+    import paper_2103_06737_amd as qh
+    from oracle.field import FieldOracle, PlaneWave
+    cfg, mesh, parts, cx, op, po = plasma64
+    cxn = copy.copy(cx)
+    cxn.neumann = True
+    dt, weight = cfg["dt"], cfg["weight"]
+    u_q = qi.QE * weight * 2.0 ** -40
+    ctx = qh.Context(0)
+    ctx.set_boundary(qh.BC_NEUMANN)
+    ctx.mesh_upload(mesh.xyz, mesh.tets)
+    ctx.set_physics(qi.EPS0, qi.MU0, dt, u_q, U_B)
+    ctx.fields_init_synthetic(qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), cfg["sigma_e"], 0.0,
+                              cfg["sigma_b"])
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = parts["e"]
+    ctx.particles_upload(sid, x, v, tet)
+    ctx.charge_background(1)
+    f0, bw, t0 = 300e6, 150e6, 0.0
+    E0 = 1e3 / (2 * np.pi * f0)    # E_inc = E0 s', s' peaks near 2 pi f0: about 1 kV/m
+    ctx.set_plane_wave(E0, f0, bw, t0)
+    ctx.precond_train(steps=60, lr=3e-3, seed=1, validate_every=0)
+    e0, b0 = ctx.fields_download()
+    _, Q0 = ctx.deposits_download()
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1)
+    st = ctx.pic_step(params)[0]
+    assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+    assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8
+    g, Q1 = ctx.deposits_download()
+    e1, b1 = ctx.fields_download()
+    rhs, sol = ctx.edge_system_download()
+    ctx.close()
+
+    fo = FieldOracle(cxn, op, dt)
+    b_real, g_real = b0.astype(np.float64) * U_B, g.astype(np.float64) * u_q
+    h_dev = rhs - fo.rhs(e0, b_real, g_real)
+    terms = abs(fo.Bm) @ np.abs(e0) + dt * (abs(op.CtMmu) @ np.abs(b_real)) + np.abs(g_real)
+    tol = 64 * np.finfo(float).eps
+    off = ~cx.wall_edge
+    assert (np.abs(h_dev[off]) <= tol * terms[off]).all()
+    sample = np.random.default_rng(5).choice(np.flatnonzero(cx.wall_edge), 256, replace=False)
+    faces = np.intersect1d(cx.C[:, sample].nonzero()[0], np.flatnonzero(cx.wall_face))
+    pw = PlaneWave(cxn, op, E0, f0, bw, t0, faces=faces)
+    hs = 0.5 * dt * (pw.h(0.0) + pw.h(dt))
+    # rounding scale of the source: s' = env (-(u/sig^2) cos(om u) - om sin(om u)) cancels near its
+    # zeros, and the rounding of the arguments om u and u^2/(2 sig^2) moves cos, sin and env by
+    # about eps times the argument, so each point counts with the size of both terms times the
+    # arguments' condition
+    habs = np.zeros(cx.Ne)
+    om = 2 * np.pi * f0
+    for t in (0.0, dt):
+        u = t - pw.xq / pw.c - pw.t0
+        y = u * u / (2 * pw.sig ** 2)
+        part = np.exp(-y) * (np.abs(u) / pw.sig ** 2 + om) * (1.0 + np.abs(om * u) + y)
+        np.add.at(habs, pw.edges, 0.5 * dt * np.abs(pw.coef) * part * pw.E0 / pw.eta)
+    assert np.abs(hs[sample]).max() > 1e6 * tol * terms[sample].max()    # the source is not lost in rounding
+    ratio = np.abs(h_dev[sample] - hs[sample]) / (tol * (terms[sample] + habs[sample]))
+    assert ratio.max() <= 1.0, (ratio.max(), np.abs(h_dev[sample] - hs[sample]).max())
+    assert np.linalg.norm(fo.A @ sol - rhs) <= 1.001e-8 * np.linalg.norm(rhs)
+    rho = u_q * (Q0 - Q1).astype(np.float64) + fo.Gf.T @ h_dev    # Q_bg = Q0
+    assert fo.gauss_error(e1, rho) <= 1.01e-8
+    u = np.rint((0.5 * dt / U_B) * (e1 + e0)).astype(np.int64)
+    assert np.array_equal(b1, b0 - cx.C @ u)
+    assert np.array_equal(cx.D @ b1, cx.D @ b0)
+
+
 def test_beam32_200_steps():
     """1M-electron beam in frozen random fields, 200 steps: continuity and D b every step on the
     device, FP32 positions within 1e-5 of the box size of the FP64 oracle's after 200 steps.

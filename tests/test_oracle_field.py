@@ -309,3 +309,23 @@ def test_plane_wave_through_natural_boundary():
     assert g6.max() < 1e-11 and g8.max() < 1e-11
     rb, _ = _plane_wave_run(6, gauss_flux=False)
     assert rb[pk].max() > 0.3
+
+
+def test_plane_wave_face_subset():
+    """The boundary term restricted to some wall faces equals the full one on every edge whose
+    wall faces are all in the subset (the full-size GPU test samples edges this way)."""
+    from oracle.complex_ import Complex
+    from oracle.whitney import Operators
+    m = qi.BoxMesh(4, 1.0)
+    cx = Complex(m.xyz, m.tets, neumann=True)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    args = (1.0, 150e6, 75e6, 2e-9)
+    full = Fo.PlaneWave(cx, op, *args)
+    rng = np.random.default_rng(3)
+    sample = rng.choice(np.flatnonzero(cx.wall_edge), 20, replace=False)
+    faces = np.intersect1d(cx.C[:, sample].nonzero()[0], np.flatnonzero(cx.wall_face))
+    part = Fo.PlaneWave(cx, op, *args, faces=faces)
+    for t in (1.5e-9, 2e-9, 3e-9):
+        hf, hp = full.h(t), part.h(t)
+        assert (np.abs(hf[sample]) > 0).sum() >= 10   # zero on the y-walls (n x y-hat = 0)
+        assert np.allclose(hp[sample], hf[sample], rtol=1e-13, atol=0)
