@@ -43,7 +43,7 @@ def lib():
         p = C.c_void_p
         L.orc_push.restype = C.c_int64
         L.orc_push.argtypes = [p, p, p, C.c_int64, p, p, p, C.c_double, C.c_double, C.c_int64,
-                               C.c_int, C.c_int, p, p, p, p, C.c_int64, p, p, p, p, p, C.c_int]
+                               C.c_int, C.c_int, C.c_int, p, p, p, p, C.c_int64, p, p, p, p, p, C.c_int]
         L.orc_deposit_list.restype = None
         L.orc_deposit_list.argtypes = [p, C.c_int64, p, p, p, p, C.c_int64, p, p, p, C.c_int, p, p]
         L.orc_quantize_points.argtypes = [p, C.c_int64, p, p, C.c_int, p]
@@ -73,8 +73,10 @@ class ParticleOracle:
                        _ptr(a["tet_faces"]), _ptr(a["tet_nbr"]), _ptr(a["minv"]))
 
     def push(self, e, b_real, x, v, tet, qm, dt, z, g=None, Q=None, max_seg=64,
-             dump_segments=0, nthreads=0):
-        """Advance particles one step (in place on float64 copies that are returned)."""
+             dump_segments=0, nthreads=0, absorb=False):
+        """Advance particles one step (in place on float64 copies that are returned). absorb:
+        walls absorb (a particle stops at the wall point, lost_flags 2, and its charge is not
+        deposited) instead of reflecting."""
         x = np.ascontiguousarray(x, dtype=np.float64).copy()
         v = np.ascontiguousarray(v, dtype=np.float64).copy()
         tet = np.ascontiguousarray(tet, dtype=np.int64).copy()
@@ -92,13 +94,13 @@ class ParticleOracle:
         e = np.ascontiguousarray(e, dtype=np.float64)
         b_real = np.ascontiguousarray(b_real, dtype=np.float64)
         nl = lib().orc_push(C.byref(self.m), _ptr(e), _ptr(b_real), n, _ptr(x), _ptr(v), _ptr(tet),
-                            float(qm), float(dt), int(z), F_BITS, int(max_seg), _ptr(g), _ptr(Q),
+                            float(qm), float(dt), int(z), F_BITS, int(max_seg), int(bool(absorb)), _ptr(g), _ptr(Q),
                             _ptr(lost), _ptr(stats), int(dump_segments), _ptr(cnt),
                             _ptr(seg["tet"]) if seg else None, _ptr(seg["l0"]) if seg else None,
                             _ptr(seg["l1"]) if seg else None, _ptr(seg["pid"]) if seg else None,
                             int(nthreads))
         out = dict(x=x.reshape(-1, 3), v=v.reshape(-1, 3), tet=tet, g=g, Q=Q, lost=int(nl),
-                   lost_flags=lost, crossings=int(stats[0]), wall_hits=int(stats[1]))
+                   lost_flags=lost, absorbed=lost == 2, crossings=int(stats[0]), wall_hits=int(stats[1]))
         if seg:
             k = int(cnt[0])
             out["segments"] = {kk: vv[:k] for kk, vv in seg.items()}

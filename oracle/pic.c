@@ -16,7 +16,9 @@
  *   - push: non-relativistic Boris, v at half steps (the paper uses a 4th-order Adams
  *     method whose details are in another paper);
  *   - path: the straight line x^n -> x^n + dt v^{n+1/2}, broken at faces and walls;
- *   - walls: specular reflection of the remaining displacement and of v;
+ *   - walls: specular reflection of the remaining displacement and of v, or (absorbing
+ *     walls) the particle stops at the wall point and leaves the domain: its path up to
+ *     the wall is deposited, its charge is not (it leaves through the wall);
  *   - exit face: smallest exit parameter, ties to the lowest local index; the face
  *     just entered is never an exit candidate in the tet it leads into;
  *   - fixed point: Lambda_i = round-half-even(lambda_i * 2^F), clamped to [0, 2^F];
@@ -144,7 +146,7 @@ static void deposit_segment(const orc_mesh *m, acc_t *A, int64_t t, const int64_
 
 static void one_particle(const orc_mesh *m, const double *e, const double *b, double *x,
                          double *v, int64_t *tet, double qm, double dt, int64_t z, int F,
-                         int max_seg, acc_t *A, int64_t pid, int32_t *lost_flag) {
+                         int max_seg, int absorb, acc_t *A, int64_t pid, int32_t *lost_flag) {
     int64_t t = *tet;
     double E[3], B[3], lam[4], lq[4], p[3], q[3], rem[3];
     gather_E(m, e, t, x, E);
@@ -194,6 +196,12 @@ static void one_particle(const orc_mesh *m, const double *e, const double *b, do
             entry = new_local;
             t = nb;
             A->crossings++;
+        } else if (absorb) {
+            for (int d = 0; d < 3; ++d) x[d] = p[d];
+            *tet = t;
+            *lost_flag = 2;
+            A->wall_hits++;
+            return;
         } else {
             /* specular reflection about the wall plane (normal along grad lambda_k) */
             const double *n = grad_of(m, t, k);
@@ -218,10 +226,11 @@ static void one_particle(const orc_mesh *m, const double *e, const double *b, do
 
 /* One push + walk + deposit for np particles.
  * x, v: 3*np (in/out), tet: np (in/out). g (Ne) and Q (Nn) are ADDED to.
+ * lost_flags: 1 = hit the piece cap, 2 = absorbed at a wall (absorb != 0).
  * seg_cap > 0 runs serially and records the straight pieces in particle order.
  * Returns the number of particles that hit the piece cap. */
 int64_t orc_push(const orc_mesh *m, const double *e, const double *b, int64_t np, double *x,
-                 double *v, int64_t *tet, double qm, double dt, int64_t z, int F, int max_seg,
+                 double *v, int64_t *tet, double qm, double dt, int64_t z, int F, int max_seg, int absorb,
                  int64_t *g, int64_t *Q, int32_t *lost_flags, int64_t *stats /* crossings, wall hits */,
                  int64_t seg_cap, int64_t *seg_count, int64_t *seg_tet, int64_t *seg_l0,
                  int64_t *seg_l1, int64_t *seg_pid, int nthreads) {
@@ -242,7 +251,7 @@ int64_t orc_push(const orc_mesh *m, const double *e, const double *b, int64_t np
 #pragma omp for schedule(static)
 #endif
         for (int64_t i = 0; i < np; ++i)
-            one_particle(m, e, b, x + 3 * i, v + 3 * i, tet + i, qm, dt, z, F, max_seg, &A, i,
+            one_particle(m, e, b, x + 3 * i, v + 3 * i, tet + i, qm, dt, z, F, max_seg, absorb, &A, i,
                          lost_flags + i);
 #ifdef _OPENMP
 #pragma omp critical

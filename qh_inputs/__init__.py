@@ -119,6 +119,106 @@ class BoxMesh:
         return pos, t.astype(np.int32)
 
 
+class CylinderMesh:
+    """Circular cylinder of radius R along z from 0 to L (the cavity of the beam test of
+    Sec. VI.B), cut into tets.
+
+    The disk is a centre node and nr concentric rings, ring k at radius R k / nr with 6k
+    nodes at angles 2 pi j / (6k); two neighbouring rings are joined by walking both in
+    angle order (6 nr^2 triangles). Layer l of the extrusion sits at z = L l / nz and node
+    (disk node n, layer l) has id l * N2 + n. Each triangular prism (a < b < c on the disk)
+    splits into (a_l, b_l, c_l, c_l+1), (a_l, b_l, b_l+1, c_l+1), (a_l, a_l+1, b_l+1, c_l+1):
+    every quadrilateral side is cut along the diagonal from its lowest id, so neighbouring
+    prisms agree. Tet vertices are listed in ascending id. bottom_tet[i] is the tet that
+    holds disk triangle i of the z = 0 face.
+    """
+
+    def __init__(self, R: float, L: float, nr: int, nz: int):
+        self.R, self.L, self.nr, self.nz = float(R), float(L), int(nr), int(nz)
+        rings = [np.array([0])]
+        xy = [(0.0, 0.0)]
+        for k in range(1, nr + 1):
+            m = 6 * k
+            ang = 2.0 * np.pi * np.arange(m) / m
+            rings.append(len(xy) + np.arange(m))
+            r = R * k / nr
+            xy += list(zip(r * np.cos(ang), r * np.sin(ang)))
+        xy = np.array(xy)
+        tri = [(0, 1 + j, 1 + (j + 1) % 6) for j in range(6)]
+        for k in range(2, nr + 1):
+            inner, outer = rings[k - 1], rings[k]
+            n1, n2 = inner.size, outer.size
+            i = j = 0
+            while i < n1 or j < n2:
+                # advance the ring whose next node comes first in angle
+                a_next = (i + 1) / n1
+                b_next = (j + 1) / n2
+                if j < n2 and (i >= n1 or b_next <= a_next + 1e-12):
+                    tri.append((inner[i % n1], outer[j % n2], outer[(j + 1) % n2]))
+                    j += 1
+                else:
+                    tri.append((inner[i % n1], outer[j % n2], inner[(i + 1) % n1]))
+                    i += 1
+        tri = np.sort(np.array(tri, dtype=np.int64), axis=1)
+        N2 = xy.shape[0]
+        z = L * np.arange(nz + 1, dtype=np.float64) / nz
+        self.xyz = np.concatenate([np.column_stack([xy, np.full(N2, zl)]) for zl in z])
+        a, b, c = tri[:, 0], tri[:, 1], tri[:, 2]
+        tets = []
+        for l in range(nz):
+            lo, hi = l * N2, (l + 1) * N2
+            tets.append(np.stack([
+                np.column_stack([a + lo, b + lo, c + lo, c + hi]),
+                np.column_stack([a + lo, b + lo, b + hi, c + hi]),
+                np.column_stack([a + lo, a + hi, b + hi, c + hi])], axis=1).reshape(-1, 4))
+        self.tets = np.concatenate(tets).astype(np.int32)
+        self.tri = tri
+        self.n2 = N2
+        self.bottom_tet = 3 * np.arange(tri.shape[0])   # (a_0, b_0, c_0, c_1) of layer 0
+
+    def locate_bottom(self, p: np.ndarray) -> np.ndarray:
+        """Disk triangle holding each point p (k x 2) of the z = 0 face (-1 if none)."""
+        P = self.xyz[self.tri][:, :, :2]                      # (T, 3, 2)
+        d = P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]
+        det = d[0][:, 0] * d[1][:, 1] - d[0][:, 1] * d[1][:, 0]
+        out = np.full(p.shape[0], -1, np.int64)
+        for i, q in enumerate(p):
+            r = q - P[:, 0]
+            u = (r[:, 0] * d[1][:, 1] - r[:, 1] * d[1][:, 0]) / det
+            w = (d[0][:, 0] * r[:, 1] - d[0][:, 1] * r[:, 0]) / det
+            inside = np.flatnonzero((u >= -1e-12) & (w >= -1e-12) & (u + w <= 1.0 + 1e-12))
+            if inside.size:
+                out[i] = inside[0]
+        return out
+
+
+def beam_injection_counts(steps: int, dt: float, per_step: float, t_on: float) -> np.ndarray:
+    """Macro-particles injected in each of the first `steps` steps for a current that rises
+    linearly from 0 to its full value over t_on and then stays (per_step particles per step
+    at full current): differences of the rounded cumulative count."""
+    t = dt * np.arange(steps + 1)
+    rate = per_step / dt
+    cum = np.where(t < t_on, 0.5 * rate * t * t / t_on, rate * (t - 0.5 * t_on))
+    c = np.rint(cum).astype(np.int64)
+    return np.diff(c)
+
+
+def beam_injection(mesh: CylinderMesh, count: int, r_beam: float, v_p: float, seed: int = 0,
+                   step: int = 0):
+    """count electrons on the z = 0 face, uniform in the disk of radius r_beam, moving along
+    +z at v_p (positions FP32, exactly on the face). Returns (x, v, tet)."""
+    gen = rng(seed, 1000 + step)
+    r = r_beam * np.sqrt(gen.random(count))
+    phi = 2.0 * np.pi * gen.random(count)
+    p = np.column_stack([r * np.cos(phi), r * np.sin(phi)]).astype(np.float32)
+    tri = mesh.locate_bottom(p.astype(np.float64))
+    assert (tri >= 0).all()
+    x = np.column_stack([p, np.zeros(count, np.float32)]).astype(np.float32)
+    v = np.zeros((count, 3), np.float32)
+    v[:, 2] = v_p
+    return x, v, mesh.bottom_tet[tri].astype(np.int32)
+
+
 def maxwellian(count: int, v_th: float, gen: np.random.Generator, drift=(0.0, 0.0, 0.0)):
     v = gen.normal(0.0, v_th, size=(count, 3))
     v += np.asarray(drift, dtype=np.float64)
@@ -186,6 +286,15 @@ CONFIGS = {
                v_th_i=2e4, weight=1e16 / 32_000_000, dt_cfl_mult=10.0, dt=5.5e-11, steps=200,
                sigma_e=0.0, bz=0.1, sigma_b=0.0, mode="solve", load="uniform", sort_every=20),
 }
+
+
+# Beam injected into a cylindrical PEC cavity (Sec. VI.B table): cavity radius 20 mm, length
+# 100 mm; electrons at v_p = 5e7 m/s through the z = 0 face inside r_b = 8 mm; 10 macro-particles
+# of 52012.58 electrons per step at the full 0.25 A, so dt = 10 * 52012.58 e / 0.25 A; the
+# current turns on linearly over 2 ns; walls absorb. Mesh: 10 rings (2 mm), 50 layers (2 mm).
+BEAM_CYL = dict(R=0.02, L=0.1, nr=10, nz=50, v_p=5e7, r_b=0.008, per_step=10, weight=52012.58,
+                current=0.25, t_on=2e-9)
+BEAM_CYL["dt"] = BEAM_CYL["per_step"] * BEAM_CYL["weight"] * QE / BEAM_CYL["current"]
 
 
 def make_mesh(cfg: dict, seed: int = 0) -> BoxMesh:
