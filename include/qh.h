@@ -126,6 +126,8 @@ int qh_create(qh_ctx **out, int device, void *stream);
 void qh_destroy(qh_ctx *ctx);
 const char *qh_last_error(const qh_ctx *ctx);
 
+#define QH_WALLS_REFLECT 0 /* particles reflect specularly at the walls (axis-aligned walls only) */
+#define QH_WALLS_ABSORB 1  /* a particle reaching a wall stops there and leaves the domain */
 #define QH_BC_PEC 0     /* walls are perfect conductors: wall edges carry no E, wall nodes are grounded */
 #define QH_BC_NEUMANN 1 /* natural boundary: every edge and node is an unknown; the Gauss-law solve
                            is singular (constants) and its potential is fixed only up to the
@@ -185,8 +187,38 @@ int qh_species_add(qh_ctx *ctx, double q_over_m, int32_t charge_number, int32_t 
  * species' particles and recomputes the node charge Q of all species. */
 int qh_particles_upload(qh_ctx *ctx, int32_t species, int64_t n, const float *x,
                         const float *v, const int32_t *tet);
-/* In upload order. Any pointer may be NULL. */
+/* Ordered by particle id (ascending; ids are the upload order, then the injection order).
+ * Any pointer may be NULL. Sizes follow qh_particles_count. */
 int qh_particles_download(const qh_ctx *ctx, int32_t species, float *x, float *v, int32_t *tet);
+/* Number of particles the species holds now (after injections and absorptions). */
+int qh_particles_count(const qh_ctx *ctx, int32_t species, int64_t *n);
+/* The ids of the species' particles, ascending (the order of qh_particles_download). */
+int qh_particles_ids(const qh_ctx *ctx, int32_t species, int32_t *ids);
+
+/* What particles do at the walls: QH_WALLS_REFLECT (default; specular reflection at
+ * axis-aligned walls) or QH_WALLS_ABSORB (the beam test of Sec. VI.B: a particle reaching a
+ * wall stops at the wall point; its current up to there is deposited, its charge is not, since
+ * it leaves through the conductor, and it is removed at the end of the step). With absorbing
+ * walls continuity holds at every node off the walls, which is what the step's verification
+ * then checks, and every step ends with a sort of each species (a device-to-host copy of the
+ * particle count, so the step synchronises its stream). */
+int qh_set_walls(qh_ctx *ctx, int32_t mode);
+
+/* Appends n particles to a species (x, v: 3n floats; tet: the tet holding each point), with
+ * ids continuing from the last one given. Their W0 charge is added to the present node charge,
+ * so the next step's continuity G^T g = Q^{n+1} - Q^n holds bit for bit. Injected at a wall
+ * (the beam test of Sec. VI.B injects through the z = 0 face) the charge lies on wall nodes,
+ * which a PEC field solve does not see: the charge enters through the wall. The species'
+ * storage grows as needed (device memory is reallocated; injected particles are sorted into
+ * place at the next sort). QH_EINVAL for a tet id out of range. */
+int qh_particles_inject(qh_ctx *ctx, int32_t species, int64_t n, const float *x, const float *v,
+                        const int32_t *tet);
+
+/* E (V/m) and B (T) at n points (xyz: 3n doubles, tet: the tet holding each point) from the
+ * present e and b, evaluated as the push gathers them (E = sum e_i W1_i linear in the tet,
+ * B = sum b_i W2_i constant in it; Sec. II.C), in FP32. Host arrays; E, B: 3n doubles (either
+ * may be NULL). A diagnostic: it allocates device memory per call. */
+int qh_probe_fields(qh_ctx *ctx, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B);
 /* Static background charge for Gauss's law: mode 0 none, mode 1 the negative of the
  * present particle charge (neutral start); rho = u_q (Q_bg - Q) on interior nodes. */
 int qh_charge_background(qh_ctx *ctx, int32_t mode);

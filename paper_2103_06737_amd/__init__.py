@@ -19,6 +19,7 @@ QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ES
     0, -1, -2, -3, -4, -5, -6, -7)
 FIELDS_FROZEN, FIELDS_SOLVE, FIELDS_WAVE = 0, 1, 2
 BC_PEC, BC_NEUMANN = 0, 1
+WALLS_REFLECT, WALLS_ABSORB = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
@@ -32,7 +33,8 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_capture_segments", "qh_segments_download", "qh_deposit", "qh_field_solve",
            "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
-           "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave"]
+           "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
+           "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields"]
 
 
 class QhError(RuntimeError):
@@ -116,6 +118,11 @@ def lib():
             "qh_species_add": [p, d, i32, C.POINTER(i32)],
             "qh_particles_upload": [p, i32, i64, p, p, p],
             "qh_particles_download": [p, i32, p, p, p],
+            "qh_particles_count": [p, i32, C.POINTER(i64)],
+            "qh_particles_ids": [p, i32, p],
+            "qh_set_walls": [p, i32],
+            "qh_particles_inject": [p, i32, i64, p, p, p],
+            "qh_probe_fields": [p, i64, p, p, p, p],
             "qh_charge_background": [p, i32],
             "qh_pic_step": [p, C.POINTER(StepParams), i32, p],
             "qh_deposits_download": [p, p, p],
@@ -259,16 +266,45 @@ class Context:
         v = _c(v, np.float32)
         tet = _c(tet, np.int32)
         self._check(self.L.qh_particles_upload(self.h, sid, tet.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
-        self._np = getattr(self, "_np", {})
-        self._np[sid] = tet.shape[0]
+
+    def particles_inject(self, sid, x, v, tet):
+        """Append particles (ids continue); their charge is added to the present node charge."""
+        x = _c(x, np.float32)
+        v = _c(v, np.float32)
+        tet = _c(tet, np.int32)
+        self._check(self.L.qh_particles_inject(self.h, sid, tet.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+
+    def particles_count(self, sid):
+        n = C.c_int64()
+        self._check(self.L.qh_particles_count(self.h, sid, C.byref(n)))
+        return n.value
+
+    def particles_ids(self, sid):
+        ids = np.zeros(self.particles_count(sid), np.int32)
+        self._check(self.L.qh_particles_ids(self.h, sid, _ptr(ids)))
+        return ids
 
     def particles_download(self, sid):
-        n = self._np[sid]
+        """(x, v, tet) ordered by particle id (see particles_ids)."""
+        n = self.particles_count(sid)
         x = np.zeros((n, 3), np.float32)
         v = np.zeros((n, 3), np.float32)
         t = np.zeros(n, np.int32)
         self._check(self.L.qh_particles_download(self.h, sid, _ptr(x), _ptr(v), _ptr(t)))
         return x, v, t
+
+    def set_walls(self, mode):
+        """WALLS_REFLECT (default) or WALLS_ABSORB."""
+        self._check(self.L.qh_set_walls(self.h, int(mode)))
+
+    def probe_fields(self, xyz, tet):
+        """E (V/m) and B (T) at points (FP32 evaluation from the present e and b)."""
+        xyz = _c(xyz, np.float64)
+        tet = _c(tet, np.int32)
+        E = np.zeros((tet.shape[0], 3))
+        B = np.zeros((tet.shape[0], 3))
+        self._check(self.L.qh_probe_fields(self.h, tet.shape[0], _ptr(xyz), _ptr(tet), _ptr(E), _ptr(B)))
+        return E, B
 
     def charge_background(self, mode):
         self._check(self.L.qh_charge_background(self.h, int(mode)))

@@ -364,6 +364,7 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = upload(c, &c->tnodes, (const int4 *)m.tn.data(), m.Nt))) return rc;
     if ((rc = upload(c, &c->tedges, te8.data(), te8.size()))) return rc;
     if ((rc = upload(c, &c->tnbr, (const int4 *)m.nbr.data(), m.Nt))) return rc;
+    if ((rc = upload(c, &c->wall_node_d, m.wall_node.data(), m.wall_node.size()))) return rc;
     if ((rc = upload(c, &c->tfaces, m.tf.data(), m.tf.size()))) return rc;
     if ((rc = upload(c, &c->tsign, m.tsign.data(), m.tsign.size()))) return rc;
     if ((rc = upload(c, &c->face_edges, m.face_edges.data(), m.face_edges.size()))) return rc;
@@ -386,7 +387,7 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = qh_alloc(c, &c->e, m.Ne)) || (rc = qh_alloc(c, &c->b, m.Nf)) || (rc = qh_alloc(c, &c->g, m.Ne)) ||
         (rc = qh_alloc(c, &c->Q, m.Nn)) || (rc = qh_alloc(c, &c->Q_old, m.Nn)) || (rc = qh_alloc(c, &c->Q_bg, m.Nn)) ||
         (rc = qh_alloc(c, &c->divb0, m.Nt)) || (rc = qh_alloc(c, &c->u_int, m.Ne)) ||
-        (rc = qh_alloc(c, &c->hist, m.Nt)) || (rc = qh_alloc(c, &c->cursor, m.Nt)) ||
+        (rc = qh_alloc(c, &c->hist, m.Nt + 1)) || (rc = qh_alloc(c, &c->cursor, m.Nt + 1)) ||
         (rc = qh_alloc(c, &c->scan_tmp, (m.Nt + 1023) / 1024 + 1)))
         return rc;
     QH_HIP(c, hipMemsetAsync(c->e, 0, sizeof(double) * m.Ne, c->stream));
@@ -514,17 +515,25 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     Species &s = c->species[sid];
     int rc;
     if (n > s.cap) {
+        QH_HIP(c, hipStreamSynchronize(c->stream));
         float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
-        for (auto p : fs)
+        for (auto p : fs) {
+            qh_release(c, *p);
             if ((rc = qh_alloc(c, p, n))) return rc;
+        }
         int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
-        for (auto p : is)
+        for (auto p : is) {
+            qh_release(c, *p);
             if ((rc = qh_alloc(c, p, n))) return rc;
+        }
+        qh_release(c, s.own);
+        qh_release(c, s.ovf);
         if ((rc = qh_alloc(c, &s.own, qh_species_blocks(n) + 1))) return rc;
         if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(n) * QH_CHUNK))) return rc;
         s.cap = n;
     }
     s.n = n;
+    s.next_id = n;
     if (n > 0) {
         std::vector<float> comp(n);
         float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
@@ -560,14 +569,141 @@ int qh_particles_download(const qh_ctx *cc, int32_t sid, float *x, float *v, int
     QH_HIP(c, hipMemcpyAsync(ids.data(), s.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipMemcpyAsync(tt.data(), s.tet, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
+    // rank of each particle by id (ids are unique; after injections and absorptions they are
+    // not a permutation of 0..n-1)
+    std::vector<int64_t> order(n), rank(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int64_t p, int64_t q) { return ids[p] < ids[q]; });
+    for (int64_t r = 0; r < n; ++r) rank[order[r]] = r;
     for (int64_t i = 0; i < n; ++i) {
-        int64_t j = ids[i];
+        int64_t j = rank[i];
         if (x)
             for (int d = 0; d < 3; ++d) x[3 * j + d] = comp[d * n + i];
         if (v)
             for (int d = 0; d < 3; ++d) v[3 * j + d] = comp[(3 + d) * n + i];
         if (tet) tet[j] = tt[i];
     }
+    return QH_OK;
+}
+
+int qh_particles_count(const qh_ctx *c, int32_t sid, int64_t *n) {
+    if (!c || !n || sid < 0 || sid >= (int32_t)c->species.size()) return QH_EINVAL;
+    *n = c->species[sid].n;
+    return QH_OK;
+}
+
+int qh_particles_ids(const qh_ctx *cc, int32_t sid, int32_t *ids) {
+    qh_ctx *c = const_cast<qh_ctx *>(cc);
+    if (!c || !ids || sid < 0 || sid >= (int32_t)c->species.size()) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    const Species &s = c->species[sid];
+    if (s.n == 0) return QH_OK;
+    QH_HIP(c, hipMemcpyAsync(ids, s.id, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    std::sort(ids, ids + s.n);
+    return QH_OK;
+}
+
+int qh_set_walls(qh_ctx *c, int32_t mode) {
+    if (!c) return QH_EINVAL;
+    if (mode != QH_WALLS_REFLECT && mode != QH_WALLS_ABSORB) return qh_fail(c, QH_EINVAL, "walls: QH_WALLS_REFLECT or QH_WALLS_ABSORB");
+    c->walls = mode;
+    return QH_OK;
+}
+
+int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet) {
+    if (!c || sid < 0 || sid >= (int32_t)c->species.size() || n < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (n == 0) return QH_OK;
+    if (!x || !v || !tet) return QH_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    Species &s = c->species[sid];
+    const int64_t n0 = s.n, n1 = n0 + n;
+    if (n1 >= ((int64_t)1 << 31) || s.next_id + n >= ((int64_t)1 << 31))
+        return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles (and ids) per species");
+    int rc;
+    if (n1 > s.cap) {
+        // grow: new arrays, the present particles copied over, the old arrays released
+        const int64_t cap = std::max<int64_t>(std::max<int64_t>(2 * s.cap, n1), 4096);
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        float **fs[6] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz};
+        float **fscr[6] = {&s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
+        int32_t **is[2] = {&s.tet, &s.id};
+        int32_t **iscr[2] = {&s.stet, &s.sid};
+        for (int k = 0; k < 6; ++k) {
+            float *p;
+            if ((rc = qh_alloc(c, &p, cap))) return rc;
+            if (n0) QH_HIP(c, hipMemcpyAsync(p, *fs[k], sizeof(float) * n0, hipMemcpyDeviceToDevice, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+            qh_release(c, *fs[k]);
+            *fs[k] = p;
+            qh_release(c, *fscr[k]);
+            if ((rc = qh_alloc(c, fscr[k], cap))) return rc;
+        }
+        for (int k = 0; k < 2; ++k) {
+            int32_t *p;
+            if ((rc = qh_alloc(c, &p, cap))) return rc;
+            if (n0) QH_HIP(c, hipMemcpyAsync(p, *is[k], sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+            qh_release(c, *is[k]);
+            *is[k] = p;
+            qh_release(c, *iscr[k]);
+            if ((rc = qh_alloc(c, iscr[k], cap))) return rc;
+        }
+        int32_t *own;
+        const int64_t nb0 = qh_species_blocks(n0);
+        if ((rc = qh_alloc(c, &own, qh_species_blocks(cap) + 1))) return rc;
+        if (s.own) QH_HIP(c, hipMemcpyAsync(own, s.own, sizeof(int32_t) * (nb0 + 1), hipMemcpyDeviceToDevice, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        qh_release(c, s.own);
+        s.own = own;
+        qh_release(c, s.ovf);
+        if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(cap) * QH_CHUNK))) return rc;
+        s.cap = cap;
+    }
+    std::vector<float> comp(n);
+    float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+    for (int k = 0; k < 6; ++k) {
+        const float *src = k < 3 ? x : v;
+        for (int64_t i = 0; i < n; ++i) comp[i] = src[3 * i + k % 3];
+        QH_HIP(c, hipMemcpyAsync(dst[k] + n0, comp.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    std::vector<int32_t> ids(n);
+    std::iota(ids.begin(), ids.end(), (int32_t)s.next_id);
+    QH_HIP(c, hipMemcpyAsync(s.tet + n0, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemcpyAsync(s.id + n0, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    s.next_id += n;
+    s.n = n1;
+    QH_HIP(c, launch_own_extend(c, s, (int32_t)qh_species_blocks(n0), (int32_t)qh_species_blocks(n1)));
+    QH_HIP(c, launch_charge_deposit(c, s, n0));
+    return sync(c);
+}
+
+int qh_probe_fields(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B) {
+    if (!c || n < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh || !c->have_phys || !c->have_fields) return qh_fail(c, QH_ESTATE, "mesh, physics and fields first");
+    if (n == 0) return QH_OK;
+    if (!xyz || !tet) return QH_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at point " + std::to_string(i));
+    double *dx = nullptr, *dE = nullptr, *dB = nullptr;
+    int32_t *dt = nullptr;
+    int rc;
+    if ((rc = qh_alloc(c, &dx, 3 * n)) || (rc = qh_alloc(c, &dt, n)) || (rc = qh_alloc(c, &dE, 3 * n)) ||
+        (rc = qh_alloc(c, &dB, 3 * n)))
+        return rc;
+    QH_HIP(c, hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, hipMemcpyAsync(dt, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    launch_field_prep(c);  // the records of the present e and b
+    QH_HIP(c, launch_probe(c, n, dx, dt, dE, dB));
+    if (E) QH_HIP(c, hipMemcpyAsync(E, dE, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    if (B) QH_HIP(c, hipMemcpyAsync(B, dB, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    qh_release(c, dx), qh_release(c, dt), qh_release(c, dE), qh_release(c, dB);
     return QH_OK;
 }
 
@@ -731,7 +867,8 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             QH_HIP(c, launch_particle_step(c, c->species[k], (int)k, capture));
             qh_tend(c, t0, QK_PARTICLE);
         }
-        if (P->sort_every > 0 && (c->step_index + 1) % P->sort_every == 0)
+        // absorbing walls: every step ends with a sort, which drops the absorbed particles
+        if (c->walls == QH_WALLS_ABSORB || (P->sort_every > 0 && (c->step_index + 1) % P->sort_every == 0))
             for (auto &s : c->species) {
                 int t0 = qh_tbeg(c);
                 int rc = qh_sort_species(c, s);

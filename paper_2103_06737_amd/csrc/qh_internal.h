@@ -91,6 +91,7 @@ struct Species {
     double qm = 0.0;
     int32_t z = 0;
     int64_t n = 0, cap = 0;
+    int64_t next_id = 0;       // id of the next particle uploaded or injected
     float *x = nullptr, *y = nullptr, *zz = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
     int32_t *tet = nullptr, *id = nullptr;
     // sort scratch (same layout)
@@ -140,6 +141,8 @@ struct LearnedPrec {
 struct qh_ctx {
     int device = 0;
     int32_t bc = QH_BC_PEC;  // field boundary condition (qh_set_boundary, before the mesh)
+    int32_t walls = QH_WALLS_REFLECT;  // what particles do at the walls (qh_set_walls)
+    uint8_t *wall_node_d = nullptr;    // geometric wall nodes (Nn)
     bool host_only = false;  // device < 0: host mesh and assembly only (no GPU calls)
     hipStream_t stream = nullptr;
     std::string err;
@@ -275,7 +278,9 @@ void qh_release(qh_ctx *c, T *&p) {
 // qh_particles.hip
 void launch_field_prep(qh_ctx *c);
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture);
-hipError_t launch_charge_deposit(qh_ctx *c, Species &s);
+hipError_t launch_charge_deposit(qh_ctx *c, Species &s, int64_t first = 0);
+hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1);
+hipError_t launch_probe(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B);
 int qh_sort_species(qh_ctx *c, Species &s);
 int64_t qh_species_blocks(int64_t n);
 hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet,

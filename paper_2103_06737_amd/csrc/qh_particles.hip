@@ -80,6 +80,7 @@ struct StepArgs {
     float hqm;              // q/m * dt / 2
     float dt;
     int32_t zq;             // charge number
+    int32_t absorb;         // walls absorb (1) or reflect (0)
     int64_t *g, *Q;         // deposits that find no mailbox slot (atomics)
     int64_t *acc_tet;       // per-tet sums, plane-major: acc_tet[k * nt + t], k = 6 edges, 4 nodes
     uint16_t *ovf;          // per block: chunk indices of queued particles past the LDS queue
@@ -250,13 +251,14 @@ __device__ __forceinline__ void record_piece(const StepArgs &a, int32_t pid, int
 // ------------------------------------------------------------------------------------------
 // Walk of one particle from (px, py, pz) in tet t along dt v^{n+1/2}, face by face (exit
 // face = smallest crossing parameter, the entry face excluded; at most QH_MAX_PIECES
-// pieces), reflecting specularly at axis-aligned walls. deposit(tet, L_start, L_end, end)
-// takes each straight piece; on return the state holds the end point, its tet and the
-// (possibly reflected) velocity.
+// pieces), reflecting specularly at axis-aligned walls, or, with absorbing walls, stopping at
+// the wall point (gone: the charge leaves through the wall, so no end point is deposited).
+// deposit(tet, L_start, L_end, end) takes each straight piece; on return the state holds the
+// end point, its tet and the (possibly reflected) velocity.
 template <bool CAPTURE, typename Dep>
 __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py, float &pz, float &vx, float &vy,
                                          float &vz, int &t, int32_t pid, Dep &&deposit, unsigned int &n_cross,
-                                         unsigned int &n_wall, unsigned int &n_lost) {
+                                         unsigned int &n_wall, unsigned int &n_lost, bool &gone) {
     int seq = 0;
     float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
     int4 nb4 = a.tnbr[t], on = a.tnodes[t];  // loaded with the geometry: one round trip per tet
@@ -316,6 +318,10 @@ __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py
             nb4 = nbn;
             on = nn;
             ++n_cross;
+        } else if (a.absorb) {
+            gone = true;
+            ++n_wall;
+            return;
         } else {
             // specular reflection at an axis-aligned wall: the wall normal is grad l_k
             float nx, ny, nz;
@@ -520,10 +526,11 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             t = a.tet[i];
         }
         const int32_t pid = CAPTURE ? a.pid[i] : 0;
-        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit_walk, n_cross, n_wall, n_lost);
+        bool gone = false;
+        walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit_walk, n_cross, n_wall, n_lost, gone);
         a.x[i] = px; a.y[i] = py; a.z[i] = pz;
         a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
-        a.tet[i] = t;
+        a.tet[i] = gone ? -1 : t;  // dropped by the sort that follows the step
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -656,6 +663,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     a.hqm = (float)(0.5 * s.qm * c->phys.dt);
     a.dt = (float)c->phys.dt;
     a.zq = s.z;
+    a.absorb = c->walls == QH_WALLS_ABSORB ? 1 : 0;
     a.g = c->g; a.Q = c->Q; a.acc_tet = c->acc_tet; a.counters = c->counters;
     a.species = sidx; a.cap = c->cap_segments; a.seg_count = c->seg_count; a.seg_buf = c->seg_buf;
     dim3 grid((unsigned)((s.n + kChunk - 1) / kChunk));
@@ -696,10 +704,52 @@ __global__ void __launch_bounds__(256) k_charge(const float4 *__restrict__ geo, 
     for (int q = 0; q < 4; ++q) atomic_add_i64(Q + nv[q], (long long)zq * QH_SCALE * L[q]);
 }
 
-hipError_t launch_charge_deposit(qh_ctx *c, Species &s) {
-    if (s.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_charge, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, c->stream, c->geo,
-                       c->tnodes, s.x, s.y, s.zz, s.tet, s.n, s.z, c->Q);
+// W0 charge of particles [first, n) of a species, added to Q.
+hipError_t launch_charge_deposit(qh_ctx *c, Species &s, int64_t first) {
+    const int64_t n = s.n - first;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_charge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->geo,
+                       c->tnodes, s.x + first, s.y + first, s.zz + first, s.tet + first, n, s.z, c->Q);
+    return hipGetLastError();
+}
+
+// Ownership after particles are appended without a sort: own[0] = 0, the blocks past the old
+// last one own no tets (own[b] = nt for b in (b0, b1]); the old last block keeps [own, nt).
+__global__ void k_own_extend(int32_t *__restrict__ own, int32_t b0, int32_t b1, int32_t nt) {
+    const int32_t b = b0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b > b1) return;
+    own[b] = b == 0 ? 0 : (b == b0 ? own[b] : nt);
+}
+
+hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1) {
+    hipLaunchKernelGGL(k_own_extend, dim3((unsigned)((b1 - b0 + 1 + 255) / 256)), dim3(256), 0, c->stream, s.own, b0,
+                       b1, (int32_t)c->hm.Nt);
+    return hipGetLastError();
+}
+
+// E and B at points from the per-tet records the push reads (FP32): E = alpha + beta x (r - c),
+// B constant in the tet.
+__global__ void k_probe(const float4 *__restrict__ geo, const float4 *__restrict__ frec, int64_t n,
+                        const double *__restrict__ xyz, const int32_t *__restrict__ tet, double *__restrict__ E,
+                        double *__restrict__ B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = tet[i];
+    const float4 A = geo[3 * t], Bg = geo[3 * t + 1], C = geo[3 * t + 2];
+    const float4 F0 = frec[3 * t], F1 = frec[3 * t + 1], F2 = frec[3 * t + 2];
+    const float dx = (float)xyz[3 * i] - A.w, dy = (float)xyz[3 * i + 1] - Bg.w, dz = (float)xyz[3 * i + 2] - C.w;
+    E[3 * i] = F0.x + (F1.x * dz - F1.y * dy);
+    E[3 * i + 1] = F0.y + (F1.y * dx - F0.w * dz);
+    E[3 * i + 2] = F0.z + (F0.w * dy - F1.x * dx);
+    B[3 * i] = F1.z;
+    B[3 * i + 1] = F1.w;
+    B[3 * i + 2] = F2.x;
+}
+
+hipError_t launch_probe(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->geo, c->frec, n, xyz,
+                       tet, E, B);
     return hipGetLastError();
 }
 
@@ -745,12 +795,15 @@ hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet
 }
 
 // ------------------------------------------------------------------------------------------
-// Invariants: continuity (G^T g == Q - Q_old at every node) and D b == D b0 in every tet.
+// Invariants: continuity (G^T g == Q - Q_old at every node; with absorbing walls at every node
+// off the walls, since the charge of absorbed particles leaves through them) and D b == D b0
+// in every tet.
 __global__ void k_continuity(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lst,
                              const int64_t *__restrict__ g, const int64_t *__restrict__ Q,
-                             const int64_t *__restrict__ Qo, int64_t nn, unsigned long long *bad) {
+                             const int64_t *__restrict__ Qo, const uint8_t *__restrict__ skip, int64_t nn,
+                             unsigned long long *bad) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    if (n >= nn || (skip && skip[n])) return;
     int64_t s = 0;
     for (int j = ptr[n]; j < ptr[n + 1]; ++j) {
         int32_t v = lst[j];
@@ -772,7 +825,8 @@ __global__ void k_divb(const int32_t *__restrict__ tfaces, const int8_t *__restr
 hipError_t launch_verify(qh_ctx *c, bool check_divb) {
     int64_t nn = c->hm.Nn;
     hipLaunchKernelGGL(k_continuity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, c->n2e_ptr,
-                       c->n2e, c->g, c->Q, c->Q_old, nn, c->counters + 4 * QH_COUNTER_SLOTS);
+                       c->n2e, c->g, c->Q, c->Q_old, c->walls == QH_WALLS_ABSORB ? c->wall_node_d : nullptr, nn,
+                       c->counters + 4 * QH_COUNTER_SLOTS);
     if (check_divb) {
         int32_t nt = (int32_t)c->hm.Nt;
         hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
@@ -809,10 +863,13 @@ __device__ __forceinline__ void wave_runs(int t, bool valid, int &head, int &len
     rank = lane - head;
 }
 
-__global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t *__restrict__ hist) {
+// Bucket of a particle: its tet, or nt for one that left through an absorbing wall (tet -1).
+__device__ __forceinline__ int sort_key(int t, int32_t nt) { return t < 0 ? nt : t; }
+
+__global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t nt, int32_t *__restrict__ hist) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
-    const int t = valid ? tet[i] : -1;
+    const int t = valid ? sort_key(tet[i], nt) : -1;
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
     if (valid && rank == 0) atomicAdd(&hist[t], len);
@@ -877,12 +934,12 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
                           const float *__restrict__ z, const float *__restrict__ vx,
                           const float *__restrict__ vy, const float *__restrict__ vz,
                           const int32_t *__restrict__ tet, const int32_t *__restrict__ id,
-                          int32_t *__restrict__ cursor, float *__restrict__ ox, float *__restrict__ oy,
+                          int32_t nt, int32_t *__restrict__ cursor, float *__restrict__ ox, float *__restrict__ oy,
                           float *__restrict__ oz, float *__restrict__ ovx, float *__restrict__ ovy,
                           float *__restrict__ ovz, int32_t *__restrict__ otet, int32_t *__restrict__ oid) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
-    const int t = valid ? tet[i] : -1;
+    const int t = valid ? sort_key(tet[i], nt) : -1;
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
     int32_t first = 0;
@@ -892,25 +949,34 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
     const int32_t j = first + rank;
     ox[j] = x[i]; oy[j] = y[i]; oz[j] = z[i];
     ovx[j] = vx[i]; ovy[j] = vy[i]; ovz[j] = vz[i];
-    otet[j] = t; oid[j] = id[i];
+    otet[j] = tet[i]; oid[j] = id[i];
 }
 
 int qh_sort_species(qh_ctx *c, Species &s) {
     if (s.n == 0) return QH_OK;
     int32_t nt = (int32_t)c->hm.Nt;
-    QH_HIP(c, hipMemsetAsync(c->hist, 0, sizeof(int32_t) * nt, c->stream));
+    const int32_t nk = nt + 1;  // buckets: the tets, then the particles absorbed by a wall
+    QH_HIP(c, hipMemsetAsync(c->hist, 0, sizeof(int32_t) * nk, c->stream));
     unsigned pb = (unsigned)((s.n + 255) / 256);
-    hipLaunchKernelGGL(k_hist, dim3(pb), dim3(256), 0, c->stream, s.tet, s.n, c->hist);
-    int32_t chunks = (nt + 1023) / 1024;
-    hipLaunchKernelGGL(k_scan_sums, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nt, c->scan_tmp);
+    hipLaunchKernelGGL(k_hist, dim3(pb), dim3(256), 0, c->stream, s.tet, s.n, nt, c->hist);
+    int32_t chunks = (nk + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_sums, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nk, c->scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->scan_tmp, chunks);
-    hipLaunchKernelGGL(k_scan_final, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nt, c->scan_tmp, c->cursor);
+    hipLaunchKernelGGL(k_scan_final, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nk, c->scan_tmp, c->cursor);
+    const bool absorb = c->walls == QH_WALLS_ABSORB;
+    int32_t live = (int32_t)s.n;  // the start of the last bucket
+    if (absorb) QH_HIP(c, hipMemcpyAsync(&live, c->cursor + nt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     hipLaunchKernelGGL(k_scatter, dim3(pb), dim3(256), 0, c->stream, s.n, s.x, s.y, s.zz, s.vx, s.vy, s.vz, s.tet,
-                       s.id, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
+                       s.id, nt, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
     QH_HIP(c, hipGetLastError());
     std::swap(s.x, s.sx); std::swap(s.y, s.sy); std::swap(s.zz, s.sz);
     std::swap(s.vx, s.svx); std::swap(s.vy, s.svy); std::swap(s.vz, s.svz);
     std::swap(s.tet, s.stet); std::swap(s.id, s.sid);
+    if (absorb) {
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        s.n = live;  // the absorbed particles sit past the live ones and are dropped
+        if (s.n == 0) return QH_OK;
+    }
     int32_t nb = (int32_t)qh_species_blocks(s.n);
     hipLaunchKernelGGL(k_own, dim3((nb + 1 + 255) / 256), dim3(256), 0, c->stream, s.tet, s.n, nb, nt, s.own);
     QH_HIP(c, hipGetLastError());

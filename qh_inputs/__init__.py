@@ -191,6 +191,28 @@ class CylinderMesh:
                 out[i] = inside[0]
         return out
 
+    def locate(self, p: np.ndarray) -> np.ndarray:
+        """Tet holding each point p (k x 3) inside the cavity: its layer from z, its disk triangle,
+        then the one of the prism's three tets whose barycentric coordinates are all >= 0 (up to
+        rounding). -1 for a point outside."""
+        p = np.asarray(p, np.float64)
+        layer = np.clip((p[:, 2] / self.L * self.nz).astype(np.int64), 0, self.nz - 1)
+        tri = self.locate_bottom(p[:, :2])
+        out = np.full(p.shape[0], -1, np.int64)
+        for i in np.flatnonzero(tri >= 0):
+            best, tbest = -np.inf, -1
+            for k in range(3):
+                t = (layer[i] * self.tri.shape[0] + tri[i]) * 3 + k
+                V = self.xyz[self.tets[t]]
+                M = np.column_stack([V[1] - V[0], V[2] - V[0], V[3] - V[0]])
+                l123 = np.linalg.solve(M, p[i] - V[0])
+                lmin = min(1.0 - l123.sum(), l123.min())
+                if lmin > best:
+                    best, tbest = lmin, t
+            if best > -1e-9:
+                out[i] = tbest
+        return out
+
 
 def beam_injection_counts(steps: int, dt: float, per_step: float, t_on: float) -> np.ndarray:
     """Macro-particles injected in each of the first `steps` steps for a current that rises

@@ -1,0 +1,205 @@
+"""Beam injected into a cylindrical PEC cavity with absorbing walls (Sec. VI.B table), on the
+GPU through the C ABI, against the oracle: the charge of injected particles, the particles the
+walls absorb, the integer deposits (the GPU's own pieces re-deposited by the oracle, bit for bit),
+continuity off the walls, the field update of a beam step, the growth of a species' storage, and
+the field probe."""
+import numpy as np
+import pytest
+
+import qh_inputs as qi
+
+from .gpu_setup import S, gpu_context, oracle_setup
+
+pytestmark = pytest.mark.gpu
+
+U_B = 2.0 ** -56
+C = qi.BEAM_CYL
+
+
+@pytest.fixture(scope="module")
+def cyl():
+    mesh = qi.CylinderMesh(C["R"], C["L"], C["nr"], C["nz"])
+    cx, op, po = oracle_setup(mesh)
+    return mesh, cx, op, po
+
+
+def _wall_bound_cloud(mesh, k=100, seed=4):
+    """Four groups of k electrons: near the side wall moving outward, near the far end moving
+    +z, near the injection face moving -z (all three cross their wall by about half a
+    millimetre or more in a step of 1e-10 s), and slow ones inside."""
+    gen = np.random.default_rng(seed)
+    phi = 2 * np.pi * gen.random(4 * k)
+    r = np.concatenate([np.full(k, 0.0185), 0.015 * np.sqrt(gen.random(3 * k))])
+    z = np.concatenate([0.01 + 0.08 * gen.random(k), np.full(k, 0.099), np.full(k, 0.0012),
+                        0.01 + 0.08 * gen.random(k)])
+    x = np.column_stack([r * np.cos(phi), r * np.sin(phi), z]).astype(np.float32)
+    v = np.zeros((4 * k, 3))
+    v[:k, 0], v[:k, 1] = 2e7 * np.cos(phi[:k]), 2e7 * np.sin(phi[:k])
+    v[k:2 * k, 2] = 3e7
+    v[2 * k:3 * k, 2] = -2e7
+    v[3 * k:] = 1e5 * gen.standard_normal((k, 3))
+    x64 = x.astype(np.float64)
+    tet = mesh.locate(x64)
+    assert (tet >= 0).all()
+    return x, v.astype(np.float32), tet.astype(np.int32)
+
+
+def _last_pieces(seg):
+    order = np.lexsort((seg["seq"], seg["pid"]))
+    pid = seg["pid"][order]
+    last = np.r_[pid[1:] != pid[:-1], True]
+    return order, last
+
+
+def test_inject_and_absorb_match_oracle(cyl):
+    import paper_2103_06737_amd as qh
+    from oracle.field import init_fields
+    mesh, cx, op, po = cyl
+    dt = 1e-10
+    ctx = gpu_context(mesh, dt)
+    ctx.set_walls(qh.WALLS_ABSORB)
+    e0, b0 = init_fields(cx, qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), 1e3, 0.0, 0.0, U_B)
+    ctx.fields_upload(e0, b0)
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = _wall_bound_cloud(mesh)
+    ctx.particles_upload(sid, x, v, tet)
+    _, Q_up = ctx.deposits_download()
+    xi, vi, ti = qi.beam_injection(mesh, 10, C["r_b"], C["v_p"], seed=0, step=0)
+    ctx.particles_inject(sid, xi, vi, ti)
+    assert ctx.particles_count(sid) == 410
+    assert np.array_equal(ctx.particles_ids(sid), np.arange(410))
+    _, Q0 = ctx.deposits_download()
+    ctx.capture_segments(4096)
+    st = ctx.pic_step(ctx.step_params(verify=1))[0]
+    g, Q1 = ctx.deposits_download()
+    nseg, seg = ctx.segments_download()
+    assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+
+    # the oracle's FP64 push of the same 410 particles with absorbing walls
+    xa = np.concatenate([x, xi]).astype(np.float64)
+    va = np.concatenate([v, vi]).astype(np.float64)
+    ta = np.concatenate([tet, ti])
+    orc = po.push(e0, b0 * U_B, xa, va, ta, -qi.QE / qi.ME, dt, -1, absorb=True)
+    gone = orc["absorbed"]
+    assert gone[:300].mean() > 0.95 and not gone[300:].any()
+    assert st["wall_hits"] == gone.sum()
+    ids = ctx.particles_ids(sid)
+    assert np.array_equal(ids, np.flatnonzero(~gone))
+    xg, vg, tg = ctx.particles_download(sid)
+    keep = ~gone
+    assert (tg == orc["tet"][keep]).mean() > 0.99
+    assert np.abs(xg - orc["x"][keep]).max() < 1e-6
+
+    # injected charge: the first pieces of the injected particles start at their quantised
+    # points; re-deposited by the oracle they give Q0 - Q_up bit for bit
+    first = seg["seq"] == 0
+    inj = first & (seg["pid"] >= 400)
+    assert inj.sum() == 10
+    _, Q_inj = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                               seg["tet"][inj], seg["lam0"][inj], -np.ones(10))
+    assert np.array_equal(Q_inj, Q0 - Q_up)
+    # the step's pieces give g bit for bit; the end pieces of the survivors give Q1
+    assert nseg == seg["tet"].size
+    g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], -np.ones(nseg), np.zeros(0),
+                              np.zeros((0, 4)), np.zeros(0))
+    assert np.array_equal(g_re, g)
+    order, last = _last_pieces(seg)
+    survivor = np.isin(seg["pid"][order][last], ids)
+    sel = order[last][survivor]
+    _, Q_re = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                              seg["tet"][sel], seg["lam1"][sel], -np.ones(sel.size))
+    assert np.array_equal(Q_re, Q1)
+    # continuity: exact off the walls; on them the charge the absorbed particles took out,
+    # at their wall points (face coordinates, the one opposite the wall zero)
+    d = cx.G.T @ g - (Q1 - Q0)
+    assert (d[~cx.wall_node] == 0).all()
+    assert d.sum() == -S * S * gone.sum()
+    out = order[last][~survivor]
+    assert ((seg["lam1"][out] == 0).sum(axis=1) >= 1).all()
+
+
+def test_beam_steps_with_field_solve(cyl):
+    """The beam of the table for 120 steps (10 electrons of 52012.58 injected per step at
+    5e7 m/s inside 8 mm, dt = 10 q / 0.25 A), full cycle with the Gauss-law correction:
+    continuity off the walls and the Gauss law every step, the count of particles, and the
+    field update of the last step against the oracle's from the same state."""
+    import paper_2103_06737_amd as qh
+    from oracle.field import FieldOracle
+    mesh, cx, op, po = cyl
+    dt, w = C["dt"], C["weight"]
+    u_q = qi.QE * w * 2.0 ** -40
+    ctx = gpu_context(mesh, dt, weight=w)
+    ctx.set_walls(qh.WALLS_ABSORB)
+    ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    injected = absorbed = 0
+    fo = FieldOracle(cx, op, dt)
+    for k in range(120):
+        xi, vi, ti = qi.beam_injection(mesh, C["per_step"], C["r_b"], C["v_p"], seed=0, step=k)
+        ctx.particles_inject(sid, xi, vi, ti)
+        injected += xi.shape[0]
+        if k == 119:
+            e_n, b_n = ctx.fields_download()
+        st = ctx.pic_step(params)[0]
+        absorbed += st["wall_hits"]
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
+        assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+    assert ctx.particles_count(sid) == injected - absorbed == 1200
+    e_g, b_g = ctx.fields_download()
+    g, Q = ctx.deposits_download()
+    e_o, b_o, _ = fo.step(e_n, b_n, U_B, g, u_q, Q, np.zeros(cx.Nn, np.int64), tol=1e-13, tol_n=1e-13)
+    assert np.linalg.norm(e_g - e_o) <= 1e-7 * np.linalg.norm(e_o)
+    assert np.abs(b_g - b_o).max() <= 2 + 1e-9 * np.abs(b_o).max()
+    # the front has moved 120 steps at v_p (the space-charge field barely slows it)
+    x, _, _ = ctx.particles_download(sid)
+    zf = x[:, 2].max()
+    assert 0.99 * 120 * dt * C["v_p"] < zf < 1.01 * 120 * dt * C["v_p"]
+
+
+def test_species_storage_grows_and_ids_continue(cyl):
+    import paper_2103_06737_amd as qh
+    mesh, cx, op, po = cyl
+    ctx = gpu_context(mesh, 1e-11)
+    ctx.set_walls(qh.WALLS_ABSORB)
+    ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+    a = ctx.species_add(-qi.QE / qi.ME, -1)
+    b = ctx.species_add(-qi.QE / qi.ME, -1)      # never uploaded: injection only
+    x, v, t = _wall_bound_cloud(mesh, k=25)
+    ctx.particles_upload(a, x, v, t)
+    xi, vi, ti = qi.beam_injection(mesh, 5000, C["r_b"], C["v_p"], seed=1)
+    ctx.particles_inject(a, xi, vi, ti)
+    ctx.particles_inject(b, xi[:700], vi[:700], ti[:700])
+    xa, va, ta = ctx.particles_download(a)
+    assert np.array_equal(xa[:100], x) and np.array_equal(xa[100:], xi) and np.array_equal(ta[100:], ti)
+    assert np.array_equal(ctx.particles_ids(b), np.arange(700))
+    absorbed = 0
+    for _ in range(3):
+        st = ctx.pic_step(ctx.step_params(verify=1))[0]
+        assert st["continuity_bad"] == 0 and st["lost"] == 0
+        absorbed += st["wall_hits"]
+    # 3 steps of 1e-11 s move nobody to a wall
+    assert absorbed == 0 and ctx.particles_count(a) == 5100 and ctx.particles_count(b) == 700
+    ids = ctx.particles_ids(a)
+    assert ids[-1] == 5099 and np.all(np.diff(ids) > 0)
+    xa2, _, _ = ctx.particles_download(a)
+    # the injected beam moved 3 steps of 5e7 m/s x 1e-11 s along z, in id order
+    inj = np.isin(ids, np.arange(100, 5100))
+    assert np.allclose(xa2[inj][:, 2], 3 * 1e-11 * C["v_p"], rtol=1e-5)
+
+
+def test_probe_matches_oracle_gather(cyl):
+    from oracle.field import init_fields
+    mesh, cx, op, po = cyl
+    ctx = gpu_context(mesh, 1e-11)
+    e, b = init_fields(cx, qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), 1e3, 0.05, 1e-3, U_B)
+    ctx.fields_upload(e, b)
+    gen = np.random.default_rng(8)
+    r = 0.019 * np.sqrt(gen.random(300))
+    ph = 2 * np.pi * gen.random(300)
+    p = np.column_stack([r * np.cos(ph), r * np.sin(ph), 0.1 * gen.random(300)])
+    t = mesh.locate(p)
+    E, B = ctx.probe_fields(p, t.astype(np.int32))
+    Eo, Bo = po.gather(e, b * U_B, p, t)
+    assert np.abs(E - Eo).max() <= 1e-5 * np.abs(Eo).max()
+    assert np.abs(B - Bo).max() <= 1e-5 * np.abs(Bo).max()
