@@ -227,6 +227,67 @@ def plane_wave_run(workload: str, particles, steps: int, f0=300e6, bw=150e6, e_p
     print(json.dumps(out))
 
 
+def beam_run(steps: int, tol_edge: float = 1e-6):
+    """The beam of Sec. VI.B: electrons injected through the z = 0 face of a PEC cylinder
+    (radius 20 mm, length 100 mm; 10 macro-particles of 52012.58 electrons per step at the full
+    0.25 A, v_p = 5e7 m/s inside r_b = 8 mm, current turned on linearly over 2 ns; absorbing
+    walls). Four runs: the trapezoidal (E-B) and wave-equation updates, each with and without
+    the Gauss-law correction, at a loose edge tolerance. Per run: time per step (injection,
+    cycle and the per-step sort; the stats of every step are read), the radial E halfway down
+    the tube at r = 16 mm (the paper's observable, mean of four probes), and the Gauss-law
+    error, sampled in time."""
+    import paper_2103_06737_amd as qh
+    c = qi.BEAM_CYL
+    mesh = qi.CylinderMesh(c["R"], c["L"], c["nr"], c["nz"])
+    dt = c["dt"]
+    counts = qi.beam_injection_counts(steps, dt, c["per_step"], c["t_on"])
+    inj = [qi.beam_injection(mesh, int(n), c["r_b"], c["v_p"], seed=0, step=k) if n else None
+           for k, n in enumerate(counts)]
+    rp = 0.016
+    probe = np.array([[rp, 0, 0.5 * c["L"]], [0, rp, 0.5 * c["L"]], [-rp, 0, 0.5 * c["L"]], [0, -rp, 0.5 * c["L"]]])
+    ptet = mesh.locate(probe).astype(np.int32)
+    rhat = probe[:, :2] / rp
+    every = max(1, steps // 40)
+    runs = []
+    for mode, gauss in ((qh.FIELDS_SOLVE, 1), (qh.FIELDS_WAVE, 1), (qh.FIELDS_SOLVE, 0), (qh.FIELDS_WAVE, 0)):
+        ctx = qh.Context(0)
+        ctx.set_walls(qh.WALLS_ABSORB)
+        ctx.mesh_upload(mesh.xyz, mesh.tets)
+        ctx.set_physics(qi.EPS0, qi.MU0, dt, qi.QE * c["weight"] * 2.0 ** -40, 2.0 ** -56)
+        mi = ctx.mesh_info()
+        ctx.fields_upload(np.zeros(mi.n_edges), np.zeros(mi.n_faces, np.int64))
+        sid = ctx.species_add(-qi.QE / qi.ME, -1)
+        prm = qh.Context.step_params(field_mode=mode, gauss=gauss, tol_edge=tol_edge, tol_node=1e-8,
+                                     max_it_edge=2000, max_it_node=5000, check_every=8)
+        t_step, series, absorbed, it_e, it_n = 0.0, [], 0, 0, 0
+        for k in range(steps):
+            w0 = time.perf_counter()
+            if inj[k] is not None:
+                ctx.particles_inject(sid, *inj[k])
+            st = ctx.pic_step(prm)[0]
+            t_step += time.perf_counter() - w0
+            absorbed += st["wall_hits"]
+            it_e += st["edge_iters"]
+            it_n += st["node_iters"]
+            if (k + 1) % every == 0:
+                E, _ = ctx.probe_fields(probe, ptet)
+                er = float(np.mean(np.sum(E[:, :2] * rhat, axis=1)))
+                series.append([round((k + 1) * dt * 1e9, 4), er, st["gauss_res"], ctx.particles_count(sid)])
+        runs.append({"update": "wave" if mode == qh.FIELDS_WAVE else "trapezoidal", "gauss_correction": bool(gauss),
+                     "ms_per_step": round(1e3 * t_step / steps, 4), "injected": int(counts.sum()),
+                     "absorbed": int(absorbed), "in_flight": ctx.particles_count(sid),
+                     "edge_iters_mean": round(it_e / steps, 2), "node_iters_mean": round(it_n / steps, 2),
+                     "samples_t_ns_Er_gaussres_count": series})
+        log(f"[beam] {runs[-1]['update']} correction {bool(gauss)}: {runs[-1]['ms_per_step']} ms/step, "
+            f"in flight {runs[-1]['in_flight']}, absorbed {absorbed}, E_r end {series[-1][1]:.4g} V/m, "
+            f"gauss_res end {series[-1][2]:.3e}")
+        ctx.close()
+    print(json.dumps({"study": "beam_injection_cylinder", "workload": "PEC cylinder r 20 mm x 100 mm "
+                      f"({mesh.tets.shape[0]} tets), beam of the Sec. VI.B table", "steps": steps, "dt": dt,
+                      "tol_edge": tol_edge, "tol_node": 1e-8, "probe": "E_r at z = 50 mm, r = 16 mm",
+                      "runs": runs}))
+
+
 def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: float = 25.0):
     """The FP64 oracle as it stands, on the host cores: one particle push over a sample of the
     particles plus one oracle field update on the full mesh; whole-step rate extrapolated to
@@ -317,6 +378,9 @@ def main():
     ap.add_argument("--plane-wave", type=int, default=0, metavar="STEPS",
                     help="the full cycle with natural walls and a plane-wave pulse entering through them; "
                          "prints its own JSON line")
+    ap.add_argument("--beam", type=int, default=0, metavar="STEPS",
+                    help="the beam injected into the cylindrical cavity (trapezoidal and wave updates, "
+                         "with and without the Gauss-law correction); prints its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
@@ -330,6 +394,9 @@ def main():
         return
     if args.plane_wave:
         plane_wave_run(args.workload, args.particles, args.plane_wave)
+        return
+    if args.beam:
+        beam_run(args.beam)
         return
     import paper_2103_06737_amd as qh
     ctx, cfg, mesh, parts, mi = setup(args.workload, args.particles)

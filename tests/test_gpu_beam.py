@@ -203,3 +203,40 @@ def test_probe_matches_oracle_gather(cyl):
     Eo, Bo = po.gather(e, b * U_B, p, t)
     assert np.abs(E - Eo).max() <= 1e-5 * np.abs(Eo).max()
     assert np.abs(B - Bo).max() <= 1e-5 * np.abs(Bo).max()
+
+
+def test_beam_field_matches_line_charge():
+    """Once the full current has reached the middle of the tube (turn-on 2 ns plus 1 ns of
+    transit), the radial field there at r = 16 mm, outside the 8 mm beam, is that of the line
+    charge lambda = I / v_p inside a grounded tube, lambda / (2 pi eps0 r) by Gauss's law (5.6
+    kV/m), up to the beam's slowing by its own potential (about 1 %), the cavity modes the
+    turn-on excites, and the pointwise error of the lowest-order edge elements at h / r of 0.1
+    to 0.25 (a few %). Trapezoidal update with the Gauss-law correction, 11250 steps (3.75 ns),
+    the probe averaged over the last 0.5 ns."""
+    import paper_2103_06737_amd as qh
+    mesh = qi.CylinderMesh(C["R"], C["L"], C["nr"], C["nz"])
+    dt, steps = C["dt"], 11250
+    ctx = gpu_context(mesh, dt, weight=C["weight"])
+    ctx.set_walls(qh.WALLS_ABSORB)
+    mi = ctx.mesh_info()
+    ctx.fields_upload(np.zeros(mi.n_edges), np.zeros(mi.n_faces, np.int64))
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    counts = qi.beam_injection_counts(steps, dt, C["per_step"], C["t_on"])
+    prm = ctx.step_params(field_mode=qh.FIELDS_SOLVE, tol_edge=1e-8, tol_node=1e-8)
+    probe = np.array([[0.016, 0, 0.05], [0, 0.016, 0.05], [-0.016, 0, 0.05], [0, -0.016, 0.05]])
+    ptet = mesh.locate(probe).astype(np.int32)
+    er, absorbed = [], 0
+    for k in range(steps):
+        if counts[k]:
+            ctx.particles_inject(sid, *qi.beam_injection(mesh, int(counts[k]), C["r_b"], C["v_p"], seed=0, step=k))
+        st = ctx.pic_step(prm)[0]
+        absorbed += st["wall_hits"]
+        assert st["lost"] == 0 and st["gauss_res"] <= 1.01e-8
+        if k >= steps - 1500 and k % 100 == 0:
+            E, _ = ctx.probe_fields(probe, ptet)
+            er.append(np.mean(np.sum(E[:, :2] * probe[:, :2] / 0.016, axis=1)))
+    assert ctx.particles_count(sid) + absorbed == counts.sum()
+    assert absorbed > 0.2 * counts.sum()   # the front reached the far wall at 2 ns
+    lam = -C["current"] / C["v_p"]
+    e_line = lam / (2 * np.pi * qi.EPS0 * 0.016)
+    assert abs(np.mean(er) / e_line - 1) < 0.10, (np.mean(er), e_line)
