@@ -663,13 +663,13 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(cap) * QH_CHUNK))) return rc;
         s.cap = cap;
     }
-    std::vector<float> comp(n);
+    // components laid out one after another; the host buffers live until the sync at the end
+    std::vector<float> comp(6 * n);
     float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
     for (int k = 0; k < 6; ++k) {
         const float *src = k < 3 ? x : v;
-        for (int64_t i = 0; i < n; ++i) comp[i] = src[3 * i + k % 3];
-        QH_HIP(c, hipMemcpyAsync(dst[k] + n0, comp.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
-        QH_HIP(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < n; ++i) comp[k * n + i] = src[3 * i + k % 3];
+        QH_HIP(c, hipMemcpyAsync(dst[k] + n0, comp.data() + k * n, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
     }
     std::vector<int32_t> ids(n);
     std::iota(ids.begin(), ids.end(), (int32_t)s.next_id);

@@ -81,6 +81,7 @@ struct StepArgs {
     float dt;
     int32_t zq;             // charge number
     int32_t absorb;         // walls absorb (1) or reflect (0)
+    int32_t zeroed;         // acc_tet was cleared before the launch: write the window sums only
     int64_t *g, *Q;         // deposits that find no mailbox slot (atomics)
     int64_t *acc_tet;       // per-tet sums, plane-major: acc_tet[k * nt + t], k = 6 edges, 4 nodes
     uint16_t *ovf;          // per block: chunk indices of queued particles past the LDS queue
@@ -369,6 +370,12 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     const int W = min(T1 - T0, kWin);
     for (int j = threadIdx.x; j < 10 * kWin; j += kBlock) acc[j] = 0;
     if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
+    // owned tets past the window get no LDS sums: the whole block zeroes them now (the mailbox
+    // kernel that follows adds their posted pieces), unless the host cleared every sum
+    if (!a.zeroed)
+        for (int j = W + threadIdx.x; j < T1 - T0; j += kBlock)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) a.acc_tet[(int64_t)k * a.nt + T0 + j] = 0;
     __syncthreads();
     unsigned int n_cross = 0, n_wall = 0, n_lost = 0, n_foreign = 0;
     auto deposit_to = [&](auto group, int tt, const int P0[4], const int P1[4], bool end) {
@@ -539,14 +546,13 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         n_lost += __shfl_xor(n_lost, off, 64);
         n_foreign += __shfl_xor(n_foreign, off, 64);
     }
-    // owned tets: window sums, zeros beyond (their deposits are posted); this wave's own LDS
-    // additions are ordered before these reads
-    const int m = T1 - T0;
+    // owned tets: the window sums (the tets beyond were zeroed at the start); this wave's own
+    // LDS additions are ordered before these reads
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         int64_t *dst = a.acc_tet + (int64_t)k * a.nt + T0;
         const long long scale = k < 6 ? (long long)a.zq : (long long)a.zq * QH_SCALE;
-        for (int j = lane; j < m; j += 64) dst[j] = j < W ? scale * acc[k * kWin + j] : 0;
+        for (int j = lane; j < W; j += 64) dst[j] = scale * acc[k * kWin + j];
     }
     // event counters: crossings, wall hits, lost, posted pieces
     if (lane < 4) {
@@ -670,6 +676,11 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     const unsigned nmail = (unsigned)((c->hm.Nt + kMailTets - 1) / kMailTets);
     hipError_t e = hipMemsetAsync(c->mail_cnt, 0, sizeof(unsigned int) * nmail, c->stream);
     if (e != hipSuccess) return e;
+    // few particles on a large mesh (the blocks' windows cannot cover it): one fill clears the
+    // per-tet sums instead of each block zeroing a long owned range
+    a.zeroed = (int64_t)grid.x * kWin < c->hm.Nt ? 1 : 0;
+    if (a.zeroed && (e = hipMemsetAsync(c->acc_tet, 0, sizeof(int64_t) * 10 * c->hm.Nt, c->stream)) != hipSuccess)
+        return e;
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
     const HostMesh &m = c->hm;
