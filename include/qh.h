@@ -126,7 +126,7 @@ int qh_create(qh_ctx **out, int device, void *stream);
 void qh_destroy(qh_ctx *ctx);
 const char *qh_last_error(const qh_ctx *ctx);
 
-#define QH_WALLS_REFLECT 0 /* particles reflect specularly at the walls (axis-aligned walls only) */
+#define QH_WALLS_REFLECT 0 /* particles reflect specularly at the walls */
 #define QH_WALLS_ABSORB 1  /* a particle reaching a wall stops there and leaves the domain */
 #define QH_BC_PEC 0     /* walls are perfect conductors: wall edges carry no E, wall nodes are grounded */
 #define QH_BC_NEUMANN 1 /* natural boundary: every edge and node is an unknown; the Gauss-law solve
@@ -195,8 +195,8 @@ int qh_particles_count(const qh_ctx *ctx, int32_t species, int64_t *n);
 /* The ids of the species' particles, ascending (the order of qh_particles_download). */
 int qh_particles_ids(const qh_ctx *ctx, int32_t species, int32_t *ids);
 
-/* What particles do at the walls: QH_WALLS_REFLECT (default; specular reflection at
- * axis-aligned walls) or QH_WALLS_ABSORB (the beam test of Sec. VI.B: a particle reaching a
+/* What particles do at the walls: QH_WALLS_REFLECT (default; specular reflection about the
+ * wall plane, exact sign flips on walls normal to an axis) or QH_WALLS_ABSORB (the beam test of Sec. VI.B: a particle reaching a
  * wall stops at the wall point; its current up to there is deposited, its charge is not, since
  * it leaves through the conductor, and it is removed at the end of the step). With absorbing
  * walls continuity holds at every node off the walls, which is what the step's verification

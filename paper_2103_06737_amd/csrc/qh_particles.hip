@@ -252,7 +252,7 @@ __device__ __forceinline__ void record_piece(const StepArgs &a, int32_t pid, int
 // ------------------------------------------------------------------------------------------
 // Walk of one particle from (px, py, pz) in tet t along dt v^{n+1/2}, face by face (exit
 // face = smallest crossing parameter, the entry face excluded; at most QH_MAX_PIECES
-// pieces), reflecting specularly at axis-aligned walls, or, with absorbing walls, stopping at
+// pieces), reflecting specularly at the walls, or, with absorbing walls, stopping at
 // the wall point (gone: the charge leaves through the wall, so no end point is deposited).
 // deposit(tet, L_start, L_end, end) takes each straight piece; on return the state holds the
 // end point, its tet and the (possibly reflected) velocity.
@@ -324,18 +324,28 @@ __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py
             ++n_wall;
             return;
         } else {
-            // specular reflection at an axis-aligned wall: the wall normal is grad l_k
+            // specular reflection: the wall normal is grad l_k. A normal along an axis (two zero
+            // components, as on box walls) flips that component exactly; any other mirrors the
+            // displacement and the velocity about the wall plane
             float nx, ny, nz;
             if (k == 0) { nx = -(A.x + B.x + C.x); ny = -(A.y + B.y + C.y); nz = -(A.z + B.z + C.z); }
             else if (k == 1) { nx = A.x; ny = A.y; nz = A.z; }
             else if (k == 2) { nx = B.x; ny = B.y; nz = B.z; }
             else { nx = C.x; ny = C.y; nz = C.z; }
-            const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
-            const bool fx = ax >= ay && ax >= az, fy = !fx && ay >= az, fz = !fx && !fy;
-            // selects, not branches: keeps the components in registers
-            rx = fx ? -rx : rx; vx = fx ? -vx : vx;
-            ry = fy ? -ry : ry; vy = fy ? -vy : vy;
-            rz = fz ? -rz : rz; vz = fz ? -vz : vz;
+            const int zeros = (nx == 0.0f) + (ny == 0.0f) + (nz == 0.0f);
+            if (zeros == 2) {
+                // selects, not branches: keeps the components in registers
+                const bool fx = nx != 0.0f, fy = ny != 0.0f, fz = nz != 0.0f;
+                rx = fx ? -rx : rx; vx = fx ? -vx : vx;
+                ry = fy ? -ry : ry; vy = fy ? -vy : vy;
+                rz = fz ? -rz : rz; vz = fz ? -vz : vz;
+            } else {
+                const float inv = 1.0f / (nx * nx + ny * ny + nz * nz);
+                const float rn = 2.0f * (rx * nx + ry * ny + rz * nz) * inv;
+                const float vn = 2.0f * (vx * nx + vy * ny + vz * nz) * inv;
+                rx -= rn * nx; ry -= rn * ny; rz -= rn * nz;
+                vx -= vn * nx; vy -= vn * ny; vz -= vn * nz;
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) Lp[r] = Lc[r];
             entry = k;

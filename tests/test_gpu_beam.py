@@ -26,11 +26,12 @@ def cyl():
 def _wall_bound_cloud(mesh, k=100, seed=4):
     """Four groups of k electrons: near the side wall moving outward, near the far end moving
     +z, near the injection face moving -z (all three cross their wall by about half a
-    millimetre or more in a step of 1e-10 s), and slow ones inside."""
+    millimetre or more in a step of 1e-10 s), and slow ones inside. Reflected, none ends on a
+    layer face (z = 97.7 mm and 0.8 mm, between the 2 mm layers)."""
     gen = np.random.default_rng(seed)
     phi = 2 * np.pi * gen.random(4 * k)
     r = np.concatenate([np.full(k, 0.0185), 0.015 * np.sqrt(gen.random(3 * k))])
-    z = np.concatenate([0.01 + 0.08 * gen.random(k), np.full(k, 0.099), np.full(k, 0.0012),
+    z = np.concatenate([0.01 + 0.08 * gen.random(k), np.full(k, 0.0993), np.full(k, 0.0012),
                         0.01 + 0.08 * gen.random(k)])
     x = np.column_stack([r * np.cos(phi), r * np.sin(phi), z]).astype(np.float32)
     v = np.zeros((4 * k, 3))
@@ -178,8 +179,8 @@ def test_species_storage_grows_and_ids_continue(cyl):
         st = ctx.pic_step(ctx.step_params(verify=1))[0]
         assert st["continuity_bad"] == 0 and st["lost"] == 0
         absorbed += st["wall_hits"]
-    # 3 steps of 1e-11 s move nobody to a wall
-    assert absorbed == 0 and ctx.particles_count(a) == 5100 and ctx.particles_count(b) == 700
+    # in 3 steps of 1e-11 s only the far-end group (0.3 mm per step from 0.7 mm) reaches a wall
+    assert absorbed == 25 and ctx.particles_count(a) == 5075 and ctx.particles_count(b) == 700
     ids = ctx.particles_ids(a)
     assert ids[-1] == 5099 and np.all(np.diff(ids) > 0)
     xa2, _, _ = ctx.particles_download(a)
@@ -240,3 +241,42 @@ def test_beam_field_matches_line_charge():
     lam = -C["current"] / C["v_p"]
     e_line = lam / (2 * np.pi * qi.EPS0 * 0.016)
     assert abs(np.mean(er) / e_line - 1) < 0.10, (np.mean(er), e_line)
+
+
+def test_reflecting_cylinder_walls_match_oracle(cyl):
+    """Specular reflection at walls that are not normal to an axis (the cylinder's side): the
+    velocity and the rest of the displacement are mirrored about the wall plane. Positions and
+    velocities agree with the oracle's FP64 mirror, speeds are kept, and continuity holds at
+    every node (nothing leaves)."""
+    import paper_2103_06737_amd as qh
+    mesh, cx, op, po = cyl
+    dt = 1e-10
+    ctx = gpu_context(mesh, dt)
+    ctx.set_walls(qh.WALLS_REFLECT)
+    ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = _wall_bound_cloud(mesh)
+    ctx.particles_upload(sid, x, v, tet)
+    _, Q0 = ctx.deposits_download()
+    ctx.capture_segments(8192)
+    st = ctx.pic_step(ctx.step_params(verify=1))[0]
+    assert st["continuity_bad"] == 0 and st["lost"] == 0 and st["wall_hits"] >= 290
+    g, Q1 = ctx.deposits_download()
+    assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+    orc = po.push(np.zeros(cx.Ne), np.zeros(cx.Nf), x, v, tet, -qi.QE / qi.ME, dt, -1)
+    assert orc["wall_hits"] == st["wall_hits"]
+    xg, vg, tg = ctx.particles_download(sid)
+    assert ctx.particles_count(sid) == 400
+    assert (tg == orc["tet"]).mean() > 0.99
+    assert np.abs(xg - orc["x"]).max() < 2e-6
+    assert np.abs(vg - orc["v"]).max() < 1e-5 * np.abs(orc["v"]).max()
+    sp0, sp1 = np.linalg.norm(v.astype(np.float64), axis=1), np.linalg.norm(vg.astype(np.float64), axis=1)
+    assert np.abs(sp1 / sp0 - 1).max() < 1e-5
+    # side-wall particles now move inward
+    side = slice(0, 100)
+    rdot = np.sum(xg[side, :2] * vg[side, :2], axis=1)
+    assert (rdot < 0).all()
+    nseg, seg = ctx.segments_download()
+    g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], -np.ones(nseg), np.zeros(0),
+                              np.zeros((0, 4)), np.zeros(0))
+    assert np.array_equal(g_re, g)
