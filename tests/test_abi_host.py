@@ -37,6 +37,32 @@ def test_host_context_rejects_device_calls():
     assert ei.value.code == qh.QH_ESTATE
 
 
+def test_host_particle_and_wall_calls_validate():
+    """Wall mode, injection, counts and the probe: argument errors are QH_EINVAL, calls that need
+    the device are QH_ESTATE on a host-only context, and nothing is half-done."""
+    import paper_2103_06737_amd as qh
+    m = qi.CylinderMesh(0.02, 0.1, 3, 4)
+    ctx = qh.Context(-1)
+    ctx.mesh_upload(m.xyz, m.tets)
+    for mode in (qh.WALLS_ABSORB, qh.WALLS_REFLECT):
+        ctx.set_walls(mode)
+    with pytest.raises(qh.QhError) as ei:
+        ctx.set_walls(2)
+    assert ei.value.code == qh.QH_EINVAL
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    assert ctx.particles_count(sid) == 0
+    with pytest.raises(qh.QhError) as ei:
+        ctx.particles_count(sid + 1)
+    assert ei.value.code == qh.QH_EINVAL
+    x, v, t = qi.beam_injection(m, 4, 0.008, 5e7)
+    for call in (lambda: ctx.particles_inject(sid, x, v, t), lambda: ctx.probe_fields(x, t),
+                 lambda: ctx.particles_ids(sid)):
+        with pytest.raises(qh.QhError) as ei:
+            call()
+        assert ei.value.code == qh.QH_ESTATE
+    assert ctx.particles_count(sid) == 0
+
+
 def test_host_rejects_bad_meshes():
     import paper_2103_06737_amd as qh
     m = qi.BoxMesh(2)
