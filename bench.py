@@ -205,7 +205,10 @@ def plane_wave_run(workload: str, particles, steps: int, f0=300e6, bw=150e6, e_p
     ctx.timing(False)
     bc = boundary_counts(mesh.tets, mi.n_nodes)
     ms_b, n_b = kt["boundary"]
-    by = 32 * bc["edges"] + 16 * bc["points"] + 24 * bc["nodes"] + 12 * 2 * bc["edges"]
+    # per wall edge: row pointer, edge id, right-hand side in and out, h sum out; per rule point:
+    # coefficient and index of its x (the table of s' per distinct x stays in L2); per wall node:
+    # list pointer, node id, flux in and out; per list entry: edge index and its h sum
+    by = 32 * bc["edges"] + 12 * bc["points"] + 24 * bc["nodes"] + 12 * 2 * bc["edges"]
     us = 1e3 * ms_b / max(n_b, 1)
     kern = {k: {"ms_total": round(ms, 4), "launches": c, "us_per_launch": round(1e3 * ms / c, 3)}
             for k, (ms, c) in kt.items() if c}

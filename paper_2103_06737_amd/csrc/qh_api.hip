@@ -297,6 +297,12 @@ int qh_set_plane_wave(qh_ctx *c, double E0, double f0, double bandwidth, double 
     }
     ptr.push_back((int32_t)pts.size());
     const int32_t nb = (int32_t)edge.size();
+    // the incident field depends on x only: s' is evaluated once per distinct x of the points
+    std::vector<double> xs(xq);
+    std::sort(xs.begin(), xs.end());
+    xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+    std::vector<int32_t> xi(xq.size());
+    for (size_t k = 0; k < xq.size(); ++k) xi[k] = (int32_t)(std::lower_bound(xs.begin(), xs.end(), xq[k]) - xs.begin());
     // boundary nodes: per node, its boundary edges with the sign of G (head +1, tail -1)
     std::vector<std::vector<int32_t>> lists(m.Nn);
     for (int32_t i = 0; i < nb; ++i) {
@@ -312,13 +318,15 @@ int qh_set_plane_wave(qh_ctx *c, double E0, double f0, double bandwidth, double 
             nptr.push_back((int32_t)nlist.size());
         }
     QH_HIP(c, hipStreamSynchronize(c->stream));  // a second call replaces the first one's tables
-    qh_release(c, c->pw_ptr), qh_release(c, c->pw_edge), qh_release(c, c->pw_coef), qh_release(c, c->pw_x);
+    qh_release(c, c->pw_ptr), qh_release(c, c->pw_edge), qh_release(c, c->pw_coef), qh_release(c, c->pw_xi);
+    qh_release(c, c->pw_xs), qh_release(c, c->pw_tab);
     qh_release(c, c->pw_nptr), qh_release(c, c->pw_nlist), qh_release(c, c->pw_node);
     qh_release(c, c->pw_hsum);
     c->pw_on = false;
     int rc;
     if ((rc = upload(c, &c->pw_ptr, ptr.data(), ptr.size())) || (rc = upload(c, &c->pw_edge, edge.data(), edge.size())) ||
-        (rc = upload(c, &c->pw_coef, coef.data(), coef.size())) || (rc = upload(c, &c->pw_x, xq.data(), xq.size())) ||
+        (rc = upload(c, &c->pw_coef, coef.data(), coef.size())) || (rc = upload(c, &c->pw_xi, xi.data(), xi.size())) ||
+        (rc = upload(c, &c->pw_xs, xs.data(), xs.size())) || (rc = qh_alloc(c, &c->pw_tab, 3 * xs.size())) ||
         (rc = upload(c, &c->pw_nptr, nptr.data(), nptr.size())) ||
         (rc = upload(c, &c->pw_nlist, nlist.data(), nlist.size())) || (rc = upload(c, &c->pw_node, node.data(), node.size())) ||
         (rc = qh_alloc(c, &c->pw_hsum, std::max<int32_t>(1, nb))))
@@ -329,6 +337,7 @@ int qh_set_plane_wave(qh_ctx *c, double E0, double f0, double bandwidth, double 
     }
     c->pw_nb = nb;
     c->pw_nn = (int32_t)node.size();
+    c->pw_nu = (int32_t)xs.size();
     c->pw_amp = E0 / std::sqrt(c->phys.mu0 / c->phys.eps0);
     c->pw_c = 1.0 / std::sqrt(c->phys.eps0 * c->phys.mu0);
     c->pw_f0 = f0;

@@ -187,9 +187,11 @@ struct qh_ctx {
     // plane wave through the natural boundary (qh_set_plane_wave)
     bool pw_on = false;
     double pw_amp = 0.0, pw_f0 = 0.0, pw_sig = 0.0, pw_t0 = 0.0, pw_c = 0.0;  // amp = E0 / eta
-    int32_t pw_nb = 0, pw_nn = 0;           // boundary edges, boundary nodes
+    int32_t pw_nb = 0, pw_nn = 0, pw_nu = 0;  // boundary edges, boundary nodes, distinct point x
     int32_t *pw_ptr = nullptr, *pw_edge = nullptr;   // per boundary edge: its rule points, its unknown index
-    double *pw_coef = nullptr, *pw_x = nullptr;      // per point: weight x W1 . (n x y-hat), x
+    double *pw_coef = nullptr;              // per point: weight x W1 . (n x y-hat)
+    int32_t *pw_xi = nullptr;               // per point: index of its x among the distinct ones
+    double *pw_xs = nullptr, *pw_tab = nullptr;      // distinct x; s' there at t^{n-1}, t^n, t^{n+1}
     double *pw_hsum = nullptr;              // per boundary edge: dt/2 (h^n + h^{n+1}) of this step
     int32_t *pw_nptr = nullptr, *pw_nlist = nullptr; // per boundary node: boundary edge index << 1 | (1: tail)
     int32_t *pw_node = nullptr;             // boundary node ids

@@ -425,22 +425,34 @@ __device__ __forceinline__ double pw_ds(double tau, double f0, double sig, doubl
     return env * (-(u / (sig * sig)) * cos(om * u) - om * sin(om * u));
 }
 
+// s'(t - x/c) at the step's three times for each distinct x of the rule points.
+__global__ void k_pw_table(int32_t nu, const double *__restrict__ xs, double f0, double sig, double t0, double c0,
+                           double t_prev, double t_n, double t_next, double *__restrict__ tab) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nu) return;
+    const double ret = xs[i] / c0;
+    tab[3 * i] = pw_ds(t_prev - ret, f0, sig, t0);
+    tab[3 * i + 1] = pw_ds(t_n - ret, f0, sig, t0);
+    tab[3 * i + 2] = pw_ds(t_next - ret, f0, sig, t0);
+}
+
 // Boundary term h_i(t) = sum over the edge's rule points of coef * (E0/eta) s'(t - x/c), at the
-// step's times; adds the update's share to the right-hand side (trapezoidal: dt/2 (h^n +
-// h^{n+1}); wave equation: dt/2 (h^{n+1} - h^{n-1})) and keeps dt/2 (h^n + h^{n+1}) for the
-// Gauss-law target.
+// step's times (s' from the table); adds the update's share to the right-hand side
+// (trapezoidal: dt/2 (h^n + h^{n+1}); wave equation: dt/2 (h^{n+1} - h^{n-1})) and keeps
+// dt/2 (h^n + h^{n+1}) for the Gauss-law target.
 __global__ void k_plane_wave(int32_t nb, const int32_t *__restrict__ ptr, const int32_t *__restrict__ edge,
-                             const double *__restrict__ coef, const double *__restrict__ xq, double amp, double f0,
-                             double sig, double t0, double c0, double t_prev, double t_n, double t_next, double half_dt,
-                             int wave, double *__restrict__ rhs, double *__restrict__ hsum) {
+                             const double *__restrict__ coef, const int32_t *__restrict__ xi,
+                             const double *__restrict__ tab, double amp, double half_dt, int wave,
+                             double *__restrict__ rhs, double *__restrict__ hsum) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     double hp = 0.0, hn = 0.0, hx = 0.0;
     for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
-        const double ret = xq[k] / c0;
-        hn += coef[k] * pw_ds(t_n - ret, f0, sig, t0);
-        hx += coef[k] * pw_ds(t_next - ret, f0, sig, t0);
-        if (wave) hp += coef[k] * pw_ds(t_prev - ret, f0, sig, t0);
+        const double w = coef[k];
+        const double *s = tab + 3 * xi[k];
+        hn += w * s[1];
+        hx += w * s[2];
+        if (wave) hp += w * s[0];
     }
     const double hs = half_dt * amp * (hn + hx);
     hsum[i] = hs;
@@ -638,9 +650,11 @@ hipError_t launch_wave_rhs(qh_ctx *c) {
 
 hipError_t launch_plane_wave(qh_ctx *c, bool wave) {
     const double dt = c->phys.dt, tn = (double)c->step_index * dt;
+    hipLaunchKernelGGL(k_pw_table, dim3((c->pw_nu + 255) / 256), dim3(256), 0, c->stream, c->pw_nu, c->pw_xs, c->pw_f0,
+                       c->pw_sig, c->pw_t0, c->pw_c, tn - dt, tn, tn + dt, c->pw_tab);
     hipLaunchKernelGGL(k_plane_wave, dim3((c->pw_nb + 255) / 256), dim3(256), 0, c->stream, c->pw_nb, c->pw_ptr,
-                       c->pw_edge, c->pw_coef, c->pw_x, c->pw_amp, c->pw_f0, c->pw_sig, c->pw_t0, c->pw_c, tn - dt, tn,
-                       tn + dt, 0.5 * dt, wave ? 1 : 0, c->cge.b, c->pw_hsum);
+                       c->pw_edge, c->pw_coef, c->pw_xi, c->pw_tab, c->pw_amp, 0.5 * dt, wave ? 1 : 0, c->cge.b,
+                       c->pw_hsum);
     hipLaunchKernelGGL(k_boundary_flux, dim3((c->pw_nn + 255) / 256), dim3(256), 0, c->stream, c->pw_nn, c->pw_nptr,
                        c->pw_nlist, c->pw_node, c->pw_hsum, c->dbnd);
     return hipGetLastError();
