@@ -329,3 +329,36 @@ def test_plane_wave_face_subset():
         hf, hp = full.h(t), part.h(t)
         assert (np.abs(hf[sample]) > 0).sum() >= 10   # zero on the y-walls (n x y-hat = 0)
         assert np.allclose(hp[sample], hf[sample], rtol=1e-13, atol=0)
+
+
+def test_explicit_limit_is_the_leapfrog_stability_bound():
+    """The explicit limit used to set the workloads' time steps, dt_CFL = 2 / sqrt(lambda_max
+    ([*eps]^-1 S)), pinned twice: its eigenvalue agrees with a dense generalized symmetric
+    eigen-solve, and it is the stability bound of the explicit leap-frog for [*eps] e'' = -S e
+    (bounded just below it, exponential growth just above it)."""
+    import scipy.linalg as sl
+    from oracle.complex_ import Complex
+    from oracle.whitney import Operators
+    m = qi.BoxMesh(3)
+    cx = Complex(m.xyz, m.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    dt = Fo.dt_cfl(op, cx, tol=1e-12)
+    ie = cx.int_edges
+    M = op.Meps[ie][:, ie].toarray()
+    K = op.S[ie][:, ie].toarray()
+    lam = sl.eigh(K, M, eigvals_only=True)
+    assert abs(dt / (2.0 / np.sqrt(lam.max())) - 1) < 1e-8
+    Minv_S = np.linalg.solve(M, K)
+    rng = np.random.default_rng(0)
+
+    def run(h, steps=600):
+        e0 = rng.standard_normal(ie.size)
+        e_prev, e = e0, e0.copy()
+        top = 0.0
+        for _ in range(steps):
+            e_prev, e = e, 2 * e - e_prev - h * h * (Minv_S @ e)
+            top = max(top, np.abs(e).max())
+        return top / np.abs(e0).max()
+
+    assert run(0.99 * dt) < 1e2
+    assert run(1.01 * dt) > 1e6
