@@ -87,6 +87,23 @@ class FieldOracle:
             self._Kz = (self.Cz.T @ self.K @ self.Cz).tocsr()
         return self._Kz
 
+    def decompose(self, e, tol=1e-13):
+        """Quasi-Helmholtz split of the edge field (Sec. III: the projector P^Sigma_e with the
+        zero-mean constraint of eq. zero_mean_constraint): rho_bar = G^T [*eps] e on the
+        unknown nodes, E_ns = K^{-1} rho_bar (node coefficients of the potential part; zero on
+        PEC walls, zero W0-weighted mean under natural walls), E_s = e - G E_ns (edge
+        coefficients, G^T [*eps] E_s = 0). Returns (E_ns on all nodes, E_s on all edges,
+        rho_bar on the unknown nodes)."""
+        rho_bar = (self.GtMeps @ e)[self.inn]
+        if self.cx.neumann:
+            y, _, _ = pcg(self.Kz, self.Cz.T @ rho_bar, tol=tol)
+            phi = self.Cz @ y
+        else:
+            phi, _, _ = pcg(self.K, rho_bar, tol=tol)
+        e_ns = np.zeros(self.cx.Nn)
+        e_ns[self.inn] = phi
+        return e_ns, e - self.Gint @ phi, rho_bar
+
     def rhs(self, e, b_real, g_real):
         r = self.Bm @ e + self.dt * (self.op.CtMmu @ b_real) - g_real
         return r[self.ie]

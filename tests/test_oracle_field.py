@@ -362,3 +362,55 @@ def test_explicit_limit_is_the_leapfrog_stability_bound():
 
     assert run(0.99 * dt) < 1e2
     assert run(1.01 * dt) > 1e6
+
+
+def test_quasi_helmholtz_split():
+    """E = grad(E_ns) + E_s (Sec. III): E_s has zero discrete divergence and is [*eps]-orthogonal
+    to the potential part; the potential part has no curl; a gradient field is all E_ns, a field
+    with [*eps] e in the range of C^T is all E_s; on a small mesh E_ns equals the literal
+    projector form of the co-tree system; under natural walls E_ns has zero W0-weighted mean
+    and E_s matches the PEC-free least-squares split."""
+    from oracle.complex_ import Complex
+    from oracle.cotree import ReducedSystem
+    from oracle.whitney import Operators
+    m = qi.make_mesh(qi.CONFIGS["jitter4"])
+    cx = Complex(m.xyz, m.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    fo = Fo.FieldOracle(cx, op, 1e-10)
+    rng = np.random.default_rng(11)
+    e = np.zeros(cx.Ne)
+    e[cx.int_edges] = rng.standard_normal(cx.int_edges.size)
+    e_ns, e_s, rho = fo.decompose(e)
+    Gf = cx.G.astype(float)
+    div = (fo.GtMeps @ e_s)[cx.int_nodes]
+    assert np.linalg.norm(div) <= 1e-11 * np.linalg.norm(rho)
+    assert np.allclose(Gf @ e_ns + e_s, e, rtol=0, atol=1e-14 * np.abs(e).max())
+    assert abs((Gf @ e_ns) @ (op.Meps @ e_s)) <= 1e-11 * np.sqrt((Gf @ e_ns) @ (op.Meps @ (Gf @ e_ns)) * (e_s @ (op.Meps @ e_s)))
+    assert np.abs(cx.C @ (Gf @ e_ns)).max() <= 1e-13 * np.abs(e_ns).max()
+    assert (e_ns[cx.wall_node] == 0).all()
+    # pure gradient: all potential
+    psi = np.zeros(cx.Nn)
+    psi[cx.int_nodes] = rng.standard_normal(cx.int_nodes.size)
+    g_ns, g_s, _ = fo.decompose(Gf @ psi)
+    assert np.allclose(g_ns, psi, atol=1e-10) and np.abs(g_s).max() < 1e-10
+    # [*eps] e = C^T w (zero discrete divergence): all solenoidal
+    w = rng.standard_normal(cx.Nf)
+    w[cx.wall_face] = 0.0
+    ie = cx.int_edges
+    e_c = np.zeros(cx.Ne)
+    import scipy.sparse.linalg as sla
+    e_c[ie] = sla.spsolve(op.Meps[ie][:, ie].tocsc(), (cx.C.T.astype(float) @ w)[ie])
+    c_ns, c_s, _ = fo.decompose(e_c)
+    assert np.abs(c_ns).max() <= 1e-10 * np.abs(e_c).max() / np.abs(Gf).max() and np.allclose(c_s, e_c, atol=1e-12 * np.abs(e_c).max())
+    # the literal projector form (dense, co-tree system)
+    rs = ReducedSystem(cx, op, 1e-10)
+    Ens_lit, _, _ = rs.decompose(e[cx.int_edges], np.zeros(np.count_nonzero(~cx.wall_face)))
+    assert np.allclose(e_ns[cx.int_nodes], Ens_lit, rtol=1e-9, atol=1e-12 * np.abs(Ens_lit).max())
+    # natural walls: zero W0-weighted mean, same E_s as the least-squares solution of the singular system
+    cn = Complex(m.xyz, m.tets, neumann=True)
+    fn = Fo.FieldOracle(cn, op, 1e-10)
+    en = rng.standard_normal(cn.Ne)
+    n_ns, n_s, n_rho = fn.decompose(en)
+    assert abs(fn.alpha @ n_ns) <= 1e-12 * np.abs(fn.alpha).sum() * np.abs(n_ns).max()
+    phi_ls = np.linalg.lstsq(fn.K.toarray(), n_rho, rcond=None)[0]
+    assert np.allclose(n_s, en - Gf @ phi_ls, atol=1e-9 * np.abs(en).max())
