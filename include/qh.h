@@ -257,6 +257,19 @@ int qh_deposit(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t
                const int32_t *lam1, const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet,
                const int32_t *pt_lam, const int32_t *pt_z, int64_t *g_out, int64_t *q_out);
 
+/* Quasi-Helmholtz split of the present electric field (Sec. III, the projector P^Sigma_e; eq.
+ * zero_mean_constraint under natural walls): rho_bar = G^T [*eps] e (the discrete divergence,
+ * which the Gauss-law correction holds equal to the charge), E_ns = K^{-1} rho_bar (node
+ * coefficients of the potential part, grad of sum E_ns,j W0_j), E_s = e - G E_ns (the
+ * solenoidal remainder, G^T [*eps] E_s = 0 to the solve's tolerance). The node solve stops at
+ * the backward error tol, as the Gauss-law correction does. Outputs (host, caller-allocated,
+ * any may be NULL): e_ns and rho_bar n_nodes values (zero on PEC wall nodes; under natural walls
+ * E_ns has zero W0-weighted mean), e_s n_edges values (zero on PEC wall edges). B is solenoidal
+ * by construction (D b = 0 in integers): B_s = b, B_ns = 0. QH_ENOTCONV if the solve stopped at
+ * max_it (outputs filled). */
+int qh_fields_decompose(qh_ctx *ctx, double tol, int32_t max_it, double *e_ns, double *e_s, double *rho_bar,
+                        qh_solve_stats_t *stats);
+
 /* Solve system (QH_SYS_EDGE or QH_SYS_NODE) A x = rhs on its interior unknowns
  * (n_int_edges or n_int_nodes values), FP64 CG with FP64 dot products, to
  * ||rhs - A x|| <= tol ||rhs||. x holds the initial guess on entry. */

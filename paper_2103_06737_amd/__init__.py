@@ -34,7 +34,8 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_matrix_info", "qh_matrix_download", "qh_timing_enable", "qh_timing_read",
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
            "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
-           "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields"]
+           "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
+           "qh_fields_decompose"]
 
 
 class QhError(RuntimeError):
@@ -123,6 +124,7 @@ def lib():
             "qh_set_walls": [p, i32],
             "qh_particles_inject": [p, i32, i64, p, p, p],
             "qh_probe_fields": [p, i64, p, p, p, p],
+            "qh_fields_decompose": [p, d, i32, p, p, p, C.POINTER(SolveStats)],
             "qh_charge_background": [p, i32],
             "qh_pic_step": [p, C.POINTER(StepParams), i32, p],
             "qh_deposits_download": [p, p, p],
@@ -359,6 +361,18 @@ class Context:
         self._check(self.L.qh_deposit(self.h, a[0].shape[0], _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]),
                                       a[4].shape[0], _ptr(a[4]), _ptr(a[5]), _ptr(a[6]), _ptr(g), _ptr(Q)))
         return g, Q
+
+    def fields_decompose(self, tol=1e-10, max_it=5000, allow=()):
+        """Quasi-Helmholtz split of the present e: (E_ns node coefficients, E_s edge values,
+        rho_bar = G^T [*eps] e on the nodes, solve stats)."""
+        mi = self.mesh_info()
+        e_ns = np.zeros(mi.n_nodes)
+        e_s = np.zeros(mi.n_edges)
+        rho = np.zeros(mi.n_nodes)
+        st = SolveStats()
+        rc = self.L.qh_fields_decompose(self.h, float(tol), int(max_it), _ptr(e_ns), _ptr(e_s), _ptr(rho), C.byref(st))
+        self._check(rc, allow)
+        return e_ns, e_s, rho, dict(iters=st.iters, res=st.res, ms=st.ms)
 
     def field_solve(self, system, rhs, x0=None, tol=1e-8, max_it=5000, precond=PC_JACOBI, allow=()):
         rhs = _c(rhs, np.float64)

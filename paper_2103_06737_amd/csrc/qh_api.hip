@@ -988,6 +988,71 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     return status;
 }
 
+int qh_fields_decompose(qh_ctx *c, double tol, int32_t max_it, double *e_ns, double *e_s, double *rho_bar,
+                        qh_solve_stats_t *stats) {
+    if (!c || !(tol > 0) || max_it < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled || !c->have_fields) return qh_fail(c, QH_ESTATE, "mesh, physics and fields first");
+    const HostMesh &m = c->hm;
+    const int32_t ne = c->A.n, nn = c->K.n;
+    int rc;
+    if (!c->dec_e && (rc = qh_alloc(c, &c->dec_e, std::max<int32_t>(ne, 1)))) return rc;
+    hipEvent_t e0, e1;
+    QH_HIP(c, hipEventCreate(&e0));
+    QH_HIP(c, hipEventCreate(&e1));
+    QH_HIP(c, hipEventRecord(e0, c->stream));
+    SolveResult sn;
+    sn.converged = true;
+    if (nn > 0) {
+        // K delta = -G^T [*eps] e, so delta = -E_ns and E_s = e + G delta
+        QH_HIP(c, launch_div_e(c, c->scratch_d, tol));
+        QH_HIP(c, hipMemsetAsync(c->cgn.x, 0, sizeof(double) * nn, c->stream));
+        if ((rc = qh_cg_solve(c, c->K, c->cgn, tol, max_it, 8, sn, c->scratch_d, true))) return rc;
+    }
+    QH_HIP(c, hipMemcpyAsync(c->dec_e, c->cge.x, sizeof(double) * ne, hipMemcpyDeviceToDevice, c->stream));
+    if (nn > 0) QH_HIP(c, launch_grad_add(c, c->cgn.x, c->dec_e));
+    QH_HIP(c, hipEventRecord(e1, c->stream));
+    std::vector<double> es(ne), dl(nn), rg(nn);
+    QH_HIP(c, hipMemcpyAsync(es.data(), c->dec_e, sizeof(double) * ne, hipMemcpyDeviceToHost, c->stream));
+    if (nn > 0) {
+        QH_HIP(c, hipMemcpyAsync(dl.data(), c->cgn.x, sizeof(double) * nn, hipMemcpyDeviceToHost, c->stream));
+        QH_HIP(c, hipMemcpyAsync(rg.data(), c->cgn.b, sizeof(double) * nn, hipMemcpyDeviceToHost, c->stream));
+    }
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e_s) {
+        std::fill(e_s, e_s + m.Ne, 0.0);
+        for (int32_t i = 0; i < ne; ++i) e_s[m.int_edges[i]] = es[i];
+    }
+    if (e_ns) {
+        std::fill(e_ns, e_ns + m.Nn, 0.0);
+        for (int32_t i = 0; i < nn; ++i) e_ns[m.int_nodes[i]] = -dl[i];
+        if (m.neumann) {
+            // the potential is fixed up to a constant: zero W0-weighted mean (alpha_i = integral of W0_i)
+            std::vector<double> alpha(m.Nn, 0.0);
+            for (int64_t t = 0; t < m.Nt; ++t)
+                for (int k = 0; k < 4; ++k) alpha[m.tn[4 * t + k]] += 0.25 * m.vol[t];
+            double sa = 0.0, sp = 0.0;
+            for (int64_t v = 0; v < m.Nn; ++v) sa += alpha[v], sp += alpha[v] * e_ns[v];
+            for (int64_t v = 0; v < m.Nn; ++v) e_ns[v] -= sp / sa;
+        }
+    }
+    if (rho_bar) {
+        std::fill(rho_bar, rho_bar + m.Nn, 0.0);
+        for (int32_t i = 0; i < nn; ++i) rho_bar[m.int_nodes[i]] = -rg[i];
+    }
+    if (stats) {
+        stats->iters = sn.iters;
+        stats->res = sn.res;
+        stats->fallback = 0;
+        stats->ms = ms;
+    }
+    return sn.converged ? QH_OK : qh_fail(c, QH_ENOTCONV, "decomposition: node solve did not converge");
+}
+
 int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, double tol, int32_t max_it,
                    int32_t precond, qh_solve_stats_t *stats) {
     if (!c || !rhs || !x || max_it < 0) return QH_EINVAL;

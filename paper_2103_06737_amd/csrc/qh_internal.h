@@ -207,6 +207,7 @@ struct qh_ctx {
     CgWork cge, cgn;            // cge.x holds e on the interior edges between steps
     CgWork cgx;                 // standalone solves (qh_field_solve)
     double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
+    double *dec_e = nullptr;      // interior edge values of E_s (qh_fields_decompose)
     unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS slots (crossings, wall hits,
                                              // lost), then continuity and D b violations
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
@@ -318,6 +319,8 @@ hipError_t launch_wave_rhs(qh_ctx *c);
 hipError_t launch_plane_wave(qh_ctx *c, bool wave);
 hipError_t launch_gauss_rhs(qh_ctx *c, double *thr2_dev, double tol_n);
 hipError_t launch_gauss_apply(qh_ctx *c);
+hipError_t launch_div_e(qh_ctx *c, double *out3, double tol_n);
+hipError_t launch_grad_add(qh_ctx *c, const double *delta, double *e_int);
 hipError_t launch_faraday(qh_ctx *c);
 hipError_t launch_true_residual(qh_ctx *c, const DevCsr &M, const double *x, const double *b,
                                 double *out2 /* [0] ||b-Ax||^2 [1] ||b||^2 */);

@@ -670,6 +670,26 @@ hipError_t launch_gauss_rhs(qh_ctx *c, double *out3, double tol_n) {
     return hipGetLastError();
 }
 
+// Quasi-Helmholtz split: cgn.b = -G^T [*eps] e (the Gauss-law right-hand side with no charge
+// and no boundary flux), with the node solve's threshold in out3 as for the correction.
+hipError_t launch_div_e(qh_ctx *c, double *out3, double tol_n) {
+    int32_t n = c->GtM.n;
+    unsigned gr = grid_rows(n);
+    hipLaunchKernelGGL(k_gauss_rhs, dim3(gr), dim3(kThreads), 0, c->stream, n, c->GtM.ptr, c->GtM.col, c->GtM.val,
+                       c->cge.x, (const int64_t *)c->Q, (const int64_t *)c->Q, c->int_nodes, 0.0, (const double *)nullptr,
+                       c->cgn.b, (double *)nullptr, c->cgn.partial);
+    hipLaunchKernelGGL(k_gauss_finish, dim3(1), dim3(kThreads), 0, c->stream, c->cgn.partial, (int)gr, out3, tol_n);
+    return hipGetLastError();
+}
+
+// e_int += G delta (interior edge values; delta on the unknown nodes)
+hipError_t launch_grad_add(qh_ctx *c, const double *delta, double *e_int) {
+    int32_t n = c->A.n;
+    hipLaunchKernelGGL(k_gauss_apply, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->int_edges, c->edge_nodes,
+                       c->int_node_of, delta, e_int);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauss_apply(qh_ctx *c) {
     int32_t n = c->A.n;
     hipLaunchKernelGGL(k_gauss_apply, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->int_edges, c->edge_nodes,

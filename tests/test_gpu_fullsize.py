@@ -103,6 +103,16 @@ def test_plasma64_full_cycle(plasma64):
     assert np.array_equal(b1, b0 - cx.C @ u)
     assert np.array_equal(cx.D @ b1, cx.D @ b0)
 
+    # quasi-Helmholtz split of the new field (Sec. III): rho_bar is the discrete divergence (the
+    # charge, by the Gauss law just enforced), E_s + G E_ns = e and E_s has no divergence
+    e_ns, e_s, rho_bar, st = ctx.fields_decompose(tol=1e-10)
+    div = (fo.GtMeps @ e1)[cx.int_nodes]
+    absd = (abs(fo.GtMeps) @ np.abs(e1))[cx.int_nodes]
+    assert (np.abs(rho_bar[cx.int_nodes] - div) <= 64 * np.finfo(float).eps * absd).all()
+    assert np.abs(cx.G.astype(float) @ e_ns + e_s - e1).max() <= 1e-12 * np.abs(e1).max()
+    assert np.linalg.norm((fo.GtMeps @ e_s)[cx.int_nodes]) <= 1e-9 * np.linalg.norm(absd)
+    assert np.linalg.norm(rho_bar[cx.int_nodes] - rho) <= 1.01e-8 * (np.linalg.norm(rho) + np.linalg.norm(absd))
+
 
 def test_plasma64_plane_wave_natural_boundary(plasma64):
     """Natural walls and a plane-wave pulse (300 MHz, 150 MHz bandwidth, its peak passing x = 0 at

@@ -340,6 +340,39 @@ def test_plane_wave_through_natural_boundary(mode):
     assert max(rel[40:64]) < 0.15
 
 
+@pytest.mark.parametrize("bc", ["pec", "neumann"])
+def test_fields_decompose_matches_oracle(jitter4, bc):
+    """Quasi-Helmholtz split (Sec. III) of a random field: rho_bar = G^T [*eps] e, the potential
+    part E_ns = K^{-1} rho_bar (zero W0-weighted mean under natural walls) and E_s = e - G E_ns
+    against the oracle's; E_s has no discrete divergence."""
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    from oracle.field import FieldOracle
+    from oracle.whitney import Operators
+    cfg, mesh, _, _, _, _, _, _ = jitter4
+    cx = Complex(mesh.xyz, mesh.tets, neumann=bc == "neumann")
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    ctx = qh.Context(0)
+    if bc == "neumann":
+        ctx.set_boundary(qh.BC_NEUMANN)
+    ctx.mesh_upload(mesh.xyz, mesh.tets)
+    ctx.set_physics(qi.EPS0, qi.MU0, 1e-10, qi.QE * 2.0 ** -40, U_B)
+    e = np.random.default_rng(12).standard_normal(cx.Ne) * 1e3
+    if bc == "pec":
+        e[cx.wall_edge] = 0.0
+    ctx.fields_upload(e, np.zeros(cx.Nf, np.int64))
+    e_ns, e_s, rho, st = ctx.fields_decompose(tol=1e-12)
+    fo = FieldOracle(cx, op, 1e-10)
+    o_ns, o_s, o_rho = fo.decompose(e, tol=1e-14)
+    terms = (abs(fo.GtMeps) @ np.abs(e))[cx.int_nodes]
+    assert (np.abs(rho[cx.int_nodes] - o_rho) <= 64 * np.finfo(float).eps * terms).all()
+    assert np.linalg.norm(e_ns - o_ns) <= 1e-8 * np.linalg.norm(o_ns)
+    assert np.linalg.norm(e_s - o_s) <= 1e-8 * np.linalg.norm(o_s)
+    div = (fo.GtMeps @ e_s)[cx.int_nodes]
+    assert np.linalg.norm(div) <= 1e-10 * np.linalg.norm(terms)
+    assert st["iters"] > 0
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
