@@ -183,8 +183,10 @@ int qh_fields_init_synthetic(qh_ctx *ctx, const double *white_e, const double *w
  * charge-to-mass ratio q_over_m (C/kg) and an integer charge number z (deposit sign and
  * multiple of u_q). */
 int qh_species_add(qh_ctx *ctx, double q_over_m, int32_t charge_number, int32_t *species_id);
-/* x, v: 3n floats (x0 y0 z0 ...); tet: n tet ids holding each point. Replaces the
- * species' particles and recomputes the node charge Q of all species. */
+/* x, v: 3n floats (x0 y0 z0 ...); tet: n tet ids holding each point, or NULL to locate them
+ * on the device (qh_locate; QH_EINVAL naming the first point outside the mesh, and the species
+ * is then left empty). Replaces the species' particles and recomputes the node charge Q of all
+ * species. */
 int qh_particles_upload(qh_ctx *ctx, int32_t species, int64_t n, const float *x,
                         const float *v, const int32_t *tet);
 /* Ordered by particle id (ascending; ids are the upload order, then the injection order).
@@ -212,7 +214,16 @@ int qh_set_walls(qh_ctx *ctx, int32_t mode);
  * storage grows as needed (device memory is reallocated; injected particles are sorted into
  * place at the next sort). QH_EINVAL for a tet id out of range. */
 int qh_particles_inject(qh_ctx *ctx, int32_t species, int64_t n, const float *x, const float *v,
-                        const int32_t *tet);
+                        const int32_t *tet);  /* tet NULL: located on the device, as for upload */
+
+/* Tet holding each of n points (xyz: 3n doubles, host), found on the device: from a seed tet
+ * of a uniform bucket grid over the bounding box, the straight segment from its centroid to the
+ * point is walked face by face in the FP32 barycentrics the push uses, so the tet is the one
+ * the push sees (a point on a face may get either neighbour; a point on a wall up to rounding,
+ * its barycentric for the wall face above -1e-5, the tet behind it). tet[i] = -1 for a point
+ * outside the mesh, or when the segment leaves a non-convex mesh. QH_EINVAL for a non-finite
+ * point. */
+int qh_locate(qh_ctx *ctx, int64_t n, const double *xyz, int32_t *tet);
 
 /* E (V/m) and B (T) at n points (xyz: 3n doubles, tet: the tet holding each point) from the
  * present e and b, evaluated as the push gathers them (E = sum e_i W1_i linear in the tet,

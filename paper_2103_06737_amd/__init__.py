@@ -35,7 +35,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
            "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
-           "qh_fields_decompose"]
+           "qh_fields_decompose", "qh_locate"]
 
 
 class QhError(RuntimeError):
@@ -125,6 +125,7 @@ def lib():
             "qh_particles_inject": [p, i32, i64, p, p, p],
             "qh_probe_fields": [p, i64, p, p, p, p],
             "qh_fields_decompose": [p, d, i32, p, p, p, C.POINTER(SolveStats)],
+            "qh_locate": [p, i64, p, p],
             "qh_charge_background": [p, i32],
             "qh_pic_step": [p, C.POINTER(StepParams), i32, p],
             "qh_deposits_download": [p, p, p],
@@ -263,18 +264,26 @@ class Context:
         self._check(self.L.qh_species_add(self.h, float(q_over_m), int(charge_number), C.byref(sid)))
         return sid.value
 
-    def particles_upload(self, sid, x, v, tet):
+    def particles_upload(self, sid, x, v, tet=None):
+        """tet None: the library locates the particles on the device."""
         x = _c(x, np.float32)
         v = _c(v, np.float32)
-        tet = _c(tet, np.int32)
-        self._check(self.L.qh_particles_upload(self.h, sid, tet.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+        tet = None if tet is None else _c(tet, np.int32)
+        self._check(self.L.qh_particles_upload(self.h, sid, x.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
 
-    def particles_inject(self, sid, x, v, tet):
+    def particles_inject(self, sid, x, v, tet=None):
         """Append particles (ids continue); their charge is added to the present node charge."""
         x = _c(x, np.float32)
         v = _c(v, np.float32)
-        tet = _c(tet, np.int32)
-        self._check(self.L.qh_particles_inject(self.h, sid, tet.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+        tet = None if tet is None else _c(tet, np.int32)
+        self._check(self.L.qh_particles_inject(self.h, sid, x.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+
+    def locate(self, xyz):
+        """Tet holding each point (-1 outside the mesh), found on the device."""
+        xyz = _c(xyz, np.float64)
+        tet = np.zeros(xyz.shape[0], np.int32)
+        self._check(self.L.qh_locate(self.h, xyz.shape[0], _ptr(xyz), _ptr(tet)))
+        return tet
 
     def particles_count(self, sid):
         n = C.c_int64()

@@ -159,6 +159,61 @@ int set_fields(qh_ctx *c, const double *e, const int64_t *b) {
     return sync(c);
 }
 
+// Seeds of point location: a uniform grid of about Nt/2 buckets over the bounding box; each
+// bucket holds a tet whose centroid lies in it, or (buckets without one) a neighbour's.
+int build_locator(qh_ctx *c) {
+    const HostMesh &m = c->hm;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < m.Nn; ++v)
+        for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], m.xyz[3 * v + d]), hi[d] = std::max(hi[d], m.xyz[3 * v + d]);
+    const double target = std::max<double>(1.0, std::min<double>(0.5 * (double)m.Nt, 16777216.0));
+    const double ext[3] = {std::max(hi[0] - lo[0], 1e-300), std::max(hi[1] - lo[1], 1e-300), std::max(hi[2] - lo[2], 1e-300)};
+    const double h = std::cbrt(ext[0] * ext[1] * ext[2] / target);
+    int64_t total = 1;
+    for (int d = 0; d < 3; ++d) {
+        c->loc_n[d] = (int32_t)std::max<double>(1.0, std::min<double>(4096.0, std::ceil(ext[d] / h)));
+        c->loc_lo[d] = (float)lo[d];
+        c->loc_inv[d] = (float)(c->loc_n[d] / ext[d]);
+        total *= c->loc_n[d];
+    }
+    const int nx = c->loc_n[0], ny = c->loc_n[1], nz = c->loc_n[2];
+    std::vector<int32_t> seed(total, -1);
+    auto bucket = [&](const double *p) {
+        int b[3];
+        for (int d = 0; d < 3; ++d)
+            b[d] = std::min(std::max((int)((p[d] - lo[d]) * (c->loc_n[d] / ext[d])), 0), c->loc_n[d] - 1);
+        return ((int64_t)b[2] * ny + b[1]) * nx + b[0];
+    };
+    std::vector<int64_t> queue;
+    for (int64_t t = 0; t < m.Nt; ++t) {
+        const int64_t b = bucket(&m.cen[3 * t]);
+        if (seed[b] < 0) seed[b] = (int32_t)t, queue.push_back(b);
+    }
+    for (size_t q = 0; q < queue.size(); ++q) {  // breadth first into the empty buckets
+        const int64_t b = queue[q];
+        const int64_t bx = b % nx, by = (b / nx) % ny, bz = b / ((int64_t)nx * ny);
+        const int64_t nbs[6][3] = {{bx - 1, by, bz}, {bx + 1, by, bz}, {bx, by - 1, bz}, {bx, by + 1, bz}, {bx, by, bz - 1}, {bx, by, bz + 1}};
+        for (auto &u : nbs) {
+            if (u[0] < 0 || u[0] >= nx || u[1] < 0 || u[1] >= ny || u[2] < 0 || u[2] >= nz) continue;
+            const int64_t w = (u[2] * ny + u[1]) * nx + u[0];
+            if (seed[w] < 0) seed[w] = seed[b], queue.push_back(w);
+        }
+    }
+    return upload(c, &c->loc_seed, seed.data(), seed.size());
+}
+
+// Locates n particles of a species from index `first` on the device (their positions are in
+// place) into s.tet; QH_EINVAL naming the first point outside the mesh.
+int locate_species(qh_ctx *c, Species &s, int64_t first, int64_t n) {
+    QH_HIP(c, launch_locate(c, n, s.x + first, s.y + first, s.zz + first, s.tet + first));
+    std::vector<int32_t> t(n);
+    QH_HIP(c, hipMemcpyAsync(t.data(), s.tet + first, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i)
+        if (t[i] < 0) return qh_fail(c, QH_EINVAL, "particle " + std::to_string(i) + " lies outside the mesh");
+    return QH_OK;
+}
+
 int recompute_charge(qh_ctx *c) {
     QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * c->hm.Nn, c->stream));
     for (auto &s : c->species) QH_HIP(c, launch_charge_deposit(c, s));
@@ -374,6 +429,7 @@ int qh_mesh_upload(qh_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets
     if ((rc = upload(c, &c->tedges, te8.data(), te8.size()))) return rc;
     if ((rc = upload(c, &c->tnbr, (const int4 *)m.nbr.data(), m.Nt))) return rc;
     if ((rc = upload(c, &c->wall_node_d, m.wall_node.data(), m.wall_node.size()))) return rc;
+    if ((rc = build_locator(c))) return rc;
     if ((rc = upload(c, &c->tfaces, m.tf.data(), m.tf.size()))) return rc;
     if ((rc = upload(c, &c->tsign, m.tsign.data(), m.tsign.size()))) return rc;
     if ((rc = upload(c, &c->face_edges, m.face_edges.data(), m.face_edges.size()))) return rc;
@@ -516,11 +572,16 @@ int qh_species_add(qh_ctx *c, double q_over_m, int32_t z, int32_t *sid) {
 int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet) {
     if (!c || sid < 0 || sid >= (int32_t)c->species.size() || n < 0) return QH_EINVAL;
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
-    if (n > 0 && (!x || !v || !tet)) return QH_EINVAL;
+    if (n > 0 && (!x || !v)) return QH_EINVAL;
     if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
     if (n >= ((int64_t)1 << 31)) return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles per species");
-    for (int64_t i = 0; i < n; ++i)
-        if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    if (tet) {
+        for (int64_t i = 0; i < n; ++i)
+            if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    } else {
+        for (int64_t i = 0; i < 3 * n; ++i)
+            if (!std::isfinite(x[i])) return qh_fail(c, QH_EINVAL, "non-finite position at particle " + std::to_string(i / 3));
+    }
     Species &s = c->species[sid];
     int rc;
     if (n > s.cap) {
@@ -555,7 +616,12 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         }
         std::vector<int32_t> ids(n);
         std::iota(ids.begin(), ids.end(), 0);
-        QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        if (tet) {
+            QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        } else if ((rc = locate_species(c, s, 0, n))) {
+            s.n = 0;  // no particle is left with an unknown tet
+            return rc;
+        }
         QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
         if ((rc = qh_sort_species(c, s))) return rc;
     }
@@ -625,9 +691,14 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
     if (n == 0) return QH_OK;
-    if (!x || !v || !tet) return QH_EINVAL;
-    for (int64_t i = 0; i < n; ++i)
-        if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    if (!x || !v) return QH_EINVAL;
+    if (tet) {
+        for (int64_t i = 0; i < n; ++i)
+            if (tet[i] < 0 || tet[i] >= c->hm.Nt) return qh_fail(c, QH_EINVAL, "tet id out of range at particle " + std::to_string(i));
+    } else {
+        for (int64_t i = 0; i < 3 * n; ++i)
+            if (!std::isfinite(x[i])) return qh_fail(c, QH_EINVAL, "non-finite position at particle " + std::to_string(i / 3));
+    }
     Species &s = c->species[sid];
     const int64_t n0 = s.n, n1 = n0 + n;
     if (n1 >= ((int64_t)1 << 31) || s.next_id + n >= ((int64_t)1 << 31))
@@ -682,13 +753,38 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     }
     std::vector<int32_t> ids(n);
     std::iota(ids.begin(), ids.end(), (int32_t)s.next_id);
-    QH_HIP(c, hipMemcpyAsync(s.tet + n0, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    if (tet) QH_HIP(c, hipMemcpyAsync(s.tet + n0, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    else if ((rc = locate_species(c, s, n0, n))) return rc;  // s.n is still n0: nothing was added
     QH_HIP(c, hipMemcpyAsync(s.id + n0, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     s.next_id += n;
     s.n = n1;
     QH_HIP(c, launch_own_extend(c, s, (int32_t)qh_species_blocks(n0), (int32_t)qh_species_blocks(n1)));
     QH_HIP(c, launch_charge_deposit(c, s, n0));
     return sync(c);
+}
+
+int qh_locate(qh_ctx *c, int64_t n, const double *xyz, int32_t *tet) {
+    if (!c || n < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (n == 0) return QH_OK;
+    if (!xyz || !tet) return QH_EINVAL;
+    std::vector<float> comp(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(xyz[3 * i + d])) return qh_fail(c, QH_EINVAL, "non-finite point " + std::to_string(i));
+            comp[d * n + i] = (float)xyz[3 * i + d];
+        }
+    float *dx = nullptr;
+    int32_t *dt = nullptr;
+    int rc;
+    if ((rc = qh_alloc(c, &dx, 3 * n)) || (rc = qh_alloc(c, &dt, n))) return rc;
+    QH_HIP(c, hipMemcpyAsync(dx, comp.data(), sizeof(float) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, launch_locate(c, n, dx, dx + n, dx + 2 * n, dt));
+    QH_HIP(c, hipMemcpyAsync(tet, dt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    qh_release(c, dx), qh_release(c, dt);
+    return QH_OK;
 }
 
 int qh_probe_fields(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B) {

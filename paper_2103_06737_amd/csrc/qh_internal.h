@@ -208,6 +208,10 @@ struct qh_ctx {
     CgWork cgx;                 // standalone solves (qh_field_solve)
     double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
     double *dec_e = nullptr;      // interior edge values of E_s (qh_fields_decompose)
+    // point location: a uniform grid of buckets over the bounding box, a seed tet per bucket
+    int32_t *loc_seed = nullptr;
+    float loc_lo[3] = {0, 0, 0}, loc_inv[3] = {0, 0, 0};
+    int32_t loc_n[3] = {0, 0, 0};
     unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS slots (crossings, wall hits,
                                              // lost), then continuity and D b violations
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
@@ -284,6 +288,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture);
 hipError_t launch_charge_deposit(qh_ctx *c, Species &s, int64_t first = 0);
 hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1);
 hipError_t launch_probe(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B);
+hipError_t launch_locate(qh_ctx *c, int64_t n, const float *x, const float *y, const float *z, int32_t *tet);
 int qh_sort_species(qh_ctx *c, Species &s);
 int64_t qh_species_blocks(int64_t n);
 hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet,

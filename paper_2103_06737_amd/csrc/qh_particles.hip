@@ -767,6 +767,86 @@ __global__ void k_probe(const float4 *__restrict__ geo, const float4 *__restrict
     B[3 * i + 2] = F2.x;
 }
 
+// Point location: from the seed tet of the point's bucket, the straight segment from that tet's
+// centroid to the point is walked face by face in the push's FP32 barycentrics, so the tet found
+// is the one the push sees. A point on a wall up to rounding (its barycentric for the wall face
+// above -kOnWall) belongs to the tet behind it. -1 when the segment leaves the mesh through a
+// wall (the point is outside, or the domain is not convex along the segment) or crosses more
+// than kLocateSteps tets.
+constexpr int kLocateSteps = 4096;
+constexpr float kOnWall = 1e-5f;
+__global__ void __launch_bounds__(256) k_locate(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+                                                const float *__restrict__ z, const float4 *__restrict__ geo,
+                                                const int4 *__restrict__ tnbr, const int4 *__restrict__ tnodes,
+                                                const int32_t *__restrict__ seed, float lx, float ly, float lz,
+                                                float ix, float iy, float iz, int nx, int ny, int nz,
+                                                int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float qx = x[i], qy = y[i], qz = z[i];
+    const int bx = min(max((int)((qx - lx) * ix), 0), nx - 1);
+    const int by = min(max((int)((qy - ly) * iy), 0), ny - 1);
+    const int bz = min(max((int)((qz - lz) * iz), 0), nz - 1);
+    int t = seed[(bz * ny + by) * nx + bx];
+    float4 A = geo[3 * t], B = geo[3 * t + 1], C = geo[3 * t + 2];
+    int4 on = tnodes[t], nb4 = tnbr[t];
+    float px = A.w, py = B.w, pz = C.w;  // the centroid (barycentrics 1/4)
+    float rx = qx - px, ry = qy - py, rz = qz - pz;
+    int entry = -1;
+    for (int step = 0; step < kLocateSteps; ++step) {
+        float l[4], gl[4];
+        lam4(A, B, C, px, py, pz, l);
+        gl[1] = A.x * rx + A.y * ry + A.z * rz;
+        gl[2] = B.x * rx + B.y * ry + B.z * rz;
+        gl[3] = C.x * rx + C.y * ry + C.z * rz;
+        gl[0] = -(gl[1] + gl[2] + gl[3]);
+        int k = -1;
+        float smin = 2.0f, lek = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r == entry) continue;
+            const float le = l[r] + gl[r];
+            if (!(le < 0.0f)) continue;
+            const float s = l[r] <= 0.0f ? 0.0f : l[r] / (l[r] - le);
+            if (s < smin) { smin = s; k = r; lek = le; }
+        }
+        if (k < 0) {
+            out[i] = t;
+            return;
+        }
+        px = __fmaf_rn(smin, rx, px); py = __fmaf_rn(smin, ry, py); pz = __fmaf_rn(smin, rz, pz);
+        const float rem = 1.0f - smin;
+        rx *= rem; ry *= rem; rz *= rem;
+        const int nb = k == 0 ? nb4.x : k == 1 ? nb4.y : k == 2 ? nb4.z : nb4.w;
+        if (nb < 0) {
+            out[i] = lek > -kOnWall ? t : -1;
+            return;
+        }
+        const int4 nn = tnodes[nb];
+        const int ov[4] = {on.x, on.y, on.z, on.w}, nv[4] = {nn.x, nn.y, nn.z, nn.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            bool found = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) found |= ov[r] == nv[j];
+            if (!found) entry = j;
+        }
+        t = nb;
+        A = geo[3 * nb]; B = geo[3 * nb + 1]; C = geo[3 * nb + 2];
+        on = nn;
+        nb4 = tnbr[nb];
+    }
+    out[i] = -1;
+}
+
+hipError_t launch_locate(qh_ctx *c, int64_t n, const float *x, const float *y, const float *z, int32_t *tet) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_locate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, x, y, z, c->geo,
+                       c->tnbr, c->tnodes, c->loc_seed, c->loc_lo[0], c->loc_lo[1], c->loc_lo[2], c->loc_inv[0],
+                       c->loc_inv[1], c->loc_inv[2], c->loc_n[0], c->loc_n[1], c->loc_n[2], tet);
+    return hipGetLastError();
+}
+
 hipError_t launch_probe(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_probe, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->geo, c->frec, n, xyz,

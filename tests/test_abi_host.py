@@ -56,7 +56,7 @@ def test_host_particle_and_wall_calls_validate():
     assert ei.value.code == qh.QH_EINVAL
     x, v, t = qi.beam_injection(m, 4, 0.008, 5e7)
     for call in (lambda: ctx.particles_inject(sid, x, v, t), lambda: ctx.probe_fields(x, t),
-                 lambda: ctx.particles_ids(sid)):
+                 lambda: ctx.particles_ids(sid), lambda: ctx.locate(x.astype(np.float64))):
         with pytest.raises(qh.QhError) as ei:
             call()
         assert ei.value.code == qh.QH_ESTATE

@@ -77,6 +77,16 @@ def test_plasma64_full_cycle(plasma64):
     assert np.array_equal(Q_re, Q1)
     assert (seg["lam0"].sum(1) == S).all() and (seg["lam1"].sum(1) == S).all()
 
+    # device point location of a million of the particles' start points: the generator's tet but
+    # for points on a face up to the FP32 rounding of barycentrics (|grad lambda| up to 110/m
+    # times a coordinate spacing of 6e-8 m near 1 m: 7e-6), which may get the neighbour
+    tl = ctx.locate(x[:1_000_000].astype(np.float64))
+    assert (tl >= 0).all()
+    mism = np.flatnonzero(tl != tet[:1_000_000])
+    assert mism.size < 1000
+    lm = np.einsum("pij,pj->pi", op.Minv[tl[mism]], np.column_stack([np.ones(mism.size), x[mism].astype(np.float64)]))
+    assert lm.min() > -1e-5
+
     # sampled particles pushed one by one by the oracle through the same start fields
     idx = np.random.default_rng(7).choice(n, 4096, replace=False)
     orc = po.push(e0, b0 * U_B, x[idx], v[idx], tet[idx], -qi.QE / qi.ME, dt, -1)

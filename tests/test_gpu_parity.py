@@ -373,6 +373,42 @@ def test_fields_decompose_matches_oracle(jitter4, bc):
     assert st["iters"] > 0
 
 
+def test_locate_and_upload_without_tets(jitter4):
+    """Point location on the device: every point inside gets a tet holding it (FP64 barycentrics
+    of the point in it >= -1e-6; the tet of the brute-force search wherever that one is not
+    within 1e-5 of a face); points outside get -1; an upload without tets locates the particles
+    and the step that follows keeps continuity."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    ctx = gpu_context(mesh, 1e-11)
+    ctx.fields_upload(e, b)
+    rng = np.random.default_rng(21)
+    pts = rng.random((5000, 3))
+    t = ctx.locate(pts)
+    lam = np.einsum("tij,pj->pti", op.Minv, np.column_stack([np.ones(len(pts)), pts]))
+    ref = np.argmax(lam.min(axis=2), axis=1)
+    clear = lam.min(axis=2)[np.arange(len(pts)), ref] > 1e-5
+    assert (t >= 0).all()
+    own = lam[np.arange(len(pts)), t].min(axis=1)
+    assert own.min() > -1e-6
+    assert (t[clear] == ref[clear]).all()
+    outside = pts + np.array([1.5, 0.0, 0.0])
+    assert (ctx.locate(outside[:100]) == -1).all()
+    x, v, tet = parts["e"]
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    ctx.particles_upload(sid, x, v)
+    _, _, tg = ctx.particles_download(sid)
+    lam_p = np.einsum("pij,pj->pi", op.Minv[tg], np.column_stack([np.ones(len(x)), x.astype(np.float64)]))
+    assert lam_p.min() > -1e-6 and (tg == tet).mean() > 0.99
+    st = ctx.pic_step(ctx.step_params(verify=1))[0]
+    assert st["continuity_bad"] == 0 and st["lost"] == 0
+    bad = x.copy()
+    bad[7] = [2.0, 0.5, 0.5]
+    with pytest.raises(qh.QhError) as ei:
+        ctx.particles_upload(sid, bad, v)
+    assert ei.value.code == qh.QH_EINVAL and ctx.particles_count(sid) == 0
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
