@@ -75,6 +75,11 @@ typedef struct {
     int64_t nnz_factor, nnz_factor_c16; /* entries of the learned factor G (lower triangle of the
                                          edge pattern) and of G and G^T together read with 16-bit
                                          columns; 0 until the learned preconditioner is built */
+    double dt_cfl; /* explicit (leap-frog) stability bound 2 / sqrt(lambda), lambda the largest
+                      element eigenvalue of S_T against [*eps]_T: at most the true explicit limit
+                      2 / sqrt(lambda_max([*eps]^-1 S)) (the assembled eigenvalue never exceeds the
+                      element ones), with the context's eps0, mu0 (vacuum before qh_set_physics);
+                      computed on the first call (one pass over the tets on the host) */
 } qh_mesh_info_t;
 
 typedef struct {

@@ -48,7 +48,7 @@ class MeshInfo(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_edges", C.c_int64), ("n_faces", C.c_int64),
                 ("n_tets", C.c_int64), ("n_int_nodes", C.c_int64), ("n_int_edges", C.c_int64),
                 ("nnz_edge", C.c_int64), ("nnz_node", C.c_int64), ("nnz_edge_c16", C.c_int64),
-                ("nnz_factor", C.c_int64), ("nnz_factor_c16", C.c_int64)]
+                ("nnz_factor", C.c_int64), ("nnz_factor_c16", C.c_int64), ("dt_cfl", C.c_double)]
 
 
 class Phys(C.Structure):

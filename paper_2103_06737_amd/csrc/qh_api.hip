@@ -483,6 +483,10 @@ int qh_mesh_info(const qh_ctx *c, qh_mesh_info_t *out) {
     out->nnz_edge_c16 = c->A.nnz_c16;
     out->nnz_factor = c->lp.built ? c->lp.nnz : 0;
     out->nnz_factor_c16 = c->lp.built ? c->lp.nnz_c16 : 0;
+    qh_ctx *mc = const_cast<qh_ctx *>(c);
+    if (mc->cfl_lambda < 0.0) mc->cfl_lambda = qh_cfl_lambda_geo(m);
+    const double eps0 = c->have_phys ? c->phys.eps0 : 8.8541878128e-12, mu0 = c->have_phys ? c->phys.mu0 : 1.25663706212e-6;
+    out->dt_cfl = mc->cfl_lambda > 0.0 ? 2.0 * std::sqrt(eps0 * mu0 / mc->cfl_lambda) : 0.0;
     return QH_OK;
 }
 

@@ -56,6 +56,8 @@ std::string qh_build_mesh(HostMesh &m, int64_t n_nodes, const double *xyz, int64
 // Assemble: A pattern with val=[*eps], val2=S (interior edges); CMb = C^T [*mu^-1]
 // (interior edges x all faces); GtM = G^T [*eps] (interior nodes x interior edges);
 // K = G^T [*eps] G (interior nodes).
+// Upper bound of lambda_max([*eps]^-1 S) for eps = mu = 1 (element eigenvalue bound).
+double qh_cfl_lambda_geo(const HostMesh &m);
 void qh_assemble(const HostMesh &m, double eps0, double mu0, HostCsr &A, HostCsr &CMb,
                  HostCsr &GtM, HostCsr &K);
 
@@ -208,6 +210,7 @@ struct qh_ctx {
     CgWork cgx;                 // standalone solves (qh_field_solve)
     double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
     double *dec_e = nullptr;      // interior edge values of E_s (qh_fields_decompose)
+    double cfl_lambda = -1.0;     // qh_cfl_lambda_geo of the mesh (computed on first request)
     // point location: a uniform grid of buckets over the bounding box, a seed tet per bucket
     int32_t *loc_seed = nullptr;
     float loc_lo[3] = {0, 0, 0}, loc_inv[3] = {0, 0, 0};

@@ -291,6 +291,71 @@ void assemble_rows(int64_t nrow, const std::vector<int32_t> &rows_global,
 
 }  // namespace
 
+// Largest element eigenvalue of [*mu^-1]-curl-curl against [*eps] with eps = mu = 1. S_T = |T|
+// C^T C with C the 3 x 6 matrix of the constant curls of W1 on the tet, so the nonzero
+// eigenvalues of M_T^-1 S_T are those of the 3 x 3 matrix |T| C M_T^-1 C^T: a Cholesky solve with
+// M_T and the largest root of a symmetric 3 x 3 characteristic polynomial (trigonometric form).
+// The assembled pair's largest eigenvalue is at most the largest element one (both element
+// matrices are positive semi-definite, M_T definite), and restricting to the interior edges
+// only lowers it.
+double qh_cfl_lambda_geo(const HostMesh &m) {
+    double lmax = 0.0;
+    for (int64_t t = 0; t < m.Nt; ++t) {
+        const double *g = &m.grad[12 * t];
+        double Mt[6][6], L[6][6] = {}, Ct[6][3];
+        for (int p = 0; p < 6; ++p) {
+            curl_w1(g, p, Ct[p]);
+            for (int q = 0; q < 6; ++q) Mt[p][q] = meps_local(g, m.vol[t], 1.0, p, q);
+        }
+        for (int i = 0; i < 6; ++i)  // Cholesky M_T = L L^T
+            for (int j = 0; j <= i; ++j) {
+                double s = Mt[i][j];
+                for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+                L[i][j] = i == j ? std::sqrt(std::max(s, 1e-300)) : s / L[j][j];
+            }
+        double X[6][3];  // X = M_T^-1 C^T
+        for (int c = 0; c < 3; ++c) {
+            double y[6];
+            for (int i = 0; i < 6; ++i) {
+                double s = Ct[i][c];
+                for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+                y[i] = s / L[i][i];
+            }
+            for (int i = 5; i >= 0; --i) {
+                double s = y[i];
+                for (int k = i + 1; k < 6; ++k) s -= L[k][i] * X[k][c];
+                X[i][c] = s / L[i][i];
+            }
+        }
+        double B[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int i = 0; i < 6; ++i) s += Ct[i][a] * X[i][b];
+                B[a][b] = m.vol[t] * s;
+            }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < a; ++b) B[a][b] = B[b][a] = 0.5 * (B[a][b] + B[b][a]);
+        const double p1 = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[1][2] * B[1][2];
+        const double q = (B[0][0] + B[1][1] + B[2][2]) / 3.0;
+        const double p2 = (B[0][0] - q) * (B[0][0] - q) + (B[1][1] - q) * (B[1][1] - q) + (B[2][2] - q) * (B[2][2] - q) + 2.0 * p1;
+        double lam = q;
+        if (p2 > 0.0) {
+            const double p = std::sqrt(p2 / 6.0);
+            double D[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) D[a][b] = (B[a][b] - (a == b ? q : 0.0)) / p;
+            const double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
+                               D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                               D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+            const double r = std::min(1.0, std::max(-1.0, 0.5 * det));
+            lam = q + 2.0 * p * std::cos(std::acos(r) / 3.0);
+        }
+        lmax = std::max(lmax, lam);
+    }
+    return lmax;
+}
+
 void qh_assemble(const HostMesh &m, double eps0, double mu0, HostCsr &A, HostCsr &CMb, HostCsr &GtM,
                  HostCsr &K) {
     const double *G = m.grad.data();

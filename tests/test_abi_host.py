@@ -116,3 +116,24 @@ def test_host_topology_and_matrices_match_oracle(cfg):
         assert abs(M - R).max() <= 1e-13 * abs(R).max(), w
     info = ctx.mesh_info()
     assert info.nnz_edge == ctx.matrix(0).nnz and info.nnz_node == ctx.matrix(5).nnz
+
+
+@pytest.mark.parametrize("name", ["jitter4", "box8", "cylinder"])
+def test_host_cfl_bound_below_the_explicit_limit(name):
+    """mesh_info's dt_cfl (element eigenvalue bound, host C++) never exceeds the oracle's explicit
+    limit 2 / sqrt(lambda_max([*eps]^-1 S)) and stays within a factor of two of it; it scales
+    as sqrt(eps mu)."""
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    from oracle.field import dt_cfl
+    from oracle.whitney import Operators
+    m = {"jitter4": lambda: qi.make_mesh(qi.CONFIGS["jitter4"]), "box8": lambda: qi.BoxMesh(8),
+         "cylinder": lambda: qi.CylinderMesh(0.02, 0.1, 4, 6)}[name]()
+    ctx = qh.Context(-1)
+    ctx.mesh_upload(m.xyz, m.tets)
+    bound = ctx.mesh_info().dt_cfl
+    cx = Complex(m.xyz, m.tets)
+    exact = dt_cfl(Operators(cx, qi.EPS0, qi.MU0), cx, tol=1e-12)
+    assert 0.5 * exact < bound <= exact * (1 + 1e-9), (bound, exact)
+    ctx.set_physics(4 * qi.EPS0, qi.MU0, 1e-12, 1.0, 2.0 ** -56)
+    assert abs(ctx.mesh_info().dt_cfl / (2 * bound) - 1) < 1e-12
