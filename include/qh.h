@@ -302,6 +302,13 @@ int qh_field_solve(qh_ctx *ctx, int32_t system, const double *rhs, double *x, do
 #define QH_MLP_NPARAM 5313
 int qh_precond_set_weights(qh_ctx *ctx, const float *w, int64_t n);
 int qh_precond_get_weights(qh_ctx *ctx, float *w, int64_t n);
+/* The network as a self-describing byte blob (magic "QHPRECND", version 1, parameter count, the
+ * FP32 weights, an FNV-1a checksum of them), to keep a trained preconditioner across runs and
+ * meshes. save: buf NULL sets *len to the size needed; a smaller *len is QH_EINVAL. load:
+ * QH_EINVAL for a blob that is short, of another version or size, or fails its checksum (the
+ * present weights are then kept). */
+int qh_precond_save(qh_ctx *ctx, void *buf, size_t *len);
+int qh_precond_load(qh_ctx *ctx, const void *buf, size_t len);
 /* Entries of G: rows/cols (interior-edge indices, row-major lower triangle of A's pattern) and
  * FP32 values for the current weights. Pass rows = cols = vals = NULL to query *nnz. */
 int qh_precond_factor(qh_ctx *ctx, int64_t *nnz, int32_t *rows, int32_t *cols, float *vals);

@@ -1231,6 +1231,55 @@ int qh_precond_get_weights(qh_ctx *c, float *w, int64_t n) {
     return sync(c);
 }
 
+namespace {
+constexpr char kBlobMagic[8] = {'Q', 'H', 'P', 'R', 'E', 'C', 'N', 'D'};
+constexpr uint32_t kBlobVersion = 1;
+constexpr size_t kBlobSize = 8 + 4 + 4 + 4 * (size_t)QH_MLP_NPARAM + 4;
+uint32_t fnv1a(const unsigned char *p, size_t n) {
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 16777619u;
+    return h;
+}
+}  // namespace
+
+int qh_precond_save(qh_ctx *c, void *buf, size_t *len) {
+    if (!c || !len) return QH_EINVAL;
+    if (!buf) {
+        *len = kBlobSize;
+        return QH_OK;
+    }
+    if (*len < kBlobSize) return qh_fail(c, QH_EINVAL, "blob buffer smaller than the size qh_precond_save(NULL) gives");
+    std::vector<float> w(QH_MLP_NPARAM);
+    int rc = qh_precond_get_weights(c, w.data(), QH_MLP_NPARAM);
+    if (rc) return rc;
+    unsigned char *p = static_cast<unsigned char *>(buf);
+    const uint32_t n = QH_MLP_NPARAM;
+    std::memcpy(p, kBlobMagic, 8);
+    std::memcpy(p + 8, &kBlobVersion, 4);
+    std::memcpy(p + 12, &n, 4);
+    std::memcpy(p + 16, w.data(), 4 * (size_t)n);
+    const uint32_t h = fnv1a(p + 16, 4 * (size_t)n);
+    std::memcpy(p + 16 + 4 * (size_t)n, &h, 4);
+    *len = kBlobSize;
+    return QH_OK;
+}
+
+int qh_precond_load(qh_ctx *c, const void *buf, size_t len) {
+    if (!c || !buf) return QH_EINVAL;
+    const unsigned char *p = static_cast<const unsigned char *>(buf);
+    uint32_t version = 0, n = 0, h = 0;
+    if (len < 16) return qh_fail(c, QH_EINVAL, "preconditioner blob too short");
+    std::memcpy(&version, p + 8, 4);
+    std::memcpy(&n, p + 12, 4);
+    if (std::memcmp(p, kBlobMagic, 8) != 0 || version != kBlobVersion || n != QH_MLP_NPARAM || len < kBlobSize)
+        return qh_fail(c, QH_EINVAL, "not a preconditioner blob of this version and size");
+    std::memcpy(&h, p + 16 + 4 * (size_t)n, 4);
+    if (h != fnv1a(p + 16, 4 * (size_t)n)) return qh_fail(c, QH_EINVAL, "preconditioner blob fails its checksum");
+    std::vector<float> w(n);
+    std::memcpy(w.data(), p + 16, 4 * (size_t)n);
+    return qh_precond_set_weights(c, w.data(), n);
+}
+
 int qh_precond_factor(qh_ctx *c, int64_t *nnz, int32_t *rows, int32_t *cols, float *vals) {
     if (!c || !nnz) return QH_EINVAL;
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");

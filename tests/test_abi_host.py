@@ -61,6 +61,13 @@ def test_host_particle_and_wall_calls_validate():
             call()
         assert ei.value.code == qh.QH_ESTATE
     assert ctx.particles_count(sid) == 0
+    # preconditioner blobs are checked before any device work
+    with pytest.raises(qh.QhError) as ei:
+        ctx.precond_load(b"QHPRECND" + bytes(40))
+    assert ei.value.code == qh.QH_EINVAL
+    with pytest.raises(qh.QhError) as ei:
+        ctx.precond_save()
+    assert ei.value.code == qh.QH_ESTATE
 
 
 def test_host_rejects_bad_meshes():

@@ -153,3 +153,37 @@ def test_full_cycle_with_learned_preconditioner(prob):
             assert st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8 and st["fallbacks"] == 0
     e, b = ctx.fields_download()
     assert not (cx.D @ b).any()
+
+
+def test_save_and_load_keep_the_preconditioner(prob):
+    """A trained network saved as a blob and loaded into a fresh context (the same mesh, and a
+    jittered one: the network does not depend on the mesh) gives the same factor bit for bit and
+    the same solve; a blob with a flipped byte, a short one and one of another size are refused
+    and leave the loaded network in place."""
+    import paper_2103_06737_amd as qh
+    mesh, A, rows, cols, f = prob
+    ctx = gpu_context(mesh, DT)
+    ctx.precond_train(steps=40, lr=3e-3, seed=3, validate_every=0)
+    blob = ctx.precond_save()
+    assert blob[:8] == b"QHPRECND" and len(blob) == 16 + 4 * qh.MLP_NPARAM + 4
+    _, _, v0 = ctx.precond_factor()
+    rhs = np.random.default_rng(4).standard_normal(A.shape[0])
+    _, s0 = ctx.field_solve(qh.SYS_EDGE, rhs, tol=1e-8, precond=qh.PC_LEARNED)
+    ctx2 = gpu_context(mesh, DT)
+    ctx2.precond_load(blob)
+    _, _, v1 = ctx2.precond_factor()
+    assert np.array_equal(v0, v1)
+    _, s1 = ctx2.field_solve(qh.SYS_EDGE, rhs, tol=1e-8, precond=qh.PC_LEARNED)
+    assert s1["iters"] == s0["iters"]
+    bad = bytearray(blob)
+    bad[100] ^= 1
+    for wrong in (bytes(bad), blob[:-10], blob[:12]):
+        with pytest.raises(qh.QhError) as ei:
+            ctx2.precond_load(wrong)
+        assert ei.value.code == qh.QH_EINVAL
+    _, _, v2 = ctx2.precond_factor()
+    assert np.array_equal(v0, v2)
+    jm = qi.make_mesh(qi.CONFIGS["jitter4"])
+    ctx3 = gpu_context(jm, 1e-11)
+    ctx3.precond_load(blob)
+    assert np.array_equal(ctx3.precond_get_weights(), ctx.precond_get_weights())
