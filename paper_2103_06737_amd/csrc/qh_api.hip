@@ -709,42 +709,36 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles (and ids) per species");
     int rc;
     if (n1 > s.cap) {
-        // grow: new arrays, the present particles copied over, the old arrays released
+        // grow: every new array first (a failed allocation leaves the species as it was), then
+        // the present particles copied over and the old arrays released
         const int64_t cap = std::max<int64_t>(std::max<int64_t>(2 * s.cap, n1), 4096);
-        QH_HIP(c, hipStreamSynchronize(c->stream));
-        float **fs[6] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz};
-        float **fscr[6] = {&s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
-        int32_t **is[2] = {&s.tet, &s.id};
-        int32_t **iscr[2] = {&s.stet, &s.sid};
-        for (int k = 0; k < 6; ++k) {
-            float *p;
-            if ((rc = qh_alloc(c, &p, cap))) return rc;
-            if (n0) QH_HIP(c, hipMemcpyAsync(p, *fs[k], sizeof(float) * n0, hipMemcpyDeviceToDevice, c->stream));
-            QH_HIP(c, hipStreamSynchronize(c->stream));
-            qh_release(c, *fs[k]);
-            *fs[k] = p;
-            qh_release(c, *fscr[k]);
-            if ((rc = qh_alloc(c, fscr[k], cap))) return rc;
-        }
-        for (int k = 0; k < 2; ++k) {
-            int32_t *p;
-            if ((rc = qh_alloc(c, &p, cap))) return rc;
-            if (n0) QH_HIP(c, hipMemcpyAsync(p, *is[k], sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, c->stream));
-            QH_HIP(c, hipStreamSynchronize(c->stream));
-            qh_release(c, *is[k]);
-            *is[k] = p;
-            qh_release(c, *iscr[k]);
-            if ((rc = qh_alloc(c, iscr[k], cap))) return rc;
-        }
-        int32_t *own;
+        float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
+        int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
+        float *nf[12] = {};
+        int32_t *ni[4] = {}, *nown = nullptr;
+        uint16_t *novf = nullptr;
+        auto drop_new = [&]() {
+            for (auto &p : nf) qh_release(c, p);
+            for (auto &p : ni) qh_release(c, p);
+            qh_release(c, nown), qh_release(c, novf);
+        };
+        for (auto &p : nf)
+            if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
+        for (auto &p : ni)
+            if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
+        if ((rc = qh_alloc(c, &nown, qh_species_blocks(cap) + 1)) || (rc = qh_alloc(c, &novf, qh_species_blocks(cap) * QH_CHUNK)))
+            return drop_new(), rc;
         const int64_t nb0 = qh_species_blocks(n0);
-        if ((rc = qh_alloc(c, &own, qh_species_blocks(cap) + 1))) return rc;
-        if (s.own) QH_HIP(c, hipMemcpyAsync(own, s.own, sizeof(int32_t) * (nb0 + 1), hipMemcpyDeviceToDevice, c->stream));
+        for (int k = 0; k < 6; ++k)  // the particle state; the sort scratch needs no copy
+            if (n0) QH_HIP(c, hipMemcpyAsync(nf[k], *fs[k], sizeof(float) * n0, hipMemcpyDeviceToDevice, c->stream));
+        for (int k = 0; k < 2; ++k)
+            if (n0) QH_HIP(c, hipMemcpyAsync(ni[k], *is[k], sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, c->stream));
+        if (s.own) QH_HIP(c, hipMemcpyAsync(nown, s.own, sizeof(int32_t) * (nb0 + 1), hipMemcpyDeviceToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
-        qh_release(c, s.own);
-        s.own = own;
-        qh_release(c, s.ovf);
-        if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(cap) * QH_CHUNK))) return rc;
+        for (int k = 0; k < 12; ++k) qh_release(c, *fs[k]), *fs[k] = nf[k];
+        for (int k = 0; k < 4; ++k) qh_release(c, *is[k]), *is[k] = ni[k];
+        qh_release(c, s.own), s.own = nown;
+        qh_release(c, s.ovf), s.ovf = novf;
         s.cap = cap;
     }
     // components laid out one after another; the host buffers live until the sync at the end
