@@ -178,6 +178,13 @@ int qh_set_physics(qh_ctx *ctx, const qh_phys_t *phys);
  * (QH_EINVAL otherwise): B then is constant inside each tet. */
 int qh_fields_upload(qh_ctx *ctx, const double *e, const int64_t *b);
 int qh_fields_download(const qh_ctx *ctx, double *e, int64_t *b);
+/* Device-pointer variants (for instance torch tensors' data_ptr()): the same arrays in device
+ * memory, copied on the context's stream and ordered with its other work (no host sync, except
+ * the upload's D b check, which reads one count back). The caller keeps ownership and keeps the
+ * buffers alive until the stream has passed the copy. qh_fields_upload_dev: QH_EINVAL if D b != 0
+ * (the fields are then unchanged); on PEC walls e is taken as 0. */
+int qh_fields_upload_dev(qh_ctx *ctx, const double *e_dev, const int64_t *b_dev);
+int qh_fields_download_dev(qh_ctx *ctx, double *e_dev, int64_t *b_dev);
 /* Synthetic initial fields from caller-drawn standard normals (white_e, white_a: Ne each):
  * e = l_e sigma_e w_e on interior edges; a = line integral of (0, bz x, 0) plus
  * sigma_b l_e^2 / (2 sqrt 3) w'_e, rounded to units of u_b; b = C a. */
@@ -251,6 +258,7 @@ int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
 /* Deposits of the last step: g (Ne) path-integrated current, Q (Nn) node charge,
  * both int64 in units of u_q. Either may be NULL. */
 int qh_deposits_download(const qh_ctx *ctx, int64_t *g, int64_t *Q);
+int qh_deposits_download_dev(qh_ctx *ctx, int64_t *g_dev, int64_t *q_dev);  /* device pointers, as above */
 /* Right-hand side of the last step's edge system (n_int_edges) and its solution e* as solved
  * to tol_edge, before the Gauss-law correction. Either may be NULL. These are the (rhs,
  * solution) pairs of the plain solver used to validate the learned preconditioner. */

@@ -35,7 +35,8 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_precond_set_weights", "qh_precond_get_weights", "qh_precond_factor", "qh_precond_loss_grad",
            "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
-           "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load"]
+           "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
+           "qh_fields_download_dev", "qh_deposits_download_dev"]
 
 
 class QhError(RuntimeError):
@@ -126,6 +127,9 @@ def lib():
             "qh_probe_fields": [p, i64, p, p, p, p],
             "qh_fields_decompose": [p, d, i32, p, p, p, C.POINTER(SolveStats)],
             "qh_locate": [p, i64, p, p],
+            "qh_fields_upload_dev": [p, p, p],
+            "qh_fields_download_dev": [p, p, p],
+            "qh_deposits_download_dev": [p, p, p],
             "qh_precond_save": [p, p, C.POINTER(C.c_size_t)],
             "qh_precond_load": [p, p, C.c_size_t],
             "qh_charge_background": [p, i32],
@@ -279,6 +283,18 @@ class Context:
         v = _c(v, np.float32)
         tet = None if tet is None else _c(tet, np.int32)
         self._check(self.L.qh_particles_inject(self.h, sid, x.shape[0], _ptr(x), _ptr(v), _ptr(tet)))
+
+    # device pointers (e.g. torch tensors' data_ptr()), ordered on the context's stream
+    def fields_upload_dev(self, e_ptr, b_ptr):
+        self._check(self.L.qh_fields_upload_dev(self.h, C.c_void_p(e_ptr), C.c_void_p(b_ptr)))
+
+    def fields_download_dev(self, e_ptr, b_ptr):
+        self._check(self.L.qh_fields_download_dev(self.h, C.c_void_p(e_ptr) if e_ptr else None,
+                                                  C.c_void_p(b_ptr) if b_ptr else None))
+
+    def deposits_download_dev(self, g_ptr, q_ptr):
+        self._check(self.L.qh_deposits_download_dev(self.h, C.c_void_p(g_ptr) if g_ptr else None,
+                                                    C.c_void_p(q_ptr) if q_ptr else None))
 
     def locate(self, xyz):
         """Tet holding each point (-1 outside the mesh), found on the device."""

@@ -879,6 +879,47 @@ int qh_edge_system_download(const qh_ctx *cc, double *rhs, double *sol) {
     return sync(c);
 }
 
+int qh_fields_download_dev(qh_ctx *c, double *e, int64_t *b) {
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (e) QH_HIP(c, hipMemcpyAsync(e, c->e, sizeof(double) * c->hm.Ne, hipMemcpyDeviceToDevice, c->stream));
+    if (b) QH_HIP(c, hipMemcpyAsync(b, c->b, sizeof(int64_t) * c->hm.Nf, hipMemcpyDeviceToDevice, c->stream));
+    return QH_OK;
+}
+
+int qh_deposits_download_dev(qh_ctx *c, int64_t *g, int64_t *Q) {
+    if (!c) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (g) QH_HIP(c, hipMemcpyAsync(g, c->g, sizeof(int64_t) * c->hm.Ne, hipMemcpyDeviceToDevice, c->stream));
+    if (Q) QH_HIP(c, hipMemcpyAsync(Q, c->Q, sizeof(int64_t) * c->hm.Nn, hipMemcpyDeviceToDevice, c->stream));
+    return QH_OK;
+}
+
+int qh_fields_upload_dev(qh_ctx *c, const double *e, const int64_t *b) {
+    if (!c || !e || !b) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    const HostMesh &m = c->hm;
+    // D b = 0 checked on the device before anything changes
+    unsigned long long *bad = c->counters + 4 * QH_COUNTER_SLOTS + 1, nbad = 0;
+    QH_HIP(c, hipMemsetAsync(c->divb0, 0, sizeof(int64_t) * m.Nt, c->stream));
+    QH_HIP(c, hipMemsetAsync(bad, 0, sizeof(unsigned long long), c->stream));
+    QH_HIP(c, launch_divb_check(c, b, bad));
+    QH_HIP(c, hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    if (nbad) return qh_fail(c, QH_EINVAL, "D b != 0 in " + std::to_string(nbad) + " tets");
+    QH_HIP(c, hipMemsetAsync(c->e, 0, sizeof(double) * m.Ne, c->stream));  // PEC wall edges stay 0
+    QH_HIP(c, launch_fields_in(c, e, c->assembled ? c->cge.x : nullptr));
+    QH_HIP(c, hipMemcpyAsync(c->b, b, sizeof(int64_t) * m.Nf, hipMemcpyDeviceToDevice, c->stream));
+    c->have_fields = true;
+    c->fields_dirty = true;
+    c->wave_hist = false;
+    if (c->dbnd) QH_HIP(c, hipMemsetAsync(c->dbnd, 0, sizeof(double) * m.Nn, c->stream));
+    return QH_OK;
+}
+
 int qh_deposits_download(const qh_ctx *cc, int64_t *g, int64_t *Q) {
     qh_ctx *c = const_cast<qh_ctx *>(cc);
     if (!c) return QH_EINVAL;

@@ -300,6 +300,8 @@ hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet
                                 const int32_t *pz, int64_t *g, int64_t *Q);
 hipError_t launch_verify(qh_ctx *c, bool check_divb);
 hipError_t launch_divb(qh_ctx *c, int64_t *out);
+hipError_t launch_divb_check(qh_ctx *c, const int64_t *b, unsigned long long *bad);
+hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x);
 
 // qh_solver.hip
 struct SolveResult {

@@ -936,6 +936,32 @@ hipError_t launch_verify(qh_ctx *c, bool check_divb) {
     return hipGetLastError();
 }
 
+// Tets where D b != 0 for a caller's device flux vector, counted into *bad.
+hipError_t launch_divb_check(qh_ctx *c, const int64_t *b, unsigned long long *bad) {
+    int32_t nt = (int32_t)c->hm.Nt;
+    hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, b, nt,
+                       (int64_t *)nullptr, (const int64_t *)c->divb0, bad);
+    return hipGetLastError();
+}
+
+// e_out <- e_in on the interior edges, 0 elsewhere (PEC walls); x[i] <- e_in[int_edges[i]]
+__global__ void k_fields_in(int32_t n_int, const int32_t *__restrict__ int_edges, const double *__restrict__ e_in,
+                            double *__restrict__ e_out, double *__restrict__ x) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    const int32_t g = int_edges[i];
+    const double v = e_in[g];
+    e_out[g] = v;
+    if (x) x[i] = v;
+}
+
+hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x) {
+    const int32_t n = (int32_t)c->hm.int_edges.size();
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fields_in, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->int_edges, e_in, c->e, x);
+    return hipGetLastError();
+}
+
 hipError_t launch_divb(qh_ctx *c, int64_t *out) {
     int32_t nt = (int32_t)c->hm.Nt;
     hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,

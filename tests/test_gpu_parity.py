@@ -409,6 +409,62 @@ def test_locate_and_upload_without_tets(jitter4):
     assert ei.value.code == qh.QH_EINVAL and ctx.particles_count(sid) == 0
 
 
+def test_device_pointer_transfers(jitter4):
+    """Fields and deposits through device pointers (torch tensors on the context's stream): the
+    downloads equal the host ones; an upload from device memory zeroes PEC wall edges and gives
+    the same step as the host upload of the same fields; a flux vector with D b != 0 is refused
+    and leaves the fields as they were."""
+    import torch
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    stream = torch.cuda.current_stream()
+
+    def context():
+        c = qh.Context(0, stream=stream.cuda_stream)
+        c.mesh_upload(mesh.xyz, mesh.tets)
+        c.set_physics(qi.EPS0, qi.MU0, 2e-10, qi.QE * 2.0 ** -40, U_B)
+        return c
+
+    ctx = context()
+    ctx.fields_upload(e, b)
+    e_t = torch.empty(cx.Ne, dtype=torch.float64, device="cuda")
+    b_t = torch.empty(cx.Nf, dtype=torch.int64, device="cuda")
+    ctx.fields_download_dev(e_t.data_ptr(), b_t.data_ptr())
+    stream.synchronize()
+    assert np.array_equal(e_t.cpu().numpy(), e) and np.array_equal(b_t.cpu().numpy(), b)
+    e2 = 2.0 * e_t
+    wall = torch.from_numpy(cx.wall_edge).to("cuda")
+    e2[wall] = 5.0
+    ctx.fields_upload_dev(e2.data_ptr(), b_t.data_ptr())
+    expect = 2.0 * e
+    expect[cx.wall_edge] = 0.0
+    eh, bh = ctx.fields_download()
+    assert np.array_equal(eh, expect) and np.array_equal(bh, b)
+    b_bad = b_t.clone()
+    b_bad[int(np.flatnonzero(~cx.wall_face)[0])] += 1
+    with pytest.raises(qh.QhError) as ei:
+        ctx.fields_upload_dev(e_t.data_ptr(), b_bad.data_ptr())
+    assert ei.value.code == qh.QH_EINVAL
+    assert np.array_equal(ctx.fields_download()[0], expect)
+    # the step after the device upload equals the step after the host upload, bit for bit
+    x, v, tet = parts["e"]
+    ref = context()
+    ref.fields_upload(expect, b)
+    outs = []
+    for c in (ctx, ref):
+        sid = c.species_add(-qi.QE / qi.ME, -1)
+        c.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
+        c.pic_step(c.step_params(field_mode=qh.FIELDS_SOLVE, tol_edge=1e-10, tol_node=1e-10))
+        outs.append(c.fields_download() + c.deposits_download())
+    for a, r in zip(outs[0], outs[1]):
+        assert np.array_equal(a, r)
+    g_t = torch.empty(cx.Ne, dtype=torch.int64, device="cuda")
+    q_t = torch.empty(cx.Nn, dtype=torch.int64, device="cuda")
+    ctx.deposits_download_dev(g_t.data_ptr(), q_t.data_ptr())
+    stream.synchronize()
+    assert np.array_equal(g_t.cpu().numpy(), outs[0][2]) and np.array_equal(q_t.cpu().numpy(), outs[0][3])
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
