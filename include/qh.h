@@ -182,7 +182,9 @@ int qh_fields_download(const qh_ctx *ctx, double *e, int64_t *b);
  * memory, copied on the context's stream and ordered with its other work (no host sync, except
  * the upload's D b check, which reads one count back). The caller keeps ownership and keeps the
  * buffers alive until the stream has passed the copy. qh_fields_upload_dev: QH_EINVAL if D b != 0
- * (the fields are then unchanged); on PEC walls e is taken as 0. */
+ * (the fields are then unchanged); on PEC walls e is taken as 0. The buffers must come from the
+ * HIP runtime this library uses: a process that also loads PyTorch's own runtime should import
+ * torch before loading this library, so that both resolve to torch's. */
 int qh_fields_upload_dev(qh_ctx *ctx, const double *e_dev, const int64_t *b_dev);
 int qh_fields_download_dev(qh_ctx *ctx, double *e_dev, int64_t *b_dev);
 /* Synthetic initial fields from caller-drawn standard normals (white_e, white_a: Ne each):

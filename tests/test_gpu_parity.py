@@ -409,60 +409,87 @@ def test_locate_and_upload_without_tets(jitter4):
     assert ei.value.code == qh.QH_EINVAL and ctx.particles_count(sid) == 0
 
 
+class _DeviceBuffers:
+    """hipMalloc / hipMemcpy from the HIP runtime the library itself loaded (same process, same
+    runtime object), for the device-pointer entry points."""
+
+    def __init__(self):
+        import ctypes as C
+        self.C = C
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        self.hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        self.hip.hipFree.argtypes = [C.c_void_p]
+        self.ptrs = []
+
+    def alloc(self, nbytes):
+        p = self.C.c_void_p()
+        assert self.hip.hipMalloc(self.C.byref(p), nbytes) == 0
+        self.ptrs.append(p.value)
+        return p.value
+
+    def put(self, arr):
+        arr = np.ascontiguousarray(arr)
+        d = self.alloc(arr.nbytes)
+        assert self.hip.hipMemcpy(d, arr.ctypes.data, arr.nbytes, 1) == 0   # host to device
+        return d
+
+    def get(self, d, like):
+        out = np.empty_like(like)
+        assert self.hip.hipMemcpy(out.ctypes.data, d, out.nbytes, 2) == 0   # device to host
+        return out
+
+    def free(self):
+        for p in self.ptrs:
+            self.hip.hipFree(p)
+
+
 def test_device_pointer_transfers(jitter4):
-    """Fields and deposits through device pointers (torch tensors on the context's stream): the
-    downloads equal the host ones; an upload from device memory zeroes PEC wall edges and gives
-    the same step as the host upload of the same fields; a flux vector with D b != 0 is refused
-    and leaves the fields as they were."""
-    import torch
+    """Fields and deposits through device pointers (buffers of the library's own HIP runtime;
+    stream-ordered copies): the downloads equal the host ones; an upload from device memory
+    zeroes PEC wall edges and gives the same step as the host upload of the same fields; a flux
+    vector with D b != 0 is refused and leaves the fields as they were."""
     import paper_2103_06737_amd as qh
     cfg, mesh, cx, op, po, e, b, parts = jitter4
-    stream = torch.cuda.current_stream()
-
-    def context():
-        c = qh.Context(0, stream=stream.cuda_stream)
-        c.mesh_upload(mesh.xyz, mesh.tets)
-        c.set_physics(qi.EPS0, qi.MU0, 2e-10, qi.QE * 2.0 ** -40, U_B)
-        return c
-
-    ctx = context()
-    ctx.fields_upload(e, b)
-    e_t = torch.empty(cx.Ne, dtype=torch.float64, device="cuda")
-    b_t = torch.empty(cx.Nf, dtype=torch.int64, device="cuda")
-    ctx.fields_download_dev(e_t.data_ptr(), b_t.data_ptr())
-    stream.synchronize()
-    assert np.array_equal(e_t.cpu().numpy(), e) and np.array_equal(b_t.cpu().numpy(), b)
-    e2 = 2.0 * e_t
-    wall = torch.from_numpy(cx.wall_edge).to("cuda")
-    e2[wall] = 5.0
-    ctx.fields_upload_dev(e2.data_ptr(), b_t.data_ptr())
-    expect = 2.0 * e
-    expect[cx.wall_edge] = 0.0
-    eh, bh = ctx.fields_download()
-    assert np.array_equal(eh, expect) and np.array_equal(bh, b)
-    b_bad = b_t.clone()
-    b_bad[int(np.flatnonzero(~cx.wall_face)[0])] += 1
-    with pytest.raises(qh.QhError) as ei:
-        ctx.fields_upload_dev(e_t.data_ptr(), b_bad.data_ptr())
-    assert ei.value.code == qh.QH_EINVAL
-    assert np.array_equal(ctx.fields_download()[0], expect)
-    # the step after the device upload equals the step after the host upload, bit for bit
-    x, v, tet = parts["e"]
-    ref = context()
-    ref.fields_upload(expect, b)
-    outs = []
-    for c in (ctx, ref):
-        sid = c.species_add(-qi.QE / qi.ME, -1)
-        c.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
-        c.pic_step(c.step_params(field_mode=qh.FIELDS_SOLVE, tol_edge=1e-10, tol_node=1e-10))
-        outs.append(c.fields_download() + c.deposits_download())
-    for a, r in zip(outs[0], outs[1]):
-        assert np.array_equal(a, r)
-    g_t = torch.empty(cx.Ne, dtype=torch.int64, device="cuda")
-    q_t = torch.empty(cx.Nn, dtype=torch.int64, device="cuda")
-    ctx.deposits_download_dev(g_t.data_ptr(), q_t.data_ptr())
-    stream.synchronize()
-    assert np.array_equal(g_t.cpu().numpy(), outs[0][2]) and np.array_equal(q_t.cpu().numpy(), outs[0][3])
+    ctx = gpu_context(mesh, 2e-10)
+    ref = gpu_context(mesh, 2e-10)
+    dev = _DeviceBuffers()
+    try:
+        ctx.fields_upload(e, b)
+        e_d, b_d = dev.alloc(8 * cx.Ne), dev.alloc(8 * cx.Nf)
+        ctx.fields_download_dev(e_d, b_d)
+        ctx.fields_download()                      # synchronises the context's stream
+        assert np.array_equal(dev.get(e_d, e), e) and np.array_equal(dev.get(b_d, b), b)
+        e2 = 2.0 * e
+        e2[cx.wall_edge] = 5.0
+        ctx.fields_upload_dev(dev.put(e2), b_d)
+        expect = 2.0 * e
+        expect[cx.wall_edge] = 0.0
+        eh, bh = ctx.fields_download()
+        assert np.array_equal(eh, expect) and np.array_equal(bh, b)
+        b_bad = b.copy()
+        b_bad[int(np.flatnonzero(~cx.wall_face)[0])] += 1
+        with pytest.raises(qh.QhError) as ei:
+            ctx.fields_upload_dev(e_d, dev.put(b_bad))
+        assert ei.value.code == qh.QH_EINVAL
+        assert np.array_equal(ctx.fields_download()[0], expect)
+        # the step after the device upload equals the step after the host upload, bit for bit
+        x, v, tet = parts["e"]
+        ref.fields_upload(expect, b)
+        outs = []
+        for c in (ctx, ref):
+            sid = c.species_add(-qi.QE / qi.ME, -1)
+            c.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
+            c.pic_step(c.step_params(field_mode=qh.FIELDS_SOLVE, tol_edge=1e-10, tol_node=1e-10))
+            outs.append(c.fields_download() + c.deposits_download())
+        for a, r in zip(outs[0], outs[1]):
+            assert np.array_equal(a, r)
+        g_d, q_d = dev.alloc(8 * cx.Ne), dev.alloc(8 * cx.Nn)
+        ctx.deposits_download_dev(g_d, q_d)
+        ctx.fields_download()
+        assert np.array_equal(dev.get(g_d, outs[0][2]), outs[0][2]) and np.array_equal(dev.get(q_d, outs[0][3]), outs[0][3])
+    finally:
+        dev.free()
 
 
 def test_field_solve_residual(jitter4):
