@@ -318,6 +318,18 @@ int qh_precond_get_weights(qh_ctx *ctx, float *w, int64_t n);
  * QH_EINVAL for a blob that is short, of another version or size, or fails its checksum (the
  * present weights are then kept). */
 int qh_precond_save(qh_ctx *ctx, void *buf, size_t *len);
+
+/* Checkpoint of a run (host blob, magic "QHSTATE1", FNV-1a checksum): e, b, the node charge Q
+ * and background Q_bg, the wave update's history (e^{n-1} and the previous step's current),
+ * the plane wave's accumulated boundary flux, the step count, and every species' particles with
+ * their ids and next id. Not in it: the mesh, physics, boundary and wall modes, plane-wave
+ * parameters and species definitions (set them up as before loading; load checks mesh sizes
+ * and each species' q/m and charge number), the learned preconditioner (qh_precond_save). The
+ * integer deposits make a resumed run bit-identical to an uninterrupted one. save: buf NULL sets
+ * *len to the size needed. load: QH_EINVAL for a blob that is corrupted or does not fit the
+ * context (nothing is changed then). */
+int qh_state_save(qh_ctx *ctx, void *buf, size_t *len);
+int qh_state_load(qh_ctx *ctx, const void *buf, size_t len);
 int qh_precond_load(qh_ctx *ctx, const void *buf, size_t len);
 /* Entries of G: rows/cols (interior-edge indices, row-major lower triangle of A's pattern) and
  * FP32 values for the current weights. Pass rows = cols = vals = NULL to query *nnz. */

@@ -36,7 +36,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
            "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
-           "qh_fields_download_dev", "qh_deposits_download_dev"]
+           "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load"]
 
 
 class QhError(RuntimeError):
@@ -131,6 +131,8 @@ def lib():
             "qh_fields_download_dev": [p, p, p],
             "qh_deposits_download_dev": [p, p, p],
             "qh_precond_save": [p, p, C.POINTER(C.c_size_t)],
+            "qh_state_save": [p, p, C.POINTER(C.c_size_t)],
+            "qh_state_load": [p, p, C.c_size_t],
             "qh_precond_load": [p, p, C.c_size_t],
             "qh_charge_background": [p, i32],
             "qh_pic_step": [p, C.POINTER(StepParams), i32, p],
@@ -411,6 +413,18 @@ class Context:
         return x, dict(iters=st.iters, res=st.res, fallback=st.fallback, ms=st.ms)
 
     # learned preconditioner -------------------------------------------------------------
+    def state_save(self):
+        """Checkpoint of the run as bytes (see qh_state_save)."""
+        n = C.c_size_t(0)
+        self._check(self.L.qh_state_save(self.h, None, C.byref(n)))
+        buf = (C.c_ubyte * n.value)()
+        self._check(self.L.qh_state_save(self.h, C.cast(buf, C.c_void_p), C.byref(n)))
+        return bytes(buf)
+
+    def state_load(self, blob):
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        self._check(self.L.qh_state_load(self.h, C.cast(buf, C.c_void_p), len(blob)))
+
     def precond_save(self):
         """The trained network as bytes (see qh_precond_save)."""
         n = C.c_size_t(0)

@@ -573,7 +573,16 @@ int qh_species_add(qh_ctx *c, double q_over_m, int32_t z, int32_t *sid) {
     return QH_OK;
 }
 
+// Replaces a species' particles; ids: given (a checkpoint) or 0..n-1, next_id the next to give.
+static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet,
+                          const int32_t *ids_in, int64_t next_id);
+
 int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet) {
+    return upload_species(c, sid, n, x, v, tet, nullptr, n);
+}
+
+static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet,
+                          const int32_t *ids_in, int64_t next_id) {
     if (!c || sid < 0 || sid >= (int32_t)c->species.size() || n < 0) return QH_EINVAL;
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     if (n > 0 && (!x || !v)) return QH_EINVAL;
@@ -607,7 +616,7 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
         s.cap = n;
     }
     s.n = n;
-    s.next_id = n;
+    s.next_id = next_id;
     if (n > 0) {
         std::vector<float> comp(n);
         float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
@@ -619,7 +628,8 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
             QH_HIP(c, hipStreamSynchronize(c->stream));
         }
         std::vector<int32_t> ids(n);
-        std::iota(ids.begin(), ids.end(), 0);
+        if (ids_in) std::copy(ids_in, ids_in + n, ids.begin());
+        else std::iota(ids.begin(), ids.end(), 0);
         if (tet) {
             QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
         } else if ((rc = locate_species(c, s, 0, n))) {
@@ -627,6 +637,7 @@ int qh_particles_upload(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
             return rc;
         }
         QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
         if ((rc = qh_sort_species(c, s))) return rc;
     }
     c->wave_hist = false;
@@ -1276,6 +1287,175 @@ uint32_t fnv1a(const unsigned char *p, size_t n) {
     return h;
 }
 }  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Checkpoints: the state of a run as one blob (see qh.h for the layout's contents).
+extern "C++" {
+namespace {
+constexpr char kStateMagic[8] = {'Q', 'H', 'S', 'T', 'A', 'T', 'E', '1'};
+
+struct Writer {
+    unsigned char *p;
+    size_t n = 0;
+    void put(const void *src, size_t k) {
+        if (p) std::memcpy(p + n, src, k);
+        n += k;
+    }
+    template <class T> void val(T v) { put(&v, sizeof(T)); }
+};
+
+struct Reader {
+    const unsigned char *p;
+    size_t len, n = 0;
+    bool ok = true;
+    const unsigned char *take(size_t k) {
+        if (!ok || n + k > len) { ok = false; return nullptr; }
+        const unsigned char *r = p + n;
+        n += k;
+        return r;
+    }
+    template <class T> T val() {
+        T v{};
+        if (const unsigned char *q = take(sizeof(T))) std::memcpy(&v, q, sizeof(T));
+        return v;
+    }
+};
+
+// Writes (or, with w.p null, sizes) the state; device arrays are copied through host buffers.
+int state_write(qh_ctx *c, Writer &w) {
+    const HostMesh &m = c->hm;
+    const int64_t ni = c->A.n;
+    const bool has_d = c->dbnd != nullptr;
+    w.put(kStateMagic, 8);
+    w.val<uint32_t>(1);
+    w.val<uint32_t>((c->wave_hist ? 1u : 0u) | (has_d ? 2u : 0u));
+    for (int64_t v : {m.Nn, m.Ne, m.Nf, m.Nt, ni, (int64_t)c->species.size(), c->step_index}) w.val<int64_t>(v);
+    auto dev = [&](const void *src, size_t bytes) -> int {
+        if (w.p) QH_HIP(c, hipMemcpy(w.p + w.n, src, bytes, hipMemcpyDeviceToHost));
+        w.n += bytes;
+        return QH_OK;
+    };
+    int rc;
+    if ((rc = dev(c->e, 8 * m.Ne)) || (rc = dev(c->b, 8 * m.Nf)) || (rc = dev(c->Q, 8 * m.Nn)) ||
+        (rc = dev(c->Q_bg, 8 * m.Nn)))
+        return rc;
+    if (c->wave_hist && ((rc = dev(c->e_prev, 8 * ni)) || (rc = dev(c->g_prev, 8 * m.Ne)))) return rc;
+    if (has_d && (rc = dev(c->dbnd, 8 * m.Nn))) return rc;
+    for (const Species &s : c->species) {
+        w.val<double>(s.qm);
+        w.val<int32_t>(s.z);
+        w.val<int32_t>(0);
+        w.val<int64_t>(s.n);
+        w.val<int64_t>(s.next_id);
+        const float *f[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+        for (auto a : f)
+            if ((rc = dev(a, 4 * s.n))) return rc;
+        if ((rc = dev(s.tet, 4 * s.n)) || (rc = dev(s.id, 4 * s.n))) return rc;
+    }
+    const uint32_t h = w.p ? fnv1a(w.p, w.n) : 0u;
+    w.val<uint32_t>(h);
+    return QH_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+int qh_state_save(qh_ctx *c, void *buf, size_t *len) {
+    if (!c || !len) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled || !c->have_fields) return qh_fail(c, QH_ESTATE, "mesh, physics and fields first");
+    Writer sizer{nullptr};
+    int rc = state_write(c, sizer);
+    if (rc) return rc;
+    if (!buf) {
+        *len = sizer.n;
+        return QH_OK;
+    }
+    if (*len < sizer.n) return qh_fail(c, QH_EINVAL, "state buffer smaller than the size qh_state_save(NULL) gives");
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    Writer w{static_cast<unsigned char *>(buf)};
+    if ((rc = state_write(c, w))) return rc;
+    *len = w.n;
+    return QH_OK;
+}
+
+int qh_state_load(qh_ctx *c, const void *buf, size_t len) {
+    if (!c || !buf) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    const HostMesh &m = c->hm;
+    const unsigned char *p = static_cast<const unsigned char *>(buf);
+    if (len < 8 + 4 + 4 + 7 * 8 + 4 || std::memcmp(p, kStateMagic, 8) != 0)
+        return qh_fail(c, QH_EINVAL, "not a state blob");
+    uint32_t h;
+    std::memcpy(&h, p + len - 4, 4);
+    if (h != fnv1a(p, len - 4)) return qh_fail(c, QH_EINVAL, "state blob fails its checksum");
+    Reader r{p, len - 4};
+    r.take(8);
+    const uint32_t version = r.val<uint32_t>(), flags = r.val<uint32_t>();
+    int64_t hdr[7];
+    for (auto &v : hdr) v = r.val<int64_t>();
+    if (version != 1) return qh_fail(c, QH_EINVAL, "state blob of another version");
+    if (hdr[0] != m.Nn || hdr[1] != m.Ne || hdr[2] != m.Nf || hdr[3] != m.Nt || hdr[4] != c->A.n ||
+        hdr[5] != (int64_t)c->species.size())
+        return qh_fail(c, QH_EINVAL, "state blob of another mesh, boundary or species list");
+    const int64_t ni = c->A.n;
+    const bool wave = flags & 1u, has_d = flags & 2u;
+    auto f64 = [&](int64_t k) { return reinterpret_cast<const double *>(r.take(8 * k)); };
+    auto i64 = [&](int64_t k) { return reinterpret_cast<const int64_t *>(r.take(8 * k)); };
+    const double *e = f64(m.Ne);
+    const int64_t *b = i64(m.Nf), *Q = i64(m.Nn), *Qbg = i64(m.Nn);
+    const double *ep = wave ? f64(ni) : nullptr;
+    const int64_t *gp = wave ? i64(m.Ne) : nullptr;
+    const double *d = has_d ? f64(m.Nn) : nullptr;
+    struct Sp {
+        int64_t n, next;
+        const float *f[6];
+        const int32_t *tet, *id;
+    };
+    std::vector<Sp> sp(c->species.size());
+    for (size_t k = 0; k < sp.size() && r.ok; ++k) {
+        const double qm = r.val<double>();
+        const int32_t z = r.val<int32_t>();
+        r.val<int32_t>();
+        sp[k].n = r.val<int64_t>();
+        sp[k].next = r.val<int64_t>();
+        if (qm != c->species[k].qm || z != c->species[k].z || sp[k].n < 0)
+            return qh_fail(c, QH_EINVAL, "species " + std::to_string(k) + " differs from the saved one");
+        for (auto &a : sp[k].f) a = reinterpret_cast<const float *>(r.take(4 * sp[k].n));
+        sp[k].tet = reinterpret_cast<const int32_t *>(r.take(4 * sp[k].n));
+        sp[k].id = reinterpret_cast<const int32_t *>(r.take(4 * sp[k].n));
+    }
+    if (!r.ok || r.n != len - 4) return qh_fail(c, QH_EINVAL, "state blob has the wrong length");
+    for (const Sp &s : sp)
+        for (int64_t i = 0; i < s.n; ++i)
+            if (s.tet[i] < 0 || s.tet[i] >= m.Nt) return qh_fail(c, QH_EINVAL, "state blob: tet id out of range");
+    // everything checked: apply
+    std::vector<double> ecopy(e, e + m.Ne);
+    std::vector<int64_t> bcopy(b, b + m.Nf);
+    int rc = set_fields(c, ecopy.data(), bcopy.data());
+    if (rc) return rc;
+    for (size_t k = 0; k < sp.size(); ++k) {
+        std::vector<float> x(3 * sp[k].n), v(3 * sp[k].n);
+        for (int64_t i = 0; i < sp[k].n; ++i)
+            for (int dd = 0; dd < 3; ++dd) x[3 * i + dd] = sp[k].f[dd][i], v[3 * i + dd] = sp[k].f[3 + dd][i];
+        if ((rc = upload_species(c, (int32_t)k, sp[k].n, x.data(), v.data(), sp[k].tet, sp[k].id, sp[k].next))) return rc;
+    }
+    QH_HIP(c, hipMemcpy(c->Q, Q, 8 * m.Nn, hipMemcpyHostToDevice));
+    QH_HIP(c, hipMemcpy(c->Q_old, Q, 8 * m.Nn, hipMemcpyHostToDevice));
+    QH_HIP(c, hipMemcpy(c->Q_bg, Qbg, 8 * m.Nn, hipMemcpyHostToDevice));
+    if (wave) {
+        QH_HIP(c, hipMemcpy(c->e_prev, ep, 8 * ni, hipMemcpyHostToDevice));
+        QH_HIP(c, hipMemcpy(c->g_prev, gp, 8 * m.Ne, hipMemcpyHostToDevice));
+    }
+    c->wave_hist = wave;
+    if (has_d) {
+        if (!c->dbnd && (rc = qh_alloc(c, &c->dbnd, m.Nn))) return rc;
+        QH_HIP(c, hipMemcpy(c->dbnd, d, 8 * m.Nn, hipMemcpyHostToDevice));
+    }
+    c->step_index = hdr[6];
+    c->fields_dirty = true;
+    return QH_OK;
+}
 
 int qh_precond_save(qh_ctx *c, void *buf, size_t *len) {
     if (!c || !len) return QH_EINVAL;

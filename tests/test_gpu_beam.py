@@ -219,6 +219,46 @@ def test_locate_in_the_cylinder(cyl):
     assert lam_i.min() > -1e-6
 
 
+def test_beam_checkpoint_resume(cyl):
+    """Injection and absorption across a checkpoint: 16 steps straight equal 8, a checkpoint, a
+    fresh context and 8 more, bit for bit, with the ids of absorbed particles gone from both."""
+    import paper_2103_06737_amd as qh
+    mesh, cx, op, po = cyl
+    x, v, tet = _wall_bound_cloud(mesh, k=25)
+    prm = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+
+    def setup(particles=True):
+        c = gpu_context(mesh, 1e-11, weight=C["weight"])
+        c.set_walls(qh.WALLS_ABSORB)
+        c.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+        s = c.species_add(-qi.QE / qi.ME, -1)
+        if particles:
+            c.particles_upload(s, x, v, tet)
+        return c, s
+
+    def run(c, s, k0, k1):
+        for k in range(k0, k1):
+            c.particles_inject(s, *qi.beam_injection(mesh, 10, C["r_b"], C["v_p"], seed=3, step=k))
+            st = c.pic_step(prm)[0]
+            assert st["continuity_bad"] == 0 and st["lost"] == 0
+
+    def state(c, s):
+        return c.fields_download() + c.deposits_download() + c.particles_download(s) + (c.particles_ids(s),)
+
+    a, sa = setup()
+    run(a, sa, 0, 16)
+    ref = state(a, sa)
+    assert ref[-1].size < 100 + 160 and ref[-1][-1] == 100 + 160 - 1   # some absorbed, ids continue
+    h, sh = setup()
+    run(h, sh, 0, 8)
+    blob = h.state_save()
+    r, sr = setup(particles=False)
+    r.state_load(blob)
+    run(r, sr, 8, 16)
+    for u, w in zip(state(r, sr), ref):
+        assert np.array_equal(u, w)
+
+
 def test_probe_matches_oracle_gather(cyl):
     from oracle.field import init_fields
     mesh, cx, op, po = cyl

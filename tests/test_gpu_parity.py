@@ -518,6 +518,58 @@ def test_particle_order_does_not_change_the_run(jitter4):
             assert np.array_equal(a, ref)
 
 
+def test_checkpoint_resume_is_bit_identical(jitter4):
+    """20 steps straight equal 10 steps, a checkpoint, a fresh context loading it, and 10 more,
+    bit for bit (fields, deposits, particles by id), in the wave-equation mode (its history of
+    e^{n-1} and the previous current is in the checkpoint) with a sort every 4 steps. A
+    corrupted blob and one from another species list are refused and change nothing."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    x, v, tet = parts["e"]
+    v = (v * 20).astype(np.float32)
+    prm = qh.Context.step_params(field_mode=qh.FIELDS_WAVE, sort_every=4, verify=1, tol_edge=1e-10, tol_node=1e-10)
+
+    def setup(particles=True):
+        c = gpu_context(mesh, 2e-10)
+        c.fields_upload(e, b)
+        s = c.species_add(-qi.QE / qi.ME, -1)
+        if particles:
+            c.particles_upload(s, x, v, tet)
+            c.charge_background(1)
+        return c, s
+
+    def state(c, s):
+        return c.fields_download() + c.deposits_download() + c.particles_download(s) + (c.particles_ids(s),)
+
+    a, sa = setup()
+    for st in a.pic_step(prm, 20):
+        assert st["continuity_bad"] == 0
+    ref = state(a, sa)
+    h, sh = setup()
+    h.pic_step(prm, 10)
+    blob = h.state_save()
+    assert blob[:8] == b"QHSTATE1"
+    r, sr = setup(particles=False)
+    r.state_load(blob)
+    for st in r.pic_step(prm, 10):
+        assert st["continuity_bad"] == 0
+    for u, w in zip(state(r, sr), ref):
+        assert np.array_equal(u, w)
+    bad = bytearray(blob)
+    bad[200] ^= 1
+    before = r.fields_download()[0]
+    with pytest.raises(qh.QhError) as ei:
+        r.state_load(bytes(bad))
+    assert ei.value.code == qh.QH_EINVAL
+    o = gpu_context(mesh, 2e-10)
+    o.fields_upload(e, b)
+    o.species_add(qi.QE / qi.MI, 1)
+    with pytest.raises(qh.QhError) as ei:
+        o.state_load(blob)
+    assert ei.value.code == qh.QH_EINVAL
+    assert np.array_equal(r.fields_download()[0], before)
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
