@@ -570,6 +570,36 @@ def test_checkpoint_resume_is_bit_identical(jitter4):
     assert np.array_equal(r.fields_download()[0], before)
 
 
+def test_walk_cap_is_reported_and_keeps_continuity(jitter4):
+    """Fault forced from the host: some particles so fast that their path needs more than the
+    64-piece walk cap in one step. The step reports QH_ELOST with the count, keeps every
+    particle (stopped where the cap hit, inside a tet), and continuity still holds bit for bit
+    (the path up to there is deposited and the charge sits at the stopping point)."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    x, v, tet = parts["e"]
+    v = v.copy()
+    v[:50] = np.float32(3e10) * np.array([0.6, 0.48, 0.64], np.float32)   # ~30 m per step in a 1 m box
+    ctx = gpu_context(mesh, 1e-9)
+    ctx.fields_upload(e, b)
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    ctx.particles_upload(sid, x, v, tet)
+    _, Q0 = ctx.deposits_download()
+    with pytest.raises(qh.QhError) as ei:
+        ctx.pic_step(ctx.step_params(verify=1))
+    assert ei.value.code == qh.QH_ELOST
+    ctx.particles_upload(sid, x, v, tet)
+    _, Q0 = ctx.deposits_download()
+    st = ctx.pic_step(ctx.step_params(verify=1), allow=(qh.QH_ELOST,))[0]
+    assert st["lost"] == 50 and st["continuity_bad"] == 0
+    g, Q1 = ctx.deposits_download()
+    assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+    xg, _, tg = ctx.particles_download(sid)
+    assert ctx.particles_count(sid) == tet.size
+    lam = np.einsum("pij,pj->pi", op.Minv[tg], np.column_stack([np.ones(tet.size), xg.astype(np.float64)]))
+    assert lam.min() > -1e-5
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
