@@ -42,7 +42,8 @@ extern "C" {
 #define QH_ENOMEM (-2)    /* device or host allocation failed */
 #define QH_EHIP (-3)      /* a HIP runtime call failed */
 #define QH_ENOTCONV (-4)  /* a Krylov solve hit its iteration cap; stats are still filled */
-#define QH_EOVERFLOW (-5) /* fixed-point headroom exceeded */
+#define QH_EOVERFLOW (-5) /* fixed-point headroom exceeded: a step's int64 current on an edge or
+                              charge on a node beyond 2^60 (the steps are still taken) */
 #define QH_ELOST (-6)     /* a particle hit the 64-piece walk cap; it is kept, flagged */
 #define QH_ESTATE (-7)    /* call out of order (e.g. a step before a mesh is uploaded) */
 
@@ -254,7 +255,8 @@ int qh_charge_background(qh_ctx *ctx, int32_t mode);
  * Sec. IV.B (trapezoidal edge solve, discrete Gauss law for the non-solenoidal part,
  * integer Faraday update of b); QH_FIELDS_WAVE replaces the edge solve's right-hand side by
  * that of the wave equation (see its definition). stats: n_steps entries or NULL. Returns QH_ENOTCONV if a
- * solve hit its cap (the step is still taken), QH_ELOST if a particle hit the walk cap. */
+ * solve hit its cap (the step is still taken), QH_ELOST if a particle hit the walk cap,
+ * QH_EOVERFLOW if a step's edge current or node charge came within 2^3 of the int64 range. */
 int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
                 qh_step_stats_t *stats);
 /* Deposits of the last step: g (Ne) path-integrated current, Q (Nn) node charge,

@@ -1003,6 +1003,10 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     bool use_ev = stats != nullptr;
     if (use_ev)
         for (auto &x : ev) QH_HIP(c, hipEventCreate(&x));
+    // fixed-point headroom count of the gathers (slot 3 past the per-block event counters), over
+    // the whole call; the other slots are cleared every step
+    unsigned long long *headroom = c->counters + 4 * QH_COUNTER_SLOTS + 3;
+    QH_HIP(c, hipMemsetAsync(headroom, 0, sizeof(unsigned long long), c->stream));
     for (int32_t st = 0; st < n_steps; ++st) {
         bool capture = c->capture_next;
         c->capture_next = false;
@@ -1016,7 +1020,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         std::swap(c->Q, c->Q_old);
         QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * m.Nn, c->stream));
         QH_HIP(c, hipMemsetAsync(c->g, 0, sizeof(int64_t) * m.Ne, c->stream));
-        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * (4 * QH_COUNTER_SLOTS + 8), c->stream));
+        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * (4 * QH_COUNTER_SLOTS + 3), c->stream));
         for (size_t k = 0; k < c->species.size(); ++k) {
             int t0 = qh_tbeg(c);
             QH_HIP(c, launch_particle_step(c, c->species[k], (int)k, capture));
@@ -1128,9 +1132,15 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     }
     if (use_ev)
         for (auto &x : ev) (void)hipEventDestroy(x);
+    unsigned long long nhead = 0;
+    QH_HIP(c, hipMemcpyAsync(&nhead, headroom, sizeof(nhead), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
     if (status == QH_ENOTCONV) c->err = "a Krylov solve hit its iteration cap";
     if (status == QH_ELOST) c->err = "a particle hit the walk cap";
+    if (nhead && status == QH_OK) {
+        status = QH_EOVERFLOW;
+        c->err = std::to_string(nhead) + " edge currents or node charges of a step beyond 2^60 (int64 headroom)";
+    }
     return status;
 }
 

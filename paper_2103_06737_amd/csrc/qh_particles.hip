@@ -582,12 +582,16 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
     return lb < nblocks ? lb : 0xffffffffu;
 }
 
+// Fixed-point headroom: a step's current on one edge or charge on one node beyond 2^60 (eight
+// times below the int64 range; a piece is at most 64 * 2^40) is counted as an overflow risk.
+constexpr long long kHeadroom = 1ll << 60;
+
 template <int OFF, int LPI>
 __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ lst,
                                                 const int64_t *__restrict__ acc_tet, int64_t nt,
                                                 int64_t *__restrict__ out,
-                                                unsigned nblocks_grid) {
+                                                unsigned nblocks_grid, unsigned long long *headroom) {
     // LPI lanes per item; the grid is padded to a multiple of 8 blocks so the remap is a
     // bijection onto [0, grid)
     const unsigned lb = xcd_block(blockIdx.x, nblocks_grid);
@@ -602,7 +606,11 @@ __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *_
     }
 #pragma unroll
     for (int off = LPI / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPI);
-    if (sub == 0 && lb != 0xffffffffu && item < nitems) out[item] += s;
+    if (sub == 0 && lb != 0xffffffffu && item < nitems) {
+        const int64_t t = out[item] + s;
+        out[item] = t;
+        if (t > kHeadroom || t < -kHeadroom) atomicAdd(headroom, 1ull);
+    }
 }
 
 // Mailbox m (tets [kMailTets m, kMailTets (m+1))) into acc_tet: each record's 10 values (as
@@ -698,10 +706,11 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     constexpr int kLpiE = 2, kLpiN = 8;  // lanes per edge / per node (edges border 4-6 tets, nodes ~24)
     const unsigned ge = (unsigned)(((m.Ne + 256 / kLpiE - 1) / (256 / kLpiE) + 7) / 8 * 8);
     const unsigned gn = (unsigned)(((m.Nn + 256 / kLpiN - 1) / (256 / kLpiN) + 7) / 8 * 8);
+    unsigned long long *headroom = c->counters + 4 * QH_COUNTER_SLOTS + 3;  // kept over a pic_step call
     hipLaunchKernelGGL((k_gather<0, kLpiE>), dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet,
-                       m.Nt, c->g, ge);
+                       m.Nt, c->g, ge, headroom);
     hipLaunchKernelGGL((k_gather<6, kLpiN>), dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet,
-                       m.Nt, c->Q, gn);
+                       m.Nt, c->Q, gn, headroom);
     return hipGetLastError();
 }
 

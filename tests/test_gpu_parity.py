@@ -600,6 +600,39 @@ def test_walk_cap_is_reported_and_keeps_continuity(jitter4):
     assert lam.min() > -1e-5
 
 
+def test_fixed_point_headroom_is_reported(jitter4):
+    """Fault forced from the host: 20,000 particles of charge number 64 move together along an
+    edge of one tet (barycentrics 0.9/0.05 -> 0.05/0.9). A node's charge in that step is about
+    20,000 * 64 * 0.9 * 2^40 > 2^60: the step reports QH_EOVERFLOW while the int64 sums are still
+    exact (continuity holds); the same particles with charge number 1 are far below it."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    t = int(np.flatnonzero(~np.isin(np.arange(cx.Nt), np.flatnonzero((cx.tet_nbr < 0).any(axis=1))))[0])
+    V = cx.xyz[cx.tets[t]]
+    p0 = np.array([0.9, 0.05, 0.025, 0.025]) @ V
+    p1 = np.array([0.05, 0.9, 0.025, 0.025]) @ V
+    n, dt = 20_000, 1e-12
+    x = np.tile(p0.astype(np.float32), (n, 1))
+    v = np.tile(((p1 - p0) / dt).astype(np.float32), (n, 1))
+    tet = np.full(n, t, np.int32)
+    for z in (64, 1):
+        ctx = gpu_context(mesh, dt)
+        ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+        sid = ctx.species_add(-z * qi.QE / qi.ME, -z)
+        ctx.particles_upload(sid, x, v, tet)
+        if z == 64:
+            with pytest.raises(qh.QhError) as ei:
+                ctx.pic_step(ctx.step_params(verify=1))
+            assert ei.value.code == qh.QH_EOVERFLOW
+            ctx.particles_upload(sid, x, v, tet)
+        _, Q0 = ctx.deposits_download()
+        st = ctx.pic_step(ctx.step_params(verify=1), allow=(qh.QH_EOVERFLOW,))[0]
+        assert st["continuity_bad"] == 0
+        g, Q1 = ctx.deposits_download()
+        assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+        assert (np.abs(Q1).max() > 2 ** 60) == (z == 64)
+
+
 def test_field_solve_residual(jitter4):
     import scipy.sparse.linalg as sla
     import paper_2103_06737_amd as qh
