@@ -11,7 +11,7 @@ from .complex_ import Complex
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pic.c")
-LIB = os.path.join(HERE, "_build", "liborc.so")
+LIB = os.environ.get("QH_ORC_LIB") or os.path.join(HERE, "_build", "liborc.so")  # QH_ORC_LIB: another build
 F_BITS = 20
 
 

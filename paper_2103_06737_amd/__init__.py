@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqh.so")
+LIB_PATH = os.environ.get("QH_LIBQH") or os.path.join(HERE, "libqh.so")  # QH_LIBQH: another build (sanitizer tests)
 
 QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
