@@ -298,6 +298,16 @@ int qh_deposit(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t
 int qh_fields_decompose(qh_ctx *ctx, double tol, int32_t max_it, double *e_ns, double *e_s, double *rho_bar,
                         qh_solve_stats_t *stats);
 
+/* Energy of the present fields (Sec. VI.A.1: the source-free trapezoidal update leaves it
+ * unchanged), in joules: *w_e = 1/2 e^T [*eps] e over the edge unknowns, *w_m =
+ * 1/2 b^T [*mu^-1] b with b in webers (b_int u_b). D b = 0 makes the Whitney 2-form field
+ * constant in each tet, so w_m = sum_T |B_T|^2 |T| / (2 mu0), evaluated with FP64 geometry.
+ * Both sums are FP64 with a fixed reduction order (the same bits on every call). The first call
+ * uploads the FP64 node coordinates (24 bytes per node) and keeps them with the context.
+ * Synchronises the context stream. QH_ESTATE without mesh, physics and fields or on a host-only
+ * context; QH_EINVAL for NULL outputs. */
+int qh_fields_energy(qh_ctx *ctx, double *w_e, double *w_m);
+
 /* Solve system (QH_SYS_EDGE or QH_SYS_NODE) A x = rhs on its interior unknowns
  * (n_int_edges or n_int_nodes values), FP64 CG with FP64 dot products, to
  * ||rhs - A x|| <= tol ||rhs||. x holds the initial guess on entry. */

@@ -36,7 +36,8 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_precond_train", "qh_edge_system_download", "qh_set_boundary", "qh_set_plane_wave",
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
            "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
-           "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load"]
+           "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load",
+           "qh_fields_energy"]
 
 
 class QhError(RuntimeError):
@@ -126,6 +127,7 @@ def lib():
             "qh_particles_inject": [p, i32, i64, p, p, p],
             "qh_probe_fields": [p, i64, p, p, p, p],
             "qh_fields_decompose": [p, d, i32, p, p, p, C.POINTER(SolveStats)],
+            "qh_fields_energy": [p, p, p],
             "qh_locate": [p, i64, p, p],
             "qh_fields_upload_dev": [p, p, p],
             "qh_fields_download_dev": [p, p, p],
@@ -402,6 +404,12 @@ class Context:
         rc = self.L.qh_fields_decompose(self.h, float(tol), int(max_it), _ptr(e_ns), _ptr(e_s), _ptr(rho), C.byref(st))
         self._check(rc, allow)
         return e_ns, e_s, rho, dict(iters=st.iters, res=st.res, ms=st.ms)
+
+    def fields_energy(self):
+        """(electric, magnetic) energy of the present fields in joules (see qh_fields_energy)."""
+        we, wm = C.c_double(0.0), C.c_double(0.0)
+        self._check(self.L.qh_fields_energy(self.h, C.byref(we), C.byref(wm)))
+        return we.value, wm.value
 
     def field_solve(self, system, rhs, x0=None, tol=1e-8, max_it=5000, precond=PC_JACOBI, allow=()):
         rhs = _c(rhs, np.float64)

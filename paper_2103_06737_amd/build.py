@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqh.so")
-SOURCES = ["qh_mesh.hip", "qh_particles.hip", "qh_solver.hip", "qh_learned.hip", "qh_api.hip"]
+SOURCES = ["qh_mesh.hip", "qh_particles.hip", "qh_solver.hip", "qh_learned.hip", "qh_diag.hip", "qh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          # no packed FP32 instructions: hipcc forms them from plain float code otherwise

@@ -1144,6 +1144,23 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     return status;
 }
 
+int qh_fields_energy(qh_ctx *c, double *w_e, double *w_m) {
+    if (!c || !w_e || !w_m) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled || !c->have_fields) return qh_fail(c, QH_ESTATE, "mesh, physics and fields first");
+    int rc;
+    const int32_t np = qh_energy_parts(c);
+    if (!c->xyz_d && (rc = upload(c, &c->xyz_d, c->hm.xyz.data(), c->hm.xyz.size()))) return rc;
+    if (!c->energy_d && (rc = qh_alloc(c, &c->energy_d, (size_t)np + 2))) return rc;
+    QH_HIP(c, launch_field_energy(c, c->energy_d, c->energy_d + np));
+    double out[2];
+    QH_HIP(c, hipMemcpyAsync(out, c->energy_d + np, sizeof out, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    *w_e = out[0];
+    *w_m = out[1];
+    return QH_OK;
+}
+
 int qh_fields_decompose(qh_ctx *c, double tol, int32_t max_it, double *e_ns, double *e_s, double *rho_bar,
                         qh_solve_stats_t *stats) {
     if (!c || !(tol > 0) || max_it < 0) return QH_EINVAL;

@@ -211,6 +211,8 @@ struct qh_ctx {
     double *scratch_d = nullptr;  // small device scalars (gauss thresholds etc.)
     double *dec_e = nullptr;      // interior edge values of E_s (qh_fields_decompose)
     double cfl_lambda = -1.0;     // qh_cfl_lambda_geo of the mesh (computed on first request)
+    double *xyz_d = nullptr;      // 3*Nn FP64 node coordinates (uploaded on the first energy request)
+    double *energy_d = nullptr;   // energy partial sums, then the two totals
     // point location: a uniform grid of buckets over the bounding box, a seed tet per bucket
     int32_t *loc_seed = nullptr;
     float loc_lo[3] = {0, 0, 0}, loc_inv[3] = {0, 0, 0};
@@ -300,6 +302,9 @@ hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet
                                 const int32_t *pz, int64_t *g, int64_t *Q);
 hipError_t launch_verify(qh_ctx *c, bool check_divb);
 hipError_t launch_divb(qh_ctx *c, int64_t *out);
+// Field energy (qh_diag.hip): qh_energy_parts(c) partial sums in part, out[0] electric, out[1] magnetic
+int32_t qh_energy_parts(const qh_ctx *c);
+hipError_t launch_field_energy(qh_ctx *c, double *part, double *out);
 hipError_t launch_divb_check(qh_ctx *c, const int64_t *b, unsigned long long *bad);
 hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x);
 

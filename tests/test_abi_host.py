@@ -68,7 +68,7 @@ def test_host_particle_and_wall_calls_validate():
     with pytest.raises(qh.QhError) as ei:
         ctx.precond_save()
     assert ei.value.code == qh.QH_ESTATE
-    for call in (ctx.state_save, lambda: ctx.state_load(b"QHSTATE1" + bytes(100))):
+    for call in (ctx.state_save, lambda: ctx.state_load(b"QHSTATE1" + bytes(100)), ctx.fields_energy):
         with pytest.raises(qh.QhError) as ei:
             call()
         assert ei.value.code == qh.QH_ESTATE

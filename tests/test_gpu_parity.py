@@ -373,6 +373,70 @@ def test_fields_decompose_matches_oracle(jitter4, bc):
     assert st["iters"] > 0
 
 
+@pytest.mark.parametrize("bc", ["pec", "neumann"])
+def test_field_energy_matches_oracle_and_is_conserved(jitter4, bc):
+    """Field energy 1/2 e^T [*eps] e + 1/2 b^T [*mu^-1] b (Sec. VI.A.1). The device evaluates the
+    magnetic part per tet from the constant B_T of a flux vector with D b = 0; the oracle takes the
+    full quadratic form of its face Hodge matrix, so agreement also pins that identity. Without
+    sources the trapezoidal update keeps the sum: with the Gauss-law solve off from a random e,
+    and with it on from the solenoidal part E_s (whose correction is then at the tolerance)."""
+    import paper_2103_06737_amd as qh
+    from oracle.complex_ import Complex
+    from oracle.whitney import Operators
+    cfg, mesh, _, _, _, _, _, _ = jitter4
+    cx = Complex(mesh.xyz, mesh.tets, neumann=bc == "neumann")
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    e, b = oracle_fields(cx, cfg, U_B, seed=4)
+    assert not (cx.D @ b).any()
+    dt = 2e-10
+
+    def context():
+        ctx = qh.Context(0)
+        if bc == "neumann":
+            ctx.set_boundary(qh.BC_NEUMANN)
+        ctx.mesh_upload(mesh.xyz, mesh.tets)
+        ctx.set_physics(qi.EPS0, qi.MU0, dt, qi.QE * 2.0 ** -40, U_B)
+        return ctx
+
+    def oracle_energy(e, b):
+        br = b * U_B
+        we, wm = 0.5 * e @ (op.Meps @ e), 0.5 * br @ (op.Mmu @ br)
+        bound_e = 64 * np.finfo(float).eps * 0.5 * np.abs(e) @ (abs(op.Meps) @ np.abs(e))
+        bound_m = 64 * np.finfo(float).eps * 0.5 * np.abs(br) @ (abs(op.Mmu) @ np.abs(br))
+        return we, wm, bound_e, bound_m
+
+    ctx = context()
+    ctx.fields_upload(e, b)
+    we, wm = ctx.fields_energy()
+    o_we, o_wm, be, bm = oracle_energy(e, b)
+    assert we > 0 and wm > 0
+    assert abs(we - o_we) <= be and abs(wm - o_wm) <= bm
+    assert ctx.fields_energy() == (we, wm)  # fixed reduction order
+    # zero fields
+    ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
+    assert ctx.fields_energy() == (0.0, 0.0)
+
+    # source-free steps, Gauss-law solve off
+    ctx.fields_upload(e, b)
+    w0 = sum(ctx.fields_energy())
+    for _ in range(12):
+        ctx.pic_step(ctx.step_params(field_mode=qh.FIELDS_SOLVE, gauss=0, tol_edge=1e-12), 1)
+        w = sum(ctx.fields_energy())
+        assert abs(w - w0) <= 1e-10 * w0
+    e_g, b_g = ctx.fields_download()
+    o = oracle_energy(e_g, b_g)
+    assert abs(w - (o[0] + o[1])) <= o[2] + o[3]
+    # with the Gauss-law solve, from the solenoidal part of e
+    _, e_s, _, _ = ctx.fields_decompose(tol=1e-13)
+    ctx2 = context()
+    ctx2.fields_upload(e_s, b)
+    w0 = sum(ctx2.fields_energy())
+    for _ in range(12):
+        st = ctx2.pic_step(ctx2.step_params(field_mode=qh.FIELDS_SOLVE, tol_edge=1e-12, tol_node=1e-12), 1)[0]
+        w = sum(ctx2.fields_energy())
+        assert abs(w - w0) <= 1e-10 * w0, st
+
+
 def test_locate_and_upload_without_tets(jitter4):
     """Point location on the device: every point inside gets a tet holding it (FP64 barycentrics
     of the point in it >= -1e-6; the tet of the brute-force search wherever that one is not
