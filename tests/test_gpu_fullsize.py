@@ -162,6 +162,38 @@ def test_plasma64_order_independent(plasma64):
         assert np.array_equal(a, ref)
 
 
+def test_plasma64_field_energy(plasma64):
+    """Field energy on the 64^3 mesh (Sec. VI.A.1): the uniform B_z of the plasma workload has
+    the closed form B_z^2 V / (2 mu0) (its fluxes are rounded to u_b, a relative 1e-12); random
+    fields agree with the oracle's Hodge quadratic forms within a rounding bound; and three
+    source-free steps (Jacobi PCG to 1e-12, no Gauss-law solve) keep the sum."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, parts, cx, op, po = plasma64
+    ctx = gpu_context(mesh, cfg["dt"], weight=cfg["weight"], u_b=U_B)
+    ctx.fields_init_synthetic(qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), 0.0, cfg["bz"], 0.0)
+    we, wm = ctx.fields_energy()
+    vol = np.prod(mesh.xyz.max(axis=0) - mesh.xyz.min(axis=0))
+    assert we == 0.0
+    assert abs(wm - cfg["bz"] ** 2 * vol / (2 * qi.MU0)) <= 1e-9 * wm
+    # E and cB of one size, so that the exchange between the two parts is visible in the sum
+    ctx.fields_init_synthetic(qi.white(cx.Ne, 1, 3), qi.white(cx.Ne, 1, 5), 3e5, 0.0, 1e-3)
+    e, b = ctx.fields_download()
+    we, wm = ctx.fields_energy()
+    assert 0.1 < we / wm < 10
+    br = b * U_B
+    tiny = 64 * np.finfo(float).eps
+    assert abs(we - 0.5 * e @ (op.Meps @ e)) <= tiny * 0.5 * np.abs(e) @ (abs(op.Meps) @ np.abs(e))
+    assert abs(wm - 0.5 * br @ (op.Mmu @ br)) <= tiny * 0.5 * np.abs(br) @ (abs(op.Mmu) @ np.abs(br))
+    w0 = we + wm
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, gauss=0, tol_edge=1e-12, max_it_edge=4000)
+    for _ in range(3):
+        st = ctx.pic_step(params)[0]
+        we1, wm1 = ctx.fields_energy()
+        assert abs(we1 + wm1 - w0) <= 1e-10 * w0, st
+    assert abs(we1 - we) > 1e-4 * w0  # energy did pass between the electric and magnetic parts
+    ctx.close()
+
+
 def test_plasma64_plane_wave_natural_boundary(plasma64):
     """Natural walls and a plane-wave pulse (300 MHz, 150 MHz bandwidth, its peak passing x = 0 at
     t = 0) on the 64^3 / 16M workload, unmagnetised (natural walls carry no surface current to
