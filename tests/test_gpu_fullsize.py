@@ -124,6 +124,44 @@ def test_plasma64_full_cycle(plasma64):
     assert np.linalg.norm(rho_bar[cx.int_nodes] - rho) <= 1.01e-8 * (np.linalg.norm(rho) + np.linalg.norm(absd))
 
 
+def test_plasma64_100_steps(plasma64):
+    """The workload's full run: 100 steps of the 64^3 / 16M cycle with the learned preconditioner
+    and a re-sort every 20 steps, every invariant checked on the device at every step (continuity
+    bit for bit, D b unchanged, no lost particle, no fallback, both residuals at 1e-8); at the end
+    the total charge is the initial one, D b is unchanged on the host and sampled particles lie
+    in the tets the device holds them in."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, parts, cx, op, po = plasma64
+    ctx = gpu_context(mesh, cfg["dt"], weight=cfg["weight"])
+    ctx.fields_init_synthetic(qi.white(cx.Ne, 0, 3), qi.white(cx.Ne, 0, 5), cfg["sigma_e"], cfg["bz"],
+                              cfg["sigma_b"])
+    sid = ctx.species_add(-qi.QE / qi.ME, -1)
+    x, v, tet = parts["e"]
+    ctx.particles_upload(sid, x, v, tet)
+    ctx.charge_background(1)
+    ctx.precond_train(steps=30, lr=3e-3, seed=1, validate_every=0)
+    _, b0 = ctx.fields_download()
+    _, Q0 = ctx.deposits_download()
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=cfg["sort_every"],
+                             verify=1)
+    stats = ctx.pic_step(params, cfg["steps"])
+    assert len(stats) == 100
+    for k, st in enumerate(stats):
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0, (k, st)
+        assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8, (k, st)
+    assert sum(st["crossings"] for st in stats) > 100 * 100_000
+    _, Q1 = ctx.deposits_download()
+    _, b1 = ctx.fields_download()
+    assert Q1.sum() == Q0.sum()
+    assert np.array_equal(cx.D @ b1, cx.D @ b0)
+    xg, _, tg = ctx.particles_download(sid)
+    assert tg.size == tet.size and (tg >= 0).all()
+    idx = np.random.default_rng(9).choice(tg.size, 200_000, replace=False)
+    lam = np.einsum("pij,pj->pi", op.Minv[tg[idx]], np.column_stack([np.ones(idx.size), xg[idx].astype(np.float64)]))
+    assert lam.min() > -1e-5
+    ctx.close()
+
+
 def test_plasma64_order_independent(plasma64):
     """The 64^3 / 16M cycle from the particles in their generated order and in a shuffled one,
     with the same trained preconditioner (saved from the first context, loaded into the second):
