@@ -394,3 +394,45 @@ def test_graded96_two_species():
             assert np.array_equal(cx.G.T @ g, Q1 - Q0)
         iters[pc] = st["edge_iters"]
     assert iters[qh.PC_LEARNED] < 0.75 * iters[qh.PC_JACOBI]
+
+
+def test_graded96_full_run():
+    """The graded workload at its full size and length: 96^3 graded mesh, 32M electrons and 32M
+    ions, learned preconditioner, 200 steps with a re-sort every 20, every invariant checked on
+    the device at every step; total charge and D b on the host at the end."""
+    import paper_2103_06737_amd as qh
+    cfg = qi.CONFIGS["graded96"]
+    mesh = qi.make_mesh(cfg)
+    parts = qi.make_particles(mesh, cfg)
+    ctx = gpu_context(mesh, cfg["dt"], weight=cfg["weight"])
+    mi = ctx.mesh_info()
+    ctx.fields_init_synthetic(qi.white(mi.n_edges, 0, 3), qi.white(mi.n_edges, 0, 5), cfg["sigma_e"], cfg["bz"],
+                              cfg["sigma_b"])
+    sids = {}
+    for name, (x, v, tet) in parts.items():
+        qm, z = (-qi.QE / qi.ME, -1) if name == "e" else (qi.QE / qi.MI, 1)
+        sids[name] = ctx.species_add(qm, z)
+        ctx.particles_upload(sids[name], x, v, tet)
+    del parts
+    ctx.charge_background(1)
+    ctx.precond_train(steps=60, lr=3e-3, seed=1, validate_every=0)
+    _, b0 = ctx.fields_download()
+    _, Q0 = ctx.deposits_download()
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=cfg["sort_every"],
+                             verify=1)
+    stats = []
+    for _ in range(4):
+        stats += ctx.pic_step(params, cfg["steps"] // 4)
+        print(f"graded96: {len(stats)} steps, edge iterations {stats[-1]['edge_iters']}", flush=True)
+    assert len(stats) == 200
+    for k, st in enumerate(stats):
+        assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0, (k, st)
+        assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8, (k, st)
+    _, Q1 = ctx.deposits_download()
+    _, b1 = ctx.fields_download()
+    assert Q1.sum() == Q0.sum()
+    from oracle.complex_ import Complex
+    cx = Complex(mesh.xyz, mesh.tets)
+    assert np.array_equal(cx.D @ b1, cx.D @ b0)
+    assert all(ctx.particles_count(s) == 32_000_000 for s in sids.values())
+    ctx.close()
