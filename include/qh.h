@@ -46,6 +46,9 @@ extern "C" {
                               charge on a node beyond 2^60 (the steps are still taken) */
 #define QH_ELOST (-6)     /* a particle hit the 64-piece walk cap; it is kept, flagged */
 #define QH_ESTATE (-7)    /* call out of order (e.g. a step before a mesh is uploaded) */
+#define QH_EVERIFY (-8)   /* verify = 1 found a broken invariant: discrete continuity G^T g = Q^{n+1} - Q^n
+                             (Sec. IV.B.1) at some node, or D b changed in some tet (Sec. IV.A); the
+                             steps are still taken */
 
 #define QH_FIELDS_FROZEN 0 /* particles only: E, B stay as uploaded */
 #define QH_FIELDS_SOLVE 1  /* full cycle: implicit field update after each push */
@@ -254,9 +257,11 @@ int qh_charge_background(qh_ctx *ctx, int32_t mode);
  * and of the W0 charge; then, if field_mode is QH_FIELDS_SOLVE, the implicit update of
  * Sec. IV.B (trapezoidal edge solve, discrete Gauss law for the non-solenoidal part,
  * integer Faraday update of b); QH_FIELDS_WAVE replaces the edge solve's right-hand side by
- * that of the wave equation (see its definition). stats: n_steps entries or NULL. Returns QH_ENOTCONV if a
- * solve hit its cap (the step is still taken), QH_ELOST if a particle hit the walk cap,
- * QH_EOVERFLOW if a step's edge current or node charge came within 2^3 of the int64 range. */
+ * that of the wave equation (see its definition). stats: n_steps entries or NULL. The status
+ * covers every step of the call whether or not stats are given, the most serious failure first:
+ * QH_EVERIFY if verification found a broken invariant, QH_ENOTCONV if a solve hit its cap (the
+ * step is still taken), QH_ELOST if a particle hit the walk cap, QH_EOVERFLOW if a step's edge
+ * current or node charge came within 2^3 of the int64 range. */
 int qh_pic_step(qh_ctx *ctx, const qh_step_params_t *params, int32_t n_steps,
                 qh_step_stats_t *stats);
 /* Deposits of the last step: g (Ne) path-integrated current, Q (Nn) node charge,
@@ -346,6 +351,10 @@ int qh_precond_load(qh_ctx *ctx, const void *buf, size_t len);
 /* Entries of G: rows/cols (interior-edge indices, row-major lower triangle of A's pattern) and
  * FP32 values for the current weights. Pass rows = cols = vals = NULL to query *nnz. */
 int qh_precond_factor(qh_ctx *ctx, int64_t *nnz, int32_t *rows, int32_t *cols, float *vals);
+/* The preconditioner's application z = G^T (G r) as the learned solve applies it (the same
+ * kernels: BF16 copies of G and G^T, FP64 products and sums), for the current weights. r, z:
+ * n_int_edges doubles (host). QH_ESTATE before mesh and physics. */
+int qh_precond_apply(qh_ctx *ctx, const double *r, double *z);
 /* Training objective L = log(tr(G A G^T)/n) - (2/n) sum_i log G_ii (log of the Kaporin
  * condition number of G A G^T up to a constant), trace estimated with the 16 probe vectors
  * probes[i*16 + p] (node-major, n_int_edges x 16); and, if grad != NULL, dL/dweights

@@ -186,3 +186,57 @@ def pcg(A, b, apply_m, tol=1e-8, maxit=5000, x0=None):
         rz = rz_new
         it += 1
     return x, it
+
+
+STALL_WINDOW = 10        # iterations over which ||r|| must drop
+STALL_DROP = 0.1         # by at least this fraction
+
+
+def pcg_learned(A, b, apply_m, tol=1e-8, maxit=5000, x0=None):
+    """Learned-preconditioner solve with the stall rule of the fallback: PCG with z = apply_m(r)
+    stops as stalled when r.z <= 0 (M not positive definite on r), on non-finite values, or when
+    ||r|| has not dropped by STALL_DROP over the last STALL_WINDOW iterations; Jacobi-PCG then
+    restarts from the present iterate (from x0 after non-finite values). Returns x, the learned
+    iterations, the Jacobi iterations and why the learned phase ended ("converged", "stalled",
+    "nonfinite" or "cap")."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    start = x.copy()
+    r = b - A @ x
+    nb = np.linalg.norm(b)
+    z = apply_m(r)
+    rz = r @ z
+    hist = [r @ r]
+    why = "cap"
+    it = 0
+    p = z.copy()
+
+    def state(rr, rz_, k):
+        if not (np.isfinite(rr) and np.isfinite(rz_)):
+            return "nonfinite"
+        if rr <= (tol * nb) ** 2:
+            return "converged"
+        if not rz_ > 0 or (k >= STALL_WINDOW and rr > (1.0 - STALL_DROP) ** 2 * hist[k - STALL_WINDOW]):
+            return "stalled"
+        return None
+
+    why = state(hist[0], rz, 0) or "cap"
+    while why == "cap" and it < maxit:
+        q = A @ p
+        alpha = rz / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = apply_m(r)
+        rz_new = r @ z
+        it += 1
+        hist.append(r @ r)
+        s_ = state(hist[-1], rz_new, it)
+        if s_:
+            why = s_
+            break
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    if why == "converged":
+        return x, it, 0, why
+    dinv = 1.0 / A.diagonal()
+    xj, it_j = pcg(A, b, lambda v: dinv * v, tol=tol, maxit=maxit, x0=start if why == "nonfinite" else x)
+    return xj, it, it_j, why

@@ -15,8 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("QH_LIBQH") or os.path.join(HERE, "libqh.so")  # QH_LIBQH: another build (sanitizer tests)
 
-QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+QH_OK, QH_EINVAL, QH_ENOMEM, QH_EHIP, QH_ENOTCONV, QH_EOVERFLOW, QH_ELOST, QH_ESTATE, QH_EVERIFY = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 FIELDS_FROZEN, FIELDS_SOLVE, FIELDS_WAVE = 0, 1, 2
 BC_PEC, BC_NEUMANN = 0, 1
 WALLS_REFLECT, WALLS_ABSORB = 0, 1
@@ -37,7 +37,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
            "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
            "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load",
-           "qh_fields_energy"]
+           "qh_fields_energy", "qh_precond_apply"]
 
 
 class QhError(RuntimeError):
@@ -151,6 +151,7 @@ def lib():
             "qh_precond_set_weights": [p, p, i64],
             "qh_precond_get_weights": [p, p, i64],
             "qh_precond_factor": [p, C.POINTER(i64), p, p, p],
+            "qh_precond_apply": [p, p, p],
             "qh_precond_loss_grad": [p, p, C.POINTER(d), p],
             "qh_precond_train": [p, C.POINTER(TrainParams), i32, p, p, C.POINTER(TrainStats)],
         }
@@ -462,6 +463,13 @@ class Context:
         vals = np.zeros(nnz.value, np.float32)
         self._check(self.L.qh_precond_factor(self.h, C.byref(nnz), _ptr(rows), _ptr(cols), _ptr(vals)))
         return rows, cols, vals
+
+    def precond_apply(self, r):
+        """z = G^T (G r) with the current weights (the learned solve's application kernels)."""
+        r = _c(r, np.float64)
+        z = np.zeros_like(r)
+        self._check(self.L.qh_precond_apply(self.h, _ptr(r), _ptr(z)))
+        return z
 
     def precond_loss_grad(self, probes, want_grad=True):
         probes = _c(probes, np.float32)

@@ -242,7 +242,7 @@ int qh_create(qh_ctx **out, int device, void *stream) {
     c->device = device;
     c->stream = (hipStream_t)stream;
     unsigned long long *cnt = nullptr;
-    if (qh_alloc(c, &cnt, 4 * QH_COUNTER_SLOTS + 8) != QH_OK) {
+    if (qh_alloc(c, &cnt, 4 * QH_COUNTER_SLOTS + QH_CNT_ALL) != QH_OK) {
         delete c;
         return QH_ENOMEM;
     }
@@ -573,6 +573,53 @@ int qh_species_add(qh_ctx *c, double q_over_m, int32_t z, int32_t *sid) {
     return QH_OK;
 }
 
+// Storage of a species for at least cap particles, all or nothing: every new array is
+// allocated before any is swapped in, so a failed allocation leaves the species (its count, its
+// particles and its arrays) as it was. The first `keep` particles and the tet ranges of their
+// blocks are copied into the new arrays; the sort scratch needs no copy.
+static int reserve_species(qh_ctx *c, Species &s, int64_t cap, int64_t keep) {
+    if (cap <= s.cap) return QH_OK;
+    float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
+    int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
+    float *nf[12] = {};
+    int32_t *ni[4] = {}, *nown = nullptr;
+    uint16_t *novf = nullptr;
+    auto drop_new = [&]() {
+        for (auto &p : nf) qh_release(c, p);
+        for (auto &p : ni) qh_release(c, p);
+        qh_release(c, nown), qh_release(c, novf);
+    };
+    int rc;
+    for (auto &p : nf)
+        if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
+    for (auto &p : ni)
+        if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
+    if ((rc = qh_alloc(c, &nown, qh_species_blocks(cap) + 1)) || (rc = qh_alloc(c, &novf, qh_species_blocks(cap) * QH_CHUNK)))
+        return drop_new(), rc;
+    hipError_t e = hipSuccess;
+    if (keep > 0) {
+        for (int k = 0; k < 6 && e == hipSuccess; ++k)
+            e = hipMemcpyAsync(nf[k], *fs[k], sizeof(float) * keep, hipMemcpyDeviceToDevice, c->stream);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k)
+            e = hipMemcpyAsync(ni[k], *is[k], sizeof(int32_t) * keep, hipMemcpyDeviceToDevice, c->stream);
+        if (s.own && e == hipSuccess)
+            e = hipMemcpyAsync(nown, s.own, sizeof(int32_t) * (qh_species_blocks(keep) + 1), hipMemcpyDeviceToDevice,
+                               c->stream);
+    }
+    // the old arrays may still be read by queued work: released only after the stream has passed
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        drop_new();
+        return qh_fail(c, QH_EHIP, std::string("species storage: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < 12; ++k) qh_release(c, *fs[k]), *fs[k] = nf[k];
+    for (int k = 0; k < 4; ++k) qh_release(c, *is[k]), *is[k] = ni[k];
+    qh_release(c, s.own), s.own = nown;
+    qh_release(c, s.ovf), s.ovf = novf;
+    s.cap = cap;
+    return QH_OK;
+}
+
 // Replaces a species' particles; ids: given (a checkpoint) or 0..n-1, next_id the next to give.
 static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, const float *v, const int32_t *tet,
                           const int32_t *ids_in, int64_t next_id);
@@ -597,25 +644,10 @@ static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, con
     }
     Species &s = c->species[sid];
     int rc;
-    if (n > s.cap) {
-        QH_HIP(c, hipStreamSynchronize(c->stream));
-        float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
-        for (auto p : fs) {
-            qh_release(c, *p);
-            if ((rc = qh_alloc(c, p, n))) return rc;
-        }
-        int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
-        for (auto p : is) {
-            qh_release(c, *p);
-            if ((rc = qh_alloc(c, p, n))) return rc;
-        }
-        qh_release(c, s.own);
-        qh_release(c, s.ovf);
-        if ((rc = qh_alloc(c, &s.own, qh_species_blocks(n) + 1))) return rc;
-        if ((rc = qh_alloc(c, &s.ovf, qh_species_blocks(n) * QH_CHUNK))) return rc;
-        s.cap = n;
-    }
-    s.n = n;
+    if ((rc = reserve_species(c, s, n, 0))) return rc;
+    // the species holds no particle until every array is in place: a failed copy or location
+    // leaves it empty, never with unset tet ids
+    s.n = 0;
     s.next_id = next_id;
     if (n > 0) {
         std::vector<float> comp(n);
@@ -630,14 +662,11 @@ static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, con
         std::vector<int32_t> ids(n);
         if (ids_in) std::copy(ids_in, ids_in + n, ids.begin());
         else std::iota(ids.begin(), ids.end(), 0);
-        if (tet) {
-            QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
-        } else if ((rc = locate_species(c, s, 0, n))) {
-            s.n = 0;  // no particle is left with an unknown tet
-            return rc;
-        }
+        if (tet) QH_HIP(c, hipMemcpyAsync(s.tet, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        else if ((rc = locate_species(c, s, 0, n))) return rc;
         QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
+        s.n = n;
         if ((rc = qh_sort_species(c, s))) return rc;
     }
     c->wave_hist = false;
@@ -719,39 +748,8 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     if (n1 >= ((int64_t)1 << 31) || s.next_id + n >= ((int64_t)1 << 31))
         return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles (and ids) per species");
     int rc;
-    if (n1 > s.cap) {
-        // grow: every new array first (a failed allocation leaves the species as it was), then
-        // the present particles copied over and the old arrays released
-        const int64_t cap = std::max<int64_t>(std::max<int64_t>(2 * s.cap, n1), 4096);
-        float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
-        int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
-        float *nf[12] = {};
-        int32_t *ni[4] = {}, *nown = nullptr;
-        uint16_t *novf = nullptr;
-        auto drop_new = [&]() {
-            for (auto &p : nf) qh_release(c, p);
-            for (auto &p : ni) qh_release(c, p);
-            qh_release(c, nown), qh_release(c, novf);
-        };
-        for (auto &p : nf)
-            if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
-        for (auto &p : ni)
-            if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
-        if ((rc = qh_alloc(c, &nown, qh_species_blocks(cap) + 1)) || (rc = qh_alloc(c, &novf, qh_species_blocks(cap) * QH_CHUNK)))
-            return drop_new(), rc;
-        const int64_t nb0 = qh_species_blocks(n0);
-        for (int k = 0; k < 6; ++k)  // the particle state; the sort scratch needs no copy
-            if (n0) QH_HIP(c, hipMemcpyAsync(nf[k], *fs[k], sizeof(float) * n0, hipMemcpyDeviceToDevice, c->stream));
-        for (int k = 0; k < 2; ++k)
-            if (n0) QH_HIP(c, hipMemcpyAsync(ni[k], *is[k], sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, c->stream));
-        if (s.own) QH_HIP(c, hipMemcpyAsync(nown, s.own, sizeof(int32_t) * (nb0 + 1), hipMemcpyDeviceToDevice, c->stream));
-        QH_HIP(c, hipStreamSynchronize(c->stream));
-        for (int k = 0; k < 12; ++k) qh_release(c, *fs[k]), *fs[k] = nf[k];
-        for (int k = 0; k < 4; ++k) qh_release(c, *is[k]), *is[k] = ni[k];
-        qh_release(c, s.own), s.own = nown;
-        qh_release(c, s.ovf), s.ovf = novf;
-        s.cap = cap;
-    }
+    if (n1 > s.cap && (rc = reserve_species(c, s, std::max<int64_t>(std::max<int64_t>(2 * s.cap, n1), 4096), n0)))
+        return rc;
     // components laid out one after another; the host buffers live until the sync at the end
     std::vector<float> comp(6 * n);
     float *dst[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
@@ -914,7 +912,7 @@ int qh_fields_upload_dev(qh_ctx *c, const double *e, const int64_t *b) {
     if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
     const HostMesh &m = c->hm;
     // D b = 0 checked on the device before anything changes
-    unsigned long long *bad = c->counters + 4 * QH_COUNTER_SLOTS + 1, nbad = 0;
+    unsigned long long *bad = c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_DIVB, nbad = 0;
     QH_HIP(c, hipMemsetAsync(c->divb0, 0, sizeof(int64_t) * m.Nt, c->stream));
     QH_HIP(c, hipMemsetAsync(bad, 0, sizeof(unsigned long long), c->stream));
     QH_HIP(c, launch_divb_check(c, b, bad));
@@ -1003,10 +1001,12 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     bool use_ev = stats != nullptr;
     if (use_ev)
         for (auto &x : ev) QH_HIP(c, hipEventCreate(&x));
-    // fixed-point headroom count of the gathers (slot 3 past the per-block event counters), over
-    // the whole call; the other slots are cleared every step
-    unsigned long long *headroom = c->counters + 4 * QH_COUNTER_SLOTS + 3;
-    QH_HIP(c, hipMemsetAsync(headroom, 0, sizeof(unsigned long long), c->stream));
+    // totals of the whole call (fixed-point headroom overflows of the gathers, lost particles,
+    // verification failures), kept whether or not stats are asked for; the per-step slots before
+    // them are cleared every step
+    unsigned long long *totals = c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_HEADROOM_CALL;
+    constexpr int kTotals = QH_CNT_DIVB_CALL - QH_CNT_HEADROOM_CALL + 1;
+    QH_HIP(c, hipMemsetAsync(totals, 0, sizeof(unsigned long long) * kTotals, c->stream));
     for (int32_t st = 0; st < n_steps; ++st) {
         bool capture = c->capture_next;
         c->capture_next = false;
@@ -1020,7 +1020,8 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         std::swap(c->Q, c->Q_old);
         QH_HIP(c, hipMemsetAsync(c->Q, 0, sizeof(int64_t) * m.Nn, c->stream));
         QH_HIP(c, hipMemsetAsync(c->g, 0, sizeof(int64_t) * m.Ne, c->stream));
-        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * (4 * QH_COUNTER_SLOTS + 3), c->stream));
+        QH_HIP(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * (4 * QH_COUNTER_SLOTS + QH_CNT_STEP_END),
+                                 c->stream));
         for (size_t k = 0; k < c->species.size(); ++k) {
             int t0 = qh_tbeg(c);
             QH_HIP(c, launch_particle_step(c, c->species[k], (int)k, capture));
@@ -1055,8 +1056,11 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             if (rc) return rc;
             int fallbacks = 0;
             if (learned && !se.converged) {
-                // Jacobi restart from e^n: the learned preconditioner stalled or produced a non-finite value
-                QH_HIP(c, hipMemcpyAsync(c->cge.x, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
+                // Jacobi restart: from the learned solve's iterate when it is finite (the stall rule or
+                // the iteration cap stopped it), from e^n after non-finite values
+                if (se.flag == 3)
+                    QH_HIP(c, hipMemcpyAsync(c->cge.x, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice,
+                                             c->stream));
                 SolveResult sj;
                 rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, sj, nullptr);
                 if (rc) return rc;
@@ -1107,8 +1111,8 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
                 for (int j = 0; j < 3; ++j) cnt[j] += raw[4 * k + j];
                 cnt[5] += raw[4 * k + 3];
             }
-            cnt[3] = raw[4 * QH_COUNTER_SLOTS];
-            cnt[4] = raw[4 * QH_COUNTER_SLOTS + 1];
+            cnt[3] = raw[4 * QH_COUNTER_SLOTS + QH_CNT_CONT];
+            cnt[4] = raw[4 * QH_COUNTER_SLOTS + QH_CNT_DIVB];
             qh_step_stats_t &S = stats[st];
             std::memset(&S, 0, sizeof(S));
             S.edge_iters = se.iters;
@@ -1125,19 +1129,30 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.fallbacks = solve ? c->last_fallbacks : 0;
             (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
             (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
-            if (S.lost && status == QH_OK) status = QH_ELOST;
         }
         qh_tflush(c);
         c->step_index++;
     }
     if (use_ev)
         for (auto &x : ev) (void)hipEventDestroy(x);
-    unsigned long long nhead = 0;
-    QH_HIP(c, hipMemcpyAsync(&nhead, headroom, sizeof(nhead), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long tot[kTotals] = {};
+    QH_HIP(c, hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
-    if (status == QH_ENOTCONV) c->err = "a Krylov solve hit its iteration cap";
-    if (status == QH_ELOST) c->err = "a particle hit the walk cap";
-    if (nhead && status == QH_OK) {
+    const unsigned long long nhead = tot[0], nlost = tot[QH_CNT_LOST_CALL - QH_CNT_HEADROOM_CALL],
+                             ncont = tot[QH_CNT_CONT_CALL - QH_CNT_HEADROOM_CALL],
+                             ndivb = tot[QH_CNT_DIVB_CALL - QH_CNT_HEADROOM_CALL];
+    // the most serious failure of the call names the status: a broken invariant, then a solve
+    // at its cap, lost particles, fixed-point headroom
+    if (ncont || ndivb) {
+        status = QH_EVERIFY;
+        c->err = "verification: continuity G^T g = Q^{n+1} - Q^n failed at " + std::to_string(ncont) +
+                 " node-steps, D b changed in " + std::to_string(ndivb) + " tet-steps";
+    } else if (status == QH_ENOTCONV) {
+        c->err = "a Krylov solve hit its iteration cap";
+    } else if (nlost) {
+        status = QH_ELOST;
+        c->err = std::to_string(nlost) + " particle-steps hit the walk cap";
+    } else if (nhead) {
         status = QH_EOVERFLOW;
         c->err = std::to_string(nhead) + " edge currents or node charges of a step beyond 2^60 (int64 headroom)";
     }
@@ -1257,7 +1272,9 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     if (rc) return rc;
     int fallback = 0;
     if (learned && !r.converged) {
-        QH_HIP(c, hipMemcpyAsync(w.x, x, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
+        // Jacobi restart from the learned solve's iterate, or from the initial guess after
+        // non-finite values
+        if (r.flag == 3) QH_HIP(c, hipMemcpyAsync(w.x, x, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
         SolveResult rj;
         rc = qh_cg_solve(c, *M, w, tol, max_it, 8, rj, nullptr);
         if (rc) return rc;
@@ -1446,8 +1463,12 @@ int qh_state_load(qh_ctx *c, const void *buf, size_t len) {
         r.val<int32_t>();
         sp[k].n = r.val<int64_t>();
         sp[k].next = r.val<int64_t>();
-        if (qm != c->species[k].qm || z != c->species[k].z || sp[k].n < 0)
+        if (qm != c->species[k].qm || z != c->species[k].z)
             return qh_fail(c, QH_EINVAL, "species " + std::to_string(k) + " differs from the saved one");
+        // counts and ids are int32 on the device: anything else is a corrupted blob (and checked
+        // before any size below is formed from it)
+        if (sp[k].n < 0 || sp[k].n >= ((int64_t)1 << 31) || sp[k].next < sp[k].n || sp[k].next >= ((int64_t)1 << 31))
+            return qh_fail(c, QH_EINVAL, "state blob: species " + std::to_string(k) + " count or next id out of range");
         for (auto &a : sp[k].f) a = reinterpret_cast<const float *>(r.take(4 * sp[k].n));
         sp[k].tet = reinterpret_cast<const int32_t *>(r.take(4 * sp[k].n));
         sp[k].id = reinterpret_cast<const int32_t *>(r.take(4 * sp[k].n));
@@ -1456,11 +1477,16 @@ int qh_state_load(qh_ctx *c, const void *buf, size_t len) {
     for (const Sp &s : sp)
         for (int64_t i = 0; i < s.n; ++i)
             if (s.tet[i] < 0 || s.tet[i] >= m.Nt) return qh_fail(c, QH_EINVAL, "state blob: tet id out of range");
-    // everything checked: apply
+    // everything checked; device storage reserved before anything changes, so a failed
+    // allocation leaves the context as it was
+    int rc;
+    for (size_t k = 0; k < sp.size(); ++k)
+        if ((rc = reserve_species(c, c->species[k], sp[k].n, c->species[k].n))) return rc;
+    if (has_d && !c->dbnd && (rc = qh_alloc(c, &c->dbnd, m.Nn))) return rc;
+    // apply
     std::vector<double> ecopy(e, e + m.Ne);
     std::vector<int64_t> bcopy(b, b + m.Nf);
-    int rc = set_fields(c, ecopy.data(), bcopy.data());
-    if (rc) return rc;
+    if ((rc = set_fields(c, ecopy.data(), bcopy.data()))) return rc;
     for (size_t k = 0; k < sp.size(); ++k) {
         std::vector<float> x(3 * sp[k].n), v(3 * sp[k].n);
         for (int64_t i = 0; i < sp[k].n; ++i)
@@ -1475,10 +1501,7 @@ int qh_state_load(qh_ctx *c, const void *buf, size_t len) {
         QH_HIP(c, hipMemcpy(c->g_prev, gp, 8 * m.Ne, hipMemcpyHostToDevice));
     }
     c->wave_hist = wave;
-    if (has_d) {
-        if (!c->dbnd && (rc = qh_alloc(c, &c->dbnd, m.Nn))) return rc;
-        QH_HIP(c, hipMemcpy(c->dbnd, d, 8 * m.Nn, hipMemcpyHostToDevice));
-    }
+    if (has_d) QH_HIP(c, hipMemcpy(c->dbnd, d, 8 * m.Nn, hipMemcpyHostToDevice));
     c->step_index = hdr[6];
     c->fields_dirty = true;
     return QH_OK;
@@ -1534,6 +1557,24 @@ int qh_precond_factor(qh_ctx *c, int64_t *nnz, int32_t *rows, int32_t *cols, flo
     if (rows) std::copy(L.h_row.begin(), L.h_row.end(), rows);
     if (cols) std::copy(L.h_col.begin(), L.h_col.end(), cols);
     if (vals) QH_HIP(c, hipMemcpyAsync(vals, L.gval, 4 * L.nnz, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int qh_precond_apply(qh_ctx *c, const double *r, double *z) {
+    if (!c || !r || !z) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    if (!c->lp.factor_valid && (rc = qh_learned_factor(c))) return rc;
+    const int32_t n = c->A.n;
+    int32_t nmax = std::max(c->A.n, c->K.n);
+    if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
+    // r in the standalone solve's residual slot, z in its preconditioned slot; the r.z partials
+    // go to its partial buffer (unused here)
+    QH_HIP(c, hipMemcpyAsync(c->cgx.r, r, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    QH_HIP(c, launch_prec_apply(c, c->cgx.r, c->cgx.z, c->cgx.partial, nullptr));
+    QH_HIP(c, hipMemcpyAsync(z, c->cgx.z, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
     return sync(c);
 }
 

@@ -13,6 +13,12 @@ constexpr int QH_FBITS = 20;                  // fixed-point bits of barycentric
 constexpr int QH_SCALE = 1 << QH_FBITS;
 constexpr int QH_MAX_PIECES = 64;             // straight pieces per particle per step
 constexpr int QH_COUNTER_SLOTS = 256;         // spread of the per-block event counters
+// Counters past the 4 * QH_COUNTER_SLOTS per-block slots (crossings, wall hits, lost, posted
+// pieces): the step's continuity and D b violations, cleared every step, then the totals of a
+// whole qh_pic_step call (cleared when the call starts): headroom overflows, lost particles,
+// continuity and D b violations.
+enum { QH_CNT_CONT = 0, QH_CNT_DIVB = 1, QH_CNT_STEP_END = 3, QH_CNT_HEADROOM_CALL = 3, QH_CNT_LOST_CALL = 4,
+       QH_CNT_CONT_CALL = 5, QH_CNT_DIVB_CALL = 6, QH_CNT_ALL = 8 };
 constexpr int QH_CHUNK = 512;                 // particles per block of the particle kernels
 constexpr int kMailTets = 128;                // tets per deposit mailbox
 constexpr int kMailCap = 1024;                // records per mailbox
@@ -217,8 +223,7 @@ struct qh_ctx {
     int32_t *loc_seed = nullptr;
     float loc_lo[3] = {0, 0, 0}, loc_inv[3] = {0, 0, 0};
     int32_t loc_n[3] = {0, 0, 0};
-    unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS slots (crossings, wall hits,
-                                             // lost), then continuity and D b violations
+    unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS + QH_CNT_ALL (see QH_CNT_*)
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
 
     std::vector<Species> species;
@@ -311,8 +316,12 @@ hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x);
 // qh_solver.hip
 struct SolveResult {
     int iters = 0;
-    double res = 0.0;
-    bool converged = false;
+    double res = 0.0;       // recomputed ||b - A x|| / ||b||
+    bool converged = false; // the recurrence met the target and so did the recomputed residual
+    bool true_ok = false;   // the recomputed residual meets the target
+    int flag = 0;           // why the iteration stopped: 0 iteration cap, 1 target met, 2 stall rule
+                            // (learned preconditioner), 3 non-finite values
+    int restarts = 0;       // restarts from the iterate after the recomputed residual missed the target
 };
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
 // Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.

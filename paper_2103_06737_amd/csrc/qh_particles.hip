@@ -568,6 +568,8 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     if (lane < 4) {
         const unsigned int v = lane == 0 ? n_cross : lane == 1 ? n_wall : lane == 2 ? n_lost : n_foreign + s_cnt[4];
         if (v) atomicAdd(&a.counters[(blockIdx.x & (QH_COUNTER_SLOTS - 1)) * 4 + lane], (unsigned long long)v);
+        // lost particles also into the total of the whole step call, which no step clears
+        if (lane == 2 && v) atomicAdd(&a.counters[4 * QH_COUNTER_SLOTS + QH_CNT_LOST_CALL], (unsigned long long)v);
     }
 }
 
@@ -706,7 +708,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     constexpr int kLpiE = 2, kLpiN = 8;  // lanes per edge / per node (edges border 4-6 tets, nodes ~24)
     const unsigned ge = (unsigned)(((m.Ne + 256 / kLpiE - 1) / (256 / kLpiE) + 7) / 8 * 8);
     const unsigned gn = (unsigned)(((m.Nn + 256 / kLpiN - 1) / (256 / kLpiN) + 7) / 8 * 8);
-    unsigned long long *headroom = c->counters + 4 * QH_COUNTER_SLOTS + 3;  // kept over a pic_step call
+    unsigned long long *headroom = c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_HEADROOM_CALL;
     hipLaunchKernelGGL((k_gather<0, kLpiE>), dim3(ge), dim3(256), 0, c->stream, m.Ne, c->e2t_ptr, c->e2t, c->acc_tet,
                        m.Nt, c->g, ge, headroom);
     hipLaunchKernelGGL((k_gather<6, kLpiN>), dim3(gn), dim3(256), 0, c->stream, m.Nn, c->n2t_ptr, c->n2t, c->acc_tet,
@@ -911,7 +913,7 @@ hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet
 __global__ void k_continuity(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lst,
                              const int64_t *__restrict__ g, const int64_t *__restrict__ Q,
                              const int64_t *__restrict__ Qo, const uint8_t *__restrict__ skip, int64_t nn,
-                             unsigned long long *bad) {
+                             unsigned long long *bad, unsigned long long *bad_total) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn || (skip && skip[n])) return;
     int64_t s = 0;
@@ -919,28 +921,35 @@ __global__ void k_continuity(const int32_t *__restrict__ ptr, const int32_t *__r
         int32_t v = lst[j];
         s += v > 0 ? g[v - 1] : -g[-v - 1];
     }
-    if (s != Q[n] - Qo[n]) atomicAdd(bad, 1ull);
+    if (s != Q[n] - Qo[n]) {
+        atomicAdd(bad, 1ull);
+        atomicAdd(bad_total, 1ull);
+    }
 }
 
 __global__ void k_divb(const int32_t *__restrict__ tfaces, const int8_t *__restrict__ tsign,
                        const int64_t *__restrict__ b, int32_t nt, int64_t *__restrict__ out,
-                       const int64_t *__restrict__ ref, unsigned long long *bad) {
+                       const int64_t *__restrict__ ref, unsigned long long *bad, unsigned long long *bad_total) {
     int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     int64_t s = (int64_t)tsign[t] * (b[tfaces[4 * t]] - b[tfaces[4 * t + 1]] + b[tfaces[4 * t + 2]] - b[tfaces[4 * t + 3]]);
     if (out) out[t] = s;
-    if (ref && s != ref[t]) atomicAdd(bad, 1ull);
+    if (ref && s != ref[t]) {
+        atomicAdd(bad, 1ull);
+        if (bad_total) atomicAdd(bad_total, 1ull);
+    }
 }
 
 hipError_t launch_verify(qh_ctx *c, bool check_divb) {
     int64_t nn = c->hm.Nn;
     hipLaunchKernelGGL(k_continuity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, c->n2e_ptr,
                        c->n2e, c->g, c->Q, c->Q_old, c->walls == QH_WALLS_ABSORB ? c->wall_node_d : nullptr, nn,
-                       c->counters + 4 * QH_COUNTER_SLOTS);
+                       c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_CONT, c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_CONT_CALL);
     if (check_divb) {
         int32_t nt = (int32_t)c->hm.Nt;
         hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
-                           (int64_t *)nullptr, c->divb0, c->counters + 4 * QH_COUNTER_SLOTS + 1);
+                           (int64_t *)nullptr, c->divb0, c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_DIVB,
+                           c->counters + 4 * QH_COUNTER_SLOTS + QH_CNT_DIVB_CALL);
     }
     return hipGetLastError();
 }
@@ -949,7 +958,7 @@ hipError_t launch_verify(qh_ctx *c, bool check_divb) {
 hipError_t launch_divb_check(qh_ctx *c, const int64_t *b, unsigned long long *bad) {
     int32_t nt = (int32_t)c->hm.Nt;
     hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, b, nt,
-                       (int64_t *)nullptr, (const int64_t *)c->divb0, bad);
+                       (int64_t *)nullptr, (const int64_t *)c->divb0, bad, (unsigned long long *)nullptr);
     return hipGetLastError();
 }
 
@@ -974,7 +983,7 @@ hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x) {
 hipError_t launch_divb(qh_ctx *c, int64_t *out) {
     int32_t nt = (int32_t)c->hm.Nt;
     hipLaunchKernelGGL(k_divb, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->tfaces, c->tsign, c->b, nt,
-                       out, (const int64_t *)nullptr, (unsigned long long *)nullptr);
+                       out, (const int64_t *)nullptr, (unsigned long long *)nullptr, (unsigned long long *)nullptr);
     return hipGetLastError();
 }
 

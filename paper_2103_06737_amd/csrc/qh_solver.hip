@@ -17,8 +17,16 @@ constexpr int kThreads = 256;
 constexpr int kLpr = 8;          // lanes per CSR row
 constexpr int kMaxBlocks = 2048; // fixed grid of the reducing kernels (fixed summation order)
 
-// device scalar slots of a CgWork
-enum { S_RZ = 0, S_RZ1, S_RR, S_THR2, S_BB, S_NSLOT };  // S_RZ + parity: r.z (double-buffered)
+// device scalar slots of a CgWork: S_RZ + parity r.z (double-buffered), S_RR r.r, S_THR2 the
+// target on r.r, S_BB b.b, S_RES the true-residual sums, S_HIST a ring of r.r by iteration
+// (the stall rule compares r.r with its value ten iterations before)
+enum { S_RZ = 0, S_RZ1, S_RR, S_THR2, S_BB, S_RES = 8, S_HIST = 16, S_NSCAL = 32 };
+constexpr int kHist = 16;
+// flags[0] after a solve: why the iteration stopped
+enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_STALLED = 2, CG_NONFINITE = 3 };
+// stall rule of the learned solve: r.z <= 0, or ||r|| not 10 % lower than ten iterations before
+constexpr int kStallWindow = 10;
+constexpr double kStallRatio2 = 0.81;  // (1 - 0.1)^2 on r.r
 
 __device__ __forceinline__ double wave_sum_lpr(double v) {
 #pragma unroll
@@ -124,10 +132,24 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(const int2 *__restrict__ t
     write_partials<3>(acc, part);
 }
 
+// Why an iteration stops, from r.r and r.z of the present iterate (the same sums, so the same
+// decision, in every block): non-finite values, convergence, and for the learned
+// preconditioner the stall rule (r.z <= 0 means M is not positive definite on r; ||r|| less
+// than 10 % lower than ten iterations before). hist: r.r by iteration (ring), or null.
+__device__ __forceinline__ int cg_state(double rr, double rz, double thr2, int stall, int32_t k, const double *hist) {
+    if (!(rr == rr) || !(rz == rz) || rr > 1.7976931348623157e308) return CG_NONFINITE;
+    if (rr <= thr2) return CG_CONVERGED;
+    if (stall) {
+        if (!(rz > 0.0)) return CG_STALLED;
+        if (hist && k >= kStallWindow && rr > kStallRatio2 * hist[(k - kStallWindow) & (kHist - 1)]) return CG_STALLED;
+    }
+    return CG_RUNNING;
+}
+
 // one block: totals of the init partials; threshold; convergence flag
 __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict__ part, int m,
                                                        const double *__restrict__ rz_part, int m_rz, double *scal,
-                                                       int32_t *flags, double tol2, const double *abs_thr2) {
+                                                       int32_t *flags, double tol2, const double *abs_thr2, int stall) {
     __shared__ double sh[kThreads / 64];
     double rz = sum_partials(rz_part, m_rz, sh);
     double rr = sum_partials(part + kMaxBlocks, m, sh);
@@ -138,7 +160,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict_
         scal[S_RR] = rr;
         scal[S_BB] = bb;
         scal[S_THR2] = thr2;
-        flags[0] = (rr <= thr2) ? 1 : 0;
+        scal[S_HIST] = rr;
+        flags[0] = cg_state(rr, rz, thr2, stall, 0, nullptr);
         flags[1] = 0;
     }
 }
@@ -156,7 +179,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8
                                                       const double *__restrict__ rz_part, int m_rz,
                                                       const double *__restrict__ rr_part, int m_rr,
                                                       double *__restrict__ part, double *scal, int32_t *flags,
-                                                      int32_t k, int32_t par) {
+                                                      int32_t k, int32_t par, int stall) {
     if (flags[0]) return;
     __shared__ double sh[kThreads / 64];
     __shared__ double prod[kTileCap];
@@ -164,14 +187,17 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8
     if (k > 0) {
         double rz_new = sum_partials(rz_part, m_rz, sh);
         double rr = sum_partials(rr_part, m_rr, sh);
-        bool done = rr <= scal[S_THR2] || !(rr == rr);
+        // the ring slot read (k - 10) differs from the one written (k): no block reads what
+        // block 0 writes in this launch
+        const int state = cg_state(rr, rz_new, scal[S_THR2], stall, k, scal + S_HIST);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             scal[S_RZ + (par ^ 1)] = rz_new;
             scal[S_RR] = rr;
+            scal[S_HIST + (k & (kHist - 1))] = rr;
             flags[1] = k;
-            if (done) flags[0] = 1;
+            if (state) flags[0] = state;
         }
-        if (done) return;  // the same decision in every block (same sums, same order)
+        if (state) return;  // the same decision in every block (same sums, same order)
         beta = rz_new / scal[S_RZ + par];
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[S_RZ + 1] = scal[S_RZ];
@@ -225,7 +251,10 @@ __global__ void __launch_bounds__(kThreads) k_cg_check(const double *__restrict_
     if (threadIdx.x == 0) {
         scal[S_RR] = rr;
         flags[1] = k;
-        if (rr <= scal[S_THR2] || !(rr == rr)) flags[0] = 1;
+        // convergence or a non-finite residual; the stall rule waits for the next product
+        // kernel, which also has r.z
+        const int state = cg_state(rr, 1.0, scal[S_THR2], 0, k, nullptr);
+        if (state) flags[0] = state;
     }
 }
 
@@ -482,12 +511,12 @@ int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n) {
     if ((rc = qh_alloc(c, &w.x, n)) || (rc = qh_alloc(c, &w.r, n)) || (rc = qh_alloc(c, &w.z, n)) ||
         (rc = qh_alloc(c, &w.q, n)) || (rc = qh_alloc(c, &w.p0, n)) || (rc = qh_alloc(c, &w.p1, n)) ||
         (rc = qh_alloc(c, &w.dinv, n)) || (rc = qh_alloc(c, &w.b, n)) ||
-        (rc = qh_alloc(c, &w.partial, 8 * kMaxBlocks)) || (rc = qh_alloc(c, &w.scal, 16)) ||
+        (rc = qh_alloc(c, &w.partial, 8 * kMaxBlocks)) || (rc = qh_alloc(c, &w.scal, S_NSCAL)) ||
         (rc = qh_alloc(c, &w.counter, 4)) || (rc = qh_alloc(c, &w.flags, 4)))
         return rc;
     QH_HIP(c, hipMemsetAsync(w.counter, 0, 4 * sizeof(unsigned int), c->stream));
     QH_HIP(c, hipMemsetAsync(w.x, 0, n * sizeof(double), c->stream));
-    QH_HIP(c, hipMemsetAsync(w.scal, 0, 16 * sizeof(double), c->stream));
+    QH_HIP(c, hipMemsetAsync(w.scal, 0, S_NSCAL * sizeof(double), c->stream));
     return QH_OK;
 }
 
@@ -503,6 +532,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     out = SolveResult();
     if (w.n == 0) {
         out.converged = true;
+        out.flag = CG_CONVERGED;
         return QH_OK;
     }
     // partials: [0, 4K) init / update (slot 0 r.z with Jacobi, 1 r.r, 2 b.b), [4K, 5K) products,
@@ -510,66 +540,81 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks, *ppart = w.partial + 5 * kMaxBlocks;
     const unsigned ge = grid_elems(w.n), gt = tile_grid(M.ntiles);
     const unsigned gp = learned ? qh_prec_grid(c) : 0;
-    int t0 = qh_tbeg(c);
-    hipLaunchKernelGGL(k_cg_init, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val, w.x,
-                       w.b, w.dinv, w.r, w.z, w.p0, upart);
-    if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, nullptr));
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt,
-                       learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gt, w.scal,
-                       w.flags, tol * tol, abs_thr2_dev);
-    qh_tend(c, t0, QK_CG_INIT);
-    QH_HIP(c, hipGetLastError());
+    const int stall = learned ? 1 : 0;
     if (check_every <= 0) check_every = 8;
-    int32_t hflags[2] = {0, 0};
-    int it = 0;
-    int m_up = (int)gt;
-    QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
-    QH_HIP(c, hipStreamSynchronize(c->stream));
     // iterations after convergence return at once on the device; sizing the first batch from
     // the previous solve avoids most of them and most host reads of the flag
     int first = w.last_iters[learned ? 1 : 0];
-    while (it < max_it && !hflags[0]) {
-        int batch = std::min(it == 0 && first > 0 ? first : check_every, max_it - it);
-        for (int k = it; k < it + batch; ++k) {
-            int par = k & 1;
-            int ta = qh_tbeg(c);
-            hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr, M.cols(),
-                               M.val, w.z, w.p0, w.q, learned ? (const double *)ppart : (const double *)upart,
-                               learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par);
-            qh_tend(c, ta, k_spmv);
-            int tb = qh_tbeg(c);
-            if (learned)
-                hipLaunchKernelGGL(k_cg_update<false>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
-                                   w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
-            else
-                hipLaunchKernelGGL(k_cg_update<true>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z, w.p0,
-                                   w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
-            qh_tend(c, tb, k_upd);
-            m_up = (int)ge;
-            if (learned) {
-                int tp = qh_tbeg(c);
-                QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, w.flags));
-                qh_tend(c, tp, QK_PREC);
-            }
-        }
-        it += batch;
-        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags, it);
+    int it = 0;
+    // Recurrence residuals drift from the true one; a solve whose recurrence converged but whose
+    // recomputed residual misses the target restarts from its iterate (at most kRestarts times)
+    constexpr int kRestarts = 2;
+    for (int restart = 0;; ++restart) {
+        int t0 = qh_tbeg(c);
+        hipLaunchKernelGGL(k_cg_init, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val,
+                           w.x, w.b, w.dinv, w.r, w.z, w.p0, upart);
+        if (learned) QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, nullptr));
+        hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt,
+                           learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)gt,
+                           w.scal, w.flags, tol * tol, abs_thr2_dev, stall);
+        qh_tend(c, t0, QK_CG_INIT);
         QH_HIP(c, hipGetLastError());
+        int32_t hflags[2] = {0, 0};
+        int m_up = (int)gt;
         QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
+        const int it0 = it;  // the device counts this run's iterations from 0
+        while (it < max_it && !hflags[0]) {
+            int batch = std::min(it == it0 && first > 0 && restart == 0 ? first : check_every, max_it - it);
+            for (int k = it - it0; k < it - it0 + batch; ++k) {
+                int par = k & 1;
+                int ta = qh_tbeg(c);
+                hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr,
+                                   M.cols(), M.val, w.z, w.p0, w.q, learned ? (const double *)ppart : (const double *)upart,
+                                   learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par,
+                                   stall);
+                qh_tend(c, ta, k_spmv);
+                int tb = qh_tbeg(c);
+                if (learned)
+                    hipLaunchKernelGGL(k_cg_update<false>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
+                                       w.p0, w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
+                else
+                    hipLaunchKernelGGL(k_cg_update<true>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
+                                       w.p0, w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
+                qh_tend(c, tb, k_upd);
+                m_up = (int)ge;
+                if (learned) {
+                    int tp = qh_tbeg(c);
+                    QH_HIP(c, launch_prec_apply(c, w.r, w.z, ppart, w.flags));
+                    qh_tend(c, tp, QK_PREC);
+                }
+            }
+            it += batch;
+            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags,
+                               it - it0);
+            QH_HIP(c, hipGetLastError());
+            QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
+        it = it0 + hflags[1];
+        out.iters = it;
+        out.flag = hflags[0];
+        // true residual, recomputed with a fresh FP64 product, against the same target
+        int tr = qh_tbeg(c);
+        hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val,
+                           w.x, w.b, upart);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + S_RES);
+        qh_tend(c, tr, QK_TRUE_RES);
+        double sc[S_RES + 2];
+        QH_HIP(c, hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        const double res2 = sc[S_RES], bb2 = sc[S_RES + 1], thr2 = sc[S_THR2];
+        out.res = bb2 > 0 ? sqrt(res2 / bb2) : 0.0;
+        out.true_ok = res2 == res2 && res2 <= thr2;
+        out.converged = out.flag == CG_CONVERGED && out.true_ok;
+        if (out.converged || out.flag != CG_CONVERGED || it >= max_it || restart == kRestarts) break;
+        out.restarts = restart + 1;
     }
-    out.iters = hflags[1];
-    // true residual, recomputed
-    int tr = qh_tbeg(c);
-    hipLaunchKernelGGL(k_true_res, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val, w.x,
-                       w.b, upart);
-    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + 8);
-    qh_tend(c, tr, QK_TRUE_RES);
-    double res2[2];
-    QH_HIP(c, hipMemcpyAsync(res2, w.scal + 8, sizeof(res2), hipMemcpyDeviceToHost, c->stream));
-    QH_HIP(c, hipStreamSynchronize(c->stream));
-    out.res = res2[1] > 0 ? sqrt(res2[0] / res2[1]) : 0.0;
-    out.converged = hflags[0] != 0 && out.res == out.res;
     if (out.converged) w.last_iters[learned ? 1 : 0] = out.iters;
     return QH_OK;
 }

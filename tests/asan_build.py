@@ -2,7 +2,7 @@
 a GPU run): libqh_asan.so (the library with its host pass instrumented; device code as usual)
 and the oracle's liborc_asan.so. Run them with the matching runtime preloaded (see runtime()).
 
-    python -m paper_2103_06737_amd.asan_build
+    python -m tests.asan_build
 """
 from __future__ import annotations
 
@@ -11,11 +11,11 @@ import glob
 import os
 import subprocess
 
-from .build import CSRC, FLAGS, HIPCC, SOURCES
+from paper_2103_06737_amd.build import CSRC, FLAGS, HIPCC, SOURCES
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT_DIR = os.path.join(HERE, "_build_asan")
-LIB = os.path.join(HERE, "libqh_asan.so")
+LIB = os.path.join(OUT_DIR, "libqh_asan.so")
 # host pass only: each sanitizer flag goes to the host compilation
 HOST_ASAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
 

@@ -7,6 +7,25 @@ import qh_inputs as qi
 S = 1 << 20
 
 
+def record(name, data):
+    """Measured figures for the documentation (error tables), written as JSON when the
+    environment variable QH_RECORD_DIR names a folder; nothing otherwise."""
+    import json
+    import os
+    d = os.environ.get("QH_RECORD_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name + ".json"), "w") as fh:
+            json.dump(data, fh, indent=1, default=float)
+
+
+def err_stats(a):
+    """max and 99th percentile of an array of errors."""
+    a = np.asarray(a, np.float64).ravel()
+    return {"max": float(a.max()) if a.size else 0.0, "p99": float(np.quantile(a, 0.99)) if a.size else 0.0,
+            "n": int(a.size)}
+
+
 def gpu_context(mesh, dt, weight=1.0, u_b=2.0 ** -56):
     import paper_2103_06737_amd as qh
     ctx = qh.Context(0)

@@ -13,7 +13,7 @@ import pytest
 
 import qh_inputs as qi
 
-from .gpu_setup import S, gpu_context, oracle_fields, oracle_setup
+from .gpu_setup import S, err_stats, gpu_context, oracle_fields, oracle_setup, record
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,19 @@ def test_plasma64_full_cycle(plasma64):
     assert same.mean() > 0.999
     assert np.abs(xg[idx] - orc["x"]).max(axis=1)[same].max() < 1e-5
     assert (np.abs(vg[idx] - orc["v"]).max(axis=1)[same] / np.abs(orc["v"]).max()).max() < 1e-5
+    # the FP32 gather (the push's per-tet records, read through the probe) against FP64 at the
+    # sampled particles' new points in the new fields
+    e1p, b1p = ctx.fields_download()
+    Ep, Bp = ctx.probe_fields(xg[idx].astype(np.float64), tg[idx])
+    Eo, Bo = po.gather(e1p, b1p * U_B, xg[idx].astype(np.float64), tg[idx])
+    assert np.abs(Ep - Eo).max() <= 1e-5 * np.abs(Eo).max()
+    assert np.abs(Bp - Bo).max() <= 1e-5 * np.abs(Bo).max()
+    record("plasma64_one_step", dict(
+        E_rel=err_stats(np.abs(Ep - Eo).max(axis=1) / np.abs(Eo).max()),
+        B_rel=err_stats(np.abs(Bp - Bo).max(axis=1) / np.abs(Bo).max()),
+        x_abs_m=err_stats(np.abs(xg[idx] - orc["x"]).max(axis=1)[same]),
+        v_rel=err_stats(np.abs(vg[idx] - orc["v"]).max(axis=1)[same] / np.abs(orc["v"]).max()),
+        same_tet=float(same.mean())))
 
     # the field update of this step, piece by piece against the oracle's FP64 operators:
     # right-hand side of the edge system (same sums, another order), the solution's residual,
@@ -159,6 +172,55 @@ def test_plasma64_100_steps(plasma64):
     idx = np.random.default_rng(9).choice(tg.size, 200_000, replace=False)
     lam = np.einsum("pij,pj->pi", op.Minv[tg[idx]], np.column_stack([np.ones(idx.size), xg[idx].astype(np.float64)]))
     assert lam.min() > -1e-5
+    ctx.close()
+
+
+def test_plasma64_preconditioner_application_sampled_rows(plasma64):
+    """The learned preconditioner's application z = G^T (G r) on the 64^3 edge system (1.8 M
+    rows) in the launch configuration of the cycle, on 512 sampled rows: against the oracle's
+    FP64 factor of the same weights, built only on the rows those outputs need (the rows k with
+    G_ki != 0 for a sampled i, each whole), within the bound of the factor's error model; and
+    against FP64 products of the kernels' own factor rounded to BF16, within the rounding of
+    the sums."""
+    import scipy.sparse as sp
+    from oracle import learned as Lr
+    from .test_gpu_learned import _bf16, _flat, _unflat, _weights, factor_model
+    cfg, mesh, parts, cx, op, po = plasma64
+    dt = cfg["dt"]
+    tau = dt * dt / 4
+    ctx = gpu_context(mesh, dt, weight=cfg["weight"])
+    w = _weights(6)
+    w32 = _unflat(_flat(w).astype(np.float64))
+    ctx.precond_set_weights(_flat(w))
+    ie = cx.int_edges
+    Me = op.Meps[ie][:, ie].tocsr()
+    Sm = op.S[ie][:, ie].tocsr()
+    A = (Me + tau * Sm).tocsr()
+    n = A.shape[0]
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(n)
+    z = ctx.precond_apply(r)
+    sample = np.sort(rng.choice(n, 512, replace=False))
+    L = sp.tril(A, format="csr")
+    LT = L.T.tocsr()                      # row i of L^T: the rows k >= i with L_ki != 0
+    need = np.unique(np.concatenate([LT.indices[LT.indptr[i]:LT.indptr[i + 1]] for i in sample]))
+    rows = np.repeat(need, np.diff(L.indptr)[need])
+    cols = np.concatenate([L.indices[L.indptr[k]:L.indptr[k + 1]] for k in need])
+    ev = (cx.xyz[cx.edges[:, 1]] - cx.xyz[cx.edges[:, 0]])[ie]
+    f = Lr.features(A, Me, Sm, tau, ev, rows, cols)
+    o, _ = Lr.mlp_forward(w32, f)
+    G, gref = Lr.factor(o, rows, cols, A.diagonal(), n)
+    Gm, bound = factor_model(w32, f, rows, cols, A.diagonal())
+    dG = sp.csr_matrix((np.abs(Gm - gref) + bound + 2.0 ** -8 * (np.abs(Gm) + bound), (rows, cols)), shape=(n, n))
+    aG, ar = abs(G), np.abs(r)
+    zo = (G.T @ (G @ r))[sample]
+    tol = (aG.T @ (dG @ ar) + dG.T @ (aG @ ar) + dG.T @ (dG @ ar) + 1e-13 * (aG.T @ (aG @ ar)))[sample]
+    assert (np.abs(z[sample] - zo) <= tol).all()
+    gr, gc, gv = ctx.precond_factor()
+    Gb = sp.csr_matrix((_bf16(gv), (gr, gc)), shape=(n, n))
+    zb = Gb.T @ (Gb @ r)
+    aGb = abs(Gb)
+    assert (np.abs(z - zb) <= 64 * np.finfo(float).eps * (aGb.T @ (aGb @ ar))).all()
     ctx.close()
 
 
@@ -353,6 +415,8 @@ def test_beam32_200_steps():
     xg, vg, tg = ctx.particles_download(sid)
     assert np.array_equal(tg, to)
     assert np.abs(xg - xo).max() <= 1e-5
+    record("beam32_200_steps", dict(x_abs_m=err_stats(np.abs(xg - xo).max(axis=1)),
+                                    v_rel=err_stats(np.abs(vg - vo).max(axis=1) / np.abs(vo).max())))
 
 
 def test_graded96_two_species():
@@ -380,6 +444,25 @@ def test_graded96_two_species():
         ctx.particles_upload(ctx.species_add(qm, z), x, v, tet)
     ctx.charge_background(1)
     cx = Complex(mesh.xyz, mesh.tets)
+    # one step of both species against the oracle's push of 4096 sampled particles of each, with
+    # the species' own q/m and charge number, through the same start fields
+    from oracle.particles import ParticleOracle
+    from oracle.whitney import barycentric
+    po = ParticleOracle(cx, barycentric(cx)[0])
+    e0, b0 = ctx.fields_download()
+    start = {k: ctx.particles_download(s) for k, s in enumerate((0, 1))}
+    ctx.pic_step(ctx.step_params(verify=1))
+    rng = np.random.default_rng(96)
+    for k, (qm, z) in enumerate(((-qi.QE / qi.ME, -1), (qi.QE / qi.MI, 1))):
+        x, v, tet = start[k]
+        xg, vg, tg = ctx.particles_download(k)
+        idx = rng.choice(tet.size, 4096, replace=False)
+        orc = po.push(e0, b0 * U_B, x[idx], v[idx], tet[idx], qm, cfg["dt"], z)
+        same = tg[idx] == orc["tet"]
+        assert same.mean() > 0.999, k
+        assert np.abs(xg[idx] - orc["x"]).max(axis=1)[same].max() < 1e-5, k
+        assert (np.abs(vg[idx] - orc["v"]).max(axis=1)[same] / np.abs(orc["v"]).max()).max() < 1e-5, k
+    del start, po
     iters = {}
     for pc in (qh.PC_JACOBI, qh.PC_LEARNED):
         if pc == qh.PC_LEARNED:

@@ -10,8 +10,8 @@ import pytest
 
 import qh_inputs as qi
 
-from .gpu_setup import (S, chained_segments, gpu_context, node_charge, oracle_fields,
-                        oracle_setup)
+from .gpu_setup import (S, chained_segments, err_stats, gpu_context, node_charge, oracle_fields,
+                        oracle_setup, record)
 
 pytestmark = pytest.mark.gpu
 
@@ -127,7 +127,90 @@ def test_one_step_fp32_vs_fp64(jitter4):
     i0 = order[first]
     lam0 = np.einsum("pij,pj->pi", op.Minv[seg["tet"][i0], :, 1:], r["x0"][seg["pid"][i0]].astype(np.float64)) \
         + op.Minv[seg["tet"][i0], :, 0]
-    assert np.abs(seg["lam0"][i0] - np.clip(lam0, 0, 1) * S).max() <= 64
+    dlam = np.abs(seg["lam0"][i0] - np.clip(lam0, 0, 1) * S)
+    # FP32 barycentrics of a start point err by about |grad lambda| |x| 2^-24 (a unit of 2^-20 or
+    # less here); rounding adds half a unit per coordinate and the largest coordinate takes the
+    # other three's remainder: at most 4 units
+    assert dlam.max() <= 4
+    # the FP32 gather (per-tet records read through the probe) against FP64 at the start points
+    Ep, Bp = r["ctx"].probe_fields(r["x0"].astype(np.float64), r["t0"])
+    Eo, Bo = po.gather(e, b * U_B, r["x0"].astype(np.float64), r["t0"])
+    assert np.abs(Ep - Eo).max() <= 1e-5 * np.abs(Eo).max()
+    assert np.abs(Bp - Bo).max() <= 1e-5 * np.abs(Bo).max()
+    record("jitter4_one_step", dict(
+        E_rel=err_stats(np.abs(Ep - Eo).max(axis=1) / np.abs(Eo).max()),
+        B_rel=err_stats(np.abs(Bp - Bo).max(axis=1) / np.abs(Bo).max()),
+        x_abs_m=err_stats(dx[same]), v_rel=err_stats(dv[same]), lambda_units=err_stats(dlam),
+        same_tet=float(same.mean())))
+
+
+def test_two_species_vs_oracle(jitter4):
+    """Electrons (q/m = -e/m_e, z = -1) and ions (q/m = +e/(1836 m_e), z = +1, the graded
+    workload's second species) in one context: after one step each species' positions and
+    velocities against the oracle's push with its own q/m and charge number (1e-5), both
+    species' pieces re-deposited by the oracle with their signs give g and Q bit for bit, and
+    continuity holds on the host; then 20 steps under tie-consistent replay per species."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    dt = 2e-9
+    xe, ve, te = parts["e"]
+    ve = (ve * 20.0).astype(np.float32)
+    rng = np.random.default_rng(41)
+    # quiet start: each ion on an electron's position, thermal speeds raised so ions cross tets
+    xi, ti = xe.copy(), te.copy()
+    vi = rng.normal(0.0, 3e7, xe.shape).astype(np.float32)
+    sp = {"e": (-qi.QE / qi.ME, -1, xe, ve, te), "i": (qi.QE / qi.MI, 1, xi, vi, ti)}
+    ctx = gpu_context(mesh, dt)
+    ctx.fields_upload(e, b)
+    sid = {k: ctx.species_add(qm, z) for k, (qm, z, *_r) in sp.items()}
+    for k, (qm, z, x, v, t) in sp.items():
+        ctx.particles_upload(sid[k], x, v, t)
+    _, Q0 = ctx.deposits_download()
+    assert not Q0.any()                                    # quiet start: neutral node by node
+    ctx.capture_segments(64 * 2 * xe.shape[0])
+    st = ctx.pic_step(ctx.step_params(verify=1))[0]
+    assert st["continuity_bad"] == 0 and st["lost"] == 0 and st["crossings"] > 500
+    g, Q1 = ctx.deposits_download()
+    assert np.array_equal(cx.G.T @ g, Q1 - Q0)
+    for k, (qm, z, x, v, t) in sp.items():
+        xg, vg, tg = ctx.particles_download(sid[k])
+        orc = po.push(e, b * U_B, x, v, t, qm, dt, z)
+        same = tg == orc["tet"]
+        assert same.mean() > 0.99, k
+        assert np.abs(xg - orc["x"]).max(axis=1)[same].max() < 1e-5, k
+        assert (np.abs(vg - orc["v"]).max(axis=1)[same] / np.abs(orc["v"]).max()).max() < 1e-5, k
+    nseg, seg = ctx.segments_download()
+    assert nseg == seg["tet"].size
+    zs = np.where(seg["species"] == sid["e"], -1, 1)
+    g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], zs, np.zeros(0), np.zeros((0, 4)), np.zeros(0))
+    assert np.array_equal(g_re, g)
+    order = np.lexsort((seg["seq"], seg["pid"], seg["species"]))
+    key = seg["species"][order] * (1 << 32) + seg["pid"][order]
+    last = np.r_[key[1:] != key[:-1], True]
+    assert last.sum() == 2 * xe.shape[0]
+    _, Q_re = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                              seg["tet"][order][last], seg["lam1"][order][last], zs[order][last])
+    assert np.array_equal(Q_re, Q1)
+    # 20 more steps, each species replayed by the oracle with its own q/m and z
+    state = {k: [ctx.particles_download(sid[k])[j].astype(np.float64 if j < 2 else np.int64) for j in range(3)]
+             for k in sp}
+    for _ in range(20):
+        st = ctx.pic_step(ctx.step_params(verify=1))[0]
+        assert st["continuity_bad"] == 0 and st["lost"] == 0
+        for k, (qm, z, *_r) in sp.items():
+            xo, vo, to = state[k]
+            out = po.push(e, b * U_B, xo, vo, to, qm, dt, z)
+            xo, vo, to = out["x"], out["v"], out["tet"]
+            xg, _, tg = ctx.particles_download(sid[k])
+            for i in np.flatnonzero(tg != to):
+                lam = op.Minv[tg[i], :, 0] + op.Minv[tg[i], :, 1:] @ xo[i]
+                if lam.min() >= -1e-5:
+                    to[i] = tg[i]
+            state[k] = [xo, vo, to]
+    for k in sp:
+        xg, vg, tg = ctx.particles_download(sid[k])
+        assert np.array_equal(tg, state[k][2]), k
+        assert np.abs(xg - state[k][0]).max() <= 1e-5, k
 
 
 def test_positions_100_steps_tie_consistent(jitter4):
@@ -157,6 +240,8 @@ def test_positions_100_steps_tie_consistent(jitter4):
     xg, vg, tg = ctx.particles_download(sid)
     assert np.abs(xg - xo).max() <= 1e-5
     assert np.array_equal(tg, to)
+    record("jitter4_100_steps", dict(x_abs_m=err_stats(np.abs(xg - xo).max(axis=1)),
+                                     v_rel=err_stats(np.abs(vg - vo).max(axis=1) / np.abs(vo).max()), ties=ties))
 
 
 def test_full_cycle_field_update_matches_oracle(jitter4):
@@ -662,12 +747,90 @@ def test_walk_cap_is_reported_and_keeps_continuity(jitter4):
     _, Q0 = ctx.deposits_download()
     st = ctx.pic_step(ctx.step_params(verify=1), allow=(qh.QH_ELOST,))[0]
     assert st["lost"] == 50 and st["continuity_bad"] == 0
+    # the status does not depend on asking for statistics
+    ctx.particles_upload(sid, x, v, tet)
+    with pytest.raises(qh.QhError) as ei:
+        ctx.pic_step(ctx.step_params(verify=1), want_stats=False)
+    assert ei.value.code == qh.QH_ELOST
+    ctx.particles_upload(sid, x, v, tet)
+    _, Q0 = ctx.deposits_download()
+    ctx.pic_step(ctx.step_params(verify=1), want_stats=False, allow=(qh.QH_ELOST,))
     g, Q1 = ctx.deposits_download()
     assert np.array_equal(cx.G.T @ g, Q1 - Q0)
     xg, _, tg = ctx.particles_download(sid)
     assert ctx.particles_count(sid) == tet.size
     lam = np.einsum("pij,pj->pi", op.Minv[tg], np.column_stack([np.ones(tet.size), xg.astype(np.float64)]))
     assert lam.min() > -1e-5
+
+
+def _fnv1a(data: bytes) -> int:
+    h = 2166136261
+    for byte in data:
+        h = ((h ^ byte) * 16777619) & 0xFFFFFFFF
+    return h
+
+
+def _reseal(blob: bytearray) -> bytes:
+    """A checkpoint blob edited on purpose, with its FNV-1a checksum recomputed."""
+    blob[-4:] = _fnv1a(bytes(blob[:-4])).to_bytes(4, "little")
+    return bytes(blob)
+
+
+def test_verification_failure_is_reported_without_stats(jitter4):
+    """Fault forced from the host: a checkpoint whose node charge Q^n is one unit off at one
+    interior node (checksum recomputed, so the blob loads). The next step's continuity
+    G^T g = Q^{n+1} - Q^n then fails at that node: with verification the call reports
+    QH_EVERIFY whether or not statistics are asked for, and the statistics count the node."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    x, v, tet = parts["e"]
+    c = gpu_context(mesh, cfg["dt"])
+    c.fields_upload(e, b)
+    sid = c.species_add(-qi.QE / qi.ME, -1)
+    c.particles_upload(sid, x, v, tet)
+    blob = bytearray(c.state_save())
+    node = int(cx.int_nodes[0])
+    off = 72 + 8 * (cx.Ne + cx.Nf) + 8 * node
+    q = int.from_bytes(blob[off:off + 8], "little", signed=True) + 1
+    blob[off:off + 8] = q.to_bytes(8, "little", signed=True)
+    bad = _reseal(blob)
+    for want_stats in (False, True):
+        c.state_load(bad)
+        with pytest.raises(qh.QhError) as ei:
+            c.pic_step(c.step_params(verify=1), want_stats=want_stats)
+        assert ei.value.code == qh.QH_EVERIFY
+    c.state_load(bad)
+    st = c.pic_step(c.step_params(verify=1), allow=(qh.QH_EVERIFY,))[0]
+    assert st["continuity_bad"] == 1 and st["divb_bad"] == 0
+    # without verification nothing is checked and the step reports no failure
+    c.state_load(bad)
+    c.pic_step(c.step_params(verify=0))
+
+
+def test_state_blob_with_out_of_range_count_is_refused(jitter4):
+    """A checkpoint whose species count is 2^31 or 2^62 (checksum recomputed) is refused with
+    QH_EINVAL before any size is formed from it, and the context keeps its fields and
+    particles."""
+    import paper_2103_06737_amd as qh
+    cfg, mesh, cx, op, po, e, b, parts = jitter4
+    x, v, tet = parts["e"]
+    c = gpu_context(mesh, cfg["dt"])
+    c.fields_upload(e, b)
+    sid = c.species_add(-qi.QE / qi.ME, -1)
+    c.particles_upload(sid, x, v, tet)
+    blob = c.state_save()
+    before = (c.fields_download()[0], c.particles_download(sid)[0])
+    off = 72 + 8 * (cx.Ne + cx.Nf + 2 * cx.Nn) + 16   # species 0: q/m, z, pad, then n
+    assert int.from_bytes(blob[off:off + 8], "little") == x.shape[0]
+    for n_bad in (1 << 31, 1 << 62, -1):
+        bad = bytearray(blob)
+        bad[off:off + 8] = n_bad.to_bytes(8, "little", signed=True)
+        with pytest.raises(qh.QhError) as ei:
+            c.state_load(_reseal(bad))
+        assert ei.value.code == qh.QH_EINVAL
+    assert np.array_equal(c.fields_download()[0], before[0])
+    assert np.array_equal(c.particles_download(sid)[0], before[1])
+    c.state_load(blob)
 
 
 def test_fixed_point_headroom_is_reported(jitter4):

@@ -120,3 +120,39 @@ def test_training_cuts_pcg_iterations():
         _, it_l = Lr.pcg(A, bt[:, k], lambda r: G.T @ (G @ r), tol=1e-8)
         _, it_j, _ = Fo.pcg(A, bt[:, k], tol=1e-8)
         assert it_l <= 0.7 * it_j, (it_l, it_j)
+
+
+def _bad_weights():
+    """Finite weights whose network makes G badly conditioned (outputs up to ~170)."""
+    w = Lr.init_weights(4)
+    rng = np.random.default_rng(14)
+    w["W3"] = rng.normal(0, 20.0, w["W3"].shape)
+    w["b1"] = rng.normal(0, 0.1, w["b1"].shape)
+    return w
+
+
+def test_stall_rule_and_fallback():
+    """The fallback of the learned solve: a network giving Jacobi exactly never trips the stall
+    rule (same iterations as plain Jacobi-PCG); finite but bad weights trip it (||r|| not 10 %
+    lower over 10 iterations) long before the iteration cap, and Jacobi-PCG restarted from the
+    iterate reaches the target; non-finite weights restart from the initial guess."""
+    A, rows, cols, f = edge_problem(5)
+    n = A.shape[0]
+    b = A @ np.random.default_rng(7).standard_normal(n)
+    _, it_j, _ = Fo.pcg(A, b, tol=1e-8)
+
+    def apply_of(w):
+        o, _ = Lr.mlp_forward(w, f)
+        G, _ = Lr.factor(o, rows, cols, A.diagonal(), n)
+        return lambda r: G.T @ (G @ r)
+
+    x, il, ij, why = Lr.pcg_learned(A, b, apply_of(Lr.init_weights(0)), tol=1e-8, maxit=2000)
+    assert why == "converged" and ij == 0 and abs(il - it_j) <= 1
+    x, il, ij, why = Lr.pcg_learned(A, b, apply_of(_bad_weights()), tol=1e-8, maxit=2000)
+    assert why == "stalled" and Lr.STALL_WINDOW <= il < 200
+    assert np.linalg.norm(A @ x - b) <= 1.0001e-8 * np.linalg.norm(b)
+    wn = Lr.init_weights(0)
+    wn["b3"][0] = np.nan
+    x, il, ij, why = Lr.pcg_learned(A, b, apply_of(wn), tol=1e-8, maxit=2000)
+    assert why == "nonfinite" and il == 0 and abs(ij - it_j) <= 1
+    assert np.linalg.norm(A @ x - b) <= 1.0001e-8 * np.linalg.norm(b)

@@ -281,3 +281,31 @@ def test_integer_deposit_list_telescopes(jitter4):
             Qe[cx.tets[t, i]] += z * S * Lend[i]
     g, _ = po.deposit_list(segs_t, l0s, l1s, zs, np.zeros(0), np.zeros((0, 4)), np.zeros(0))
     assert np.array_equal(cx.G.T @ g, Qe - Qs)
+
+
+def test_gather_random_dofs_matches_whitney_sums(jitter4):
+    """E = sum_e e_e W1_e(r) and B = sum_f b_f W2_f(r) (Sec. II.C) for random edge and face
+    DOFs (no D b = 0: the face field is then affine in each tet) at random points of random tets
+    of the jittered mesh: the C gather of the particle oracle against the Whitney sums of
+    oracle.whitney, which the continuity and incidence tests pin, to 1e-13 of the field size."""
+    m, cx, op = jitter4
+    po = P.ParticleOracle(cx, op.Minv)
+    rng = np.random.default_rng(21)
+    e = rng.normal(0.0, 1e3, cx.Ne) * cx.edge_lengths()
+    b = rng.normal(0.0, 1e-3, cx.Nf)
+    n = 4000
+    tet = rng.integers(0, cx.Nt, n)
+    w = rng.dirichlet(np.ones(4), n)
+    x = np.einsum("pi,pid->pd", w, cx.xyz[cx.tets[tet]])
+    Ec, Bc = po.gather(e, b, x, tet)
+    Ep = W.field_E(cx, op.Minv, e, tet, x)
+    Bp = W.field_B(cx, op.Minv, b, tet, x)
+    assert np.abs(Ec - Ep).max() <= 1e-13 * np.abs(Ep).max()
+    assert np.abs(Bc - Bp).max() <= 1e-13 * np.abs(Bp).max()
+    # the sums are not degenerate: every edge and face term moves the result
+    e2 = e.copy()
+    e2[cx.tet_edges[tet[0], 3]] += 1.0
+    assert not np.allclose(po.gather(e2, b, x[:1], tet[:1])[0], Ec[:1], rtol=0, atol=1e-12)
+    b2 = b.copy()
+    b2[cx.tet_faces[tet[0], 2]] += 1e-3
+    assert not np.allclose(po.gather(e, b2, x[:1], tet[:1])[1], Bc[:1], rtol=0, atol=1e-15)

@@ -91,7 +91,7 @@ def _run(code, env_extra):
 
 
 def test_library_host_code_under_asan():
-    from paper_2103_06737_amd import asan_build
+    from tests import asan_build
     lib = asan_build.build_library()
     assert _instrumented(lib)
     out = _run(LIBRARY_RUN, {"QH_LIBQH": lib, "LD_PRELOAD": asan_build.runtime("clang")})
@@ -99,7 +99,7 @@ def test_library_host_code_under_asan():
 
 
 def test_oracle_walk_under_asan():
-    from paper_2103_06737_amd import asan_build
+    from tests import asan_build
     lib = asan_build.build_oracle()
     assert _instrumented(lib)
     out = _run(ORACLE_RUN, {"QH_ORC_LIB": lib, "LD_PRELOAD": asan_build.runtime("gcc")})
