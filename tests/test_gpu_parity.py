@@ -185,7 +185,7 @@ def test_two_species_vs_oracle(jitter4):
     g_re, _ = po.deposit_list(seg["tet"], seg["lam0"], seg["lam1"], zs, np.zeros(0), np.zeros((0, 4)), np.zeros(0))
     assert np.array_equal(g_re, g)
     order = np.lexsort((seg["seq"], seg["pid"], seg["species"]))
-    key = seg["species"][order] * (1 << 32) + seg["pid"][order]
+    key = seg["species"][order].astype(np.int64) * (1 << 32) + seg["pid"][order]
     last = np.r_[key[1:] != key[:-1], True]
     assert last.sum() == 2 * xe.shape[0]
     _, Q_re = po.deposit_list(np.zeros(0), np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
