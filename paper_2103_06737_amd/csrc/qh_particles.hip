@@ -453,12 +453,16 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         VX = ((const float2 *)a.vx)[v]; VY = ((const float2 *)a.vy)[v]; VZ = ((const float2 *)a.vz)[v];
         TT = ((const int2 *)a.tet)[v];
     }
+    // set for every q before the loop: a thread past the block's last slot leaves it early
     bool queued[kPpt];
     int leave_t[kPpt];   // tet outside the block's range at the end of the step, or -1
 #pragma unroll
     for (int q = 0; q < kPpt; ++q) {
         queued[q] = false;
         leave_t[q] = -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kPpt; ++q) {
         const int64_t i = i0 + q;
         if (!full && li0 + q >= topb) break;
         float px, py, pz, vx, vy, vz;
@@ -746,6 +750,7 @@ __global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const int64_t src = emi_slot[k];
         const int32_t t = emi_tet[k];
+        if (t < 0 || t >= own[nblk]) continue;  // only tets of the mesh are listed
         int32_t lo = 0, hi = nblk;  // own[0] = 0 <= t < own[nblk]
         while (hi - lo > 1) {
             const int32_t mid = (lo + hi) >> 1;
