@@ -244,7 +244,7 @@ struct qh_ctx {
     // by each species' step)
     int32_t *emi_slot = nullptr, *emi_tet = nullptr;
     unsigned int *emi_n = nullptr;
-    int64_t emi_cap = 0;
+    int64_t emi_cap = 0;                      // entries per segment of the list
 
     std::vector<Species> species;
 

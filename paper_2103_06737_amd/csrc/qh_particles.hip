@@ -255,22 +255,27 @@ __device__ __forceinline__ void record_piece(const StepArgs &a, int32_t pid, int
 }
 
 // A particle ending the step in a tet outside its block's range is listed (its slot and its
-// tet) to move to the block that owns the tet; one atomic per wave reserves the list entries.
-// Past the list's capacity it stays where it is (its deposits then go through the mailboxes)
-// and is listed again at the next step.
+// tet) to move to the block that owns the tet. The list has kLeaverSegs segments with a counter
+// each (block b writes to segment b % kLeaverSegs), so the counters are spread over many
+// addresses; one atomic per wave reserves the entries. Past its segment's capacity a particle
+// stays where it is (its deposits then go through the mailboxes) and is listed again at the
+// next step.
+constexpr int kLeaverSegs = 256;
 __device__ __forceinline__ void list_leaver(const StepArgs &a, bool leaves, int64_t slot, int t) {
     const unsigned long long m = __ballot(leaves);
     if (!m) return;
     const int lane = __lane_id();
     const int leader = __ffsll(m) - 1;
+    const unsigned int seg = blockIdx.x % kLeaverSegs;
     unsigned int first = 0;
-    if (lane == leader) first = atomicAdd(a.emi_n, (unsigned int)__popcll(m));
+    if (lane == leader) first = atomicAdd(a.emi_n + seg, (unsigned int)__popcll(m));
     first = (unsigned int)__shfl((int)first, leader);
     if (leaves) {
         const unsigned int k = first + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
-        if (k < a.emi_cap) {
-            a.emi_slot[k] = (int32_t)slot;
-            a.emi_tet[k] = t;
+        if (k < a.emi_cap) {  // emi_cap: entries per segment
+            const int64_t e = (int64_t)seg * a.emi_cap + k;
+            a.emi_slot[e] = (int32_t)slot;
+            a.emi_tet[e] = t;
         }
     }
 }
@@ -746,10 +751,13 @@ __global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi
                                                  float *__restrict__ y, float *__restrict__ z, float *__restrict__ vx,
                                                  float *__restrict__ vy, float *__restrict__ vz, int32_t *__restrict__ tet,
                                                  int32_t *__restrict__ id) {
-    const uint32_t n = min(*emi_n, emi_cap);
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const int64_t src = emi_slot[k];
-        const int32_t t = emi_tet[k];
+    // segment blockIdx.x % kLeaverSegs of the list (the grid is a multiple of kLeaverSegs blocks)
+    const uint32_t seg = blockIdx.x % kLeaverSegs, per = gridDim.x / kLeaverSegs;
+    const uint32_t n = min(emi_n[seg], emi_cap);
+    for (uint32_t k = (blockIdx.x / kLeaverSegs) * blockDim.x + threadIdx.x; k < n; k += per * blockDim.x) {
+        const int64_t e = (int64_t)seg * emi_cap + k;
+        const int64_t src = emi_slot[e];
+        const int32_t t = emi_tet[e];
         if (t < 0 || t >= own[nblk]) continue;  // only tets of the mesh are listed
         int32_t lo = 0, hi = nblk;  // own[0] = 0 <= t < own[nblk]
         while (hi - lo > 1) {
@@ -797,15 +805,17 @@ __global__ void k_blocks_init(int32_t *__restrict__ tet, int64_t live, int32_t n
 
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     if (s.n == 0 || s.nblk == 0) return hipSuccess;
-    // the list of particles leaving their block's range: room for 1/8 of the slots
-    const int64_t want = std::max<int64_t>(s.slots() / 8, 4096);
+    // the list of particles leaving their block's range: room for 1/8 of the slots, in
+    // kLeaverSegs segments (emi_cap entries each)
+    const int64_t want = std::max<int64_t>(s.slots() / 8 / kLeaverSegs, 64);
     if (c->emi_cap < want) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return e;
         qh_release(c, c->emi_slot), qh_release(c, c->emi_tet);
         c->emi_cap = 0;
-        if (qh_alloc(c, &c->emi_slot, want) || qh_alloc(c, &c->emi_tet, want)) return hipErrorOutOfMemory;
-        if (!c->emi_n && qh_alloc(c, &c->emi_n, 1)) return hipErrorOutOfMemory;
+        if (qh_alloc(c, &c->emi_slot, want * kLeaverSegs) || qh_alloc(c, &c->emi_tet, want * kLeaverSegs))
+            return hipErrorOutOfMemory;
+        if (!c->emi_n && qh_alloc(c, &c->emi_n, kLeaverSegs)) return hipErrorOutOfMemory;
         c->emi_cap = want;
     }
     StepArgs a;
@@ -825,7 +835,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     const unsigned nmail = (unsigned)((c->hm.Nt + kMailTets - 1) / kMailTets);
     hipError_t e = hipMemsetAsync(c->mail_cnt, 0, sizeof(unsigned int) * nmail, c->stream);
     if (e != hipSuccess) return e;
-    if ((e = hipMemsetAsync(c->emi_n, 0, sizeof(unsigned int), c->stream)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(c->emi_n, 0, sizeof(unsigned int) * kLeaverSegs, c->stream)) != hipSuccess) return e;
     // few particles on a large mesh (the blocks' windows cannot cover it): one fill clears the
     // per-tet sums instead of each block zeroing a long owned range
     a.zeroed = (int64_t)grid.x * kWin < c->hm.Nt ? 1 : 0;
@@ -833,8 +843,8 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
         return e;
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
-    // the listed particles move to the blocks owning their tets (a grid-stride loop over the list)
-    const unsigned gm = (unsigned)std::min<int64_t>((c->emi_cap + 255) / 256, 1024);
+    // the listed particles move to the blocks owning their tets (per segment, a strided loop)
+    const unsigned gm = (unsigned)(kLeaverSegs * std::min<int64_t>((c->emi_cap + 255) / 256, 4));
     hipLaunchKernelGGL(k_migrate, dim3(gm), dim3(256), 0, c->stream, c->emi_slot, c->emi_tet, c->emi_n,
                        (uint32_t)c->emi_cap, s.own, (int32_t)s.nblk, s.fill, s.nfree, s.top, s.freel, s.x, s.y, s.zz,
                        s.vx, s.vy, s.vz, s.tet, s.id);
@@ -1166,7 +1176,10 @@ __global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t nt, i
     const int t = valid ? sort_key(tet[i], nt) : -1;
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
-    if (valid && rank == 0) atomicAdd(&hist[t], len);
+    // free slots and absorbed particles (the last bucket) are dropped uncounted: they are many
+    // (the blocks' spare slots), and counting them would put one atomic per wave on one address;
+    // the exclusive scan's value at that bucket is then the number of particles kept
+    if (valid && rank == 0 && t < nt) atomicAdd(&hist[t], len);
 }
 
 // scan over chunks of 1024: per-chunk sums
@@ -1240,7 +1253,7 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
     int32_t first = 0;
-    if (valid && rank == 0) first = atomicAdd(&cursor[t], len);
+    if (valid && rank == 0 && t < nt) first = atomicAdd(&cursor[t], len);
     first = __shfl(first, head, 64);
     if (!valid || t == nt) return;
     const int32_t p = first + rank;
