@@ -68,6 +68,14 @@ def setup(wl: str, n_particles: int | None, boundary: int = 0, **override):
     return ctx, cfg, mesh, parts, mi
 
 
+def phase_bytes(mi, n_particles: int, crossings: float, n_occ: int) -> int:
+    """Algorithmic bytes of one particle phase (gather, push, walk, deposit): the particle state
+    read and written once (x, v as FP32 and the tet as int32: 56 B), per occupied tet and per
+    further tet a crossing enters the FP32 geometry (64 B), the E/B record (40 B), node and edge
+    ids (40 B) and neighbours (16 B), and the int64 edge and node accumulators written once."""
+    return 56 * n_particles + 160 * n_occ + 160 * crossings + 16 * (mi.n_edges + mi.n_nodes)
+
+
 def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False):
     """Bytes one launch must move at least (each datum read or written once)."""
     if kernel in ("cg_spmv",):
@@ -102,7 +110,7 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
 # HIP kernels behind each timed entry (one entry may launch several kernels)
 HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
                "precond": ["k_prec_g<false>", "k_prec_g<true>"],
-               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
+               "particle_step": ["k_particle_step<false>", "k_migrate", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
                "edge_rhs": ["k_edge_rhs_e", "k_edge_rhs_b"], "field_prep": ["k_field_prep"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plasma_64cube_16M.md")
 # headers every kernel file includes: part of the source a traffic figure was taken from
@@ -340,6 +348,32 @@ def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: 
                       f"{t_field:.2f}s); rate = N_p / (push time scaled to N_p + field time)"}
 
 
+def frozen_particle_phase(workload: str, warmup: int, steps: int):
+    """The particle phase alone in frozen fields (the 32^3 beam workload: 1M electrons, its 200
+    steps), timed per step with the library's HIP events (field prep, push, walk, deposit and the
+    particles' moves between blocks), with its roofline on the phase's algorithmic bytes. Its
+    particle state (28 MB) and mesh records fit the 256 MB last-level cache: the bytes need not
+    all come from HBM."""
+    import paper_2103_06737_amd as qh
+    ctx, cfg, mesh, parts, mi = setup(workload, None)
+    n_p = sum(p[2].size for p in parts.values())
+    n_occ = int(np.unique(np.concatenate([p[2] for p in parts.values()])).size)
+    prm = qh.Context.step_params(field_mode=qh.FIELDS_FROZEN, sort_every=cfg.get("sort_every", 0))
+    ctx.pic_step(prm, warmup, want_stats=False)
+    st = ctx.pic_step(prm, steps, want_stats=True)
+    ms = float(np.mean([s["ms_particles"] for s in st]))
+    cross = float(np.mean([s["crossings"] for s in st]))
+    by = phase_bytes(mi, n_p, cross, n_occ)
+    ach = by / (ms * 1e-3) / 1e9
+    ctx.close()
+    return {"workload": f"{workload}: {WORKLOADS[workload]}", "particles": n_p, "steps": steps,
+            "ms_per_step": round(ms, 4), "particle_steps_per_s": round(n_p / (ms * 1e-3), 1),
+            "crossings_per_step": cross, "occupied_tets": n_occ,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": int(by),
+                         "note": "state and records fit the 256 MB last-level cache"}}
+
+
 def copy_calibration(mib: int, reps: int = 5):
     """A plain elementwise copy of known size (reads and writes mib MiB once per launch): the
     profiler's FETCH_SIZE / WRITE_SIZE for this kernel, divided by the known bytes, gives the
@@ -366,7 +400,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="plasma64", choices=sorted(WORKLOADS))
     ap.add_argument("--particles", type=int, default=None, help="override the particle count")
-    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="steps timed per kernel with stats (default: one whole re-sort cycle)")
+    ap.add_argument("--no-frozen", action="store_true", help="skip the frozen-field beam32 particle phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
@@ -402,8 +438,16 @@ def main():
         beam_run(args.beam)
         return
     import paper_2103_06737_amd as qh
+    frozen = None
+    if not args.no_frozen and args.workload == "plasma64":
+        frozen = frozen_particle_phase("beam32", 10, qi.CONFIGS["beam32"]["steps"])
+        log(f"[bench] beam32 frozen-field particle phase: {frozen['ms_per_step']} ms/step, "
+            f"{frozen['roofline']['frac']} of HBM peak")
     ctx, cfg, mesh, parts, mi = setup(args.workload, args.particles)
     n_p = sum(p[2].size for p in parts.values())
+    n_occ = int(np.unique(np.concatenate([p[2] for p in parts.values()])).size)
+    if args.profile_steps is None:
+        args.profile_steps = cfg.get("sort_every", 0) or 3
     solve = cfg["mode"] == "solve"
     params = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE if solve else qh.FIELDS_FROZEN,
                                     sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
@@ -467,7 +511,11 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k, args.workload), "kernel": k,
                 "hip_kernels": HIP_KERNELS.get(k, []),
                 "algorithmic_bytes_per_launch": int(by), "us_per_launch": kern[k]["us_per_launch"]}
+    # the particle phase per step over the profiled steps (a whole re-sort cycle: the sort is in),
+    # field prep, push, walk, deposit, moves between blocks, sort
     ms_part = float(np.mean([s["ms_particles"] for s in pst]))
+    by_phase = phase_bytes(mi, n_p, crossings, n_occ)
+    ach_phase = by_phase / (ms_part * 1e-3) / 1e9
     fs_j = float(np.mean([s["ms_fields"] for s in pst_j]))
     fs_l = float(np.mean([s["ms_fields"] for s in learned["pst"]])) if learned else None
     out = {
@@ -481,13 +529,21 @@ def main():
         "roofline": roof(dom, kernels),
         "particle_phase": {"ms_per_step": round(ms_part, 4),
                            "particle_steps_per_s": round(n_p / (ms_part * 1e-3), 1),
-                           "roofline": roof("particle_step", kernels)},
+                           "steps_timed": len(pst), "sort_every": cfg.get("sort_every", 0),
+                           "covers": "field prep, gather/push/walk/deposit, moves between blocks, the sort "
+                                     "once per cycle (HIP events around the phase, every step of the cycle)",
+                           "roofline": {"bound": "hbm", "achieved": round(ach_phase, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(ach_phase / HBM_PEAK_GBS, 4),
+                                        "algorithmic_bytes_per_step": int(by_phase), "occupied_tets": n_occ,
+                                        "crossings_per_step": crossings}},
+        "particle_kernels": roof("particle_step", kernels),
         "field_solve_ms_per_step": {"jacobi": round(fs_j, 4), "learned": round(fs_l, 4) if fs_l else None},
         "jacobi_cycle": {"ms_per_step": round(1e3 * wall_j / args.steps, 4),
                          "particle_steps_per_s": round(n_p * args.steps / wall_j, 1),
                          "edge_iters": [s["edge_iters"] for s in pst_j], "kernels": kern_j},
         "solver": {"edge_iters": [s["edge_iters"] for s in pst], "node_iters": [s["node_iters"] for s in pst],
                    "edge_res": max(s["edge_res"] for s in pst), "gauss_res": max(s["gauss_res"] for s in pst),
+                   "gauss_res_rho": max(s["gauss_res_rho"] for s in pst),
                    "fallbacks": sum(s["fallbacks"] for s in pst)},
         "kernels": kernels,
         "crossings_per_step": crossings,
@@ -495,6 +551,8 @@ def main():
     }
     if learned:
         out["learned_training"] = learned["train"]
+    if frozen:
+        out["frozen_particle_phase"] = frozen
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         try:

@@ -118,6 +118,8 @@ typedef struct {
     int32_t fallbacks;              /* learned -> Jacobi restarts */
     float ms_particles, ms_fields;  /* device time of the two halves (HIP events) */
     int64_t foreign;                /* deposits into tets outside a block's range (mailbox records) */
+    double gauss_res_rho;           /* ||rho - G^T[*eps] e|| / ||rho|| (0 when rho = 0): the same residual
+                                       against the charge alone, for comparison with gauss_res */
 } qh_step_stats_t;
 
 typedef struct {

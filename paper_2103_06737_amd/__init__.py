@@ -70,7 +70,7 @@ class StepStats(C.Structure):
                 ("node_res", C.c_double), ("gauss_res", C.c_double), ("crossings", C.c_int64),
                 ("wall_hits", C.c_int64), ("lost", C.c_int64), ("continuity_bad", C.c_int64),
                 ("divb_bad", C.c_int64), ("fallbacks", C.c_int32), ("ms_particles", C.c_float),
-                ("ms_fields", C.c_float), ("foreign", C.c_int64)]
+                ("ms_fields", C.c_float), ("foreign", C.c_int64), ("gauss_res_rho", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

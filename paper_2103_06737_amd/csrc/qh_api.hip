@@ -1082,7 +1082,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             }
         if (use_ev) QH_HIP(c, hipEventRecord(ev[1], c->stream));
         SolveResult se, sn;
-        double gauss_out[3] = {0, 0, 0};
+        double gauss_out[4] = {0, 0, 0, 0};
         if (solve) {
             QH_HIP(c, hipMemcpyAsync(c->e_old, c->cge.x, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
             // the wave-equation right-hand side needs e^{n-1} and the previous current: without
@@ -1165,6 +1165,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.edge_res = se.res;
             S.node_res = sn.res;
             S.gauss_res = gauss_out[1] > 0 ? std::sqrt(gauss_out[2]) / gauss_out[1] : 0.0;
+            S.gauss_res_rho = gauss_out[3] > 0 ? std::sqrt(gauss_out[2]) / gauss_out[3] : 0.0;
             S.crossings = (int64_t)cnt[0];
             S.wall_hits = (int64_t)cnt[1];
             S.lost = (int64_t)cnt[2];

@@ -120,6 +120,7 @@ struct Species {
     int32_t *fill = nullptr;   // per block: particles that claimed a slot of it this step
     int32_t *nfree = nullptr;  // per block: entries of its free-slot list
     uint16_t *freel = nullptr; // per slot: the block's free slots below top (list of nfree)
+    int32_t *tblk = nullptr;   // per tet: the block owning it (since the last sort)
     uint16_t *ovf = nullptr;   // per slot: overflow list of the walk queue
     int64_t slots() const { return nblk * QH_CHUNK; }
 };

@@ -685,7 +685,8 @@ __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *_
 // Mailbox m (tets [kMailTets m, kMailTets (m+1))) into acc_tet: each record's 10 values (as
 // in the particle kernel) summed in LDS by tet, then added to the (already written) per-tet
 // sums. One block per mailbox, so every tet has a single writer.
-__global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restrict__ mail_cnt,
+constexpr int kMailThreads = 64;  // one wave per mailbox: a mailbox holds a few dozen records
+__global__ void __launch_bounds__(kMailThreads) k_mail_apply(const unsigned int *__restrict__ mail_cnt,
                                                     const int32_t *__restrict__ mail, int32_t zq, int64_t nt,
                                                     int64_t *__restrict__ acc_tet) {
     const int o = blockIdx.x;
@@ -694,12 +695,12 @@ __global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restri
     __shared__ long long acc[10 * kMailTets];
     const int T0 = o * kMailTets;
     const int W = (int)min((int64_t)kMailTets, nt - T0);
-    for (int j = threadIdx.x; j < 10 * kMailTets; j += 256) acc[j] = 0;
+    for (int j = threadIdx.x; j < 10 * kMailTets; j += kMailThreads) acc[j] = 0;
     __syncthreads();
     const int LE0[6] = {0, 0, 0, 1, 1, 2};
     const int LE1[6] = {1, 2, 3, 2, 3, 3};
     const int32_t *box = mail + (int64_t)o * kMailCap * kMailWords;
-    for (unsigned int r = threadIdx.x; r < cnt; r += 256) {
+    for (unsigned int r = threadIdx.x; r < cnt; r += kMailThreads) {
         const uint4 pk = reinterpret_cast<const uint4 *>(box)[r];
         const int head = box[4 * kMailCap + r];
         const int tt = head & 0x7fffffff;
@@ -719,22 +720,25 @@ __global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restri
             if (v[k]) atomic_add_lds(&acc[k * kMailTets + slot], v[k]);
     }
     __syncthreads();
-    // all loads of a thread issued before its stores
-    constexpr int kPer = 10 * kMailTets / 256;
-    long long vv[kPer], old[kPer];
-    int64_t at[kPer];
+    // in groups of five per thread, all loads of a group issued before its stores
+    constexpr int kGroup = 5, kPer = 10 * kMailTets / kMailThreads;
+    static_assert(kPer % kGroup == 0, "mailbox sums per thread");
+    for (int u0 = 0; u0 < kPer; u0 += kGroup) {
+        long long vv[kGroup], old[kGroup];
+        int64_t at[kGroup];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int j = threadIdx.x + 256 * u;
-        const int k = j / kMailTets, sl = j - k * kMailTets;
-        vv[u] = sl < W ? acc[j] : 0;
-        at[u] = (int64_t)k * nt + T0 + sl;
+        for (int u = 0; u < kGroup; ++u) {
+            const int j = threadIdx.x + kMailThreads * (u0 + u);
+            const int k = j / kMailTets, sl = j - k * kMailTets;
+            vv[u] = sl < W ? acc[j] : 0;
+            at[u] = (int64_t)k * nt + T0 + sl;
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) old[u] = vv[u] ? acc_tet[at[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+            if (vv[u]) acc_tet[at[u]] = old[u] + vv[u];
     }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) old[u] = vv[u] ? acc_tet[at[u]] : 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u)
-        if (vv[u]) acc_tet[at[u]] = old[u] + vv[u];
 }
 
 // A listed particle moves to the block that owns its tet (the last block b with own[b] <= t):
@@ -745,7 +749,8 @@ __global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restri
 // atomics, and nothing computed from the particles depends on where they are stored.
 __global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi_slot, const int32_t *__restrict__ emi_tet,
                                                  const unsigned int *__restrict__ emi_n, uint32_t emi_cap,
-                                                 const int32_t *__restrict__ own, int32_t nblk, int32_t *__restrict__ fill,
+                                                 const int32_t *__restrict__ own, const int32_t *__restrict__ tblk,
+                                                 int32_t nblk, int32_t *__restrict__ fill,
                                                  const int32_t *__restrict__ nfree, const int32_t *__restrict__ top,
                                                  const uint16_t *__restrict__ freel, float *__restrict__ x,
                                                  float *__restrict__ y, float *__restrict__ z, float *__restrict__ vx,
@@ -759,14 +764,8 @@ __global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi
         const int64_t src = emi_slot[e];
         const int32_t t = emi_tet[e];
         if (t < 0 || t >= own[nblk]) continue;  // only tets of the mesh are listed
-        int32_t lo = 0, hi = nblk;  // own[0] = 0 <= t < own[nblk]
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (own[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-        const int32_t d = lo;
-        if (own[d] > t) continue;  // no block owns the tet (only blocks appended since the sort)
+        const int32_t d = tblk[t];
+        if (d < 0 || d >= nblk || own[d] > t || own[d + 1] <= t) continue;  // no block owns the tet
         const int32_t c = atomicAdd(&fill[d], 1);
         const int32_t nf = nfree[d];
         int64_t dst;
@@ -782,6 +781,14 @@ __global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi
         tet[dst] = t; id[dst] = id[src];
         tet[src] = -1;
     }
+}
+
+// The owner of each tet after a sort: tblk[t] = b for t in [own[b], own[b+1]) (one block of
+// threads per layout block; the ranges tile [0, nt)).
+__global__ void k_tet_owner(const int32_t *__restrict__ own, int32_t *__restrict__ tblk) {
+    const int32_t b = blockIdx.x;
+    const int32_t t0 = own[b], t1 = own[b + 1];
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) tblk[t] = b;
 }
 
 // Block layout after a re-sort of `live` particles: block b holds sorted particles
@@ -843,13 +850,14 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
         return e;
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
-    // the listed particles move to the blocks owning their tets (per segment, a strided loop)
+    // the listed particles move to the blocks owning their tets (per segment, a strided loop);
+    // a species not sorted yet (particles only appended so far) has no owners to move to
     const unsigned gm = (unsigned)(kLeaverSegs * std::min<int64_t>((c->emi_cap + 255) / 256, 4));
-    hipLaunchKernelGGL(k_migrate, dim3(gm), dim3(256), 0, c->stream, c->emi_slot, c->emi_tet, c->emi_n,
-                       (uint32_t)c->emi_cap, s.own, (int32_t)s.nblk, s.fill, s.nfree, s.top, s.freel, s.x, s.y, s.zz,
+    if (s.tblk) hipLaunchKernelGGL(k_migrate, dim3(gm), dim3(256), 0, c->stream, c->emi_slot, c->emi_tet, c->emi_n,
+                       (uint32_t)c->emi_cap, s.own, s.tblk, (int32_t)s.nblk, s.fill, s.nfree, s.top, s.freel, s.x, s.y, s.zz,
                        s.vx, s.vy, s.vz, s.tet, s.id);
     const HostMesh &m = c->hm;
-    hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(256), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
+    hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(kMailThreads), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
     constexpr int kLpiE = 2, kLpiN = 8;  // lanes per edge / per node (edges border 4-6 tets, nodes ~24)
     const unsigned ge = (unsigned)(((m.Ne + 256 / kLpiE - 1) / (256 / kLpiE) + 7) / 8 * 8);
     const unsigned gn = (unsigned)(((m.Nn + 256 / kLpiN - 1) / (256 / kLpiN) + 7) / 8 * 8);
@@ -1297,6 +1305,11 @@ int qh_sort_species(qh_ctx *c, Species &s, int64_t extent) {
     if (nblk == 0) return QH_OK;
     hipLaunchKernelGGL(k_blocks_init, dim3((unsigned)nblk), dim3(64), 0, c->stream, s.tet, (int64_t)live,
                        (int32_t)nblk, nt, s.own, s.top, s.fill, s.nfree);
+    if (!s.tblk) {
+        int rc = qh_alloc(c, &s.tblk, nt);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_tet_owner, dim3((unsigned)nblk), dim3(64), 0, c->stream, s.own, s.tblk);
     QH_HIP(c, hipGetLastError());
     return QH_OK;
 }

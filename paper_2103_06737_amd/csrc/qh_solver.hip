@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kThreads) k_gauss_rhs(int32_t n, const int32_t
     write_partials<3>(acc, part);
 }
 
-// one block: out[0] = (tol_n scale)^2, out[1] = scale, out[2] = ||r||^2
+// one block: out[0] = (tol_n scale)^2, out[1] = scale, out[2] = ||r||^2, out[3] = ||rho||
 __global__ void __launch_bounds__(kThreads) k_gauss_finish(const double *__restrict__ part, int m, double *out,
                                                            double tol_n) {
     __shared__ double sh[kThreads / 64];
@@ -358,6 +358,7 @@ __global__ void __launch_bounds__(kThreads) k_gauss_finish(const double *__restr
         out[0] = tol_n * tol_n * scale * scale;
         out[1] = scale;
         out[2] = c;
+        out[3] = sqrt(a);
     }
 }
 
