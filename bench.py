@@ -110,7 +110,7 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
 # HIP kernels behind each timed entry (one entry may launch several kernels)
 HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
                "precond": ["k_prec_g<false>", "k_prec_g<true>"],
-               "particle_step": ["k_particle_step<false>", "k_migrate", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
+               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
                "edge_rhs": ["k_edge_rhs_e", "k_edge_rhs_b"], "field_prep": ["k_field_prep"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plasma_64cube_16M.md")
 # headers every kernel file includes: part of the source a traffic figure was taken from

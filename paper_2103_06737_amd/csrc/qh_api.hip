@@ -573,44 +573,38 @@ int qh_species_add(qh_ctx *c, double q_over_m, int32_t z, int32_t *sid) {
     return QH_OK;
 }
 
-// Storage of a species for at least cap slots, all or nothing: every new array is allocated
-// before any is swapped in, so a failed allocation leaves the species (its count, its particles
-// and its arrays) as it was. The first `keep` slots and the state of their blocks are copied
-// into the new arrays; the re-sort output needs no copy.
+// Storage of a species for at least cap particles, all or nothing: every new array is
+// allocated before any is swapped in, so a failed allocation leaves the species (its count, its
+// particles and its arrays) as it was. The first `keep` particles and the tet ranges of their
+// blocks are copied into the new arrays; the sort scratch needs no copy.
 static int reserve_species(qh_ctx *c, Species &s, int64_t cap, int64_t keep) {
     if (cap <= s.cap) return QH_OK;
-    cap = (cap + QH_CHUNK - 1) / QH_CHUNK * QH_CHUNK;
-    const int64_t nb = cap / QH_CHUNK, keep_b = (keep + QH_CHUNK - 1) / QH_CHUNK;
     float **fs[12] = {&s.x, &s.y, &s.zz, &s.vx, &s.vy, &s.vz, &s.sx, &s.sy, &s.sz, &s.svx, &s.svy, &s.svz};
     int32_t **is[4] = {&s.tet, &s.id, &s.stet, &s.sid};
-    int32_t **bs[4] = {&s.own, &s.top, &s.fill, &s.nfree};
     float *nf[12] = {};
-    int32_t *ni[4] = {}, *nbk[4] = {};
-    uint16_t *nfl = nullptr, *novf = nullptr;
+    int32_t *ni[4] = {}, *nown = nullptr;
+    uint16_t *novf = nullptr;
     auto drop_new = [&]() {
         for (auto &p : nf) qh_release(c, p);
         for (auto &p : ni) qh_release(c, p);
-        for (auto &p : nbk) qh_release(c, p);
-        qh_release(c, nfl), qh_release(c, novf);
+        qh_release(c, nown), qh_release(c, novf);
     };
     int rc;
     for (auto &p : nf)
         if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
     for (auto &p : ni)
         if ((rc = qh_alloc(c, &p, cap))) return drop_new(), rc;
-    for (auto &p : nbk)
-        if ((rc = qh_alloc(c, &p, nb + 1))) return drop_new(), rc;
-    if ((rc = qh_alloc(c, &nfl, cap)) || (rc = qh_alloc(c, &novf, cap))) return drop_new(), rc;
+    if ((rc = qh_alloc(c, &nown, qh_species_blocks(cap) + 1)) || (rc = qh_alloc(c, &novf, qh_species_blocks(cap) * QH_CHUNK)))
+        return drop_new(), rc;
     hipError_t e = hipSuccess;
     if (keep > 0) {
         for (int k = 0; k < 6 && e == hipSuccess; ++k)
             e = hipMemcpyAsync(nf[k], *fs[k], sizeof(float) * keep, hipMemcpyDeviceToDevice, c->stream);
         for (int k = 0; k < 2 && e == hipSuccess; ++k)
             e = hipMemcpyAsync(ni[k], *is[k], sizeof(int32_t) * keep, hipMemcpyDeviceToDevice, c->stream);
-        for (int k = 0; k < 4 && e == hipSuccess; ++k)
-            if (*bs[k]) e = hipMemcpyAsync(nbk[k], *bs[k], sizeof(int32_t) * (keep_b + 1), hipMemcpyDeviceToDevice, c->stream);
-        if (s.freel && e == hipSuccess)
-            e = hipMemcpyAsync(nfl, s.freel, sizeof(uint16_t) * keep, hipMemcpyDeviceToDevice, c->stream);
+        if (s.own && e == hipSuccess)
+            e = hipMemcpyAsync(nown, s.own, sizeof(int32_t) * (qh_species_blocks(keep) + 1), hipMemcpyDeviceToDevice,
+                               c->stream);
     }
     // the old arrays may still be read by queued work: released only after the stream has passed
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -620,42 +614,9 @@ static int reserve_species(qh_ctx *c, Species &s, int64_t cap, int64_t keep) {
     }
     for (int k = 0; k < 12; ++k) qh_release(c, *fs[k]), *fs[k] = nf[k];
     for (int k = 0; k < 4; ++k) qh_release(c, *is[k]), *is[k] = ni[k];
-    for (int k = 0; k < 4; ++k) qh_release(c, *bs[k]), *bs[k] = nbk[k];
-    qh_release(c, s.freel), s.freel = nfl;
+    qh_release(c, s.own), s.own = nown;
     qh_release(c, s.ovf), s.ovf = novf;
     s.cap = cap;
-    return QH_OK;
-}
-
-// Live particles of a species copied to the host in slot order (free slots skipped): the six
-// components (x, y, z, vx, vy, vz, n values each, one after another), tets and ids.
-static int species_to_host(qh_ctx *c, const Species &s, std::vector<float> &comp, std::vector<int32_t> &tet,
-                           std::vector<int32_t> &ids) {
-    const int64_t e = s.slots();
-    std::vector<float> raw(6 * e);
-    std::vector<int32_t> rt(e), ri(e);
-    const float *src[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
-    for (int k = 0; k < 6 && e; ++k)
-        QH_HIP(c, hipMemcpyAsync(raw.data() + k * e, src[k], sizeof(float) * e, hipMemcpyDeviceToHost, c->stream));
-    if (e) {
-        QH_HIP(c, hipMemcpyAsync(rt.data(), s.tet, sizeof(int32_t) * e, hipMemcpyDeviceToHost, c->stream));
-        QH_HIP(c, hipMemcpyAsync(ri.data(), s.id, sizeof(int32_t) * e, hipMemcpyDeviceToHost, c->stream));
-    }
-    QH_HIP(c, hipStreamSynchronize(c->stream));
-    int64_t n = 0;
-    for (int64_t i = 0; i < e; ++i) n += rt[i] >= 0;
-    if (n != s.n) return qh_fail(c, QH_ESTATE, "species layout holds " + std::to_string(n) + " particles, not " + std::to_string(s.n));
-    comp.resize(6 * n);
-    tet.resize(n);
-    ids.resize(n);
-    int64_t j = 0;
-    for (int64_t i = 0; i < e; ++i) {
-        if (rt[i] < 0) continue;
-        for (int k = 0; k < 6; ++k) comp[k * n + j] = raw[k * e + i];
-        tet[j] = rt[i];
-        ids[j] = ri[i];
-        ++j;
-    }
     return QH_OK;
 }
 
@@ -683,12 +644,10 @@ static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, con
     }
     Species &s = c->species[sid];
     int rc;
-    // room for the particles as given and for their block layout
-    if ((rc = reserve_species(c, s, std::max<int64_t>(n, qh_species_blocks(n) * QH_CHUNK), 0))) return rc;
+    if ((rc = reserve_species(c, s, n, 0))) return rc;
     // the species holds no particle until every array is in place: a failed copy or location
     // leaves it empty, never with unset tet ids
     s.n = 0;
-    s.nblk = 0;
     s.next_id = next_id;
     if (n > 0) {
         std::vector<float> comp(n);
@@ -708,7 +667,7 @@ static int upload_species(qh_ctx *c, int32_t sid, int64_t n, const float *x, con
         QH_HIP(c, hipMemcpyAsync(s.id, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
         s.n = n;
-        if ((rc = qh_sort_species(c, s, n))) return rc;  // into the block layout
+        if ((rc = qh_sort_species(c, s))) return rc;
     }
     c->wave_hist = false;
     return recompute_charge(c);
@@ -721,10 +680,14 @@ int qh_particles_download(const qh_ctx *cc, int32_t sid, float *x, float *v, int
     const Species &s = c->species[sid];
     int64_t n = s.n;
     if (n == 0) return QH_OK;
-    std::vector<int32_t> ids, tt;
-    std::vector<float> comp;
-    int rc = species_to_host(c, s, comp, tt, ids);
-    if (rc) return rc;
+    std::vector<int32_t> ids(n), tt(n);
+    std::vector<float> comp(6 * n);
+    const float *src[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+    for (int k = 0; k < 6; ++k)
+        QH_HIP(c, hipMemcpyAsync(comp.data() + k * n, src[k], sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipMemcpyAsync(ids.data(), s.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipMemcpyAsync(tt.data(), s.tet, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
     // rank of each particle by id (ids are unique; after injections and absorptions they are
     // not a permutation of 0..n-1)
     std::vector<int64_t> order(n), rank(n);
@@ -754,11 +717,8 @@ int qh_particles_ids(const qh_ctx *cc, int32_t sid, int32_t *ids) {
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     const Species &s = c->species[sid];
     if (s.n == 0) return QH_OK;
-    std::vector<int32_t> id, tt;
-    std::vector<float> comp;
-    int rc = species_to_host(c, s, comp, tt, id);
-    if (rc) return rc;
-    std::copy(id.begin(), id.end(), ids);
+    QH_HIP(c, hipMemcpyAsync(ids, s.id, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
     std::sort(ids, ids + s.n);
     return QH_OK;
 }
@@ -787,12 +747,8 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     const int64_t n0 = s.n, n1 = n0 + n;
     if (n1 >= ((int64_t)1 << 31) || s.next_id + n >= ((int64_t)1 << 31))
         return qh_fail(c, QH_EINVAL, "at most 2^31-1 particles (and ids) per species");
-    // the new particles fill new blocks past the layout's end; the storage also keeps room for
-    // the block layout of all particles (the next sort)
-    const int64_t e0 = s.slots(), b0 = s.nblk, b1 = b0 + (n + QH_CHUNK - 1) / QH_CHUNK;
-    const int64_t need = std::max<int64_t>(b1 * QH_CHUNK, qh_species_blocks(n1) * QH_CHUNK);
     int rc;
-    if (need > s.cap && (rc = reserve_species(c, s, std::max<int64_t>(std::max<int64_t>(2 * s.cap, need), 4096), e0)))
+    if (n1 > s.cap && (rc = reserve_species(c, s, std::max<int64_t>(std::max<int64_t>(2 * s.cap, n1), 4096), n0)))
         return rc;
     // components laid out one after another; the host buffers live until the sync at the end
     std::vector<float> comp(6 * n);
@@ -800,18 +756,17 @@ int qh_particles_inject(qh_ctx *c, int32_t sid, int64_t n, const float *x, const
     for (int k = 0; k < 6; ++k) {
         const float *src = k < 3 ? x : v;
         for (int64_t i = 0; i < n; ++i) comp[k * n + i] = src[3 * i + k % 3];
-        QH_HIP(c, hipMemcpyAsync(dst[k] + e0, comp.data() + k * n, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(dst[k] + n0, comp.data() + k * n, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
     }
     std::vector<int32_t> ids(n);
     std::iota(ids.begin(), ids.end(), (int32_t)s.next_id);
-    if (tet) QH_HIP(c, hipMemcpyAsync(s.tet + e0, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
-    else if ((rc = locate_species(c, s, e0, n))) return rc;  // the layout still ends at e0: nothing was added
-    QH_HIP(c, hipMemcpyAsync(s.id + e0, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    if (tet) QH_HIP(c, hipMemcpyAsync(s.tet + n0, tet, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    else if ((rc = locate_species(c, s, n0, n))) return rc;  // s.n is still n0: nothing was added
+    QH_HIP(c, hipMemcpyAsync(s.id + n0, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     s.next_id += n;
     s.n = n1;
-    s.nblk = b1;
-    QH_HIP(c, launch_own_extend(c, s, (int32_t)b0, (int32_t)b1, n));
-    QH_HIP(c, launch_charge_deposit(c, s, e0));
+    QH_HIP(c, launch_own_extend(c, s, (int32_t)qh_species_blocks(n0), (int32_t)qh_species_blocks(n1)));
+    QH_HIP(c, launch_charge_deposit(c, s, n0));
     return sync(c);
 }
 
@@ -1437,16 +1392,10 @@ int state_write(qh_ctx *c, Writer &w) {
         w.val<int32_t>(0);
         w.val<int64_t>(s.n);
         w.val<int64_t>(s.next_id);
-        if (!w.p) {
-            w.n += 32 * (size_t)s.n;  // six components, tet and id, 4 bytes each per particle
-            continue;
-        }
-        std::vector<float> comp;
-        std::vector<int32_t> tt, ids;
-        if (s.n && (rc = species_to_host(c, s, comp, tt, ids))) return rc;
-        w.put(comp.data(), 4 * comp.size());
-        w.put(tt.data(), 4 * tt.size());
-        w.put(ids.data(), 4 * ids.size());
+        const float *f[6] = {s.x, s.y, s.zz, s.vx, s.vy, s.vz};
+        for (auto a : f)
+            if ((rc = dev(a, 4 * s.n))) return rc;
+        if ((rc = dev(s.tet, 4 * s.n)) || (rc = dev(s.id, 4 * s.n))) return rc;
     }
     const uint32_t h = w.p ? fnv1a(w.p, w.n) : 0u;
     w.val<uint32_t>(h);
@@ -1532,11 +1481,8 @@ int qh_state_load(qh_ctx *c, const void *buf, size_t len) {
     // everything checked; device storage reserved before anything changes, so a failed
     // allocation leaves the context as it was
     int rc;
-    for (size_t k = 0; k < sp.size(); ++k) {
-        Species &s = c->species[k];
-        const int64_t need = std::max<int64_t>(sp[k].n, qh_species_blocks(sp[k].n) * QH_CHUNK);
-        if ((rc = reserve_species(c, s, need, s.slots()))) return rc;
-    }
+    for (size_t k = 0; k < sp.size(); ++k)
+        if ((rc = reserve_species(c, c->species[k], sp[k].n, c->species[k].n))) return rc;
     if (has_d && !c->dbnd && (rc = qh_alloc(c, &c->dbnd, m.Nn))) return rc;
     // apply
     std::vector<double> ecopy(e, e + m.Ne);

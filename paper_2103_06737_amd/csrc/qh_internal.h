@@ -19,9 +19,7 @@ constexpr int QH_COUNTER_SLOTS = 256;         // spread of the per-block event c
 // continuity and D b violations.
 enum { QH_CNT_CONT = 0, QH_CNT_DIVB = 1, QH_CNT_STEP_END = 3, QH_CNT_HEADROOM_CALL = 3, QH_CNT_LOST_CALL = 4,
        QH_CNT_CONT_CALL = 5, QH_CNT_DIVB_CALL = 6, QH_CNT_ALL = 8 };
-constexpr int QH_CHUNK = 512;                 // particle slots per block of the particle kernels
-constexpr int QH_FILL = 448;                  // particles per block after a re-sort (the rest is room
-                                              // for particles moving in from other blocks)
+constexpr int QH_CHUNK = 512;                 // particles per block of the particle kernels
 constexpr int kMailTets = 128;                // tets per deposit mailbox
 constexpr int kMailCap = 1024;                // records per mailbox
 constexpr int kMailWords = 5;                 // int32 words per record: both points packed (4), tet | end << 31 (1)
@@ -97,32 +95,18 @@ struct DevCsr {
     TileCols cols() const { return TileCols{col, col16, tbase}; }
 };
 
-// Particles of one species live in blocks of QH_CHUNK slots (block b: slots [b QH_CHUNK,
-// (b+1) QH_CHUNK)); block b owns the tets [own[b], own[b+1]) and its particles sit in its
-// first top[b] slots, where a slot holds a particle or is free (tet -1). A re-sort by tet
-// fills each block with QH_FILL particles; between re-sorts a particle whose tet has left its
-// block's range moves to the block owning its new tet when that block has a free slot (see
-// qh_particles.hip).
 struct Species {
     double qm = 0.0;
     int32_t z = 0;
-    int64_t n = 0;             // particles held
-    int64_t nblk = 0;          // blocks of the layout (slots nblk * QH_CHUNK)
-    int64_t cap = 0;           // slots allocated
+    int64_t n = 0, cap = 0;
     int64_t next_id = 0;       // id of the next particle uploaded or injected
     float *x = nullptr, *y = nullptr, *zz = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
     int32_t *tet = nullptr, *id = nullptr;
-    // re-sort output (same layout; swapped with the above after a re-sort)
+    // sort scratch (same layout)
     float *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
     int32_t *stet = nullptr, *sid = nullptr;
-    int32_t *own = nullptr;    // per block + 1: owned tet range
-    int32_t *top = nullptr;    // per block: slots in use (particles and free slots among them)
-    int32_t *fill = nullptr;   // per block: particles that claimed a slot of it this step
-    int32_t *nfree = nullptr;  // per block: entries of its free-slot list
-    uint16_t *freel = nullptr; // per slot: the block's free slots below top (list of nfree)
-    int32_t *tblk = nullptr;   // per tet: the block owning it (since the last sort)
-    uint16_t *ovf = nullptr;   // per slot: overflow list of the walk queue
-    int64_t slots() const { return nblk * QH_CHUNK; }
+    int32_t *own = nullptr;    // owned tet range per particle block (see qh_particles.hip)
+    uint16_t *ovf = nullptr;   // per particle block: overflow list of the walk queue
 };
 
 // Krylov workspace for one system.
@@ -241,11 +225,6 @@ struct qh_ctx {
     int32_t loc_n[3] = {0, 0, 0};
     unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS + QH_CNT_ALL (see QH_CNT_*)
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
-    // particles leaving their block's tet range in a step: slot and new tet (one list, reused
-    // by each species' step)
-    int32_t *emi_slot = nullptr, *emi_tet = nullptr;
-    unsigned int *emi_n = nullptr;
-    int64_t emi_cap = 0;                      // entries per segment of the list
 
     std::vector<Species> species;
 
@@ -317,13 +296,11 @@ void qh_release(qh_ctx *c, T *&p) {
 void launch_field_prep(qh_ctx *c);
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture);
 hipError_t launch_charge_deposit(qh_ctx *c, Species &s, int64_t first = 0);
-hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1, int64_t n_new);
+hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1);
 hipError_t launch_probe(qh_ctx *c, int64_t n, const double *xyz, const int32_t *tet, double *E, double *B);
 hipError_t launch_locate(qh_ctx *c, int64_t n, const float *x, const float *y, const float *z, int32_t *tet);
-// Re-sort by tet of the first `extent` slots (free slots dropped) into the block layout.
-int qh_sort_species(qh_ctx *c, Species &s, int64_t extent);
 int qh_sort_species(qh_ctx *c, Species &s);
-int64_t qh_species_blocks(int64_t n);  // blocks of the layout a re-sort of n particles makes
+int64_t qh_species_blocks(int64_t n);
 hipError_t launch_deposit_lists(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet,
                                 const int32_t *l0, const int32_t *l1, const int32_t *sz,
                                 int64_t n_pt, const int32_t *pt_tet, const int32_t *pl,

@@ -14,7 +14,6 @@
 // faces by vertex id) the piece adds z (L_a^0 L_b^1 - L_a^1 L_b^0) to edge a->b and the end
 // point adds z 2^20 L_n to node n. G^T g then telescopes to Q^{n+1} - Q^n in int64: discrete
 // continuity holds bit for bit and the sums are independent of order.
-#include <algorithm>
 #include <type_traits>
 
 #include "qh_internal.h"
@@ -74,13 +73,9 @@ struct StepArgs {
     int32_t *tet;
     const int32_t *pid;
     const int32_t *own;     // own[b] .. own[b+1]: tets owned by block b (from the last sort)
-    int32_t *top, *fill, *nfree;  // per block: slots in use, slots claimed by arriving particles, free slots listed
-    uint16_t *freel;        // per block: its free slots below top
-    int32_t *emi_slot, *emi_tet;  // particles that left their block's range: slot, new tet
-    unsigned int *emi_n;
-    uint32_t emi_cap;
     unsigned int *mail_cnt; // records posted to each mailbox (tets [kMailTets m, kMailTets (m+1))) this launch
     int32_t *mail;          // per mailbox: kMailCap packed point pairs (uint4), then kMailCap heads (tet | end << 31)
+    int64_t n;
     int32_t nt;
     float hqm;              // q/m * dt / 2
     float dt;
@@ -254,32 +249,6 @@ __device__ __forceinline__ void record_piece(const StepArgs &a, int32_t pid, int
     }
 }
 
-// A particle ending the step in a tet outside its block's range is listed (its slot and its
-// tet) to move to the block that owns the tet. The list has kLeaverSegs segments with a counter
-// each (block b writes to segment b % kLeaverSegs), so the counters are spread over many
-// addresses; one atomic per wave reserves the entries. Past its segment's capacity a particle
-// stays where it is (its deposits then go through the mailboxes) and is listed again at the
-// next step.
-constexpr int kLeaverSegs = 256;
-__device__ __forceinline__ void list_leaver(const StepArgs &a, bool leaves, int64_t slot, int t) {
-    const unsigned long long m = __ballot(leaves);
-    if (!m) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll(m) - 1;
-    const unsigned int seg = blockIdx.x % kLeaverSegs;
-    unsigned int first = 0;
-    if (lane == leader) first = atomicAdd(a.emi_n + seg, (unsigned int)__popcll(m));
-    first = (unsigned int)__shfl((int)first, leader);
-    if (leaves) {
-        const unsigned int k = first + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
-        if (k < a.emi_cap) {  // emi_cap: entries per segment
-            const int64_t e = (int64_t)seg * a.emi_cap + k;
-            a.emi_slot[e] = (int32_t)slot;
-            a.emi_tet[e] = t;
-        }
-    }
-}
-
 // ------------------------------------------------------------------------------------------
 // Walk of one particle from (px, py, pz) in tet t along dt v^{n+1/2}, face by face (exit
 // face = smallest crossing parameter, the entry face excluded; at most QH_MAX_PIECES
@@ -391,34 +360,26 @@ __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused particle step. A block takes the slots of its block of the layout (particles of its
-// tet range, sorted by tet at the last sort, plus those that moved in since), kPpt consecutive
-// slots per thread; free slots (tet -1) are skipped and listed.
+// Fused particle step. A block takes kChunk consecutive particles (sorted by tet at the last
+// sort), kPpt consecutive ones per thread.
 // Phase A (all waves): gather, Boris; a particle whose straight path stays in its tet gets its
 // new position and the deposit of the piece (LDS window or post) and is written back from
 // registers; a particle whose path leaves the tet is queued in LDS with its start state (past
 // kQueue queued particles: its new velocity to memory and its index to an overflow list).
 // Phase B (wave 0 only; the other waves exit): the queued particles are walked one per lane and
 // written back; then the window sums go to acc_tet as plain stores (zeros for owned tets past the
-// window), the event counters to memory, and the block's free slots (with the slot count) for the
-// particles that move in after the step. Waves 1-3 do not wait for the walks. A particle that
-// ends the step outside the block's tet range is listed to move (k_migrate).
+// window) and the event counters to memory. Waves 1-3 do not wait for the walks.
 constexpr int kQueue = 128;
 template <bool CAPTURE>
 __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     __shared__ long long acc[10 * kWin];  // plane-major: acc[k * kWin + slot]
     __shared__ float4 qrec[2 * kQueue];   // queued particle: (x, y, z, vx) (vy, vz, tet, chunk index) as bits
-    __shared__ unsigned int s_cnt[6];     // queued particles, -, -, -, posted pieces of phase A, free slots
-    __shared__ uint16_t s_free[kChunk];   // the block's free slots
-    const int blk = blockIdx.x;
-    const int64_t base = (int64_t)blk * kChunk;
-    const int T0 = a.own[blk], T1 = a.own[blk + 1];
+    __shared__ unsigned int s_cnt[5];     // queued particles, -, -, -, posted pieces of phase A
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const int T0 = a.own[blockIdx.x], T1 = a.own[blockIdx.x + 1];
     const int W = min(T1 - T0, kWin);
-    // slots in use: last step's, plus those past it taken by particles that moved in (after the
-    // listed free slots were used)
-    const int topb = min(a.top[blk] + max(a.fill[blk] - a.nfree[blk], 0), kChunk);
     for (int j = threadIdx.x; j < 10 * kWin; j += kBlock) acc[j] = 0;
-    if (threadIdx.x < 6) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
     // owned tets past the window get no LDS sums: the whole block zeroes them now (the mailbox
     // kernel that follows adds their posted pieces), unless the host cleared every sum
     if (!a.zeroed)
@@ -447,9 +408,8 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
     };
 
     // ---- phase A
-    const int li0 = threadIdx.x * kPpt;          // slot within the block
-    const int64_t i0 = base + li0;
-    const bool full = li0 + kPpt <= topb;
+    const int64_t i0 = base + (int64_t)threadIdx.x * kPpt;
+    const bool full = base + kChunk <= a.n;
     float2 X, Y, Z, VX, VY, VZ;
     int2 TT;
     if (full) {
@@ -458,18 +418,12 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         VX = ((const float2 *)a.vx)[v]; VY = ((const float2 *)a.vy)[v]; VZ = ((const float2 *)a.vz)[v];
         TT = ((const int2 *)a.tet)[v];
     }
-    // set for every q before the loop: a thread past the block's last slot leaves it early
     bool queued[kPpt];
-    int leave_t[kPpt];   // tet outside the block's range at the end of the step, or -1
 #pragma unroll
     for (int q = 0; q < kPpt; ++q) {
         queued[q] = false;
-        leave_t[q] = -1;
-    }
-#pragma unroll
-    for (int q = 0; q < kPpt; ++q) {
         const int64_t i = i0 + q;
-        if (!full && li0 + q >= topb) break;
+        if (!full && i >= a.n) break;
         float px, py, pz, vx, vy, vz;
         int t;
         if (full) {
@@ -484,11 +438,6 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             px = a.x[i]; py = a.y[i]; pz = a.z[i];
             vx = a.vx[i]; vy = a.vy[i]; vz = a.vz[i];
             t = a.tet[i];
-        }
-        if (t < 0) {
-            // a free slot: listed, nothing written (a full pair writes its loaded values back)
-            s_free[atomicAdd(&s_cnt[5], 1u)] = (uint16_t)(li0 + q);
-            continue;
         }
         // gather at x^n: E = alpha + beta x (r - c), B constant
         const float4 A = a.geo[3 * t], B = a.geo[3 * t + 1], C = a.geo[3 * t + 2];
@@ -527,7 +476,6 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             quantize(l, -1, L1);
             deposit(t, L0, L1, true);
             if (CAPTURE) record_piece(a, a.pid[i], 0, t, L0, L1);
-            if ((unsigned)(t - T0) >= (unsigned)(T1 - T0)) leave_t[q] = t;
         } else {
             const unsigned int k = atomicAdd(&s_cnt[0], 1u);
             queued[q] = true;
@@ -568,9 +516,6 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
             a.vz[i0 + 1] = VZ.y; a.tet[i0 + 1] = TT.y;
         }
     }
-    // particles that stayed in a tet outside the block's range: listed to move
-#pragma unroll
-    for (int q = 0; q < kPpt; ++q) list_leaver(a, leave_t[q] >= 0, i0 + q, leave_t[q]);
     // posted pieces of phase A
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) n_foreign += __shfl_xor(n_foreign, off, 64);
@@ -602,10 +547,7 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         walk_one<CAPTURE>(a, px, py, pz, vx, vy, vz, t, pid, deposit_walk, n_cross, n_wall, n_lost, gone);
         a.x[i] = px; a.y[i] = py; a.z[i] = pz;
         a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
-        a.tet[i] = gone ? -1 : t;  // absorbed: its slot is free from now on
-        if (gone) s_free[atomicAdd(&s_cnt[5], 1u)] = (uint16_t)(i - base);
-        const bool out = !gone && (unsigned)(t - T0) >= (unsigned)(T1 - T0);
-        list_leaver(a, out, i, t);
+        a.tet[i] = gone ? -1 : t;  // dropped by the sort that follows the step
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -621,15 +563,6 @@ __global__ void __launch_bounds__(kBlock) k_particle_step(StepArgs a) {
         int64_t *dst = a.acc_tet + (int64_t)k * a.nt + T0;
         const long long scale = k < 6 ? (long long)a.zq : (long long)a.zq * QH_SCALE;
         for (int j = lane; j < W; j += 64) dst[j] = scale * acc[k * kWin + j];
-    }
-    // the block's free slots (this wave's LDS additions are ordered before these reads) and
-    // counters, for the particles moving in after this step (k_migrate)
-    const int nf = (int)s_cnt[5];
-    for (int j = lane; j < nf; j += 64) a.freel[base + j] = s_free[j];
-    if (lane == 0) {
-        a.top[blk] = topb;
-        a.fill[blk] = 0;
-        a.nfree[blk] = nf;
     }
     // event counters: crossings, wall hits, lost, posted pieces
     if (lane < 4) {
@@ -685,8 +618,7 @@ __global__ void __launch_bounds__(256) k_gather(int64_t nitems, const int32_t *_
 // Mailbox m (tets [kMailTets m, kMailTets (m+1))) into acc_tet: each record's 10 values (as
 // in the particle kernel) summed in LDS by tet, then added to the (already written) per-tet
 // sums. One block per mailbox, so every tet has a single writer.
-constexpr int kMailThreads = 64;  // one wave per mailbox: a mailbox holds a few dozen records
-__global__ void __launch_bounds__(kMailThreads) k_mail_apply(const unsigned int *__restrict__ mail_cnt,
+__global__ void __launch_bounds__(256) k_mail_apply(const unsigned int *__restrict__ mail_cnt,
                                                     const int32_t *__restrict__ mail, int32_t zq, int64_t nt,
                                                     int64_t *__restrict__ acc_tet) {
     const int o = blockIdx.x;
@@ -695,12 +627,12 @@ __global__ void __launch_bounds__(kMailThreads) k_mail_apply(const unsigned int 
     __shared__ long long acc[10 * kMailTets];
     const int T0 = o * kMailTets;
     const int W = (int)min((int64_t)kMailTets, nt - T0);
-    for (int j = threadIdx.x; j < 10 * kMailTets; j += kMailThreads) acc[j] = 0;
+    for (int j = threadIdx.x; j < 10 * kMailTets; j += 256) acc[j] = 0;
     __syncthreads();
     const int LE0[6] = {0, 0, 0, 1, 1, 2};
     const int LE1[6] = {1, 2, 3, 2, 3, 3};
     const int32_t *box = mail + (int64_t)o * kMailCap * kMailWords;
-    for (unsigned int r = threadIdx.x; r < cnt; r += kMailThreads) {
+    for (unsigned int r = threadIdx.x; r < cnt; r += 256) {
         const uint4 pk = reinterpret_cast<const uint4 *>(box)[r];
         const int head = box[4 * kMailCap + r];
         const int tt = head & 0x7fffffff;
@@ -720,117 +652,39 @@ __global__ void __launch_bounds__(kMailThreads) k_mail_apply(const unsigned int 
             if (v[k]) atomic_add_lds(&acc[k * kMailTets + slot], v[k]);
     }
     __syncthreads();
-    // in groups of five per thread, all loads of a group issued before its stores
-    constexpr int kGroup = 5, kPer = 10 * kMailTets / kMailThreads;
-    static_assert(kPer % kGroup == 0, "mailbox sums per thread");
-    for (int u0 = 0; u0 < kPer; u0 += kGroup) {
-        long long vv[kGroup], old[kGroup];
-        int64_t at[kGroup];
+    // all loads of a thread issued before its stores
+    constexpr int kPer = 10 * kMailTets / 256;
+    long long vv[kPer], old[kPer];
+    int64_t at[kPer];
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            const int j = threadIdx.x + kMailThreads * (u0 + u);
-            const int k = j / kMailTets, sl = j - k * kMailTets;
-            vv[u] = sl < W ? acc[j] : 0;
-            at[u] = (int64_t)k * nt + T0 + sl;
-        }
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) old[u] = vv[u] ? acc_tet[at[u]] : 0;
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-            if (vv[u]) acc_tet[at[u]] = old[u] + vv[u];
+    for (int u = 0; u < kPer; ++u) {
+        const int j = threadIdx.x + 256 * u;
+        const int k = j / kMailTets, sl = j - k * kMailTets;
+        vv[u] = sl < W ? acc[j] : 0;
+        at[u] = (int64_t)k * nt + T0 + sl;
     }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) old[u] = vv[u] ? acc_tet[at[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        if (vv[u]) acc_tet[at[u]] = old[u] + vv[u];
 }
 
-// A listed particle moves to the block that owns its tet (the last block b with own[b] <= t):
-// into one of that block's listed free slots, else past its top, while the block has room; the
-// slot it leaves becomes free (it is listed by the next step). Particles finding no room stay
-// where they are. Destination slots are free slots or slots past a top, never another listed
-// particle's, so the moves do not interfere; which particle gets which slot is decided by
-// atomics, and nothing computed from the particles depends on where they are stored.
-__global__ void __launch_bounds__(256) k_migrate(const int32_t *__restrict__ emi_slot, const int32_t *__restrict__ emi_tet,
-                                                 const unsigned int *__restrict__ emi_n, uint32_t emi_cap,
-                                                 const int32_t *__restrict__ own, const int32_t *__restrict__ tblk,
-                                                 int32_t nblk, int32_t *__restrict__ fill,
-                                                 const int32_t *__restrict__ nfree, const int32_t *__restrict__ top,
-                                                 const uint16_t *__restrict__ freel, float *__restrict__ x,
-                                                 float *__restrict__ y, float *__restrict__ z, float *__restrict__ vx,
-                                                 float *__restrict__ vy, float *__restrict__ vz, int32_t *__restrict__ tet,
-                                                 int32_t *__restrict__ id) {
-    // segment blockIdx.x % kLeaverSegs of the list (the grid is a multiple of kLeaverSegs blocks)
-    const uint32_t seg = blockIdx.x % kLeaverSegs, per = gridDim.x / kLeaverSegs;
-    const uint32_t n = min(emi_n[seg], emi_cap);
-    for (uint32_t k = (blockIdx.x / kLeaverSegs) * blockDim.x + threadIdx.x; k < n; k += per * blockDim.x) {
-        const int64_t e = (int64_t)seg * emi_cap + k;
-        const int64_t src = emi_slot[e];
-        const int32_t t = emi_tet[e];
-        if (t < 0 || t >= own[nblk]) continue;  // only tets of the mesh are listed
-        const int32_t d = tblk[t];
-        if (d < 0 || d >= nblk || own[d] > t || own[d + 1] <= t) continue;  // no block owns the tet
-        const int32_t c = atomicAdd(&fill[d], 1);
-        const int32_t nf = nfree[d];
-        int64_t dst;
-        if (c < nf) {
-            dst = (int64_t)d * kChunk + freel[(int64_t)d * kChunk + c];
-        } else {
-            const int32_t j = top[d] + (c - nf);
-            if (j >= kChunk) continue;  // no room: stays
-            dst = (int64_t)d * kChunk + j;
-        }
-        x[dst] = x[src]; y[dst] = y[src]; z[dst] = z[src];
-        vx[dst] = vx[src]; vy[dst] = vy[src]; vz[dst] = vz[src];
-        tet[dst] = t; id[dst] = id[src];
-        tet[src] = -1;
-    }
-}
-
-// The owner of each tet after a sort: tblk[t] = b for t in [own[b], own[b+1]) (one block of
-// threads per layout block; the ranges tile [0, nt)).
-__global__ void k_tet_owner(const int32_t *__restrict__ own, int32_t *__restrict__ tblk) {
-    const int32_t b = blockIdx.x;
-    const int32_t t0 = own[b], t1 = own[b + 1];
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) tblk[t] = b;
-}
-
-// Block layout after a re-sort of `live` particles: block b holds sorted particles
-// [b QH_FILL, (b+1) QH_FILL) in its first slots and owns the tets from its first particle's to
-// the next block's first particle's; its other slots are free (tet -1).
-__global__ void k_blocks_init(int32_t *__restrict__ tet, int64_t live, int32_t nblk, int32_t nt,
-                              int32_t *__restrict__ own, int32_t *__restrict__ top, int32_t *__restrict__ fill,
-                              int32_t *__restrict__ nfree) {
-    const int32_t b = blockIdx.x;
-    const int64_t first = (int64_t)b * QH_FILL;
-    const int32_t cnt = (int32_t)min((int64_t)QH_FILL, live - first);
-    for (int j = cnt + threadIdx.x; j < kChunk; j += blockDim.x) tet[(int64_t)b * kChunk + j] = -1;
-    if (threadIdx.x == 0) {
-        own[b] = b == 0 ? 0 : tet[(int64_t)b * kChunk];
-        top[b] = cnt;
-        fill[b] = 0;
-        nfree[b] = 0;
-        if (b == nblk - 1) own[nblk] = nt;
-    }
+// owned tet ranges after a sort: own[b] = tet of the block's first particle, own[0] = 0,
+// own[nblocks] = nt
+__global__ void k_own(const int32_t *__restrict__ tet, int64_t n, int32_t nblocks, int32_t nt,
+                      int32_t *__restrict__ own) {
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nblocks) return;
+    own[b] = b == 0 ? 0 : b == nblocks ? nt : tet[(int64_t)b * kChunk];
 }
 
 hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
-    if (s.n == 0 || s.nblk == 0) return hipSuccess;
-    // the list of particles leaving their block's range: room for 1/8 of the slots, in
-    // kLeaverSegs segments (emi_cap entries each)
-    const int64_t want = std::max<int64_t>(s.slots() / 8 / kLeaverSegs, 64);
-    if (c->emi_cap < want) {
-        hipError_t e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return e;
-        qh_release(c, c->emi_slot), qh_release(c, c->emi_tet);
-        c->emi_cap = 0;
-        if (qh_alloc(c, &c->emi_slot, want * kLeaverSegs) || qh_alloc(c, &c->emi_tet, want * kLeaverSegs))
-            return hipErrorOutOfMemory;
-        if (!c->emi_n && qh_alloc(c, &c->emi_n, kLeaverSegs)) return hipErrorOutOfMemory;
-        c->emi_cap = want;
-    }
+    if (s.n == 0) return hipSuccess;
     StepArgs a;
     a.geo = c->geo; a.frec = c->frec; a.tnodes = c->tnodes; a.tedges = c->tedges; a.tnbr = c->tnbr;
     a.x = s.x; a.y = s.y; a.z = s.zz; a.vx = s.vx; a.vy = s.vy; a.vz = s.vz;
-    a.tet = s.tet; a.pid = s.id; a.own = s.own; a.nt = (int32_t)c->hm.Nt;
-    a.top = s.top; a.fill = s.fill; a.nfree = s.nfree; a.freel = s.freel;
-    a.emi_slot = c->emi_slot; a.emi_tet = c->emi_tet; a.emi_n = c->emi_n; a.emi_cap = (uint32_t)c->emi_cap;
+    a.tet = s.tet; a.pid = s.id; a.own = s.own; a.n = s.n; a.nt = (int32_t)c->hm.Nt;
     a.mail_cnt = c->mail_cnt; a.mail = c->mail; a.ovf = s.ovf;
     a.hqm = (float)(0.5 * s.qm * c->phys.dt);
     a.dt = (float)c->phys.dt;
@@ -838,11 +692,10 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     a.absorb = c->walls == QH_WALLS_ABSORB ? 1 : 0;
     a.g = c->g; a.Q = c->Q; a.acc_tet = c->acc_tet; a.counters = c->counters;
     a.species = sidx; a.cap = c->cap_segments; a.seg_count = c->seg_count; a.seg_buf = c->seg_buf;
-    dim3 grid((unsigned)s.nblk);
+    dim3 grid((unsigned)((s.n + kChunk - 1) / kChunk));
     const unsigned nmail = (unsigned)((c->hm.Nt + kMailTets - 1) / kMailTets);
     hipError_t e = hipMemsetAsync(c->mail_cnt, 0, sizeof(unsigned int) * nmail, c->stream);
     if (e != hipSuccess) return e;
-    if ((e = hipMemsetAsync(c->emi_n, 0, sizeof(unsigned int) * kLeaverSegs, c->stream)) != hipSuccess) return e;
     // few particles on a large mesh (the blocks' windows cannot cover it): one fill clears the
     // per-tet sums instead of each block zeroing a long owned range
     a.zeroed = (int64_t)grid.x * kWin < c->hm.Nt ? 1 : 0;
@@ -850,14 +703,8 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
         return e;
     if (capture) hipLaunchKernelGGL(k_particle_step<true>, grid, dim3(kBlock), 0, c->stream, a);
     else hipLaunchKernelGGL(k_particle_step<false>, grid, dim3(kBlock), 0, c->stream, a);
-    // the listed particles move to the blocks owning their tets (per segment, a strided loop);
-    // a species not sorted yet (particles only appended so far) has no owners to move to
-    const unsigned gm = (unsigned)(kLeaverSegs * std::min<int64_t>((c->emi_cap + 255) / 256, 4));
-    if (s.tblk) hipLaunchKernelGGL(k_migrate, dim3(gm), dim3(256), 0, c->stream, c->emi_slot, c->emi_tet, c->emi_n,
-                       (uint32_t)c->emi_cap, s.own, s.tblk, (int32_t)s.nblk, s.fill, s.nfree, s.top, s.freel, s.x, s.y, s.zz,
-                       s.vx, s.vy, s.vz, s.tet, s.id);
     const HostMesh &m = c->hm;
-    hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(kMailThreads), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
+    hipLaunchKernelGGL(k_mail_apply, dim3(nmail), dim3(256), 0, c->stream, c->mail_cnt, c->mail, s.z, m.Nt, c->acc_tet);
     constexpr int kLpiE = 2, kLpiN = 8;  // lanes per edge / per node (edges border 4-6 tets, nodes ~24)
     const unsigned ge = (unsigned)(((m.Ne + 256 / kLpiE - 1) / (256 / kLpiE) + 7) / 8 * 8);
     const unsigned gn = (unsigned)(((m.Nn + 256 / kLpiN - 1) / (256 / kLpiN) + 7) / 8 * 8);
@@ -869,7 +716,7 @@ hipError_t launch_particle_step(qh_ctx *c, Species &s, int sidx, bool capture) {
     return hipGetLastError();
 }
 
-int64_t qh_species_blocks(int64_t n) { return (n + QH_FILL - 1) / QH_FILL; }
+int64_t qh_species_blocks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
 // ------------------------------------------------------------------------------------------
 // W0 charge of the present positions (after an upload).
@@ -880,7 +727,6 @@ __global__ void __launch_bounds__(256) k_charge(const float4 *__restrict__ geo, 
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int t = tet[i];
-    if (t < 0) return;  // a free slot
     float l[4];
     int L[4];
     lam4(geo[3 * t], geo[3 * t + 1], geo[3 * t + 2], x[i], y[i], z[i], l);
@@ -890,39 +736,26 @@ __global__ void __launch_bounds__(256) k_charge(const float4 *__restrict__ geo, 
     for (int q = 0; q < 4; ++q) atomic_add_i64(Q + nv[q], (long long)zq * QH_SCALE * L[q]);
 }
 
-// W0 charge of the particles in slots [first, end of the layout) of a species, added to Q.
+// W0 charge of particles [first, n) of a species, added to Q.
 hipError_t launch_charge_deposit(qh_ctx *c, Species &s, int64_t first) {
-    const int64_t n = s.slots() - first;
+    const int64_t n = s.n - first;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_charge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->geo,
                        c->tnodes, s.x + first, s.y + first, s.zz + first, s.tet + first, n, s.z, c->Q);
     return hipGetLastError();
 }
 
-// Blocks b0 .. b1-1 appended after the last one (particles added without a sort, n_new of them
-// in their slots from the first): they own no tets (own = nt) until the next sort, so their
-// particles move to their tets' blocks when those have room; the slots past the last particle
-// are free.
-__global__ void k_blocks_append(int32_t *__restrict__ own, int32_t *__restrict__ top, int32_t *__restrict__ fill,
-                                int32_t *__restrict__ nfree, int32_t *__restrict__ tet, int32_t b0, int32_t b1,
-                                int64_t n_new, int32_t nt) {
-    const int32_t b = b0 + (int32_t)blockIdx.x;
-    const int64_t first = (int64_t)(b - b0) * kChunk;
-    const int32_t cnt = (int32_t)min((int64_t)kChunk, n_new - first);
-    for (int j = cnt + threadIdx.x; j < kChunk; j += blockDim.x) tet[(int64_t)b * kChunk + j] = -1;
-    if (threadIdx.x == 0) {
-        if (b == 0) own[0] = nt;  // a species that held no block
-        own[b + 1] = nt;
-        top[b] = cnt;
-        fill[b] = 0;
-        nfree[b] = 0;
-    }
+// Ownership after particles are appended without a sort: own[0] = 0, the blocks past the old
+// last one own no tets (own[b] = nt for b in (b0, b1]); the old last block keeps [own, nt).
+__global__ void k_own_extend(int32_t *__restrict__ own, int32_t b0, int32_t b1, int32_t nt) {
+    const int32_t b = b0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b > b1) return;
+    own[b] = b == 0 ? 0 : (b == b0 ? own[b] : nt);
 }
 
-hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1, int64_t n_new) {
-    if (b1 <= b0) return hipSuccess;
-    hipLaunchKernelGGL(k_blocks_append, dim3((unsigned)(b1 - b0)), dim3(256), 0, c->stream, s.own, s.top, s.fill,
-                       s.nfree, s.tet, b0, b1, n_new, (int32_t)c->hm.Nt);
+hipError_t launch_own_extend(qh_ctx *c, Species &s, int32_t b0, int32_t b1) {
+    hipLaunchKernelGGL(k_own_extend, dim3((unsigned)((b1 - b0 + 1 + 255) / 256)), dim3(256), 0, c->stream, s.own, b0,
+                       b1, (int32_t)c->hm.Nt);
     return hipGetLastError();
 }
 
@@ -1184,10 +1017,7 @@ __global__ void k_hist(const int32_t *__restrict__ tet, int64_t n, int32_t nt, i
     const int t = valid ? sort_key(tet[i], nt) : -1;
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
-    // free slots and absorbed particles (the last bucket) are dropped uncounted: they are many
-    // (the blocks' spare slots), and counting them would put one atomic per wave on one address;
-    // the exclusive scan's value at that bucket is then the number of particles kept
-    if (valid && rank == 0 && t < nt) atomicAdd(&hist[t], len);
+    if (valid && rank == 0) atomicAdd(&hist[t], len);
 }
 
 // scan over chunks of 1024: per-chunk sums
@@ -1245,9 +1075,6 @@ __global__ void __launch_bounds__(1024) k_scan_final(const int32_t *__restrict__
     if (i < n) out[i] = sums[blockIdx.x] + sh[threadIdx.x] - v;
 }
 
-// Sorted position p (a particle's rank among the kept ones, by tet) goes to slot
-// (p / QH_FILL) QH_CHUNK + p % QH_FILL of the block layout; particles of the last bucket (free
-// slots, absorbed particles) are dropped.
 __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
                           const float *__restrict__ z, const float *__restrict__ vx,
                           const float *__restrict__ vy, const float *__restrict__ vz,
@@ -1261,55 +1088,42 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
     int head, len, rank;
     wave_runs(t, valid, head, len, rank);
     int32_t first = 0;
-    if (valid && rank == 0 && t < nt) first = atomicAdd(&cursor[t], len);
+    if (valid && rank == 0) first = atomicAdd(&cursor[t], len);
     first = __shfl(first, head, 64);
-    if (!valid || t == nt) return;
-    const int32_t p = first + rank;
-    const int64_t j = (int64_t)(p / QH_FILL) * kChunk + p % QH_FILL;
+    if (!valid) return;
+    const int32_t j = first + rank;
     ox[j] = x[i]; oy[j] = y[i]; oz[j] = z[i];
     ovx[j] = vx[i]; ovy[j] = vy[i]; ovz[j] = vz[i];
     otet[j] = tet[i]; oid[j] = id[i];
 }
 
-int qh_sort_species(qh_ctx *c, Species &s) { return qh_sort_species(c, s, s.slots()); }
-
-int qh_sort_species(qh_ctx *c, Species &s, int64_t extent) {
-    if (extent == 0 || s.n == 0) {
-        s.n = 0;
-        s.nblk = 0;
-        return QH_OK;
-    }
+int qh_sort_species(qh_ctx *c, Species &s) {
+    if (s.n == 0) return QH_OK;
     int32_t nt = (int32_t)c->hm.Nt;
-    const int32_t nk = nt + 1;  // buckets: the tets, then free slots and absorbed particles
+    const int32_t nk = nt + 1;  // buckets: the tets, then the particles absorbed by a wall
     QH_HIP(c, hipMemsetAsync(c->hist, 0, sizeof(int32_t) * nk, c->stream));
-    unsigned pb = (unsigned)((extent + 255) / 256);
-    hipLaunchKernelGGL(k_hist, dim3(pb), dim3(256), 0, c->stream, s.tet, extent, nt, c->hist);
+    unsigned pb = (unsigned)((s.n + 255) / 256);
+    hipLaunchKernelGGL(k_hist, dim3(pb), dim3(256), 0, c->stream, s.tet, s.n, nt, c->hist);
     int32_t chunks = (nk + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_sums, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nk, c->scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->scan_tmp, chunks);
     hipLaunchKernelGGL(k_scan_final, dim3(chunks), dim3(1024), 0, c->stream, c->hist, nk, c->scan_tmp, c->cursor);
-    int32_t live = 0;  // the start of the last bucket
-    QH_HIP(c, hipMemcpyAsync(&live, c->cursor + nt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    QH_HIP(c, hipStreamSynchronize(c->stream));
-    const int64_t nblk = qh_species_blocks(live);
-    if (nblk * kChunk > s.cap) return qh_fail(c, QH_ESTATE, "species storage smaller than its block layout");
-    if (live > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(pb), dim3(256), 0, c->stream, extent, s.x, s.y, s.zz, s.vx, s.vy, s.vz,
-                           s.tet, s.id, nt, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
+    const bool absorb = c->walls == QH_WALLS_ABSORB;
+    int32_t live = (int32_t)s.n;  // the start of the last bucket
+    if (absorb) QH_HIP(c, hipMemcpyAsync(&live, c->cursor + nt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(k_scatter, dim3(pb), dim3(256), 0, c->stream, s.n, s.x, s.y, s.zz, s.vx, s.vy, s.vz, s.tet,
+                       s.id, nt, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
     QH_HIP(c, hipGetLastError());
     std::swap(s.x, s.sx); std::swap(s.y, s.sy); std::swap(s.zz, s.sz);
     std::swap(s.vx, s.svx); std::swap(s.vy, s.svy); std::swap(s.vz, s.svz);
     std::swap(s.tet, s.stet); std::swap(s.id, s.sid);
-    s.n = live;
-    s.nblk = nblk;
-    if (nblk == 0) return QH_OK;
-    hipLaunchKernelGGL(k_blocks_init, dim3((unsigned)nblk), dim3(64), 0, c->stream, s.tet, (int64_t)live,
-                       (int32_t)nblk, nt, s.own, s.top, s.fill, s.nfree);
-    if (!s.tblk) {
-        int rc = qh_alloc(c, &s.tblk, nt);
-        if (rc) return rc;
+    if (absorb) {
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        s.n = live;  // the absorbed particles sit past the live ones and are dropped
+        if (s.n == 0) return QH_OK;
     }
-    hipLaunchKernelGGL(k_tet_owner, dim3((unsigned)nblk), dim3(64), 0, c->stream, s.own, s.tblk);
+    int32_t nb = (int32_t)qh_species_blocks(s.n);
+    hipLaunchKernelGGL(k_own, dim3((nb + 1 + 255) / 256), dim3(256), 0, c->stream, s.tet, s.n, nb, nt, s.own);
     QH_HIP(c, hipGetLastError());
     return QH_OK;
 }
