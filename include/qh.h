@@ -292,6 +292,19 @@ int qh_deposit(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t
                const int32_t *lam1, const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet,
                const int32_t *pt_lam, const int32_t *pt_z, int64_t *g_out, int64_t *q_out);
 
+/* qh_deposit without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments and
+ * results, bit for bit. The staged lists and the edge and node sums live in one file-scope
+ * device array of 64 MiB per GPU (held until the process ends; its address is looked up when a
+ * context is created on the device). A call needs 8 bytes per edge and node of the mesh, 40 per
+ * piece and 24 per point; beyond 64 MiB it returns QH_EINVAL and does nothing. Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (several contexts or threads, or
+ * streams not ordered with each other) race and must be serialised by the caller. Synchronises
+ * the context stream. */
+int qh_deposit_noalloc(qh_ctx *ctx, int64_t n_seg, const int32_t *seg_tet, const int32_t *lam0,
+                       const int32_t *lam1, const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet,
+                       const int32_t *pt_lam, const int32_t *pt_z, int64_t *g_out, int64_t *q_out);
+
 /* Quasi-Helmholtz split of the present electric field (Sec. III, the projector P^Sigma_e; eq.
  * zero_mean_constraint under natural walls): rho_bar = G^T [*eps] e (the discrete divergence,
  * which the Gauss-law correction holds equal to the charge), E_ns = K^{-1} rho_bar (node

@@ -37,7 +37,7 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
            "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
            "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load",
-           "qh_fields_energy", "qh_precond_apply"]
+           "qh_fields_energy", "qh_precond_apply", "qh_deposit_noalloc"]
 
 
 class QhError(RuntimeError):
@@ -142,6 +142,7 @@ def lib():
             "qh_capture_segments": [p, i64],
             "qh_segments_download": [p, C.POINTER(i64), p, p, p, p, p, p],
             "qh_deposit": [p, i64, p, p, p, p, i64, p, p, p, p, p],
+            "qh_deposit_noalloc": [p, i64, p, p, p, p, i64, p, p, p, p, p],
             "qh_field_solve": [p, i32, p, p, d, i32, i32, C.POINTER(SolveStats)],
             "qh_matrix_info": [p, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
             "qh_matrix_download": [p, i32, p, p, p],
@@ -392,6 +393,16 @@ class Context:
         Q = np.zeros(self.info.n_nodes, np.int64)
         self._check(self.L.qh_deposit(self.h, a[0].shape[0], _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]),
                                       a[4].shape[0], _ptr(a[4]), _ptr(a[5]), _ptr(a[6]), _ptr(g), _ptr(Q)))
+        return g, Q
+
+    def deposit_noalloc(self, seg_tet, lam0, lam1, seg_z, pt_tet, pt_lam, pt_z):
+        """qh_deposit through the library's static scratch array (no device allocation)."""
+        a = [_c(seg_tet, np.int32), _c(lam0, np.int32), _c(lam1, np.int32), _c(seg_z, np.int32),
+             _c(pt_tet, np.int32), _c(pt_lam, np.int32), _c(pt_z, np.int32)]
+        g = np.zeros(self.info.n_edges, np.int64)
+        Q = np.zeros(self.info.n_nodes, np.int64)
+        self._check(self.L.qh_deposit_noalloc(self.h, a[0].shape[0], _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]),
+                                              a[4].shape[0], _ptr(a[4]), _ptr(a[5]), _ptr(a[6]), _ptr(g), _ptr(Q)))
         return g, Q
 
     def fields_decompose(self, tol=1e-10, max_it=5000, allow=()):

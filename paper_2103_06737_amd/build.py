@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqh.so")
-SOURCES = ["qh_mesh.hip", "qh_particles.hip", "qh_solver.hip", "qh_learned.hip", "qh_diag.hip", "qh_api.hip"]
+SOURCES = ["qh_mesh.hip", "qh_particles.hip", "qh_solver.hip", "qh_learned.hip", "qh_diag.hip", "qh_static.hip",
+           "qh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          # no packed FP32 instructions: hipcc forms them from plain float code otherwise
@@ -27,7 +28,7 @@ def _compile(src: str) -> str:
 
 def build() -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=5) as ex:
+    with cf.ThreadPoolExecutor(max_workers=7) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])

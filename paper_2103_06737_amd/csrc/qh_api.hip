@@ -252,6 +252,9 @@ int qh_create(qh_ctx **out, int device, void *stream) {
         delete c;
         return QH_ENOMEM;
     }
+    // the address of this device's static scratch array (qh_deposit_noalloc); a failure is kept
+    // in the context's message and reported by that call
+    (void)qh_static_scratch_init(c);
     *out = c;
     return QH_OK;
 }
@@ -978,6 +981,26 @@ int qh_deposit(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *
     (void)hipFree(gd);
     if (e != hipSuccess) return qh_fail(c, QH_EHIP, std::string("deposit: ") + hipGetErrorString(e));
     return QH_OK;
+}
+
+int qh_deposit_noalloc(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *lam0, const int32_t *lam1,
+                       const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet, const int32_t *pt_lam,
+                       const int32_t *pt_z, int64_t *g_out, int64_t *q_out) {
+    if (!c || n_seg < 0 || n_pt < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->have_mesh) return qh_fail(c, QH_ESTATE, "no mesh");
+    if (n_seg > 0 && (!seg_tet || !lam0 || !lam1 || !seg_z)) return QH_EINVAL;
+    if (n_pt > 0 && (!pt_tet || !pt_lam || !pt_z)) return QH_EINVAL;
+    const HostMesh &m = c->hm;
+    const size_t need = qh_static_deposit_bytes(m.Ne, m.Nn, n_seg, n_pt), have = qh_static_scratch_bytes();
+    if (n_seg > ((int64_t)1 << 40) || n_pt > ((int64_t)1 << 40) || need > have)
+        return qh_fail(c, QH_EINVAL, "deposit needs " + std::to_string(need) + " bytes of the static scratch array, which holds " +
+                                         std::to_string(have) + " (8 bytes per edge and node, 40 per piece, 24 per point)");
+    for (int64_t s = 0; s < n_seg; ++s)
+        if (seg_tet[s] < 0 || seg_tet[s] >= m.Nt) return qh_fail(c, QH_EINVAL, "segment tet out of range");
+    for (int64_t p = 0; p < n_pt; ++p)
+        if (pt_tet[p] < 0 || pt_tet[p] >= m.Nt) return qh_fail(c, QH_EINVAL, "point tet out of range");
+    return qh_static_deposit(c, n_seg, seg_tet, lam0, lam1, seg_z, n_pt, pt_tet, pt_lam, pt_z, g_out, q_out);
 }
 
 int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_stats_t *stats) {

@@ -313,6 +313,14 @@ hipError_t launch_field_energy(qh_ctx *c, double *part, double *out);
 hipError_t launch_divb_check(qh_ctx *c, const int64_t *b, unsigned long long *bad);
 hipError_t launch_fields_in(qh_ctx *c, const double *e_in, double *x);
 
+// qh_static.hip: the deposit from explicit lists in a file-scope device array (no allocation)
+size_t qh_static_scratch_bytes();
+int qh_static_scratch_init(qh_ctx *c);
+size_t qh_static_deposit_bytes(int64_t ne, int64_t nn, int64_t n_seg, int64_t n_pt);
+int qh_static_deposit(qh_ctx *c, int64_t n_seg, const int32_t *seg_tet, const int32_t *lam0, const int32_t *lam1,
+                      const int32_t *seg_z, int64_t n_pt, const int32_t *pt_tet, const int32_t *pt_lam,
+                      const int32_t *pt_z, int64_t *g_out, int64_t *q_out);
+
 // qh_solver.hip
 struct SolveResult {
     int iters = 0;
