@@ -378,20 +378,40 @@ int qh_precond_loss_grad(qh_ctx *ctx, const float *probes, double *loss, float *
 typedef struct {
     int32_t steps;          /* Adam steps, 16 Rademacher probes each */
     float lr;
-    uint64_t seed;          /* probe generator seed */
+    uint64_t seed;          /* probe and pair-batch generator seed */
     int32_t validate_every; /* PCG on the first (up to 2) pairs every k steps; best weights kept */
     double val_tol;         /* validation solve tolerance (e.g. 1e-8) */
     int32_t val_max_it;
+    double pair_weight;     /* lambda: the objective is L + lambda L_E, L_E the energy-norm loss on a
+                               batch of 16 recorded solver pairs per step (qh_pairs_record); 0: L only */
 } qh_train_params_t;
 typedef struct {
     int32_t steps_done;
     double loss_first, loss_last;
     int32_t val_iters_jacobi, val_iters_best, best_step; /* summed over the validation pairs */
     float ms;
+    double pair_loss_first, pair_loss_last; /* L_E of the first and last step's batch (0 without pairs) */
+    double val_energy_err;  /* max over the validation pairs of ||x - M b||_A / ||x||_A, kept weights */
 } qh_train_stats_t;
-/* Train on the GPU. rhs, sol: n_pairs x n_int_edges (pair-major) right-hand sides and solutions
- * of the edge system produced by the plain solver; they validate each candidate (PCG iterations
- * to val_tol) and select the weights kept. */
+/* Solver pairs for training: every following field step of qh_pic_step (QH_FIELDS_SOLVE or
+ * QH_FIELDS_WAVE) stores its edge system's right-hand side and solution e* (as solved, before the
+ * Gauss-law correction) in FP32 into a device bank of `capacity` pairs (8 bytes per interior edge
+ * and pair), until it is full. A call replaces the bank (capacity 0 frees it). With the plain
+ * (Jacobi) solver these are the pairs "the plain solver generates". */
+int qh_pairs_record(qh_ctx *ctx, int32_t capacity);
+int qh_pairs_count(const qh_ctx *ctx, int32_t *n);
+/* Appends n_pairs host pairs (rhs, sol: n_pairs x n_int_edges, pair-major) to the bank (after
+ * qh_pairs_record; QH_EINVAL past its capacity). */
+int qh_pairs_add(qh_ctx *ctx, int32_t n_pairs, const double *rhs, const double *sol);
+/* The energy-norm loss L_E on 16 bank pairs (idx: 16 indices) and, if grad != NULL, dL_E/dweights
+ * (QH_MLP_NPARAM floats) from the same kernels training uses. */
+int qh_precond_pair_loss_grad(qh_ctx *ctx, const int32_t *idx, double *loss, float *grad);
+/* Train on the GPU: Adam on L (the log Kaporin number above, 16 Rademacher probes per step) plus
+ * pair_weight times the energy-norm loss L_E = mean ||x - G^T G b||_A^2 / ||x||_A^2 over a batch
+ * of 16 pairs drawn from the recorded bank (QH_ESTATE if pair_weight > 0 and the bank is empty).
+ * rhs, sol: n_pairs x n_int_edges (pair-major) held-out right-hand sides and solutions of the
+ * edge system from the plain solver: the first (up to 2) validate each candidate (PCG iterations
+ * to val_tol) and select the weights kept, and give the kept network's energy-norm error. */
 int qh_precond_train(qh_ctx *ctx, const qh_train_params_t *params, int32_t n_pairs,
                      const double *rhs, const double *sol, qh_train_stats_t *stats);
 

@@ -17,8 +17,9 @@ with tr(G A G^T)/n estimated by T = mean_p v_p^T G A G^T v_p / |v_p|^2 over Rade
 K >= 1 with equality iff G A G^T is a multiple of I; CG converges in a number of iterations
 bounded through K, and L does not depend on the scale of G. Gradient (w_p = G^T v_p):
     dL/dG_ij = (2 / (P T)) sum_p (A w_p)_j v_p,i / |v_p|^2  - [i = j] 2 / (n G_ii).
-The (rhs, solution) pairs of the plain solver measure the result: PCG iterations to 1e-8 and
-the energy-norm error ||x - M b||_A / ||x||_A.
+Solver pairs (b, x) with A x = b, from the plain solver, enter training through the energy-norm
+loss L_E = mean ||x - M b||_A^2 / ||x||_A^2 (pair_energy_loss_grad), added to L with a weight;
+they also measure the result: PCG iterations to 1e-8 and the energy-norm error.
 """
 from __future__ import annotations
 
@@ -145,6 +146,30 @@ def kaporin_loss_grad(w, A, feats, rows, cols, V):
     sig = 1.0 / (1.0 + np.exp(-(o + S0)))
     d_o = np.where(diag, dG * sig / np.sqrt(dA[rows]), dG / np.sqrt(dA[cols]))
     return L, mlp_backward(w, cache, d_o), vals
+
+
+def pair_energy_loss_grad(w, A, feats, rows, cols, B, X):
+    """Energy-norm loss of the preconditioner on solver pairs (columns of B, X with A x = b):
+        L_E = mean_k ||x_k - M b_k||_A^2 / ||x_k||_A^2,   M = G^T G,
+    and its gradients with respect to the network weights. With v = x - G^T G b,
+        dL_E/dG_ij = -(2/P) sum_k [(G b_k)_i (A v_k)_j + (G A v_k)_i (b_k)_j] / ||x_k||_A^2."""
+    n = A.shape[0]
+    dA = A.diagonal()
+    o, cache = mlp_forward(w, feats)
+    G, vals = factor(o, rows, cols, dA, n)
+    GB = G @ B
+    V = X - G.T @ GB
+    AV = A @ V
+    xAx = np.einsum("ik,ik->k", X, A @ X)
+    P = B.shape[1]
+    L = float(np.mean(np.einsum("ik,ik->k", V, AV) / xAx))
+    GAV = G @ AV
+    dG = -2.0 / P * (np.einsum("pk,pk,k->p", GB[rows], AV[cols], 1.0 / xAx)
+                     + np.einsum("pk,pk,k->p", GAV[rows], B[cols], 1.0 / xAx))
+    diag = rows == cols
+    sig = 1.0 / (1.0 + np.exp(-(o + S0)))
+    d_o = np.where(diag, dG * sig / np.sqrt(dA[rows]), dG / np.sqrt(dA[cols]))
+    return L, mlp_backward(w, cache, d_o)
 
 
 def energy_error(A, G, b, x):

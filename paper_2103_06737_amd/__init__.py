@@ -37,7 +37,8 @@ EXPORTS = ["qh_create", "qh_destroy", "qh_last_error", "qh_mesh_upload", "qh_mes
            "qh_particles_count", "qh_particles_ids", "qh_set_walls", "qh_particles_inject", "qh_probe_fields",
            "qh_fields_decompose", "qh_locate", "qh_precond_save", "qh_precond_load", "qh_fields_upload_dev",
            "qh_fields_download_dev", "qh_deposits_download_dev", "qh_state_save", "qh_state_load",
-           "qh_fields_energy", "qh_precond_apply", "qh_deposit_noalloc"]
+           "qh_fields_energy", "qh_precond_apply", "qh_deposit_noalloc", "qh_pairs_record", "qh_pairs_count",
+           "qh_pairs_add", "qh_precond_pair_loss_grad"]
 
 
 class QhError(RuntimeError):
@@ -78,13 +79,14 @@ class StepStats(C.Structure):
 
 class TrainParams(C.Structure):
     _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64), ("validate_every", C.c_int32),
-                ("val_tol", C.c_double), ("val_max_it", C.c_int32)]
+                ("val_tol", C.c_double), ("val_max_it", C.c_int32), ("pair_weight", C.c_double)]
 
 
 class TrainStats(C.Structure):
     _fields_ = [("steps_done", C.c_int32), ("loss_first", C.c_double), ("loss_last", C.c_double),
                 ("val_iters_jacobi", C.c_int32), ("val_iters_best", C.c_int32), ("best_step", C.c_int32),
-                ("ms", C.c_float)]
+                ("ms", C.c_float), ("pair_loss_first", C.c_double), ("pair_loss_last", C.c_double),
+                ("val_energy_err", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -153,6 +155,10 @@ def lib():
             "qh_precond_get_weights": [p, p, i64],
             "qh_precond_factor": [p, C.POINTER(i64), p, p, p],
             "qh_precond_apply": [p, p, p],
+            "qh_pairs_record": [p, i32],
+            "qh_pairs_count": [p, C.POINTER(i32)],
+            "qh_pairs_add": [p, i32, p, p],
+            "qh_precond_pair_loss_grad": [p, p, C.POINTER(d), p],
             "qh_precond_loss_grad": [p, p, C.POINTER(d), p],
             "qh_precond_train": [p, C.POINTER(TrainParams), i32, p, p, C.POINTER(TrainStats)],
         }
@@ -489,9 +495,29 @@ class Context:
         self._check(self.L.qh_precond_loss_grad(self.h, _ptr(probes), C.byref(loss), _ptr(grad)))
         return loss.value, grad
 
+    def pairs_record(self, capacity):
+        """Record the next field steps' (rhs, solution) pairs into a device bank of `capacity`."""
+        self._check(self.L.qh_pairs_record(self.h, int(capacity)))
+
+    def pairs_add(self, rhs, sol):
+        rhs, sol = _c(rhs, np.float64), _c(sol, np.float64)
+        self._check(self.L.qh_pairs_add(self.h, rhs.shape[0], _ptr(rhs), _ptr(sol)))
+
+    def precond_pair_loss_grad(self, idx, want_grad=True):
+        idx = _c(idx, np.int32)
+        loss = C.c_double()
+        grad = np.zeros(MLP_NPARAM, np.float32) if want_grad else None
+        self._check(self.L.qh_precond_pair_loss_grad(self.h, _ptr(idx), C.byref(loss), _ptr(grad)))
+        return loss.value, grad
+
+    def pairs_count(self):
+        n = C.c_int32()
+        self._check(self.L.qh_pairs_count(self.h, C.byref(n)))
+        return n.value
+
     def precond_train(self, steps=200, lr=3e-3, seed=1, validate_every=25, val_tol=1e-8, val_max_it=3000,
-                      rhs=None, sol=None):
-        P = TrainParams(steps, lr, seed, validate_every, val_tol, val_max_it)
+                      rhs=None, sol=None, pair_weight=0.0):
+        P = TrainParams(steps, lr, seed, validate_every, val_tol, val_max_it, float(pair_weight))
         n_pairs = 0 if rhs is None else rhs.shape[0]
         rhs = None if rhs is None else _c(rhs, np.float64)
         sol = None if sol is None else _c(sol, np.float64)

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <numeric>
 
+#include <random>
+
 #include "qh_internal.h"
 #include "qh_spmv.h"
 
@@ -1094,6 +1096,8 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             c->last_fallbacks = fallbacks;
             if (!se.converged) status = QH_ENOTCONV;
             QH_HIP(c, hipMemcpyAsync(c->e_star, c->cge.x, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice, c->stream));
+            // the (rhs, solution) pair of this step into the bank, while recording
+            if (c->lp.pair_rec && (rc = qh_learned_record_pair(c, c->cge.b, c->e_star))) return rc;
             if (P->gauss) {
                 t0 = qh_tbeg(c);
                 QH_HIP(c, launch_gauss_rhs(c, c->scratch_d, P->tol_node));
@@ -1617,6 +1621,77 @@ int qh_precond_loss_grad(qh_ctx *c, const float *probes, double *loss, float *gr
     return sync(c);
 }
 
+int qh_pairs_record(qh_ctx *c, int32_t capacity) {
+    if (!c || capacity < 0) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    LearnedPrec &L = c->lp;
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    qh_release(c, L.pair_b), qh_release(c, L.pair_x), qh_release(c, L.pair_xb);
+    L.pair_cap = L.pair_n = 0;
+    L.pair_rec = false;
+    if (capacity == 0) return QH_OK;
+    const int64_t n = c->A.n;
+    int rc;
+    if ((rc = qh_alloc(c, &L.pair_b, n * capacity)) || (rc = qh_alloc(c, &L.pair_x, n * capacity)) ||
+        (rc = qh_alloc(c, &L.pair_xb, capacity)) || (!L.ppart && (rc = qh_alloc(c, &L.ppart, 1024)))) {
+        qh_release(c, L.pair_b), qh_release(c, L.pair_x), qh_release(c, L.pair_xb);
+        return rc;
+    }
+    L.pair_cap = capacity;
+    L.pair_rec = true;
+    return QH_OK;
+}
+
+int qh_pairs_add(qh_ctx *c, int32_t n_pairs, const double *rhs, const double *sol) {
+    if (!c || n_pairs < 0 || (n_pairs > 0 && (!rhs || !sol))) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    LearnedPrec &L = c->lp;
+    if (!L.pair_b) return qh_fail(c, QH_ESTATE, "no pair bank (qh_pairs_record first)");
+    if (L.pair_n + n_pairs > L.pair_cap) return qh_fail(c, QH_EINVAL, "pair bank too small");
+    const int64_t n = c->A.n;
+    int32_t nmax = std::max(c->A.n, c->K.n);
+    int rc;
+    if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
+    const bool rec = L.pair_rec;
+    L.pair_rec = true;
+    for (int32_t k = 0; k < n_pairs; ++k) {
+        QH_HIP(c, hipMemcpyAsync(c->cgx.r, rhs + k * n, 8 * n, hipMemcpyHostToDevice, c->stream));
+        QH_HIP(c, hipMemcpyAsync(c->cgx.z, sol + k * n, 8 * n, hipMemcpyHostToDevice, c->stream));
+        if ((rc = qh_learned_record_pair(c, c->cgx.r, c->cgx.z))) {
+            L.pair_rec = rec;
+            return rc;
+        }
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    L.pair_rec = rec;
+    return QH_OK;
+}
+
+int qh_precond_pair_loss_grad(qh_ctx *c, const int32_t *idx, double *loss, float *grad) {
+    if (!c || !idx || !loss) return QH_EINVAL;
+    if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
+    if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
+    LearnedPrec &L = c->lp;
+    for (int p = 0; p < QH_PAIR_BATCH; ++p)
+        if (idx[p] < 0 || idx[p] >= L.pair_n) return qh_fail(c, QH_EINVAL, "pair index out of the bank");
+    int rc = qh_learned_setup(c);
+    if (rc) return rc;
+    if ((rc = qh_learned_loss_grad(c, nullptr, grad != nullptr, 1.0, idx))) return rc;
+    double l[3];
+    QH_HIP(c, hipMemcpyAsync(l, L.loss, sizeof(l), hipMemcpyDeviceToHost, c->stream));
+    if (grad) QH_HIP(c, hipMemcpyAsync(grad, L.grad, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToHost, c->stream));
+    QH_HIP(c, hipStreamSynchronize(c->stream));
+    *loss = l[2];
+    return QH_OK;
+}
+
+int qh_pairs_count(const qh_ctx *c, int32_t *n) {
+    if (!c || !n) return QH_EINVAL;
+    *n = c->lp.pair_n;
+    return QH_OK;
+}
+
 int qh_precond_train(qh_ctx *c, const qh_train_params_t *P, int32_t n_pairs, const double *rhs, const double *sol,
                      qh_train_stats_t *st) {
     if (!c || !P || P->steps < 0 || n_pairs < 0 || (n_pairs > 0 && !rhs)) return QH_EINVAL;
@@ -1665,12 +1740,31 @@ int qh_precond_train(qh_ctx *c, const qh_train_params_t *P, int32_t n_pairs, con
         QH_HIP(c, hipMemcpyAsync(L.best_w, L.w, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
     }
     S.best_step = 0;
+    // recorded solver pairs in the objective: a batch drawn without replacement per step
+    const bool use_pairs = P->pair_weight > 0.0 && L.pair_n > 0;
+    if (P->pair_weight > 0.0 && L.pair_n == 0) return qh_fail(c, QH_ESTATE, "pair weight > 0 but no recorded pairs");
+    std::mt19937_64 prng(P->seed ^ 0x5eed5eedull);
+    int32_t idx[QH_PAIR_BATCH];
     for (int32_t step = 1; step <= P->steps; ++step) {
         if ((rc = qh_learned_probes(c, L.V, P->seed * 1000003ull + (uint64_t)(L.adam_t + 1)))) return rc;
-        if ((rc = qh_learned_loss_grad(c, L.V, true))) return rc;
+        if (use_pairs)
+            for (int p = 0; p < QH_PAIR_BATCH; ++p) {
+                // distinct pairs while the bank holds enough of them
+                for (;;) {
+                    idx[p] = (int32_t)(prng() % (uint64_t)L.pair_n);
+                    bool dup = false;
+                    for (int q = 0; q < p && L.pair_n >= QH_PAIR_BATCH; ++q) dup |= idx[q] == idx[p];
+                    if (!dup) break;
+                }
+            }
+        if ((rc = qh_learned_loss_grad(c, L.V, true, use_pairs ? P->pair_weight : 0.0, use_pairs ? idx : nullptr)))
+            return rc;
         if (step == 1) {
-            QH_HIP(c, hipMemcpyAsync(&S.loss_first, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            double lf[3];
+            QH_HIP(c, hipMemcpyAsync(lf, L.loss, sizeof(lf), hipMemcpyDeviceToHost, c->stream));
             QH_HIP(c, hipStreamSynchronize(c->stream));
+            S.loss_first = lf[0];
+            S.pair_loss_first = use_pairs ? lf[2] : 0.0;
         }
         L.adam_t += 1;
         if ((rc = qh_learned_adam(c, P->lr, L.adam_t))) return rc;
@@ -1685,16 +1779,49 @@ int qh_precond_train(qh_ctx *c, const qh_train_params_t *P, int32_t n_pairs, con
             }
         }
     }
-    QH_HIP(c, hipMemcpyAsync(&S.loss_last, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double ll[3];
+    QH_HIP(c, hipMemcpyAsync(ll, L.loss, sizeof(ll), hipMemcpyDeviceToHost, c->stream));
     if (n_val > 0) QH_HIP(c, hipMemcpyAsync(L.w, L.best_w, 4 * QH_MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
     QH_HIP(c, hipEventRecord(e1, c->stream));
     QH_HIP(c, hipStreamSynchronize(c->stream));
     (void)hipEventElapsedTime(&S.ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    S.loss_last = ll[0];
+    S.pair_loss_last = use_pairs ? ll[2] : 0.0;
     S.val_iters_best = n_val > 0 ? best : 0;
     L.factor_valid = false;
-    (void)sol;
+    // energy-norm error of the kept network on the validation pairs, ||x - M b||_A / ||x||_A,
+    // with M b from the application kernels and the products with A on the host (FP64)
+    S.val_energy_err = 0.0;
+    if (n_val > 0 && sol) {
+        if ((rc = qh_learned_factor(c))) return rc;
+        const HostCsr &H = c->hA;
+        const double tau = c->tau_assembled;
+        std::vector<double> z(n), vv(n);
+        double worst = 0.0;
+        for (int k = 0; k < n_val; ++k) {
+            QH_HIP(c, hipMemcpyAsync(w.r, rhs + (int64_t)k * n, 8 * (int64_t)n, hipMemcpyHostToDevice, c->stream));
+            QH_HIP(c, launch_prec_apply(c, w.r, w.z, w.partial, nullptr));
+            QH_HIP(c, hipMemcpyAsync(z.data(), w.z, 8 * (int64_t)n, hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+            const double *x = sol + (int64_t)k * n;
+            for (int32_t i = 0; i < n; ++i) vv[i] = x[i] - z[i];
+            double vav = 0.0, xax = 0.0;
+            for (int32_t i = 0; i < n; ++i) {
+                double av = 0.0, ax = 0.0;
+                for (int32_t q = H.ptr[i]; q < H.ptr[i + 1]; ++q) {
+                    const double a = H.val[q] + tau * H.val2[q];
+                    av += a * vv[H.col[q]];
+                    ax += a * x[H.col[q]];
+                }
+                vav += vv[i] * av;
+                xax += x[i] * ax;
+            }
+            worst = std::max(worst, xax > 0 ? std::sqrt(vav / xax) : 0.0);
+        }
+        S.val_energy_err = worst;
+    }
     if (st) *st = S;
     return QH_OK;
 }

@@ -144,6 +144,14 @@ struct LearnedPrec {
     float *gpart = nullptr, *W = nullptr, *AW = nullptr, *V = nullptr;
     double *tpart = nullptr, *lpart = nullptr, *loss = nullptr, *gpart2 = nullptr;
     int32_t adam_t = 0;
+    // (rhs, solution) pairs of the edge system recorded from field steps, FP32, pair-major
+    // [k][n], with x.b of each (= ||x||_A^2 for A x = b), and the training's pair products
+    float *pair_b = nullptr, *pair_x = nullptr;
+    double *pair_xb = nullptr;
+    int32_t pair_cap = 0, pair_n = 0;
+    bool pair_rec = false;
+    float *PB = nullptr, *PX = nullptr, *PY = nullptr, *PV = nullptr, *PAV = nullptr, *PGAV = nullptr;
+    double *ppart = nullptr, *pw = nullptr;
 };
 
 struct qh_ctx {
@@ -341,7 +349,11 @@ int qh_learned_setup(qh_ctx *c);
 int qh_learned_factor(qh_ctx *c);
 unsigned qh_prec_grid(qh_ctx *c);
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done);
-int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad);
+int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad, double pair_weight = 0.0,
+                         const int32_t *pair_idx = nullptr);
+// records the edge system's (rhs, solution) into the next slot of the pair bank
+int qh_learned_record_pair(qh_ctx *c, const double *rhs, const double *sol);
+constexpr int QH_PAIR_BATCH = 16;  // pairs per training step
 int qh_learned_adam(qh_ctx *c, float lr, int32_t t);
 int qh_learned_probes(qh_ctx *c, float *V_dev, uint64_t seed);
 hipError_t launch_diag_inv(qh_ctx *c, const DevCsr &M, double *dinv);

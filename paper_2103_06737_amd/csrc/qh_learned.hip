@@ -399,6 +399,110 @@ __global__ void __launch_bounds__(256) k_kaporin_grad(int64_t nnz, int32_t n, co
     if (threadIdx.x == 0) lpart[blockIdx.x] = sh[0];
 }
 
+// ---------------------------------------------------------------------------------------
+// Solver pairs in the objective: the energy-norm loss
+//   L_E = mean_k ||x_k - G^T G b_k||_A^2 / ||x_k||_A^2
+// over a batch of QH_PAIR_BATCH recorded pairs (b_k, x_k), A x_k = b_k, so ||x_k||_A^2 = x_k.b_k
+// (kept per pair). With Y = G B, V = X - G^T Y, AV = A V, GAV = G AV (node-major [n][16]):
+//   dL_E/dG_ij = -(2/P) sum_k (Y_ik AV_jk + GAV_ik B_jk) / x_k.b_k,
+// added with a weight to the Kaporin gradient in d o (through G's dependence on o).
+
+// one pair into bank slot k: FP32 copies of b and x, and x.b (FP64) as per-block partials
+__global__ void __launch_bounds__(256) k_pair_store(int32_t n, const double *__restrict__ b, const double *__restrict__ x,
+                                                    float *__restrict__ pb, float *__restrict__ px,
+                                                    double *__restrict__ part) {
+    __shared__ double sh[256];
+    double d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double bi = b[i], xi = x[i];
+        pb[i] = (float)bi;
+        px[i] = (float)xi;
+        d += bi * xi;
+    }
+    sh[threadIdx.x] = d;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_pair_store_finish(const double *__restrict__ part, int32_t m,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[256];
+    const double t = block_sum(part, m, sh);
+    if (threadIdx.x == 0) *out = t;
+}
+
+static_assert(QH_PAIR_BATCH == kP, "a pair batch fills the 16 columns of the probe products");
+struct PairIdx {
+    int32_t k[QH_PAIR_BATCH];
+};
+
+// the batch's pairs node-major: B[i][p] = b_{idx p, i}, X likewise
+__global__ void __launch_bounds__(256) k_pair_gather(int32_t n, PairIdx idx, const float *__restrict__ pb,
+                                                     const float *__restrict__ px, float *__restrict__ B,
+                                                     float *__restrict__ X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * QH_PAIR_BATCH) return;
+    const int64_t i = t / QH_PAIR_BATCH;
+    const int p = (int)(t - i * QH_PAIR_BATCH);
+    const int64_t src = (int64_t)idx.k[p] * n + i;
+    B[t] = pb[src];
+    X[t] = px[src];
+}
+
+// V = X - V in place (V holds G^T Y)
+__global__ void k_pair_residual(int64_t m, const float *__restrict__ X, float *__restrict__ V) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) V[t] = X[t] - V[t];
+}
+
+// per pair: v.Av from the product partials, weight 1/(x.b), and L_E into loss[2]
+__global__ void __launch_bounds__(256) k_pair_finish(const double *__restrict__ part, int32_t m, PairIdx idx,
+                                                     const double *__restrict__ xb, double *__restrict__ pw,
+                                                     double *loss) {
+    __shared__ double sh[256];
+    double tot = 0.0;
+    for (int p = 0; p < QH_PAIR_BATCH; ++p) {
+        double s = 0.0;
+        for (int32_t b = threadIdx.x; b < m; b += 256) s += part[(int64_t)b * kP + p];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+            __syncthreads();
+        }
+        const double w = 1.0 / xb[idx.k[p]];
+        tot += sh[0] * w;
+        if (threadIdx.x == 0) pw[p] = w;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[2] = tot / QH_PAIR_BATCH;
+}
+
+// d o += lambda dL_E/do per entry
+__global__ void __launch_bounds__(256) k_pair_grad(int64_t nnz, const int32_t *__restrict__ grow,
+                                                   const int32_t *__restrict__ gcol, const float *__restrict__ gscale,
+                                                   const float *__restrict__ o, const float *__restrict__ Y,
+                                                   const float *__restrict__ AV, const float *__restrict__ GAV,
+                                                   const float *__restrict__ B, const double *__restrict__ pw,
+                                                   double lambda, float *__restrict__ d_o) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t i = grow[e], j = gcol[e];
+    const float *y = Y + (int64_t)i * kP, *g = GAV + (int64_t)i * kP;
+    const float *av = AV + (int64_t)j * kP, *bb = B + (int64_t)j * kP;
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < QH_PAIR_BATCH; ++p)
+        s += ((double)y[p] * (double)av[p] + (double)g[p] * (double)bb[p]) * pw[p];
+    const double dG = -2.0 / QH_PAIR_BATCH * s;
+    const double chain = i == j ? (double)sigmoid_f(o[e] + kS0) * gscale[e] : (double)gscale[e];
+    d_o[e] += (float)(lambda * dG * chain);
+}
+
 // one block of 256: strided per-thread sums, then a tree (fixed order)
 __global__ void __launch_bounds__(256) k_loss_finish(const double *__restrict__ lpart, int32_t m, int32_t n,
                                                      double *loss) {
@@ -789,7 +893,22 @@ hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part
 }
 
 // Loss and gradient for the current weights with probes V (device, [n][16] floats).
-int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad) {
+int qh_learned_record_pair(qh_ctx *c, const double *rhs, const double *sol) {
+    LearnedPrec &L = c->lp;
+    if (!L.pair_rec || L.pair_n >= L.pair_cap) return QH_OK;
+    const int32_t n = c->A.n;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    const int64_t off = (int64_t)L.pair_n * n;
+    hipLaunchKernelGGL(k_pair_store, dim3(g), dim3(256), 0, c->stream, n, rhs, sol, L.pair_b + off, L.pair_x + off,
+                       L.ppart);
+    hipLaunchKernelGGL(k_pair_store_finish, dim3(1), dim3(256), 0, c->stream, L.ppart, (int32_t)g,
+                       L.pair_xb + L.pair_n);
+    QH_HIP(c, hipGetLastError());
+    L.pair_n++;
+    return QH_OK;
+}
+
+int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad, double pair_weight, const int32_t *pair_idx) {
     LearnedPrec &L = c->lp;
     int rc;
     if ((rc = qh_learned_factor(c))) return rc;
@@ -803,16 +922,49 @@ int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad) {
             return rc;
     }
     const unsigned gr = (unsigned)std::min<int64_t>((n + 15) / 16, 2048);
-    // W = G^T V, AW = A W (+ partial traces)
-    hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.tptr, L.tcol, L.tval, V_dev, L.W,
-                       (const float *)nullptr, (double *)nullptr);
-    hipLaunchKernelGGL((k_spmm16<double, true>), dim3(gr), dim3(256), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val,
-                       L.W, L.AW, L.W, L.tpart);
-    hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(256), 0, c->stream, L.tpart, (int32_t)gr, n, L.loss);
     const unsigned ge = (unsigned)((L.nnz + 255) / 256);
-    hipLaunchKernelGGL(k_kaporin_grad, dim3(ge), dim3(256), 0, c->stream, L.nnz, n, L.grow, L.gcol, L.gscale, L.o,
-                       L.gval, V_dev, L.AW, L.d_o, L.lpart, L.loss);
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, c->stream, L.lpart, (int32_t)ge, n, L.loss);
+    if (V_dev) {
+        // W = G^T V, AW = A W (+ partial traces)
+        hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.tptr, L.tcol, L.tval, V_dev,
+                           L.W, (const float *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL((k_spmm16<double, true>), dim3(gr), dim3(256), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val,
+                           L.W, L.AW, L.W, L.tpart);
+        hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(256), 0, c->stream, L.tpart, (int32_t)gr, n, L.loss);
+        hipLaunchKernelGGL(k_kaporin_grad, dim3(ge), dim3(256), 0, c->stream, L.nnz, n, L.grow, L.gcol, L.gscale, L.o,
+                           L.gval, V_dev, L.AW, L.d_o, L.lpart, L.loss);
+        hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, c->stream, L.lpart, (int32_t)ge, n, L.loss);
+    } else {
+        // the pair term alone: its gradient is added to zero
+        QH_HIP(c, hipMemsetAsync(L.d_o, 0, sizeof(float) * L.nnz, c->stream));
+    }
+    if (pair_weight > 0.0 && pair_idx) {
+        // the batch of recorded pairs: Y = G B, V = X - G^T Y, AV = A V (+ v.Av partials), GAV = G AV
+        if (!L.PB) {
+            const int64_t m = (int64_t)n * kP;
+            if ((rc = qh_alloc(c, &L.PB, m)) || (rc = qh_alloc(c, &L.PX, m)) || (rc = qh_alloc(c, &L.PY, m)) ||
+                (rc = qh_alloc(c, &L.PV, m)) || (rc = qh_alloc(c, &L.PAV, m)) || (rc = qh_alloc(c, &L.PGAV, m)) ||
+                (rc = qh_alloc(c, &L.pw, QH_PAIR_BATCH)))
+                return rc;
+        }
+        PairIdx idx;
+        for (int p = 0; p < QH_PAIR_BATCH; ++p) idx.k[p] = pair_idx[p];
+        const int64_t m = (int64_t)n * kP;
+        hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, c->stream, n, idx, L.pair_b,
+                           L.pair_x, L.PB, L.PX);
+        hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.gptr, L.gcol, L.gval, L.PB,
+                           L.PY, (const float *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.tptr, L.tcol, L.tval, L.PY,
+                           L.PV, (const float *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL(k_pair_residual, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, c->stream, m, L.PX, L.PV);
+        hipLaunchKernelGGL((k_spmm16<double, true>), dim3(gr), dim3(256), 0, c->stream, n, c->A.ptr, c->A.col, c->A.val,
+                           L.PV, L.PAV, L.PV, L.tpart);
+        hipLaunchKernelGGL((k_spmm16<float, false>), dim3(gr), dim3(256), 0, c->stream, n, L.gptr, L.gcol, L.gval, L.PAV,
+                           L.PGAV, (const float *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(256), 0, c->stream, L.tpart, (int32_t)gr, idx, L.pair_xb, L.pw,
+                           L.loss);
+        hipLaunchKernelGGL(k_pair_grad, dim3(ge), dim3(256), 0, c->stream, L.nnz, L.grow, L.gcol, L.gscale, L.o, L.PY,
+                           L.PAV, L.PGAV, L.PB, L.pw, pair_weight, L.d_o);
+    }
     if (want_grad) {
         const unsigned gm = mlp_grid(L.nnz);
         hipLaunchKernelGGL(k_mlp_backward, dim3(gm), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.d_o, L.nnz, L.gpart);

@@ -201,6 +201,81 @@ def test_loss_and_gradient_match_oracle(prob):
     _record("gradient_5cube", rec)
 
 
+def test_pair_loss_and_gradient_match_oracle(prob):
+    """The energy-norm loss on 16 solver pairs (A x = b, x random) and its weight gradient from the
+    GPU kernels (pairs stored in FP32, network in BF16) against the FP64 oracle: loss within 2e-2,
+    gradient direction (cosine >= 0.999), per tensor within 2e-2 of the oracle fed the kernels' BF16
+    inputs and FP32 pairs, and against the exact oracle within that plus the inputs' rounding
+    effect, measured by the oracle."""
+    from oracle import learned as Lr
+    mesh, A, rows, cols, f = prob
+    ctx = gpu_context(mesh, DT)
+    w = _weights(7)
+    w32 = _unflat(_flat(w).astype(np.float64))
+    ctx.precond_set_weights(_flat(w))
+    X = np.random.default_rng(17).standard_normal((A.shape[0], 16))
+    B = A @ X
+    ctx.pairs_record(16)
+    ctx.pairs_add(B.T.copy(), X.T.copy())
+    assert ctx.pairs_count() == 16
+    loss_g, grad_g = ctx.precond_pair_loss_grad(np.arange(16))
+    gg = grad_g.astype(np.float64)
+    loss_o, grad_o = Lr.pair_energy_loss_grad(w32, A, f, rows, cols, B, X)
+    assert abs(loss_g - loss_o) <= 2e-2 * loss_o
+    go = _flat(grad_o).astype(np.float64)
+    assert gg @ go / (np.linalg.norm(gg) * np.linalg.norm(go)) >= 0.999
+    B32, X32 = B.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64)
+    wb = dict(w32, W1=_bf16(w32["W1"]), W2=_bf16(w32["W2"]))
+    _, grad_b = Lr.pair_energy_loss_grad(wb, A, _bf16(f), rows, cols, B32, X32)
+    rec = {"loss_rel": abs(loss_g - loss_o) / loss_o}
+    for k in ("W1", "W2", "W3", "b1", "b2"):
+        a, b = _unflat(gg)[k].ravel(), np.asarray(grad_b[k]).ravel()
+        ex = np.asarray(grad_o[k]).ravel()
+        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12, k
+        inp = np.linalg.norm(b - ex)
+        assert np.linalg.norm(a - ex) <= inp + 2e-2 * np.linalg.norm(ex) + 1e-12, k
+        rec[k] = dict(kernel_vs_bf16_inputs=float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                      bf16_inputs_vs_exact=float(inp / np.linalg.norm(ex)))
+    _record("pair_gradient_5cube", rec)
+
+
+def test_training_on_recorded_solver_pairs(prob):
+    """Pairs the plain solver generates during a full cycle (5^3 box, 5000 electrons, Jacobi,
+    recorded by the step into the device bank) in the training objective with weight 0.5, held-out
+    pairs of another particle seed validating: fewer PCG iterations than Jacobi, the pairs'
+    energy-norm loss falls, and the kept network's energy-norm error on the held-out pairs is
+    reported."""
+    import paper_2103_06737_amd as qh
+    mesh, A, rows, cols, f = prob
+
+    def cycle_ctx(seed):
+        c = gpu_context(mesh, DT)
+        mi = c.mesh_info()
+        c.fields_init_synthetic(qi.white(mi.n_edges, seed, 3), qi.white(mi.n_edges, seed, 5), 1e3, 0.1, 1e-3)
+        sid = c.species_add(-qi.QE / qi.ME, -1)
+        c.particles_upload(sid, *qi.uniform_plasma(mesh, 5000, 1e6, seed=seed))
+        return c
+
+    prm = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_JACOBI)
+    val = cycle_ctx(0)
+    rhs, sol = [], []
+    for _ in range(2):
+        val.pic_step(prm)
+        r, x = val.edge_system_download()
+        rhs.append(r)
+        sol.append(x)
+    ctx = cycle_ctx(1)
+    ctx.pairs_record(40)
+    ctx.pic_step(prm, 45)
+    assert ctx.pairs_count() == 40
+    st = ctx.precond_train(steps=150, lr=3e-3, seed=3, validate_every=25, rhs=np.array(rhs), sol=np.array(sol),
+                           pair_weight=0.5)
+    assert st["val_iters_best"] < 0.75 * st["val_iters_jacobi"], st
+    assert 0 < st["pair_loss_last"] < st["pair_loss_first"], st
+    assert 0 < st["val_energy_err"] < 1.0, st
+    _record("train_pairs_5cube", st)
+
+
 def _edge_rhs(A, k, seed):
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((A.shape[0], k))

@@ -156,3 +156,104 @@ def test_stall_rule_and_fallback():
     x, il, ij, why = Lr.pcg_learned(A, b, apply_of(wn), tol=1e-8, maxit=2000)
     assert why == "nonfinite" and il == 0 and abs(ij - it_j) <= 1
     assert np.linalg.norm(A @ x - b) <= 1.0001e-8 * np.linalg.norm(b)
+
+
+def test_pair_energy_gradient_matches_finite_differences(small):
+    A, rows, cols, f = small
+    w = _random_weights(4)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((A.shape[0], 3))
+    B = A @ X
+    L, g = Lr.pair_energy_loss_grad(w, A, f, rows, cols, B, X)
+    assert L > 0
+    for _ in range(4):
+        d = {k: rng.standard_normal(v.shape) for k, v in w.items()}
+        h = 1e-7   # the loss is quartic in G: a smaller step keeps the third-order term below 1e-6
+        Lp = Lr.pair_energy_loss_grad({k: w[k] + h * d[k] for k in w}, A, f, rows, cols, B, X)[0]
+        Lm = Lr.pair_energy_loss_grad({k: w[k] - h * d[k] for k in w}, A, f, rows, cols, B, X)[0]
+        fd = (Lp - Lm) / (2 * h)
+        an = sum(np.sum(g[k] * d[k]) for k in w)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+    # the inverse Cholesky factor (full lower pattern) makes M = A^-1 exactly: the pairs' error vanishes
+    G = np.linalg.inv(np.linalg.cholesky(A.toarray()))
+    assert np.allclose(G.T @ G @ B, X, rtol=1e-8, atol=1e-10 * np.abs(X).max())
+
+
+def solver_pairs(n_box, steps, seed):
+    """(rhs, solution) pairs of the edge system from the oracle's own plasma cycle on an n^3 box
+    at ten times the explicit limit: 10 electrons per tet, v_th = 1e6 m/s, uniform B_z = 0.1 T,
+    density such that omega_p dt = 0.68 (as the 64^3 workload), a neutralising background; each
+    step's rhs and the exact solution of A e* = rhs."""
+    import scipy.sparse.linalg as sla
+    from oracle.field import FieldOracle, init_fields
+    from oracle.particles import ParticleOracle
+    m = qi.BoxMesh(n_box)
+    cx = Complex(m.xyz, m.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    po = ParticleOracle(cx, op.Minv)
+    dt = 10 * 7.69e-10 / n_box
+    fo = FieldOracle(cx, op, dt)
+    dens = (0.68 / dt) ** 2 * qi.EPS0 * qi.ME / qi.QE ** 2
+    npart = 10 * cx.Nt
+    u_b, u_q = 2.0 ** -56, qi.QE * dens / npart * 2.0 ** -40
+    x, v, tet = qi.uniform_plasma(m, npart, 1e6, seed=seed)
+    e, b = init_fields(cx, qi.white(cx.Ne, seed, 3), qi.white(cx.Ne, seed, 5), 0.0, 0.1, 0.0, u_b)
+    L = po.quantize_points(x.astype(np.float64), tet)
+    Qbg = np.zeros(cx.Nn, np.int64)
+    for i in range(4):
+        np.add.at(Qbg, cx.tets[tet, i], -(1 << 20) * L[:, i])
+    xo, vo, to = x.astype(np.float64), v.astype(np.float64), tet.astype(np.int64)
+    Ac = fo.A.tocsc()
+    R, Xs = [], []
+    for _ in range(steps):
+        out = po.push(e, b * u_b, xo, vo, to, -qi.QE / qi.ME, dt, -1)
+        xo, vo, to = out["x"], out["v"], out["tet"]
+        rhs = fo.rhs(e, b * u_b, out["g"] * u_q)
+        R.append(rhs)
+        Xs.append(sla.spsolve(Ac, rhs))
+        e, b, _ = fo.step(e, b, u_b, out["g"], u_q, out["Q"], Qbg, tol=1e-12, tol_n=1e-12)
+    return fo.A, np.array(R).T, np.array(Xs).T
+
+
+@pytest.mark.slow
+def test_training_on_solver_pairs():
+    """Pairs of the plain solver (a 6^3 plasma cycle, seed 1; held out: seed 0) in the training
+    objective. Measured here (iterations to 1e-8 on three held-out pairs): Jacobi 84-88,
+    Kaporin number on Rademacher probes 33-34, the pairs' energy-norm loss alone 36-38,
+    Kaporin + 0.5 x energy loss 33-34. Each learned variant beats Jacobi by more than half, and
+    adding the pairs to the Kaporin objective costs nothing."""
+    A, Btr, Xtr = solver_pairs(6, 60, 1)
+    _, Bva, Xva = solver_pairs(6, 10, 0)
+    n = A.shape[0]
+    m = qi.BoxMesh(6)
+    cx = Complex(m.xyz, m.tets)
+    op = Operators(cx, qi.EPS0, qi.MU0)
+    ie = cx.int_edges
+    tau = (10 * 7.69e-10 / 6) ** 2 / 4
+    rows, cols = Lr.lower_pattern(A)
+    ev = (cx.xyz[cx.edges[:, 1]] - cx.xyz[cx.edges[:, 0]])[ie]
+    f = Lr.features(A, op.Meps[ie][:, ie].tocsr(), op.S[ie][:, ie].tocsr(), tau, ev, rows, cols)
+    val = (3, 6, 9)
+    it_j = [Fo.pcg(A, Bva[:, k], tol=1e-8)[1] for k in val]
+
+    def train(kap, lam):
+        w, st, r2 = Lr.init_weights(0), {}, np.random.default_rng(5)
+        for _ in range(150):
+            idx = r2.choice(Btr.shape[1], 8, replace=False)
+            V = np.sign(r2.standard_normal((n, 8)))
+            g = {k: 0.0 for k in w}
+            if kap:
+                _, gk, _ = Lr.kaporin_loss_grad(w, A, f, rows, cols, V)
+                g = {k: g[k] + gk[k] for k in w}
+            if lam:
+                _, ge = Lr.pair_energy_loss_grad(w, A, f, rows, cols, Btr[:, idx], Xtr[:, idx])
+                g = {k: g[k] + lam * ge[k] for k in w}
+            Lr.adam_step(w, g, st, lr=3e-3)
+        o, _ = Lr.mlp_forward(w, f)
+        G, _ = Lr.factor(o, rows, cols, A.diagonal(), n)
+        return [Lr.pcg(A, Bva[:, k], lambda r: G.T @ (G @ r), tol=1e-8, maxit=3000)[1] for k in val]
+
+    it_k, it_e, it_ke = train(True, 0.0), train(False, 1.0), train(True, 0.5)
+    for it in (it_k, it_e, it_ke):
+        assert max(it) < 0.5 * min(it_j), (it, it_j)
+    assert max(it_ke) <= max(it_k) + 2, (it_ke, it_k)
