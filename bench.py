@@ -37,7 +37,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup(wl: str, n_particles: int | None, boundary: int = 0, **override):
+def setup(wl: str, n_particles: int | None, boundary: int = 0, seed: int = 0, **override):
     import paper_2103_06737_amd as qh
     cfg = dict(qi.CONFIGS[wl], **override)
     mesh = qi.make_mesh(cfg)
@@ -55,7 +55,7 @@ def setup(wl: str, n_particles: int | None, boundary: int = 0, **override):
     log(f"[bench] mesh + assembly {time.perf_counter() - t0:.1f}s  tets={mi.n_tets} edges={mi.n_edges} "
         f"nnz_edge={mi.nnz_edge}")
     t0 = time.perf_counter()
-    parts = qi.make_particles(mesh, cfg, n_e=n_e)
+    parts = qi.make_particles(mesh, cfg, seed=seed, n_e=n_e)
     sids = []
     for name, (x, v, tet) in parts.items():
         qm, z = (-qi.QE / qi.ME, -1) if name == "e" else (qi.QE / qi.MI, 1)
@@ -407,6 +407,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
     ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--pairs", type=int, default=2000,
+                    help="(rhs, solution) pairs of the plain solver recorded for training (particle seed 1; "
+                         "0: train on probes only)")
+    ap.add_argument("--pair-weight", type=float, default=0.5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) a few times, to "
                          "scale the HBM byte counters of the profiler; prints its own JSON line")
@@ -477,14 +481,36 @@ def main():
     wall, pst, kernels, used = wall_j, pst_j, kern_j, "jacobi"
     learned = None
     if solve and args.precond == "learned":
-        # (rhs, solution) pairs from the plain solver validate the network during training
+        # held-out (rhs, solution) pairs of the plain solver on this run (particle seed 0) validate
+        # the network during training
         pairs = []
         for _ in range(2):
             ctx.pic_step(params, 1, want_stats=False)
             pairs.append(ctx.edge_system_download())
         rhs = np.stack([p[0] for p in pairs])
         sol = np.stack([p[1] for p in pairs])
-        tst = ctx.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol)
+        gen = None
+        if args.pairs > 0:
+            # training pairs: the plain solver's, recorded over the same workload with particle
+            # seed 1 (its own context), the network trained there and carried over by save/load
+            t0 = time.perf_counter()
+            ctx1, _c1, _m1, _p1, _mi1 = setup(args.workload, args.particles, seed=1)
+            if cfg["mode"] == "solve":
+                ctx1.charge_background(1)
+            ctx1.pairs_record(args.pairs)
+            t1 = time.perf_counter()
+            ctx1.pic_step(params, args.pairs, want_stats=False)
+            gen = {"pairs": ctx1.pairs_count(), "seed": 1, "solver": "jacobi", "tol": 1e-8,
+                   "s_generate": round(time.perf_counter() - t1, 2), "s_setup": round(t1 - t0, 2)}
+            tst = ctx1.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol,
+                                     pair_weight=args.pair_weight)
+            ctx.precond_load(ctx1.precond_save())
+            ctx1.close()
+            del ctx1
+        else:
+            tst = ctx.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol)
+        tst["pair_weight"] = args.pair_weight if args.pairs > 0 else 0.0
+        tst["pair_generation"] = gen
         log(f"[bench] training: {tst}")
         params_l = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED,
                                           sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
