@@ -282,7 +282,10 @@ __device__ __forceinline__ void walk_one(const StepArgs &a, float &px, float &py
         for (int r = 0; r < 4; ++r) {
             if (r == entry) continue;
             float le = l[r] + gl[r];
-            if (!(le < 0.0f)) continue;
+            // a face is crossed only when the path moves out through it: a point rounded to just
+            // outside a face (at a crossing or a wall corner) that moves back in does not leave
+            // (it would bounce between two walls, reflected outward, until the piece cap)
+            if (!(le < 0.0f) || !(gl[r] < 0.0f)) continue;
             float s = l[r] <= 0.0f ? 0.0f : l[r] / (l[r] - le);
             if (s < smin) { smin = s; k = r; }
         }
