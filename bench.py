@@ -80,9 +80,9 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
     """Bytes one launch must move at least (each datum read or written once)."""
     if kernel in ("cg_spmv",):
         # A: FP64 value + column (2 bytes in tiles read with 16-bit offsets, else 4); rowptr;
-        # z, p_old in; p_new, q out
+        # z, p_old, q_old in; p_new, q out
         n, nnz, c16 = mi.n_int_edges, mi.nnz_edge, mi.nnz_edge_c16
-        return 8 * nnz + 2 * c16 + 4 * (nnz - c16) + 4 * (n + 1) + 32 * n
+        return 8 * nnz + 2 * c16 + 4 * (nnz - c16) + 4 * (n + 1) + 40 * n
     if kernel in ("node_spmv",):
         n, nnz = mi.n_int_nodes, mi.nnz_node
         return 12 * nnz + 4 * (n + 1) + 32 * n
@@ -542,6 +542,15 @@ def main():
     ms_part = float(np.mean([s["ms_particles"] for s in pst]))
     by_phase = phase_bytes(mi, n_p, crossings, n_occ)
     ach_phase = by_phase / (ms_part * 1e-3) / 1e9
+    def per_iteration(kern, pst_):
+        # edge CG cost per iteration: the kernels every iteration launches once (product, update,
+        # and with the learned preconditioner its two passes), over the profiled iterations
+        its = sum(s["edge_iters"] for s in pst_)
+        if not its:
+            return None
+        parts_ = {k: round(1e3 * kern[k]["ms_total"] / its, 2) for k in ("cg_spmv", "cg_update", "precond")
+                  if k in kern}
+        return {"us_per_iteration": round(sum(parts_.values()), 2), "iterations": its, "us_by_kernel": parts_}
     fs_j = float(np.mean([s["ms_fields"] for s in pst_j]))
     fs_l = float(np.mean([s["ms_fields"] for s in learned["pst"]])) if learned else None
     out = {
@@ -564,6 +573,8 @@ def main():
                                         "crossings_per_step": crossings}},
         "particle_kernels": roof("particle_step", kernels),
         "field_solve_ms_per_step": {"jacobi": round(fs_j, 4), "learned": round(fs_l, 4) if fs_l else None},
+        "edge_cg_iteration": {"jacobi": per_iteration(kern_j, pst_j),
+                              "learned": per_iteration(learned["kernels"], learned["pst"]) if learned else None},
         "jacobi_cycle": {"ms_per_step": round(1e3 * wall_j / args.steps, 4),
                          "particle_steps_per_s": round(n_p * args.steps / wall_j, 1),
                          "edge_iters": [s["edge_iters"] for s in pst_j], "kernels": kern_j},

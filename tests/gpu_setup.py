@@ -19,6 +19,20 @@ def record(name, data):
             json.dump(data, fh, indent=1, default=float)
 
 
+# FP32 unit roundoff and the bars derived from it for one FP32 gather and push against FP64
+# (measured on the jittered 4^3 mesh and 4096 sampled 64^3 particles: at most 3 u for E and B,
+# 2.3 u of the unit cube's extent for positions, 4 u for velocities):
+#  - E = alpha + beta x (r - c) and B from FP32 records: the record's own rounding (a few u),
+#    r - c formed in FP32 (u |r| against |r - c| ~ h/4: up to 8 u of the affine term); 32 u
+#  - x + dt v and the reflection in FP32 inside the unit cube: half an ulp of 1 per operation plus
+#    dt times the velocity's error; 16 u (metres, coordinates <= 1)
+#  - Boris rotation and the two half kicks, about 20 FP32 operations; 32 u of max |v|
+U32 = 2.0 ** -24
+GATHER_REL = 32 * U32
+PUSH_X_ABS = 16 * U32
+PUSH_V_REL = 32 * U32
+
+
 def err_stats(a):
     """max and 99th percentile of an array of errors."""
     a = np.asarray(a, np.float64).ravel()

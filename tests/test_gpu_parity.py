@@ -10,7 +10,8 @@ import pytest
 
 import qh_inputs as qi
 
-from .gpu_setup import (S, chained_segments, err_stats, gpu_context, node_charge, oracle_fields,
+from .gpu_setup import (GATHER_REL, PUSH_V_REL, PUSH_X_ABS, S, chained_segments, err_stats, gpu_context,
+                        node_charge, oracle_fields,
                         oracle_setup, record)
 
 pytestmark = pytest.mark.gpu
@@ -113,9 +114,9 @@ def test_one_step_fp32_vs_fp64(jitter4):
     same = r["tg"] == orc["tet"]
     assert same.mean() > 0.99
     dx = np.abs(r["xg"] - orc["x"]).max(axis=1)
-    assert dx[same].max() < 1e-5
+    assert dx[same].max() <= PUSH_X_ABS
     dv = np.abs(r["vg"] - orc["v"]).max(axis=1) / np.abs(orc["v"]).max()
-    assert dv[same].max() < 1e-5
+    assert dv[same].max() <= PUSH_V_REL
     # a different final tet only inside the tie band
     for i in np.flatnonzero(~same):
         lam = op.Minv[r["tg"][i], :, 0] + op.Minv[r["tg"][i], :, 1:] @ orc["x"][i]
@@ -135,8 +136,8 @@ def test_one_step_fp32_vs_fp64(jitter4):
     # the FP32 gather (per-tet records read through the probe) against FP64 at the start points
     Ep, Bp = r["ctx"].probe_fields(r["x0"].astype(np.float64), r["t0"])
     Eo, Bo = po.gather(e, b * U_B, r["x0"].astype(np.float64), r["t0"])
-    assert np.abs(Ep - Eo).max() <= 1e-5 * np.abs(Eo).max()
-    assert np.abs(Bp - Bo).max() <= 1e-5 * np.abs(Bo).max()
+    assert np.abs(Ep - Eo).max() <= GATHER_REL * np.abs(Eo).max()
+    assert np.abs(Bp - Bo).max() <= GATHER_REL * np.abs(Bo).max()
     record("jitter4_one_step", dict(
         E_rel=err_stats(np.abs(Ep - Eo).max(axis=1) / np.abs(Eo).max()),
         B_rel=err_stats(np.abs(Bp - Bo).max(axis=1) / np.abs(Bo).max()),
