@@ -76,21 +76,26 @@ def phase_bytes(mi, n_particles: int, crossings: float, n_occ: int) -> int:
     return 56 * n_particles + 160 * n_occ + 160 * crossings + 16 * (mi.n_edges + mi.n_nodes)
 
 
-def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False):
-    """Bytes one launch must move at least (each datum read or written once)."""
+def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False,
+                      mixed: bool = False):
+    """Bytes one launch must move at least (each datum read or written once). mixed: the inner
+    iterations of the mixed-precision edge solve (FP32 matrix values and vectors)."""
+    v = 4 if mixed else 8   # bytes per vector entry (and per value of A) in the edge iterations
     if kernel in ("cg_spmv",):
-        # A: FP64 value + column (2 bytes in tiles read with 16-bit offsets, else 4); rowptr;
+        # A: value + column (2 bytes in tiles read with 16-bit offsets, else 4); rowptr;
         # z, p_old, q_old in; p_new, q out
         n, nnz, c16 = mi.n_int_edges, mi.nnz_edge, mi.nnz_edge_c16
-        return 8 * nnz + 2 * c16 + 4 * (nnz - c16) + 4 * (n + 1) + 40 * n
+        return v * nnz + 2 * c16 + 4 * (nnz - c16) + 4 * (n + 1) + 5 * v * n
     if kernel in ("node_spmv",):
         n, nnz = mi.n_int_nodes, mi.nnz_node
         return 12 * nnz + 4 * (n + 1) + 32 * n
-    if kernel in ("cg_update", "node_update"):
-        n = mi.n_int_edges if kernel == "cg_update" else mi.n_int_nodes
-        if learned and kernel == "cg_update":
-            return 48 * n                                # x, r rw; p, q in (z comes from the factor)
-        return 64 * n                                    # x, r rw; p, q, dinv in; z out
+    if kernel == "node_update":
+        return 64 * mi.n_int_nodes
+    if kernel == "cg_update":
+        n = mi.n_int_edges
+        if learned:
+            return 6 * v * n                             # x, r rw; p, q in (z comes from the factor)
+        return 8 * v * n                                 # x, r rw; p, q, dinv in; z out
     if kernel == "particle_step":
         # particle state in+out (28 B each way), per tet: geometry 48 + field 48 + vertex ids 16
         # + edge ids 24, per crossing: neighbour ids 16 + the next tet's records 136,
@@ -101,29 +106,43 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
         # column of 2 or 4 bytes as in cg_spmv); per row: r in, y out, y in, z out, r in (dot),
         # row pointers
         n, nnz_l, c16 = mi.n_int_edges, mi.nnz_factor, mi.nnz_factor_c16
-        return 4 * nnz_l + 2 * c16 + 4 * (2 * nnz_l - c16) + 40 * n + 8 * (n + 1)
+        return 4 * nnz_l + 2 * c16 + 4 * (2 * nnz_l - c16) + 5 * v * n + 8 * (n + 1)
     if kernel == "field_prep":
         return (48 + 24 + 16 + 48) * mi.n_tets + 8 * mi.n_edges + 8 * mi.n_faces
     return None
 
 
 # HIP kernels behind each timed entry (one entry may launch several kernels)
-HIP_KERNELS = {"cg_spmv": ["k_cg_spmv"], "cg_update": ["k_cg_update<true>"],
-               "precond": ["k_prec_g<false>", "k_prec_g<true>"],
-               "particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
+HIP_KERNELS = {"particle_step": ["k_particle_step<false>", "k_mail_apply", "k_gather<0, 2>", "k_gather<6, 8>"],
                "edge_rhs": ["k_edge_rhs_e", "k_edge_rhs_b"], "field_prep": ["k_field_prep"]}
+
+
+def hip_kernels(entry: str, mixed: bool = False, learned: bool = False):
+    """HIP kernels behind a timed entry; the edge iterations' kernels are instantiated on FP64
+    vectors, or FP32 in the mixed-precision solve, and the update computes z = D^-1 r only with
+    Jacobi."""
+    t = "float" if mixed else "double"
+    if entry == "cg_spmv":
+        return [f"k_cg_spmv<{t}, {t}>"]
+    if entry == "cg_update":
+        return [f"k_cg_update<{'false' if learned else 'true'}, {t}>"]
+    if entry == "precond":
+        return [f"k_prec_g<false, {t}>", f"k_prec_g<true, {t}>"]
+    return HIP_KERNELS.get(entry, [])
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plasma_64cube_16M.md")
 # headers every kernel file includes: part of the source a traffic figure was taken from
 SHARED_SOURCES = ["paper_2103_06737_amd/csrc/qh_spmv.h", "paper_2103_06737_amd/csrc/qh_internal.h"]
 
 
-def measured_traffic(entry: str, workload: str):
+def measured_traffic(entry: str, workload: str, kernels):
     """HBM bytes per launch from the profiler's byte counters (scaled by the copy calibration),
     as recorded in the traffic summary; None when the summary is absent, covers another
     workload, or any kernel's source (its file and the shared headers) has changed since the
     counters were taken."""
     import hashlib
-    if workload != "plasma64" or entry not in HIP_KERNELS or not os.path.exists(TRAFFIC_FILE):
+    if workload != "plasma64" or not kernels or not os.path.exists(TRAFFIC_FILE):
         return None
     rows = {}
     for line in open(TRAFFIC_FILE):
@@ -132,7 +151,7 @@ def measured_traffic(entry: str, workload: str):
             src = cells[5].split()
             rows[cells[0].strip("`")] = (float(cells[4]) * 1e6, src)
     total = 0.0
-    for k in HIP_KERNELS[entry]:
+    for k in kernels:
         if k not in rows or len(rows[k][1]) != 2:
             return None
         path, digest = rows[k][1]
@@ -406,6 +425,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
+    ap.add_argument("--solver", default="mixed", choices=["mixed", "fp64"],
+                    help="edge solve of the headline run: FP64 PCG, or FP64 residual refinement around FP32 "
+                         "inner PCG; both stop on the FP64 residual 1e-8 and both are timed")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--pairs", type=int, default=2000,
                     help="(rhs, solution) pairs of the plain solver recorded for training (particle seed 1; "
@@ -453,9 +475,15 @@ def main():
     if args.profile_steps is None:
         args.profile_steps = cfg.get("sort_every", 0) or 3
     solve = cfg["mode"] == "solve"
-    params = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE if solve else qh.FIELDS_FROZEN,
-                                    sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
-                                    max_it_edge=2000, max_it_node=5000, check_every=16)
+    sort_every = cfg.get("sort_every", 0)
+
+    def prm_of(pc, solver):
+        return qh.Context.step_params(field_mode=qh.FIELDS_SOLVE if solve else qh.FIELDS_FROZEN,
+                                      precond=qh.PC_LEARNED if pc == "learned" else qh.PC_JACOBI,
+                                      sort_every=sort_every, tol_edge=1e-8, tol_node=1e-8, max_it_edge=2000,
+                                      max_it_node=5000, check_every=16,
+                                      solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
+
     def timed(prm, steps):
         t0 = time.perf_counter()
         ctx.pic_step(prm, steps, want_stats=False)   # returns after its stream is synchronised
@@ -472,20 +500,30 @@ def main():
                 kern[k] = {"ms_total": round(ms, 4), "launches": cnt, "us_per_launch": round(1e3 * ms / cnt, 3)}
         return pst, kern
 
-    # plain solver (Jacobi-preconditioned CG)
-    st = ctx.pic_step(params, args.warmup, want_stats=True)
+    def run(pc, solver):
+        # a few untimed steps (the first solve of a configuration sizes its first check batch),
+        # the timed steps, then a whole sort cycle with the two phase events per step only, and
+        # one with a HIP event pair around every launch (per-kernel times; about 4 % slower)
+        prm = prm_of(pc, solver)
+        ctx.pic_step(prm, 2, want_stats=False)
+        wall = timed(prm, args.steps)
+        pst = ctx.pic_step(prm, args.profile_steps, want_stats=True)
+        pst_k, kern = profile(prm, args.profile_steps)
+        log(f"[bench] {pc} {solver}: {1e3 * wall / args.steps:.3f} ms/step, edge iters "
+            f"{[s['edge_iters'] for s in pst]}, refinements {[s['edge_refinements'] for s in pst][:4]}")
+        return {"wall": wall, "pst": pst, "pst_k": pst_k, "kernels": kern, "precond": pc, "solver": solver}
+
+    st = ctx.pic_step(prm_of("jacobi", "fp64"), args.warmup, want_stats=True)
     log(f"[bench] warmup done: last step {st[-1]}")
-    wall_j = timed(params, args.steps)
-    pst_j, kern_j = profile(params, args.profile_steps)
-    log(f"[bench] jacobi: {1e3 * wall_j / args.steps:.3f} ms/step, edge iters {[s['edge_iters'] for s in pst_j]}")
-    wall, pst, kernels, used = wall_j, pst_j, kern_j, "jacobi"
-    learned = None
+    solvers = ["fp64", "mixed"] if solve else ["fp64"]
+    runs = {f"jacobi_{sv}": run("jacobi", sv) for sv in solvers}
+    train = None
     if solve and args.precond == "learned":
         # held-out (rhs, solution) pairs of the plain solver on this run (particle seed 0) validate
         # the network during training
         pairs = []
         for _ in range(2):
-            ctx.pic_step(params, 1, want_stats=False)
+            ctx.pic_step(prm_of("jacobi", "fp64"), 1, want_stats=False)
             pairs.append(ctx.edge_system_download())
         rhs = np.stack([p[0] for p in pairs])
         sol = np.stack([p[1] for p in pairs])
@@ -499,49 +537,53 @@ def main():
                 ctx1.charge_background(1)
             ctx1.pairs_record(args.pairs)
             t1 = time.perf_counter()
-            ctx1.pic_step(params, args.pairs, want_stats=False)
+            ctx1.pic_step(prm_of("jacobi", "fp64"), args.pairs, want_stats=False)
             gen = {"pairs": ctx1.pairs_count(), "seed": 1, "solver": "jacobi", "tol": 1e-8,
                    "s_generate": round(time.perf_counter() - t1, 2), "s_setup": round(t1 - t0, 2)}
-            tst = ctx1.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol,
-                                     pair_weight=args.pair_weight)
+            train = ctx1.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol,
+                                       pair_weight=args.pair_weight)
             ctx.precond_load(ctx1.precond_save())
             ctx1.close()
             del ctx1
         else:
-            tst = ctx.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol)
-        tst["pair_weight"] = args.pair_weight if args.pairs > 0 else 0.0
-        tst["pair_generation"] = gen
-        log(f"[bench] training: {tst}")
-        params_l = qh.Context.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED,
-                                          sort_every=cfg.get("sort_every", 0), tol_edge=1e-8, tol_node=1e-8,
-                                          max_it_edge=2000, max_it_node=5000, check_every=16)
-        ctx.pic_step(params_l, 2, want_stats=False)
-        wall_l = timed(params_l, args.steps)
-        pst_l, kern_l = profile(params_l, args.profile_steps)
-        log(f"[bench] learned: {1e3 * wall_l / args.steps:.3f} ms/step, edge iters {[s['edge_iters'] for s in pst_l]}")
-        learned = {"train": tst, "pst": pst_l, "kernels": kern_l, "wall": wall_l}
-        wall, pst, kernels, used = wall_l, pst_l, kern_l, "learned"
+            train = ctx.precond_train(steps=args.train_steps, lr=3e-3, seed=1, validate_every=25, rhs=rhs, sol=sol)
+        train["pair_weight"] = args.pair_weight if args.pairs > 0 else 0.0
+        train["pair_generation"] = gen
+        log(f"[bench] training: {train}")
+        for sv in solvers:
+            runs[f"learned_{sv}"] = run("learned", sv)
+    headline = f"{args.precond if train else 'jacobi'}_{args.solver if solve else 'fp64'}"
+    H = runs[headline]
+    wall, pst, pst_k, kernels = H["wall"], H["pst"], H["pst_k"], H["kernels"]
+    learned_used = H["precond"] == "learned"
+    mixed_used = H["solver"] == "mixed"
     ms_step = 1e3 * wall / args.steps
     value = n_p * args.steps / wall
     crossings = float(np.mean([s["crossings"] for s in pst]))
     mi = ctx.mesh_info()  # now with the learned factor's sizes
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
 
-    def roof(k, kern):
-        by = algorithmic_bytes(k, mi, n_p, crossings, learned=used == "learned")
+    def roof(k, kern, r):
+        by = algorithmic_bytes(k, mi, n_p, crossings, learned=r["precond"] == "learned", mixed=r["solver"] == "mixed")
         if by is None or k not in kern:
             return None
-        avg_s = kern[k]["ms_total"] / kern[k]["launches"] * 1e-3
+        # the edge iterations' kernels: the time of all their launches over the iterations that
+        # did work (launches past convergence return at once and are counted as part of it)
+        its = sum(s["edge_iters"] for s in r["pst_k"])
+        n_work = its if k in ("cg_spmv", "cg_update", "precond") and its else kern[k]["launches"]
+        avg_s = kern[k]["ms_total"] / n_work * 1e-3
         ach = by / avg_s / 1e9
+        hk = hip_kernels(k, r["solver"] == "mixed", r["precond"] == "learned")
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k, args.workload), "kernel": k,
-                "hip_kernels": HIP_KERNELS.get(k, []),
-                "algorithmic_bytes_per_launch": int(by), "us_per_launch": kern[k]["us_per_launch"]}
-    # the particle phase per step over the profiled steps (a whole re-sort cycle: the sort is in),
-    # field prep, push, walk, deposit, moves between blocks, sort
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k, args.workload, hk), "kernel": k,
+                "hip_kernels": hk, "algorithmic_bytes_per_launch": int(by),
+                "us_per_launch": round(avg_s * 1e6, 3), "working_launches": n_work}
+    # the particle phase per step over a whole re-sort cycle (the sort is in), field prep, push,
+    # walk, deposit, moves between blocks, sort; phase events only
     ms_part = float(np.mean([s["ms_particles"] for s in pst]))
     by_phase = phase_bytes(mi, n_p, crossings, n_occ)
     ach_phase = by_phase / (ms_part * 1e-3) / 1e9
+
     def per_iteration(kern, pst_):
         # edge CG cost per iteration: the kernels every iteration launches once (product, update,
         # and with the learned preconditioner its two passes), over the profiled iterations
@@ -551,33 +593,39 @@ def main():
         parts_ = {k: round(1e3 * kern[k]["ms_total"] / its, 2) for k in ("cg_spmv", "cg_update", "precond")
                   if k in kern}
         return {"us_per_iteration": round(sum(parts_.values()), 2), "iterations": its, "us_by_kernel": parts_}
-    fs_j = float(np.mean([s["ms_fields"] for s in pst_j]))
-    fs_l = float(np.mean([s["ms_fields"] for s in learned["pst"]])) if learned else None
+
+    def summary(r):
+        return {"ms_per_step": round(1e3 * r["wall"] / args.steps, 4),
+                "particle_steps_per_s": round(n_p * args.steps / r["wall"], 1),
+                "field_solve_ms_per_step": round(float(np.mean([s["ms_fields"] for s in r["pst"]])), 4),
+                "edge_iters": [s["edge_iters"] for s in r["pst"]],
+                "edge_refinements": [s["edge_refinements"] for s in r["pst"]],
+                "edge_res_max": max(s["edge_res"] for s in r["pst"]),
+                "fallbacks": sum(s["fallbacks"] for s in r["pst"]),
+                "edge_cg_iteration": per_iteration(r["kernels"], r["pst_k"])}
     out = {
         "metric": "particle-steps/s (gather+push+deposit), % HBM roofline; field-solve ms/step learned vs Jacobi",
         "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 push / int64 deposit / f64 solve", "data": "synthetic",
+        "vs_baseline": None,
+        "dtype": "f32 push / int64 deposit / f64 edge residual" + (" with f32 inner PCG" if mixed_used else " and PCG"),
+        "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "particles": n_p,
                    "tets": mi.n_tets, "edges": mi.n_edges, "nnz_edge": mi.nnz_edge, "dt": cfg["dt"],
-                   "sort_every": cfg.get("sort_every", 0), "tol": 1e-8, "precond": used},
-        "roofline": roof(dom, kernels),
+                   "sort_every": sort_every, "tol": 1e-8, "precond": H["precond"], "solver": H["solver"]},
+        "roofline": roof(dom, kernels, H),
         "particle_phase": {"ms_per_step": round(ms_part, 4),
                            "particle_steps_per_s": round(n_p / (ms_part * 1e-3), 1),
-                           "steps_timed": len(pst), "sort_every": cfg.get("sort_every", 0),
+                           "steps_timed": len(pst), "sort_every": sort_every,
                            "covers": "field prep, gather/push/walk/deposit, moves between blocks, the sort "
                                      "once per cycle (HIP events around the phase, every step of the cycle)",
                            "roofline": {"bound": "hbm", "achieved": round(ach_phase, 1), "peak": HBM_PEAK_GBS,
                                         "unit": "GB/s", "frac": round(ach_phase / HBM_PEAK_GBS, 4),
                                         "algorithmic_bytes_per_step": int(by_phase), "occupied_tets": n_occ,
                                         "crossings_per_step": crossings}},
-        "particle_kernels": roof("particle_step", kernels),
-        "field_solve_ms_per_step": {"jacobi": round(fs_j, 4), "learned": round(fs_l, 4) if fs_l else None},
-        "edge_cg_iteration": {"jacobi": per_iteration(kern_j, pst_j),
-                              "learned": per_iteration(learned["kernels"], learned["pst"]) if learned else None},
-        "jacobi_cycle": {"ms_per_step": round(1e3 * wall_j / args.steps, 4),
-                         "particle_steps_per_s": round(n_p * args.steps / wall_j, 1),
-                         "edge_iters": [s["edge_iters"] for s in pst_j], "kernels": kern_j},
+        "particle_kernels": roof("particle_step", kernels, H),
+        "field_solve_ms_per_step": {k: summary(r)["field_solve_ms_per_step"] for k, r in runs.items()},
+        "solvers": {k: summary(r) for k, r in runs.items()},
         "solver": {"edge_iters": [s["edge_iters"] for s in pst], "node_iters": [s["node_iters"] for s in pst],
                    "edge_res": max(s["edge_res"] for s in pst), "gauss_res": max(s["gauss_res"] for s in pst),
                    "gauss_res_rho": max(s["gauss_res_rho"] for s in pst),
@@ -586,8 +634,8 @@ def main():
         "crossings_per_step": crossings,
         "foreign_deposits_per_step": float(np.mean([s["foreign"] for s in pst])),
     }
-    if learned:
-        out["learned_training"] = learned["train"]
+    if train:
+        out["learned_training"] = train
     if frozen:
         out["frozen_particle_phase"] = frozen
     if not args.no_cpu_baseline:

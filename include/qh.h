@@ -106,7 +106,14 @@ typedef struct {
                             of a solve comes after as many iterations as the previous solve of
                             the same system and preconditioner took */
     int32_t verify;      /* 1: check continuity and D b on the device every step */
+    int32_t solver;      /* edge solve: QH_SOLVER_FP64 (0), or QH_SOLVER_MIXED (1): FP64 residual
+                            refinement around FP32 inner PCG iterations (same preconditioner; FP32
+                            copy of A's values and FP32 vectors, FP64 products and dot products),
+                            stopping on the same FP64 residual tol_edge */
 } qh_step_params_t;
+
+#define QH_SOLVER_FP64 0
+#define QH_SOLVER_MIXED 1
 
 typedef struct {
     int32_t edge_iters, node_iters; /* Krylov iterations of this step */
@@ -120,6 +127,8 @@ typedef struct {
     int64_t foreign;                /* deposits into tets outside a block's range (mailbox records) */
     double gauss_res_rho;           /* ||rho - G^T[*eps] e|| / ||rho|| (0 when rho = 0): the same residual
                                        against the charge alone, for comparison with gauss_res */
+    int32_t edge_refinements;       /* QH_SOLVER_MIXED: FP64 residual refinements of the edge solve
+                                       (inner FP32 solves taken); 0 otherwise */
 } qh_step_stats_t;
 
 typedef struct {
@@ -329,10 +338,12 @@ int qh_fields_decompose(qh_ctx *ctx, double tol, int32_t max_it, double *e_ns, d
 int qh_fields_energy(qh_ctx *ctx, double *w_e, double *w_m);
 
 /* Solve system (QH_SYS_EDGE or QH_SYS_NODE) A x = rhs on its interior unknowns
- * (n_int_edges or n_int_nodes values), FP64 CG with FP64 dot products, to
- * ||rhs - A x|| <= tol ||rhs||. x holds the initial guess on entry. */
+ * (n_int_edges or n_int_nodes values), to ||rhs - A x|| <= tol ||rhs|| in FP64: FP64 PCG with
+ * FP64 dot products (solver = QH_SOLVER_FP64), or FP64 residual refinement around FP32 inner PCG
+ * (QH_SOLVER_MIXED). x holds the initial guess on entry. A learned or mixed solve that does not
+ * converge is restarted as FP64 Jacobi-PCG (stats->fallback = 1). */
 int qh_field_solve(qh_ctx *ctx, int32_t system, const double *rhs, double *x, double tol,
-                   int32_t max_it, int32_t precond, qh_solve_stats_t *stats);
+                   int32_t max_it, int32_t precond, int32_t solver, qh_solve_stats_t *stats);
 
 /* Learned preconditioner for the edge system (used with precond = QH_PC_LEARNED).
  * M = G^T G with G sparse lower triangular on the pattern of A; a network 16 -> 64 -> 64 -> 1

@@ -21,6 +21,7 @@ FIELDS_FROZEN, FIELDS_SOLVE, FIELDS_WAVE = 0, 1, 2
 BC_PEC, BC_NEUMANN = 0, 1
 WALLS_REFLECT, WALLS_ABSORB = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
+SOLVER_FP64, SOLVER_MIXED = 0, 1
 SYS_EDGE, SYS_NODE = 0, 1
 KERNELS = ["field_prep", "particle_step", "sort", "edge_rhs", "cg_spmv", "cg_update", "cg_init",
            "gauss", "faraday", "true_res", "node_spmv", "node_update", "precond", "boundary"]
@@ -63,7 +64,7 @@ class StepParams(C.Structure):
     _fields_ = [("field_mode", C.c_int32), ("sort_every", C.c_int32), ("precond", C.c_int32),
                 ("gauss", C.c_int32), ("tol_edge", C.c_double), ("tol_node", C.c_double),
                 ("max_it_edge", C.c_int32), ("max_it_node", C.c_int32),
-                ("check_every", C.c_int32), ("verify", C.c_int32)]
+                ("check_every", C.c_int32), ("verify", C.c_int32), ("solver", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -71,7 +72,8 @@ class StepStats(C.Structure):
                 ("node_res", C.c_double), ("gauss_res", C.c_double), ("crossings", C.c_int64),
                 ("wall_hits", C.c_int64), ("lost", C.c_int64), ("continuity_bad", C.c_int64),
                 ("divb_bad", C.c_int64), ("fallbacks", C.c_int32), ("ms_particles", C.c_float),
-                ("ms_fields", C.c_float), ("foreign", C.c_int64), ("gauss_res_rho", C.c_double)]
+                ("ms_fields", C.c_float), ("foreign", C.c_int64), ("gauss_res_rho", C.c_double),
+                ("edge_refinements", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -145,7 +147,7 @@ def lib():
             "qh_segments_download": [p, C.POINTER(i64), p, p, p, p, p, p],
             "qh_deposit": [p, i64, p, p, p, p, i64, p, p, p, p, p],
             "qh_deposit_noalloc": [p, i64, p, p, p, p, i64, p, p, p, p, p],
-            "qh_field_solve": [p, i32, p, p, d, i32, i32, C.POINTER(SolveStats)],
+            "qh_field_solve": [p, i32, p, p, d, i32, i32, i32, C.POINTER(SolveStats)],
             "qh_matrix_info": [p, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
             "qh_matrix_download": [p, i32, p, p, p],
             "qh_timing_enable": [p, i32],
@@ -354,9 +356,9 @@ class Context:
     @staticmethod
     def step_params(field_mode=FIELDS_FROZEN, sort_every=0, precond=PC_JACOBI, gauss=1,
                     tol_edge=1e-8, tol_node=1e-8, max_it_edge=2000, max_it_node=5000,
-                    check_every=8, verify=0):
+                    check_every=8, verify=0, solver=0):
         return StepParams(field_mode, sort_every, precond, gauss, tol_edge, tol_node, max_it_edge,
-                          max_it_node, check_every, verify)
+                          max_it_node, check_every, verify, solver)
 
     def pic_step(self, params, n_steps=1, want_stats=True, allow=()):
         stats = (StepStats * n_steps)() if want_stats else None
@@ -429,12 +431,13 @@ class Context:
         self._check(self.L.qh_fields_energy(self.h, C.byref(we), C.byref(wm)))
         return we.value, wm.value
 
-    def field_solve(self, system, rhs, x0=None, tol=1e-8, max_it=5000, precond=PC_JACOBI, allow=()):
+    def field_solve(self, system, rhs, x0=None, tol=1e-8, max_it=5000, precond=PC_JACOBI, solver=SOLVER_FP64,
+                    allow=()):
         rhs = _c(rhs, np.float64)
         x = np.zeros_like(rhs) if x0 is None else _c(x0, np.float64).copy()
         st = SolveStats()
         rc = self.L.qh_field_solve(self.h, int(system), _ptr(rhs), _ptr(x), float(tol), int(max_it),
-                                   int(precond), C.byref(st))
+                                   int(precond), int(solver), C.byref(st))
         self._check(rc, allow)
         return x, dict(iters=st.iters, res=st.res, fallback=st.fallback, ms=st.ms)
 

@@ -1014,6 +1014,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
         return qh_fail(c, QH_EINVAL, "field_mode");
     const bool solve = P->field_mode != QH_FIELDS_FROZEN;
     if (P->precond != QH_PC_JACOBI && P->precond != QH_PC_LEARNED) return qh_fail(c, QH_EINVAL, "precond");
+    if (P->solver != QH_SOLVER_FP64 && P->solver != QH_SOLVER_MIXED) return qh_fail(c, QH_EINVAL, "solver");
     const bool learned = P->precond == QH_PC_LEARNED && solve;
     if (learned) {
         int rc = qh_learned_setup(c);
@@ -1076,13 +1077,16 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
                 QH_HIP(c, launch_plane_wave(c, wave));
                 qh_tend(c, t0, QK_BOUNDARY);
             }
-            int rc = qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr, false,
-                                 learned);
+            const bool mixed = P->solver == QH_SOLVER_MIXED;
+            int rc = mixed ? qh_cg_solve_mixed(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, learned)
+                           : qh_cg_solve(c, c->A, c->cge, P->tol_edge, P->max_it_edge, P->check_every, se, nullptr,
+                                         false, learned);
             if (rc) return rc;
+            c->last_refinements = se.refinements;
             int fallbacks = 0;
-            if (learned && !se.converged) {
-                // Jacobi restart: from the learned solve's iterate when it is finite (the stall rule or
-                // the iteration cap stopped it), from e^n after non-finite values
+            if ((learned || mixed) && !se.converged) {
+                // FP64 Jacobi restart: from the iterate when it is finite (the stall rule, the
+                // iteration cap or the refinement cap stopped it), from e^n after non-finite values
                 if (se.flag == 3)
                     QH_HIP(c, hipMemcpyAsync(c->cge.x, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice,
                                              c->stream));
@@ -1155,6 +1159,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             S.divb_bad = P->verify ? (int64_t)cnt[4] : -1;
             S.foreign = (int64_t)cnt[5];
             S.fallbacks = solve ? c->last_fallbacks : 0;
+            S.edge_refinements = solve ? c->last_refinements : 0;
             (void)hipEventElapsedTime(&S.ms_particles, ev[0], ev[1]);
             (void)hipEventElapsedTime(&S.ms_fields, ev[1], ev[2]);
         }
@@ -1270,11 +1275,12 @@ int qh_fields_decompose(qh_ctx *c, double tol, int32_t max_it, double *e_ns, dou
 }
 
 int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, double tol, int32_t max_it,
-                   int32_t precond, qh_solve_stats_t *stats) {
+                   int32_t precond, int32_t solver, qh_solve_stats_t *stats) {
     if (!c || !rhs || !x || max_it < 0) return QH_EINVAL;
+    if (solver != QH_SOLVER_FP64 && solver != QH_SOLVER_MIXED) return qh_fail(c, QH_EINVAL, "solver");
     if (c->host_only) return qh_fail(c, QH_ESTATE, "host-only context has no device");
     if (!c->assembled) return qh_fail(c, QH_ESTATE, "mesh and physics first");
-    const DevCsr *M = system == QH_SYS_EDGE ? &c->A : system == QH_SYS_NODE ? &c->K : nullptr;
+    DevCsr *M = system == QH_SYS_EDGE ? &c->A : system == QH_SYS_NODE ? &c->K : nullptr;
     if (!M) return qh_fail(c, QH_EINVAL, "system must be QH_SYS_EDGE or QH_SYS_NODE");
     if (precond != QH_PC_JACOBI && !(precond == QH_PC_LEARNED && system == QH_SYS_EDGE))
         return qh_fail(c, QH_EINVAL, "the learned preconditioner exists for the edge system only");
@@ -1286,6 +1292,8 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     }
     int32_t nmax = std::max(c->A.n, c->K.n);
     if (c->cgx.n < nmax && (rc = qh_cg_alloc(c, c->cgx, nmax))) return rc;
+    const bool mixed = solver == QH_SOLVER_MIXED;
+    if (mixed && (rc = qh_cg_alloc32(c, c->cgx, nmax))) return rc;
     CgWork w = c->cgx;
     w.n = M->n;
     QH_HIP(c, hipMemcpyAsync(w.b, rhs, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
@@ -1296,12 +1304,12 @@ int qh_field_solve(qh_ctx *c, int32_t system, const double *rhs, double *x, doub
     QH_HIP(c, hipEventCreate(&e1));
     QH_HIP(c, hipEventRecord(e0, c->stream));
     SolveResult r;
-    rc = qh_cg_solve(c, *M, w, tol, max_it, 8, r, nullptr, false, learned);
+    rc = mixed ? qh_cg_solve_mixed(c, *M, w, tol, max_it, 8, r, learned)
+               : qh_cg_solve(c, *M, w, tol, max_it, 8, r, nullptr, false, learned);
     if (rc) return rc;
     int fallback = 0;
-    if (learned && !r.converged) {
-        // Jacobi restart from the learned solve's iterate, or from the initial guess after
-        // non-finite values
+    if ((learned || mixed) && !r.converged) {
+        // FP64 Jacobi restart from the iterate, or from the initial guess after non-finite values
         if (r.flag == 3) QH_HIP(c, hipMemcpyAsync(w.x, x, sizeof(double) * w.n, hipMemcpyHostToDevice, c->stream));
         SolveResult rj;
         rc = qh_cg_solve(c, *M, w, tol, max_it, 8, rj, nullptr);

@@ -87,6 +87,8 @@ struct DevCsr {
     int32_t *ptr = nullptr, *col = nullptr;
     double *val = nullptr;
     double *val2 = nullptr;
+    float *val32 = nullptr; // FP32 copy of val for the mixed-precision solve (allocated on first use)
+    double val32_tau = -1.0; // the context's tau when val32 was taken (A's values follow dt)
     int2 *tiles = nullptr;  // row tiles of the tiled product (qh_spmv.h)
     int32_t ntiles = 0;
     uint16_t *col16 = nullptr;  // per-tile 16-bit columns (TileCols)
@@ -118,7 +120,15 @@ struct CgWork {
     double *scal = nullptr;     // device scalars (see qh_solver.hip)
     unsigned int *counter = nullptr;
     int32_t *flags = nullptr;   // [0] done, [1] iterations
-    int32_t last_iters[2] = {0, 0};  // iterations of the last converged solve (Jacobi, learned)
+    // iterations of the last converged solve (Jacobi, learned), and of the inner solves of the
+    // last mixed-precision solve by refinement (Jacobi, learned; the first kMixedHist)
+    static constexpr int kMixedHist = 4;
+    int32_t last_iters[2] = {0, 0};
+    int32_t last_inner[2][kMixedHist] = {};
+    // mixed-precision solve: FP32 inner iterate, residual, preconditioned residual, directions,
+    // inverse diagonal (allocated on first use, n32 entries)
+    float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *dinv32 = nullptr;
+    int32_t n32 = 0;
 };
 
 // Learned preconditioner state (qh_learned.hip)
@@ -140,6 +150,7 @@ struct LearnedPrec {
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;
     uint16_t *gval_h = nullptr, *tval_h = nullptr;  // BF16 copies of G and G^T for the application
     double *y = nullptr;
+    float *y32 = nullptr;  // the application's intermediate G r on FP32 vectors (allocated on first use)
     float *w = nullptr, *best_w = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
     float *gpart = nullptr, *W = nullptr, *AW = nullptr, *V = nullptr;
     double *tpart = nullptr, *lpart = nullptr, *loss = nullptr, *gpart2 = nullptr;
@@ -192,6 +203,7 @@ struct qh_ctx {
     double *A_S = nullptr;  // S values on the pattern of A
     double *A_rhs = nullptr;  // [*eps] - tau S on the pattern of A (right-hand side)
     double tau_assembled = -1.0;
+    int32_t last_refinements = 0;  // the last step's mixed-precision refinements
     bool assembled = false;
 
     // fields and deposits
@@ -338,17 +350,26 @@ struct SolveResult {
     int flag = 0;           // why the iteration stopped: 0 iteration cap, 1 target met, 2 stall rule
                             // (learned preconditioner), 3 non-finite values
     int restarts = 0;       // restarts from the iterate after the recomputed residual missed the target
+    int refinements = 0;    // mixed precision: inner FP32 solves taken
 };
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
 // Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
                 SolveResult &out, const double *abs_thr2_dev, bool node_system = false, bool learned = false);
+// The edge system in mixed precision: FP64 residual refinement around FP32 inner PCG (Jacobi or the
+// learned preconditioner), stopping on the FP64 residual ||b - A x|| <= tol ||b||.
+int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
+                      SolveResult &out, bool learned);
+// FP32 buffers of a CgWork for n unknowns (kept when large enough)
+int qh_cg_alloc32(qh_ctx *c, CgWork &w, int32_t n);
 
 // qh_learned.hip
 int qh_learned_setup(qh_ctx *c);
 int qh_learned_factor(qh_ctx *c);
 unsigned qh_prec_grid(qh_ctx *c);
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done);
+// the same on FP32 vectors (the mixed-precision solve's inner iterations)
+hipError_t launch_prec_apply32(qh_ctx *c, const float *r, float *z, double *part, const int32_t *done);
 int qh_learned_loss_grad(qh_ctx *c, const float *V_dev, bool want_grad, double pair_weight = 0.0,
                          const int32_t *pair_idx = nullptr);
 // records the edge system's (rhs, solution) into the next slot of the pair bank

@@ -226,20 +226,23 @@ __global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const f
 // partials of r.z, from BF16 copies of G and G^T (the network's own precision; the products
 // and sums are FP64, so M = G^T G stays one fixed SPD operator), both as tiled products (each block a contiguous, XCD-grouped range of row
 // tiles). Grids are multiples of 8 blocks, at most 2048.
-template <bool DOT>
+// T: the vectors' type (FP64, or FP32 in the inner iterations of the mixed-precision solve; the
+// products and sums are FP64 either way, and the dot product takes the stored values).
+template <bool DOT, typename T>
 __global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict__ tiles, int32_t ntiles,
                                                          const int32_t *__restrict__ ptr,
                                                          const TileCols cols, const uint16_t *__restrict__ val,
-                                                         const double *__restrict__ in, double *__restrict__ out,
-                                                         const double *__restrict__ r, double *__restrict__ part,
+                                                         const T *__restrict__ in, T *__restrict__ out,
+                                                         const T *__restrict__ r, double *__restrict__ part,
                                                          const int32_t *__restrict__ done) {
     if (done && done[0]) return;  // the solve has converged: nothing left to precondition
     __shared__ double prod[kTileCap];
     double acc = 0.0;
-    tile_spmv(tiles, ntiles, ptr, cols, val, in, prod, [&](int32_t row) { return DOT ? r[row] : 0.0; },
+    tile_spmv(tiles, ntiles, ptr, cols, val, in, prod, [&](int32_t row) { return DOT ? (double)r[row] : 0.0; },
               [&](int32_t row, double s, double rr) {
-        out[row] = s;
-        if (DOT) acc += s * rr;
+        const T st = (T)s;
+        out[row] = st;
+        if (DOT) acc += (double)st * rr;
     });
     if (DOT) {
         __shared__ double sh[kTileThreads / 64];
@@ -885,10 +888,26 @@ unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 // passes return at once when done[0] is set (a converged solve).
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
-    hipLaunchKernelGGL(k_prec_g<false>, dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, double>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
                        L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
-    hipLaunchKernelGGL(k_prec_g<true>, dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, double>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
                        L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase}, L.tval_h, L.y, z, r, part, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_prec_apply32(qh_ctx *c, const float *r, float *z, double *part, const int32_t *done) {
+    LearnedPrec &L = c->lp;
+    if (!L.y32) {
+        float *y = nullptr;
+        if (hipMalloc((void **)&y, sizeof(float) * (size_t)std::max<int32_t>(1, L.n)) != hipSuccess)
+            return hipErrorOutOfMemory;
+        c->allocations.push_back((void *)y);
+        L.y32 = y;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, float>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase}, L.gval_h, r, L.y32, (const float *)nullptr, (double *)nullptr, done);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, float>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase}, L.tval_h, L.y32, z, r, part, done);
     return hipGetLastError();
 }
 

@@ -170,12 +170,15 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(const double *__restrict_
 // r.r from its partials, convergence test, beta. Then, with w = A z (the only gathered
 // vector), p = z + beta p and q = A p = w + beta q in place (own rows only), and the
 // partials of p.q. Gathering one vector instead of z and p halves the scattered loads.
+// VT, XT: the matrix values' and the vectors' types (FP64, or FP32 in the inner iterations of
+// the mixed-precision solve; products, sums and dot products are FP64 either way).
+template <typename VT, typename XT>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) k_cg_spmv(int32_t n, const int2 *__restrict__ tiles, int32_t ntiles,
                                                       const int32_t *__restrict__ ptr,
                                                       const TileCols cols,
-                                                      const double *__restrict__ val,
-                                                      const double *__restrict__ z,
-                                                      double *__restrict__ p, double *__restrict__ q,
+                                                      const VT *__restrict__ val,
+                                                      const XT *__restrict__ z,
+                                                      XT *__restrict__ p, XT *__restrict__ q,
                                                       const double *__restrict__ rz_part, int m_rz,
                                                       const double *__restrict__ rr_part, int m_rr,
                                                       double *__restrict__ part, double *scal, int32_t *flags,
@@ -205,23 +208,23 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8
     double acc[1] = {0.0};
     tile_spmv(tiles, ntiles, ptr, cols, val, z, prod, [&](int32_t) { return 0; },
               [&](int32_t row, double s, int) {
-        const double pn = k > 0 ? z[row] + beta * p[row] : z[row];
-        const double qn = k > 0 ? s + beta * q[row] : s;
+        const XT pn = (XT)(k > 0 ? (double)z[row] + beta * (double)p[row] : (double)z[row]);
+        const XT qn = (XT)(k > 0 ? s + beta * (double)q[row] : s);
         p[row] = pn;
         q[row] = qn;
-        acc[0] += pn * qn;
+        acc[0] += (double)pn * (double)qn;
     });
     write_partials<1>(acc, part);
 }
 
 // alpha = r.z / p.q; x += alpha p; r -= alpha q; with Jacobi also z = D^-1 r; partials of
-// r.z (Jacobi) and r.r
-template <bool JAC>
-__global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__restrict__ x,
-                                                        double *__restrict__ r, double *__restrict__ z,
-                                                        const double *__restrict__ p,
-                                                        const double *__restrict__ q,
-                                                        const double *__restrict__ dinv,
+// r.z (Jacobi) and r.r of the stored values. XT: the vectors' type, as in k_cg_spmv.
+template <bool JAC, typename XT>
+__global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, XT *__restrict__ x,
+                                                        XT *__restrict__ r, XT *__restrict__ z,
+                                                        const XT *__restrict__ p,
+                                                        const XT *__restrict__ q,
+                                                        const XT *__restrict__ dinv,
                                                         const double *__restrict__ qpart, double *__restrict__ part,
                                                         int m, const double *scal, const int32_t *flags, int32_t par) {
     if (flags[0]) return;
@@ -229,17 +232,74 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int32_t n, double *__res
     const double alpha = scal[S_RZ + (par ^ 1)] / sum_partials(qpart, m, sh);
     double acc[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        x[i] += alpha * p[i];
-        double ri = r[i] - alpha * q[i];
+        x[i] = (XT)((double)x[i] + alpha * (double)p[i]);
+        const XT ri = (XT)((double)r[i] - alpha * (double)q[i]);
         r[i] = ri;
         if (JAC) {
-            double zi = ri * dinv[i];
+            const XT zi = (XT)((double)ri * (double)dinv[i]);
             z[i] = zi;
-            acc[0] += ri * zi;
+            acc[0] += (double)ri * (double)zi;
         }
-        acc[1] += ri * ri;
+        acc[1] += (double)ri * (double)ri;
     }
     write_partials<2>(acc, part);
+}
+
+// Mixed-precision solve. Outer step: r = b - A x in FP64, stored, with partials of r.r and b.b.
+__global__ void __launch_bounds__(kThreads) k_res_store(const int2 *__restrict__ tiles, int32_t ntiles,
+                                                        const int32_t *__restrict__ ptr, const TileCols cols,
+                                                        const double *__restrict__ val, const double *__restrict__ x,
+                                                        const double *__restrict__ b, double *__restrict__ r,
+                                                        double *__restrict__ part) {
+    __shared__ double prod[kTileCap];
+    double acc[2] = {0.0, 0.0};
+    tile_spmv(tiles, ntiles, ptr, cols, val, x, prod, [&](int32_t row) { return b[row]; },
+              [&](int32_t row, double s, double bb) {
+        const double ri = bb - s;
+        r[row] = ri;
+        acc[0] += ri * ri;
+        acc[1] += bb * bb;
+    });
+    write_partials<2>(acc, part);
+}
+
+// Inner start: the FP32 system A d = r / ||r|| (unit right-hand side) from d = 0: r32 = r / ||r||,
+// d = p = 0, with Jacobi z = D^-1 r32; partials of r.z (Jacobi), r.r and b.b (= r.r here).
+// rr: ||r||^2 on the device.
+template <bool JAC>
+__global__ void __launch_bounds__(kThreads) k_inner_init(int32_t n, const double *__restrict__ r, const double *rr,
+                                                         float *__restrict__ r32, float *__restrict__ x32,
+                                                         float *__restrict__ z32, float *__restrict__ p32,
+                                                         const float *__restrict__ dinv32, double *__restrict__ part) {
+    const double inv = 1.0 / sqrt(*rr);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const float ri = (float)(r[i] * inv);
+        r32[i] = ri;
+        x32[i] = 0.0f;
+        p32[i] = 0.0f;
+        if (JAC) {
+            const float zi = (float)((double)ri * (double)dinv32[i]);
+            z32[i] = zi;
+            acc[0] += (double)ri * (double)zi;
+        }
+        acc[1] += (double)ri * (double)ri;
+    }
+    acc[2] = acc[1];
+    write_partials<3>(acc, part);
+}
+
+// Outer update: x += ||r|| d (FP64).
+__global__ void k_refine(int32_t n, double *__restrict__ x, const float *__restrict__ d, const double *rr) {
+    const double s = sqrt(*rr);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += s * (double)d[i];
+}
+
+template <typename S, typename D>
+__global__ void k_convert(int64_t n, const S *__restrict__ in, D *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (D)in[i];
 }
 
 // one block, after a batch: finish the last update's convergence test
@@ -546,6 +606,7 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     // iterations after convergence return at once on the device; sizing the first batch from
     // the previous solve avoids most of them and most host reads of the flag
     int first = w.last_iters[learned ? 1 : 0];
+    if (first > 0) ++first;  // one idle launch when the count repeats, no second batch when it grows by one
     int it = 0;
     // Recurrence residuals drift from the true one; a solve whose recurrence converged but whose
     // recomputed residual misses the target restarts from its iterate (at most kRestarts times)
@@ -570,17 +631,17 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
             for (int k = it - it0; k < it - it0 + batch; ++k) {
                 int par = k & 1;
                 int ta = qh_tbeg(c);
-                hipLaunchKernelGGL(k_cg_spmv, dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr,
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_spmv<double, double>), dim3(gt), dim3(kThreads), 0, c->stream, w.n, M.tiles, M.ntiles, M.ptr,
                                    M.cols(), M.val, w.z, w.p0, w.q, learned ? (const double *)ppart : (const double *)upart,
                                    learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par,
                                    stall);
                 qh_tend(c, ta, k_spmv);
                 int tb = qh_tbeg(c);
                 if (learned)
-                    hipLaunchKernelGGL(k_cg_update<false>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<false, double>), dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
                                        w.p0, w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
                 else
-                    hipLaunchKernelGGL(k_cg_update<true>, dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<true, double>), dim3(ge), dim3(kThreads), 0, c->stream, w.n, w.x, w.r, w.z,
                                        w.p0, w.q, w.dinv, qpart, upart, (int)gt, w.scal, w.flags, par);
                 qh_tend(c, tb, k_upd);
                 m_up = (int)ge;
@@ -617,6 +678,158 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
         out.restarts = restart + 1;
     }
     if (out.converged) w.last_iters[learned ? 1 : 0] = out.iters;
+    return QH_OK;
+}
+
+// Mixed-precision edge solve (iterative refinement): with r = b - A x computed in FP64, each
+// refinement solves A d = r / ||r|| by FP32 PCG (the FP32 copy of A's values, FP32 vectors,
+// FP64 products and dot products, the same preconditioner) to the relative residual eta that
+// the FP64 target still needs (halved for safety; at least 1e-5, near the FP32 floor; at most
+// 0.1), and adds ||r|| d to x in FP64. The FP64 residual of the next step decides convergence,
+// so the stopping rule is the FP64 solve's. An inner solve that meets non-finite values is not
+// applied (flag 3); one stopped by the stall rule is applied and the solve returns (flag 2).
+int qh_cg_alloc32(qh_ctx *c, CgWork &w, int32_t n) {
+    if (w.n32 >= n) return QH_OK;
+    int rc;
+    if ((rc = qh_alloc(c, &w.x32, n)) || (rc = qh_alloc(c, &w.r32, n)) || (rc = qh_alloc(c, &w.z32, n)) ||
+        (rc = qh_alloc(c, &w.p32, n)) || (rc = qh_alloc(c, &w.q32, n)) || (rc = qh_alloc(c, &w.dinv32, n)))
+        return rc;
+    w.n32 = n;
+    return QH_OK;
+}
+
+int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
+                      SolveResult &out, bool learned) {
+    out = SolveResult();
+    const int32_t n = w.n;
+    if (n == 0) {
+        out.converged = out.true_ok = true;
+        out.flag = CG_CONVERGED;
+        return QH_OK;
+    }
+    int rc;
+    if ((rc = qh_cg_alloc32(c, w, n))) return rc;
+    // FP32 copies: the matrix values once per time step size, the inverse diagonal every solve
+    // (a work area may serve several systems)
+    if (!M.val32 || M.val32_tau != c->tau_assembled) {
+        if (!M.val32 && (rc = qh_alloc(c, &M.val32, (size_t)M.nnz))) return rc;
+        const unsigned gc = (unsigned)std::min<int64_t>((M.nnz + 255) / 256, 8192);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_convert<double, float>), dim3(gc), dim3(256), 0, c->stream, M.nnz, M.val,
+                           M.val32);
+        M.val32_tau = c->tau_assembled;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_convert<double, float>), dim3(grid_elems(n)), dim3(256), 0, c->stream,
+                       (int64_t)n, (const double *)w.dinv, w.dinv32);
+    QH_HIP(c, hipGetLastError());
+    double *upart = w.partial, *qpart = w.partial + 4 * kMaxBlocks, *ppart = w.partial + 5 * kMaxBlocks;
+    const unsigned ge = grid_elems(n), gt = tile_grid(M.ntiles);
+    const unsigned gp = learned ? qh_prec_grid(c) : 0;
+    const int stall = learned ? 1 : 0;
+    if (check_every <= 0) check_every = 8;
+    constexpr int kRefineMax = 8;
+    int total = 0;
+    int flag = CG_RUNNING;
+    for (int outer = 0;; ++outer) {
+        // FP64 residual of the present x (also the true residual of the solve)
+        int tr = qh_tbeg(c);
+        hipLaunchKernelGGL(k_res_store, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val,
+                           w.x, w.b, w.r, upart);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + S_RES);
+        qh_tend(c, tr, QK_TRUE_RES);
+        QH_HIP(c, hipGetLastError());
+        double sc[2];
+        QH_HIP(c, hipMemcpyAsync(sc, w.scal + S_RES, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        const double rr = sc[0], bb = sc[1], thr2 = tol * tol * bb;
+        out.res = bb > 0 ? sqrt(rr / bb) : 0.0;
+        out.true_ok = rr == rr && rr <= thr2;
+        if (out.true_ok) {
+            flag = CG_CONVERGED;
+            break;
+        }
+        if (!(rr == rr) || rr > 1.7976931348623157e308) {
+            flag = CG_NONFINITE;
+            break;
+        }
+        if (flag == CG_STALLED || outer == kRefineMax || total >= max_it) break;
+        const double eta = std::min(0.1, std::max(1e-5, 0.5 * sqrt(thr2 / rr)));
+        // inner FP32 PCG on A d = r / ||r||, d = 0
+        int t0 = qh_tbeg(c);
+        if (learned) {
+            hipLaunchKernelGGL(k_inner_init<false>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES,
+                               w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
+            QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, nullptr));
+        } else {
+            hipLaunchKernelGGL(k_inner_init<true>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES,
+                               w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
+        }
+        hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)ge,
+                           learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)ge,
+                           w.scal, w.flags, eta * eta, (const double *)nullptr, stall);
+        qh_tend(c, t0, QK_CG_INIT);
+        QH_HIP(c, hipGetLastError());
+        int32_t hflags[2] = {0, 0};
+        QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        int m_up = (int)ge;
+        int it = 0;
+        const int cap = max_it - total;
+        // the first batch: one iteration more than this refinement took in the last solve (a
+        // solve that needs one more then costs one idle launch, not a second batch and host read)
+        const int prev = outer < CgWork::kMixedHist ? w.last_inner[learned ? 1 : 0][outer] : 0;
+        const int first = prev > 0 ? prev + 1 : 0;
+        while (it < cap && !hflags[0]) {
+            const int batch = std::min(it == 0 && first > 0 ? first : check_every, cap - it);
+            for (int k = it; k < it + batch; ++k) {
+                const int par = k & 1;
+                int ta = qh_tbeg(c);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_spmv<float, float>), dim3(gt), dim3(kThreads), 0, c->stream, n,
+                                   M.tiles, M.ntiles, M.ptr, M.cols(), (const float *)M.val32, (const float *)w.z32,
+                                   w.p32, w.q32, learned ? (const double *)ppart : (const double *)upart,
+                                   learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par,
+                                   stall);
+                qh_tend(c, ta, QK_CG_SPMV);
+                int tb = qh_tbeg(c);
+                if (learned)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<false, float>), dim3(ge), dim3(kThreads), 0, c->stream, n,
+                                       w.x32, w.r32, w.z32, (const float *)w.p32, (const float *)w.q32,
+                                       (const float *)w.dinv32, qpart, upart, (int)gt, w.scal, w.flags, par);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_update<true, float>), dim3(ge), dim3(kThreads), 0, c->stream, n,
+                                       w.x32, w.r32, w.z32, (const float *)w.p32, (const float *)w.q32,
+                                       (const float *)w.dinv32, qpart, upart, (int)gt, w.scal, w.flags, par);
+                qh_tend(c, tb, QK_CG_UPDATE);
+                m_up = (int)ge;
+                if (learned) {
+                    int tp = qh_tbeg(c);
+                    QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, w.flags));
+                    qh_tend(c, tp, QK_PREC);
+                }
+            }
+            it += batch;
+            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags, it);
+            QH_HIP(c, hipGetLastError());
+            QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
+        const int done = hflags[0] ? hflags[1] : it;
+        if (outer < CgWork::kMixedHist) w.last_inner[learned ? 1 : 0][outer] = hflags[0] == CG_CONVERGED ? done : 0;
+        total += done;
+        out.refinements = outer + 1;
+        if (hflags[0] == CG_NONFINITE) {
+            flag = CG_NONFINITE;  // d is not applied; x keeps the last refinement's value
+            break;
+        }
+        int tf = qh_tbeg(c);
+        hipLaunchKernelGGL(k_refine, dim3(ge), dim3(kThreads), 0, c->stream, n, w.x, (const float *)w.x32,
+                           (const double *)(w.scal + S_RES));
+        qh_tend(c, tf, QK_TRUE_RES);
+        QH_HIP(c, hipGetLastError());
+        flag = hflags[0] == CG_STALLED ? CG_STALLED : CG_RUNNING;
+    }
+    out.iters = total;
+    out.flag = flag;
+    out.converged = flag == CG_CONVERGED;
     return QH_OK;
 }
 

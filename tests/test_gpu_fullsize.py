@@ -30,7 +30,11 @@ def plasma64():
     return cfg, mesh, parts, cx, op, po
 
 
-def test_plasma64_full_cycle(plasma64):
+@pytest.mark.parametrize("solver", ["mixed", "fp64"])
+def test_plasma64_full_cycle(plasma64, solver):
+    """One step of the 64^3 / 16M cycle in the launch configuration the benchmark times (learned
+    preconditioner; the mixed-precision edge solve of its headline run, and the FP64 one), checked
+    piece by piece against the oracle."""
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
     cfg, mesh, parts, cx, op, po = plasma64
@@ -52,8 +56,10 @@ def test_plasma64_full_cycle(plasma64):
     e0, b0 = ctx.fields_download()
     _, Q0 = ctx.deposits_download()
     ctx.capture_segments(int(1.5 * n))
-    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     st = ctx.pic_step(params)[0]
+    assert (st["edge_refinements"] >= 1) == (solver == "mixed")
     assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
     assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8
     assert st["crossings"] > 100_000
@@ -140,7 +146,7 @@ def test_plasma64_full_cycle(plasma64):
 
 def test_plasma64_100_steps(plasma64):
     """The workload's full run: 100 steps of the 64^3 / 16M cycle with the learned preconditioner
-    and a re-sort every 20 steps, every invariant checked on the device at every step (continuity
+    (mixed-precision edge solve, as the benchmark runs it) and a re-sort every 20 steps, every invariant checked on the device at every step (continuity
     bit for bit, D b unchanged, no lost particle, no fallback, both residuals at 1e-8); at the end
     the total charge is the initial one, D b is unchanged on the host and sampled particles lie
     in the tets the device holds them in."""
@@ -157,7 +163,7 @@ def test_plasma64_100_steps(plasma64):
     _, b0 = ctx.fields_download()
     _, Q0 = ctx.deposits_download()
     params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=cfg["sort_every"],
-                             verify=1)
+                             verify=1, solver=qh.SOLVER_MIXED)
     stats = ctx.pic_step(params, cfg["steps"])
     assert len(stats) == 100
     for k, st in enumerate(stats):
@@ -328,8 +334,10 @@ def test_plasma64_plane_wave_natural_boundary(plasma64):
     ctx.precond_train(steps=60, lr=3e-3, seed=1, validate_every=0)
     e0, b0 = ctx.fields_download()
     _, Q0 = ctx.deposits_download()
-    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=qh.PC_LEARNED, sort_every=20, verify=1,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     st = ctx.pic_step(params)[0]
+    assert (st["edge_refinements"] >= 1) == (solver == "mixed")
     assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
     assert st["fallbacks"] == 0 and st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8
     g, Q1 = ctx.deposits_download()

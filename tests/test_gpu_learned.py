@@ -309,9 +309,10 @@ def test_nonfinite_network_falls_back_to_jacobi(prob):
     w[5312] = np.nan
     ctx.precond_set_weights(w)
     b, _ = _edge_rhs(A, 1, 7)
-    x, st = ctx.field_solve(qh.SYS_EDGE, b[0], tol=1e-8, precond=qh.PC_LEARNED, max_it=400)
-    assert st["fallback"] == 1 and st["res"] <= 1e-8
-    assert np.linalg.norm(A @ x - b[0]) <= 1.0001e-8 * np.linalg.norm(b[0])
+    for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
+        x, st = ctx.field_solve(qh.SYS_EDGE, b[0], tol=1e-8, precond=qh.PC_LEARNED, max_it=400, solver=solver)
+        assert st["fallback"] == 1 and st["res"] <= 1e-8
+        assert np.linalg.norm(A @ x - b[0]) <= 1.0001e-8 * np.linalg.norm(b[0])
 
 
 def test_stalled_network_falls_back_quickly(prob):
@@ -325,11 +326,12 @@ def test_stalled_network_falls_back_quickly(prob):
     ctx = gpu_context(mesh, DT)
     ctx.precond_set_weights(_flat(_bad_weights()))
     b, _ = _edge_rhs(A, 1, 7)
-    x, st = ctx.field_solve(qh.SYS_EDGE, b[0], tol=1e-8, precond=qh.PC_LEARNED, max_it=2000)
     _, sj = ctx.field_solve(qh.SYS_EDGE, b[0], tol=1e-8, precond=qh.PC_JACOBI, max_it=2000)
-    assert st["fallback"] == 1 and st["res"] <= 1e-8
-    assert st["iters"] < sj["iters"] + 200        # without the rule: 2000 learned iterations first
-    assert np.linalg.norm(A @ x - b[0]) <= 1.0001e-8 * np.linalg.norm(b[0])
+    for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
+        x, st = ctx.field_solve(qh.SYS_EDGE, b[0], tol=1e-8, precond=qh.PC_LEARNED, max_it=2000, solver=solver)
+        assert st["fallback"] == 1 and st["res"] <= 1e-8
+        assert st["iters"] < sj["iters"] + 200        # without the rule: 2000 learned iterations first
+        assert np.linalg.norm(A @ x - b[0]) <= 1.0001e-8 * np.linalg.norm(b[0])
     from oracle import learned as Lr
     ctx.precond_set_weights(_flat(Lr.init_weights(0)))
     ctx.precond_train(steps=80, lr=3e-3, seed=2, validate_every=0)
@@ -350,10 +352,12 @@ def test_full_cycle_with_learned_preconditioner(prob):
     ctx.particles_upload(sid, *parts)
     cx = Complex(mesh.xyz, mesh.tets)
     for pc in (qh.PC_LEARNED, qh.PC_JACOBI):
-        p = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=pc, verify=1)
-        for st in ctx.pic_step(p, 3):
-            assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
-            assert st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8 and st["fallbacks"] == 0
+        for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
+            p = ctx.step_params(field_mode=qh.FIELDS_SOLVE, precond=pc, verify=1, solver=solver)
+            for st in ctx.pic_step(p, 3):
+                assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
+                assert st["edge_res"] <= 1e-8 and st["gauss_res"] <= 1e-8 and st["fallbacks"] == 0
+                assert (st["edge_refinements"] >= 1) == (solver == qh.SOLVER_MIXED)
     e, b = ctx.fields_download()
     assert not (cx.D @ b).any()
 

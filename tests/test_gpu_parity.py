@@ -245,8 +245,12 @@ def test_positions_100_steps_tie_consistent(jitter4):
                                      v_rel=err_stats(np.abs(vg - vo).max(axis=1) / np.abs(vo).max()), ties=ties))
 
 
-def test_full_cycle_field_update_matches_oracle(jitter4):
-    """Each GPU field update equals the oracle's applied to the same state and deposits."""
+@pytest.mark.parametrize("solver", ["fp64", "mixed"])
+def test_full_cycle_field_update_matches_oracle(jitter4, solver):
+    """Each GPU field update equals the oracle's applied to the same state and deposits, with the
+    FP64 edge solve and with the mixed-precision one (FP64 residual refinement around FP32 inner
+    iterations, stopping on the same FP64 residual)."""
+    import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
     cfg, mesh, cx, op, po, e, b, parts = jitter4
     dt = 2e-10
@@ -257,13 +261,15 @@ def test_full_cycle_field_update_matches_oracle(jitter4):
     ctx.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
     fo = FieldOracle(cx, op, dt)
     u_q = qi.QE * 2.0 ** -40
-    params = ctx.step_params(field_mode=1, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    params = ctx.step_params(field_mode=1, verify=1, tol_edge=1e-10, tol_node=1e-10,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     Qbg = np.zeros(cx.Nn, np.int64)
     for k in range(8):
         e_n, b_n = ctx.fields_download()
         st = ctx.pic_step(params)[0]
         assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
-        assert st["edge_res"] <= 1e-10 * 1.0001
+        assert st["edge_res"] <= 1e-10 * 1.0001 and st["fallbacks"] == 0
+        assert (st["edge_refinements"] >= 1) == (solver == "mixed")
         assert st["gauss_res"] <= 1e-9
         e_g, b_g = ctx.fields_download()
         g, Q = ctx.deposits_download()
@@ -879,11 +885,14 @@ def test_field_solve_residual(jitter4):
     K = op.K[inn][:, inn].tocsc()
     for system, M in ((qh.SYS_EDGE, A), (qh.SYS_NODE, K)):
         rhs = rng.standard_normal(M.shape[0]) * 1e-12
-        x, st = ctx.field_solve(system, rhs, tol=1e-8)
         ref = sla.spsolve(M, rhs)
-        assert st["res"] <= 1e-8
-        assert np.linalg.norm(M @ x - rhs) <= 1.0001e-8 * np.linalg.norm(rhs)
-        assert np.linalg.norm(x - ref) <= 1e-5 * np.linalg.norm(ref)
+        # FP64 PCG, and FP64 refinement around FP32 inner PCG (the right-hand side of order 1e-12
+        # checks its scaling to a unit residual)
+        for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
+            x, st = ctx.field_solve(system, rhs, tol=1e-8, solver=solver)
+            assert st["res"] <= 1e-8 and st["fallback"] == 0
+            assert np.linalg.norm(M @ x - rhs) <= 1.0001e-8 * np.linalg.norm(rhs)
+            assert np.linalg.norm(x - ref) <= 1e-5 * np.linalg.norm(ref)
 
 
 def test_degenerate_particle_sets(jitter4):
@@ -1030,6 +1039,11 @@ def test_scattered_numbering_reads_wide_column_tiles():
     xl, stl = ctx.field_solve(qh.SYS_EDGE, rhs, tol=1e-8, precond=qh.PC_LEARNED)
     assert stl["fallback"] == 0 and stl["iters"] < st["iters"]
     assert np.linalg.norm(A @ xl - rhs) <= 1.0001e-8 * np.linalg.norm(rhs)
+    # the FP32 inner iterations of the mixed solve through the same 32-bit column tiles
+    for pc in (qh.PC_JACOBI, qh.PC_LEARNED):
+        xm, stm = ctx.field_solve(qh.SYS_EDGE, rhs, tol=1e-8, precond=pc, solver=qh.SOLVER_MIXED)
+        assert stm["fallback"] == 0
+        assert np.linalg.norm(A @ xm - rhs) <= 1.0001e-8 * np.linalg.norm(rhs)
 
 
 def test_sort_keeps_particles_and_invariants(jitter4):
