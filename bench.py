@@ -354,6 +354,13 @@ def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: 
         fo.step(e, b, u_b, out["g"], u_q, out["Q"], out["Q"], tol=1e-8, tol_n=1e-8)
         t_field = time.perf_counter() - t0
     t_step = t_push * n_total / n_s + t_field
+    # the same on one thread: the push over a sample as many times smaller as there were threads
+    # (about the same seconds), the field update as above (its sparse products run on one thread)
+    n_1 = max(min(n_s, 10_000), n_s // cores)
+    t0 = time.perf_counter()
+    po.push(e, b * u_b, x[:n_1], v[:n_1], tet[:n_1], -qi.QE / qi.ME, cfg["dt"], -1, nthreads=1)
+    t_push1 = time.perf_counter() - t0
+    t_step1 = t_push1 * n_total / n_1 + t_field
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -363,8 +370,13 @@ def cpu_baseline(wl: str, cfg, mesh, parts, sample_particles: int, seconds_cap: 
     return {"value": n_total / t_step, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "cpu_model": model, "push_s": round(t_push, 3), "field_s": round(t_field, 3),
             "sample": f"one step of {n_s} of {n_total} particles (FP64 C oracle, {cores} threads, "
-                      f"{t_push:.2f}s) + one FP64 field update on the full mesh (numpy/scipy, "
-                      f"{t_field:.2f}s); rate = N_p / (push time scaled to N_p + field time)"}
+                      f"{t_push:.2f}s) + one FP64 field update on the full mesh (numpy/scipy sparse "
+                      f"products and PCG, one thread, {t_field:.2f}s); rate = N_p / (push time scaled "
+                      f"to N_p + field time)",
+            "single_thread": {"value": n_total / t_step1, "unit": "particle-steps/s", "cores": 1,
+                              "push_s": round(t_push1, 3), "push_particles": n_1, "field_s": round(t_field, 3),
+                              "push_only_particle_steps_per_s": round(n_1 / t_push1, 1)},
+            "push_only_particle_steps_per_s": round(n_s / t_push, 1)}
 
 
 def frozen_particle_phase(workload: str, warmup: int, steps: int):

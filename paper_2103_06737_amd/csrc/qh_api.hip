@@ -19,8 +19,10 @@ int qh_tbeg(qh_ctx *c) {
     if (!c->timing) return -1;
     int slot = (int)c->pending.size() * 2;
     while ((int)c->ev_pool.size() < slot + 2) {
+        // timing only, read after the stream is synchronised: no system-scope fence on record
+        // (the fence writes back and invalidates the caches, which would slow the next kernel)
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         c->ev_pool.push_back(e);
     }
     (void)hipEventRecord(c->ev_pool[slot], c->stream);
@@ -1026,7 +1028,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
     hipEvent_t ev[4];
     bool use_ev = stats != nullptr;
     if (use_ev)
-        for (auto &x : ev) QH_HIP(c, hipEventCreate(&x));
+        for (auto &x : ev) QH_HIP(c, hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
     // totals of the whole call (fixed-point headroom overflows of the gathers, lost particles,
     // verification failures), kept whether or not stats are asked for; the per-step slots before
     // them are cleared every step
