@@ -77,7 +77,7 @@ def phase_bytes(mi, n_particles: int, crossings: float, n_occ: int) -> int:
 
 
 def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learned: bool = False,
-                      mixed: bool = False):
+                      mixed: bool = False, n_species: int = 1):
     """Bytes one launch must move at least (each datum read or written once). mixed: the inner
     iterations of the mixed-precision edge solve (FP32 matrix values and vectors)."""
     v = 4 if mixed else 8   # bytes per vector entry (and per value of A) in the edge iterations
@@ -97,10 +97,13 @@ def algorithmic_bytes(kernel: str, mi, n_particles: int, crossings: float, learn
             return 6 * v * n                             # x, r rw; p, q in (z comes from the factor)
         return 8 * v * n                                 # x, r rw; p, q, dinv in; z out
     if kernel == "particle_step":
-        # particle state in+out (28 B each way), per tet: geometry 48 + field 48 + vertex ids 16
-        # + edge ids 24, per crossing: neighbour ids 16 + the next tet's records 136,
-        # accumulators read-modify-write once (16 B per edge and node)
-        return 56 * n_particles + 136 * mi.n_tets + 152 * crossings + 16 * (mi.n_edges + mi.n_nodes)
+        # one launch per species: particle state in+out (28 B each way), per tet: geometry 48 +
+        # field 48 + vertex ids 16 + edge ids 24, per crossing: neighbour ids 16 + the next tet's
+        # records 136, accumulators read-modify-write once (16 B per edge and node); n_particles
+        # and crossings are the step's totals, and the result is the average launch's share
+        per_step = (56 * n_particles + n_species * (136 * mi.n_tets + 16 * (mi.n_edges + mi.n_nodes))
+                    + 152 * crossings)
+        return per_step / n_species
     if kernel == "precond":
         # z = G^T (G r): two CSR passes over the lower factor and its transpose (BF16 value,
         # column of 2 or 4 bytes as in cg_spmv); per row: r in, y out, y in, z out, r in (dot),
@@ -576,7 +579,8 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
 
     def roof(k, kern, r):
-        by = algorithmic_bytes(k, mi, n_p, crossings, learned=r["precond"] == "learned", mixed=r["solver"] == "mixed")
+        by = algorithmic_bytes(k, mi, n_p, crossings, learned=r["precond"] == "learned", mixed=r["solver"] == "mixed",
+                               n_species=len(parts))
         if by is None or k not in kern:
             return None
         # the edge iterations' kernels: the time of all their launches over the iterations that
