@@ -621,10 +621,15 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
                            w.scal, w.flags, tol * tol, abs_thr2_dev, stall);
         qh_tend(c, t0, QK_CG_INIT);
         QH_HIP(c, hipGetLastError());
+        // the start's verdict is read on the host only when the last solve needed no iteration
+        // (or there was none); otherwise the first batch is launched at once, and its launches
+        // return at once if the start already stopped the iteration
         int32_t hflags[2] = {0, 0};
         int m_up = (int)gt;
-        QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
-        QH_HIP(c, hipStreamSynchronize(c->stream));
+        if (!(first > 0 && restart == 0)) {
+            QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
         const int it0 = it;  // the device counts this run's iterations from 0
         while (it < max_it && !hflags[0]) {
             int batch = std::min(it == it0 && first > 0 && restart == 0 ? first : check_every, max_it - it);
@@ -768,9 +773,7 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
                            w.scal, w.flags, eta * eta, (const double *)nullptr, stall);
         qh_tend(c, t0, QK_CG_INIT);
         QH_HIP(c, hipGetLastError());
-        int32_t hflags[2] = {0, 0};
-        QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
-        QH_HIP(c, hipStreamSynchronize(c->stream));
+        int32_t hflags[2] = {0, 0};  // as in qh_cg_solve: read now only without a batch size from history
         int m_up = (int)ge;
         int it = 0;
         const int cap = max_it - total;
@@ -778,6 +781,10 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
         // solve that needs one more then costs one idle launch, not a second batch and host read)
         const int prev = outer < CgWork::kMixedHist ? w.last_inner[learned ? 1 : 0][outer] : 0;
         const int first = prev > 0 ? prev + 1 : 0;
+        if (first == 0) {
+            QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
+            QH_HIP(c, hipStreamSynchronize(c->stream));
+        }
         while (it < cap && !hflags[0]) {
             const int batch = std::min(it == 0 && first > 0 ? first : check_every, cap - it);
             for (int k = it; k < it + batch; ++k) {
