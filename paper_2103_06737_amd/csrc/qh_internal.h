@@ -79,6 +79,9 @@ struct TileCols {
     const int32_t *col;
     const uint16_t *col16;
     const int4 *tbase;
+    // optional, BF16 values only: value bits << 16 | 16-bit column per entry, one load each in
+    // the compact tiles (the value and column arrays still serve the others)
+    const uint32_t *pk = nullptr;
 };
 
 struct DevCsr {
@@ -149,6 +152,7 @@ struct LearnedPrec {
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;
     uint16_t *gval_h = nullptr, *tval_h = nullptr;  // BF16 copies of G and G^T for the application
+    uint32_t *gpk = nullptr, *tpk = nullptr;         // the same packed with their 16-bit columns
     double *y = nullptr;
     float *y32 = nullptr;  // the application's intermediate G r on FP32 vectors (allocated on first use)
     float *w = nullptr, *best_w = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;

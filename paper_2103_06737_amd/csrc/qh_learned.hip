@@ -211,13 +211,19 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_factor(const float *__restr
 
 // G^T values out[k] = in[src[k]], and BF16 copies of G and G^T for the application
 __global__ void k_gather_f32(int64_t n, const int32_t *__restrict__ src, const float *__restrict__ in,
-                             float *__restrict__ out, uint16_t *__restrict__ in_h, uint16_t *__restrict__ out_h) {
+                             float *__restrict__ out, uint16_t *__restrict__ in_h, uint16_t *__restrict__ out_h,
+                             const uint16_t *__restrict__ in_c16, const uint16_t *__restrict__ out_c16,
+                             uint32_t *__restrict__ in_pk, uint32_t *__restrict__ out_pk) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) {
         const float v = in[src[k]];
         out[k] = v;
-        out_h[k] = (uint16_t)f2bf(v);
-        in_h[k] = (uint16_t)f2bf(in[k]);
+        const uint32_t vo = (uint16_t)f2bf(v), vi = (uint16_t)f2bf(in[k]);
+        out_h[k] = (uint16_t)vo;
+        in_h[k] = (uint16_t)vi;
+        // packed with the compact columns (BF16 bits high, column low)
+        out_pk[k] = vo << 16 | out_c16[k];
+        in_pk[k] = vi << 16 | in_c16[k];
     }
 }
 
@@ -778,7 +784,8 @@ int qh_learned_setup(qh_ctx *c) {
         std::vector<uint16_t> g16, t16;
         L.nnz_c16 = qh_compact_cols(gcol.data(), gt, gb, g16) + qh_compact_cols(tcol.data(), tt, tb, t16);
         if ((rc = qh_alloc(c, &L.gtbase, gb.size())) || (rc = qh_alloc(c, &L.ttbase, tb.size())) ||
-            (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())))
+            (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())) ||
+            (rc = qh_alloc(c, &L.gpk, g16.size())) || (rc = qh_alloc(c, &L.tpk, t16.size())))
             return rc;
         QH_HIP(c, hipMemcpyAsync(L.gtbase, gb.data(), sizeof(int4) * gb.size(), hipMemcpyHostToDevice, c->stream));
         QH_HIP(c, hipMemcpyAsync(L.ttbase, tb.data(), sizeof(int4) * tb.size(), hipMemcpyHostToDevice, c->stream));
@@ -876,7 +883,8 @@ int qh_learned_factor(qh_ctx *c) {
     hipLaunchKernelGGL(k_mlp_factor, dim3(mlp_grid(L.nnz)), dim3(64 * kWaves), 0, c->stream, L.w, L.feats, L.grow,
                        L.gcol, L.gscale, L.nnz, L.o, L.gval);
     hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((L.nnz + 255) / 256)), dim3(256), 0, c->stream, L.nnz, L.tsrc,
-                       L.gval, L.tval, L.gval_h, L.tval_h);
+                       L.gval, L.tval, L.gval_h, L.tval_h, (const uint16_t *)L.gcol16, (const uint16_t *)L.tcol16,
+                       L.gpk, L.tpk);
     QH_HIP(c, hipGetLastError());
     L.factor_valid = true;
     return QH_OK;
@@ -889,9 +897,9 @@ unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, double>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, double>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase}, L.tval_h, L.y, z, r, part, done);
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk}, L.tval_h, L.y, z, r, part, done);
     return hipGetLastError();
 }
 
@@ -905,9 +913,9 @@ hipError_t launch_prec_apply32(qh_ctx *c, const float *r, float *z, double *part
         L.y32 = y;
     }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, float>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase}, L.gval_h, r, L.y32, (const float *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk}, L.gval_h, r, L.y32, (const float *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, float>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase}, L.tval_h, L.y32, z, r, part, done);
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk}, L.tval_h, L.y32, z, r, part, done);
     return hipGetLastError();
 }
 

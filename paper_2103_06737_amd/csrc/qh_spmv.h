@@ -11,6 +11,8 @@
 // as 16 bits (a window of the tile and an offset in it) wherever the tile allows it (TileCols).
 #pragma once
 
+#include <type_traits>
+
 #include "qh_internal.h"
 
 constexpr int kTileThreads = 256;
@@ -85,7 +87,20 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
         for (int32_t b = 0; b < cnt; b += kTileUnroll * kTileThreads) {
             VT v[kTileUnroll];
             int32_t c[kTileUnroll];
-            if (base0.x >= 0) {  // the same for the whole block
+            bool packed = false;
+            if constexpr (std::is_same<VT, uint16_t>::value) packed = cols.pk != nullptr;
+            if (base0.x >= 0 && packed) {  // the same for the whole block
+#pragma unroll
+                for (int u = 0; u < kTileUnroll; ++u) {
+                    int32_t j = b + u * kTileThreads + tid;
+                    j = j < cnt ? j : cnt - 1;  // clamped: every load stays inside the tile
+                    const uint32_t e = cols.pk[t0.y + j];
+                    v[u] = (VT)(e >> 16);
+                    const uint32_t h = e & 0xffffu;
+                    const uint32_t w = h >> 14;
+                    c[u] = (w == 0 ? base0.x : w == 1 ? base0.y : w == 2 ? base0.z : base0.w) + (int32_t)(h & 0x3fffu);
+                }
+            } else if (base0.x >= 0) {
 #pragma unroll
                 for (int u = 0; u < kTileUnroll; ++u) {
                     int32_t j = b + u * kTileThreads + tid;
