@@ -148,3 +148,20 @@ def test_host_cfl_bound_below_the_explicit_limit(name):
     assert 0.5 * exact < bound <= exact * (1 + 1e-9), (bound, exact)
     ctx.set_physics(4 * qi.EPS0, qi.MU0, 1e-12, 1.0, 2.0 ** -56)
     assert abs(ctx.mesh_info().dt_cfl / (2 * bound) - 1) < 1e-12
+
+
+def test_host_field_solve_validates_the_solver():
+    """qh_field_solve: an unknown solver is QH_EINVAL before anything else; FP64 and mixed
+    precision both need the device (QH_ESTATE on a host-only context)."""
+    import paper_2103_06737_amd as qh
+    m = qi.BoxMesh(2)
+    ctx = qh.Context(-1)
+    ctx.mesh_upload(m.xyz, m.tets)
+    rhs = np.zeros(max(ctx.info.n_int_edges, 1))
+    with pytest.raises(qh.QhError) as ei:
+        ctx.field_solve(qh.SYS_EDGE, rhs, solver=2)
+    assert ei.value.code == qh.QH_EINVAL
+    for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
+        with pytest.raises(qh.QhError) as ei:
+            ctx.field_solve(qh.SYS_EDGE, rhs, solver=solver)
+        assert ei.value.code == qh.QH_ESTATE
