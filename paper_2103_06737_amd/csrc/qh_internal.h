@@ -249,6 +249,8 @@ struct qh_ctx {
     int32_t loc_n[3] = {0, 0, 0};
     unsigned long long *counters = nullptr;  // 4*QH_COUNTER_SLOTS + QH_CNT_ALL (see QH_CNT_*)
     int32_t *hist = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
+    int32_t *perm = nullptr;   // the sort's source index per destination slot (perm_cap entries)
+    int64_t perm_cap = 0;
 
     std::vector<Species> species;
 

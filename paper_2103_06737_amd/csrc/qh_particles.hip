@@ -1078,13 +1078,13 @@ __global__ void __launch_bounds__(1024) k_scan_final(const int32_t *__restrict__
     if (i < n) out[i] = sums[blockIdx.x] + sh[threadIdx.x] - v;
 }
 
-__global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
-                          const float *__restrict__ z, const float *__restrict__ vx,
-                          const float *__restrict__ vy, const float *__restrict__ vz,
-                          const int32_t *__restrict__ tet, const int32_t *__restrict__ id,
-                          int32_t nt, int32_t *__restrict__ cursor, float *__restrict__ ox, float *__restrict__ oy,
-                          float *__restrict__ oz, float *__restrict__ ovx, float *__restrict__ ovy,
-                          float *__restrict__ ovz, int32_t *__restrict__ otet, int32_t *__restrict__ oid) {
+// Destination slot of every particle (its bucket's cursor, one atomic per run of equal keys in a
+// wave), recorded as perm[slot] = source index. After many steps of drift the runs are short and
+// the slots of a wave's particles scatter; moving the particle state in a second pass, in slot
+// order (k_permute), keeps the state's stores coalesced and leaves the scatter to the reads,
+// which stay near their slots.
+__global__ void k_sort_slots(int64_t n, const int32_t *__restrict__ tet, int32_t nt, int32_t *__restrict__ cursor,
+                             int32_t *__restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
     const int t = valid ? sort_key(tet[i], nt) : -1;
@@ -1093,8 +1093,19 @@ __global__ void k_scatter(int64_t n, const float *__restrict__ x, const float *_
     int32_t first = 0;
     if (valid && rank == 0) first = atomicAdd(&cursor[t], len);
     first = __shfl(first, head, 64);
-    if (!valid) return;
-    const int32_t j = first + rank;
+    if (valid) perm[first + rank] = (int32_t)i;
+}
+
+__global__ void k_permute(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ x,
+                          const float *__restrict__ y, const float *__restrict__ z, const float *__restrict__ vx,
+                          const float *__restrict__ vy, const float *__restrict__ vz,
+                          const int32_t *__restrict__ tet, const int32_t *__restrict__ id, float *__restrict__ ox,
+                          float *__restrict__ oy, float *__restrict__ oz, float *__restrict__ ovx,
+                          float *__restrict__ ovy, float *__restrict__ ovz, int32_t *__restrict__ otet,
+                          int32_t *__restrict__ oid) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t i = perm[j];
     ox[j] = x[i]; oy[j] = y[i]; oz[j] = z[i];
     ovx[j] = vx[i]; ovy[j] = vy[i]; ovz[j] = vz[i];
     otet[j] = tet[i]; oid[j] = id[i];
@@ -1114,8 +1125,18 @@ int qh_sort_species(qh_ctx *c, Species &s) {
     const bool absorb = c->walls == QH_WALLS_ABSORB;
     int32_t live = (int32_t)s.n;  // the start of the last bucket
     if (absorb) QH_HIP(c, hipMemcpyAsync(&live, c->cursor + nt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    hipLaunchKernelGGL(k_scatter, dim3(pb), dim3(256), 0, c->stream, s.n, s.x, s.y, s.zz, s.vx, s.vy, s.vz, s.tet,
-                       s.id, nt, c->cursor, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
+    if (c->perm_cap < s.n) {
+        // queued work may still read the old index buffer: released after the stream passes it
+        QH_HIP(c, hipStreamSynchronize(c->stream));
+        qh_release(c, c->perm);
+        c->perm_cap = 0;
+        int rc = qh_alloc(c, &c->perm, (size_t)s.cap);
+        if (rc) return rc;
+        c->perm_cap = s.cap;
+    }
+    hipLaunchKernelGGL(k_sort_slots, dim3(pb), dim3(256), 0, c->stream, s.n, s.tet, nt, c->cursor, c->perm);
+    hipLaunchKernelGGL(k_permute, dim3(pb), dim3(256), 0, c->stream, s.n, (const int32_t *)c->perm, s.x, s.y, s.zz,
+                       s.vx, s.vy, s.vz, s.tet, s.id, s.sx, s.sy, s.sz, s.svx, s.svy, s.svz, s.stet, s.sid);
     QH_HIP(c, hipGetLastError());
     std::swap(s.x, s.sx); std::swap(s.y, s.sy); std::swap(s.zz, s.sz);
     std::swap(s.vx, s.svx); std::swap(s.vy, s.svy); std::swap(s.vz, s.svz);
