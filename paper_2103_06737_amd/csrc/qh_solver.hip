@@ -18,9 +18,10 @@ constexpr int kLpr = 8;          // lanes per CSR row
 constexpr int kMaxBlocks = 2048; // fixed grid of the reducing kernels (fixed summation order)
 
 // device scalar slots of a CgWork: S_RZ + parity r.z (double-buffered), S_RR r.r, S_THR2 the
-// target on r.r, S_BB b.b, S_RES the true-residual sums, S_HIST a ring of r.r by iteration
+// target on r.r, S_BB b.b, S_RES the true-residual sums, S_SCALE the mixed-precision solve's
+// residual scale, S_HIST a ring of r.r by iteration
 // (the stall rule compares r.r with its value ten iterations before)
-enum { S_RZ = 0, S_RZ1, S_RR, S_THR2, S_BB, S_RES = 8, S_HIST = 16, S_NSCAL = 32 };
+enum { S_RZ = 0, S_RZ1, S_RR, S_THR2, S_BB, S_RES = 8, S_SCALE = 10, S_HIST = 16, S_NSCAL = 32 };
 constexpr int kHist = 16;
 // flags[0] after a solve: why the iteration stopped
 enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_STALLED = 2, CG_NONFINITE = 3 };
@@ -263,15 +264,17 @@ __global__ void __launch_bounds__(kThreads) k_res_store(const int2 *__restrict__
     write_partials<2>(acc, part);
 }
 
-// Inner start: the FP32 system A d = r / ||r|| (unit right-hand side) from d = 0: r32 = r / ||r||,
-// d = p = 0, with Jacobi z = D^-1 r32; partials of r.z (Jacobi), r.r and b.b (= r.r here).
-// rr: ||r||^2 on the device.
+// Mixed-precision solve. Start: the FP32 system A d = r0 / s, s = ||r0|| (a unit right-hand
+// side), from d = 0: r32 = r0 / s, d = p = 0, with Jacobi z = D^-1 r32; partials of r.z (Jacobi),
+// r.r and b.b (= r.r here). rr: ||r0||^2 on the device; s is kept in scal[S_SCALE] for the solve.
 template <bool JAC>
 __global__ void __launch_bounds__(kThreads) k_inner_init(int32_t n, const double *__restrict__ r, const double *rr,
-                                                         float *__restrict__ r32, float *__restrict__ x32,
-                                                         float *__restrict__ z32, float *__restrict__ p32,
-                                                         const float *__restrict__ dinv32, double *__restrict__ part) {
-    const double inv = 1.0 / sqrt(*rr);
+                                                         double *scal, float *__restrict__ r32,
+                                                         float *__restrict__ x32, float *__restrict__ z32,
+                                                         float *__restrict__ p32, const float *__restrict__ dinv32,
+                                                         double *__restrict__ part) {
+    const double s = sqrt(*rr), inv = 1.0 / s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_SCALE] = s;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const float ri = (float)(r[i] * inv);
@@ -289,11 +292,40 @@ __global__ void __launch_bounds__(kThreads) k_inner_init(int32_t n, const double
     write_partials<3>(acc, part);
 }
 
-// Outer update: x += ||r|| d (FP64).
-__global__ void k_refine(int32_t n, double *__restrict__ x, const float *__restrict__ d, const double *rr) {
-    const double s = sqrt(*rr);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+// Reliable update, first half: x += s d in FP64 and d = 0.
+__global__ void k_refine(int32_t n, double *__restrict__ x, float *__restrict__ d, const double *scal) {
+    const double s = scal[S_SCALE];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += s * (double)d[i];
+        d[i] = 0.0f;
+    }
+}
+
+// Reliable update, second half (after r = b - A x in FP64): the recurrence's residual replaced by
+// r32 = r / s, with Jacobi z = D^-1 r32, and the partials of r.z (Jacobi) and r.r written where
+// the update kernel writes them, so the iteration continues with the next product (its beta
+// from the new r.z), and the stop flag is cleared. The stall rule's history of r.r goes on: the
+// replaced residual differs from the recurrence's by its FP32 drift only, far below the rule's
+// 10 % over ten iterations while the solve converges, and a stalled solve stays stalled.
+template <bool JAC>
+__global__ void __launch_bounds__(kThreads) k_replace(int32_t n, const double *__restrict__ r, double *scal,
+                                                      float *__restrict__ r32, float *__restrict__ z32,
+                                                      const float *__restrict__ dinv32, double *__restrict__ part,
+                                                      int32_t *flags) {
+    const double inv = 1.0 / scal[S_SCALE];
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const float ri = (float)(r[i] * inv);
+        r32[i] = ri;
+        if (JAC) {
+            const float zi = (float)((double)ri * (double)dinv32[i]);
+            z32[i] = zi;
+            acc[0] += (double)ri * (double)zi;
+        }
+        acc[1] += (double)ri * (double)ri;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = CG_RUNNING;
+    write_partials<2>(acc, part);
 }
 
 template <typename S, typename D>
@@ -686,13 +718,15 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
     return QH_OK;
 }
 
-// Mixed-precision edge solve (iterative refinement): with r = b - A x computed in FP64, each
-// refinement solves A d = r / ||r|| by FP32 PCG (the FP32 copy of A's values, FP32 vectors,
-// FP64 products and dot products, the same preconditioner) to the relative residual eta that
-// the FP64 target still needs (halved for safety; at least 1e-5, near the FP32 floor; at most
-// 0.1), and adds ||r|| d to x in FP64. The FP64 residual of the next step decides convergence,
-// so the stopping rule is the FP64 solve's. An inner solve that meets non-finite values is not
-// applied (flag 3); one stopped by the stall rule is applied and the solve returns (flag 2).
+// Mixed-precision solve: PCG in FP32 (the FP32 copy of A's values, FP32 vectors, FP64 products
+// and dot products, the same preconditioner) on A d = r0 / s from the FP64 residual r0 = b - A x0,
+// s = ||r0||, with reliable updates: at the end of each batch of iterations x += s d in FP64,
+// r = b - A x is recomputed in FP64 (the convergence test: ||r|| <= tol ||b||, the FP64 solve's
+// stopping rule) and, unless it is met, replaces the recurrence's residual, which then continues
+// without a restart (its Krylov space and convergence rate are kept). The first batch ends near
+// half of the last solve's iterations and the second one past their end, so a step normally takes
+// two reliable updates. A batch that meets non-finite values is not applied (flag 3); one stopped
+// by the stall rule is applied and the solve returns (flag 2).
 int qh_cg_alloc32(qh_ctx *c, CgWork &w, int32_t n) {
     if (w.n32 >= n) return QH_OK;
     int rc;
@@ -731,70 +765,64 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
     const unsigned gp = learned ? qh_prec_grid(c) : 0;
     const int stall = learned ? 1 : 0;
     if (check_every <= 0) check_every = 8;
-    constexpr int kRefineMax = 8;
-    int total = 0;
-    int flag = CG_RUNNING;
-    for (int outer = 0;; ++outer) {
-        // FP64 residual of the present x (also the true residual of the solve)
+    // r = b - A x in FP64 with ||r||^2 and ||b||^2 on the host
+    double sc[2] = {0.0, 0.0};
+    auto fp64_residual = [&]() -> int {
         int tr = qh_tbeg(c);
         hipLaunchKernelGGL(k_res_store, dim3(gt), dim3(kThreads), 0, c->stream, M.tiles, M.ntiles, M.ptr, M.cols(), M.val,
                            w.x, w.b, w.r, upart);
         hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)gt, w.scal + S_RES);
         qh_tend(c, tr, QK_TRUE_RES);
         QH_HIP(c, hipGetLastError());
-        double sc[2];
         QH_HIP(c, hipMemcpyAsync(sc, w.scal + S_RES, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
         QH_HIP(c, hipStreamSynchronize(c->stream));
-        const double rr = sc[0], bb = sc[1], thr2 = tol * tol * bb;
-        out.res = bb > 0 ? sqrt(rr / bb) : 0.0;
-        out.true_ok = rr == rr && rr <= thr2;
-        if (out.true_ok) {
-            flag = CG_CONVERGED;
-            break;
-        }
-        if (!(rr == rr) || rr > 1.7976931348623157e308) {
-            flag = CG_NONFINITE;
-            break;
-        }
-        if (flag == CG_STALLED || outer == kRefineMax || total >= max_it) break;
-        const double eta = std::min(0.1, std::max(1e-5, 0.5 * sqrt(thr2 / rr)));
-        // inner FP32 PCG on A d = r / ||r||, d = 0
-        int t0 = qh_tbeg(c);
-        if (learned) {
-            hipLaunchKernelGGL(k_inner_init<false>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES,
-                               w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
-            QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, nullptr));
-        } else {
-            hipLaunchKernelGGL(k_inner_init<true>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES,
-                               w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
-        }
-        hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)ge,
-                           learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)ge,
-                           w.scal, w.flags, eta * eta, (const double *)nullptr, stall);
-        qh_tend(c, t0, QK_CG_INIT);
-        QH_HIP(c, hipGetLastError());
-        int32_t hflags[2] = {0, 0};  // as in qh_cg_solve: read now only without a batch size from history
-        int m_up = (int)ge;
-        int it = 0;
-        const int cap = max_it - total;
-        // the first batch: one iteration more than this refinement took in the last solve (a
-        // solve that needs one more then costs one idle launch, not a second batch and host read)
-        const int prev = outer < CgWork::kMixedHist ? w.last_inner[learned ? 1 : 0][outer] : 0;
-        const int first = prev > 0 ? prev + 1 : 0;
-        if (first == 0) {
-            QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
-            QH_HIP(c, hipStreamSynchronize(c->stream));
-        }
-        while (it < cap && !hflags[0]) {
-            const int batch = std::min(it == 0 && first > 0 ? first : check_every, cap - it);
-            for (int k = it; k < it + batch; ++k) {
-                const int par = k & 1;
+        return QH_OK;
+    };
+    if ((rc = fp64_residual())) return rc;
+    const double rr0 = sc[0], bb = sc[1], thr2 = tol * tol * bb;
+    out.res = bb > 0 ? sqrt(rr0 / bb) : 0.0;
+    if (!(rr0 == rr0) || rr0 > 1.7976931348623157e308) {
+        out.flag = CG_NONFINITE;
+        return QH_OK;
+    }
+    if (rr0 <= thr2) {
+        out.converged = out.true_ok = true;
+        out.flag = CG_CONVERGED;
+        return QH_OK;
+    }
+    // start of the FP32 recurrence; its target on the scaled residual: (0.9 tol ||b|| / s)^2, a
+    // little below the FP64 target, which the reliable update then usually confirms at once
+    int t0 = qh_tbeg(c);
+    if (learned) {
+        hipLaunchKernelGGL(k_inner_init<false>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES, w.scal,
+                           w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
+        QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, nullptr));
+    } else {
+        hipLaunchKernelGGL(k_inner_init<true>, dim3(ge), dim3(kThreads), 0, c->stream, n, w.r, w.scal + S_RES, w.scal,
+                           w.r32, w.x32, w.z32, w.p32, w.dinv32, upart);
+    }
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)ge,
+                       learned ? (const double *)ppart : (const double *)upart, learned ? (int)gp : (int)ge,
+                       w.scal, w.flags, 0.81 * thr2 / rr0, (const double *)nullptr, stall);
+    qh_tend(c, t0, QK_CG_INIT);
+    QH_HIP(c, hipGetLastError());
+    const int prev = w.last_inner[learned ? 1 : 0][0];  // iterations of the last converged solve
+    int k = 0, flag = CG_RUNNING;
+    for (int update = 0;; ++update) {
+        // a batch: to half of the last solve's iterations, then to one past their end, then
+        // check_every at a time
+        const int target = prev > 0 ? (update == 0 ? (prev + 1) / 2 : prev + 1) : 0;
+        const int batch = std::min(target > k ? target - k : check_every, max_it - k);
+        int32_t hflags[2] = {0, 0};
+        if (batch > 0) {
+            for (int kk = k; kk < k + batch; ++kk) {
+                const int par = kk & 1;
                 int ta = qh_tbeg(c);
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_spmv<float, float>), dim3(gt), dim3(kThreads), 0, c->stream, n,
                                    M.tiles, M.ntiles, M.ptr, M.cols(), (const float *)M.val32, (const float *)w.z32,
                                    w.p32, w.q32, learned ? (const double *)ppart : (const double *)upart,
-                                   learned ? (int)gp : m_up, upart + kMaxBlocks, m_up, qpart, w.scal, w.flags, k, par,
-                                   stall);
+                                   learned ? (int)gp : (int)ge, upart + kMaxBlocks, (int)ge, qpart, w.scal, w.flags,
+                                   kk, par, stall);
                 qh_tend(c, ta, QK_CG_SPMV);
                 int tb = qh_tbeg(c);
                 if (learned)
@@ -806,37 +834,62 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
                                        w.x32, w.r32, w.z32, (const float *)w.p32, (const float *)w.q32,
                                        (const float *)w.dinv32, qpart, upart, (int)gt, w.scal, w.flags, par);
                 qh_tend(c, tb, QK_CG_UPDATE);
-                m_up = (int)ge;
                 if (learned) {
                     int tp = qh_tbeg(c);
                     QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, w.flags));
                     qh_tend(c, tp, QK_PREC);
                 }
             }
-            it += batch;
-            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, m_up, w.scal, w.flags, it);
+            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, c->stream, upart, (int)ge, w.scal, w.flags,
+                               k + batch);
             QH_HIP(c, hipGetLastError());
             QH_HIP(c, hipMemcpyAsync(hflags, w.flags, sizeof(hflags), hipMemcpyDeviceToHost, c->stream));
             QH_HIP(c, hipStreamSynchronize(c->stream));
+            k = hflags[0] ? hflags[1] : k + batch;
         }
-        const int done = hflags[0] ? hflags[1] : it;
-        if (outer < CgWork::kMixedHist) w.last_inner[learned ? 1 : 0][outer] = hflags[0] == CG_CONVERGED ? done : 0;
-        total += done;
-        out.refinements = outer + 1;
         if (hflags[0] == CG_NONFINITE) {
-            flag = CG_NONFINITE;  // d is not applied; x keeps the last refinement's value
+            flag = CG_NONFINITE;  // the batch is not applied: x keeps the last reliable update
             break;
         }
+        // reliable update: x += s d, r = b - A x in FP64
         int tf = qh_tbeg(c);
-        hipLaunchKernelGGL(k_refine, dim3(ge), dim3(kThreads), 0, c->stream, n, w.x, (const float *)w.x32,
-                           (const double *)(w.scal + S_RES));
+        hipLaunchKernelGGL(k_refine, dim3(ge), dim3(kThreads), 0, c->stream, n, w.x, w.x32, (const double *)w.scal);
         qh_tend(c, tf, QK_TRUE_RES);
         QH_HIP(c, hipGetLastError());
-        flag = hflags[0] == CG_STALLED ? CG_STALLED : CG_RUNNING;
+        if ((rc = fp64_residual())) return rc;
+        out.refinements = update + 1;
+        const double rr = sc[0];
+        out.res = bb > 0 ? sqrt(rr / bb) : 0.0;
+        if (rr == rr && rr <= thr2) {
+            flag = CG_CONVERGED;
+            break;
+        }
+        if (!(rr == rr) || rr > 1.7976931348623157e308) {
+            flag = CG_NONFINITE;
+            break;
+        }
+        if (hflags[0] == CG_STALLED) {
+            flag = CG_STALLED;
+            break;
+        }
+        if (k >= max_it) break;
+        // the recurrence continues from the FP64 residual
+        int tq = qh_tbeg(c);
+        if (learned) {
+            hipLaunchKernelGGL(k_replace<false>, dim3(ge), dim3(kThreads), 0, c->stream, n, (const double *)w.r, w.scal,
+                               w.r32, w.z32, (const float *)w.dinv32, upart, w.flags);
+            QH_HIP(c, launch_prec_apply32(c, w.r32, w.z32, ppart, nullptr));
+        } else {
+            hipLaunchKernelGGL(k_replace<true>, dim3(ge), dim3(kThreads), 0, c->stream, n, (const double *)w.r, w.scal,
+                               w.r32, w.z32, (const float *)w.dinv32, upart, w.flags);
+        }
+        qh_tend(c, tq, QK_CG_INIT);
+        QH_HIP(c, hipGetLastError());
     }
-    out.iters = total;
+    out.iters = k;
     out.flag = flag;
-    out.converged = flag == CG_CONVERGED;
+    out.converged = out.true_ok = flag == CG_CONVERGED;
+    if (out.converged) w.last_inner[learned ? 1 : 0][0] = k;
     return QH_OK;
 }
 
