@@ -441,8 +441,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--precond", default="learned", choices=["learned", "jacobi"])
     ap.add_argument("--solver", default="mixed", choices=["mixed", "fp64"],
-                    help="edge solve of the headline run: FP64 PCG, or FP64 residual refinement around FP32 "
-                         "inner PCG; both stop on the FP64 residual 1e-8 and both are timed")
+                    help="edge solve of the headline run: FP64 PCG, or FP32 PCG with FP64 reliable updates; "
+                         "both stop on the FP64 residual 1e-8 and both are timed")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--pairs", type=int, default=2000,
                     help="(rhs, solution) pairs of the plain solver recorded for training (particle seed 1; "
@@ -525,7 +525,7 @@ def main():
         pst = ctx.pic_step(prm, args.profile_steps, want_stats=True)
         pst_k, kern = profile(prm, args.profile_steps)
         log(f"[bench] {pc} {solver}: {1e3 * wall / args.steps:.3f} ms/step, edge iters "
-            f"{[s['edge_iters'] for s in pst]}, refinements {[s['edge_refinements'] for s in pst][:4]}")
+            f"{[s['edge_iters'] for s in pst]}, reliable updates {[s['edge_refinements'] for s in pst][:4]}")
         return {"wall": wall, "pst": pst, "pst_k": pst_k, "kernels": kern, "precond": pc, "solver": solver}
 
     st = ctx.pic_step(prm_of("jacobi", "fp64"), args.warmup, want_stats=True)
@@ -624,7 +624,7 @@ def main():
         "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 push / int64 deposit / f64 edge residual" + (" with f32 inner PCG" if mixed_used else " and PCG"),
+        "dtype": "f32 push / int64 deposit / f64 edge residual" + (" with f32 PCG iterations" if mixed_used else " and PCG"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "particles": n_p,
                    "tets": mi.n_tets, "edges": mi.n_edges, "nnz_edge": mi.nnz_edge, "dt": cfg["dt"],

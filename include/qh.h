@@ -106,10 +106,11 @@ typedef struct {
                             of a solve comes after as many iterations as the previous solve of
                             the same system and preconditioner took */
     int32_t verify;      /* 1: check continuity and D b on the device every step */
-    int32_t solver;      /* edge solve: QH_SOLVER_FP64 (0), or QH_SOLVER_MIXED (1): FP64 residual
-                            refinement around FP32 inner PCG iterations (same preconditioner; FP32
-                            copy of A's values and FP32 vectors, FP64 products and dot products),
-                            stopping on the same FP64 residual tol_edge */
+    int32_t solver;      /* edge solve: QH_SOLVER_FP64 (0), or QH_SOLVER_MIXED (1): PCG in FP32 (FP32
+                            copy of A's values and FP32 vectors, FP64 products and dot products, the
+                            same preconditioner) with reliable updates in FP64 (x accumulated and
+                            b - A x recomputed in FP64 between batches, replacing the FP32
+                            residual), stopping on the same FP64 residual tol_edge */
 } qh_step_params_t;
 
 #define QH_SOLVER_FP64 0
@@ -127,8 +128,8 @@ typedef struct {
     int64_t foreign;                /* deposits into tets outside a block's range (mailbox records) */
     double gauss_res_rho;           /* ||rho - G^T[*eps] e|| / ||rho|| (0 when rho = 0): the same residual
                                        against the charge alone, for comparison with gauss_res */
-    int32_t edge_refinements;       /* QH_SOLVER_MIXED: FP64 residual refinements of the edge solve
-                                       (inner FP32 solves taken); 0 otherwise */
+    int32_t edge_refinements;       /* QH_SOLVER_MIXED: reliable updates of the edge solve (FP64
+                                       residuals recomputed after the start); 0 otherwise */
 } qh_step_stats_t;
 
 typedef struct {
@@ -339,7 +340,7 @@ int qh_fields_energy(qh_ctx *ctx, double *w_e, double *w_m);
 
 /* Solve system (QH_SYS_EDGE or QH_SYS_NODE) A x = rhs on its interior unknowns
  * (n_int_edges or n_int_nodes values), to ||rhs - A x|| <= tol ||rhs|| in FP64: FP64 PCG with
- * FP64 dot products (solver = QH_SOLVER_FP64), or FP64 residual refinement around FP32 inner PCG
+ * FP64 dot products (solver = QH_SOLVER_FP64), or FP32 PCG with FP64 reliable updates
  * (QH_SOLVER_MIXED). x holds the initial guess on entry. A learned or mixed solve that does not
  * converge is restarted as FP64 Jacobi-PCG (stats->fallback = 1). */
 int qh_field_solve(qh_ctx *ctx, int32_t system, const double *rhs, double *x, double tol,

@@ -1088,7 +1088,7 @@ int qh_pic_step(qh_ctx *c, const qh_step_params_t *P, int32_t n_steps, qh_step_s
             int fallbacks = 0;
             if ((learned || mixed) && !se.converged) {
                 // FP64 Jacobi restart: from the iterate when it is finite (the stall rule, the
-                // iteration cap or the refinement cap stopped it), from e^n after non-finite values
+                // iteration cap stopped it), from e^n after non-finite values
                 if (se.flag == 3)
                     QH_HIP(c, hipMemcpyAsync(c->cge.x, c->e_old, sizeof(double) * c->A.n, hipMemcpyDeviceToDevice,
                                              c->stream));

@@ -123,11 +123,9 @@ struct CgWork {
     double *scal = nullptr;     // device scalars (see qh_solver.hip)
     unsigned int *counter = nullptr;
     int32_t *flags = nullptr;   // [0] done, [1] iterations
-    // iterations of the last converged solve (Jacobi, learned), and of the inner solves of the
-    // last mixed-precision solve by refinement (Jacobi, learned; the first kMixedHist)
-    static constexpr int kMixedHist = 4;
+    // iterations of the last converged solve (Jacobi, learned), FP64 and mixed precision
     int32_t last_iters[2] = {0, 0};
-    int32_t last_inner[2][kMixedHist] = {};
+    int32_t last_mixed[2] = {0, 0};
     // mixed-precision solve: FP32 inner iterate, residual, preconditioned residual, directions,
     // inverse diagonal (allocated on first use, n32 entries)
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *dinv32 = nullptr;
@@ -207,7 +205,7 @@ struct qh_ctx {
     double *A_S = nullptr;  // S values on the pattern of A
     double *A_rhs = nullptr;  // [*eps] - tau S on the pattern of A (right-hand side)
     double tau_assembled = -1.0;
-    int32_t last_refinements = 0;  // the last step's mixed-precision refinements
+    int32_t last_refinements = 0;  // the last step's reliable updates (mixed-precision edge solve)
     bool assembled = false;
 
     // fields and deposits
@@ -356,13 +354,13 @@ struct SolveResult {
     int flag = 0;           // why the iteration stopped: 0 iteration cap, 1 target met, 2 stall rule
                             // (learned preconditioner), 3 non-finite values
     int restarts = 0;       // restarts from the iterate after the recomputed residual missed the target
-    int refinements = 0;    // mixed precision: inner FP32 solves taken
+    int refinements = 0;    // mixed precision: reliable updates (FP64 residuals after the start)
 };
 int qh_cg_alloc(qh_ctx *c, CgWork &w, int32_t n);
 // Jacobi PCG on matrix M, rhs in w.b, initial guess in w.x; thr2 target on ||r||^2 set on device.
 int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
                 SolveResult &out, const double *abs_thr2_dev, bool node_system = false, bool learned = false);
-// The edge system in mixed precision: FP64 residual refinement around FP32 inner PCG (Jacobi or the
+// The edge system in mixed precision: FP32 PCG with FP64 reliable updates (Jacobi or the
 // learned preconditioner), stopping on the FP64 residual ||b - A x|| <= tol ||b||.
 int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, int check_every,
                       SolveResult &out, bool learned);

@@ -806,7 +806,7 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
                        w.scal, w.flags, 0.81 * thr2 / rr0, (const double *)nullptr, stall);
     qh_tend(c, t0, QK_CG_INIT);
     QH_HIP(c, hipGetLastError());
-    const int prev = w.last_inner[learned ? 1 : 0][0];  // iterations of the last converged solve
+    const int prev = w.last_mixed[learned ? 1 : 0];  // iterations of the last converged solve
     int k = 0, flag = CG_RUNNING;
     for (int update = 0;; ++update) {
         // a batch: to half of the last solve's iterations, then to one past their end, then
@@ -889,7 +889,7 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
     out.iters = k;
     out.flag = flag;
     out.converged = out.true_ok = flag == CG_CONVERGED;
-    if (out.converged) w.last_inner[learned ? 1 : 0][0] = k;
+    if (out.converged) w.last_mixed[learned ? 1 : 0] = k;
     return QH_OK;
 }
 

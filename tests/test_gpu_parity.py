@@ -248,8 +248,8 @@ def test_positions_100_steps_tie_consistent(jitter4):
 @pytest.mark.parametrize("solver", ["fp64", "mixed"])
 def test_full_cycle_field_update_matches_oracle(jitter4, solver):
     """Each GPU field update equals the oracle's applied to the same state and deposits, with the
-    FP64 edge solve and with the mixed-precision one (FP64 residual refinement around FP32 inner
-    iterations, stopping on the same FP64 residual)."""
+    FP64 edge solve and with the mixed-precision one (FP32 PCG with FP64 reliable updates,
+    stopping on the same FP64 residual)."""
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
     cfg, mesh, cx, op, po, e, b, parts = jitter4
@@ -886,7 +886,7 @@ def test_field_solve_residual(jitter4):
     for system, M in ((qh.SYS_EDGE, A), (qh.SYS_NODE, K)):
         rhs = rng.standard_normal(M.shape[0]) * 1e-12
         ref = sla.spsolve(M, rhs)
-        # FP64 PCG, and FP64 refinement around FP32 inner PCG (the right-hand side of order 1e-12
+        # FP64 PCG, and FP32 PCG with FP64 reliable updates (the right-hand side of order 1e-12
         # checks its scaling to a unit residual)
         for solver in (qh.SOLVER_FP64, qh.SOLVER_MIXED):
             x, st = ctx.field_solve(system, rhs, tol=1e-8, solver=solver)
