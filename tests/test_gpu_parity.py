@@ -249,7 +249,8 @@ def test_positions_100_steps_tie_consistent(jitter4):
 def test_full_cycle_field_update_matches_oracle(jitter4, solver):
     """Each GPU field update equals the oracle's applied to the same state and deposits, with the
     FP64 edge solve and with the mixed-precision one (FP32 PCG with FP64 reliable updates,
-    stopping on the same FP64 residual)."""
+    stopping on the same FP64 residual); halfway the time step changes, so A (and its FP32 copy)
+    is formed again."""
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
     cfg, mesh, cx, op, po, e, b, parts = jitter4
@@ -265,6 +266,10 @@ def test_full_cycle_field_update_matches_oracle(jitter4, solver):
                              solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     Qbg = np.zeros(cx.Nn, np.int64)
     for k in range(8):
+        if k == 4:
+            dt = 3e-10
+            ctx.set_physics(qi.EPS0, qi.MU0, dt, u_q, U_B)
+            fo = FieldOracle(cx, op, dt)
         e_n, b_n = ctx.fields_download()
         st = ctx.pic_step(params)[0]
         assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
