@@ -123,9 +123,11 @@ struct CgWork {
     double *scal = nullptr;     // device scalars (see qh_solver.hip)
     unsigned int *counter = nullptr;
     int32_t *flags = nullptr;   // [0] done, [1] iterations
-    // iterations of the last converged solve (Jacobi, learned), FP64 and mixed precision
+    // iterations of the last converged solve (Jacobi, learned), FP64 and mixed precision, and
+    // for the mixed one its iterations per 1e-4 of residual reduction (0: unknown)
     int32_t last_iters[2] = {0, 0};
     int32_t last_mixed[2] = {0, 0};
+    int32_t last_segment[2] = {0, 0};
     // mixed-precision solve: FP32 inner iterate, residual, preconditioned residual, directions,
     // inverse diagonal (allocated on first use, n32 entries)
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *dinv32 = nullptr;

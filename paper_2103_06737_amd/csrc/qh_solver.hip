@@ -7,6 +7,7 @@
 // Gauss law (eq. discreteGauss): G^T [*eps] G delta = rho^{n+1} - G^T [*eps] e*, e = e* + G delta
 // Faraday: b^{n+1} = b^n - C round((dt/2)(e^{n+1} + e^n)/u_b)  (D C = 0 keeps D b fixed).
 #include <algorithm>
+#include <cmath>
 
 #include "qh_internal.h"
 #include "qh_spmv.h"
@@ -723,10 +724,13 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
 // s = ||r0||, with reliable updates: at the end of each batch of iterations x += s d in FP64,
 // r = b - A x is recomputed in FP64 (the convergence test: ||r|| <= tol ||b||, the FP64 solve's
 // stopping rule) and, unless it is met, replaces the recurrence's residual, which then continues
-// without a restart (its Krylov space and convergence rate are kept). The first batch ends near
-// half of the last solve's iterations and the second one past their end, so a step normally takes
-// two reliable updates. A batch that meets non-finite values is not applied (flag 3); one stopped
-// by the stall rule is applied and the solve returns (flag 2).
+// without a restart (its Krylov space and convergence rate are kept). A segment between updates
+// may reduce the residual by about 1e-4 at most (the FP32 correction d holds the FP64 solution's
+// change only to FP32 accuracy): its length comes from the last solve's rate of convergence, and
+// the last batch ends one past the last solve's iteration count, so a step of the benchmark takes
+// two reliable updates. Without a history, batches of check_every iterations. A batch that meets
+// non-finite values is not applied (flag 3); one stopped by the stall rule is applied and the
+// solve returns (flag 2).
 int qh_cg_alloc32(qh_ctx *c, CgWork &w, int32_t n) {
     if (w.n32 >= n) return QH_OK;
     int rc;
@@ -806,12 +810,13 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
                        w.scal, w.flags, 0.81 * thr2 / rr0, (const double *)nullptr, stall);
     qh_tend(c, t0, QK_CG_INIT);
     QH_HIP(c, hipGetLastError());
-    const int prev = w.last_mixed[learned ? 1 : 0];  // iterations of the last converged solve
+    const int prev = w.last_mixed[learned ? 1 : 0];     // iterations of the last converged solve
+    const int seg = w.last_segment[learned ? 1 : 0];    // its iterations per 1e-4 of reduction
     int k = 0, flag = CG_RUNNING;
     for (int update = 0;; ++update) {
-        // a batch: to half of the last solve's iterations, then to one past their end, then
+        // a batch: to the next segment end, at most one past the last solve's iterations, then
         // check_every at a time
-        const int target = prev > 0 ? (update == 0 ? (prev + 1) / 2 : prev + 1) : 0;
+        const int target = prev > 0 && seg > 0 ? std::min((update + 1) * seg, prev + 1) : 0;
         const int batch = std::min(target > k ? target - k : check_every, max_it - k);
         int32_t hflags[2] = {0, 0};
         if (batch > 0) {
@@ -889,7 +894,13 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
     out.iters = k;
     out.flag = flag;
     out.converged = out.true_ok = flag == CG_CONVERGED;
-    if (out.converged) w.last_mixed[learned ? 1 : 0] = k;
+    if (out.converged) {
+        w.last_mixed[learned ? 1 : 0] = k;
+        // iterations per 1e-4 of residual reduction (1e-8 of r.r), at least check_every
+        const double drop = sc[0] > 0 && k > 0 ? std::log(sc[0] / rr0) / k : 0.0;
+        w.last_segment[learned ? 1 : 0] =
+            drop < 0 ? (int)std::max<double>(check_every, std::min(1e6, std::ceil(std::log(1e-8) / drop))) : 0;
+    }
     return QH_OK;
 }
 
