@@ -727,10 +727,11 @@ int qh_cg_solve(qh_ctx *c, const DevCsr &M, CgWork &w, double tol, int max_it, i
 // without a restart (its Krylov space and convergence rate are kept). A segment between updates
 // may reduce the residual by about 1e-4 at most (the FP32 correction d holds the FP64 solution's
 // change only to FP32 accuracy): its length comes from the last solve's rate of convergence, and
-// the last batch ends one past the last solve's iteration count, so a step of the benchmark takes
-// two reliable updates. Without a history, batches of check_every iterations. A batch that meets
-// non-finite values is not applied (flag 3); one stopped by the stall rule is applied and the
-// solve returns (flag 2).
+// the last batch ends at the last solve's iteration count (from the second segment on, taking in
+// a remainder of at most an eighth of a segment), where the FP64 residual usually meets the
+// target already (the recurrence aims a little lower), so a step of the benchmark takes two
+// reliable updates. Without a history, batches of check_every iterations. A batch that meets non-finite values is not
+// applied (flag 3); one stopped by the stall rule is applied and the solve returns (flag 2).
 int qh_cg_alloc32(qh_ctx *c, CgWork &w, int32_t n) {
     if (w.n32 >= n) return QH_OK;
     int rc;
@@ -814,9 +815,14 @@ int qh_cg_solve_mixed(qh_ctx *c, DevCsr &M, CgWork &w, double tol, int max_it, i
     const int seg = w.last_segment[learned ? 1 : 0];    // its iterations per 1e-4 of reduction
     int k = 0, flag = CG_RUNNING;
     for (int update = 0;; ++update) {
-        // a batch: to the next segment end, at most one past the last solve's iterations, then
-        // check_every at a time
-        const int target = prev > 0 && seg > 0 ? std::min((update + 1) * seg, prev + 1) : 0;
+        // a batch: to the next segment end, at most to the last solve's iteration count (from
+        // the second segment on, a last remainder of at most an eighth of a segment joins the
+        // one before it), then check_every at a time
+        int target = 0;
+        if (prev > 0 && seg > 0) {
+            target = std::min((update + 1) * seg, prev);
+            if (update > 0 && prev - target <= seg / 8) target = prev;
+        }
         const int batch = std::min(target > k ? target - k : check_every, max_it - k);
         int32_t hflags[2] = {0, 0};
         if (batch > 0) {
