@@ -82,6 +82,8 @@ struct TileCols {
     // optional, BF16 values only: value bits << 16 | 16-bit column per entry, one load each in
     // the compact tiles (the value and column arrays still serve the others)
     const uint32_t *pk = nullptr;
+    // every tile compact and non-empty: the packed words alone describe the matrix
+    bool all_pk = false;
 };
 
 struct DevCsr {
@@ -148,6 +150,7 @@ struct LearnedPrec {
     uint16_t *gcol16 = nullptr, *tcol16 = nullptr;               // their compact columns (TileCols)
     int4 *gtbase = nullptr, *ttbase = nullptr;
     int64_t nnz_c16 = 0;                                         // entries of G and G^T in such tiles
+    bool g_all_pk = false, t_all_pk = false;                     // every tile compact and non-empty
     unsigned short *feats = nullptr;         // nnz x 16 BF16 features
     float *gscale = nullptr;                 // 1/sqrt(A_jj) (1/sqrt(A_ii) on the diagonal)
     float *gval = nullptr, *tval = nullptr, *o = nullptr, *d_o = nullptr;

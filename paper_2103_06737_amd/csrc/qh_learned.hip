@@ -244,12 +244,16 @@ __global__ void __launch_bounds__(kTileThreads) k_prec_g(const int2 *__restrict_
     if (done && done[0]) return;  // the solve has converged: nothing left to precondition
     __shared__ double prod[kTileCap];
     double acc = 0.0;
-    tile_spmv(tiles, ntiles, ptr, cols, val, in, prod, [&](int32_t row) { return DOT ? (double)r[row] : 0.0; },
-              [&](int32_t row, double s, double rr) {
+    auto pre = [&](int32_t row) { return DOT ? r[row] : (T)0; };
+    auto epi = [&](int32_t row, double s, T rr) {
         const T st = (T)s;
         out[row] = st;
-        if (DOT) acc += (double)st * rr;
-    });
+        if (DOT) acc += (double)st * (double)rr;
+    };
+    if (cols.all_pk)  // packed words only: the next tile's loaded during this one
+        tile_spmv_pk(tiles, ntiles, ptr, cols, in, prod, pre, epi);
+    else
+        tile_spmv(tiles, ntiles, ptr, cols, val, in, prod, pre, epi);
     if (DOT) {
         __shared__ double sh[kTileThreads / 64];
 #pragma unroll
@@ -783,6 +787,13 @@ int qh_learned_setup(qh_ctx *c) {
         std::vector<int4> gb, tb;
         std::vector<uint16_t> g16, t16;
         L.nnz_c16 = qh_compact_cols(gcol.data(), gt, gb, g16) + qh_compact_cols(tcol.data(), tt, tb, t16);
+        auto all_compact = [](const std::vector<int4> &b) {
+            for (const int4 &q : b)
+                if (q.x < 0) return false;
+            return !b.empty();
+        };
+        L.g_all_pk = all_compact(gb);
+        L.t_all_pk = all_compact(tb);
         if ((rc = qh_alloc(c, &L.gtbase, gb.size())) || (rc = qh_alloc(c, &L.ttbase, tb.size())) ||
             (rc = qh_alloc(c, &L.gcol16, g16.size())) || (rc = qh_alloc(c, &L.tcol16, t16.size())) ||
             (rc = qh_alloc(c, &L.gpk, g16.size())) || (rc = qh_alloc(c, &L.tpk, t16.size())))
@@ -897,9 +908,9 @@ unsigned qh_prec_grid(qh_ctx *c) { return tile_grid(c->lp.nttiles); }
 hipError_t launch_prec_apply(qh_ctx *c, const double *r, double *z, double *part, const int32_t *done) {
     LearnedPrec &L = c->lp;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, double>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk, L.g_all_pk}, L.gval_h, r, L.y, (const double *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, double>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk}, L.tval_h, L.y, z, r, part, done);
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk, L.t_all_pk}, L.tval_h, L.y, z, r, part, done);
     return hipGetLastError();
 }
 
@@ -913,9 +924,9 @@ hipError_t launch_prec_apply32(qh_ctx *c, const float *r, float *z, double *part
         L.y32 = y;
     }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<false, float>), dim3(tile_grid(L.ngtiles)), dim3(kTileThreads), 0, c->stream, L.gtiles,
-                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk}, L.gval_h, r, L.y32, (const float *)nullptr, (double *)nullptr, done);
+                       L.ngtiles, L.gptr, TileCols{L.gcol, L.gcol16, L.gtbase, L.gpk, L.g_all_pk}, L.gval_h, r, L.y32, (const float *)nullptr, (double *)nullptr, done);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prec_g<true, float>), dim3(tile_grid(L.nttiles)), dim3(kTileThreads), 0, c->stream, L.ttiles,
-                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk}, L.tval_h, L.y32, z, r, part, done);
+                       L.nttiles, L.tptr, TileCols{L.tcol, L.tcol16, L.ttbase, L.tpk, L.t_all_pk}, L.tval_h, L.y32, z, r, part, done);
     return hipGetLastError();
 }
 

@@ -141,6 +141,104 @@ __device__ __forceinline__ void tile_spmv_g(const int2 *__restrict__ tiles, int3
     }
 }
 
+// Block barrier that orders LDS only: a wave waits for its own LDS operations, not for its
+// global loads in flight (a plain __syncthreads also waits for those).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// BF16 entries with packed words (cols.pk: value bits << 16 | 16-bit column), for matrices
+// whose tiles are all compact and non-empty (cols.all_pk): a tile's words are one load per
+// thread and unroll slot (a tile holds at most kTileUnroll * kTileThreads entries), so the next
+// tile's words are loaded while this tile's vector gathers, products and row sums run. They
+// are issued after the gathers, with the next tile's row bounds (the memory counter completes
+// in order, so waiting for the gathers does not wait for them); the block barriers order LDS
+// only, so these loads stay in flight across them. Per tile one
+// dependent memory round trip remains exposed (the gathers) instead of two. epi and pre as in
+// tile_spmv_g.
+static_assert(kTileCap == kTileUnroll * kTileThreads, "a tile is one round of loads");
+template <typename XT, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_spmv_pk(const int2 *__restrict__ tiles, int32_t ntiles,
+                                             const int32_t *__restrict__ ptr, const TileCols cols,
+                                             const XT *__restrict__ x, double *prod /* LDS, kTileCap */,
+                                             Pre &&pre, Epi &&epi) {
+    using PF = decltype(pre(0));
+    int32_t tb, te;
+    tile_range(ntiles, tb, te);
+    if (tb >= te) return;  // the same for every thread of the block
+    const int tid = threadIdx.x;
+    const uint32_t *__restrict__ pk = cols.pk;
+    // the words of the tile whose entries start at first (cnt >= 1 of them; cnt = 0 asks for
+    // none, and the loads then repeat entry 0, unused); the slots past cnt repeat the tile's last
+    // entry, so every load stays inside the array
+    auto load_words = [&](uint32_t w[kTileUnroll], int32_t first, int32_t cnt) {
+        if (cnt < 1) first = 0, cnt = 1;
+#pragma unroll
+        for (int u = 0; u < kTileUnroll; ++u) {
+            const int32_t j = u * kTileThreads + tid;
+            w[u] = pk[first + (j < cnt ? j : cnt - 1)];
+        }
+    };
+    int2 t0 = uniform2(tiles[tb]), t1 = uniform2(tiles[tb + 1]);
+    int4 base0 = uniform4(cols.tbase[tb]);
+    uint32_t w[kTileUnroll];
+    load_words(w, t0.y, t1.y - t0.y);
+    int32_t row = t0.x + tid, js = 0, je = 0;  // this thread's row of the tile and its entries
+    PF pf{};
+    if (row < t1.x) {
+        js = ptr[row];
+        je = ptr[row + 1];
+        pf = pre(row);
+    }
+    for (int32_t ti = tb; ti < te; ++ti) {
+        const bool more = ti + 1 < te;
+        const int2 t2 = uniform2(tiles[ti + 2 <= ntiles ? ti + 2 : ntiles]);
+        const int4 base1 = more ? uniform4(cols.tbase[ti + 1]) : base0;
+        float v[kTileUnroll];  // BF16 values, exact in FP32
+        int32_t c[kTileUnroll];
+#pragma unroll
+        for (int u = 0; u < kTileUnroll; ++u) {
+            v[u] = __uint_as_float(w[u] & 0xffff0000u);
+            const uint32_t h = w[u] & 0xffffu;
+            const uint32_t q = h >> 14;
+            c[u] = (q == 0 ? base0.x : q == 1 ? base0.y : q == 2 ? base0.z : base0.w) + (int32_t)(h & 0x3fffu);
+        }
+        XT xv[kTileUnroll];
+#pragma unroll
+        for (int u = 0; u < kTileUnroll; ++u) xv[u] = x[c[u]];
+        // the next tile's row bounds and words
+        const int32_t rn = t1.x + tid;
+        int32_t jsn = 0, jen = 0;
+        PF pfn{};
+        if (more && rn < t2.x) {
+            jsn = ptr[rn];
+            jen = ptr[rn + 1];
+            pfn = pre(rn);
+        }
+        load_words(w, t1.y, more ? t2.y - t1.y : 0);
+        // every slot is stored (those past the tile's entries repeat its last one, and no row
+        // reads them)
+#pragma unroll
+        for (int u = 0; u < kTileUnroll; ++u) prod[u * kTileThreads + tid] = (double)v[u] * (double)xv[u];
+        lds_barrier();
+        if (row < t1.x) {
+            double s = 0.0;
+            for (int32_t j = js - t0.y; j < je - t0.y; ++j) s += prod[j];
+            epi(row, s, pf);
+        }
+        lds_barrier();
+        row = rn;
+        js = jsn;
+        je = jen;
+        pf = pfn;
+        t0 = t1;
+        t1 = t2;
+        base0 = base1;
+    }
+}
+
 // The same with the gathered vector read from memory (converted to FP64).
 template <typename VT, typename XT, typename Pre, typename Epi>
 __device__ __forceinline__ void tile_spmv(const int2 *__restrict__ tiles, int32_t ntiles,
