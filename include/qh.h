@@ -104,7 +104,9 @@ typedef struct {
     int32_t max_it_edge, max_it_node;
     int32_t check_every; /* iterations between host reads of the convergence flag; the first read
                             of a solve comes after as many iterations as the previous solve of
-                            the same system and preconditioner took */
+                            the same system and preconditioner took (QH_SOLVER_MIXED: a read and
+                            reliable update each time the previous solve had reduced its residual
+                            by another 1e-4, the last at its iteration count) */
     int32_t verify;      /* 1: check continuity and D b on the device every step */
     int32_t solver;      /* edge solve: QH_SOLVER_FP64 (0), or QH_SOLVER_MIXED (1): PCG in FP32 (FP32
                             copy of A's values and FP32 vectors, FP64 products and dot products, the
