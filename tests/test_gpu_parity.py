@@ -284,10 +284,11 @@ def test_full_cycle_field_update_matches_oracle(jitter4, solver):
         assert not (cx.D @ b_g).any()
 
 
-def test_wave_field_update_matches_oracle(jitter4):
+@pytest.mark.parametrize("solver", ["fp64", "mixed"])
+def test_wave_field_update_matches_oracle(jitter4, solver):
     """Field updates of the wave-equation mode (eq. wave_cont): the first step (no history) is the
     trapezoidal update, every later one equals the oracle's wave update applied to the same
-    e^n, e^{n-1}, b^n and step currents."""
+    e^n, e^{n-1}, b^n and step currents; with the FP64 edge solve and the mixed-precision one."""
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle, WaveOracle
     cfg, mesh, cx, op, po, e, b, parts = jitter4
@@ -299,7 +300,8 @@ def test_wave_field_update_matches_oracle(jitter4):
     ctx.particles_upload(sid, x, (v * 20).astype(np.float32), tet)
     fo, wo = FieldOracle(cx, op, dt), WaveOracle(cx, op, dt)
     u_q = qi.QE * 2.0 ** -40
-    params = ctx.step_params(field_mode=qh.FIELDS_WAVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    params = ctx.step_params(field_mode=qh.FIELDS_WAVE, verify=1, tol_edge=1e-10, tol_node=1e-10,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     Qbg = np.zeros(cx.Nn, np.int64)
     e_prev = g_prev = None
     for k in range(8):
@@ -307,6 +309,7 @@ def test_wave_field_update_matches_oracle(jitter4):
         st = ctx.pic_step(params)[0]
         assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
         assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+        assert st["fallbacks"] == 0 and (st["edge_refinements"] >= 1) == (solver == "mixed")
         e_g, b_g = ctx.fields_download()
         g, Q = ctx.deposits_download()
         if k == 0:
@@ -339,11 +342,12 @@ def test_wave_mode_equals_trapezoidal_source_free(jitter4):
     assert np.abs(b_w - b_t).max() <= 2 + 1e-8 * np.abs(b_t).max()
 
 
-def test_neumann_field_update_matches_oracle(jitter4):
+@pytest.mark.parametrize("solver", ["fp64", "mixed"])
+def test_neumann_field_update_matches_oracle(jitter4, solver):
     """Natural boundary (eq. zero_mean_constraint): every edge and node is an unknown and the
     Gauss-law system is singular (constants). The device solves it by CG on the consistent right-
     hand side (a neutral plasma); the oracle on the zero-mean subspace of the paper. e does not
-    see the constant, so the field updates agree step by step."""
+    see the constant, so the field updates agree step by step, with either edge solve."""
     import paper_2103_06737_amd as qh
     from oracle.complex_ import Complex
     from oracle.field import FieldOracle
@@ -367,12 +371,14 @@ def test_neumann_field_update_matches_oracle(jitter4):
     ctx.charge_background(1)
     _, Q_bg = ctx.deposits_download()
     fo = FieldOracle(cx, op, dt)
-    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     for k in range(6):
         e_n, b_n = ctx.fields_download()
         st = ctx.pic_step(params)[0]
         assert st["continuity_bad"] == 0 and st["divb_bad"] == 0
         assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+        assert st["fallbacks"] == 0 and (st["edge_refinements"] >= 1) == (solver == "mixed")
         e_g, b_g = ctx.fields_download()
         g, Q = ctx.deposits_download()
         e_o, b_o, _ = fo.step(e_n, b_n, U_B, g, u_q, Q, Q_bg, tol=1e-13, tol_n=1e-13)
@@ -380,15 +386,16 @@ def test_neumann_field_update_matches_oracle(jitter4):
         assert np.abs(b_g - b_o).max() <= 2 + 1e-9 * np.abs(b_o).max()
 
 
+@pytest.mark.parametrize("solver", ["fp64", "mixed"])
 @pytest.mark.parametrize("mode", ["trapezoidal", "wave"])
-def test_plane_wave_through_natural_boundary(mode):
+def test_plane_wave_through_natural_boundary(mode, solver):
     """Sec. VI.A.2: a resolved plane wave (150 MHz on a 1 m box of 6^3 cells) enters through the
     natural boundary. Every step of the device agrees with the oracle's update from the same
     fields with the same boundary term (step average for the trapezoidal update, central
     difference for the wave update) and the same accumulated boundary flux in the Gauss-law
     target; the field follows the incident wave. Half way the wave is set again (the flux
     already brought in stays); for the last steps it is switched off (no boundary term, the
-    flux stays)."""
+    flux stays). With the FP64 edge solve and the mixed-precision one."""
     import paper_2103_06737_amd as qh
     from oracle.complex_ import Complex
     from oracle.field import PlaneWave, WaveOracle
@@ -407,7 +414,8 @@ def test_plane_wave_through_natural_boundary(mode):
     ctx.set_plane_wave(E0, f0, bw, t0)
     fo = WaveOracle(cx, op, dt)
     params = ctx.step_params(field_mode=qh.FIELDS_WAVE if mode == "wave" else qh.FIELDS_SOLVE,
-                             verify=1, tol_edge=1e-12, tol_node=1e-12)
+                             verify=1, tol_edge=1e-12, tol_node=1e-12,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64)
     g0 = np.zeros(cx.Ne, np.int64)
     d = np.zeros(cx.Nn)
     e_prev, on, rel = None, True, []
@@ -419,7 +427,7 @@ def test_plane_wave_through_natural_boundary(mode):
             on = False
         e_n, b_n = ctx.fields_download()
         st = ctx.pic_step(params)[0]
-        assert st["divb_bad"] == 0 and st["gauss_res"] <= 1e-9
+        assert st["divb_bad"] == 0 and st["gauss_res"] <= 1e-9 and st["fallbacks"] == 0
         e_g, b_g = ctx.fields_download()
         h = (lambda t: pw.h(t)) if on else (lambda t: np.zeros(cx.Ne))
         hs = 0.5 * dt * (h(k * dt) + h((k + 1) * dt))
