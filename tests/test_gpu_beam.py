@@ -119,11 +119,14 @@ def test_inject_and_absorb_match_oracle(cyl):
     assert ((seg["lam1"][out] == 0).sum(axis=1) >= 1).all()
 
 
-def test_beam_steps_with_field_solve(cyl):
+@pytest.mark.parametrize("solver,precond", [("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned")])
+def test_beam_steps_with_field_solve(cyl, solver, precond):
     """The beam of the table for 120 steps (10 electrons of 52012.58 injected per step at
     5e7 m/s inside 8 mm, dt = 10 q / 0.25 A), full cycle with the Gauss-law correction:
     continuity off the walls and the Gauss law every step, the count of particles, and the
-    field update of the last step against the oracle's from the same state."""
+    field update of the last step against the oracle's from the same state; with the FP64 and
+    the mixed-precision edge solve on this unstructured mesh, and with the learned
+    preconditioner's initial network."""
     import paper_2103_06737_amd as qh
     from oracle.field import FieldOracle
     mesh, cx, op, po = cyl
@@ -133,7 +136,9 @@ def test_beam_steps_with_field_solve(cyl):
     ctx.set_walls(qh.WALLS_ABSORB)
     ctx.fields_upload(np.zeros(cx.Ne), np.zeros(cx.Nf, np.int64))
     sid = ctx.species_add(-qi.QE / qi.ME, -1)
-    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10)
+    params = ctx.step_params(field_mode=qh.FIELDS_SOLVE, verify=1, tol_edge=1e-10, tol_node=1e-10,
+                             solver=qh.SOLVER_MIXED if solver == "mixed" else qh.SOLVER_FP64,
+                             precond=qh.PC_LEARNED if precond == "learned" else qh.PC_JACOBI)
     injected = absorbed = 0
     fo = FieldOracle(cx, op, dt)
     for k in range(120):
@@ -146,6 +151,7 @@ def test_beam_steps_with_field_solve(cyl):
         absorbed += st["wall_hits"]
         assert st["continuity_bad"] == 0 and st["divb_bad"] == 0 and st["lost"] == 0
         assert st["edge_res"] <= 1e-10 * 1.0001 and st["gauss_res"] <= 1e-9
+        assert st["fallbacks"] == 0
     assert ctx.particles_count(sid) == injected - absorbed == 1200
     e_g, b_g = ctx.fields_download()
     g, Q = ctx.deposits_download()
