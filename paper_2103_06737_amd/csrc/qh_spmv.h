@@ -1,5 +1,6 @@
-// Tiled CSR products y_i = sum_j a_ij x_j for the FP64 solver (shared by qh_solver.hip and
-// qh_learned.hip).
+// Tiled CSR products y_i = sum_j a_ij x_j for the solvers (FP64 or FP32 values and vectors,
+// FP64 products and sums) and the learned factor (BF16 entries); shared by qh_solver.hip and
+// qh_learned.hip.
 //
 // A tile is a run of at most kTileRows consecutive rows holding at most kTileCap entries.
 // One 256-thread block walks a contiguous range of tiles. Per tile, every thread first forms
@@ -56,8 +57,9 @@ __device__ __forceinline__ int4 uniform4(int4 v) {
                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
 }
 
-// For every row of this block's tiles: epi(row, sum_j a_row,j xg(j), pre(row)). pre(row) loads what the epilogue needs from the row's own entries; it is issued with
-// the tile's entry loads, and the next tile's header is fetched one tile ahead, so a tile costs
+// For every row of this block's tiles: epi(row, sum_j a_row,j xg(j), pre(row)). pre(row) loads
+// what the epilogue needs from the row's own entries; it is issued with the tile's entry loads,
+// and the next tile's header is fetched one tile ahead, so a tile costs
 // two dependent memory round trips (entries, then gathered vector). All threads of the block
 // must call it (it synchronises the block).
 template <typename VT, typename XG, typename Pre, typename Epi>
